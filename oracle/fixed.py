@@ -1,0 +1,219 @@
+"""Fixed-membrane OK dynamics: localization-split ETD1 / ETDRK2 (Section 2.2).
+
+TEST INFRASTRUCTURE ONLY (see the package header).  FP64 throughout.
+
+With g > 0 fixed, the FD semi-discrete system (eqn:ODE_eqn) reads
+    d(sqrt(g) u)/dt + L (sqrt(g) u) = R(u),
+    L = B I - eps_u g^{-1/2} Delta_{S,h} g^{-1/2}  =  B I + eps_u H,
+    R(u) = B sqrt(g) u - sqrt(g) W'(u)/eps_u
+           - gamma sqrt(g) (-Delta)^{-1}(g f(u)) f'(u)
+           - M <g (f(u) - ubar), 1>_h sqrt(g) f'(u).
+ETD1 (eqn:ETD1):  sqrt(g) U^{n+1} = phi0(tau L) sqrt(g) U^n + tau phi1(tau L) R(U^n).
+ETDRK2 (eqn:ETDRK2): the ETD1 value is the predictor U~, then
+    sqrt(g) U^{n+1} = sqrt(g) U~ + tau phi2(tau L) (R(U~) - R(U^n)).
+
+Readings (ambiguity register entries, recorded in the design notes):
+  * (-Delta)^{-1} is the constant-coefficient periodic FD pseudo-inverse
+    applied by DFT (zero mode removed); the theorems only use its symmetry,
+    semidefiniteness and sup-norm bound C.
+  * The nonlocal argument is g f(u) as in the discrete R and energy; the
+    flag ``nonlocal_with_ubar`` selects g (f(u) - ubar) as in the PDE.
+  * phi_k(tau L) v is computed by a dense eigendecomposition of the
+    symmetric matrix L on small grids and by Lanczos with full
+    reorthogonalization otherwise (the paper does not say how).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import core
+from .core import Grid
+
+# constants of Lemma lemma:MBPbdd / Theorem thm:Energy (bounds on [0, 1])
+L_W2 = 36.0      # max |W''|
+L_F2 = 6.0       # max |f''|
+L_F1 = 1.5       # max |f'|
+L_G = 9.0 / 8.0  # max g
+
+
+@dataclass
+class FixedParams:
+    eps_u: float
+    gamma: float
+    M: float
+    ubar: float
+    B: float
+    nonlocal_with_ubar: bool = False
+
+
+def B_mbp(eps_u, gamma, M, C, vol):
+    """Condition (eqn:cond_MBP): the smallest B with the discrete MBP."""
+    return L_W2 / eps_u + gamma * C * L_F2 * L_G + M * vol * L_F2 * L_G
+
+
+def B_es(eps_u, gamma, M, C, vol):
+    """Condition (eqn:cond_ES) of Theorem thm:Energy."""
+    return L_W2 / eps_u + (0.5 * gamma * C + 0.5 * M * vol) * (L_F2 + L_F1 ** 2) * L_G
+
+
+def mass_f(U, g, p: FixedParams, grid: Grid) -> float:
+    """m_f = <g (f(U) - ubar), 1>_h."""
+    return grid.cell * float(np.sum(g * (core.f_ind(U) - p.ubar)))
+
+
+def nonlocal_arg(U, g, p: FixedParams):
+    fu = core.f_ind(U)
+    return g * (fu - p.ubar) if p.nonlocal_with_ubar else g * fu
+
+
+def R_phi(U, g, p: FixedParams, grid: Grid) -> np.ndarray:
+    """Nonlinear remainder R(U) of the localization split."""
+    sg = np.sqrt(g)
+    psi = core.lapinv(nonlocal_arg(U, g, p), grid)
+    mf = mass_f(U, g, p, grid)
+    fp = core.fp_ind(U)
+    return (p.B * sg * U - sg * core.Wp(U) / p.eps_u
+            - p.gamma * sg * psi * fp - p.M * mf * sg * fp)
+
+
+def H_apply(w, g, grid: Grid):
+    """H w = -g^{-1/2} Delta_{S,h}(g^{-1/2} w)."""
+    isg = 1.0 / np.sqrt(g)
+    return -isg * core.lap_S(isg * w, g, grid)
+
+
+def L_apply(w, g, p: FixedParams, grid: Grid):
+    return p.B * w + p.eps_u * H_apply(w, g, grid)
+
+
+# ---------------------------------------------------------------------------
+# actions of phi_k(tau L)
+# ---------------------------------------------------------------------------
+
+
+class DenseExpo:
+    """phi(tau L) v through the eigendecomposition L = V diag(lam) V^T."""
+
+    def __init__(self, g, p: FixedParams, grid: Grid):
+        n = int(np.prod(grid.n))
+        eye = np.eye(n).reshape((n,) + tuple(grid.n))
+        cols = L_apply(eye, g, p, grid).reshape(n, n)     # row j = L e_j
+        Lm = cols.T
+        self.L = 0.5 * (Lm + Lm.T)
+        self.asym = float(np.abs(Lm - Lm.T).max())
+        self.lam, self.V = np.linalg.eigh(self.L)
+        self.shape = tuple(grid.n)
+
+    def apply(self, fun, tau, v):
+        c = self.V.T @ v.reshape(-1)
+        return (self.V @ (fun(tau * self.lam) * c)).reshape(self.shape)
+
+
+class LanczosExpo:
+    """phi(tau L) v by Lanczos with full reorthogonalization.
+
+    Stops once two successive Krylov approximations agree to ``tol``
+    relative; the spectrum of tau L lies in [tau B, tau (B + eps_u rho)], where
+    the phi-functions are smooth, so convergence is fast.
+    """
+
+    def __init__(self, g, p: FixedParams, grid: Grid, tol=1e-15, max_iter=400):
+        self.g, self.p, self.grid = g, p, grid
+        self.tol, self.max_iter = tol, max_iter
+        self.last_iters = 0
+
+    def apply(self, fun, tau, v):
+        shape = v.shape
+        v = v.reshape(-1)
+        beta0 = float(np.linalg.norm(v))
+        if beta0 == 0.0:
+            return np.zeros(shape)
+        Q = [v / beta0]
+        alphas, betas = [], []
+        prev, prev_diff = None, np.inf
+        y = None
+        for j in range(self.max_iter):
+            w = L_apply(Q[j].reshape(shape), self.g, self.p, self.grid).reshape(-1)
+            a = float(w @ Q[j])
+            alphas.append(a)
+            Qm = np.array(Q)
+            for _ in range(2):
+                w = w - Qm.T @ (Qm @ w)
+            T = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+            lam, S = np.linalg.eigh(T)
+            coef = S @ (fun(tau * lam) * S[0, :])
+            y = beta0 * (Qm.T @ coef)
+            b = float(np.linalg.norm(w))
+            if prev is not None:
+                diff = float(np.linalg.norm(y - prev))
+                ny = float(np.linalg.norm(y))
+                if diff <= self.tol * ny or (diff <= 1e-13 * ny and diff >= prev_diff):
+                    break
+                prev_diff = diff
+            if b <= 1e-300:
+                break
+            betas.append(b)
+            Q.append(w / b)
+            prev = y
+        self.last_iters = j + 1
+        return y.reshape(shape)
+
+
+def make_expo(g, p: FixedParams, grid: Grid):
+    n = int(np.prod(grid.n))
+    return DenseExpo(g, p, grid) if n <= 4096 else LanczosExpo(g, p, grid)
+
+
+# ---------------------------------------------------------------------------
+# schemes
+# ---------------------------------------------------------------------------
+
+
+def etd1_step(U, g, p: FixedParams, grid: Grid, tau: float, expo, R=None):
+    """One ETD1 step (eqn:ETD1).  ``R`` overrides the remainder (tests)."""
+    R = R or R_phi
+    sg = np.sqrt(g)
+    w = sg * U
+    w1 = expo.apply(core.phi0, tau, w) + tau * expo.apply(core.phi1, tau, R(U, g, p, grid))
+    return w1 / sg
+
+
+def etdrk2_step(U, g, p: FixedParams, grid: Grid, tau: float, expo, R=None):
+    """One ETDRK2 step (eqn:ETDRK2)."""
+    R = R or R_phi
+    sg = np.sqrt(g)
+    w = sg * U
+    Rn = R(U, g, p, grid)
+    wt = expo.apply(core.phi0, tau, w) + tau * expo.apply(core.phi1, tau, Rn)
+    Ut = wt / sg
+    w2 = wt + tau * expo.apply(core.phi2, tau, R(Ut, g, p, grid) - Rn)
+    return w2 / sg
+
+
+def step(U, g, p, grid, tau, scheme, expo, R=None):
+    return (etd1_step if scheme == 1 else etdrk2_step)(U, g, p, grid, tau, expo, R)
+
+
+# ---------------------------------------------------------------------------
+# energy (eqn:Energy_dis) and diagnostics
+# ---------------------------------------------------------------------------
+
+
+def energy(U, g, p: FixedParams, grid: Grid) -> dict:
+    """E_{phi,h}[U] and its four terms, each from the literal formula."""
+    e_grad = 0.5 * p.eps_u * core.inner(-core.lap_S(U, g, grid), U, grid)
+    e_well = core.inner(g * core.W(U), np.ones_like(U), grid) / p.eps_u
+    q = nonlocal_arg(U, g, p)
+    e_nl = 0.5 * p.gamma * core.inner(core.lapinv(q, grid), q, grid)
+    mf = mass_f(U, g, p, grid)
+    e_mass = 0.5 * p.M * mf * mf
+    return dict(E=e_grad + e_well + e_nl + e_mass, E_grad=e_grad, E_well=e_well,
+                E_nonlocal=e_nl, E_mass=e_mass)
+
+
+def diagnostics(U, g, p: FixedParams, grid: Grid) -> dict:
+    return dict(m=mass_f(U, g, p, grid), Q=grid.cell * float(np.sum(g * U)),
+                umin=float(U.min()), umax=float(U.max()),
+                bound=float(np.abs(2.0 * U - 1.0).max()))
