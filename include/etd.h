@@ -1,0 +1,227 @@
+/*
+ * etd.h -- C ABI of the MI355X ETD stepper for the multicomponent-membrane
+ * phase-field model of Luo, Qiao and Zhao ("Exponential Time Differencing
+ * Schemes for a Phase-Field Model of Multicomponent Membranes").
+ *
+ * Two models, one plan object:
+ *   ETD_COUPLED         the coupled phi / u system, stepped by the stabilized
+ *                       spectral ETD1 / ETDRK2 of Section 3.3 (Algorithm 1);
+ *   ETD_FIXED_MEMBRANE  the OK dynamics on a fixed membrane g > 0, stepped by
+ *                       the localization-split FD ETD1 (eqn:ETD1) / ETDRK2
+ *                       (eqn:ETDRK2) of Section 2.2.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns etd_status (0 == ETD_OK); nothing throws.
+ *   - Variables use the paper's [0,1] convention: phi ~ 1 inside the vesicle,
+ *     0 outside; W(s) = 18 (s^2 - s)^2; g(phi) = 18 (phi^2 - phi)^2.
+ *   - Grid: Omega = prod_d [-X_d, X_d), h_d = 2 X_d / N_d, x_i = -X_d + i h_d
+ *     (Section 2.1, Section 3.2).  Arrays crossing the ABI are real, dense,
+ *     C order (last axis contiguous), N_0 x N_1 (x N_2) elements.
+ *   - Device pointers live on the plan's device; the caller owns them.  The
+ *     plan owns its workspace and frees it in etd_plan_destroy.
+ *   - Work is enqueued on the HIP stream given at creation and is
+ *     stream-ordered; only the calls documented as "synchronizes" block.
+ *   - Argument checks happen before any HIP call, so invalid arguments are
+ *     reported (ETD_E_ARG / ETD_E_SIZE / ETD_E_STATE) even without a GPU.
+ *   - A plan is not thread safe; distinct plans on distinct streams are
+ *     independent.
+ */
+#ifndef ETD_H
+#define ETD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct etd_plan* etd_plan_t;
+
+typedef enum {
+    ETD_OK = 0,
+    ETD_E_ARG = -1,        /* null pointer, non-finite or out-of-range value      */
+    ETD_E_SIZE = -2,       /* unsupported grid size (see etd_grid)                */
+    ETD_E_STATE = -3,      /* call out of order (e.g. step before set_state)      */
+    ETD_E_HIP = -4,        /* a HIP runtime call failed; see etd_last_error       */
+    ETD_E_NOMEM = -5,      /* device allocation failed                            */
+    ETD_E_NONFINITE = -6,  /* NaN/Inf detected in the state (reported at sync)    */
+    ETD_E_CAPACITY = -7    /* output buffer too small; *count_out holds the need  */
+} etd_status;
+
+typedef enum { ETD_FIXED_MEMBRANE = 0, ETD_COUPLED = 1 } etd_model;
+typedef enum { ETD_ETD1 = 1, ETD_ETDRK2 = 2 } etd_scheme;
+
+/* Arithmetic of the step.
+ *   ETD_FP64: every stage in FP64.
+ *   ETD_FP32: coupled model -- FFTs and pointwise work in FP32 with FP32
+ *             accumulation; the phi-function multipliers are formed in FP64
+ *             and rounded; integrals, energies, max-bound in FP64.
+ *             fixed model -- only the nonlocal (-Delta)^{-1} FFT runs in FP32;
+ *             everything else stays FP64 (g reaches 1e-47 and underflows FP32). */
+typedef enum { ETD_FP64 = 0, ETD_FP32 = 1 } etd_precision;
+
+/* Element type of arrays passed through set/get_state and band building. */
+typedef enum { ETD_F64 = 0, ETD_F32 = 1 } etd_dtype;
+
+/* Grid.  dim is 2 or 3; n[d] for d < dim, each even, >= 8 and <= 512, of the
+ * form 2^a or 3 * 2^a (radix-2/4/8 and radix-3 transforms); half_len[d] = X_d > 0.
+ * The coupled model requires dim == 3. */
+typedef struct {
+    int dim;
+    int n[3];
+    double half_len[3];
+} etd_grid;
+
+/* Coupled-model parameters (eqn:model_force, eqn:model_OK; stabilizers of
+ * eqn:linear_force and eqn:linear_OK).  u0 is the shift in alpha (u + u0).
+ * A0 is the area-constraint target; with A0_from_initial != 0 it is set to
+ * h^3 sum phi^0 at etd_set_state. */
+typedef struct {
+    double mu, lambda_surf, kappa, lambda_line, M_area, alpha, u0;
+    double eps_phi, eps_u, gamma, ubar, M;
+    double A1, A2, B1, B2;
+    double A0;
+    int A0_from_initial;
+} etd_coupled_params;
+
+/* Fixed-membrane parameters (eqn:model_OK_fix, R_phi of Section 2.2).
+ * B <= 0 selects B = B_MBP of (eqn:cond_MBP) with C = ||(-Delta_h)^{-1}||_inf
+ * computed at plan creation.  nonlocal_with_ubar = 0 uses g f(u) as the
+ * nonlocal argument (the discrete R_phi and energy); 1 uses g (f(u) - ubar)
+ * as in the continuous equation. */
+typedef struct {
+    double eps_u, gamma, ubar, M;
+    double B;
+    int nonlocal_with_ubar;
+} etd_fixed_params;
+
+/* flags */
+#define ETD_F_MASS_PROJECT 0x1u   /* after each step, shift U on {g > recover_threshold}
+                                      so that <g U, 1>_h keeps its value from set_state */
+
+/* One simulation instance. */
+typedef struct {
+    etd_model model;
+    etd_scheme scheme;
+    etd_precision precision;
+    etd_grid grid;
+    double tau;                              /* time step, > 0                          */
+    const etd_coupled_params* coupled;       /* required for ETD_COUPLED                */
+    const etd_fixed_params* fixed;           /* required for ETD_FIXED_MEMBRANE         */
+    double band_threshold;                   /* coupled: > 0 restricts the surface terms
+                                                to {|2 phi - 1| < band_threshold}
+                                                (Section 3.2 narrow band); 0 = off       */
+    int band_rebuild_every;                  /* rebuild the band when step % this == 0  */
+    double recover_threshold;                /* U = GU/G where G > this (default 1e-3)  */
+    unsigned flags;                          /* ETD_F_* bits                            */
+} etd_instance_desc;
+
+/* Create a plan for n_instances independent instances advanced together by
+ * etd_step.  hip_stream is a hipStream_t (NULL = default stream).  Validates
+ * every descriptor before touching HIP; then allocates device workspace and
+ * forms the per-plan constants (for the fixed model: C, B, the Gershgorin
+ * bound of H and the Chebyshev coefficients of phi1 and phi2).
+ * Errors: ETD_E_ARG, ETD_E_SIZE, ETD_E_HIP, ETD_E_NOMEM.  On error *out is NULL. */
+etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void* hip_stream,
+                           etd_plan_t* out);
+
+/* Free all plan-owned device memory (synchronizes the plan's stream). */
+etd_status etd_plan_destroy(etd_plan_t plan);
+
+/* Load the state of one instance from device arrays in the grid layout.
+ *   coupled: a = phi^0, u = u^0 (Algorithm 1 inputs);
+ *   fixed:   a = g (fixed localization field, every value > 0), u = U^0.
+ * dtype gives the element type of a and u.  Copies on the plan's stream;
+ * the caller may reuse the arrays after the stream reaches this point. */
+etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const void* u,
+                         etd_dtype dtype);
+
+/* Copy the current state of one instance into device arrays.
+ *   coupled: a <- phi^n, u <- u^n;  fixed: a <- g (may be NULL), u <- U^n.
+ * Synchronizes; returns ETD_E_NONFINITE if a NaN/Inf was detected. */
+etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dtype dtype);
+
+/* Advance every instance by nsteps time steps (ETD1 or ETDRK2 as planned).
+ * Asynchronous.  Steps after a detected non-finite state are no-ops. */
+etd_status etd_step(etd_plan_t plan, int nsteps);
+
+/* Energy of one instance, FP64, written to host_out (synchronizes).
+ *   fixed   (eqn:Energy_dis), n_out >= 5: [E, E_grad, E_well, E_nonlocal, E_mass]
+ *   coupled (n_out >= 6): [E_surf, E_bend, E_area, E_ok, E_nonlocal, E_mass]
+ *           with E_surf = lambda_surf <|grad phi|^2/2 + W(phi)/eps^2, 1>_h,
+ *           E_bend = (kappa/2) <(Delta phi - W'(phi)/eps^2)^2, 1>_h,
+ *           E_area = (M_area/2)(int phi - A0)^2, E_ok = the OK gradient and well
+ *           terms with g(phi), E_nonlocal = (gamma/2) <(-Delta)^{-1} q, q>_h,
+ *           E_mass = (M/2) <q, 1>_h^2, q = g(phi)(u - ubar). */
+etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out);
+
+/* Per-instance diagnostics (FP64). */
+typedef struct {
+    int64_t step;        /* steps taken since set_state                            */
+    double int_phi;      /* h^d sum phi (coupled) / 0 (fixed)                      */
+    double mass;         /* coupled: <g(phi)(u - ubar), 1>_h; fixed: <g (f(U) - ubar), 1>_h */
+    double Q;            /* <g U, 1>_h                                             */
+    double umin, umax;   /* min / max of U                                         */
+    double bound;        /* max |2 U - 1| (the paper's max-bound check)            */
+    int64_t band_count;  /* current narrow-band size (coupled with a band), else 0 */
+    int nonfinite;       /* 1 if a NaN/Inf was seen                                */
+    int b_warning;       /* fixed: 1 if the planned B is below B_MBP               */
+} etd_diag;
+
+/* Compute and return the diagnostics of one instance (synchronizes). */
+etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* host_out);
+
+/* Narrow band of Section 3.2 for a phase field phi (device array, grid layout
+ * of the instance): the ascending C-order linear indices i with
+ * |2 phi_i - 1| < threshold, decided in FP64, written as int32 to dev_idx_out.
+ * If the band holds more than capacity points, nothing is written,
+ * *count_out is set to the band size and ETD_E_CAPACITY is returned.
+ * count_out is a host pointer; the call synchronizes. */
+etd_status etd_narrowband_build(etd_plan_t plan, int instance, const void* phi, etd_dtype dtype,
+                                double threshold, int32_t* dev_idx_out, int64_t capacity,
+                                int64_t* count_out);
+
+/* Apply one of the plan's spectral operators to a real field through the
+ * instance's own transforms (forward r2c, multiplier, inverse c2r):
+ *   ETD_OP_IDENTITY  round trip (multiplier 1)
+ *   ETD_OP_LAPLACE   spectral Laplacian, symbol -k^2 with the wavenumbers of
+ *                    Section 3.2 (lambda(i) = pi i / X for i <= N/2, pi (N - i)/X above)
+ *   ETD_OP_DX/DY/DZ  spectral first derivative i k_d along array axis 0/1/2
+ *                    (Nyquist bin zeroed); a 2D grid has axes 0 and 1 only,
+ *                    and ETD_OP_DZ returns ETD_E_ARG there
+ *   ETD_OP_LAPINV    (-Delta_h)^{-1}: inverse of the periodic (2d+1)-point FD
+ *                    Laplacian with the mean removed (symbol 1/mu_k, 0 at k = 0)
+ * in and out are device arrays in the grid layout (they may alias).  The
+ * transforms run in the instance's precision (fixed model: FP64, or FP32 on
+ * the FP32-FFT path).  Uses only the instance's scratch buffers, never its
+ * state.  Asynchronous on the plan's stream. */
+typedef enum {
+    ETD_OP_IDENTITY = 0, ETD_OP_LAPLACE = 1, ETD_OP_DX = 2, ETD_OP_DY = 3, ETD_OP_DZ = 4, ETD_OP_LAPINV = 5
+} etd_spectral_op;
+etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op, const void* in, void* out,
+                              etd_dtype dtype);
+
+/* Scalar plan facts for one instance (host doubles):
+ *   ETD_Q_B          stabilizer B in use (fixed)
+ *   ETD_Q_B_MBP      B_MBP of (eqn:cond_MBP) (fixed)
+ *   ETD_Q_B_ES       B of (eqn:cond_ES) (fixed)
+ *   ETD_Q_C          ||(-Delta_h)^{-1}||_inf (fixed)
+ *   ETD_Q_RHO        Gershgorin bound of H = -g^{-1/2} Delta_{S,h} g^{-1/2} (fixed)
+ *   ETD_Q_CHEB_DEG   degree of the Chebyshev expansions of phi1 / phi2 (fixed)
+ *   ETD_Q_A0         area target A0 (coupled)
+ *   ETD_Q_WORKSPACE  bytes of device workspace held by the instance */
+typedef enum {
+    ETD_Q_B = 0, ETD_Q_B_MBP = 1, ETD_Q_B_ES = 2, ETD_Q_C = 3, ETD_Q_RHO = 4,
+    ETD_Q_CHEB_DEG = 5, ETD_Q_A0 = 6, ETD_Q_WORKSPACE = 7
+} etd_query;
+etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double* out);
+
+/* Static strings; never NULL. */
+const char* etd_status_string(etd_status s);
+const char* etd_last_error(etd_plan_t plan);   /* plan may be NULL: last global error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETD_H */

@@ -111,6 +111,39 @@ class DenseExpo:
         return (self.V @ (fun(tau * self.lam) * c)).reshape(self.shape)
 
 
+class UspaceExpo:
+    """phi(tau L) w computed in the U variable (small grids, one fixed tau).
+
+    With D = diag(sqrt g), phi(tau L) w = D phi(tau Lt) D^{-1} w where
+    Lt = D^{-1} L D = B I - eps_u G^{-1} Delta_{S,h}.  Unlike L, whose entries
+    carry factors g^{-1/2} up to ~1e8 where g is tiny, Lt's entries are ratios
+    of neighbouring g values, so the block-matrix exponential
+        expm([[A, I, 0], [0, 0, I], [0, 0, 0]]),  A = -tau Lt,
+    whose first block row is [e^A, phi1, phi2] (phi_k in the convention of
+    Section 2.2 evaluated at tau Lt), yields U-space results accurate relative
+    to U itself, also where g ~ 1e-17.  scipy's expm is the library primitive.
+    """
+
+    def __init__(self, g, p: FixedParams, grid: Grid, tau: float):
+        import scipy.linalg as sla
+        n = int(np.prod(grid.n))
+        eye = np.eye(n).reshape((n,) + tuple(grid.n))
+        cols = (p.B * eye - p.eps_u * core.lap_S(eye, g, grid) / g).reshape(n, n)
+        Lt = cols.T
+        aug = np.zeros((3 * n, 3 * n))
+        aug[:n, :n] = -tau * Lt
+        aug[:n, n:2 * n] = np.eye(n)
+        aug[n:2 * n, 2 * n:] = np.eye(n)
+        E = sla.expm(aug)
+        self.mats = {core.phi0: E[:n, :n], core.phi1: E[:n, n:2 * n], core.phi2: E[:n, 2 * n:]}
+        self.tau, self.sg, self.shape = tau, np.sqrt(g), tuple(grid.n)
+
+    def apply(self, fun, tau, v):
+        assert tau == self.tau
+        x = (v / self.sg).reshape(-1)
+        return self.sg * (self.mats[fun] @ x).reshape(self.shape)
+
+
 class LanczosExpo:
     """phi(tau L) v by Lanczos with full reorthogonalization.
 

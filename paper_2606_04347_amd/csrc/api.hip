@@ -1,0 +1,930 @@
+// Host runtime of the C ABI: validation, plan/workspace management, the step
+// schedules of both models, Chebyshev set-up, energies and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "etd.h"
+#include "fft.h"
+#include "kernels.h"
+
+using namespace etd;
+
+namespace {
+
+std::string g_last_error = "";
+
+etd_status fail(std::string* sink, etd_status st, const std::string& msg) {
+    g_last_error = msg;
+    if (sink) *sink = msg;
+    return st;
+}
+
+// device scalar slots
+enum Slot {
+    S_INTPHI = 0, S_MASS = 1, S_Q0 = 2, S_MPS = 3 /* 2 values */, S_TMP = 5,
+    S_DIAG = 8 /* 7 */, S_ENERGY = 16 /* 7 */, S_GERSH = 24, S_ABS = 25, S_COUNT = 32
+};
+
+struct Instance {
+    etd_instance_desc d{};
+    etd_coupled_params cp{};
+    etd_fixed_params fp{};
+    GridK g{};
+    bool f32 = false;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    FFTTables<float> tf;
+    FFTTables<double> td;
+    // coupled buffers (element type float or double)
+    void *phiA = nullptr, *phiB = nullptr, *u = nullptr, *ut = nullptr, *lap = nullptr, *gx = nullptr,
+         *gy = nullptr, *gz = nullptr, *P = nullptr, *Q = nullptr, *gp = nullptr, *vx = nullptr, *vy = nullptr,
+         *vz = nullptr, *psi = nullptr;
+    void *Sphi = nullptr, *St = nullptr, *Sra = nullptr, *Sa = nullptr, *Sb = nullptr, *Sgu = nullptr,
+         *Stmp = nullptr;
+    // fixed buffers (double unless noted)
+    double *G = nullptr, *sg = nullptr, *isg = nullptr, *U = nullptr, *w = nullptr, *R0 = nullptr, *R1 = nullptr,
+           *vv = nullptr, *t1 = nullptr, *t2 = nullptr, *acc = nullptr, *q = nullptr, *mq = nullptr,
+           *psid = nullptr;
+    float *qf = nullptr, *psif = nullptr;   // FP32-FFT variant of the nonlocal term
+    // shared
+    uint8_t* mask = nullptr;
+    int32_t* band_idx = nullptr;
+    int64_t* band_cnt = nullptr;   // band_blocks + 1 entries, then the total
+    int64_t* band_total = nullptr;
+    double* scal = nullptr;
+    double* part = nullptr;
+    CoupledK K{};
+    FixedK FK{};
+    double A0 = 0.0;
+    long step = 0;
+    bool has_state = false;
+    bool band_active = false;
+    // fixed-model constants
+    double C = 0, Bmbp = 0, Bes = 0, rho = 0, a = 0, b = 0;
+    std::vector<double> ch1, ch2;   // Chebyshev coefficients of phi1(tau x), phi2(tau x) on [a, b]
+};
+
+}  // namespace
+
+struct etd_plan {
+    std::vector<Instance> inst;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+};
+
+namespace {
+
+#define HIPCHK(plan, call)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail(plan ? &plan->err : nullptr, ETD_E_HIP,                                         \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                             \
+    } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+etd_status validate(const etd_instance_desc& d, std::string& msg) {
+    if (d.model != ETD_COUPLED && d.model != ETD_FIXED_MEMBRANE) { msg = "unknown model"; return ETD_E_ARG; }
+    if (d.scheme != ETD_ETD1 && d.scheme != ETD_ETDRK2) { msg = "unknown scheme"; return ETD_E_ARG; }
+    if (d.precision != ETD_FP64 && d.precision != ETD_FP32) { msg = "unknown precision"; return ETD_E_ARG; }
+    if (d.grid.dim != 2 && d.grid.dim != 3) { msg = "grid.dim must be 2 or 3"; return ETD_E_ARG; }
+    if (d.model == ETD_COUPLED && d.grid.dim != 3) { msg = "the coupled model is three-dimensional"; return ETD_E_ARG; }
+    for (int k = 0; k < d.grid.dim; ++k) {
+        const int n = d.grid.n[k];
+        if (n < 8 || n > 512 || (n % 2) != 0) { msg = "grid.n must be even and in [8, 512]"; return ETD_E_SIZE; }
+        if (!fft_length_supported(n)) { msg = "grid.n must be 2^a or 3*2^a"; return ETD_E_SIZE; }
+        if (!finite_pos(d.grid.half_len[k])) { msg = "grid.half_len must be finite and > 0"; return ETD_E_ARG; }
+    }
+    if (!finite_pos(d.tau)) { msg = "tau must be finite and > 0"; return ETD_E_ARG; }
+    if (!std::isfinite(d.recover_threshold) || d.recover_threshold < 0.0) {
+        msg = "recover_threshold must be finite and >= 0"; return ETD_E_ARG;
+    }
+    if (!std::isfinite(d.band_threshold) || d.band_threshold < 0.0) {
+        msg = "band_threshold must be finite and >= 0"; return ETD_E_ARG;
+    }
+    if (d.band_threshold > 0.0 && d.band_rebuild_every < 1) { msg = "band_rebuild_every must be >= 1"; return ETD_E_ARG; }
+    long total = 1;
+    for (int k = 0; k < d.grid.dim; ++k) total *= d.grid.n[k];
+    if (total >= (1L << 31)) { msg = "grid too large for int32 band indices"; return ETD_E_SIZE; }
+    if (d.model == ETD_COUPLED) {
+        if (!d.coupled) { msg = "coupled parameters missing"; return ETD_E_ARG; }
+        const etd_coupled_params& p = *d.coupled;
+        const double all[] = {p.mu, p.lambda_surf, p.kappa, p.lambda_line, p.M_area, p.alpha, p.u0, p.eps_phi,
+                              p.eps_u, p.gamma, p.ubar, p.M, p.A1, p.A2, p.B1, p.B2, p.A0};
+        for (double v : all)
+            if (!std::isfinite(v)) { msg = "non-finite coupled parameter"; return ETD_E_ARG; }
+        if (!(p.mu > 0 && p.eps_phi > 0 && p.eps_u > 0)) { msg = "mu, eps_phi, eps_u must be > 0"; return ETD_E_ARG; }
+        if (p.B2 < 0 || p.B1 < 0 || p.A1 < 0 || p.A2 < 0) { msg = "stabilizers must be >= 0"; return ETD_E_ARG; }
+    } else {
+        if (!d.fixed) { msg = "fixed-membrane parameters missing"; return ETD_E_ARG; }
+        const etd_fixed_params& p = *d.fixed;
+        const double all[] = {p.eps_u, p.gamma, p.ubar, p.M, p.B};
+        for (double v : all)
+            if (!std::isfinite(v)) { msg = "non-finite fixed parameter"; return ETD_E_ARG; }
+        if (!(p.eps_u > 0)) { msg = "eps_u must be > 0"; return ETD_E_ARG; }
+        if (p.gamma < 0 || p.M < 0) { msg = "gamma and M must be >= 0"; return ETD_E_ARG; }
+    }
+    return ETD_OK;
+}
+
+GridK make_grid(const etd_grid& gr) {
+    GridK g{};
+    g.dim = gr.dim;
+    if (gr.dim == 2) {
+        g.nx = 1;
+        g.ny = gr.n[0];
+        g.nz = gr.n[1];
+        g.X[0] = 1.0;
+        g.X[1] = gr.half_len[0];
+        g.X[2] = gr.half_len[1];
+    } else {
+        g.nx = gr.n[0];
+        g.ny = gr.n[1];
+        g.nz = gr.n[2];
+        g.X[0] = gr.half_len[0];
+        g.X[1] = gr.half_len[1];
+        g.X[2] = gr.half_len[2];
+    }
+    g.nzh = g.nz / 2 + 1;
+    g.h[0] = g.nx > 1 ? 2.0 * g.X[0] / g.nx : 1.0;
+    g.h[1] = 2.0 * g.X[1] / g.ny;
+    g.h[2] = 2.0 * g.X[2] / g.nz;
+    g.cell = (g.nx > 1 ? g.h[0] : 1.0) * g.h[1] * g.h[2];
+    return g;
+}
+
+double domain_volume(const GridK& g) {
+    return (g.nx > 1 ? 2.0 * g.X[0] : 1.0) * 2.0 * g.X[1] * 2.0 * g.X[2];
+}
+
+etd_status dalloc(etd_plan* P, Instance& I, size_t bytes, void** out) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        return fail(&P->err, ETD_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    I.allocs.push_back(p);
+    I.bytes += bytes;
+    *out = p;
+    return ETD_OK;
+}
+
+#define ALLOC(ptr, bytes)                                                 \
+    do {                                                                  \
+        void* tmp_ = nullptr;                                             \
+        etd_status st_ = dalloc(P, I, (bytes), &tmp_);                    \
+        if (st_ != ETD_OK) return st_;                                    \
+        ptr = reinterpret_cast<decltype(ptr)>(tmp_);                      \
+    } while (0)
+
+template <typename T> etd_status upload_table(etd_plan* P, Instance& I, int n, const c2<T>** out) {
+    std::vector<double> h(2 * (size_t)n);
+    fft_twiddles_host(n, h.data());
+    std::vector<T> hv(2 * (size_t)n);
+    for (size_t k = 0; k < h.size(); ++k) hv[k] = (T)h[k];
+    c2<T>* d = nullptr;
+    ALLOC(d, sizeof(c2<T>) * (size_t)n);
+    HIPCHK(P, hipMemcpy(d, hv.data(), sizeof(c2<T>) * (size_t)n, hipMemcpyHostToDevice));
+    *out = d;
+    return ETD_OK;
+}
+
+template <typename T> etd_status make_tables(etd_plan* P, Instance& I, FFTTables<T>& t) {
+    etd_status st;
+    if (I.g.nx > 1 && (st = upload_table<T>(P, I, I.g.nx, &t.tx)) != ETD_OK) return st;
+    if ((st = upload_table<T>(P, I, I.g.ny, &t.ty)) != ETD_OK) return st;
+    if ((st = upload_table<T>(P, I, I.g.nz / 2, &t.tzh)) != ETD_OK) return st;
+    if ((st = upload_table<T>(P, I, I.g.nz, &t.tzf)) != ETD_OK) return st;
+    return ETD_OK;
+}
+
+// ------------------------------------------------------------------ Chebyshev (host, FP64)
+double phi1_host(double z) { return std::fabs(z) < 1e-5 ? 1.0 - z / 2.0 + z * z / 6.0 : -std::expm1(-z) / z; }
+double phi2_host(double z) {
+    if (std::fabs(z) < 0.1) {
+        double out = 0.0, fact = 1.0;
+        double c[20];
+        fact = 0.5;
+        c[0] = fact;
+        for (int j = 1; j < 16; ++j) c[j] = c[j - 1] / (double)(j + 2);
+        for (int j = 15; j >= 0; --j) out = out * (-z) + c[j];
+        return out;
+    }
+    return (std::expm1(-z) + z) / (z * z);
+}
+
+// Chebyshev coefficients of x -> f(tau x) on [a, b]: f ~ c_0/2 + sum_k c_k T_k(t),
+// t = (2x - a - b)/(b - a).
+std::vector<double> cheb_coeffs(double (*f)(double), double tau, double a, double b) {
+    const int M = 512;
+    std::vector<double> F(M), c(M);
+    double fmax = 0.0;
+    for (int j = 0; j < M; ++j) {
+        const double th = kPi * (j + 0.5) / M;
+        const double x = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(th);
+        F[j] = f(tau * x);
+        fmax = std::fmax(fmax, std::fabs(F[j]));
+    }
+    for (int k = 0; k < M; ++k) {
+        long double s = 0.0L;
+        for (int j = 0; j < M; ++j) s += (long double)F[j] * cosl((long double)kPi * k * (j + 0.5L) / M);
+        c[k] = (double)(2.0L * s / M);
+    }
+    // the DCT's own rounding leaves |c_k| ~ 1e-17 max|f| in the tail; keep every
+    // coefficient above 2e-16 max|f| plus two more
+    int K = 1;
+    for (int k = 0; k < M; ++k)
+        if (std::fabs(c[k]) > 2e-16 * fmax) K = k;
+    K = std::min(M - 1, K + 2);
+    c.resize(K + 1);
+    return c;
+}
+
+// ------------------------------------------------------------------ instance set-up
+etd_status setup_coupled(etd_plan* P, Instance& I) {
+    const GridK& g = I.g;
+    const size_t nr = (size_t)g.nreal(), ns = (size_t)g.nspec();
+    const size_t es = I.f32 ? sizeof(float) : sizeof(double);
+    const size_t cs = 2 * es;
+    void** reals[] = {&I.phiA, &I.phiB, &I.u, &I.ut, &I.lap, &I.gx, &I.gy, &I.gz, &I.P, &I.Q, &I.gp, &I.vx,
+                      &I.vy, &I.vz, &I.psi};
+    for (void** r : reals) ALLOC(*r, nr * es);
+    void** specs[] = {&I.Sphi, &I.St, &I.Sra, &I.Sa, &I.Sb, &I.Sgu, &I.Stmp};
+    for (void** r : specs) ALLOC(*r, ns * cs);
+    ALLOC(I.mask, nr);
+    ALLOC(I.band_idx, nr * sizeof(int32_t));
+    ALLOC(I.band_cnt, (band_blocks((long)nr) + 2) * sizeof(int64_t));
+    ALLOC(I.band_total, sizeof(int64_t));
+    etd_status st = I.f32 ? make_tables<float>(P, I, I.tf) : make_tables<double>(P, I, I.td);
+    if (st != ETD_OK) return st;
+    const etd_coupled_params& p = I.cp;
+    CoupledK& K = I.K;
+    K.mu = p.mu; K.lambda_surf = p.lambda_surf; K.kappa = p.kappa; K.lambda_line = p.lambda_line;
+    K.M_area = p.M_area; K.alpha = p.alpha; K.u0 = p.u0; K.eps_phi = p.eps_phi; K.eps_u = p.eps_u;
+    K.gamma = p.gamma; K.ubar = p.ubar; K.M = p.M; K.A1 = p.A1; K.A2 = p.A2; K.B1 = p.B1; K.B2 = p.B2;
+    K.tau = I.d.tau;
+    const double e2 = p.eps_phi * p.eps_phi;
+    K.c1 = p.kappa / (p.mu * e2);
+    K.lp4 = p.kappa / p.mu;
+    K.lp2 = (p.kappa * (p.A1 + p.A2) + p.lambda_surf * e2) / (p.mu * e2);
+    K.lp0 = (p.kappa * p.A1 * p.A2 + p.lambda_surf * p.A1 * e2) / (p.mu * e2 * e2);
+    K.thr = I.d.recover_threshold;
+    return ETD_OK;
+}
+
+etd_status setup_fixed(etd_plan* P, Instance& I) {
+    const GridK& g = I.g;
+    const size_t nr = (size_t)g.nreal(), ns = (size_t)g.nspec();
+    double** reals[] = {&I.G, &I.sg, &I.isg, &I.U, &I.w, &I.R0, &I.R1, &I.vv, &I.t1, &I.t2, &I.acc, &I.q, &I.mq,
+                        &I.psid};
+    for (double** r : reals) ALLOC(*r, nr * sizeof(double));
+    ALLOC(I.Sa, ns * sizeof(double2));
+    ALLOC(I.Stmp, ns * sizeof(double2));
+    etd_status st = make_tables<double>(P, I, I.td);
+    if (st != ETD_OK) return st;
+    if (I.f32) {
+        ALLOC(I.qf, nr * sizeof(float));
+        ALLOC(I.psif, nr * sizeof(float));
+        ALLOC(I.Sb, ns * sizeof(float2));
+        ALLOC(I.Sgu, ns * sizeof(float2));
+        if ((st = make_tables<float>(P, I, I.tf)) != ETD_OK) return st;
+    }
+    const etd_fixed_params& p = I.fp;
+    I.FK.eps_u = p.eps_u; I.FK.gamma = p.gamma; I.FK.ubar = p.ubar; I.FK.M = p.M;
+    I.FK.with_ubar = p.nonlocal_with_ubar ? 1 : 0;
+    // C = sum_j |a_j| with a = IDFT(1/mu) (zero mode removed): the column of the
+    // pseudo-inverse at index 0, i.e. (-Delta_h)^{-1} of a unit impulse.
+    hipStream_t s = P->stream;
+    set_delta(g.nreal(), I.q, s);
+    HIPCHK(P, fft_r2c_3d<double>(g, I.td, I.q, (double2*)I.Sa, s));
+    spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+    HIPCHK(P, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
+    reduce_abs_sum(g.nreal(), I.psid, I.part, I.scal + S_ABS, s);
+    HIPCHK(P, hipGetLastError());
+    double C = 0.0;
+    HIPCHK(P, hipMemcpyAsync(&C, I.scal + S_ABS, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(P, hipStreamSynchronize(s));
+    I.C = C;
+    const double vol = domain_volume(g);
+    const double LW2 = 36.0, LF2 = 6.0, LF1 = 1.5, LG = 9.0 / 8.0;
+    I.Bmbp = LW2 / p.eps_u + p.gamma * C * LF2 * LG + p.M * vol * LF2 * LG;
+    I.Bes = LW2 / p.eps_u + (0.5 * p.gamma * C + 0.5 * p.M * vol) * (LF2 + LF1 * LF1) * LG;
+    I.FK.B = p.B > 0.0 ? p.B : I.Bmbp;
+    return ETD_OK;
+}
+
+etd_status setup_common(etd_plan* P, Instance& I) {
+    ALLOC(I.scal, S_COUNT * sizeof(double));
+    ALLOC(I.part, (size_t)kRedBlocks * 8 * sizeof(double));
+    HIPCHK(P, hipMemset(I.scal, 0, S_COUNT * sizeof(double)));
+    return ETD_OK;
+}
+
+etd_status check_instance(etd_plan* plan, int instance) {
+    if (!plan) return fail(nullptr, ETD_E_ARG, "null plan");
+    if (instance < 0 || instance >= (int)plan->inst.size())
+        return fail(&plan->err, ETD_E_ARG, "instance out of range");
+    return ETD_OK;
+}
+
+// ------------------------------------------------------------------ coupled step
+template <typename T> struct CoupledView {
+    T *phiA, *phiB, *u, *ut, *lap, *gx, *gy, *gz, *P, *Q, *gp, *vx, *vy, *vz, *psi;
+    c2<T> *Sphi, *St, *Sra, *Sa, *Sb, *Sgu, *Stmp;
+    explicit CoupledView(Instance& I) {
+        phiA = (T*)I.phiA; phiB = (T*)I.phiB; u = (T*)I.u; ut = (T*)I.ut; lap = (T*)I.lap; gx = (T*)I.gx;
+        gy = (T*)I.gy; gz = (T*)I.gz; P = (T*)I.P; Q = (T*)I.Q; gp = (T*)I.gp; vx = (T*)I.vx; vy = (T*)I.vy;
+        vz = (T*)I.vz; psi = (T*)I.psi;
+        Sphi = (c2<T>*)I.Sphi; St = (c2<T>*)I.St; Sra = (c2<T>*)I.Sra; Sa = (c2<T>*)I.Sa; Sb = (c2<T>*)I.Sb;
+        Sgu = (c2<T>*)I.Sgu; Stmp = (c2<T>*)I.Stmp;
+    }
+};
+
+template <typename T> const FFTTables<T>& tables(const Instance& I);
+template <> const FFTTables<float>& tables<float>(const Instance& I) { return I.tf; }
+template <> const FFTTables<double>& tables<double>(const Instance& I) { return I.td; }
+
+// phi and its spectral derivatives from a spectrum: out phi, lap, gx, gy, gz
+template <typename T>
+hipError_t phi_and_derivs(const Instance& I, const c2<T>* S, T* phi, T* lap, T* gx, T* gy, T* gz, c2<T>* work,
+                          c2<T>* tmp, hipStream_t s) {
+    const GridK& g = I.g;
+    const FFTTables<T>& t = tables<T>(I);
+    hipError_t e = fft_c2r_3d<T>(g, t, S, tmp, phi, s);
+    if (e != hipSuccess) return e;
+    const SpecOp ops[4] = {SPEC_NEG_K2, SPEC_IKX, SPEC_IKY, SPEC_IKZ};
+    T* outs[4] = {lap, gx, gy, gz};
+    for (int k = 0; k < 4; ++k) {
+        spec_apply<T>(g, ops[k], S, work, s);
+        if ((e = fft_c2r_3d<T>(g, t, work, tmp, outs[k], s)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// q = g (u - ubar) (masked), gu = g u; m = h^3 sum q; psi = (-Delta_h)^{-1} q; P = P2(u);
+// Sa <- FFT(P2), Sb <- FFT(g u)
+template <typename T>
+hipError_t u_remainder(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, hipStream_t s) {
+    const GridK& g = I.g;
+    const FFTTables<T>& t = tables<T>(I);
+    coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, s);
+    reduce_sum<T>(g.nreal(), v.P, g.cell, I.part, I.scal + S_MASS, s);
+    hipError_t e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s);
+    if (e != hipSuccess) return e;
+    spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, s);
+    if ((e = fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s)) != hipSuccess) return e;
+    if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
+    coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
+    if ((e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const FFTTables<T>& t = tables<T>(I);
+    CoupledView<T> v(I);
+    const long n = g.nreal();
+    const bool rk2 = I.d.scheme == ETD_ETDRK2;
+    const uint8_t* mask = nullptr;
+    if (I.d.band_threshold > 0.0) {
+        if (I.step % I.d.band_rebuild_every == 0) {
+            band_flags<T>(n, v.phiA, I.d.band_threshold, I.mask, s);
+            band_compact(n, I.mask, I.band_cnt, I.band_idx, n, I.band_total, s);
+        }
+        mask = I.mask;
+    }
+    // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
+    reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
+    coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q, s);
+    HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
+    HIPCHK(plan, fft_r2c_3d<T>(g, t, v.Q, v.Sb, s));
+    if (!rk2) {
+        spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, v.Sphi, v.Sra, v.Sphi, s);
+    } else {
+        spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, v.Sphi, v.Sra, v.St, s);
+        HIPCHK(plan, phi_and_derivs<T>(I, v.St, v.phiB, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+        reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s);
+        coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
+                            s);
+        HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
+        HIPCHK(plan, fft_r2c_3d<T>(g, t, v.Q, v.Sb, s));
+        spec_etd_phi2<T>(g, I.K, v.Sa, v.Sb, v.St, v.Sra, v.Sphi, s);
+    }
+    // phi^{n+1} and its derivatives (kept for the next step), g+ and the velocity
+    HIPCHK(plan, phi_and_derivs<T>(I, v.Sphi, v.phiB, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+    coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
+    // ---- g u stages with g = g(phi^{n+1})
+    // The spectral g u values are kept as increments D over FFT(g+ u^n), so the
+    // inverse transforms carry only the per-step change; g+ u^n is added back in
+    // real space inside the recovery (same scheme, smaller rounding in FP32).
+    HIPCHK(plan, u_remainder<T>(I, v, v.u, mask, s));            // Sa = FFT(P2(u^n)), Sb = FFT(g+ u^n)
+    spec_etd_u1<T>(g, I.K, v.Sa, v.Sb, v.Sgu, v.Sra, s);            // Sgu = GU~^ - FFT(g+ u^n), Sra = R2(u^n)^
+    HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
+    recover_increment<T>(n, v.u, v.P, v.gp, v.ut, I.K.thr, s);      // U~
+    if (!rk2) {
+        std::swap(I.u, I.ut);
+    } else {
+        HIPCHK(plan, u_remainder<T>(I, v, v.ut, mask, s));       // Sa = FFT(P2(U~)), Sb = FFT(g+ U~)
+        spec_etd_u2<T>(g, I.K, v.Sa, v.Sb, v.Sgu, v.Sra, s);
+        HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
+        recover_increment<T>(n, v.u, v.P, v.gp, v.u, I.K.thr, s);   // U^{n+1}
+    }
+    if (I.d.flags & ETD_F_MASS_PROJECT) {
+        mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);
+        mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+    }
+    std::swap(I.phiA, I.phiB);
+    HIPCHK(plan, hipGetLastError());
+    return ETD_OK;
+}
+
+// ------------------------------------------------------------------ fixed step
+// psi = (-Delta_h)^{-1} q  (FP64, or FP32 transforms on the FP32-FFT path)
+etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStream_t s) {
+    const GridK& g = I.g;
+    if (!I.f32) {
+        HIPCHK(plan, fft_r2c_3d<double>(g, I.td, q, (double2*)I.Sa, s));
+        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+        HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
+    } else {
+        convert<double, float>(g.nreal(), q, I.qf, s);
+        HIPCHK(plan, fft_r2c_3d<float>(g, I.tf, I.qf, (float2*)I.Sb, s));
+        spec_apply<float>(g, SPEC_INV_FD, (const float2*)I.Sb, (float2*)I.Sb, s);
+        HIPCHK(plan, fft_c2r_3d<float>(g, I.tf, (const float2*)I.Sb, (float2*)I.Sgu, I.psif, s));
+    }
+    return ETD_OK;
+}
+
+etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipStream_t s) {
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, s);
+    reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s);
+    etd_status st = fixed_nonlocal(plan, I, I.q, s);
+    if (st != ETD_OK) return st;
+    if (!I.f32) fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
+    else fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
+    return ETD_OK;
+}
+
+// acc = f(tau L) v by the Chebyshev recurrence (coefficients c)
+void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, double* acc, hipStream_t s) {
+    const GridK& g = I.g;
+    double* tk = I.t1;       // T_1 v, then rotating with t2
+    double* tkm1 = I.t2;
+    // first: T_1 v = Atil v; acc = c0/2 v + c1 T_1 v
+    fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
+                    0.5 * c[0], 1, s);
+    const double* prev = v;
+    for (size_t k = 2; k < c.size(); ++k) {
+        // T_k = 2 Atil T_{k-1} - T_{k-2}; written over the T_{k-2} buffer (prev == v at k = 2)
+        double* out = (k == 2) ? tkm1 : const_cast<double*>(prev);
+        fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
+        prev = tk;
+        tk = out;
+    }
+}
+
+etd_status step_fixed(etd_plan* plan, Instance& I) {
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    etd_status st;
+    // w = sg U;  v = R(U) - L w;  w~ = w + tau phi1(tau L) v
+    mul(n, I.sg, I.U, I.w, s);
+    if ((st = fixed_R(plan, I, I.U, I.R0, s)) != ETD_OK) return st;
+    fixed_L_apply(g, I.FK, I.G, I.isg, I.w, I.vv, s);
+    axpby(n, 1.0, I.R0, -1.0, I.vv, I.vv, s);
+    cheb_apply(I, I.ch1, I.vv, I.acc, s);
+    axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);             // w = w~
+    mul(n, I.isg, I.w, I.U, s);                               // U = w~ / sg  (ETD1 result / predictor)
+    if (I.d.scheme == ETD_ETDRK2) {
+        if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
+        axpby(n, 1.0, I.R1, -1.0, I.R0, I.vv, s);
+        cheb_apply(I, I.ch2, I.vv, I.acc, s);
+        axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
+        mul(n, I.isg, I.w, I.U, s);
+    }
+    if (I.d.flags & ETD_F_MASS_PROJECT) {
+        mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
+        mass_project_apply<double>(n, I.G, I.U, I.d.recover_threshold, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+    }
+    HIPCHK(plan, hipGetLastError());
+    return ETD_OK;
+}
+
+template <typename TI, typename TO> void copy_conv(long n, const void* in, void* out, hipStream_t s) {
+    convert<TI, TO>(n, (const TI*)in, (TO*)out, s);
+}
+
+// state element type T (float/double) <-> ABI dtype
+template <typename T> void load_field(long n, const void* src, etd_dtype dt, T* dst, hipStream_t s) {
+    if (dt == ETD_F64) copy_conv<double, T>(n, src, dst, s);
+    else copy_conv<float, T>(n, src, dst, s);
+}
+template <typename T> void store_field(long n, const T* src, etd_dtype dt, void* dst, hipStream_t s) {
+    if (dt == ETD_F64) copy_conv<T, double>(n, src, dst, s);
+    else copy_conv<T, float>(n, src, dst, s);
+}
+
+template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, const void* a, const void* u,
+                                                   etd_dtype dt) {
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    CoupledView<T> v(I);
+    load_field<T>(n, a, dt, v.phiA, s);
+    load_field<T>(n, u, dt, v.u, s);
+    HIPCHK(plan, fft_r2c_3d<T>(g, tables<T>(I), v.phiA, v.Sphi, s));
+    // phi^0 from its spectrum (as every later phi^n is), with its derivatives
+    HIPCHK(plan, phi_and_derivs<T>(I, v.Sphi, v.phiA, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+    reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
+    gloc_field<T>(n, v.phiA, v.gp, s);
+    mass_project_sums<T>(n, v.gp, v.u, I.K.thr, I.part, I.scal + S_MPS, s);
+    double host[3] = {0, 0, 0};
+    HIPCHK(plan, hipMemcpyAsync(host, I.scal + S_INTPHI, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipMemcpyAsync(host + 1, I.scal + S_MPS, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipStreamSynchronize(s));
+    I.A0 = I.cp.A0_from_initial ? host[0] : I.cp.A0;
+    const double Q0 = host[1] * g.cell;
+    HIPCHK(plan, hipMemcpy(I.scal + S_Q0, &Q0, sizeof(double), hipMemcpyHostToDevice));
+    return ETD_OK;
+}
+
+etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const void* u, etd_dtype dt) {
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    load_field<double>(n, a, dt, I.G, s);
+    load_field<double>(n, u, dt, I.U, s);
+    fixed_prep(g, I.G, I.sg, I.isg, s);
+    fixed_gershgorin(g, I.G, I.isg, I.part, I.scal + S_GERSH, s);
+    mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
+    // min g and a non-finite count, through the diagnostics reduction with g in the u slot
+    reduce_diag<double>(g, nullptr, I.G, I.G, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
+    double host[3], dg[7];
+    HIPCHK(plan, hipMemcpyAsync(host, I.scal + S_GERSH, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipMemcpyAsync(host + 1, I.scal + S_MPS, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipMemcpyAsync(dg, I.scal + S_DIAG, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipStreamSynchronize(s));
+    const double gmin = -dg[3];
+    if (!(gmin > 0.0) || dg[6] > 0.0 || !std::isfinite(host[0]))
+        return fail(&plan->err, ETD_E_ARG, "g must be finite and strictly positive");
+    I.rho = host[0];
+    I.a = I.FK.B;
+    I.b = I.FK.B + I.FK.eps_u * I.rho;
+    if (!(I.b > I.a)) I.b = I.a * (1.0 + 1e-12) + 1e-300;
+    I.ch1 = cheb_coeffs(phi1_host, I.d.tau, I.a, I.b);
+    I.ch2 = cheb_coeffs(phi2_host, I.d.tau, I.a, I.b);
+    const double Q0 = host[1] * g.cell;
+    HIPCHK(plan, hipMemcpy(I.scal + S_Q0, &Q0, sizeof(double), hipMemcpyHostToDevice));
+    return ETD_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* etd_status_string(etd_status s) {
+    switch (s) {
+        case ETD_OK: return "ok";
+        case ETD_E_ARG: return "invalid argument";
+        case ETD_E_SIZE: return "unsupported size";
+        case ETD_E_STATE: return "invalid state (call order)";
+        case ETD_E_HIP: return "HIP runtime error";
+        case ETD_E_NOMEM: return "device out of memory";
+        case ETD_E_NONFINITE: return "non-finite state";
+        case ETD_E_CAPACITY: return "capacity too small";
+    }
+    return "unknown status";
+}
+
+const char* etd_last_error(etd_plan_t plan) {
+    if (plan) return plan->err.c_str();
+    return g_last_error.c_str();
+}
+
+etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void* hip_stream, etd_plan_t* out) {
+    if (!out) return fail(nullptr, ETD_E_ARG, "out is null");
+    *out = nullptr;
+    if (!inst || n_instances < 1) return fail(nullptr, ETD_E_ARG, "need at least one instance descriptor");
+    for (int i = 0; i < n_instances; ++i) {
+        std::string msg;
+        etd_status st = validate(inst[i], msg);
+        if (st != ETD_OK) return fail(nullptr, st, "instance " + std::to_string(i) + ": " + msg);
+    }
+    etd_plan* P = new etd_plan();
+    P->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(nullptr, ETD_E_HIP, "no HIP device");
+    }
+    P->inst.resize(n_instances);
+    for (int i = 0; i < n_instances; ++i) {
+        Instance& I = P->inst[i];
+        I.d = inst[i];
+        if (inst[i].model == ETD_COUPLED) I.cp = *inst[i].coupled;
+        else I.fp = *inst[i].fixed;
+        I.d.coupled = nullptr;
+        I.d.fixed = nullptr;
+        I.g = make_grid(inst[i].grid);
+        I.f32 = inst[i].precision == ETD_FP32;
+        etd_status st = setup_common(P, I);
+        if (st == ETD_OK) st = (I.d.model == ETD_COUPLED) ? setup_coupled(P, I) : setup_fixed(P, I);
+        if (st != ETD_OK) {
+            g_last_error = P->err;
+            etd_plan_destroy(P);
+            return st;
+        }
+    }
+    *out = P;
+    return ETD_OK;
+}
+
+etd_status etd_plan_destroy(etd_plan_t plan) {
+    if (!plan) return ETD_OK;
+    (void)hipStreamSynchronize(plan->stream);
+    for (Instance& I : plan->inst)
+        for (void* p : I.allocs) (void)hipFree(p);
+    delete plan;
+    return ETD_OK;
+}
+
+etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const void* u, etd_dtype dtype) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!a || !u) return fail(&plan->err, ETD_E_ARG, "state pointers must not be null");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    Instance& I = plan->inst[instance];
+    if (I.d.model == ETD_COUPLED)
+        st = I.f32 ? set_state_coupled<float>(plan, I, a, u, dtype) : set_state_coupled<double>(plan, I, a, u, dtype);
+    else
+        st = set_state_fixed(plan, I, a, u, dtype);
+    if (st != ETD_OK) return st;
+    I.step = 0;
+    I.has_state = true;
+    return ETD_OK;
+}
+
+etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dtype dtype) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    Instance& I = plan->inst[instance];
+    if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "get_state before set_state");
+    if (!u || (I.d.model == ETD_COUPLED && !a)) return fail(&plan->err, ETD_E_ARG, "null output pointer");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    hipStream_t s = plan->stream;
+    const long n = I.g.nreal();
+    if (I.d.model == ETD_COUPLED) {
+        if (I.f32) {
+            store_field<float>(n, (const float*)I.phiA, dtype, a, s);
+            store_field<float>(n, (const float*)I.u, dtype, u, s);
+        } else {
+            store_field<double>(n, (const double*)I.phiA, dtype, a, s);
+            store_field<double>(n, (const double*)I.u, dtype, u, s);
+        }
+    } else {
+        if (a) store_field<double>(n, I.G, dtype, a, s);
+        store_field<double>(n, I.U, dtype, u, s);
+    }
+    HIPCHK(plan, hipGetLastError());
+    HIPCHK(plan, hipStreamSynchronize(s));
+    return ETD_OK;
+}
+
+etd_status etd_step(etd_plan_t plan, int nsteps) {
+    if (!plan) return fail(nullptr, ETD_E_ARG, "null plan");
+    if (nsteps < 0) return fail(&plan->err, ETD_E_ARG, "nsteps must be >= 0");
+    for (Instance& I : plan->inst)
+        if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "step before set_state");
+    for (int k = 0; k < nsteps; ++k) {
+        for (Instance& I : plan->inst) {
+            etd_status st;
+            if (I.d.model == ETD_COUPLED) st = I.f32 ? step_coupled<float>(plan, I) : step_coupled<double>(plan, I);
+            else st = step_fixed(plan, I);
+            if (st != ETD_OK) return st;
+            ++I.step;
+        }
+    }
+    return ETD_OK;
+}
+
+etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    Instance& I = plan->inst[instance];
+    if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "energy before set_state");
+    if (!host_out) return fail(&plan->err, ETD_E_ARG, "null output");
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    double sums[7] = {0};
+    if (I.d.model == ETD_FIXED_MEMBRANE) {
+        if (n_out < 5) return fail(&plan->err, ETD_E_ARG, "fixed energy needs n_out >= 5");
+        fixed_nonlocal_arg(n, I.FK, I.G, I.U, I.q, I.mq, s);
+        HIPCHK(plan, fft_r2c_3d<double>(g, I.td, I.q, (double2*)I.Sa, s));
+        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+        HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
+        reduce_energy_fixed(g, I.FK, I.G, I.U, I.psid, I.q, I.part, I.scal + S_ENERGY, s);
+        HIPCHK(plan, hipMemcpyAsync(sums, I.scal + S_ENERGY, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(plan, hipStreamSynchronize(s));
+        const double c = g.cell;
+        const double eg = 0.5 * I.FK.eps_u * c * sums[0], ew = c * sums[1] / I.FK.eps_u,
+                     en = 0.5 * I.FK.gamma * c * sums[2], mf = c * sums[3], em = 0.5 * I.FK.M * mf * mf;
+        host_out[0] = eg + ew + en + em;
+        host_out[1] = eg;
+        host_out[2] = ew;
+        host_out[3] = en;
+        host_out[4] = em;
+    } else {
+        if (n_out < 6) return fail(&plan->err, ETD_E_ARG, "coupled energy needs n_out >= 6");
+        auto run = [&](auto tag) -> etd_status {
+            using T = decltype(tag);
+            CoupledView<T> v(I);
+            const FFTTables<T>& t = tables<T>(I);
+            gloc_field<T>(n, v.phiA, v.gp, s);
+            coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, s);
+            HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
+            spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, s);
+            HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s));
+            reduce_energy_coupled<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, v.psi, v.P, I.part,
+                                     I.scal + S_ENERGY, s);
+            return ETD_OK;
+        };
+        st = I.f32 ? run(0.0f) : run(0.0);
+        if (st != ETD_OK) return st;
+        HIPCHK(plan, hipMemcpyAsync(sums, I.scal + S_ENERGY, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(plan, hipStreamSynchronize(s));
+        const double c = g.cell;
+        const etd_coupled_params& p = I.cp;
+        const double area = c * sums[2] - I.A0;
+        const double mq = c * sums[6];
+        host_out[0] = p.lambda_surf * c * sums[0];
+        host_out[1] = 0.5 * p.kappa * c * sums[1];
+        host_out[2] = 0.5 * p.M_area * area * area;
+        host_out[3] = 0.5 * p.eps_u * c * sums[3] + c * sums[4] / p.eps_u;
+        host_out[4] = 0.5 * p.gamma * c * sums[5];
+        host_out[5] = 0.5 * p.M * mq * mq;
+    }
+    for (int k = 0; k < (I.d.model == ETD_COUPLED ? 6 : 5); ++k)
+        if (!std::isfinite(host_out[k])) return fail(&plan->err, ETD_E_NONFINITE, "non-finite energy");
+    return ETD_OK;
+}
+
+etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* out) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    Instance& I = plan->inst[instance];
+    if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "diagnostics before set_state");
+    if (!out) return fail(&plan->err, ETD_E_ARG, "null output");
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    if (I.d.model == ETD_COUPLED) {
+        if (I.f32) reduce_diag<float>(g, (const float*)I.phiA, nullptr, (const float*)I.u, I.cp.ubar, false, I.part,
+                                      I.scal + S_DIAG, s);
+        else reduce_diag<double>(g, (const double*)I.phiA, nullptr, (const double*)I.u, I.cp.ubar, false, I.part,
+                                 I.scal + S_DIAG, s);
+    } else {
+        reduce_diag<double>(g, nullptr, I.G, I.U, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
+    }
+    double d[7];
+    int64_t bc = 0;
+    HIPCHK(plan, hipMemcpyAsync(d, I.scal + S_DIAG, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (I.d.model == ETD_COUPLED && I.d.band_threshold > 0.0 && I.band_total)
+        HIPCHK(plan, hipMemcpyAsync(&bc, I.band_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipStreamSynchronize(s));
+    out->step = I.step;
+    out->int_phi = I.d.model == ETD_COUPLED ? d[0] : 0.0;
+    out->mass = d[1];
+    out->Q = d[2];
+    out->umin = -d[3];
+    out->umax = d[4];
+    out->bound = d[5];
+    out->band_count = bc;
+    out->nonfinite = d[6] > 0.0 ? 1 : 0;
+    out->b_warning = (I.d.model == ETD_FIXED_MEMBRANE && I.FK.B < I.Bmbp) ? 1 : 0;
+    if (out->nonfinite) return fail(&plan->err, ETD_E_NONFINITE, "non-finite state");
+    return ETD_OK;
+}
+
+etd_status etd_narrowband_build(etd_plan_t plan, int instance, const void* phi, etd_dtype dtype, double threshold,
+                                int32_t* dev_idx_out, int64_t capacity, int64_t* count_out) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!phi || !count_out) return fail(&plan->err, ETD_E_ARG, "null pointer");
+    if (!std::isfinite(threshold) || threshold <= 0.0) return fail(&plan->err, ETD_E_ARG, "threshold must be > 0");
+    if (capacity < 0) return fail(&plan->err, ETD_E_ARG, "capacity must be >= 0");
+    if (capacity > 0 && !dev_idx_out) return fail(&plan->err, ETD_E_ARG, "null index buffer");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    Instance& I = plan->inst[instance];
+    hipStream_t s = plan->stream;
+    const long n = I.g.nreal();
+    // scratch: the instance's mask and tile counters (coupled) or a temporary (fixed)
+    uint8_t* flags = I.mask;
+    int64_t* cnt = I.band_cnt;
+    int64_t* total = I.band_total;
+    std::vector<void*> tmp;
+    if (!flags) {
+        void* p1 = nullptr;
+        void* p2 = nullptr;
+        HIPCHK(plan, hipMalloc(&p1, (size_t)n));
+        if (hipMalloc(&p2, (band_blocks(n) + 3) * sizeof(int64_t)) != hipSuccess) {
+            (void)hipFree(p1);
+            return fail(&plan->err, ETD_E_NOMEM, "band scratch");
+        }
+        tmp = {p1, p2};
+        flags = (uint8_t*)p1;
+        cnt = (int64_t*)p2;
+        total = cnt + band_blocks(n) + 2;
+    }
+    if (dtype == ETD_F64) band_flags<double>(n, (const double*)phi, threshold, flags, s);
+    else band_flags<float>(n, (const float*)phi, threshold, flags, s);
+    band_compact(n, flags, cnt, capacity > 0 ? dev_idx_out : nullptr, capacity, total, s);
+    int64_t c = 0;
+    hipError_t e = hipMemcpyAsync(&c, total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (void* p : tmp) (void)hipFree(p);
+    if (e != hipSuccess) return fail(&plan->err, ETD_E_HIP, std::string("band: ") + hipGetErrorString(e));
+    *count_out = c;
+    if (c > capacity) return fail(&plan->err, ETD_E_CAPACITY, "band larger than capacity");
+    return ETD_OK;
+}
+
+etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op, const void* in, void* out,
+                              etd_dtype dtype) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!in || !out) return fail(&plan->err, ETD_E_ARG, "null pointer");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    Instance& I = plan->inst[instance];
+    const bool two_d = I.g.nx == 1;
+    SpecOp sop;
+    bool ident = false;
+    switch (op) {
+        case ETD_OP_IDENTITY: ident = true; sop = SPEC_NEG_K2; break;
+        case ETD_OP_LAPLACE: sop = SPEC_NEG_K2; break;
+        case ETD_OP_DX: sop = two_d ? SPEC_IKY : SPEC_IKX; break;
+        case ETD_OP_DY: sop = two_d ? SPEC_IKZ : SPEC_IKY; break;
+        case ETD_OP_DZ:
+            if (two_d) return fail(&plan->err, ETD_E_ARG, "DZ on a 2D grid");
+            sop = SPEC_IKZ;
+            break;
+        case ETD_OP_LAPINV: sop = SPEC_INV_FD; break;
+        default: return fail(&plan->err, ETD_E_ARG, "unknown spectral op");
+    }
+    hipStream_t s = plan->stream;
+    const GridK& g = I.g;
+    const long n = g.nreal();
+    auto run = [&](auto tag, void* rbuf, void* sa, void* sb, void* stmp, const FFTTables<decltype(tag)>& t) {
+        using T = decltype(tag);
+        load_field<T>(n, in, dtype, (T*)rbuf, s);
+        hipError_t e = fft_r2c_3d<T>(g, t, (const T*)rbuf, (c2<T>*)sa, s);
+        if (e != hipSuccess) return e;
+        const c2<T>* src = (const c2<T>*)sa;
+        if (!ident) {
+            spec_apply<T>(g, sop, (const c2<T>*)sa, (c2<T>*)sb, s);
+            src = (const c2<T>*)sb;
+        }
+        if ((e = fft_c2r_3d<T>(g, t, src, (c2<T>*)stmp, (T*)rbuf, s)) != hipSuccess) return e;
+        store_field<T>(n, (const T*)rbuf, dtype, out, s);
+        return hipGetLastError();
+    };
+    hipError_t e;
+    if (I.d.model == ETD_COUPLED) {
+        e = I.f32 ? run(0.0f, I.P, I.Sa, I.Sb, I.Stmp, I.tf) : run(0.0, I.P, I.Sa, I.Sb, I.Stmp, I.td);
+    } else {
+        e = I.f32 ? run(0.0f, I.qf, I.Sb, I.Sb, I.Sgu, I.tf) : run(0.0, I.q, I.Sa, I.Sa, I.Stmp, I.td);
+    }
+    if (e != hipSuccess) return fail(&plan->err, ETD_E_HIP, std::string("spectral_apply: ") + hipGetErrorString(e));
+    return ETD_OK;
+}
+
+etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double* out) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!out) return fail(&plan->err, ETD_E_ARG, "null output");
+    const Instance& I = plan->inst[instance];
+    switch (what) {
+        case ETD_Q_B: *out = I.FK.B; break;
+        case ETD_Q_B_MBP: *out = I.Bmbp; break;
+        case ETD_Q_B_ES: *out = I.Bes; break;
+        case ETD_Q_C: *out = I.C; break;
+        case ETD_Q_RHO: *out = I.rho; break;
+        case ETD_Q_CHEB_DEG: *out = (double)std::max(I.ch1.size(), I.ch2.size()); break;
+        case ETD_Q_A0: *out = I.A0; break;
+        case ETD_Q_WORKSPACE: *out = (double)I.bytes; break;
+        default: return fail(&plan->err, ETD_E_ARG, "unknown query");
+    }
+    return ETD_OK;
+}
+
+}  // extern "C"

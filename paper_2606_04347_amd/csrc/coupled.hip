@@ -1,0 +1,407 @@
+// Coupled-model kernels: spectral multipliers and ETD combines (Section 3.2,
+// Section 3.3) and the real-space remainders R1, R2 (Section 3.1) with the
+// second-order FD operators of Section 2.1.
+#include "kernels.h"
+
+namespace etd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// ----------------------------------------------------------------- phi-functions (FP64)
+// phi1(z) = (1 - e^{-z})/z, phi2(z) = (e^{-z} - 1 + z)/z^2; for |z| < 0.1 the
+// series sum_j (-z)^j / (j + k)! (14 terms, truncation < 1e-25) avoids the
+// cancellation of the closed forms.
+__device__ __forceinline__ double phi_taylor(double z, int k) {
+    double fact[20];
+    double f = 1.0;
+    for (int j = 1; j <= k; ++j) f *= j;
+    double out = 0.0;
+    // coefficients 1/(j+k)! for j = 0..13, evaluated by Horner from the top
+    fact[0] = 1.0 / f;
+    for (int j = 1; j < 14; ++j) fact[j] = fact[j - 1] / (double)(j + k);
+    for (int j = 13; j >= 0; --j) out = out * (-z) + fact[j];
+    return out;
+}
+__device__ __forceinline__ double phi1d(double z) {
+    return fabs(z) < 0.1 ? phi_taylor(z, 1) : -expm1(-z) / z;
+}
+__device__ __forceinline__ double phi2d(double z) {
+    return fabs(z) < 0.1 ? phi_taylor(z, 2) : (expm1(-z) + z) / (z * z);
+}
+
+// wavenumbers of half-spectrum entry idx (layout [nx][ny][nzh])
+struct Wave {
+    double k2;      // sum_d lambda_d^2
+    double kd[3];   // first-derivative wavenumbers (Nyquist zeroed)
+    double mu;      // FD symbol sum_d (4/h_d^2) sin^2(pi i_d / N_d)
+};
+
+__device__ __forceinline__ Wave wave(const GridK& g, long idx, bool need_mu) {
+    const int iz = (int)(idx % g.nzh);
+    const long t = idx / g.nzh;
+    const int iy = (int)(t % g.ny);
+    const int ix = (int)(t / g.ny);
+    const double ax = kPi / g.X[0], ay = kPi / g.X[1], az = kPi / g.X[2];
+    const double lx = ax * lam_index(ix, g.nx), ly = ay * lam_index(iy, g.ny), lz = az * iz;
+    Wave w;
+    w.k2 = lx * lx + ly * ly + lz * lz;
+    w.kd[0] = ax * der_index(ix, g.nx);
+    w.kd[1] = ay * der_index(iy, g.ny);
+    w.kd[2] = az * der_index(iz, g.nz);
+    w.mu = 0.0;
+    if (need_mu) {
+        double m = 0.0;
+        if (g.nx > 1) {
+            const double sx = sin(kPi * ix / g.nx);
+            m += 4.0 / (g.h[0] * g.h[0]) * sx * sx;
+        }
+        const double sy = sin(kPi * iy / g.ny), sz = sin(kPi * iz / g.nz);
+        m += 4.0 / (g.h[1] * g.h[1]) * sy * sy + 4.0 / (g.h[2] * g.h[2]) * sz * sz;
+        w.mu = m;
+    }
+    return w;
+}
+
+__device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K.lp4 * k2 + K.lp2) * k2 + K.lp0; }
+__device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
+
+template <typename T>
+__global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out) {
+    const long n = g.nspec();
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Wave w = wave(g, i, op == SPEC_INV_FD);
+        const c2<T> a = in[i];
+        c2<T> r;
+        if (op == SPEC_NEG_K2) {
+            const T m = (T)(-w.k2);
+            r = mk<T>(m * a.x, m * a.y);
+        } else if (op == SPEC_INV_FD) {
+            const T m = (T)(w.mu > 0.0 ? 1.0 / w.mu : 0.0);
+            r = mk<T>(m * a.x, m * a.y);
+        } else {
+            const T k = (T)w.kd[op - 1];   // i k a = (-k a.y, k a.x)
+            r = mk<T>(-k * a.y, k * a.x);
+        }
+        out[i] = r;
+    }
+}
+
+template <typename T>
+__global__ void k_etd_phi1(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q,
+                           const c2<T>* ph, c2<T>* __restrict__ RA, c2<T>* out) {
+    const long n = g.nspec();
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Wave w = wave(g, i, false);
+        const double z = K.tau * lphi(K, w.k2);
+        const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.c1 * w.k2);
+        const c2<T> p = P[i], q = Q[i], f = ph[i];
+        const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
+        RA[i] = R;
+        out[i] = mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
+    }
+}
+
+template <typename T>
+__global__ void k_etd_phi2(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q,
+                           const c2<T>* __restrict__ pt, const c2<T>* __restrict__ RA, c2<T>* out) {
+    const long n = g.nspec();
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Wave w = wave(g, i, false);
+        const double z = K.tau * lphi(K, w.k2);
+        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.c1 * w.k2);
+        const c2<T> p = P[i], q = Q[i], t = pt[i], ra = RA[i];
+        const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
+        out[i] = mk<T>(t.x + te2 * dx, t.y + te2 * dy);
+    }
+}
+
+// The g u stages are carried as increments over the restart value FFT(g+ u^n):
+// GU~^ - FFT(g+ u^n) = (E0 - 1) GU0 + tau E1 R = tau phi1(z) (R - l_u GU0), using
+// E0 - 1 = -z phi1(z).  The inverse transform then only carries the increment,
+// and g+ u^n is added back exactly in real space.
+template <typename T>
+__global__ void k_etd_u1(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ GU0,
+                         c2<T>* __restrict__ D, c2<T>* __restrict__ RA) {
+    const long n = g.nspec();
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Wave w = wave(g, i, false);
+        const double l = lu(K, w.k2);
+        const double z = K.tau * l;
+        const T te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.eps_u * K.B1 * w.k2), lt = (T)l;
+        const c2<T> p = P[i], gu = GU0[i];
+        const c2<T> R = mk<T>(p.x + ck * gu.x, p.y + ck * gu.y);
+        RA[i] = R;
+        D[i] = mk<T>(te1 * (R.x - lt * gu.x), te1 * (R.y - lt * gu.y));
+    }
+}
+
+template <typename T>
+__global__ void k_etd_u2(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ GB, c2<T>* D,
+                         const c2<T>* __restrict__ RA) {
+    const long n = g.nspec();
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Wave w = wave(g, i, false);
+        const double z = K.tau * lu(K, w.k2);
+        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.eps_u * K.B1 * w.k2);
+        const c2<T> p = P[i], gb = GB[i], d = D[i], ra = RA[i];
+        const T dx = (p.x + ck * gb.x) - ra.x, dy = (p.y + ck * gb.y) - ra.y;
+        D[i] = mk<T>(d.x + te2 * dx, d.y + te2 * dy);
+    }
+}
+
+// ----------------------------------------------------------------- real space
+struct Nbr {
+    long c, xm, xp, ym, yp, zm, zp;
+};
+__device__ __forceinline__ Nbr neighbours(const GridK& g, long i) {
+    const int iz = (int)(i % g.nz);
+    const long t = i / g.nz;
+    const int iy = (int)(t % g.ny);
+    const int ix = (int)(t / g.ny);
+    const long sx = (long)g.ny * g.nz, sy = g.nz;
+    Nbr n;
+    n.c = i;
+    n.xp = i + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
+    n.xm = i + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
+    n.yp = i + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
+    n.ym = i + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
+    n.zp = i + ((iz + 1 < g.nz) ? 1 : -(long)(g.nz - 1));
+    n.zm = i + ((iz > 0) ? -1 : (long)(g.nz - 1));
+    return n;
+}
+
+template <typename T> __device__ __forceinline__ T gloc(T p) {
+    const T a = p * p - p;
+    return (T)18 * a * a;
+}
+template <typename T> __device__ __forceinline__ T Wp(T s) { return (T)36 * (s * s - s) * ((T)2 * s - (T)1); }
+template <typename T> __device__ __forceinline__ T Wpp(T s) { return (T)36 * ((T)6 * s * s - (T)6 * s + (T)1); }
+
+// D^-(g_{i+1/2} D^+ u) along one axis, g at the three points given
+template <typename T>
+__device__ __forceinline__ T lapS_axis(T um, T uc, T up, T gm, T gc, T gp, T ih2) {
+    const T ghp = (T)0.5 * (gc + gp), ghm = (T)0.5 * (gm + gc);
+    return (ghp * (up - uc) - ghm * (uc - um)) * ih2;
+}
+
+template <typename T>
+__global__ void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const T* __restrict__ lap,
+                           const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
+                           const T* __restrict__ u, const uint8_t* __restrict__ mask,
+                           const double* __restrict__ int_phi, double A0, T* __restrict__ P, T* __restrict__ Q) {
+    const long n = g.nreal();
+    const T e2 = (T)(K.eps_phi * K.eps_phi);
+    const T c1 = (T)K.c1, A1 = (T)K.A1, A2 = (T)K.A2;
+    const T cW = (T)(K.kappa / (K.mu * K.eps_phi * K.eps_phi * K.eps_phi * K.eps_phi));
+    const T cs = (T)(K.lambda_surf / (K.mu * K.eps_phi * K.eps_phi));
+    const T cl = (T)(K.lambda_line / K.mu), ca = (T)(K.alpha / K.mu);
+    const T area = (T)((K.M_area / K.mu) * (int_phi[0] - A0));
+    const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), ep = (T)K.eps_phi, iep = (T)(1.0 / K.eps_phi);
+    const T u0 = (T)K.u0;
+    const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
+    const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Nbr nb = neighbours(g, i);
+        const T p = phi[i], L = lap[i];
+        const T a = gx[i], b = gy[i], c = gz[i];
+        const T gn = sqrt(a * a + b * b + c * c);
+        const T uc = u[i];
+        const T gc = gloc(p);
+        T S = lapS_axis(u[nb.xm], uc, u[nb.xp], gloc(phi[nb.xm]), gc, gloc(phi[nb.xp]), ihx);
+        S += lapS_axis(u[nb.ym], uc, u[nb.yp], gloc(phi[nb.ym]), gc, gloc(phi[nb.yp]), ihy);
+        S += lapS_axis(u[nb.zm], uc, u[nb.zp], gloc(phi[nb.zm]), gc, gloc(phi[nb.zp]), ihz);
+        const T wp = Wp(p), wpp = Wpp(p);
+        const T q1 = wp - A1 * p;
+        T p1 = c1 * (wpp - A2) * (L - A1 * p / e2) - (cW * wpp + cs) * q1;
+        T surf = cl * (eu * S - gc * Wp(uc) * ieu) * gn - area * gn + ca * (uc + u0) * gn * (ep * L - wp * iep);
+        if (mask) surf = mask[i] ? surf : (T)0;
+        P[i] = p1 + surf;
+        Q[i] = q1;
+    }
+}
+
+template <typename T>
+__global__ void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const T* __restrict__ pn,
+                           const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
+                           T* __restrict__ gp, T* __restrict__ vx, T* __restrict__ vy, T* __restrict__ vz) {
+    const long n = g.nreal();
+    const T itau = (T)(1.0 / K.tau);
+    const T thr = (T)K.thr;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const T p = pn[i];
+        const T G = gloc(p);
+        const T a = gx[i], b = gy[i], c = gz[i];
+        const T gn2 = a * a + b * b + c * c;
+        const bool sel = (G > thr) && (gn2 > (T)0);
+        const T dt = (p - po[i]) * itau;
+        gp[i] = G;
+        vx[i] = sel ? (-dt * a) / gn2 : (T)0;
+        vy[i] = sel ? (-dt * b) / gn2 : (T)0;
+        vz[i] = sel ? (-dt * c) / gn2 : (T)0;
+    }
+}
+
+template <typename T>
+__global__ void k_q_gu(long n, T ubar, const T* __restrict__ u, const T* __restrict__ G,
+                       const uint8_t* __restrict__ mask, T* __restrict__ q, T* __restrict__ gu) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const T uc = u[i], Gc = G[i];
+        T qq = Gc * (uc - ubar);
+        if (mask) qq = mask[i] ? qq : (T)0;
+        q[i] = qq;
+        gu[i] = Gc * uc;
+    }
+}
+
+template <typename T>
+__global__ void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u, const T* __restrict__ G,
+                           const T* __restrict__ vx, const T* __restrict__ vy, const T* __restrict__ vz,
+                           const T* __restrict__ psi, const double* __restrict__ m, const uint8_t* __restrict__ mask,
+                           T* __restrict__ P) {
+    const long n = g.nreal();
+    const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), B2 = (T)K.B2, gam = (T)K.gamma;
+    const T Mm = (T)(K.M * m[0]);
+    const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
+    const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
+    const T i2hx = (T)(g.nx > 1 ? 0.5 / g.h[0] : 0.0), i2hy = (T)(0.5 / g.h[1]), i2hz = (T)(0.5 / g.h[2]);
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const Nbr nb = neighbours(g, i);
+        const T uc = u[i], Gc = G[i];
+        T S = lapS_axis(u[nb.xm], uc, u[nb.xp], G[nb.xm], Gc, G[nb.xp], ihx);
+        S += lapS_axis(u[nb.ym], uc, u[nb.yp], G[nb.ym], Gc, G[nb.yp], ihy);
+        S += lapS_axis(u[nb.zm], uc, u[nb.zp], G[nb.zm], Gc, G[nb.zp], ihz);
+        const T div = (G[nb.xp] * u[nb.xp] * vx[nb.xp] - G[nb.xm] * u[nb.xm] * vx[nb.xm]) * i2hx +
+                      (G[nb.yp] * u[nb.yp] * vy[nb.yp] - G[nb.ym] * u[nb.ym] * vy[nb.ym]) * i2hy +
+                      (G[nb.zp] * u[nb.zp] * vz[nb.zp] - G[nb.zm] * u[nb.zm] * vz[nb.zm]) * i2hz;
+        T p2 = eu * S + B2 * Gc * uc - Gc * Wp(uc) * ieu - gam * Gc * psi[i] - Mm * Gc - div;
+        if (mask) p2 = mask[i] ? p2 : (T)0;
+        P[i] = p2;
+    }
+}
+
+// Recovery of U from GU = g+ u_old + d (Section 3.3 after Algorithm 1):
+// U = GU / G = u_old + d / G where G > thr, U = GU elsewhere.  out may alias u_old.
+template <typename T>
+__global__ void k_recover_inc(long n, const T* u_old, const T* __restrict__ d, const T* __restrict__ G, T* out,
+                              T thr) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+        const T Gc = G[i], uo = u_old[i], dd = d[i];
+        out[i] = (Gc > thr) ? uo + dd / Gc : Gc * uo + dd;
+    }
+}
+
+template <typename TI, typename TO> __global__ void k_convert(long n, const TI* __restrict__ in, TO* __restrict__ out) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) out[i] = (TO)in[i];
+}
+
+template <typename T> __global__ void k_gloc(long n, const T* __restrict__ phi, T* __restrict__ G) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) G[i] = gloc(phi[i]);
+}
+
+__global__ void k_delta(long n, double* x) {
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) x[i] = (i == 0) ? 1.0 : 0.0;
+}
+
+int grid_for(long n) {
+    long b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+template <typename T> void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_spec_apply<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, (int)op, in, out);
+}
+template <typename T>
+void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* ph, c2<T>* RA,
+                   c2<T>* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_etd_phi1<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q, ph, RA, out);
+}
+template <typename T>
+void spec_etd_phi2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* pt,
+                   const c2<T>* RA, c2<T>* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_etd_phi2<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q, pt, RA, out);
+}
+template <typename T>
+void spec_etd_u1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GU0, c2<T>* D, c2<T>* RA,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_etd_u1<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GU0, D, RA);
+}
+template <typename T>
+void spec_etd_u2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GB, c2<T>* D, const c2<T>* RA,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_etd_u2<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GB, D, RA);
+}
+template <typename T>
+void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
+                      const T* gz, const T* u, const uint8_t* mask, const double* int_phi, double A0, T* P, T* Q,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_R1_point<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, phi, lap, gx, gy, gz, u,
+                       mask, int_phi, A0, P, Q);
+}
+template <typename T>
+void coupled_velocity(const GridK& g, const CoupledK& K, const T* po, const T* pn, const T* gx, const T* gy,
+                      const T* gz, T* gp, T* vx, T* vy, T* vz, hipStream_t s) {
+    hipLaunchKernelGGL(k_velocity<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, po, pn, gx, gy, gz, gp, vx,
+                       vy, vz);
+}
+template <typename T>
+void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* G, const uint8_t* mask, T* q, T* gu,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_q_gu<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g.nreal(), (T)K.ubar, u, G, mask, q,
+                       gu);
+}
+template <typename T>
+void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
+                      const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_P2_point<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, psi, m,
+                       mask, P);
+}
+template <typename T>
+void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s) {
+    hipLaunchKernelGGL(k_recover_inc<T>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, u_old, d, G, out, (T)thr);
+}
+template <typename TI, typename TO> void convert(long n, const TI* in, TO* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<TI, TO>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out);
+}
+
+template <typename T> void gloc_field(long n, const T* phi, T* G, hipStream_t s) {
+    hipLaunchKernelGGL(k_gloc<T>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, phi, G);
+}
+void set_delta(long n, double* x, hipStream_t s) {
+    hipLaunchKernelGGL(k_delta, dim3(grid_for(n)), dim3(kBlock), 0, s, n, x);
+}
+
+#define INST(T)                                                                                                   \
+    template void gloc_field<T>(long, const T*, T*, hipStream_t);                                                 \
+    template void spec_apply<T>(const GridK&, SpecOp, const c2<T>*, c2<T>*, hipStream_t);                        \
+    template void spec_etd_phi1<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \
+                                   c2<T>*, c2<T>*, hipStream_t);                                                  \
+    template void spec_etd_phi2<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \
+                                   const c2<T>*, c2<T>*, hipStream_t);                                            \
+    template void spec_etd_u1<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, c2<T>*, c2<T>*,       \
+                                 hipStream_t);                                                                    \
+    template void spec_etd_u2<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, c2<T>*,               \
+                                 const c2<T>*, hipStream_t);                                                      \
+    template void coupled_R1_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
+                                      const T*, const T*, const uint8_t*, const double*, double, T*, T*,          \
+                                      hipStream_t);                                                               \
+    template void coupled_velocity<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
+                                      const T*, T*, T*, T*, T*, hipStream_t);                                     \
+    template void coupled_q_gu<T>(const GridK&, const CoupledK&, const T*, const T*, const uint8_t*, T*, T*,      \
+                                  hipStream_t);                                                                   \
+    template void coupled_P2_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
+                                      const T*, const T*, const double*, const uint8_t*, T*, hipStream_t);        \
+    template void recover_increment<T>(long, const T*, const T*, const T*, T*, double, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+template void convert<float, double>(long, const float*, double*, hipStream_t);
+template void convert<double, float>(long, const double*, float*, hipStream_t);
+template void convert<double, double>(long, const double*, double*, hipStream_t);
+template void convert<float, float>(long, const float*, float*, hipStream_t);
+
+}  // namespace etd

@@ -1,0 +1,417 @@
+// Batched Stockham autosort FFTs for gfx950 and the 3D real transforms.
+//
+// Each workgroup (256 threads, four 64-wide wavefronts) owns L independent
+// lines of length N held in LDS.  A radix-R stage reads the R inputs of each
+// butterfly into registers, applies the twiddles w_N^(r k N/(Ns R)) with k the
+// position inside the current span Ns, does the R-point DFT, and writes the
+// outputs to their autosorted positions (span Ns -> Ns R), so the final order
+// is natural and no bit reversal pass exists.  Radices: 3 (once, first), then
+// 8 and 4 (2 only for N = 2 * 8^a), all with constant internal twiddles.
+//
+// Passes over a 3D array (real [nx][ny][nz] <-> half spectrum [nx][ny][nzh]):
+//   z  : contiguous rows; r2c packs x_{2n} + i x_{2n+1} into a length-nz/2
+//        complex transform and splits it with w_nz^k; c2r inverts that.
+//   y,x: strided lines.  A workgroup takes L consecutive kz columns of one
+//        line family so that every global access is a run of L contiguous
+//        complex values (L = 16: 128 B in FP32, 256 B in FP64).
+#include "fft.h"
+
+#include <cmath>
+#include <mutex>
+
+namespace etd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int M> struct Ilog2 { static constexpr int v = 1 + Ilog2<M / 2>::v; };
+template <> struct Ilog2<1> { static constexpr int v = 0; };
+
+// Radix of the next stage for the remaining length M.
+template <int M> struct NextRadix {
+    static constexpr int k = Ilog2<M>::v;
+    static constexpr int v = (M % 3 == 0) ? 3 : (k == 1 ? 2 : ((k % 3 == 1 || k == 2) ? 4 : 8));
+};
+
+// multiply by DIR * i  (the quarter-turn of the transform's sign)
+template <typename T, int DIR> __device__ __forceinline__ c2<T> qturn(c2<T> a) {
+    return DIR > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft2(c2<T>* v) {
+    c2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft4(c2<T>* v) {
+    c2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    c2<T> t2 = cadd(v[1], v[3]), t3 = qturn<T, DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft8(c2<T>* v) {
+    const T r = (T)0.70710678118654752440084436210484903;
+    c2<T> b[4], c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        b[j] = cadd(v[j], v[j + 4]);
+        c[j] = csub(v[j], v[j + 4]);
+    }
+    // c_j *= w_8^j with w_8 = (1 + DIR i) / sqrt(2)
+    c[1] = cscale(cadd(c[1], qturn<T, DIR>(c[1])), r);
+    c[2] = qturn<T, DIR>(c[2]);
+    c[3] = cscale(csub(qturn<T, DIR>(c[3]), c[3]), r);
+    dft4<T, DIR>(b);
+    dft4<T, DIR>(c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v[2 * m] = b[m];
+        v[2 * m + 1] = c[m];
+    }
+}
+
+template <typename T, int DIR> __device__ __forceinline__ void dft3(c2<T>* v) {
+    const T s3 = (T)0.86602540378443864676372317075293618;
+    c2<T> t = cadd(v[1], v[2]);
+    c2<T> s = cscale(qturn<T, DIR>(csub(v[1], v[2])), s3);
+    c2<T> m = csub(v[0], cscale(t, (T)0.5));
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, s);
+    v[2] = csub(m, s);
+}
+
+template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(c2<T>* v) {
+    if constexpr (R == 2) dft2<T, DIR>(v);
+    else if constexpr (R == 3) dft3<T, DIR>(v);
+    else if constexpr (R == 4) dft4<T, DIR>(v);
+    else dft8<T, DIR>(v);
+}
+
+// One radix-R Stockham stage on L lines of length N in LDS (line stride LS).
+template <typename T, int N, int L, int LS, int R, int NS, int DIR>
+__device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
+    constexpr int NR = N / R;
+    constexpr int NB = L * NR;
+    constexpr int BPT = (NB + kThreads - 1) / kThreads;
+    c2<T> v[BPT][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = tid + i * kThreads;
+        if ((NB % kThreads == 0) || b < NB) {
+            const int l = b / NR, j = b % NR;
+            const c2<T>* src = lds + l * LS + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[r * NR];
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c2<T> w = tw[r * k * (N / (NS * R))];
+                    if constexpr (DIR > 0) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            dftR<T, R, DIR>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int b = tid + i * kThreads;
+        if ((NB % kThreads == 0) || b < NB) {
+            const int l = b / NR, j = b % NR;
+            const int k = j % NS;
+            c2<T>* dst = lds + l * LS + (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int L, int LS, int NS, int DIR>
+__device__ __forceinline__ void stockham(c2<T>* lds, const c2<T>* tw) {
+    if constexpr (NS < N) {
+        constexpr int R = NextRadix<N / NS>::v;
+        stage<T, N, L, LS, R, NS, DIR>(lds, tw);
+        stockham<T, N, L, LS, NS * R, DIR>(lds, tw);
+    }
+}
+
+template <typename T> __device__ __forceinline__ void load_table(c2<T>* dst, const c2<T>* src, int n) {
+    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- strided lines
+template <int N> constexpr int strided_lines() { return N <= 256 ? 16 : 8; }
+
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_strided(const c2<T>* in, c2<T>* out,
+                                                          const c2<T>* __restrict__ tw, int C, int ntiles,
+                                                          long ostride, long estride) {
+    constexpr int L = strided_lines<N>();
+    constexpr int LS = N + 1;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, tw, N);
+    const int o = blockIdx.x / ntiles;
+    const int c0 = (blockIdx.x % ntiles) * L;
+    const int nl = min(L, C - c0);
+    const long base = (long)o * ostride + c0;
+    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
+        const int l = idx % L, e = idx / L;
+        lds[l * LS + e] = (l < nl) ? in[base + l + (long)e * estride] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    stockham<T, N, L, LS, 1, DIR>(lds, stw);
+    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
+        const int l = idx % L, e = idx / L;
+        if (l < nl) out[base + l + (long)e * estride] = lds[l * LS + e];
+    }
+}
+
+// ---------------------------------------------------------------- z rows (r2c / c2r)
+template <int NR> constexpr int z_rows() { return NR >= 512 ? 8 : (NR >= 256 ? 16 : (4096 / NR)); }
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in, c2<T>* __restrict__ out,
+                                                        const c2<T>* __restrict__ twh,
+                                                        const c2<T>* __restrict__ twf, long nrows) {
+    constexpr int M = NR / 2;
+    constexpr int L = z_rows<NR>();
+    constexpr int LS = M + 1;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, twh, M);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    const c2<T>* src = reinterpret_cast<const c2<T>*>(in + row0 * NR);
+    for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+        const int r = idx / M, n = idx % M;
+        lds[r * LS + n] = (r < nl) ? src[idx] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    stockham<T, M, L, LS, 1, -1>(lds, stw);
+    c2<T>* dst = out + row0 * (M + 1);
+    const T half = (T)0.5;
+    for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
+        const int r = idx / (M + 1), k = idx % (M + 1);
+        if (r < nl) {
+            const c2<T> zk = lds[r * LS + (k == M ? 0 : k)];
+            const c2<T> zc = cconj(lds[r * LS + (k == 0 ? 0 : M - k)]);
+            const c2<T> ev = cadd(zk, zc);                  // 2 E_k
+            const c2<T> od = csub(zk, zc);                  // 2 i O_k
+            const c2<T> w = twf[k];
+            // X_k = E_k + w^k O_k = (ev - i w od) / 2
+            const c2<T> wod = cmul(w, od);
+            dst[idx] = mk<T>(half * (ev.x + wod.y), half * (ev.y - wod.x));
+        }
+    }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict__ in, T* __restrict__ out,
+                                                        const c2<T>* __restrict__ twh,
+                                                        const c2<T>* __restrict__ twf, long nrows,
+                                                        T scale) {
+    constexpr int M = NR / 2;
+    constexpr int L = z_rows<NR>();
+    constexpr int LS = M + 1;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, twh, M);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    const c2<T>* src = in + row0 * (M + 1);
+    for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
+        const int r = idx / (M + 1), k = idx % (M + 1);
+        lds[r * LS + k] = (r < nl) ? src[idx] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{+2 pi i k / NR}; each thread
+    // owns the pair (k, M - k), so the update is in place without a barrier.
+    constexpr int HP = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < L * HP; idx += kThreads) {
+        const int r = idx / HP, k = idx % HP;
+        c2<T>* row = lds + r * LS;
+        c2<T> a = row[k], b = row[M - k];
+        if (k == 0) {
+            a.y = 0;
+            b.y = 0;
+        }
+        {
+            const c2<T> s = cadd(a, cconj(b));
+            const c2<T> d = cmul(csub(a, cconj(b)), cconj(twf[k]));
+            row[k] = mk<T>(s.x - d.y, s.y + d.x);
+        }
+        if (k != 0 && 2 * k != M) {
+            const c2<T> s = cadd(b, cconj(a));
+            const c2<T> d = cmul(csub(b, cconj(a)), cconj(twf[M - k]));
+            row[M - k] = mk<T>(s.x - d.y, s.y + d.x);
+        }
+    }
+    __syncthreads();
+    stockham<T, M, L, LS, 1, +1>(lds, stw);
+    c2<T>* dst = reinterpret_cast<c2<T>*>(out + row0 * NR);
+    for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+        const int r = idx / M, n = idx % M;
+        if (r < nl) dst[idx] = cscale(lds[r * LS + n], scale);
+    }
+}
+
+// ---------------------------------------------------------------- launch helpers
+// Raises the dynamic-LDS limit of one kernel instantiation once (each call
+// site below is its own template instantiation, hence its own flag).
+template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag& flag) {
+    std::call_once(flag, [&] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    });
+}
+
+template <typename T, int N, int DIR>
+hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter, long ostride,
+                          long estride, hipStream_t s) {
+    constexpr int L = strided_lines<N>();
+    const size_t smem = sizeof(c2<T>) * (size_t)(L * (N + 1) + N);
+    auto kern = k_fft_strided<T, N, DIR>;
+    static std::once_flag flag;
+    set_smem_limit(kern, smem, flag);
+    const int ntiles = (C + L - 1) / L;
+    hipLaunchKernelGGL(kern, dim3(ntiles * nouter), dim3(kThreads), smem, s, in, out, tw, C, ntiles,
+                       ostride, estride);
+    return hipGetLastError();
+}
+
+template <typename T, int NR>
+hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, const c2<T>* twf, long nrows,
+                    T scale, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = sizeof(c2<T>) * (size_t)(L * (NR / 2 + 1) + NR / 2);
+    const int nblk = (int)((nrows + L - 1) / L);
+    if (forward) {
+        auto kern = k_fft_z_r2c<T, NR>;
+        static std::once_flag flag_f;
+        set_smem_limit(kern, smem, flag_f);
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), smem, s, (const T*)in, (c2<T>*)out, twh, twf,
+                           nrows);
+    } else {
+        auto kern = k_fft_z_c2r<T, NR>;
+        static std::once_flag flag_i;
+        set_smem_limit(kern, smem, flag_i);
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), smem, s, (const c2<T>*)in, (T*)out, twh, twf,
+                           nrows, scale);
+    }
+    return hipGetLastError();
+}
+
+#define ETD_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(12) X(24) X(48) X(96) X(192) X(384)
+
+template <typename T, int DIR>
+hipError_t dispatch_strided(int N, const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter,
+                            long ostride, long estride, hipStream_t s) {
+    switch (N) {
+#define CASE(n) \
+    case n: return launch_strided<T, n, DIR>(in, out, tw, C, nouter, ostride, estride, s);
+        ETD_FFT_SIZES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t dispatch_z(int NR, bool forward, const void* in, void* out, const c2<T>* twh, const c2<T>* twf,
+                      long nrows, T scale, hipStream_t s) {
+    switch (NR) {
+#define CASE(n) \
+    case n: return launch_z<T, n>(forward, in, out, twh, twf, nrows, scale, s);
+        ETD_FFT_SIZES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool fft_length_supported(int n) {
+    switch (n) {
+#define CASE(v) case v:
+        ETD_FFT_SIZES(CASE)
+#undef CASE
+        return true;
+        default: return false;
+    }
+}
+
+void fft_twiddles_host(int n, double* re_im) {
+    // exp(-2 pi i k / n) from the exact integer k, evaluated in long double and
+    // rounded once; the quarter points are set exactly.
+    const long double twopi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < n; ++k) {
+        const long double a = twopi * (long double)k / (long double)n;
+        re_im[2 * k] = (double)cosl(a);
+        re_im[2 * k + 1] = (double)(-sinl(a));
+    }
+    // exact values at the quarter points
+    for (int k = 0; k < n; ++k) {
+        if ((4L * k) % n == 0) {
+            const int q = (int)((4L * k) / n);
+            const double c[4] = {1, 0, -1, 0}, sn[4] = {0, -1, 0, 1};
+            re_im[2 * k] = c[q];
+            re_im[2 * k + 1] = sn[q];
+        }
+    }
+}
+
+template <typename T>
+hipError_t fft_r2c_3d(const GridK& g, const FFTTables<T>& t, const T* in, c2<T>* out, hipStream_t s) {
+    const long rows = (long)g.nx * g.ny;
+    hipError_t e = dispatch_z<T>(g.nz, true, in, out, t.tzh, t.tzf, rows, (T)1, s);
+    if (e != hipSuccess) return e;
+    if (g.ny > 1) {   // y lines: outer x, stride nzh
+        e = dispatch_strided<T, -1>(g.ny, out, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        if (e != hipSuccess) return e;
+    }
+    if (g.nx > 1) {   // x lines: outer y, stride ny * nzh
+        e = dispatch_strided<T, -1>(g.nx, out, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t fft_c2r_3d(const GridK& g, const FFTTables<T>& t, const c2<T>* in, c2<T>* tmp, T* out,
+                      hipStream_t s) {
+    const c2<T>* cur = in;
+    hipError_t e = hipSuccess;
+    if (g.nx > 1) {
+        e = dispatch_strided<T, +1>(g.nx, cur, tmp, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+        if (e != hipSuccess) return e;
+        cur = tmp;
+    }
+    if (g.ny > 1) {
+        e = dispatch_strided<T, +1>(g.ny, cur, tmp, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        if (e != hipSuccess) return e;
+        cur = tmp;
+    }
+    const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+    return dispatch_z<T>(g.nz, false, cur, out, t.tzh, t.tzf, (long)g.nx * g.ny, scale, s);
+}
+
+template hipError_t fft_r2c_3d<float>(const GridK&, const FFTTables<float>&, const float*, float2*, hipStream_t);
+template hipError_t fft_r2c_3d<double>(const GridK&, const FFTTables<double>&, const double*, double2*,
+                                       hipStream_t);
+template hipError_t fft_c2r_3d<float>(const GridK&, const FFTTables<float>&, const float2*, float2*, float*,
+                                      hipStream_t);
+template hipError_t fft_c2r_3d<double>(const GridK&, const FFTTables<double>&, const double2*, double2*,
+                                       double*, hipStream_t);
+
+}  // namespace etd

@@ -1,0 +1,134 @@
+// Launchers of the pointwise, stencil, spectral and reduction kernels.
+#pragma once
+
+#include "common.h"
+
+namespace etd {
+
+// Constants of the coupled model as the kernels use them (Section 3.1).
+struct CoupledK {
+    double mu, lambda_surf, kappa, lambda_line, M_area, alpha, u0;
+    double eps_phi, eps_u, gamma, ubar, M, A1, A2, B1, B2;
+    double tau;
+    double c1;                 // kappa / (mu eps_phi^2)
+    double lp4, lp2, lp0;      // l_phi(k^2) = lp4 k^4 + lp2 k^2 + lp0  (eqn:linear_force)
+    double thr;                // recovery threshold on g
+};
+
+// ------------------------------------------------------------------ spectral
+enum SpecOp { SPEC_NEG_K2 = 0, SPEC_IKX = 1, SPEC_IKY = 2, SPEC_IKZ = 3, SPEC_INV_FD = 4 };
+
+// out = m(k) in for one of the SpecOp multipliers (FP64-formed, rounded to T).
+template <typename T> void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, hipStream_t s);
+
+// phi stage 1: R = P - c1 k^2 Q  -> RA;  out = E0 phi_hat + tau E1 R.
+template <typename T>
+void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* phi_hat,
+                   c2<T>* RA, c2<T>* out, hipStream_t s);
+// phi stage 2: out = phit + tau E2 ((P - c1 k^2 Q) - RA).
+template <typename T>
+void spec_etd_phi2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* phit,
+                   const c2<T>* RA, c2<T>* out, hipStream_t s);
+// u stage 1: RA = P + eps_u B1 k^2 GU0;  D = GU~^ - GU0 = tau phi1(tau l_u) (RA - l_u GU0).
+template <typename T>
+void spec_etd_u1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GU0, c2<T>* D, c2<T>* RA,
+                 hipStream_t s);
+// u stage 2: D <- D + tau E2u ((P + eps_u B1 k^2 GB) - RA).
+template <typename T>
+void spec_etd_u2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GB, c2<T>* D,
+                 const c2<T>* RA, hipStream_t s);
+
+// ------------------------------------------------------------------ real space, coupled
+template <typename T>
+void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
+                      const T* gz, const T* u, const uint8_t* mask, const double* int_phi, double A0, T* P,
+                      T* Q, hipStream_t s);
+template <typename T>
+void coupled_velocity(const GridK& g, const CoupledK& K, const T* phi_old, const T* phi_new, const T* gx,
+                      const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, hipStream_t s);
+template <typename T>
+void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const uint8_t* mask, T* q,
+                  T* gu, hipStream_t s);
+template <typename T>
+void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const T* vx, const T* vy,
+                      const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s);
+// out = u_old + d / G where G > thr, G u_old + d elsewhere (out may alias u_old)
+template <typename T>
+void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s);
+
+// ------------------------------------------------------------------ reductions (FP64, deterministic)
+constexpr int kRedBlocks = 512;
+
+// out[0] = scale * sum_i x_i  (Neumaier-compensated, fixed order).  part: kRedBlocks doubles.
+template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s);
+
+// Diagnostics of a state: out = [h^d sum phi, h^d sum g (u - ubar), h^d sum g u, min u, max u,
+// max |2u - 1|, nonfinite count].  phi may be null (then g is taken from gfix, the fixed membrane).
+// For the fixed model the second entry is h^d sum g (f(u) - ubar).
+template <typename T>
+void reduce_diag(const GridK& g, const T* phi, const double* gfix, const T* u, double ubar, bool fixed_model,
+                 double* part, double* out, hipStream_t s);
+
+// Coupled energy sums: out = [sum(|grad phi|^2/2 + W(phi)/eps^2), sum (lap - W'(phi)/eps^2)^2,
+// sum phi, sum g_half (D+ u)^2 (edges), sum g W(u), sum psi q, sum q]  (unscaled).
+template <typename T>
+void reduce_energy_coupled(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx,
+                           const T* gy, const T* gz, const T* u, const T* psi, const T* q, double* part,
+                           double* out, hipStream_t s);
+
+// ------------------------------------------------------------------ conversions / small helpers
+template <typename TI, typename TO> void convert(long n, const TI* in, TO* out, hipStream_t s);
+// G = g(phi) = 18 (phi^2 - phi)^2
+template <typename T> void gloc_field(long n, const T* phi, T* G, hipStream_t s);
+// x = unit impulse at index 0
+void set_delta(long n, double* x, hipStream_t s);
+// out[0] = sum |x_i|
+void reduce_abs_sum(long n, const double* x, double* part, double* out, hipStream_t s);
+
+// ------------------------------------------------------------------ fixed membrane (FP64)
+struct FixedK {
+    double eps_u, gamma, ubar, M, B;
+    int with_ubar;
+};
+void fixed_prep(const GridK& g, const double* gg, double* sg, double* isg, hipStream_t s);
+// H row bound: out[i] = H_ii + sum_j |H_ij|; reduced with max.
+void fixed_gershgorin(const GridK& g, const double* gg, const double* isg, double* part, double* out,
+                      hipStream_t s);
+// q = g f(U) (or g (f(U) - ubar)); mq = g (f(U) - ubar) (for the mass integral)
+void fixed_nonlocal_arg(long n, const FixedK& K, const double* gg, const double* U, double* q, double* mq,
+                        hipStream_t s);
+// R = B sg U - sg W'(U)/eps_u - gamma sg psi f'(U) - M m sg f'(U)
+template <typename TP>
+void fixed_remainder(long n, const FixedK& K, const double* sg, const double* U, const TP* psi,
+                     const double* m, double* R, hipStream_t s);
+// y = alpha * Atil x - beta * xprev  (Atil = (2 L - (a + b)) / (b - a), L = B + eps_u H),
+// acc (+)= c * y.  xprev may be null when beta == 0.  first != 0: acc = c0 * x + c * y.
+void fixed_cheb_step(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
+                     double alpha, double beta, const double* x, const double* xprev, double* y, double* acc,
+                     double c, double c0, int first, hipStream_t s);
+// out = L x
+void fixed_L_apply(const GridK& g, const FixedK& K, const double* gg, const double* isg, const double* x,
+                   double* out, hipStream_t s);
+// elementwise helpers
+void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
+void mul(long n, const double* x, const double* y, double* out, hipStream_t s);
+// Fixed energy sums: out = [sum g_half (D+U)^2 (edges), sum g W(U), sum psi q, sum g (f(U) - ubar)] (unscaled)
+void reduce_energy_fixed(const GridK& g, const FixedK& K, const double* gg, const double* U, const double* psi,
+                         const double* q, double* part, double* out, hipStream_t s);
+// Mass projection: U += c on {g > thr}, c = (Q0 - h^d sum g U) / (h^d sum_{g > thr} g), read from sums[0..1].
+template <typename T>
+void mass_project_sums(long n, const T* G, const T* U, double thr, double* part, double* out, hipStream_t s);
+template <typename T>
+void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const double* Q0,
+                        const double* sums, hipStream_t s);
+
+// ------------------------------------------------------------------ narrow band
+// flags[i] = |2 phi_i - 1| < thr (FP64); counts per block, exclusive scan, stable scatter.
+template <typename T>
+void band_flags(long n, const T* phi, double thr, uint8_t* flags, hipStream_t s);
+// Compact flagged indices in ascending order.  blockcnt: scratch of band_blocks(n) + 1 int64.
+long band_blocks(long n);
+void band_compact(long n, const uint8_t* flags, int64_t* blockcnt, int32_t* idx_out, int64_t capacity,
+                  int64_t* total_dev, hipStream_t s);
+
+}  // namespace etd

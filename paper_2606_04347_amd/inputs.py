@@ -221,7 +221,7 @@ class CoupledInputs:
 NAMED_COEFFS = ("kappa", "lambda_surf", "M_area", "lambda_line", "alpha")
 
 
-def coupled_membrane(n: int = 256, seed: int = DEFAULT_SEED, instance: int = 0, R0: float = 1.5,
+def coupled_membrane(n=256, seed: int = DEFAULT_SEED, instance: int = 0, R0: float = 1.5,
                      eps_pm_in_h: float = 3.0, tau: float = 1e-4, half_len: float = math.pi,
                      lmax: int = 4, amp: float = 0.05, base: dict | None = None,
                      coeff_range=(0.5, 2.0), u_amp_pm: float = 0.1, u_mask_pm: float = 0.9,
@@ -234,9 +234,9 @@ def coupled_membrane(n: int = 256, seed: int = DEFAULT_SEED, instance: int = 0, 
     inside the mask and set to 0 outside.  The five named coupling
     coefficients are drawn as base * U(coeff_range).
     """
-    shape = (n, n, n)
+    shape = tuple(n) if isinstance(n, (tuple, list)) else (n, n, n)
     hl = (half_len,) * 3
-    h = 2.0 * half_len / n
+    h = 2.0 * half_len / min(shape)
     eps_pm = eps_pm_in_h * h
     X, Y, Z = mesh(shape, hl)
     r = np.sqrt(X * X + Y * Y + Z * Z)

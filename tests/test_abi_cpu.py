@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects
+invalid descriptors before any HIP call (CPU only: no compute is run)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2606_04347_amd import etd
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "etd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:etd_status|const char\*)\s+(etd_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = etd.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(etd.EXPORTS) == set(names)
+
+
+def _desc(model=etd.COUPLED, shape=(16, 16, 16), tau=1e-4, scheme=2, prec=0):
+    d = (etd.InstanceDesc * 1)()
+    d[0].model, d[0].scheme, d[0].precision = model, scheme, prec
+    d[0].grid = etd.make_grid(shape, (1.0,) * len(shape))
+    d[0].tau = tau
+    d[0].recover_threshold = 1e-3
+    cp = etd.CoupledParams()
+    cp.mu, cp.eps_phi, cp.eps_u = 2.0, 0.3, 0.15
+    fp = etd.FixedParams(0.1, 1.0, 0.4, 600.0, 0.0, 0)
+    d[0].coupled = C.pointer(cp)
+    d[0].fixed = C.pointer(fp)
+    return d, (cp, fp)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda d: setattr(d[0], "tau", 0.0), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "tau", float("nan")), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "grid", etd.make_grid((15, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
+    (lambda d: setattr(d[0], "grid", etd.make_grid((20, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
+    (lambda d: setattr(d[0], "grid", etd.make_grid((1024, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
+    (lambda d: setattr(d[0], "grid", etd.make_grid((16, 16), (1, 1))), etd.ETD_E_ARG),   # coupled is 3D
+    (lambda d: setattr(d[0].grid, "dim", 4), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "model", 7), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "scheme", 3), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "coupled", C.POINTER(etd.CoupledParams)()), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0].coupled.contents, "eps_phi", -1.0), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0].coupled.contents, "gamma", float("inf")), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "recover_threshold", -1.0), etd.ETD_E_ARG),
+    (lambda d: (setattr(d[0], "band_threshold", 0.995), setattr(d[0], "band_rebuild_every", 0)), etd.ETD_E_ARG),
+])
+def test_plan_create_rejects_invalid_descriptors(mutate, status):
+    L = etd.lib()
+    d, keep = _desc()
+    mutate(d)
+    p = C.c_void_p()
+    assert L.etd_plan_create(d, 1, None, C.byref(p)) == status
+    assert not p.value
+    assert L.etd_last_error(None)
+
+
+def test_fixed_membrane_validation():
+    L = etd.lib()
+    d, keep = _desc(model=etd.FIXED_MEMBRANE, shape=(64, 64), scheme=1)
+    d[0].fixed.contents.eps_u = 0.0
+    p = C.c_void_p()
+    assert L.etd_plan_create(d, 1, None, C.byref(p)) == etd.ETD_E_ARG
+    d[0].fixed.contents.eps_u = 0.1
+    d[0].fixed = C.POINTER(etd.FixedParams)()
+    assert L.etd_plan_create(d, 1, None, C.byref(p)) == etd.ETD_E_ARG
+
+
+def test_null_arguments_and_status_strings():
+    L = etd.lib()
+    p = C.c_void_p()
+    assert L.etd_plan_create(None, 1, None, C.byref(p)) == etd.ETD_E_ARG
+    d, keep = _desc()
+    assert L.etd_plan_create(d, 0, None, C.byref(p)) == etd.ETD_E_ARG
+    assert L.etd_step(None, 1) == etd.ETD_E_ARG
+    assert L.etd_plan_destroy(None) == etd.ETD_OK
+    for s in range(-7, 1):
+        assert L.etd_status_string(s)

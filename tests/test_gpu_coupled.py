@@ -1,0 +1,113 @@
+"""GPU: the coupled stabilized ETD1/ETDRK2 step (Algorithm 1) through the C
+ABI against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, needs_gpu, rel_linf, report, torch
+from oracle import band as oband
+from oracle.core import Grid
+from oracle.coupled import CoupledOracle
+from paper_2606_04347_amd import etd, inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def make_case(shape, tau=1e-4, seed=31, **kw):
+    return inputs.coupled_membrane(n=shape, seed=seed, tau=tau, **kw)
+
+
+def run_pair(ci, scheme, precision, nsteps, **inst_kw):
+    grid = Grid(ci.shape, ci.half_len)
+    o = CoupledOracle(grid, ci.params, ci.tau, scheme,
+                      band_threshold=inst_kw.get("band_threshold", 0.0),
+                      band_rebuild_every=inst_kw.get("band_rebuild_every", 10),
+                      mass_projection=bool(inst_kw.get("flags", 0) & etd.F_MASS_PROJECT))
+    o.set_state(ci.phi0, ci.u0)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=scheme, precision=precision, **inst_kw))
+    dt = torch.float64 if precision == etd.FP64 else torch.float32
+    plan.set_state(0, dev(ci.phi0, dt), dev(ci.u0, dt))
+    o.run(nsteps)
+    plan.step(nsteps)
+    phi_g, u_g = plan.get_state(0)
+    return o, plan, host(phi_g), host(u_g)
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+@pytest.mark.parametrize("shape,nsteps", [((16, 16, 16), 1), ((16, 16, 16), 5), ((24, 16, 32), 3),
+                                          ((48, 48, 48), 2)])
+def test_fp64_step_matches_oracle(shape, nsteps, scheme):
+    ci = make_case(shape)
+    o, plan, phi, u = run_pair(ci, scheme, etd.FP64, nsteps)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_fp64", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi, err_u=eu)
+    assert ephi <= 1e-12 and eu <= 1e-12
+    # diagnostics and energy components, FP64
+    d = plan.diagnostics(0)
+    od = o.diagnostics()
+    for k_gpu, k_or in (("int_phi", "I_phi"), ("mass", "m"), ("Q", "Q"), ("umin", "umin"), ("umax", "umax"),
+                        ("bound", "bound")):
+        assert abs(d[k_gpu] - od[k_or]) <= 1e-11 * max(1.0, abs(od[k_or])), (k_gpu, d[k_gpu], od[k_or])
+    e = plan.energy(0)
+    oe = o.energy()
+    for k in ("E_surf", "E_bend", "E_area", "E_ok", "E_nonlocal", "E_mass"):
+        assert abs(e[k] - oe[k]) <= 1e-10 * max(1e-8, abs(oe[k])) + 1e-14, (k, e[k], oe[k])
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_fp32_step_close_to_oracle(scheme):
+    ci = make_case((32, 32, 32))
+    o, plan, phi, u = run_pair(ci, scheme, etd.FP32, 20)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_fp32", scheme=scheme, err_phi=ephi, err_u=eu)
+    assert ephi <= 1e-4 and eu <= 1e-4
+    plan.close()
+
+
+def test_band_restricted_step_matches_oracle():
+    ci = make_case((32, 32, 32))
+    o, plan, phi, u = run_pair(ci, etd.ETDRK2, etd.FP64, 12, band_threshold=0.995, band_rebuild_every=10)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_band", err_phi=ephi, err_u=eu, band=plan.diagnostics(0)["band_count"])
+    assert ephi <= 1e-12 and eu <= 1e-12
+    # the band in use was rebuilt from phi^10
+    assert plan.diagnostics(0)["band_count"] > 0
+    plan.close()
+
+
+def test_mass_projection_matches_oracle_and_conserves():
+    ci = make_case((16, 16, 16))
+    o, plan, phi, u = run_pair(ci, etd.ETDRK2, etd.FP64, 4, flags=etd.F_MASS_PROJECT)
+    assert rel_linf(u, o.u) <= 1e-12
+    # <g(phi^n) U^n, 1>_h is the set_state value Q0
+    assert abs(plan.diagnostics(0)["Q"] - o.Q0) <= 1e-12 * abs(o.Q0)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
+def test_narrowband_list_bit_exact(precision):
+    for shape in ((32, 32, 32), (128, 128, 128)):
+        ci = make_case(shape)
+        dt = torch.float64 if precision == etd.FP64 else torch.float32
+        phi_d = dev(ci.phi0, dt)
+        ref = oband.band_list(host(phi_d), 0.995)      # decided in FP64 on the same values
+        plan = etd.Plan(etd.coupled_instance(ci, precision=precision))
+        idx = plan.narrowband(0, phi_d, 0.995).cpu().numpy()
+        report("band", shape=str(shape), n=len(ref))
+        assert idx.dtype == np.int32 and np.array_equal(idx, ref)
+        with pytest.raises(etd.EtdError) as ei:
+            plan.narrowband(0, phi_d, 0.995, capacity=len(ref) - 1)
+        assert ei.value.status == etd.ETD_E_CAPACITY
+        plan.close()
+
+
+def test_steps_are_deterministic():
+    ci = make_case((24, 24, 24))
+    outs = []
+    for _ in range(2):
+        plan = etd.Plan(etd.coupled_instance(ci))
+        plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+        plan.step(3)
+        outs.append([host(t) for t in plan.get_state(0)])
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

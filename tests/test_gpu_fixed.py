@@ -1,0 +1,133 @@
+"""GPU: the fixed-membrane localization-split ETD1/ETDRK2 step (Section 2.2)
+through the C ABI against the FP64 oracle, plus the discrete maximum bound
+principle and energy decay on the GPU."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, needs_gpu, rel_linf, report, torch
+from oracle import core, fixed
+from oracle.core import Grid
+from paper_2606_04347_amd import etd, inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def oracle_params(fi, B=None):
+    grid = Grid(fi.shape, fi.half_len)
+    C = core.lapinv_inf_norm(grid)
+    Bm = fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, C, grid.volume)
+    return grid, fixed.FixedParams(fi.eps_u, fi.gamma, fi.M, fi.ubar, Bm if B is None else B), C
+
+
+def gpu_run(fi, scheme, nsteps, precision=etd.FP64, B=0.0, flags=0):
+    plan = etd.Plan(etd.fixed_instance(fi, B=B, scheme=scheme, precision=precision, flags=flags))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    plan.step(nsteps)
+    _, u = plan.get_state(0)
+    return plan, host(u)
+
+
+def test_constants_match_oracle():
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    grid, p, C = oracle_params(fi)
+    plan = etd.Plan(etd.fixed_instance(fi))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    assert abs(plan.query(0, etd.Q_C) - C) <= 1e-12 * C
+    assert abs(plan.query(0, etd.Q_B_MBP) - p.B) <= 1e-12 * p.B
+    assert abs(plan.query(0, etd.Q_B) - p.B) <= 1e-12 * p.B
+    Bes = fixed.B_es(fi.eps_u, fi.gamma, fi.M, C, grid.volume)
+    assert abs(plan.query(0, etd.Q_B_ES) - Bes) <= 1e-12 * Bes
+    report("fixed_constants", C=plan.query(0, etd.Q_C), B=plan.query(0, etd.Q_B),
+           rho=plan.query(0, etd.Q_RHO), deg=plan.query(0, etd.Q_CHEB_DEG))
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_fp64_2d_matches_uspace_oracle(scheme):
+    """Config-1 geometry (eps = 0.0625) on 32^2: g reaches 1e-17, and the U-space
+    block-exponential oracle resolves U there to rounding."""
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+    assert fi.g.min() < 1e-15
+    grid, p, _ = oracle_params(fi)
+    ex = fixed.UspaceExpo(fi.g, p, grid, fi.tau)
+    U = fi.u0.copy()
+    for _ in range(10):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, scheme, ex)
+    plan, Ug = gpu_run(fi, scheme, 10)
+    err = rel_linf(Ug, U)
+    report("fixed2d_fp64", scheme=scheme, err=err)
+    assert err <= 1e-12
+    e, oe = plan.energy(0), fixed.energy(U, fi.g, p, grid)
+    for k in ("E", "E_grad", "E_well", "E_nonlocal", "E_mass"):
+        assert abs(e[k] - oe[k]) <= 1e-11 * max(abs(oe[k]), 1e-12), (k, e[k], oe[k])
+    d, od = plan.diagnostics(0), fixed.diagnostics(U, fi.g, p, grid)
+    for k in ("mass", "Q", "umin", "umax", "bound"):
+        ok = {"mass": "m"}.get(k, k)
+        assert abs(d[k] - od[ok]) <= 1e-11 * max(1.0, abs(od[ok])), (k, d[k], od[ok])
+    plan.close()
+
+
+def test_fp64_config1_64x64_etd1_matches_oracle():
+    """64^2 config 1 against the eigendecomposition oracle, compared in the
+    scheme's own variable w = sqrt(g) U (eqn:ODE_eqn): the dense route is
+    accurate to rounding relative to max |w|, not where sqrt(g) ~ 4e-9."""
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    grid, p, _ = oracle_params(fi)
+    ex = fixed.DenseExpo(fi.g, p, grid)
+    U = fi.u0.copy()
+    for _ in range(5):
+        U = fixed.etd1_step(U, fi.g, p, grid, fi.tau, ex)
+    plan, Ug = gpu_run(fi, etd.ETD1, 5)
+    sg = np.sqrt(fi.g)
+    err_w = rel_linf(sg * Ug, sg * U)
+    sel = fi.g >= 1e-4          # where the dense route's w-space rounding stays below 1e-12 in U
+    err_u = rel_linf(Ug[sel], U[sel])
+    report("fixed_config1", err_w=err_w, err_u_g_ge_1e4=err_u, err_u_all=rel_linf(Ug, U))
+    assert err_w <= 1e-12 and err_u <= 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_fp64_3d_matches_lanczos_oracle(scheme):
+    fi = inputs.fixed_membrane(dim=3, n=24, eps_pm_in_h=2.0, tau=0.02)
+    grid, p, _ = oracle_params(fi)
+    ex = fixed.LanczosExpo(fi.g, p, grid)
+    U = fi.u0.copy()
+    for _ in range(3):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, scheme, ex)
+    plan, Ug = gpu_run(fi, scheme, 3)
+    err = rel_linf(Ug, U)
+    report("fixed3d_fp64", scheme=scheme, err=err)
+    assert err <= 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_mbp_and_energy_decay_on_gpu(scheme):
+    """Theorems thm:MBP and thm:Energy on the 64^2 configuration, 200 steps."""
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    plan = etd.Plan(etd.fixed_instance(fi, scheme=scheme))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    E0 = plan.energy(0)["E"]
+    for k in range(20):
+        plan.step(10)
+        d = plan.diagnostics(0)
+        E1 = plan.energy(0)["E"]
+        assert d["umin"] >= 0.0 and d["umax"] <= 1.0 and d["bound"] <= 1.0
+        assert E1 <= E0 + 1e-13 * abs(E0)
+        E0 = E1
+    report("fixed_mbp_energy", scheme=scheme, E=E0, bound=d["bound"])
+    plan.close()
+
+
+def test_fp32_fft_variant_close_and_bounded():
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    grid, p, _ = oracle_params(fi)
+    _, U64 = gpu_run(fi, etd.ETDRK2, 20)
+    plan, U32 = gpu_run(fi, etd.ETDRK2, 20, precision=etd.FP32)
+    err = rel_linf(U32, U64)
+    report("fixed_fp32fft", err=err)
+    assert err <= 1e-5
+    d = plan.diagnostics(0)
+    assert d["umin"] >= 0.0 and d["umax"] <= 1.0
+    plan.close()

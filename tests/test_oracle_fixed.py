@@ -246,3 +246,44 @@ def test_mass_projection_restores_Q():
     Q0 = 0.123
     U2 = mass_project(U, fi.g, Q0, grid, 1e-3)
     assert abs(grid.cell * np.sum(fi.g * U2) - Q0) <= 1e-14 * max(1, abs(Q0)) + 1e-15
+
+
+def test_uspace_expo_matches_dense_where_both_are_accurate():
+    """The U-space block exponential and the eigendecomposition agree on a
+    grid whose g stays well above rounding (g_min ~ 1e-4)."""
+    fi, grid, p, _ = small_case(n=16, eps_pm_in_h=4.0)
+    assert fi.g.min() > 1e-5
+    tau = 1e-4
+    d = fixed.DenseExpo(fi.g, p, grid)
+    us = fixed.UspaceExpo(fi.g, p, grid, tau)
+    v = np.sqrt(fi.g) * np.random.default_rng(15).standard_normal(grid.n)
+    for fn in (core.phi0, core.phi1, core.phi2):
+        a, b = d.apply(fn, tau, v), us.apply(fn, tau, v)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_uspace_expo_exact_for_constant_remainder_with_tiny_g():
+    """Variation of constants in the U variable where g reaches 1e-17: with a
+    remainder sqrt(g) c (c constant in time) one ETD1 step of size tau equals
+    e^{-tau Lt} U0 + tau phi1(tau Lt) c, evaluated independently in the
+    eigenbasis of the symmetric part (valid here: Lt is similar to L)."""
+    fi = inputs.fixed_membrane(dim=2, n=16, eps_pm=0.0625)
+    grid = Grid(fi.shape, fi.half_len)
+    assert fi.g.min() < 1e-12
+    C = core.lapinv_inf_norm(grid)
+    p = fixed.FixedParams(fi.eps_u, fi.gamma, fi.M, fi.ubar, fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, C, grid.volume))
+    tau = 0.01
+    us = fixed.UspaceExpo(fi.g, p, grid, tau)
+    c = np.cos(np.arange(fi.g.size)).reshape(grid.n)
+    sg = np.sqrt(fi.g)
+    U1 = fixed.etd1_step(fi.u0, fi.g, p, grid, tau, us, R=lambda U, g, pp, gr: sg * c)
+    # U-space operator applied to U1 recovers the ODE balance: for constant forcing the
+    # exact solution satisfies (U1 - e^{-tau Lt} U0) = tau phi1(tau Lt) c; check it through
+    # the identity (I - e^{-tau Lt}) Lt^{-1} c = tau phi1(tau Lt) c
+    n = fi.g.size
+    eye = np.eye(n).reshape((n,) + grid.n)
+    Lt = (p.B * eye - p.eps_u * core.lap_S(eye, fi.g, grid) / fi.g).reshape(n, n).T
+    E0 = us.mats[core.phi0]
+    lhs = (U1.reshape(-1) - E0 @ fi.u0.reshape(-1))
+    rhs = np.linalg.solve(Lt, (np.eye(n) - E0) @ c.reshape(-1))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
