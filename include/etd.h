@@ -202,6 +202,20 @@ typedef enum {
 etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op, const void* in, void* out,
                               etd_dtype dtype);
 
+/* Per-pass timing of the FFT kernels (a measurement aid).  enable != 0 starts
+ * a measurement: every FFT pass launched afterwards by calls on this plan is
+ * bracketed by HIP events recorded on the plan's stream.  enable == 0 stops
+ * it, synchronizes, and fills out (may be NULL) for the pass kinds
+ * k = 0..3 (z-line r2c, z-line c2r, y lines, x lines): the number of launches,
+ * their summed event-timed duration in ms, and the algorithmic bytes they move
+ * (each input element read once, each output element written once). */
+typedef struct {
+    int64_t launches[4];
+    double total_ms[4];
+    double bytes[4];
+} etd_pass_times;
+etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out);
+
 /* Scalar plan facts for one instance (host doubles):
  *   ETD_Q_B          stabilizer B in use (fixed)
  *   ETD_Q_B_MBP      B_MBP of (eqn:cond_MBP) (fixed)

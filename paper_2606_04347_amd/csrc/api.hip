@@ -71,11 +71,57 @@ struct Instance {
 
 }  // namespace
 
+namespace {
+
+// Event pairs around FFT pass launches (etd_pass_timing).
+struct EventHook : PassHook {
+    struct Rec {
+        int kind;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    hipEvent_t pending = nullptr;
+    void begin(int, hipStream_t s) override {
+        pending = take();
+        if (pending) (void)hipEventRecord(pending, s);
+    }
+    void end(int kind, double bytes, hipStream_t s) override {
+        hipEvent_t e1 = take();
+        if (!pending || !e1) return;
+        (void)hipEventRecord(e1, s);
+        recs.push_back({kind, bytes, pending, e1});
+        pending = nullptr;
+    }
+    void reset() {
+        used = 0;
+        recs.clear();
+        pending = nullptr;
+    }
+    ~EventHook() override {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
 struct etd_plan {
     std::vector<Instance> inst;
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
+    EventHook hook;
+    bool timing = false;
 };
 
 namespace {
@@ -652,6 +698,7 @@ etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void*
 
 etd_status etd_plan_destroy(etd_plan_t plan) {
     if (!plan) return ETD_OK;
+    if (plan->timing) fft_set_pass_hook(nullptr);
     (void)hipStreamSynchronize(plan->stream);
     for (Instance& I : plan->inst)
         for (void* p : I.allocs) (void)hipFree(p);
@@ -905,6 +952,30 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
         e = I.f32 ? run(0.0f, I.qf, I.Sb, I.Sb, I.Sgu, I.tf) : run(0.0, I.q, I.Sa, I.Sa, I.Stmp, I.td);
     }
     if (e != hipSuccess) return fail(&plan->err, ETD_E_HIP, std::string("spectral_apply: ") + hipGetErrorString(e));
+    return ETD_OK;
+}
+
+etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out) {
+    if (!plan) return fail(nullptr, ETD_E_ARG, "null plan");
+    if (enable) {
+        plan->hook.reset();
+        plan->timing = true;
+        fft_set_pass_hook(&plan->hook);
+        return ETD_OK;
+    }
+    fft_set_pass_hook(nullptr);
+    plan->timing = false;
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    etd_pass_times t{};
+    for (const auto& r : plan->hook.recs) {
+        float ms = 0.f;
+        HIPCHK(plan, hipEventElapsedTime(&ms, r.e0, r.e1));
+        t.launches[r.kind] += 1;
+        t.total_ms[r.kind] += ms;
+        t.bytes[r.kind] += r.bytes;
+    }
+    plan->hook.reset();
+    if (out) *out = t;
     return ETD_OK;
 }
 

@@ -39,10 +39,14 @@ struct Wave {
 };
 
 __device__ __forceinline__ Wave wave(const GridK& g, long idx, bool need_mu) {
-    const int iz = (int)(idx % g.nzh);
-    const long t = idx / g.nzh;
-    const int iy = (int)(t % g.ny);
-    const int ix = (int)(t / g.ny);
+    // the half spectrum has fewer than 2^32 entries: 32-bit decode (64-bit
+    // division is a long software sequence on the GPU)
+    const unsigned u = (unsigned)idx;
+    const unsigned t = u / (unsigned)g.nzh;
+    const int iz = (int)(u - t * (unsigned)g.nzh);
+    const unsigned ix_ = t / (unsigned)g.ny;
+    const int iy = (int)(t - ix_ * (unsigned)g.ny);
+    const int ix = (int)ix_;
     const double ax = kPi / g.X[0], ay = kPi / g.X[1], az = kPi / g.X[2];
     const double lx = ax * lam_index(ix, g.nx), ly = ay * lam_index(iy, g.ny), lz = az * iz;
     Wave w;
@@ -156,10 +160,12 @@ struct Nbr {
     long c, xm, xp, ym, yp, zm, zp;
 };
 __device__ __forceinline__ Nbr neighbours(const GridK& g, long i) {
-    const int iz = (int)(i % g.nz);
-    const long t = i / g.nz;
-    const int iy = (int)(t % g.ny);
-    const int ix = (int)(t / g.ny);
+    const unsigned u = (unsigned)i;     // grids hold fewer than 2^31 points
+    const unsigned t = u / (unsigned)g.nz;
+    const int iz = (int)(u - t * (unsigned)g.nz);
+    const unsigned ix_ = t / (unsigned)g.ny;
+    const int iy = (int)(t - ix_ * (unsigned)g.ny);
+    const int ix = (int)ix_;
     const long sx = (long)g.ny * g.nz, sy = g.nz;
     Nbr n;
     n.c = i;

@@ -18,6 +18,17 @@ template <typename T> struct FFTTables {
 // True if a 1D transform of this length is compiled in (8..512, 2^a or 3 * 2^a).
 bool fft_length_supported(int n);
 
+// Optional per-launch timing of the FFT passes: when set, every pass launch is
+// bracketed by begin(kind) / end(kind) on its stream.  kind: 0 z-r2c, 1 z-c2r,
+// 2 y lines, 3 x lines.  bytes: algorithmic bytes the launch must move (each
+// input element read once, each output element written once).
+struct PassHook {
+    virtual void begin(int kind, hipStream_t s) = 0;
+    virtual void end(int kind, double bytes, hipStream_t s) = 0;
+    virtual ~PassHook() = default;
+};
+void fft_set_pass_hook(PassHook* h);
+
 // Host-side table of exp(-2 pi i k / n), k < n, in double (extended-precision trig).
 void fft_twiddles_host(int n, double* re_im /* 2n values */);
 

@@ -92,6 +92,19 @@ template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(c2<T>
     else dft8<T, DIR>(v);
 }
 
+// LDS layout of one line: element e sits at slot e + (e >> 4), one pad slot per
+// 16 elements, which spreads the strided writes of the early Stockham stages
+// (stride R Ns) over the LDS banks.
+__host__ __device__ __forceinline__ constexpr int sk(int e) { return e + (e >> 4); }
+template <int N> constexpr int line_stride() { return N + (N >> 4) + 1; }
+
+// Round-robin dispatch puts block b on XCD b % 8; renumber so that each XCD
+// works on one contiguous range of tiles (neighbouring tiles share L2 lines).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 // One radix-R Stockham stage on L lines of length N in LDS (line stride LS).
 template <typename T, int N, int L, int LS, int R, int NS, int DIR>
 __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
@@ -105,9 +118,9 @@ __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
         const int b = tid + i * kThreads;
         if ((NB % kThreads == 0) || b < NB) {
             const int l = b / NR, j = b % NR;
-            const c2<T>* src = lds + l * LS + j;
+            const c2<T>* src = lds + l * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[r * NR];
+            for (int r = 0; r < R; ++r) v[i][r] = src[sk(j + r * NR)];
             if constexpr (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
@@ -127,9 +140,10 @@ __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
         if ((NB % kThreads == 0) || b < NB) {
             const int l = b / NR, j = b % NR;
             const int k = j % NS;
-            c2<T>* dst = lds + l * LS + (j / NS) * NS * R + k;
+            c2<T>* dst = lds + l * LS;
+            const int o = (j / NS) * NS * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+            for (int r = 0; r < R; ++r) dst[sk(o + r * NS)] = v[i][r];
         }
     }
     __syncthreads();
@@ -151,30 +165,45 @@ template <typename T> __device__ __forceinline__ void load_table(c2<T>* dst, con
 // ---------------------------------------------------------------- strided lines
 template <int N> constexpr int strided_lines() { return N <= 256 ? 16 : 8; }
 
+// Lines are numbered j = o * C + c (o the outer index, c the contiguous column
+// index, C columns); line j starts at o * ostride + c and its elements are
+// estride apart.  A workgroup takes L consecutive line numbers, so no tile is
+// ragged and (for the x pass, where o * ostride + c == j) every tile row is one
+// aligned run of L complex values.
 template <typename T, int N, int DIR>
-__global__ __launch_bounds__(kThreads) void k_fft_strided(const c2<T>* in, c2<T>* out,
-                                                          const c2<T>* __restrict__ tw, int C, int ntiles,
-                                                          long ostride, long estride) {
+__device__ __forceinline__ void fft_lines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw, int C,
+                                          int nlines, long ostride, long estride) {
     constexpr int L = strided_lines<N>();
-    constexpr int LS = N + 1;
+    constexpr int LS = line_stride<N>();
+    static_assert(kThreads % L == 0, "a thread keeps one line in the load/store loops");
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * LS;
     load_table<T>(stw, tw, N);
-    const int o = blockIdx.x / ntiles;
-    const int c0 = (blockIdx.x % ntiles) * L;
-    const int nl = min(L, C - c0);
-    const long base = (long)o * ostride + c0;
-    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-        const int l = idx % L, e = idx / L;
-        lds[l * LS + e] = (l < nl) ? in[base + l + (long)e * estride] : mk<T>(0, 0);
-    }
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int l = threadIdx.x % L;
+    const int j = tile * L + l;
+    const bool valid = j < nlines;
+    const long base = valid ? (long)(j / C) * ostride + (j % C) : 0;
+    c2<T>* row = lds + l * LS;
+    for (int e = threadIdx.x / L; e < N; e += kThreads / L)
+        row[sk(e)] = valid ? in[base + (long)e * estride] : mk<T>(0, 0);
     __syncthreads();
     stockham<T, N, L, LS, 1, DIR>(lds, stw);
-    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-        const int l = idx % L, e = idx / L;
-        if (l < nl) out[base + l + (long)e * estride] = lds[l * LS + e];
-    }
+    if (valid)
+        for (int e = threadIdx.x / L; e < N; e += kThreads / L) out[base + (long)e * estride] = row[sk(e)];
+}
+
+// The y- and x-line passes share the body; separate symbols keep them apart in traces.
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_ylines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
+                                                         int C, int nlines, long ostride, long estride) {
+    fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
+}
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(kThreads) void k_fft_xlines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
+                                                         int C, int nlines, long ostride, long estride) {
+    fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
 }
 
 // ---------------------------------------------------------------- z rows (r2c / c2r)
@@ -186,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in
                                                         const c2<T>* __restrict__ twf, long nrows) {
     constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
-    constexpr int LS = M + 1;
+    constexpr int LS = line_stride<M + 1>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * LS;
@@ -196,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in
     const c2<T>* src = reinterpret_cast<const c2<T>*>(in + row0 * NR);
     for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
         const int r = idx / M, n = idx % M;
-        lds[r * LS + n] = (r < nl) ? src[idx] : mk<T>(0, 0);
+        lds[r * LS + sk(n)] = (r < nl) ? src[idx] : mk<T>(0, 0);
     }
     __syncthreads();
     stockham<T, M, L, LS, 1, -1>(lds, stw);
@@ -205,8 +234,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in
     for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
         const int r = idx / (M + 1), k = idx % (M + 1);
         if (r < nl) {
-            const c2<T> zk = lds[r * LS + (k == M ? 0 : k)];
-            const c2<T> zc = cconj(lds[r * LS + (k == 0 ? 0 : M - k)]);
+            const c2<T> zk = lds[r * LS + sk(k == M ? 0 : k)];
+            const c2<T> zc = cconj(lds[r * LS + sk(k == 0 ? 0 : M - k)]);
             const c2<T> ev = cadd(zk, zc);                  // 2 E_k
             const c2<T> od = csub(zk, zc);                  // 2 i O_k
             const c2<T> w = twf[k];
@@ -224,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
                                                         T scale) {
     constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
-    constexpr int LS = M + 1;
+    constexpr int LS = line_stride<M + 1>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * LS;
@@ -234,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
     const c2<T>* src = in + row0 * (M + 1);
     for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
         const int r = idx / (M + 1), k = idx % (M + 1);
-        lds[r * LS + k] = (r < nl) ? src[idx] : mk<T>(0, 0);
+        lds[r * LS + sk(k)] = (r < nl) ? src[idx] : mk<T>(0, 0);
     }
     __syncthreads();
     // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{+2 pi i k / NR}; each thread
@@ -243,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
     for (int idx = threadIdx.x; idx < L * HP; idx += kThreads) {
         const int r = idx / HP, k = idx % HP;
         c2<T>* row = lds + r * LS;
-        c2<T> a = row[k], b = row[M - k];
+        c2<T> a = row[sk(k)], b = row[sk(M - k)];
         if (k == 0) {
             a.y = 0;
             b.y = 0;
@@ -251,12 +280,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
         {
             const c2<T> s = cadd(a, cconj(b));
             const c2<T> d = cmul(csub(a, cconj(b)), cconj(twf[k]));
-            row[k] = mk<T>(s.x - d.y, s.y + d.x);
+            row[sk(k)] = mk<T>(s.x - d.y, s.y + d.x);
         }
         if (k != 0 && 2 * k != M) {
             const c2<T> s = cadd(b, cconj(a));
             const c2<T> d = cmul(csub(b, cconj(a)), cconj(twf[M - k]));
-            row[M - k] = mk<T>(s.x - d.y, s.y + d.x);
+            row[sk(M - k)] = mk<T>(s.x - d.y, s.y + d.x);
         }
     }
     __syncthreads();
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
     c2<T>* dst = reinterpret_cast<c2<T>*>(out + row0 * NR);
     for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
         const int r = idx / M, n = idx % M;
-        if (r < nl) dst[idx] = cscale(lds[r * LS + n], scale);
+        if (r < nl) dst[idx] = cscale(lds[r * LS + sk(n)], scale);
     }
 }
 
@@ -278,17 +307,18 @@ template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag
     });
 }
 
-template <typename T, int N, int DIR>
+template <typename T, int N, int DIR, bool XLINES>
 hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter, long ostride,
                           long estride, hipStream_t s) {
     constexpr int L = strided_lines<N>();
-    const size_t smem = sizeof(c2<T>) * (size_t)(L * (N + 1) + N);
-    auto kern = k_fft_strided<T, N, DIR>;
+    const size_t smem = sizeof(c2<T>) * (size_t)(L * line_stride<N>() + N);
+    auto kern = XLINES ? k_fft_xlines<T, N, DIR> : k_fft_ylines<T, N, DIR>;
     static std::once_flag flag;
     set_smem_limit(kern, smem, flag);
-    const int ntiles = (C + L - 1) / L;
-    hipLaunchKernelGGL(kern, dim3(ntiles * nouter), dim3(kThreads), smem, s, in, out, tw, C, ntiles,
-                       ostride, estride);
+    const long nlines = (long)C * nouter;
+    const int ntiles = (int)((nlines + L - 1) / L);
+    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), smem, s, in, out, tw, C, (int)nlines, ostride,
+                       estride);
     return hipGetLastError();
 }
 
@@ -296,7 +326,7 @@ template <typename T, int NR>
 hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, const c2<T>* twf, long nrows,
                     T scale, hipStream_t s) {
     constexpr int L = z_rows<NR>();
-    const size_t smem = sizeof(c2<T>) * (size_t)(L * (NR / 2 + 1) + NR / 2);
+    const size_t smem = sizeof(c2<T>) * (size_t)(L * line_stride<NR / 2 + 1>() + NR / 2);
     const int nblk = (int)((nrows + L - 1) / L);
     if (forward) {
         auto kern = k_fft_z_r2c<T, NR>;
@@ -316,12 +346,12 @@ hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, c
 
 #define ETD_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(12) X(24) X(48) X(96) X(192) X(384)
 
-template <typename T, int DIR>
+template <typename T, int DIR, bool XLINES>
 hipError_t dispatch_strided(int N, const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter,
                             long ostride, long estride, hipStream_t s) {
     switch (N) {
 #define CASE(n) \
-    case n: return launch_strided<T, n, DIR>(in, out, tw, C, nouter, ostride, estride, s);
+    case n: return launch_strided<T, n, DIR, XLINES>(in, out, tw, C, nouter, ostride, estride, s);
         ETD_FFT_SIZES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -372,17 +402,36 @@ void fft_twiddles_host(int n, double* re_im) {
     }
 }
 
+PassHook* g_hook = nullptr;
+
+void fft_set_pass_hook(PassHook* h) { g_hook = h; }
+
+// Run one pass launch under the optional timing hook.
+template <typename F> hipError_t timed_pass(int kind, double bytes, hipStream_t s, F&& launch) {
+    if (g_hook) g_hook->begin(kind, s);
+    hipError_t e = launch();
+    if (g_hook) g_hook->end(kind, bytes, s);
+    return e;
+}
+
 template <typename T>
 hipError_t fft_r2c_3d(const GridK& g, const FFTTables<T>& t, const T* in, c2<T>* out, hipStream_t s) {
     const long rows = (long)g.nx * g.ny;
-    hipError_t e = dispatch_z<T>(g.nz, true, in, out, t.tzh, t.tzf, rows, (T)1, s);
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();     // one complex half spectrum
+    hipError_t e = timed_pass(0, cb + sizeof(T) * (double)g.nreal(), s, [&] {
+        return dispatch_z<T>(g.nz, true, in, out, t.tzh, t.tzf, rows, (T)1, s);
+    });
     if (e != hipSuccess) return e;
     if (g.ny > 1) {   // y lines: outer x, stride nzh
-        e = dispatch_strided<T, -1>(g.ny, out, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        e = timed_pass(2, 2.0 * cb, s, [&] {
+            return dispatch_strided<T, -1, false>(g.ny, out, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        });
         if (e != hipSuccess) return e;
     }
     if (g.nx > 1) {   // x lines: outer y, stride ny * nzh
-        e = dispatch_strided<T, -1>(g.nx, out, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+        e = timed_pass(3, 2.0 * cb, s, [&] {
+            return dispatch_strided<T, -1, true>(g.nx, out, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+        });
     }
     return e;
 }
@@ -392,18 +441,25 @@ hipError_t fft_c2r_3d(const GridK& g, const FFTTables<T>& t, const c2<T>* in, c2
                       hipStream_t s) {
     const c2<T>* cur = in;
     hipError_t e = hipSuccess;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     if (g.nx > 1) {
-        e = dispatch_strided<T, +1>(g.nx, cur, tmp, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+        e = timed_pass(3, 2.0 * cb, s, [&] {
+            return dispatch_strided<T, +1, true>(g.nx, cur, tmp, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+        });
         if (e != hipSuccess) return e;
         cur = tmp;
     }
     if (g.ny > 1) {
-        e = dispatch_strided<T, +1>(g.ny, cur, tmp, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        e = timed_pass(2, 2.0 * cb, s, [&] {
+            return dispatch_strided<T, +1, false>(g.ny, cur, tmp, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+        });
         if (e != hipSuccess) return e;
         cur = tmp;
     }
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
-    return dispatch_z<T>(g.nz, false, cur, out, t.tzh, t.tzf, (long)g.nx * g.ny, scale, s);
+    return timed_pass(1, cb + sizeof(T) * (double)g.nreal(), s, [&] {
+        return dispatch_z<T>(g.nz, false, cur, out, t.tzh, t.tzf, (long)g.nx * g.ny, scale, s);
+    });
 }
 
 template hipError_t fft_r2c_3d<float>(const GridK&, const FFTTables<float>&, const float*, float2*, hipStream_t);

@@ -51,10 +51,12 @@ __global__ void k_remainder(long n, FixedK K, const double* __restrict__ sg, con
 // (H x)_i with H = -isg_i sum_d D^-(g_{i+1/2} D^+(isg x))
 __device__ __forceinline__ double H_apply(const GridK& g, long i, const double* G, const double* isg,
                                           const double* x) {
-    const int iz = (int)(i % g.nz);
-    const long t = i / g.nz;
-    const int iy = (int)(t % g.ny);
-    const int ix = (int)(t / g.ny);
+    const unsigned u = (unsigned)i;
+    const unsigned t = u / (unsigned)g.nz;
+    const int iz = (int)(u - t * (unsigned)g.nz);
+    const unsigned ix_ = t / (unsigned)g.ny;
+    const int iy = (int)(t - ix_ * (unsigned)g.ny);
+    const int ix = (int)ix_;
     const long sx = (long)g.ny * g.nz, sy = g.nz;
     const double gc = G[i];
     const double zc = isg[i] * x[i];

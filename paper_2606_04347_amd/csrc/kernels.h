@@ -57,7 +57,7 @@ template <typename T>
 void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s);
 
 // ------------------------------------------------------------------ reductions (FP64, deterministic)
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;
 
 // out[0] = scale * sum_i x_i  (Neumaier-compensated, fixed order).  part: kRedBlocks doubles.
 template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s);

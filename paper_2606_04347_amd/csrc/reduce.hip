@@ -134,10 +134,12 @@ struct Idx3 {
     long xp, yp, zp;
 };
 __device__ __forceinline__ Idx3 plus_neighbours(const GridK& g, long i) {
-    const int iz = (int)(i % g.nz);
-    const long t = i / g.nz;
-    const int iy = (int)(t % g.ny);
-    const int ix = (int)(t / g.ny);
+    const unsigned u = (unsigned)i;
+    const unsigned t = u / (unsigned)g.nz;
+    const int iz = (int)(u - t * (unsigned)g.nz);
+    const unsigned ix_ = t / (unsigned)g.ny;
+    const int iy = (int)(t - ix_ * (unsigned)g.ny);
+    const int ix = (int)ix_;
     const long sx = (long)g.ny * g.nz, sy = g.nz;
     Idx3 r;
     r.xp = i + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);

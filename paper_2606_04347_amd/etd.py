@@ -27,7 +27,8 @@ Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
 
 EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
-           "etd_plan_query", "etd_status_string", "etd_last_error")
+           "etd_pass_timing", "etd_plan_query", "etd_status_string", "etd_last_error")
+PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines")
 
 
 class Grid(C.Structure):
@@ -52,6 +53,10 @@ class InstanceDesc(C.Structure):
                 ("fixed", C.POINTER(FixedParams)), ("band_threshold", C.c_double),
                 ("band_rebuild_every", C.c_int), ("recover_threshold", C.c_double),
                 ("flags", C.c_uint)]
+
+
+class PassTimes(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 4), ("total_ms", C.c_double * 4), ("bytes", C.c_double * 4)]
 
 
 class Diag(C.Structure):
@@ -82,6 +87,7 @@ def lib():
         L.etd_narrowband_build.argtypes = [vp, i, vp, i, d, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.etd_spectral_apply.argtypes = [vp, i, i, vp, vp, i]
         L.etd_plan_query.argtypes = [vp, i, i, C.POINTER(d)]
+        L.etd_pass_timing.argtypes = [vp, i, C.POINTER(PassTimes)]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -246,6 +252,15 @@ class Plan:
         out = torch.empty_like(x) if out is None else out
         self._c(lib().etd_spectral_apply(self._ptr, i, int(op), self._dev(x), self._dev(out), self._dt(x)))
         return out
+
+    def pass_timing(self, enable):
+        """Start (True) or stop (False) FFT pass timing; stop returns per-kind totals."""
+        t = PassTimes()
+        self._c(lib().etd_pass_timing(self._ptr, 1 if enable else 0, C.byref(t)))
+        if enable:
+            return None
+        return {k: dict(launches=t.launches[n], ms=t.total_ms[n], bytes=t.bytes[n])
+                for n, k in enumerate(PASS_KINDS)}
 
     def query(self, i, what):
         v = C.c_double(0.0)

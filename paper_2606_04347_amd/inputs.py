@@ -240,16 +240,37 @@ def coupled_membrane(n=256, seed: int = DEFAULT_SEED, instance: int = 0, R0: flo
     eps_pm = eps_pm_in_h * h
     X, Y, Z = mesh(shape, hl)
     r = np.sqrt(X * X + Y * Y + Z * Z)
-    theta = np.arccos(np.clip(np.divide(Z, r, out=np.ones_like(Z), where=r > 0), -1.0, 1.0))
+    ct = np.clip(np.divide(Z, r, out=np.ones_like(Z), where=r > 0), -1.0, 1.0)   # cos(theta)
     azim = np.arctan2(Y, X)
+    del X, Y, Z
     nco = sum(2 * l + 1 for l in range(1, lmax + 1))
     a = normal(seed, instance, 2, nco)
-    pert = np.zeros(shape)
+    # sum_{l=1..lmax, m=-l..l} a_lm Y_lm with a_lm in (l, m) order; the Legendre
+    # functions of one order m are built once by the upward recurrence in l
+    coef = {}
     c = 0
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
-            pert += a[c] * real_sph_harm(l, m, theta, azim)
+            coef[(l, m)] = a[c]
             c += 1
+    pert = np.zeros(shape)
+    for m in range(0, lmax + 1):
+        plm = {m: _assoc_legendre(m, m, ct)}
+        if m + 1 <= lmax:
+            plm[m + 1] = _assoc_legendre(m + 1, m, ct)
+        for l in range(m + 2, lmax + 1):
+            plm[l] = ((2 * l - 1) * ct * plm[l - 1] - (l + m - 1) * plm[l - 2]) / (l - m)
+        if m == 0:
+            for l in range(1, lmax + 1):
+                nrm = math.sqrt((2 * l + 1) / (4 * math.pi))
+                pert += (coef[(l, 0)] * nrm) * plm[l]
+        else:
+            cm, sm = np.cos(m * azim), np.sin(m * azim)
+            for l in range(m, lmax + 1):
+                nrm = math.sqrt(2.0) * math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - m)
+                                                 / math.factorial(l + m))
+                pert += (nrm * plm[l]) * (coef[(l, m)] * cm + coef[(l, -m)] * sm)
+    del ct, azim
     R = R0 * (1.0 + amp * pert)
     phi_pm = np.tanh((R - r) / (math.sqrt(2.0) * eps_pm))
     phi0 = 0.5 * (1.0 + phi_pm)
