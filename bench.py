@@ -77,14 +77,32 @@ def run_precision(ci, prec, dt, steps, warmup, pass_steps):
     return ms, passes
 
 
-def roofline(passes, pass_steps):
+def measured_traffic(kind, n, precision):
+    """HBM bytes per launch of a pass kind from the committed counter summary
+    (profiles/traffic_fp32_256cubed.json: calibrated FETCH_SIZE + WRITE_SIZE),
+    only while the FFT source is the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_fp32_256cubed.json")
+    src = os.path.join(ROOT, "paper_2606_04347_amd", "csrc", "fft.hip")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("fft_source_sha256") != h or rec.get("grid") != n or rec.get("precision") != precision:
+        return None
+    p = rec.get("passes", {}).get(kind)
+    return p["bytes_per_launch"] if p else None
+
+
+def roofline(passes, pass_steps, n, precision):
     kind = max(passes, key=lambda k: passes[k]["ms"])
     p = passes[kind]
     avg_ms = p["ms"] / max(p["launches"], 1)
     per_launch = p["bytes"] / max(p["launches"], 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind, n, precision),
             "kernel": kind, "launches_per_step": p["launches"] / pass_steps,
             "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
 
@@ -163,7 +181,7 @@ def main():
             continue
         ms, passes = run_precision(ci, prec, dt, a.steps, a.warmup, pass_steps)
         res[name] = dict(ms_per_step=ms / a.steps, value=npts * a.steps / (ms * 1e-3),
-                         roofline=roofline(passes, pass_steps))
+                         roofline=roofline(passes, pass_steps, n, name))
         log(f"{name}: {ms / a.steps:.3f} ms/step, {res[name]['value']:.3e} pt-steps/s, "
             f"dominant {res[name]['roofline']['kernel']} {res[name]['roofline']['achieved']:.0f} GB/s")
     out = {

@@ -58,6 +58,7 @@ struct Instance {
     int64_t* band_total = nullptr;
     double* scal = nullptr;
     double* part = nullptr;
+    double* fd = nullptr;          // per-axis FD symbol tables 4/h^2 sin^2(pi i / N)
     CoupledK K{};
     FixedK FK{};
     double A0 = 0.0;
@@ -350,7 +351,7 @@ etd_status setup_fixed(etd_plan* P, Instance& I) {
     hipStream_t s = P->stream;
     set_delta(g.nreal(), I.q, s);
     HIPCHK(P, fft_r2c_3d<double>(g, I.td, I.q, (double2*)I.Sa, s));
-    spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+    spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, I.fd, s);
     HIPCHK(P, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
     reduce_abs_sum(g.nreal(), I.psid, I.part, I.scal + S_ABS, s);
     HIPCHK(P, hipGetLastError());
@@ -370,6 +371,21 @@ etd_status setup_common(etd_plan* P, Instance& I) {
     ALLOC(I.scal, S_COUNT * sizeof(double));
     ALLOC(I.part, (size_t)kRedBlocks * 8 * sizeof(double));
     HIPCHK(P, hipMemset(I.scal, 0, S_COUNT * sizeof(double)));
+    // eigenvalues of the periodic second difference per axis, mu_d(i) = (4/h^2) sin^2(pi i / N)
+    const GridK& g = I.g;
+    const int ns[3] = {g.nx, g.ny, g.nz};
+    std::vector<double> fd;
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < ns[d]; ++i) {
+            if (ns[d] == 1) {
+                fd.push_back(0.0);
+                continue;
+            }
+            const long double sn = sinl(3.141592653589793238462643383279502884L * i / ns[d]);
+            fd.push_back((double)(4.0L / ((long double)g.h[d] * g.h[d]) * sn * sn));
+        }
+    ALLOC(I.fd, fd.size() * sizeof(double));
+    HIPCHK(P, hipMemcpy(I.fd, fd.data(), fd.size() * sizeof(double), hipMemcpyHostToDevice));
     return ETD_OK;
 }
 
@@ -408,7 +424,7 @@ hipError_t phi_and_derivs(const Instance& I, const c2<T>* S, T* phi, T* lap, T* 
     const SpecOp ops[4] = {SPEC_NEG_K2, SPEC_IKX, SPEC_IKY, SPEC_IKZ};
     T* outs[4] = {lap, gx, gy, gz};
     for (int k = 0; k < 4; ++k) {
-        spec_apply<T>(g, ops[k], S, work, s);
+        spec_apply<T>(g, ops[k], S, work, I.fd, s);
         if ((e = fft_c2r_3d<T>(g, t, work, tmp, outs[k], s)) != hipSuccess) return e;
     }
     return hipGetLastError();
@@ -424,7 +440,7 @@ hipError_t u_remainder(Instance& I, CoupledView<T>& v, const T* uu, const uint8_
     reduce_sum<T>(g.nreal(), v.P, g.cell, I.part, I.scal + S_MASS, s);
     hipError_t e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s);
     if (e != hipSuccess) return e;
-    spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, s);
+    spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
     if ((e = fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s)) != hipSuccess) return e;
     if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
     coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
@@ -498,12 +514,12 @@ etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStrea
     const GridK& g = I.g;
     if (!I.f32) {
         HIPCHK(plan, fft_r2c_3d<double>(g, I.td, q, (double2*)I.Sa, s));
-        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, I.fd, s);
         HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
     } else {
         convert<double, float>(g.nreal(), q, I.qf, s);
         HIPCHK(plan, fft_r2c_3d<float>(g, I.tf, I.qf, (float2*)I.Sb, s));
-        spec_apply<float>(g, SPEC_INV_FD, (const float2*)I.Sb, (float2*)I.Sb, s);
+        spec_apply<float>(g, SPEC_INV_FD, (const float2*)I.Sb, (float2*)I.Sb, I.fd, s);
         HIPCHK(plan, fft_c2r_3d<float>(g, I.tf, (const float2*)I.Sb, (float2*)I.Sgu, I.psif, s));
     }
     return ETD_OK;
@@ -779,7 +795,7 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
         if (n_out < 5) return fail(&plan->err, ETD_E_ARG, "fixed energy needs n_out >= 5");
         fixed_nonlocal_arg(n, I.FK, I.G, I.U, I.q, I.mq, s);
         HIPCHK(plan, fft_r2c_3d<double>(g, I.td, I.q, (double2*)I.Sa, s));
-        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, s);
+        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, I.fd, s);
         HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
         reduce_energy_fixed(g, I.FK, I.G, I.U, I.psid, I.q, I.part, I.scal + S_ENERGY, s);
         HIPCHK(plan, hipMemcpyAsync(sums, I.scal + S_ENERGY, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -801,7 +817,7 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
             gloc_field<T>(n, v.phiA, v.gp, s);
             coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, s);
             HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
-            spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, s);
+            spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
             HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s));
             reduce_energy_coupled<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, v.psi, v.P, I.part,
                                      I.scal + S_ENERGY, s);
@@ -938,7 +954,7 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
         if (e != hipSuccess) return e;
         const c2<T>* src = (const c2<T>*)sa;
         if (!ident) {
-            spec_apply<T>(g, sop, (const c2<T>*)sa, (c2<T>*)sb, s);
+            spec_apply<T>(g, sop, (const c2<T>*)sa, (c2<T>*)sb, I.fd, s);
             src = (const c2<T>*)sb;
         }
         if ((e = fft_c2r_3d<T>(g, t, src, (c2<T>*)stmp, (T*)rbuf, s)) != hipSuccess) return e;

@@ -38,7 +38,7 @@ struct Wave {
     double mu;      // FD symbol sum_d (4/h_d^2) sin^2(pi i_d / N_d)
 };
 
-__device__ __forceinline__ Wave wave(const GridK& g, long idx, bool need_mu) {
+__device__ __forceinline__ Wave wave(const GridK& g, long idx, const double* fd) {
     // the half spectrum has fewer than 2^32 entries: 32-bit decode (64-bit
     // division is a long software sequence on the GPU)
     const unsigned u = (unsigned)idx;
@@ -54,17 +54,8 @@ __device__ __forceinline__ Wave wave(const GridK& g, long idx, bool need_mu) {
     w.kd[0] = ax * der_index(ix, g.nx);
     w.kd[1] = ay * der_index(iy, g.ny);
     w.kd[2] = az * der_index(iz, g.nz);
-    w.mu = 0.0;
-    if (need_mu) {
-        double m = 0.0;
-        if (g.nx > 1) {
-            const double sx = sin(kPi * ix / g.nx);
-            m += 4.0 / (g.h[0] * g.h[0]) * sx * sx;
-        }
-        const double sy = sin(kPi * iy / g.ny), sz = sin(kPi * iz / g.nz);
-        m += 4.0 / (g.h[1] * g.h[1]) * sy * sy + 4.0 / (g.h[2] * g.h[2]) * sz * sz;
-        w.mu = m;
-    }
+    // FD symbol from the per-axis tables fd = [4/h_x^2 sin^2(pi i/N_x) | ... y | ... z]
+    w.mu = fd ? fd[ix] + fd[g.nx + iy] + fd[g.nx + g.ny + iz] : 0.0;
     return w;
 }
 
@@ -72,10 +63,10 @@ __device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K
 __device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
 
 template <typename T>
-__global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out) {
+__global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const double* __restrict__ fd) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, op == SPEC_INV_FD);
+        const Wave w = wave(g, i, op == SPEC_INV_FD ? fd : nullptr);
         const c2<T> a = in[i];
         c2<T> r;
         if (op == SPEC_NEG_K2) {
@@ -97,7 +88,7 @@ __global__ void k_etd_phi1(GridK g, CoupledK K, const c2<T>* __restrict__ P, con
                            const c2<T>* ph, c2<T>* __restrict__ RA, c2<T>* out) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, false);
+        const Wave w = wave(g, i, nullptr);
         const double z = K.tau * lphi(K, w.k2);
         const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.c1 * w.k2);
         const c2<T> p = P[i], q = Q[i], f = ph[i];
@@ -112,7 +103,7 @@ __global__ void k_etd_phi2(GridK g, CoupledK K, const c2<T>* __restrict__ P, con
                            const c2<T>* __restrict__ pt, const c2<T>* __restrict__ RA, c2<T>* out) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, false);
+        const Wave w = wave(g, i, nullptr);
         const double z = K.tau * lphi(K, w.k2);
         const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.c1 * w.k2);
         const c2<T> p = P[i], q = Q[i], t = pt[i], ra = RA[i];
@@ -130,7 +121,7 @@ __global__ void k_etd_u1(GridK g, CoupledK K, const c2<T>* __restrict__ P, const
                          c2<T>* __restrict__ D, c2<T>* __restrict__ RA) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, false);
+        const Wave w = wave(g, i, nullptr);
         const double l = lu(K, w.k2);
         const double z = K.tau * l;
         const T te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.eps_u * K.B1 * w.k2), lt = (T)l;
@@ -146,7 +137,7 @@ __global__ void k_etd_u2(GridK g, CoupledK K, const c2<T>* __restrict__ P, const
                          const c2<T>* __restrict__ RA) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, false);
+        const Wave w = wave(g, i, nullptr);
         const double z = K.tau * lu(K, w.k2);
         const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.eps_u * K.B1 * w.k2);
         const c2<T> p = P[i], gb = GB[i], d = D[i], ra = RA[i];
@@ -318,8 +309,9 @@ int grid_for(long n) {
 
 }  // namespace
 
-template <typename T> void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_spec_apply<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, (int)op, in, out);
+template <typename T>
+void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, const double* fd, hipStream_t s) {
+    hipLaunchKernelGGL(k_spec_apply<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, (int)op, in, out, fd);
 }
 template <typename T>
 void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* ph, c2<T>* RA,
@@ -383,7 +375,7 @@ void set_delta(long n, double* x, hipStream_t s) {
 
 #define INST(T)                                                                                                   \
     template void gloc_field<T>(long, const T*, T*, hipStream_t);                                                 \
-    template void spec_apply<T>(const GridK&, SpecOp, const c2<T>*, c2<T>*, hipStream_t);                        \
+    template void spec_apply<T>(const GridK&, SpecOp, const c2<T>*, c2<T>*, const double*, hipStream_t);         \
     template void spec_etd_phi1<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \
                                    c2<T>*, c2<T>*, hipStream_t);                                                  \
     template void spec_etd_phi2<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \

@@ -19,7 +19,9 @@ struct CoupledK {
 enum SpecOp { SPEC_NEG_K2 = 0, SPEC_IKX = 1, SPEC_IKY = 2, SPEC_IKZ = 3, SPEC_INV_FD = 4 };
 
 // out = m(k) in for one of the SpecOp multipliers (FP64-formed, rounded to T).
-template <typename T> void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, hipStream_t s);
+// fd: per-axis FD symbol tables [4/h_x^2 sin^2(pi i/N_x), i < N_x | y | z] (SPEC_INV_FD).
+template <typename T>
+void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, const double* fd, hipStream_t s);
 
 // phi stage 1: R = P - c1 k^2 Q  -> RA;  out = E0 phi_hat + tau E1 R.
 template <typename T>
