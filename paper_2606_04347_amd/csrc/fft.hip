@@ -1,12 +1,5 @@
-// Batched Stockham autosort FFTs for gfx950 and the 3D real transforms.
-//
-// Each workgroup (256 threads, four 64-wide wavefronts) owns L independent
-// lines of length N held in LDS.  A radix-R stage reads the R inputs of each
-// butterfly into registers, applies the twiddles w_N^(r k N/(Ns R)) with k the
-// position inside the current span Ns, does the R-point DFT, and writes the
-// outputs to their autosorted positions (span Ns -> Ns R), so the final order
-// is natural and no bit reversal pass exists.  Radices: 3 (once, first), then
-// 8 and 4 (2 only for N = 2 * 8^a), all with constant internal twiddles.
+// Batched 1D FFT passes (Stockham engine in stockham.h) and the 3D real
+// transforms built from them.
 //
 // Passes over a 3D array (real [nx][ny][nz] <-> half spectrum [nx][ny][nzh]):
 //   z  : contiguous rows; r2c packs x_{2n} + i x_{2n+1} into a length-nz/2
@@ -19,151 +12,36 @@
 #include <cmath>
 #include <mutex>
 
+#include "lines.h"
+
 namespace etd {
+
+using namespace stk;
 
 namespace {
 
-constexpr int kThreads = 256;
-
-template <int M> struct Ilog2 { static constexpr int v = 1 + Ilog2<M / 2>::v; };
-template <> struct Ilog2<1> { static constexpr int v = 0; };
-
-// Radix of the next stage for the remaining length M.
-template <int M> struct NextRadix {
-    static constexpr int k = Ilog2<M>::v;
-    static constexpr int v = (M % 3 == 0) ? 3 : (k == 1 ? 2 : ((k % 3 == 1 || k == 2) ? 4 : 8));
-};
-
-// multiply by DIR * i  (the quarter-turn of the transform's sign)
-template <typename T, int DIR> __device__ __forceinline__ c2<T> qturn(c2<T> a) {
-    return DIR > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
-}
-
-template <typename T, int DIR> __device__ __forceinline__ void dft2(c2<T>* v) {
-    c2<T> a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-}
-
-template <typename T, int DIR> __device__ __forceinline__ void dft4(c2<T>* v) {
-    c2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    c2<T> t2 = cadd(v[1], v[3]), t3 = qturn<T, DIR>(csub(v[1], v[3]));
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
-}
-
-template <typename T, int DIR> __device__ __forceinline__ void dft8(c2<T>* v) {
-    const T r = (T)0.70710678118654752440084436210484903;
-    c2<T> b[4], c[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        b[j] = cadd(v[j], v[j + 4]);
-        c[j] = csub(v[j], v[j + 4]);
-    }
-    // c_j *= w_8^j with w_8 = (1 + DIR i) / sqrt(2)
-    c[1] = cscale(cadd(c[1], qturn<T, DIR>(c[1])), r);
-    c[2] = qturn<T, DIR>(c[2]);
-    c[3] = cscale(csub(qturn<T, DIR>(c[3]), c[3]), r);
-    dft4<T, DIR>(b);
-    dft4<T, DIR>(c);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        v[2 * m] = b[m];
-        v[2 * m + 1] = c[m];
-    }
-}
-
-template <typename T, int DIR> __device__ __forceinline__ void dft3(c2<T>* v) {
-    const T s3 = (T)0.86602540378443864676372317075293618;
-    c2<T> t = cadd(v[1], v[2]);
-    c2<T> s = cscale(qturn<T, DIR>(csub(v[1], v[2])), s3);
-    c2<T> m = csub(v[0], cscale(t, (T)0.5));
-    v[0] = cadd(v[0], t);
-    v[1] = cadd(m, s);
-    v[2] = csub(m, s);
-}
-
-template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(c2<T>* v) {
-    if constexpr (R == 2) dft2<T, DIR>(v);
-    else if constexpr (R == 3) dft3<T, DIR>(v);
-    else if constexpr (R == 4) dft4<T, DIR>(v);
-    else dft8<T, DIR>(v);
-}
-
-// LDS layout of one line: element e sits at slot e + (e >> 4), one pad slot per
-// 16 elements, which spreads the strided writes of the early Stockham stages
-// (stride R Ns) over the LDS banks.
-__host__ __device__ __forceinline__ constexpr int sk(int e) { return e + (e >> 4); }
-template <int N> constexpr int line_stride() { return N + (N >> 4) + 1; }
-
-// Round-robin dispatch puts block b on XCD b % 8; renumber so that each XCD
-// works on one contiguous range of tiles (neighbouring tiles share L2 lines).
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
-    return x * q + min(x, r) + k;
-}
-
-// One radix-R Stockham stage on L lines of length N in LDS (line stride LS).
-template <typename T, int N, int L, int LS, int R, int NS, int DIR>
-__device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
-    constexpr int NR = N / R;
-    constexpr int NB = L * NR;
-    constexpr int BPT = (NB + kThreads - 1) / kThreads;
-    c2<T> v[BPT][R];
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int b = tid + i * kThreads;
-        if ((NB % kThreads == 0) || b < NB) {
-            const int l = b / NR, j = b % NR;
-            const c2<T>* src = lds + l * LS;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[sk(j + r * NR)];
-            if constexpr (NS > 1) {
-                const int k = j % NS;
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    c2<T> w = tw[r * k * (N / (NS * R))];
-                    if constexpr (DIR > 0) w.y = -w.y;
-                    v[i][r] = cmul(v[i][r], w);
-                }
-            }
-            dftR<T, R, DIR>(v[i]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-        const int b = tid + i * kThreads;
-        if ((NB % kThreads == 0) || b < NB) {
-            const int l = b / NR, j = b % NR;
-            const int k = j % NS;
-            c2<T>* dst = lds + l * LS;
-            const int o = (j / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) dst[sk(o + r * NS)] = v[i][r];
-        }
-    }
-    __syncthreads();
-}
-
-template <typename T, int N, int L, int LS, int NS, int DIR>
-__device__ __forceinline__ void stockham(c2<T>* lds, const c2<T>* tw) {
-    if constexpr (NS < N) {
-        constexpr int R = NextRadix<N / NS>::v;
-        stage<T, N, L, LS, R, NS, DIR>(lds, tw);
-        stockham<T, N, L, LS, NS * R, DIR>(lds, tw);
-    }
-}
-
-template <typename T> __device__ __forceinline__ void load_table(c2<T>* dst, const c2<T>* src, int n) {
-    for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------- strided lines
-template <int N> constexpr int strided_lines() { return N <= 256 ? 16 : 8; }
+template <typename T, int N> constexpr int strided_lines() { return lines_per_block<T, N, 1>(); }
+
+// Plain transform of lines: element e of line l at sbase[l] + e * estride
+// (sbase[l] < 0: the line is past the end).  In place is safe: every read of a
+// tile happens in the first stage, every write in the last, with barriers in
+// between, and tiles are disjoint.
+template <typename T> struct PlainLinesOp {
+    static constexpr int NS = 1;
+    const c2<T>* in;
+    c2<T>* out;
+    const long* sbase;
+    long estride;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        const long b = sbase[l];
+        v[0] = b >= 0 ? in[b + (long)e * estride] : mk<T>(0, 0);
+    }
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        const long b = sbase[l];
+        if (b >= 0) out[b + (long)e * estride] = v;
+    }
+};
 
 // Lines are numbered j = o * C + c (o the outer index, c the contiguous column
 // index, C columns); line j starts at o * ostride + c and its elements are
@@ -173,25 +51,20 @@ template <int N> constexpr int strided_lines() { return N <= 256 ? 16 : 8; }
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void fft_lines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw, int C,
                                           int nlines, long ostride, long estride) {
-    constexpr int L = strided_lines<N>();
+    constexpr int L = strided_lines<T, N>();
     constexpr int LS = line_stride<N>();
-    static_assert(kThreads % L == 0, "a thread keeps one line in the load/store loops");
     extern __shared__ unsigned char smem_raw[];
+    __shared__ long sbase[L];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * LS;
     load_table<T>(stw, tw, N);
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int l = threadIdx.x % L;
-    const int j = tile * L + l;
-    const bool valid = j < nlines;
-    const long base = valid ? (long)(j / C) * ostride + (j % C) : 0;
-    c2<T>* row = lds + l * LS;
-    for (int e = threadIdx.x / L; e < N; e += kThreads / L)
-        row[sk(e)] = valid ? in[base + (long)e * estride] : mk<T>(0, 0);
+    if (threadIdx.x < L) {
+        const int j = tile * L + threadIdx.x;
+        sbase[threadIdx.x] = j < nlines ? (long)(j / C) * ostride + (j % C) : -1;
+    }
     __syncthreads();
-    stockham<T, N, L, LS, 1, DIR>(lds, stw);
-    if (valid)
-        for (int e = threadIdx.x / L; e < N; e += kThreads / L) out[base + (long)e * estride] = row[sk(e)];
+    lines_fft<T, N, L, DIR>(lds, stw, PlainLinesOp<T>{in, out, sbase, estride});
 }
 
 // The y- and x-line passes share the body; separate symbols keep them apart in traces.
@@ -310,8 +183,8 @@ template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag
 template <typename T, int N, int DIR, bool XLINES>
 hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter, long ostride,
                           long estride, hipStream_t s) {
-    constexpr int L = strided_lines<N>();
-    const size_t smem = sizeof(c2<T>) * (size_t)(L * line_stride<N>() + N);
+    constexpr int L = strided_lines<T, N>();
+    const size_t smem = lines_smem<T, N, L, 1>();
     auto kern = XLINES ? k_fft_xlines<T, N, DIR> : k_fft_ylines<T, N, DIR>;
     static std::once_flag flag;
     set_smem_limit(kern, smem, flag);

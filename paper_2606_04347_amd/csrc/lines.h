@@ -1,0 +1,139 @@
+// Line-FFT driver with register-resident first and last stages (device code).
+//
+// A workgroup transforms L lines of length N, each carrying NS "slots"
+// (independent transforms formed from the same loaded elements, e.g. S,
+// i k S and -k^2 S).  Stage 1 reads its R inputs per butterfly straight from
+// global memory (Op::load, consecutive threads on consecutive lines, so the
+// accesses of a wavefront are runs of contiguous elements), does the DFT in
+// registers for every slot and writes the autosorted results to LDS; the
+// middle stages run in LDS (stockham.h); the last stage reads LDS, applies its
+// twiddles and hands each output straight to Op::store.  A transform of
+// R1 * R2 * R3 points therefore makes two LDS round trips instead of four, and
+// a single-stage transform none.
+//
+// Op concept (T the real type):
+//   static constexpr int NS;                                   // slots per line
+//   __device__ void load(int l, int e, c2<T>* v) const;        // v[0..NS) at element e of line l
+//   __device__ void store(int l, int s, int e, c2<T> v) const; // output of slot s at element e
+#pragma once
+
+#include "stockham.h"
+
+namespace etd {
+namespace stk {
+
+// First stage (span 1, radix R): global -> registers -> DFT -> LDS.
+template <typename T, int N, int L, int LS, int R, int DIR, class Op>
+__device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
+    constexpr int NS = Op::NS;
+    constexpr int NR = N / R;
+    constexpr int NB = L * NR;
+    for (int b = threadIdx.x; b < NB; b += kThreads) {
+        const int l = b % L, j = b / L;
+        c2<T> v[NS][R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            c2<T> x[NS];
+            op.load(l, j + r * NR, x);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[s][r] = x[s];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            dftR<T, R, DIR>(v[s]);
+            c2<T>* dst = lds + (s * L + l) * LS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[sk(j * R + r)] = v[s][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Last stage (span NS_ = N / R): LDS -> twiddles -> DFT -> Op::store.
+template <typename T, int N, int L, int LS, int R, int DIR, class Op>
+__device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int NS = Op::NS;
+    constexpr int SP = N / R;          // span before this stage
+    constexpr int LL = L * NS;
+    constexpr int NB = LL * SP;
+    for (int b = threadIdx.x; b < NB; b += kThreads) {
+        const int ll = b % LL, j = b / LL;
+        const int s = ll / L, l = ll % L;
+        const c2<T>* src = lds + ll * LS;
+        c2<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[sk(j + r * SP)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            c2<T> w = tw[r * j];
+            if constexpr (DIR > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+        dftR<T, R, DIR>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) op.store(l, s, j + r * SP, v[r]);
+    }
+}
+
+// Middle stages from span NSP up to the last stage.
+template <typename T, int N, int LL, int LS, int NSP, int DIR, class Op>
+__device__ __forceinline__ void middle_and_last(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int R = NextRadix<N / NSP>::v;
+    if constexpr (NSP * R == N) {
+        last_stage<T, N, LL / Op::NS, LS, R, DIR, Op>(lds, tw, op);
+    } else {
+        stage<T, N, LL, LS, R, NSP, DIR>(lds, tw);
+        middle_and_last<T, N, LL, LS, NSP * R, DIR, Op>(lds, tw, op);
+    }
+}
+
+// Single-stage transform (N is one radix): global -> registers -> global.
+template <typename T, int N, int L, int DIR, class Op>
+__device__ __forceinline__ void single_stage(const Op& op) {
+    constexpr int NS = Op::NS;
+    for (int l = threadIdx.x; l < L; l += kThreads) {
+        c2<T> v[NS][N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            c2<T> x[NS];
+            op.load(l, e, x);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[s][e] = x[s];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            dftR<T, N, DIR>(v[s]);
+#pragma unroll
+            for (int e = 0; e < N; ++e) op.store(l, s, e, v[s][e]);
+        }
+    }
+}
+
+// L lines x NS slots of length N; lds holds L * NS * LS elements, tw the N
+// twiddles (already in LDS).
+template <typename T, int N, int L, int DIR, class Op>
+__device__ __forceinline__ void lines_fft(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int LS = line_stride<N>();
+    constexpr int R0 = NextRadix<N>::v;
+    if constexpr (R0 == N) {
+        single_stage<T, N, L, DIR, Op>(op);
+    } else {
+        first_stage<T, N, L, LS, R0, DIR, Op>(lds, op);
+        middle_and_last<T, N, L * Op::NS, LS, R0, DIR, Op>(lds, tw, op);
+    }
+}
+
+// LDS elements needed by lines_fft plus the twiddle table.
+template <typename T, int N, int L, int NS> constexpr size_t lines_smem() {
+    return sizeof(c2<T>) * (size_t)(L * NS * line_stride<N>() + N);
+}
+
+// Lines per workgroup: coalescing wants >= 8 consecutive lines; keep the LDS
+// of one workgroup near 64 KiB so several fit in a CU.
+template <typename T, int N, int NS> constexpr int lines_per_block() {
+    constexpr size_t per_line = sizeof(c2<T>) * NS * line_stride<N>();
+    return per_line * 16 <= 72 * 1024 ? 16 : (per_line * 8 <= 80 * 1024 ? 8 : 4);
+}
+
+}  // namespace stk
+}  // namespace etd
