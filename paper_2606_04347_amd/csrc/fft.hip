@@ -64,7 +64,7 @@ __device__ __forceinline__ void fft_lines(const c2<T>* in, c2<T>* out, const c2<
         sbase[threadIdx.x] = j < nlines ? (long)(j / C) * ostride + (j % C) : -1;
     }
     __syncthreads();
-    lines_fft<T, N, L, DIR>(lds, stw, PlainLinesOp<T>{in, out, sbase, estride});
+    lines_fft<T, N, L, DIR, true>(lds, stw, PlainLinesOp<T>{in, out, sbase, estride});
 }
 
 // The y- and x-line passes share the body; separate symbols keep them apart in traces.
@@ -82,6 +82,28 @@ __global__ __launch_bounds__(kThreads) void k_fft_xlines(const c2<T>* in, c2<T>*
 // ---------------------------------------------------------------- z rows (r2c / c2r)
 template <int NR> constexpr int z_rows() { return NR >= 512 ? 8 : (NR >= 256 ? 16 : (4096 / NR)); }
 
+// Row l of a z tile viewed as M complex pairs (x_{2n}, x_{2n+1}); rows past the end read 0.
+template <typename T, int M> struct RowPairLoad {
+    static constexpr int NS = 1;
+    const c2<T>* src;   // first row of the tile
+    int nl;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        v[0] = l < nl ? src[(long)l * M + e] : mk<T>(0, 0);
+    }
+    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
+};
+
+template <typename T, int M> struct RowPairStore {
+    static constexpr int NS = 1;
+    c2<T>* dst;         // first row of the tile, as pairs
+    int nl;
+    T scale;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        if (l < nl) dst[(long)l * M + e] = cscale(v, scale);
+    }
+};
+
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in, c2<T>* __restrict__ out,
                                                         const c2<T>* __restrict__ twh,
@@ -96,12 +118,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
     const c2<T>* src = reinterpret_cast<const c2<T>*>(in + row0 * NR);
-    for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
-        const int r = idx / M, n = idx % M;
-        lds[r * LS + sk(n)] = (r < nl) ? src[idx] : mk<T>(0, 0);
+    if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
+        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+            const int r = idx / M, n = idx % M;
+            lds[r * LS + sk(n)] = (r < nl) ? src[idx] : mk<T>(0, 0);
+        }
+        __syncthreads();
+        stockham<T, M, L, LS, 1, -1>(lds, stw);
+    } else {
+        // z_n = x_{2n} + i x_{2n+1}: first stage straight from the real rows
+        lines_fft_to_lds<T, M, L, LS, 1, -1, false>(lds, stw, RowPairLoad<T, M>{src, nl});
     }
-    __syncthreads();
-    stockham<T, M, L, LS, 1, -1>(lds, stw);
     c2<T>* dst = out + row0 * (M + 1);
     const T half = (T)0.5;
     for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
@@ -162,11 +189,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
         }
     }
     __syncthreads();
-    stockham<T, M, L, LS, 1, +1>(lds, stw);
     c2<T>* dst = reinterpret_cast<c2<T>*>(out + row0 * NR);
-    for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
-        const int r = idx / M, n = idx % M;
-        if (r < nl) dst[idx] = cscale(lds[r * LS + sk(n)], scale);
+    if constexpr (NextRadix<M>::v == M) {
+        stockham<T, M, L, LS, 1, +1>(lds, stw);
+        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+            const int r = idx / M, n = idx % M;
+            if (r < nl) dst[idx] = cscale(lds[r * LS + sk(n)], scale);
+        }
+    } else {
+        // the last stage writes the real pairs (x_{2n}, x_{2n+1}) = z_n straight to the rows
+        lines_fft_from_lds<T, M, L, LS, +1, false>(lds, stw, RowPairStore<T, M>{dst, nl, scale});
     }
 }
 

@@ -3,13 +3,16 @@
 // A workgroup transforms L lines of length N, each carrying NS "slots"
 // (independent transforms formed from the same loaded elements, e.g. S,
 // i k S and -k^2 S).  Stage 1 reads its R inputs per butterfly straight from
-// global memory (Op::load, consecutive threads on consecutive lines, so the
-// accesses of a wavefront are runs of contiguous elements), does the DFT in
-// registers for every slot and writes the autosorted results to LDS; the
-// middle stages run in LDS (stockham.h); the last stage reads LDS, applies its
-// twiddles and hands each output straight to Op::store.  A transform of
-// R1 * R2 * R3 points therefore makes two LDS round trips instead of four, and
-// a single-stage transform none.
+// global memory (Op::load), does the DFT in registers for every slot and
+// writes the autosorted results to LDS; the middle stages run in LDS
+// (stockham.h); the last stage reads LDS, applies its twiddles and hands each
+// output straight to Op::store.  A transform of R1 * R2 * R3 points therefore
+// makes two LDS round trips instead of four, and a single-stage transform none.
+//
+// LF selects the thread mapping of the global accesses: true (strided line
+// passes) puts consecutive lines on consecutive threads, so a wavefront reads
+// runs of contiguous line starts; false (contiguous rows) puts consecutive
+// elements of a line on consecutive threads.
 //
 // Op concept (T the real type):
 //   static constexpr int NS;                                   // slots per line
@@ -23,13 +26,13 @@ namespace etd {
 namespace stk {
 
 // First stage (span 1, radix R): global -> registers -> DFT -> LDS.
-template <typename T, int N, int L, int LS, int R, int DIR, class Op>
+template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
 __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
     constexpr int NS = Op::NS;
     constexpr int NR = N / R;
     constexpr int NB = L * NR;
     for (int b = threadIdx.x; b < NB; b += kThreads) {
-        const int l = b % L, j = b / L;
+        const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
         c2<T> v[NS][R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -49,15 +52,15 @@ __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
     __syncthreads();
 }
 
-// Last stage (span NS_ = N / R): LDS -> twiddles -> DFT -> Op::store.
-template <typename T, int N, int L, int LS, int R, int DIR, class Op>
+// Last stage (span SP = N / R): LDS -> twiddles -> DFT -> Op::store.
+template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
 __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int NS = Op::NS;
-    constexpr int SP = N / R;          // span before this stage
+    constexpr int SP = N / R;
     constexpr int LL = L * NS;
     constexpr int NB = LL * SP;
     for (int b = threadIdx.x; b < NB; b += kThreads) {
-        const int ll = b % LL, j = b / LL;
+        const int ll = LF ? b % LL : b / SP, j = LF ? b / LL : b % SP;
         const int s = ll / L, l = ll % L;
         const c2<T>* src = lds + ll * LS;
         c2<T> v[R];
@@ -75,15 +78,15 @@ __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, co
     }
 }
 
-// Middle stages from span NSP up to the last stage.
-template <typename T, int N, int LL, int LS, int NSP, int DIR, class Op>
+// Stages from span NSP on; the last one goes to Op::store.
+template <typename T, int N, int LL, int LS, int NSP, int DIR, bool LF, class Op>
 __device__ __forceinline__ void middle_and_last(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int R = NextRadix<N / NSP>::v;
     if constexpr (NSP * R == N) {
-        last_stage<T, N, LL / Op::NS, LS, R, DIR, Op>(lds, tw, op);
+        last_stage<T, N, LL / Op::NS, LS, R, DIR, LF, Op>(lds, tw, op);
     } else {
         stage<T, N, LL, LS, R, NSP, DIR>(lds, tw);
-        middle_and_last<T, N, LL, LS, NSP * R, DIR, Op>(lds, tw, op);
+        middle_and_last<T, N, LL, LS, NSP * R, DIR, LF, Op>(lds, tw, op);
     }
 }
 
@@ -109,18 +112,35 @@ __device__ __forceinline__ void single_stage(const Op& op) {
     }
 }
 
-// L lines x NS slots of length N; lds holds L * NS * LS elements, tw the N
-// twiddles (already in LDS).
-template <typename T, int N, int L, int DIR, class Op>
+// Global -> global: L lines x NS slots of length N; lds holds L * NS * LS
+// elements, tw the N twiddles (already in LDS).
+template <typename T, int N, int L, int DIR, bool LF, class Op>
 __device__ __forceinline__ void lines_fft(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int LS = line_stride<N>();
     constexpr int R0 = NextRadix<N>::v;
     if constexpr (R0 == N) {
         single_stage<T, N, L, DIR, Op>(op);
     } else {
-        first_stage<T, N, L, LS, R0, DIR, Op>(lds, op);
-        middle_and_last<T, N, L * Op::NS, LS, R0, DIR, Op>(lds, tw, op);
+        first_stage<T, N, L, LS, R0, DIR, LF, Op>(lds, op);
+        middle_and_last<T, N, L * Op::NS, LS, R0, DIR, LF, Op>(lds, tw, op);
     }
+}
+
+// LDS -> global: the L * NS lines (line stride LS) are already in LDS in
+// natural order (after a barrier); every stage runs from LDS, the last one
+// stores through Op.
+template <typename T, int N, int L, int LS, int DIR, bool LF, class Op>
+__device__ __forceinline__ void lines_fft_from_lds(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    middle_and_last<T, N, L * Op::NS, LS, 1, DIR, LF, Op>(lds, tw, op);
+}
+
+// Global -> LDS: first stage from Op::load, every later stage in LDS; the
+// result is left in LDS in natural order, after a barrier.
+template <typename T, int N, int L, int LS, int NSLOT, int DIR, bool LF, class Op>
+__device__ __forceinline__ void lines_fft_to_lds(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int R0 = NextRadix<N>::v;
+    first_stage<T, N, L, LS, R0, DIR, LF, Op>(lds, op);
+    stockham<T, N, L * NSLOT, LS, R0, DIR>(lds, tw);
 }
 
 // LDS elements needed by lines_fft plus the twiddle table.
