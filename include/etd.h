@@ -205,14 +205,23 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
 /* Per-pass timing of the FFT kernels (a measurement aid).  enable != 0 starts
  * a measurement: every FFT pass launched afterwards by calls on this plan is
  * bracketed by HIP events recorded on the plan's stream.  enable == 0 stops
- * it, synchronizes, and fills out (may be NULL) for the pass kinds
- * k = 0..3 (z-line r2c, z-line c2r, y lines, x lines): the number of launches,
- * their summed event-timed duration in ms, and the algorithmic bytes they move
- * (each input element read once, each output element written once). */
+ * it, synchronizes, and fills out (may be NULL) per pass kind: the number of
+ * launches, their summed event-timed duration in ms, and the algorithmic bytes
+ * they move (each distinct input element read once, each output element
+ * written once).  Kinds:
+ *   0 z-row r2c            1 z-row c2r             2 y lines
+ *   3 x lines              4 inverse x lines S -> (S, i kx S, -kx^2 S)
+ *   5 inverse y lines, 3 -> 4 spectra (derivatives)
+ *   6 z-row c2r, 4 spectra -> phi, grad phi, lap phi
+ *   7 z-row r2c of two fields          8 forward y lines of two spectra
+ *   9 forward x lines of two spectra with the ETD combine
+ *  10 last forward axis times 1/mu and back ((-Delta_h)^{-1})
+ *  11..15 unused. */
+#define ETD_PASS_KINDS 16
 typedef struct {
-    int64_t launches[4];
-    double total_ms[4];
-    double bytes[4];
+    int64_t launches[ETD_PASS_KINDS];
+    double total_ms[ETD_PASS_KINDS];
+    double bytes[ETD_PASS_KINDS];
 } etd_pass_times;
 etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out);
 

@@ -10,6 +10,7 @@
 
 #include "etd.h"
 #include "fft.h"
+#include "fused.h"
 #include "kernels.h"
 
 using namespace etd;
@@ -413,39 +414,58 @@ template <typename T> const FFTTables<T>& tables(const Instance& I);
 template <> const FFTTables<float>& tables<float>(const Instance& I) { return I.tf; }
 template <> const FFTTables<double>& tables<double>(const Instance& I) { return I.td; }
 
-// phi and its spectral derivatives from a spectrum: out phi, lap, gx, gy, gz
+// phi and its spectral derivatives from a spectrum: out phi, lap, gx, gy, gz.
+// Three-dimensional grids take the fused three-pass pipeline with the work
+// spectra Sa, Sb, Sgu, Stmp (S must be none of them); two-dimensional grids
+// take one c2r per field.
 template <typename T>
-hipError_t phi_and_derivs(const Instance& I, const c2<T>* S, T* phi, T* lap, T* gx, T* gy, T* gz, c2<T>* work,
-                          c2<T>* tmp, hipStream_t s) {
+hipError_t phi_and_derivs(const Instance& I, CoupledView<T>& v, const c2<T>* S, T* phi, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
-    hipError_t e = fft_c2r_3d<T>(g, t, S, tmp, phi, s);
+    if (g.nx > 1) return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, s);
+    hipError_t e = fft_c2r_3d<T>(g, t, S, v.Stmp, phi, s);
     if (e != hipSuccess) return e;
     const SpecOp ops[4] = {SPEC_NEG_K2, SPEC_IKX, SPEC_IKY, SPEC_IKZ};
-    T* outs[4] = {lap, gx, gy, gz};
+    T* outs[4] = {v.lap, v.gx, v.gy, v.gz};
     for (int k = 0; k < 4; ++k) {
-        spec_apply<T>(g, ops[k], S, work, I.fd, s);
-        if ((e = fft_c2r_3d<T>(g, t, work, tmp, outs[k], s)) != hipSuccess) return e;
+        spec_apply<T>(g, ops[k], S, v.Sa, I.fd, s);
+        if ((e = fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, outs[k], s)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
 
-// q = g (u - ubar) (masked), gu = g u; m = h^3 sum q; psi = (-Delta_h)^{-1} q; P = P2(u);
-// Sa <- FFT(P2), Sb <- FFT(g u)
+// Forward transforms of the remainder pair (P, Q) and the ETD combine of the
+// stage: fused into the x pass on three-dimensional grids.
 template <typename T>
-hipError_t u_remainder(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, hipStream_t s) {
+hipError_t remainder_etd(const Instance& I, CoupledView<T>& v, EtdStage st, const EtdArgs<T>& a, hipStream_t s) {
+    const GridK& g = I.g;
+    const FFTTables<T>& t = tables<T>(I);
+    if (g.nx > 1) return fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, s);
+    hipError_t e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s);
+    if (e != hipSuccess) return e;
+    if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
+    switch (st) {
+        case ETD_STAGE_PHI1: spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, s); break;
+        case ETD_STAGE_PHI2: spec_etd_phi2<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, s); break;
+        case ETD_STAGE_U1: spec_etd_u1<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, s); break;
+        case ETD_STAGE_U2: spec_etd_u2<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, s); break;
+    }
+    return hipGetLastError();
+}
+
+// One u stage up to the increment spectrum: q = g (u - ubar) (masked) -> P,
+// g u -> Q; m = h^3 sum q; psi = (-Delta_h)^{-1} q; P = P2(u); then the
+// transforms of (P2, g u) and the combine into Sgu (D) and Sra.
+template <typename T>
+hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, EtdStage st, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, s);
     reduce_sum<T>(g.nreal(), v.P, g.cell, I.part, I.scal + S_MASS, s);
-    hipError_t e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s);
+    hipError_t e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s);
     if (e != hipSuccess) return e;
-    spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
-    if ((e = fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s)) != hipSuccess) return e;
-    if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
     coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
-    if ((e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s)) != hipSuccess) return e;
-    return hipGetLastError();
+    return remainder_etd<T>(I, v, st, EtdArgs<T>{nullptr, v.Sra, v.Sgu}, s);
 }
 
 template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
@@ -466,36 +486,30 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
     reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
     coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q, s);
-    HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
-    HIPCHK(plan, fft_r2c_3d<T>(g, t, v.Q, v.Sb, s));
     if (!rk2) {
-        spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, v.Sphi, v.Sra, v.Sphi, s);
+        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, s));
     } else {
-        spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, v.Sphi, v.Sra, v.St, s);
-        HIPCHK(plan, phi_and_derivs<T>(I, v.St, v.phiB, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, s));
+        HIPCHK(plan, phi_and_derivs<T>(I, v, v.St, v.phiB, s));
         reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s);
         coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
                             s);
-        HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
-        HIPCHK(plan, fft_r2c_3d<T>(g, t, v.Q, v.Sb, s));
-        spec_etd_phi2<T>(g, I.K, v.Sa, v.Sb, v.St, v.Sra, v.Sphi, s);
+        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, s));
     }
     // phi^{n+1} and its derivatives (kept for the next step), g+ and the velocity
-    HIPCHK(plan, phi_and_derivs<T>(I, v.Sphi, v.phiB, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+    HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiB, s));
     coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
     // ---- g u stages with g = g(phi^{n+1})
     // The spectral g u values are kept as increments D over FFT(g+ u^n), so the
     // inverse transforms carry only the per-step change; g+ u^n is added back in
     // real space inside the recovery (same scheme, smaller rounding in FP32).
-    HIPCHK(plan, u_remainder<T>(I, v, v.u, mask, s));            // Sa = FFT(P2(u^n)), Sb = FFT(g+ u^n)
-    spec_etd_u1<T>(g, I.K, v.Sa, v.Sb, v.Sgu, v.Sra, s);            // Sgu = GU~^ - FFT(g+ u^n), Sra = R2(u^n)^
+    HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, s));      // Sgu = GU~^ - FFT(g+ u^n), Sra = R2(u^n)^
     HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
     recover_increment<T>(n, v.u, v.P, v.gp, v.ut, I.K.thr, s);      // U~
     if (!rk2) {
         std::swap(I.u, I.ut);
     } else {
-        HIPCHK(plan, u_remainder<T>(I, v, v.ut, mask, s));       // Sa = FFT(P2(U~)), Sb = FFT(g+ U~)
-        spec_etd_u2<T>(g, I.K, v.Sa, v.Sb, v.Sgu, v.Sra, s);
+        HIPCHK(plan, u_stage<T>(I, v, v.ut, mask, ETD_STAGE_U2, s));
         HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
         recover_increment<T>(n, v.u, v.P, v.gp, v.u, I.K.thr, s);   // U^{n+1}
     }
@@ -513,14 +527,10 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
 etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStream_t s) {
     const GridK& g = I.g;
     if (!I.f32) {
-        HIPCHK(plan, fft_r2c_3d<double>(g, I.td, q, (double2*)I.Sa, s));
-        spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, I.fd, s);
-        HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
+        HIPCHK(plan, lapinv_fused<double>(g, I.td, I.fd, q, (double2*)I.Sa, I.psid, s));
     } else {
         convert<double, float>(g.nreal(), q, I.qf, s);
-        HIPCHK(plan, fft_r2c_3d<float>(g, I.tf, I.qf, (float2*)I.Sb, s));
-        spec_apply<float>(g, SPEC_INV_FD, (const float2*)I.Sb, (float2*)I.Sb, I.fd, s);
-        HIPCHK(plan, fft_c2r_3d<float>(g, I.tf, (const float2*)I.Sb, (float2*)I.Sgu, I.psif, s));
+        HIPCHK(plan, lapinv_fused<float>(g, I.tf, I.fd, I.qf, (float2*)I.Sb, I.psif, s));
     }
     return ETD_OK;
 }
@@ -607,7 +617,7 @@ template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, 
     load_field<T>(n, u, dt, v.u, s);
     HIPCHK(plan, fft_r2c_3d<T>(g, tables<T>(I), v.phiA, v.Sphi, s));
     // phi^0 from its spectrum (as every later phi^n is), with its derivatives
-    HIPCHK(plan, phi_and_derivs<T>(I, v.Sphi, v.phiA, v.lap, v.gx, v.gy, v.gz, v.Sa, v.Stmp, s));
+    HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiA, s));
     reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
     gloc_field<T>(n, v.phiA, v.gp, s);
     mass_project_sums<T>(n, v.gp, v.u, I.K.thr, I.part, I.scal + S_MPS, s);
@@ -986,6 +996,7 @@ etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out) {
     for (const auto& r : plan->hook.recs) {
         float ms = 0.f;
         HIPCHK(plan, hipEventElapsedTime(&ms, r.e0, r.e1));
+        if (r.kind < 0 || r.kind >= ETD_PASS_KINDS) continue;
         t.launches[r.kind] += 1;
         t.total_ms[r.kind] += ms;
         t.bytes[r.kind] += r.bytes;

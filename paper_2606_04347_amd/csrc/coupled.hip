@@ -1,35 +1,13 @@
 // Coupled-model kernels: spectral multipliers and ETD combines (Section 3.2,
 // Section 3.3) and the real-space remainders R1, R2 (Section 3.1) with the
 // second-order FD operators of Section 2.1.
-#include "kernels.h"
+#include "etd_point.h"
 
 namespace etd {
 
 namespace {
 
 constexpr int kBlock = 256;
-
-// ----------------------------------------------------------------- phi-functions (FP64)
-// phi1(z) = (1 - e^{-z})/z, phi2(z) = (e^{-z} - 1 + z)/z^2; for |z| < 0.1 the
-// series sum_j (-z)^j / (j + k)! (14 terms, truncation < 1e-25) avoids the
-// cancellation of the closed forms.
-__device__ __forceinline__ double phi_taylor(double z, int k) {
-    double fact[20];
-    double f = 1.0;
-    for (int j = 1; j <= k; ++j) f *= j;
-    double out = 0.0;
-    // coefficients 1/(j+k)! for j = 0..13, evaluated by Horner from the top
-    fact[0] = 1.0 / f;
-    for (int j = 1; j < 14; ++j) fact[j] = fact[j - 1] / (double)(j + k);
-    for (int j = 13; j >= 0; --j) out = out * (-z) + fact[j];
-    return out;
-}
-__device__ __forceinline__ double phi1d(double z) {
-    return fabs(z) < 0.1 ? phi_taylor(z, 1) : -expm1(-z) / z;
-}
-__device__ __forceinline__ double phi2d(double z) {
-    return fabs(z) < 0.1 ? phi_taylor(z, 2) : (expm1(-z) + z) / (z * z);
-}
 
 // wavenumbers of half-spectrum entry idx (layout [nx][ny][nzh])
 struct Wave {
@@ -59,8 +37,6 @@ __device__ __forceinline__ Wave wave(const GridK& g, long idx, const double* fd)
     return w;
 }
 
-__device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K.lp4 * k2 + K.lp2) * k2 + K.lp0; }
-__device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
 
 template <typename T>
 __global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const double* __restrict__ fd) {
@@ -83,66 +59,13 @@ __global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const
     }
 }
 
-template <typename T>
-__global__ void k_etd_phi1(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q,
-                           const c2<T>* ph, c2<T>* __restrict__ RA, c2<T>* out) {
+// One ETD combine (etd_point.h) per half-spectrum entry: p = P[i], q = Q[i].
+template <int ST, typename T>
+__global__ void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q, EtdArgs<T> a) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const Wave w = wave(g, i, nullptr);
-        const double z = K.tau * lphi(K, w.k2);
-        const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.c1 * w.k2);
-        const c2<T> p = P[i], q = Q[i], f = ph[i];
-        const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
-        RA[i] = R;
-        out[i] = mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
-    }
-}
-
-template <typename T>
-__global__ void k_etd_phi2(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q,
-                           const c2<T>* __restrict__ pt, const c2<T>* __restrict__ RA, c2<T>* out) {
-    const long n = g.nspec();
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, nullptr);
-        const double z = K.tau * lphi(K, w.k2);
-        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.c1 * w.k2);
-        const c2<T> p = P[i], q = Q[i], t = pt[i], ra = RA[i];
-        const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
-        out[i] = mk<T>(t.x + te2 * dx, t.y + te2 * dy);
-    }
-}
-
-// The g u stages are carried as increments over the restart value FFT(g+ u^n):
-// GU~^ - FFT(g+ u^n) = (E0 - 1) GU0 + tau E1 R = tau phi1(z) (R - l_u GU0), using
-// E0 - 1 = -z phi1(z).  The inverse transform then only carries the increment,
-// and g+ u^n is added back exactly in real space.
-template <typename T>
-__global__ void k_etd_u1(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ GU0,
-                         c2<T>* __restrict__ D, c2<T>* __restrict__ RA) {
-    const long n = g.nspec();
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, nullptr);
-        const double l = lu(K, w.k2);
-        const double z = K.tau * l;
-        const T te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.eps_u * K.B1 * w.k2), lt = (T)l;
-        const c2<T> p = P[i], gu = GU0[i];
-        const c2<T> R = mk<T>(p.x + ck * gu.x, p.y + ck * gu.y);
-        RA[i] = R;
-        D[i] = mk<T>(te1 * (R.x - lt * gu.x), te1 * (R.y - lt * gu.y));
-    }
-}
-
-template <typename T>
-__global__ void k_etd_u2(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ GB, c2<T>* D,
-                         const c2<T>* __restrict__ RA) {
-    const long n = g.nspec();
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const Wave w = wave(g, i, nullptr);
-        const double z = K.tau * lu(K, w.k2);
-        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.eps_u * K.B1 * w.k2);
-        const c2<T> p = P[i], gb = GB[i], d = D[i], ra = RA[i];
-        const T dx = (p.x + ck * gb.x) - ra.x, dy = (p.y + ck * gb.y) - ra.y;
-        D[i] = mk<T>(d.x + te2 * dx, d.y + te2 * dy);
+        etd_combine<ST, T>(K, w.k2, i, P[i], Q[i], a);
     }
 }
 
@@ -316,22 +239,26 @@ void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, const do
 template <typename T>
 void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* ph, c2<T>* RA,
                    c2<T>* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_etd_phi1<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q, ph, RA, out);
+    hipLaunchKernelGGL((k_etd<ETD_STAGE_PHI1, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q,
+                       EtdArgs<T>{ph, RA, out});
 }
 template <typename T>
 void spec_etd_phi2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* pt,
                    const c2<T>* RA, c2<T>* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_etd_phi2<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q, pt, RA, out);
+    hipLaunchKernelGGL((k_etd<ETD_STAGE_PHI2, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q,
+                       EtdArgs<T>{pt, const_cast<c2<T>*>(RA), out});
 }
 template <typename T>
 void spec_etd_u1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GU0, c2<T>* D, c2<T>* RA,
                  hipStream_t s) {
-    hipLaunchKernelGGL(k_etd_u1<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GU0, D, RA);
+    hipLaunchKernelGGL((k_etd<ETD_STAGE_U1, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GU0,
+                       EtdArgs<T>{nullptr, RA, D});
 }
 template <typename T>
 void spec_etd_u2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GB, c2<T>* D, const c2<T>* RA,
                  hipStream_t s) {
-    hipLaunchKernelGGL(k_etd_u2<T>, dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GB, D, RA);
+    hipLaunchKernelGGL((k_etd<ETD_STAGE_U2, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GB,
+                       EtdArgs<T>{nullptr, const_cast<c2<T>*>(RA), D});
 }
 template <typename T>
 void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,

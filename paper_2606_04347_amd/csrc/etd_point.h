@@ -1,0 +1,80 @@
+// Pointwise ETD combines of the coupled scheme in Fourier space (Section 3.3,
+// Algorithm 1), shared by the standalone spectral kernels and the epilogue of
+// the fused forward x pass.  The phi-function values are formed in FP64 from
+// the FP64 wavenumber and rounded to the working precision T.
+#pragma once
+
+#include "kernels.h"
+
+namespace etd {
+
+// phi1(z) = (1 - e^{-z})/z, phi2(z) = (e^{-z} - 1 + z)/z^2; for |z| < 0.1 the
+// series sum_j (-z)^j / (j + k)! (14 terms, truncation < 1e-25) avoids the
+// cancellation of the closed forms.
+__device__ __forceinline__ double phi_taylor(double z, int k) {
+    double f = 1.0;
+    for (int j = 1; j <= k; ++j) f *= j;
+    double fact[14];
+    fact[0] = 1.0 / f;
+    for (int j = 1; j < 14; ++j) fact[j] = fact[j - 1] / (double)(j + k);
+    double out = 0.0;
+    for (int j = 13; j >= 0; --j) out = out * (-z) + fact[j];
+    return out;
+}
+__device__ __forceinline__ double phi1d(double z) { return fabs(z) < 0.1 ? phi_taylor(z, 1) : -expm1(-z) / z; }
+__device__ __forceinline__ double phi2d(double z) {
+    return fabs(z) < 0.1 ? phi_taylor(z, 2) : (expm1(-z) + z) / (z * z);
+}
+
+// linear symbols (eqn:linear_force and the u equation)
+__device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K.lp4 * k2 + K.lp2) * k2 + K.lp0; }
+__device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
+
+// The four combines.  p = FFT of the first remainder field, q = FFT of the
+// second (W'(phi) - A1 phi for phi, g+ u for u); index i addresses the other
+// spectra of the stage.
+enum EtdStage { ETD_STAGE_PHI1 = 0, ETD_STAGE_PHI2 = 1, ETD_STAGE_U1 = 2, ETD_STAGE_U2 = 3 };
+
+template <typename T> struct EtdArgs {
+    const c2<T>* prev;   // PHI1: phi^n hat;  PHI2: phi~ hat
+    c2<T>* ra;           // stage-1 remainder R(.)^ (written by *1, read by *2)
+    c2<T>* out;          // PHI*: new phi hat;  U*: increment D (U2 reads and updates it)
+};
+
+template <int ST, typename T>
+__device__ __forceinline__ void etd_combine(const CoupledK& K, double k2, long i, c2<T> p, c2<T> q,
+                                            const EtdArgs<T>& a) {
+    if constexpr (ST == ETD_STAGE_PHI1) {
+        // R = P - c1 k^2 Q;  phi~ = e^{-tau l} phi^n + tau phi1(tau l) R
+        const double z = K.tau * lphi(K, k2);
+        const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.c1 * k2);
+        const c2<T> f = a.prev[i];
+        const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
+        a.ra[i] = R;
+        a.out[i] = mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
+    } else if constexpr (ST == ETD_STAGE_PHI2) {
+        // phi^{n+1} = phi~ + tau phi2(tau l) (R~ - R)
+        const double z = K.tau * lphi(K, k2);
+        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.c1 * k2);
+        const c2<T> t = a.prev[i], ra = a.ra[i];
+        const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
+        a.out[i] = mk<T>(t.x + te2 * dx, t.y + te2 * dy);
+    } else if constexpr (ST == ETD_STAGE_U1) {
+        // R = P + eps_u B1 k^2 GU;  D = tau phi1(tau l_u) (R - l_u GU)  (GU~ - GU^n)
+        const double l = lu(K, k2);
+        const double z = K.tau * l;
+        const T te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.eps_u * K.B1 * k2), lt = (T)l;
+        const c2<T> R = mk<T>(p.x + ck * q.x, p.y + ck * q.y);
+        a.ra[i] = R;
+        a.out[i] = mk<T>(te1 * (R.x - lt * q.x), te1 * (R.y - lt * q.y));
+    } else {
+        // D <- D + tau phi2(tau l_u) (R~ - R)
+        const double z = K.tau * lu(K, k2);
+        const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.eps_u * K.B1 * k2);
+        const c2<T> d = a.out[i], ra = a.ra[i];
+        const T dx = (p.x + ck * q.x) - ra.x, dy = (p.y + ck * q.y) - ra.y;
+        a.out[i] = mk<T>(d.x + te2 * dx, d.y + te2 * dy);
+    }
+}
+
+}  // namespace etd

@@ -1,6 +1,8 @@
 // Batched Stockham FFTs and the 3D real transforms built from them.
 #pragma once
 
+#include <mutex>
+
 #include "common.h"
 
 namespace etd {
@@ -17,17 +19,50 @@ template <typename T> struct FFTTables {
 
 // True if a 1D transform of this length is compiled in (8..512, 2^a or 3 * 2^a).
 bool fft_length_supported(int n);
+#define ETD_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(12) X(24) X(48) X(96) X(192) X(384)
+
+// Raises the dynamic-LDS limit of one kernel instantiation once (each launcher
+// instantiation owns its flag).
+template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag& flag) {
+    std::call_once(flag, [&] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    });
+}
 
 // Optional per-launch timing of the FFT passes: when set, every pass launch is
-// bracketed by begin(kind) / end(kind) on its stream.  kind: 0 z-r2c, 1 z-c2r,
-// 2 y lines, 3 x lines.  bytes: algorithmic bytes the launch must move (each
-// input element read once, each output element written once).
+// bracketed by begin(kind) / end(kind) on its stream (kinds: PassKind).
+// bytes: algorithmic bytes the launch must move (each input element read
+// once, each output element written once).
+enum PassKind {
+    PASS_Z_R2C = 0,        // z rows, real -> half spectrum
+    PASS_Z_C2R = 1,        // z rows, half spectrum -> real
+    PASS_Y = 2,            // y lines
+    PASS_X = 3,            // x lines
+    PASS_X_DERIV = 4,      // inverse x lines, S -> (S, i kx S, -kx^2 S)
+    PASS_Y_DERIV = 5,      // inverse y lines, 3 -> 4 spectra
+    PASS_Z_DERIV = 6,      // z rows c2r, 4 spectra -> phi, grad phi, lap phi
+    PASS_Z_R2C_PAIR = 7,   // z rows r2c of two fields
+    PASS_Y_PAIR = 8,       // forward y lines of two spectra
+    PASS_X_ETD = 9,        // forward x lines of two spectra + ETD combine
+    PASS_LAPINV = 10,      // last forward axis, times 1/mu, inverse along the same axis
+    PASS_KIND_COUNT = 16
+};
 struct PassHook {
     virtual void begin(int kind, hipStream_t s) = 0;
     virtual void end(int kind, double bytes, hipStream_t s) = 0;
     virtual ~PassHook() = default;
 };
 void fft_set_pass_hook(PassHook* h);
+extern PassHook* g_pass_hook;
+
+// Run one pass launch under the optional timing hook.
+template <typename F> hipError_t timed_pass(int kind, double bytes, hipStream_t s, F&& launch) {
+    if (g_pass_hook) g_pass_hook->begin(kind, s);
+    hipError_t e = launch();
+    if (g_pass_hook) g_pass_hook->end(kind, bytes, s);
+    return e;
+}
 
 // Host-side table of exp(-2 pi i k / n), k < n, in double (extended-precision trig).
 void fft_twiddles_host(int n, double* re_im /* 2n values */);
@@ -43,5 +78,17 @@ hipError_t fft_r2c_3d(const GridK& g, const FFTTables<T>& t, const T* in, c2<T>*
 template <typename T>
 hipError_t fft_c2r_3d(const GridK& g, const FFTTables<T>& t, const c2<T>* in, c2<T>* tmp, T* out,
                       hipStream_t s);
+
+// Single passes (timed like the 3D transforms).  z: real rows <-> half-spectrum
+// rows (forward = r2c); y / x: in-place-capable complex line passes over the
+// half spectrum, dir -1 forward, +1 inverse (unnormalized; the z c2r pass
+// applies scale).
+template <typename T>
+hipError_t fft_pass_z(const GridK& g, const FFTTables<T>& t, bool forward, const void* in, void* out, T scale,
+                      hipStream_t s);
+template <typename T>
+hipError_t fft_pass_y(const GridK& g, const FFTTables<T>& t, int dir, const c2<T>* in, c2<T>* out, hipStream_t s);
+template <typename T>
+hipError_t fft_pass_x(const GridK& g, const FFTTables<T>& t, int dir, const c2<T>* in, c2<T>* out, hipStream_t s);
 
 }  // namespace etd

@@ -10,9 +10,8 @@
 #include "fft.h"
 
 #include <cmath>
-#include <mutex>
 
-#include "lines.h"
+#include "zrows.h"
 
 namespace etd {
 
@@ -80,70 +79,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_xlines(const c2<T>* in, c2<T>*
 }
 
 // ---------------------------------------------------------------- z rows (r2c / c2r)
-template <int NR> constexpr int z_rows() { return NR >= 512 ? 8 : (NR >= 256 ? 16 : (4096 / NR)); }
-
-// Row l of a z tile viewed as M complex pairs (x_{2n}, x_{2n+1}); rows past the end read 0.
-template <typename T, int M> struct RowPairLoad {
-    static constexpr int NS = 1;
-    const c2<T>* src;   // first row of the tile
-    int nl;
-    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
-        v[0] = l < nl ? src[(long)l * M + e] : mk<T>(0, 0);
-    }
-    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
-};
-
-template <typename T, int M> struct RowPairStore {
-    static constexpr int NS = 1;
-    c2<T>* dst;         // first row of the tile, as pairs
-    int nl;
-    T scale;
-    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
-    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
-        if (l < nl) dst[(long)l * M + e] = cscale(v, scale);
-    }
-};
-
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in, c2<T>* __restrict__ out,
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
-    constexpr int LS = line_stride<M + 1>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, twh, M);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
-    const c2<T>* src = reinterpret_cast<const c2<T>*>(in + row0 * NR);
-    if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
-        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
-            const int r = idx / M, n = idx % M;
-            lds[r * LS + sk(n)] = (r < nl) ? src[idx] : mk<T>(0, 0);
-        }
-        __syncthreads();
-        stockham<T, M, L, LS, 1, -1>(lds, stw);
-    } else {
-        // z_n = x_{2n} + i x_{2n+1}: first stage straight from the real rows
-        lines_fft_to_lds<T, M, L, LS, 1, -1, false>(lds, stw, RowPairLoad<T, M>{src, nl});
-    }
-    c2<T>* dst = out + row0 * (M + 1);
-    const T half = (T)0.5;
-    for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
-        const int r = idx / (M + 1), k = idx % (M + 1);
-        if (r < nl) {
-            const c2<T> zk = lds[r * LS + sk(k == M ? 0 : k)];
-            const c2<T> zc = cconj(lds[r * LS + sk(k == 0 ? 0 : M - k)]);
-            const c2<T> ev = cadd(zk, zc);                  // 2 E_k
-            const c2<T> od = csub(zk, zc);                  // 2 i O_k
-            const c2<T> w = twf[k];
-            // X_k = E_k + w^k O_k = (ev - i w od) / 2
-            const c2<T> wod = cmul(w, od);
-            dst[idx] = mk<T>(half * (ev.x + wod.y), half * (ev.y - wod.x));
-        }
-    }
+    zrow_forward<T, NR>(lds, stw, twf, in + row0 * NR, out + row0 * (NR / 2 + 1), nl);
 }
 
 template <typename T, int NR>
@@ -151,67 +98,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows,
                                                         T scale) {
-    constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
-    constexpr int LS = line_stride<M + 1>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, twh, M);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
-    const c2<T>* src = in + row0 * (M + 1);
-    for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
-        const int r = idx / (M + 1), k = idx % (M + 1);
-        lds[r * LS + sk(k)] = (r < nl) ? src[idx] : mk<T>(0, 0);
-    }
-    __syncthreads();
-    // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) e^{+2 pi i k / NR}; each thread
-    // owns the pair (k, M - k), so the update is in place without a barrier.
-    constexpr int HP = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < L * HP; idx += kThreads) {
-        const int r = idx / HP, k = idx % HP;
-        c2<T>* row = lds + r * LS;
-        c2<T> a = row[sk(k)], b = row[sk(M - k)];
-        if (k == 0) {
-            a.y = 0;
-            b.y = 0;
-        }
-        {
-            const c2<T> s = cadd(a, cconj(b));
-            const c2<T> d = cmul(csub(a, cconj(b)), cconj(twf[k]));
-            row[sk(k)] = mk<T>(s.x - d.y, s.y + d.x);
-        }
-        if (k != 0 && 2 * k != M) {
-            const c2<T> s = cadd(b, cconj(a));
-            const c2<T> d = cmul(csub(b, cconj(a)), cconj(twf[M - k]));
-            row[sk(M - k)] = mk<T>(s.x - d.y, s.y + d.x);
-        }
-    }
-    __syncthreads();
-    c2<T>* dst = reinterpret_cast<c2<T>*>(out + row0 * NR);
-    if constexpr (NextRadix<M>::v == M) {
-        stockham<T, M, L, LS, 1, +1>(lds, stw);
-        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
-            const int r = idx / M, n = idx % M;
-            if (r < nl) dst[idx] = cscale(lds[r * LS + sk(n)], scale);
-        }
-    } else {
-        // the last stage writes the real pairs (x_{2n}, x_{2n+1}) = z_n straight to the rows
-        lines_fft_from_lds<T, M, L, LS, +1, false>(lds, stw, RowPairStore<T, M>{dst, nl, scale});
-    }
+    zrow_inverse<T, NR, false>(lds, stw, twf, in + row0 * (NR / 2 + 1), out + row0 * NR, nl, scale, 0.0);
 }
 
 // ---------------------------------------------------------------- launch helpers
-// Raises the dynamic-LDS limit of one kernel instantiation once (each call
-// site below is its own template instantiation, hence its own flag).
-template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag& flag) {
-    std::call_once(flag, [&] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    });
-}
-
 template <typename T, int N, int DIR, bool XLINES>
 hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter, long ostride,
                           long estride, hipStream_t s) {
@@ -231,7 +128,7 @@ template <typename T, int NR>
 hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, const c2<T>* twf, long nrows,
                     T scale, hipStream_t s) {
     constexpr int L = z_rows<NR>();
-    const size_t smem = sizeof(c2<T>) * (size_t)(L * line_stride<NR / 2 + 1>() + NR / 2);
+    const size_t smem = z_smem<T, NR>();
     const int nblk = (int)((nrows + L - 1) / L);
     if (forward) {
         auto kern = k_fft_z_r2c<T, NR>;
@@ -249,7 +146,6 @@ hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, c
     return hipGetLastError();
 }
 
-#define ETD_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(12) X(24) X(48) X(96) X(192) X(384)
 
 template <typename T, int DIR, bool XLINES>
 hipError_t dispatch_strided(int N, const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, int nouter,
@@ -307,37 +203,43 @@ void fft_twiddles_host(int n, double* re_im) {
     }
 }
 
-PassHook* g_hook = nullptr;
+PassHook* g_pass_hook = nullptr;
 
-void fft_set_pass_hook(PassHook* h) { g_hook = h; }
+void fft_set_pass_hook(PassHook* h) { g_pass_hook = h; }
 
-// Run one pass launch under the optional timing hook.
-template <typename F> hipError_t timed_pass(int kind, double bytes, hipStream_t s, F&& launch) {
-    if (g_hook) g_hook->begin(kind, s);
-    hipError_t e = launch();
-    if (g_hook) g_hook->end(kind, bytes, s);
-    return e;
+template <typename T>
+hipError_t fft_pass_z(const GridK& g, const FFTTables<T>& t, bool forward, const void* in, void* out, T scale,
+                      hipStream_t s) {
+    const double bytes = 2.0 * sizeof(T) * (double)g.nspec() + sizeof(T) * (double)g.nreal();
+    return timed_pass(forward ? PASS_Z_R2C : PASS_Z_C2R, bytes, s, [&] {
+        return dispatch_z<T>(g.nz, forward, in, out, t.tzh, t.tzf, (long)g.nx * g.ny, scale, s);
+    });
+}
+
+template <typename T>
+hipError_t fft_pass_y(const GridK& g, const FFTTables<T>& t, int dir, const c2<T>* in, c2<T>* out, hipStream_t s) {
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    return timed_pass(PASS_Y, 2.0 * cb, s, [&] {
+        return dir < 0 ? dispatch_strided<T, -1, false>(g.ny, in, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s)
+                       : dispatch_strided<T, +1, false>(g.ny, in, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
+    });
+}
+
+template <typename T>
+hipError_t fft_pass_x(const GridK& g, const FFTTables<T>& t, int dir, const c2<T>* in, c2<T>* out, hipStream_t s) {
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    return timed_pass(PASS_X, 2.0 * cb, s, [&] {
+        return dir < 0 ? dispatch_strided<T, -1, true>(g.nx, in, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s)
+                       : dispatch_strided<T, +1, true>(g.nx, in, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
+    });
 }
 
 template <typename T>
 hipError_t fft_r2c_3d(const GridK& g, const FFTTables<T>& t, const T* in, c2<T>* out, hipStream_t s) {
-    const long rows = (long)g.nx * g.ny;
-    const double cb = 2.0 * sizeof(T) * (double)g.nspec();     // one complex half spectrum
-    hipError_t e = timed_pass(0, cb + sizeof(T) * (double)g.nreal(), s, [&] {
-        return dispatch_z<T>(g.nz, true, in, out, t.tzh, t.tzf, rows, (T)1, s);
-    });
+    hipError_t e = fft_pass_z<T>(g, t, true, in, out, (T)1, s);
     if (e != hipSuccess) return e;
-    if (g.ny > 1) {   // y lines: outer x, stride nzh
-        e = timed_pass(2, 2.0 * cb, s, [&] {
-            return dispatch_strided<T, -1, false>(g.ny, out, out, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
-        });
-        if (e != hipSuccess) return e;
-    }
-    if (g.nx > 1) {   // x lines: outer y, stride ny * nzh
-        e = timed_pass(3, 2.0 * cb, s, [&] {
-            return dispatch_strided<T, -1, true>(g.nx, out, out, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
-        });
-    }
+    if (g.ny > 1 && (e = fft_pass_y<T>(g, t, -1, out, out, s)) != hipSuccess) return e;
+    if (g.nx > 1) e = fft_pass_x<T>(g, t, -1, out, out, s);
     return e;
 }
 
@@ -346,25 +248,16 @@ hipError_t fft_c2r_3d(const GridK& g, const FFTTables<T>& t, const c2<T>* in, c2
                       hipStream_t s) {
     const c2<T>* cur = in;
     hipError_t e = hipSuccess;
-    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     if (g.nx > 1) {
-        e = timed_pass(3, 2.0 * cb, s, [&] {
-            return dispatch_strided<T, +1, true>(g.nx, cur, tmp, t.tx, g.nzh, g.ny, g.nzh, (long)g.ny * g.nzh, s);
-        });
-        if (e != hipSuccess) return e;
+        if ((e = fft_pass_x<T>(g, t, +1, cur, tmp, s)) != hipSuccess) return e;
         cur = tmp;
     }
     if (g.ny > 1) {
-        e = timed_pass(2, 2.0 * cb, s, [&] {
-            return dispatch_strided<T, +1, false>(g.ny, cur, tmp, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, g.nzh, s);
-        });
-        if (e != hipSuccess) return e;
+        if ((e = fft_pass_y<T>(g, t, +1, cur, tmp, s)) != hipSuccess) return e;
         cur = tmp;
     }
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
-    return timed_pass(1, cb + sizeof(T) * (double)g.nreal(), s, [&] {
-        return dispatch_z<T>(g.nz, false, cur, out, t.tzh, t.tzf, (long)g.nx * g.ny, scale, s);
-    });
+    return fft_pass_z<T>(g, t, false, cur, out, scale, s);
 }
 
 template hipError_t fft_r2c_3d<float>(const GridK&, const FFTTables<float>&, const float*, float2*, hipStream_t);
@@ -374,5 +267,13 @@ template hipError_t fft_c2r_3d<float>(const GridK&, const FFTTables<float>&, con
                                       hipStream_t);
 template hipError_t fft_c2r_3d<double>(const GridK&, const FFTTables<double>&, const double2*, double2*,
                                        double*, hipStream_t);
+#define INST_PASS(T)                                                                                            \
+    template hipError_t fft_pass_z<T>(const GridK&, const FFTTables<T>&, bool, const void*, void*, T,          \
+                                      hipStream_t);                                                            \
+    template hipError_t fft_pass_y<T>(const GridK&, const FFTTables<T>&, int, const c2<T>*, c2<T>*, hipStream_t); \
+    template hipError_t fft_pass_x<T>(const GridK&, const FFTTables<T>&, int, const c2<T>*, c2<T>*, hipStream_t);
+INST_PASS(float)
+INST_PASS(double)
+#undef INST_PASS
 
 }  // namespace etd

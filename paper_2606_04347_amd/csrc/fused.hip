@@ -1,0 +1,558 @@
+// Fused spectral pipelines (fused.h): several transforms, spectral
+// multipliers and the ETD combine share one pass over memory.
+//
+// Strided line passes number their lines j = o * C + c (o the outer index, c
+// the kz column, C = nzh columns); a workgroup takes L consecutive j, so each
+// row of its tile is a contiguous run of L complex values.  On an x line the
+// wavenumbers ky (from o) and kz (from c) are constants of the line; on a y
+// line (x already in real space) kz is.
+#include "fused.h"
+
+#include "zrows.h"
+
+namespace etd {
+
+using namespace stk;
+
+namespace {
+
+template <int L> struct LineTile {
+    long base[L];   // offset of element 0 of line l (< 0: past the end)
+    int o[L];       // outer index
+    int c[L];       // kz column
+};
+
+template <int L>
+__device__ __forceinline__ void tile_setup(LineTile<L>& t, int tile, int C, int nlines, long ostride) {
+    if (threadIdx.x < L) {
+        const int j = tile * L + threadIdx.x;
+        const bool ok = j < nlines;
+        const int o = ok ? j / C : 0, c = ok ? j % C : 0;
+        t.base[threadIdx.x] = ok ? (long)o * ostride + c : -1;
+        t.o[threadIdx.x] = o;
+        t.c[threadIdx.x] = c;
+    }
+}
+
+template <typename T> __device__ __forceinline__ c2<T> times_ik(T k, c2<T> v) { return mk<T>(-k * v.y, k * v.x); }
+
+// ------------------------------------------------------------------ derivative pipeline
+// Inverse x lines at fixed (ky, kz):  A = X^-1 S,  B = X^-1 (i kx S),  C = X^-1 (-kx^2 S).
+template <typename T, int L> struct DerivXOp {
+    static constexpr int NT = 3;
+    struct In {
+        c2<T> s;
+    };
+    const LineTile<L>* t;
+    const c2<T>* S;
+    c2<T>* A;
+    c2<T>* B;
+    c2<T>* C;
+    long es;
+    int n;
+    double a;   // pi / X_x
+    __device__ __forceinline__ void load(int l, int e, In& in) const {
+        const long b = t->base[l];
+        in.s = b >= 0 ? S[b + (long)e * es] : mk<T>(0, 0);
+    }
+    template <int K> __device__ __forceinline__ c2<T> input(int, int e, const In& in) const {
+        if constexpr (K == 0) {
+            return in.s;
+        } else if constexpr (K == 1) {
+            return times_ik((T)(a * der_index(e, n)), in.s);
+        } else {
+            const double lx = a * lam_index(e, n);
+            return cscale(in.s, (T)(-(lx * lx)));
+        }
+    }
+    template <int K> __device__ __forceinline__ void store(int l, int e, c2<T> v) const {
+        const long b = t->base[l];
+        if (b < 0) return;
+        c2<T>* dst = K == 0 ? A : (K == 1 ? B : C);
+        dst[b + (long)e * es] = v;
+    }
+};
+
+// Inverse y lines at fixed (x, kz) over the x-pass outputs A, B, C:
+//   Y^-1 B -> B,  Y^-1 (C - (ky^2 + kz^2) A) -> C,  Y^-1 A -> A,  Y^-1 (i ky A) -> D.
+// B and C are read by the transform that overwrites them; A is kept in registers.
+template <typename T, int L> struct DerivYOp {
+    static constexpr int NT = 4;
+    struct In {
+        c2<T> a;
+    };
+    const LineTile<L>* t;
+    c2<T>* A;
+    c2<T>* B;
+    c2<T>* C;
+    c2<T>* D;
+    long es;
+    int n;
+    double ay, az;
+    __device__ __forceinline__ void load(int l, int e, In& in) const {
+        const long b = t->base[l];
+        in.a = b >= 0 ? A[b + (long)e * es] : mk<T>(0, 0);
+    }
+    template <int K> __device__ __forceinline__ c2<T> input(int l, int e, const In& in) const {
+        const long b = t->base[l];
+        if constexpr (K == 0) {
+            return b >= 0 ? B[b + (long)e * es] : mk<T>(0, 0);
+        } else if constexpr (K == 1) {
+            const double ly = ay * lam_index(e, n), lz = az * t->c[l];
+            const T m = (T)(-(ly * ly + lz * lz));
+            const c2<T> c = b >= 0 ? C[b + (long)e * es] : mk<T>(0, 0);
+            return mk<T>(c.x + m * in.a.x, c.y + m * in.a.y);
+        } else if constexpr (K == 2) {
+            return in.a;
+        } else {
+            return times_ik((T)(ay * der_index(e, n)), in.a);
+        }
+    }
+    template <int K> __device__ __forceinline__ void store(int l, int e, c2<T> v) const {
+        const long b = t->base[l];
+        if (b < 0) return;
+        c2<T>* dst = K == 0 ? B : (K == 1 ? C : (K == 2 ? A : D));
+        dst[b + (long)e * es] = v;
+    }
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_deriv_x(GridK g, const c2<T>* S, c2<T>* A, c2<T>* B, c2<T>* C,
+                                                      const c2<T>* __restrict__ tw) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int LS = line_stride<N>();
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ LineTile<L> tile;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, tw, N);
+    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
+    __syncthreads();
+    lines_fft_seq<T, N, L, +1, true>(
+        lds, stw, DerivXOp<T, L>{&tile, S, A, B, C, (long)g.ny * g.nzh, g.nx, kPi / g.X[0]});
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_deriv_y(GridK g, c2<T>* A, c2<T>* B, c2<T>* C, c2<T>* D,
+                                                      const c2<T>* __restrict__ tw) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int LS = line_stride<N>();
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ LineTile<L> tile;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, tw, N);
+    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
+    __syncthreads();
+    lines_fft_seq<T, N, L, +1, true>(
+        lds, stw, DerivYOp<T, L>{&tile, A, B, C, D, (long)g.nzh, g.ny, kPi / g.X[1], kPi / g.X[2]});
+}
+
+// z rows c2r of the y-pass outputs: phi = Z^-1 A, gz = Z^-1 (i kz A), gx = Z^-1 B,
+// gy = Z^-1 D, lap = Z^-1 C.
+template <typename T> struct DerivZArgs {
+    const c2<T>* A;
+    const c2<T>* B;
+    const c2<T>* C;
+    const c2<T>* D;
+    T* phi;
+    T* gx;
+    T* gy;
+    T* gz;
+    T* lap;
+};
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<T>* __restrict__ twh,
+                                                      const c2<T>* __restrict__ twf, long nrows, T scale,
+                                                      double az) {
+    constexpr int L = z_rows<NR>();
+    constexpr int MS = NR / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    const long si = row0 * MS, ro = row0 * NR;
+    zrow_inverse<T, NR, false>(lds, stw, twf, z.A + si, z.phi + ro, nl, scale, az);
+    __syncthreads();
+    zrow_inverse<T, NR, true>(lds, stw, twf, z.A + si, z.gz + ro, nl, scale, az);
+    __syncthreads();
+    zrow_inverse<T, NR, false>(lds, stw, twf, z.B + si, z.gx + ro, nl, scale, az);
+    __syncthreads();
+    zrow_inverse<T, NR, false>(lds, stw, twf, z.D + si, z.gy + ro, nl, scale, az);
+    __syncthreads();
+    zrow_inverse<T, NR, false>(lds, stw, twf, z.C + si, z.lap + ro, nl, scale, az);
+}
+
+// ------------------------------------------------------------------ forward pair + ETD
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
+                                                         const c2<T>* __restrict__ twh,
+                                                         const c2<T>* __restrict__ twf, long nrows) {
+    constexpr int L = z_rows<NR>();
+    constexpr int MS = NR / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    __syncthreads();
+    zrow_forward<T, NR>(lds, stw, twf, P + row0 * NR, WP + row0 * MS, nl);
+    __syncthreads();
+    zrow_forward<T, NR>(lds, stw, twf, Q + row0 * NR, WQ + row0 * MS, nl);
+}
+
+// two spectra through the same plain line transform, one after the other
+template <typename T, int L> struct PairOp {
+    static constexpr int NT = 2;
+    struct In {};
+    const LineTile<L>* t;
+    c2<T>* X0;
+    c2<T>* X1;
+    long es;
+    __device__ __forceinline__ void load(int, int, In&) const {}
+    template <int K> __device__ __forceinline__ c2<T> input(int l, int e, const In&) const {
+        const long b = t->base[l];
+        return b >= 0 ? (K == 0 ? X0 : X1)[b + (long)e * es] : mk<T>(0, 0);
+    }
+    template <int K> __device__ __forceinline__ void store(int l, int e, c2<T> v) const {
+        const long b = t->base[l];
+        if (b >= 0) (K == 0 ? X0 : X1)[b + (long)e * es] = v;
+    }
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_y_pair(GridK g, c2<T>* X0, c2<T>* X1, const c2<T>* __restrict__ tw) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int LS = line_stride<N>();
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ LineTile<L> tile;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, tw, N);
+    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
+    __syncthreads();
+    lines_fft_seq<T, N, L, -1, true>(lds, stw, PairOp<T, L>{&tile, X0, X1, (long)g.nzh});
+}
+
+// forward x lines of (P, Q) held together; the epilogue forms k^2 in FP64
+// (same association as the standalone combine) and applies the ETD combine
+template <int ST, typename T, int L> struct EtdXOp {
+    static constexpr int NS = 2;
+    const LineTile<L>* t;
+    const c2<T>* P;
+    const c2<T>* Q;
+    long es;
+    int nx, ny;
+    double ax, ay, az;
+    const CoupledK* K;
+    EtdArgs<T> a;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        const long b = t->base[l];
+        v[0] = b >= 0 ? P[b + (long)e * es] : mk<T>(0, 0);
+        v[1] = b >= 0 ? Q[b + (long)e * es] : mk<T>(0, 0);
+    }
+    __device__ __forceinline__ void store_joint(int l, int e, const c2<T>* v) const {
+        const long b = t->base[l];
+        if (b < 0) return;
+        const double lx = ax * lam_index(e, nx), ly = ay * lam_index(t->o[l], ny), lz = az * t->c[l];
+        const double k2 = lx * lx + ly * ly + lz * lz;
+        etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a);
+    }
+};
+
+template <int ST, typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
+                                                    EtdArgs<T> a, const c2<T>* __restrict__ tw) {
+    constexpr int L = lines_per_block<T, N, 2>();
+    constexpr int LS = line_stride<N>();
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ LineTile<L> tile;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + 2 * L * LS;
+    load_table<T>(stw, tw, N);
+    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
+    __syncthreads();
+    lines_fft_joint<T, N, L, -1, true>(lds, stw,
+                                       EtdXOp<ST, T, L>{&tile, P, Q, (long)g.ny * g.nzh, g.nx, g.ny, kPi / g.X[0],
+                                                        kPi / g.X[1], kPi / g.X[2], &K, a});
+}
+
+// ------------------------------------------------------------------ (-Delta_h)^{-1}
+template <typename T, int L> struct TileLoad {
+    static constexpr int NS = 1;
+    const LineTile<L>* t;
+    const c2<T>* X;
+    long es;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        const long b = t->base[l];
+        v[0] = b >= 0 ? X[b + (long)e * es] : mk<T>(0, 0);
+    }
+    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
+};
+template <typename T, int L> struct TileStore {
+    static constexpr int NS = 1;
+    const LineTile<L>* t;
+    c2<T>* X;
+    long es;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        const long b = t->base[l];
+        if (b >= 0) X[b + (long)e * es] = v;
+    }
+};
+
+// Lines along the last forward axis: forward transform, times 1/mu with
+// mu = fde[e] + fdo[o] + fdc[c] (0 where mu = 0), inverse transform, in place.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_lapinv_lines(c2<T>* X, const c2<T>* __restrict__ tw, int C,
+                                                           int nlines, long ostride, long es,
+                                                           const double* __restrict__ fde,
+                                                           const double* __restrict__ fdo,
+                                                           const double* __restrict__ fdc) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int LS = line_stride<N>();
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ LineTile<L> tile;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * LS;
+    load_table<T>(stw, tw, N);
+    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), C, nlines, ostride);
+    __syncthreads();
+    lines_fft_to_lds<T, N, L, LS, 1, -1, true>(lds, stw, TileLoad<T, L>{&tile, X, es});
+    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
+        const int l = idx % L, e = idx / L;
+        const double mu = fde[e] + fdo[tile.o[l]] + fdc[tile.c[l]];
+        const T m = (T)(mu > 0.0 ? 1.0 / mu : 0.0);
+        c2<T>& v = lds[l * LS + sk(e)];
+        v = cscale(v, m);
+    }
+    __syncthreads();
+    lines_fft_from_lds<T, N, L, LS, +1, true>(lds, stw, TileStore<T, L>{&tile, X, es});
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int N> hipError_t launch_deriv_x(const GridK& g, const c2<T>* S, c2<T>* A, c2<T>* B, c2<T>* C,
+                                                       const c2<T>* tw, hipStream_t s) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    const size_t smem = lines_smem<T, N, L, 1>();
+    static std::once_flag flag;
+    set_smem_limit(k_deriv_x<T, N>, smem, flag);
+    const int ntiles = (g.ny * g.nzh + L - 1) / L;
+    hipLaunchKernelGGL((k_deriv_x<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, S, A, B, C, tw);
+    return hipGetLastError();
+}
+template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A, c2<T>* B, c2<T>* C, c2<T>* D,
+                                                       const c2<T>* tw, hipStream_t s) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    const size_t smem = lines_smem<T, N, L, 1>();
+    static std::once_flag flag;
+    set_smem_limit(k_deriv_y<T, N>, smem, flag);
+    const int ntiles = (g.nx * g.nzh + L - 1) / L;
+    hipLaunchKernelGGL((k_deriv_y<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, A, B, C, D, tw);
+    return hipGetLastError();
+}
+template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z, const c2<T>* twh,
+                                                        const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_deriv_z<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+    hipLaunchKernelGGL((k_deriv_z<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, z, twh, twf,
+                       nrows, scale, kPi / g.X[2]);
+    return hipGetLastError();
+}
+template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
+                                                       const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_pair<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    hipLaunchKernelGGL((k_z_r2c_pair<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, P, Q, WP, WQ,
+                       twh, twf, nrows);
+    return hipGetLastError();
+}
+template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0, c2<T>* X1, const c2<T>* tw,
+                                                      hipStream_t s) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    const size_t smem = lines_smem<T, N, L, 1>();
+    static std::once_flag flag;
+    set_smem_limit(k_y_pair<T, N>, smem, flag);
+    const int ntiles = (g.nx * g.nzh + L - 1) / L;
+    hipLaunchKernelGGL((k_y_pair<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, X0, X1, tw);
+    return hipGetLastError();
+}
+template <int ST, typename T, int N>
+hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
+                        const c2<T>* tw, hipStream_t s) {
+    constexpr int L = lines_per_block<T, N, 2>();
+    const size_t smem = lines_smem<T, N, L, 2>();
+    static std::once_flag flag;
+    set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
+    const int ntiles = (g.ny * g.nzh + L - 1) / L;
+    hipLaunchKernelGGL((k_x_etd<ST, T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, tw);
+    return hipGetLastError();
+}
+template <typename T, int N>
+hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostride, long es, const double* fde,
+                         const double* fdo, const double* fdc, hipStream_t s) {
+    constexpr int L = lines_per_block<T, N, 1>();
+    const size_t smem = lines_smem<T, N, L, 1>();
+    static std::once_flag flag;
+    set_smem_limit(k_lapinv_lines<T, N>, smem, flag);
+    const int nlines = C * nouter;
+    const int ntiles = (nlines + L - 1) / L;
+    hipLaunchKernelGGL((k_lapinv_lines<T, N>), dim3(ntiles), dim3(kThreads), smem, s, X, tw, C, nlines, ostride, es,
+                       fde, fdo, fdc);
+    return hipGetLastError();
+}
+
+template <int ST, typename T>
+hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
+                          const c2<T>* tw, hipStream_t s) {
+    switch (g.nx) {
+#define CASE(n) \
+    case n: return launch_x_etd<ST, T, n>(g, K, P, Q, a, tw, s);
+        ETD_FFT_SIZES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
+                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    hipError_t e = timed_pass(PASS_X_DERIV, 4.0 * cb, s, [&]() -> hipError_t {
+        switch (g.nx) {
+#define CASE(n) \
+    case n: return launch_deriv_x<T, n>(g, S, W0, W1, W2, t.tx, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    e = timed_pass(PASS_Y_DERIV, 7.0 * cb, s, [&]() -> hipError_t {
+        switch (g.ny) {
+#define CASE(n) \
+    case n: return launch_deriv_y<T, n>(g, W0, W1, W2, W3, t.ty, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    const DerivZArgs<T> z{W0, W1, W2, W3, phi, gx, gy, gz, lap};
+    return timed_pass(PASS_Z_DERIV, 4.0 * cb + 5.0 * rb, s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_deriv_z<T, n>(g, z, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+}
+
+template <typename T>
+hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, const T* P,
+                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    hipError_t e = timed_pass(PASS_Z_R2C_PAIR, 2.0 * (cb + rb), s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_pair<T, n>(g, P, Q, WP, WQ, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    e = timed_pass(PASS_Y_PAIR, 4.0 * cb, s, [&]() -> hipError_t {
+        switch (g.ny) {
+#define CASE(n) \
+    case n: return launch_y_pair<T, n>(g, WP, WQ, t.ty, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    // spectra the combine moves besides the two inputs
+    const double extra = (stage == ETD_STAGE_U1) ? 2.0 : 3.0;
+    return timed_pass(PASS_X_ETD, (2.0 + extra) * cb, s, [&]() -> hipError_t {
+        switch (stage) {
+            case ETD_STAGE_PHI1: return dispatch_x_etd<ETD_STAGE_PHI1, T>(g, K, WP, WQ, a, t.tx, s);
+            case ETD_STAGE_PHI2: return dispatch_x_etd<ETD_STAGE_PHI2, T>(g, K, WP, WQ, a, t.tx, s);
+            case ETD_STAGE_U1: return dispatch_x_etd<ETD_STAGE_U1, T>(g, K, WP, WQ, a, t.tx, s);
+            case ETD_STAGE_U2: return dispatch_x_etd<ETD_STAGE_U2, T>(g, K, WP, WQ, a, t.tx, s);
+        }
+        return hipErrorInvalidValue;
+    });
+}
+
+template <typename T>
+hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
+                        hipStream_t s) {
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    hipError_t e = fft_pass_z<T>(g, t, true, q, W, (T)1, s);
+    if (e != hipSuccess) return e;
+    const double* fdx = fd;
+    const double* fdy = fd + g.nx;
+    const double* fdz = fd + g.nx + g.ny;
+    if (g.nx > 1) {
+        if ((e = fft_pass_y<T>(g, t, -1, W, W, s)) != hipSuccess) return e;
+        // x lines: outer y (stride nzh), elements ny * nzh apart
+        e = timed_pass(PASS_LAPINV, 2.0 * cb, s, [&]() -> hipError_t {
+            switch (g.nx) {
+#define CASE(n) \
+    case n: return launch_lapinv<T, n>(W, t.tx, g.nzh, g.ny, (long)g.nzh, (long)g.ny * g.nzh, fdx, fdy, fdz, s);
+                ETD_FFT_SIZES(CASE)
+#undef CASE
+                default: return hipErrorInvalidValue;
+            }
+        });
+        if (e != hipSuccess) return e;
+        if ((e = fft_pass_y<T>(g, t, +1, W, W, s)) != hipSuccess) return e;
+    } else {
+        // y lines of a two-dimensional grid: outer x (one), elements nzh apart
+        e = timed_pass(PASS_LAPINV, 2.0 * cb, s, [&]() -> hipError_t {
+            switch (g.ny) {
+#define CASE(n) \
+    case n: return launch_lapinv<T, n>(W, t.ty, g.nzh, g.nx, (long)g.ny * g.nzh, (long)g.nzh, fdy, fdx, fdz, s);
+                ETD_FFT_SIZES(CASE)
+#undef CASE
+                default: return hipErrorInvalidValue;
+            }
+        });
+        if (e != hipSuccess) return e;
+    }
+    const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+    return fft_pass_z<T>(g, t, false, W, psi, scale, s);
+}
+
+#define INST(T)                                                                                                   \
+    template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
+                                        c2<T>*, T*, T*, T*, T*, T*, hipStream_t);                                 \
+    template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
+                                        const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, hipStream_t);                \
+    template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
+                                        hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace etd

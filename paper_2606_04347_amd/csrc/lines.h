@@ -143,6 +143,169 @@ __device__ __forceinline__ void lines_fft_to_lds(c2<T>* lds, const c2<T>* tw, co
     stockham<T, N, L * NSLOT, LS, R0, DIR>(lds, tw);
 }
 
+// ---------------------------------------------------------------- sequential transforms
+// NT transforms per line, run one after another through the LDS of a single
+// transform.  Their inputs are formed from per-element values loaded once by
+// the first stage and kept in registers (Op::In), so one read of a line family
+// feeds several outputs (e.g. S -> F^-1 S, F^-1 i k S, F^-1 (-k^2) S).
+//
+// SeqOp concept (T the real type):
+//   static constexpr int NT;
+//   struct In;                                                    // per-element register cache
+//   void load(int l, int e, In& in) const;
+//   template <int S> c2<T> input(int l, int e, const In& in) const;
+//   template <int S> void store(int l, int e, c2<T> v) const;
+// input<S> may also read global memory; an array read there must not be
+// written by a transform S' < S of the same line (writes of transform S' are
+// issued before transform S starts).
+
+template <typename T, class Op, int S> struct SlotStore {
+    static constexpr int NS = 1;
+    const Op& op;
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const { op.template store<S>(l, e, v); }
+};
+
+template <typename T, int N, int L, int LS, int R0, int IT, int DIR, bool LF, class Op, int S>
+__device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, const Op& op,
+                                               const typename Op::In (&in)[IT][R0]) {
+    constexpr int NR = N / R0;
+    constexpr int NB = L * NR;
+    if constexpr (R0 == N) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int l = threadIdx.x + it * kThreads;
+            if (l < NB) {
+                c2<T> v[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, r, in[it][r]);
+                dftR<T, R0, DIR>(v);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) op.template store<S>(l, r, v[r]);
+            }
+        }
+    } else {
+        if constexpr (S > 0) __syncthreads();   // the previous transform's last stage has read the LDS
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int b = threadIdx.x + it * kThreads;
+            if (b < NB) {
+                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+                c2<T> v[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, j + r * NR, in[it][r]);
+                dftR<T, R0, DIR>(v);
+                c2<T>* dst = lds + l * LS;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) dst[sk(j * R0 + r)] = v[r];
+            }
+        }
+        __syncthreads();
+        middle_and_last<T, N, L, LS, R0, DIR, LF>(lds, tw, SlotStore<T, Op, S>{op});
+    }
+    if constexpr (S + 1 < Op::NT) seq_transforms<T, N, L, LS, R0, IT, DIR, LF, Op, S + 1>(lds, tw, op, in);
+}
+
+template <typename T, int N, int L, int DIR, bool LF, class Op>
+__device__ __forceinline__ void lines_fft_seq(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int LS = line_stride<N>();
+    constexpr int R0 = NextRadix<N>::v;
+    constexpr int NR = N / R0;
+    constexpr int NB = L * NR;
+    constexpr int IT = (NB + kThreads - 1) / kThreads;
+    typename Op::In in[IT][R0];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if (b < NB) {
+            const int l = (R0 == N) ? b : (LF ? b % L : b / NR), j = (R0 == N) ? 0 : (LF ? b / L : b % NR);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) op.load(l, j + r * NR, in[it][r]);
+        }
+    }
+    seq_transforms<T, N, L, LS, R0, IT, DIR, LF, Op, 0>(lds, tw, op, in);
+}
+
+// ---------------------------------------------------------------- joint transforms
+// NS transforms per line held together in LDS (slot s of line l at row
+// s * L + l); the last stage finishes element (l, e) of every slot in one
+// thread and hands the NS results to Op::store_joint(l, e, v[NS]), so an
+// epilogue can combine the slots (e.g. R = F P - c k^2 F Q).
+
+template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
+__device__ __forceinline__ void last_stage_joint(const c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int NS = Op::NS;
+    constexpr int SP = N / R;
+    constexpr int NB = L * SP;
+    for (int b = threadIdx.x; b < NB; b += kThreads) {
+        const int l = LF ? b % L : b / SP, j = LF ? b / L : b % SP;
+        c2<T> v[NS][R];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const c2<T>* src = lds + (s * L + l) * LS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[s][r] = src[sk(j + r * SP)];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                c2<T> w = tw[r * j];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[s][r] = cmul(v[s][r], w);
+            }
+            dftR<T, R, DIR>(v[s]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            c2<T> o[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s] = v[s][r];
+            op.store_joint(l, j + r * SP, o);
+        }
+    }
+}
+
+template <typename T, int N, int L, int LS, int NSP, int DIR, bool LF, class Op>
+__device__ __forceinline__ void middle_and_last_joint(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int R = NextRadix<N / NSP>::v;
+    if constexpr (NSP * R == N) {
+        last_stage_joint<T, N, L, LS, R, DIR, LF, Op>(lds, tw, op);
+    } else {
+        stage<T, N, L * Op::NS, LS, R, NSP, DIR>(lds, tw);
+        middle_and_last_joint<T, N, L, LS, NSP * R, DIR, LF, Op>(lds, tw, op);
+    }
+}
+
+// JointOp concept: NS, load(l, e, v[NS]) as for lines_fft, and
+// store_joint(int l, int e, const c2<T>* v /* NS values */).
+template <typename T, int N, int L, int DIR, bool LF, class Op>
+__device__ __forceinline__ void lines_fft_joint(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int NS = Op::NS;
+    constexpr int LS = line_stride<N>();
+    constexpr int R0 = NextRadix<N>::v;
+    if constexpr (R0 == N) {
+        for (int l = threadIdx.x; l < L; l += kThreads) {
+            c2<T> v[NS][N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                c2<T> x[NS];
+                op.load(l, e, x);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) v[s][e] = x[s];
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) dftR<T, N, DIR>(v[s]);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                c2<T> o[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) o[s] = v[s][e];
+                op.store_joint(l, e, o);
+            }
+        }
+    } else {
+        first_stage<T, N, L, LS, R0, DIR, LF, Op>(lds, op);
+        middle_and_last_joint<T, N, L, LS, R0, DIR, LF, Op>(lds, tw, op);
+    }
+}
+
 // LDS elements needed by lines_fft plus the twiddle table.
 template <typename T, int N, int L, int NS> constexpr size_t lines_smem() {
     return sizeof(c2<T>) * (size_t)(L * NS * line_stride<N>() + N);

@@ -28,7 +28,9 @@ Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
 EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_status_string", "etd_last_error")
-PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines")
+PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
+              "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines")
+N_PASS_SLOTS = 16
 
 
 class Grid(C.Structure):
@@ -56,7 +58,8 @@ class InstanceDesc(C.Structure):
 
 
 class PassTimes(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("total_ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * N_PASS_SLOTS), ("total_ms", C.c_double * N_PASS_SLOTS),
+                ("bytes", C.c_double * N_PASS_SLOTS)]
 
 
 class Diag(C.Structure):
