@@ -216,7 +216,8 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
  *   7 z-row r2c of two fields          8 forward y lines of two spectra
  *   9 forward x lines of two spectra with the ETD combine
  *  10 last forward axis times 1/mu and back ((-Delta_h)^{-1})
- *  11..15 unused. */
+ *  11 z-row c2r of a G U increment with the recovery of U in the store
+ *  12..15 unused. */
 #define ETD_PASS_KINDS 16
 typedef struct {
     int64_t launches[ETD_PASS_KINDS];

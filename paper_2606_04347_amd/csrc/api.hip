@@ -504,14 +504,12 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
     // inverse transforms carry only the per-step change; g+ u^n is added back in
     // real space inside the recovery (same scheme, smaller rounding in FP32).
     HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, s));      // Sgu = GU~^ - FFT(g+ u^n), Sra = R2(u^n)^
-    HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
-    recover_increment<T>(n, v.u, v.P, v.gp, v.ut, I.K.thr, s);      // U~
+    HIPCHK(plan, c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, v.ut, I.K.thr, s));   // U~
     if (!rk2) {
         std::swap(I.u, I.ut);
     } else {
         HIPCHK(plan, u_stage<T>(I, v, v.ut, mask, ETD_STAGE_U2, s));
-        HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sgu, v.Stmp, v.P, s));
-        recover_increment<T>(n, v.u, v.P, v.gp, v.u, I.K.thr, s);   // U^{n+1}
+        HIPCHK(plan, c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, v.u, I.K.thr, s));   // U^{n+1}
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
         mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);

@@ -73,4 +73,12 @@ __host__ __device__ __forceinline__ int der_index(int i, int N) {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
+// Round-robin dispatch puts block b on XCD b % 8 (eight XCDs, each with its
+// own L2); renumber so that each XCD works on one contiguous range of tiles
+// (neighbouring tiles then share L2 lines).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 }  // namespace etd

@@ -110,7 +110,8 @@ template <typename T>
 __global__ void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const T* __restrict__ lap,
                            const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
                            const T* __restrict__ u, const uint8_t* __restrict__ mask,
-                           const double* __restrict__ int_phi, double A0, T* __restrict__ P, T* __restrict__ Q) {
+                           const double* __restrict__ int_phi, double A0, T* __restrict__ P, T* __restrict__ Q,
+                           int tpb) {
     const long n = g.nreal();
     const T e2 = (T)(K.eps_phi * K.eps_phi);
     const T c1 = (T)K.c1, A1 = (T)K.A1, A2 = (T)K.A2;
@@ -122,7 +123,12 @@ __global__ void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const
     const T u0 = (T)K.u0;
     const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
     const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    // a block takes tpb consecutive tiles of kBlock points, blocks in XCD-contiguous
+    // order, so that the y and x neighbour rows of a tile are read through the same L2
+    const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
+    for (int it = 0; it < tpb; ++it) {
+        const long i = (t0 + it) * kBlock + threadIdx.x;
+        if (i >= n) return;
         const Nbr nb = neighbours(g, i);
         const T p = phi[i], L = lap[i];
         const T a = gx[i], b = gy[i], c = gz[i];
@@ -179,14 +185,19 @@ template <typename T>
 __global__ void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u, const T* __restrict__ G,
                            const T* __restrict__ vx, const T* __restrict__ vy, const T* __restrict__ vz,
                            const T* __restrict__ psi, const double* __restrict__ m, const uint8_t* __restrict__ mask,
-                           T* __restrict__ P) {
+                           T* __restrict__ P, int tpb) {
     const long n = g.nreal();
     const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), B2 = (T)K.B2, gam = (T)K.gamma;
     const T Mm = (T)(K.M * m[0]);
     const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
     const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
     const T i2hx = (T)(g.nx > 1 ? 0.5 / g.h[0] : 0.0), i2hy = (T)(0.5 / g.h[1]), i2hz = (T)(0.5 / g.h[2]);
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    // a block takes tpb consecutive tiles of kBlock points, blocks in XCD-contiguous
+    // order, so that the y and x neighbour rows of a tile are read through the same L2
+    const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
+    for (int it = 0; it < tpb; ++it) {
+        const long i = (t0 + it) * kBlock + threadIdx.x;
+        if (i >= n) return;
         const Nbr nb = neighbours(g, i);
         const T uc = u[i], Gc = G[i];
         T S = lapS_axis(u[nb.xm], uc, u[nb.xp], G[nb.xm], Gc, G[nb.xp], ihx);
@@ -222,6 +233,17 @@ template <typename T> __global__ void k_gloc(long n, const T* __restrict__ phi, 
 
 __global__ void k_delta(long n, double* x) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) x[i] = (i == 0) ? 1.0 : 0.0;
+}
+
+// Stencil launches: tiles of kBlock points, tpb consecutive tiles per block,
+// at most 8192 blocks (grids hold fewer than 2^31 points).
+struct TileGrid {
+    int blocks, tpb;
+};
+TileGrid tiles_for(long n) {
+    const long tiles = (n + kBlock - 1) / kBlock;
+    const int tpb = (int)((tiles + 8191) / 8192);
+    return {(int)((tiles + tpb - 1) / tpb), tpb};
 }
 
 int grid_for(long n) {
@@ -264,8 +286,9 @@ template <typename T>
 void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
                       const T* gz, const T* u, const uint8_t* mask, const double* int_phi, double A0, T* P, T* Q,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_R1_point<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, phi, lap, gx, gy, gz, u,
-                       mask, int_phi, A0, P, Q);
+    const TileGrid tg = tiles_for(g.nreal());
+    hipLaunchKernelGGL(k_R1_point<T>, dim3(tg.blocks), dim3(kBlock), 0, s, g, K, phi, lap, gx, gy, gz, u, mask, int_phi,
+                       A0, P, Q, tg.tpb);
 }
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* po, const T* pn, const T* gx, const T* gy,
@@ -282,8 +305,9 @@ void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* G, con
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
                       const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s) {
-    hipLaunchKernelGGL(k_P2_point<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, psi, m,
-                       mask, P);
+    const TileGrid tg = tiles_for(g.nreal());
+    hipLaunchKernelGGL(k_P2_point<T>, dim3(tg.blocks), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, psi, m, mask, P,
+                       tg.tpb);
 }
 template <typename T>
 void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s) {

@@ -46,6 +46,7 @@ enum PassKind {
     PASS_Y_PAIR = 8,       // forward y lines of two spectra
     PASS_X_ETD = 9,        // forward x lines of two spectra + ETD combine
     PASS_LAPINV = 10,      // last forward axis, times 1/mu, inverse along the same axis
+    PASS_Z_RECOVER = 11,   // z rows c2r of an increment with the recovery of U
     PASS_KIND_COUNT = 16
 };
 struct PassHook {

@@ -31,4 +31,12 @@ template <typename T>
 hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
                         hipStream_t s);
 
+// U from an increment spectrum D of G U (Section 3.3 after Algorithm 1):
+// d = F^-1 D, out = u_old + d / G where G > thr, G u_old + d elsewhere; the
+// recovery runs in the store of the z c2r pass.  W: complex work array (D is
+// preserved); out may alias u_old.
+template <typename T>
+hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
+                       T* out, double thr, hipStream_t s);
+
 }  // namespace etd

@@ -75,7 +75,9 @@ template <typename T, int L> struct DerivXOp {
 
 // Inverse y lines at fixed (x, kz) over the x-pass outputs A, B, C:
 //   Y^-1 B -> B,  Y^-1 (C - (ky^2 + kz^2) A) -> C,  Y^-1 A -> A,  Y^-1 (i ky A) -> D.
-// B and C are read by the transform that overwrites them; A is kept in registers.
+// A is fetched up front into registers; B and C are read by the transform
+// that overwrites them (fetching all three up front measured slower: the
+// extra registers cost more occupancy than the early loads gain).
 template <typename T, int L> struct DerivYOp {
     static constexpr int NT = 4;
     struct In {
@@ -168,22 +170,81 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<
                                                       double az) {
     constexpr int L = z_rows<NR>();
     constexpr int MS = NR / 2 + 1;
+    constexpr int M = NR / 2;
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
+    load_table<T>(stw, twh, M);
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
     const long si = row0 * MS, ro = row0 * NR;
-    zrow_inverse<T, NR, false>(lds, stw, twf, z.A + si, z.phi + ro, nl, scale, az);
+    auto out = [&](T* f) { return RowPairStore<T, M>{reinterpret_cast<c2<T>*>(f + ro), nl, scale}; };
+    // each input is fetched into registers while the previous output is transformed
+    c2<T> pre[z_fetch_count<NR>()];
+    zrow_fetch<T, NR>(pre, z.A + si, nl);
+    zrow_put<T, NR, false>(lds, pre, az);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.phi));
     __syncthreads();
-    zrow_inverse<T, NR, true>(lds, stw, twf, z.A + si, z.gz + ro, nl, scale, az);
+    zrow_put<T, NR, true>(lds, pre, az);
+    zrow_fetch<T, NR>(pre, z.B + si, nl);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gz));
     __syncthreads();
-    zrow_inverse<T, NR, false>(lds, stw, twf, z.B + si, z.gx + ro, nl, scale, az);
+    zrow_put<T, NR, false>(lds, pre, az);
+    zrow_fetch<T, NR>(pre, z.D + si, nl);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gx));
     __syncthreads();
-    zrow_inverse<T, NR, false>(lds, stw, twf, z.D + si, z.gy + ro, nl, scale, az);
+    zrow_put<T, NR, false>(lds, pre, az);
+    zrow_fetch<T, NR>(pre, z.C + si, nl);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gy));
     __syncthreads();
-    zrow_inverse<T, NR, false>(lds, stw, twf, z.C + si, z.lap + ro, nl, scale, az);
+    zrow_put<T, NR, false>(lds, pre, az);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.lap));
+}
+
+// z rows c2r of an increment spectrum D with the recovery of U in the store
+// (Section 3.3 after Algorithm 1): d = Z^-1 D, out = u_old + d / G where
+// G > thr, G u_old + d elsewhere (out may alias u_old).
+template <typename T, int M> struct RecoverStore {
+    static constexpr int NS = 1;
+    const c2<T>* uo;    // first row of the tile, as pairs
+    const c2<T>* G;
+    c2<T>* out;
+    int nl;
+    T scale, thr;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        if (l >= nl) return;
+        const long i = (long)l * M + e;
+        const c2<T> u = uo[i], g = G[i];
+        const T d0 = v.x * scale, d1 = v.y * scale;
+        c2<T> r;
+        r.x = (g.x > thr) ? u.x + d0 / g.x : g.x * u.x + d0;
+        r.y = (g.y > thr) ? u.y + d1 / g.y : g.y * u.y + d1;
+        out[i] = r;
+    }
+};
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_z_c2r_recover(const c2<T>* D, const T* uo, const T* G, T* out,
+                                                            const c2<T>* __restrict__ twh,
+                                                            const c2<T>* __restrict__ twf, long nrows, T scale,
+                                                            T thr) {
+    constexpr int L = z_rows<NR>();
+    constexpr int M = NR / 2;
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, M);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    const long ro = row0 * NR;
+    c2<T> pre[z_fetch_count<NR>()];
+    zrow_fetch<T, NR>(pre, D + row0 * (M + 1), nl);
+    zrow_put<T, NR, false>(lds, pre, 0.0);
+    zrow_inverse_lds<T, NR>(lds, stw, twf,
+                            RecoverStore<T, M>{reinterpret_cast<const c2<T>*>(uo + ro),
+                                               reinterpret_cast<const c2<T>*>(G + ro),
+                                               reinterpret_cast<c2<T>*>(out + ro), nl, scale, thr});
 }
 
 // ------------------------------------------------------------------ forward pair + ETD
@@ -206,6 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q,
 }
 
 // two spectra through the same plain line transform, one after the other
+// (each read by its own transform)
 template <typename T, int L> struct PairOp {
     static constexpr int NT = 2;
     struct In {};
@@ -238,10 +300,14 @@ __global__ __launch_bounds__(kThreads) void k_y_pair(GridK g, c2<T>* X0, c2<T>* 
     lines_fft_seq<T, N, L, -1, true>(lds, stw, PairOp<T, L>{&tile, X0, X1, (long)g.nzh});
 }
 
-// forward x lines of (P, Q) held together; the epilogue forms k^2 in FP64
-// (same association as the standalone combine) and applies the ETD combine
+// forward x lines of P and Q (both fetched up front, transformed one after
+// the other); the epilogue forms k^2 in FP64 (same association as the
+// standalone combine) and applies the ETD combine
 template <int ST, typename T, int L> struct EtdXOp {
-    static constexpr int NS = 2;
+    static constexpr int NT = 2;
+    struct In {
+        c2<T> p, q;
+    };
     const LineTile<L>* t;
     const c2<T>* P;
     const c2<T>* Q;
@@ -250,10 +316,13 @@ template <int ST, typename T, int L> struct EtdXOp {
     double ax, ay, az;
     const CoupledK* K;
     EtdArgs<T> a;
-    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+    __device__ __forceinline__ void load(int l, int e, In& in) const {
         const long b = t->base[l];
-        v[0] = b >= 0 ? P[b + (long)e * es] : mk<T>(0, 0);
-        v[1] = b >= 0 ? Q[b + (long)e * es] : mk<T>(0, 0);
+        in.p = b >= 0 ? P[b + (long)e * es] : mk<T>(0, 0);
+        in.q = b >= 0 ? Q[b + (long)e * es] : mk<T>(0, 0);
+    }
+    template <int K> __device__ __forceinline__ c2<T> input(int, int, const In& in) const {
+        return K == 0 ? in.p : in.q;
     }
     __device__ __forceinline__ void store_joint(int l, int e, const c2<T>* v) const {
         const long b = t->base[l];
@@ -267,18 +336,18 @@ template <int ST, typename T, int L> struct EtdXOp {
 template <int ST, typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
                                                     EtdArgs<T> a, const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block<T, N, 2>();
+    constexpr int L = lines_per_block<T, N, 1>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + 2 * L * LS;
+    c2<T>* stw = lds + L * LS;
     load_table<T>(stw, tw, N);
     tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
     __syncthreads();
-    lines_fft_joint<T, N, L, -1, true>(lds, stw,
-                                       EtdXOp<ST, T, L>{&tile, P, Q, (long)g.ny * g.nzh, g.nx, g.ny, kPi / g.X[0],
-                                                        kPi / g.X[1], kPi / g.X[2], &K, a});
+    lines_fft_seq_joint<T, N, L, -1, true>(lds, stw,
+                                           EtdXOp<ST, T, L>{&tile, P, Q, (long)g.ny * g.nzh, g.nx, g.ny,
+                                                            kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K, a});
 }
 
 // ------------------------------------------------------------------ (-Delta_h)^{-1}
@@ -367,6 +436,19 @@ template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const De
                        nrows, scale, kPi / g.X[2]);
     return hipGetLastError();
 }
+template <typename T, int NR>
+hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T* G, T* out, double thr,
+                            const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_c2r_recover<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+    hipLaunchKernelGGL((k_z_c2r_recover<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, D, uo, G,
+                       out, twh, twf, nrows, scale, (T)thr);
+    return hipGetLastError();
+}
 template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows<NR>();
@@ -391,8 +473,8 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
 template <int ST, typename T, int N>
 hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
                         const c2<T>* tw, hipStream_t s) {
-    constexpr int L = lines_per_block<T, N, 2>();
-    const size_t smem = lines_smem<T, N, L, 2>();
+    constexpr int L = lines_per_block<T, N, 1>();
+    const size_t smem = lines_smem<T, N, L, 1>();
     static std::once_flag flag;
     set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
@@ -544,7 +626,32 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
     return fft_pass_z<T>(g, t, false, W, psi, scale, s);
 }
 
+template <typename T>
+hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
+                       T* out, double thr, hipStream_t s) {
+    const c2<T>* cur = D;
+    hipError_t e = hipSuccess;
+    if (g.nx > 1) {
+        if ((e = fft_pass_x<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
+        cur = W;
+    }
+    if ((e = fft_pass_y<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    return timed_pass(PASS_Z_RECOVER, cb + 3.0 * rb, s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+}
+
 #define INST(T)                                                                                                   \
+    template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
+                                       const T*, T*, double, hipStream_t);                                        \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
                                         c2<T>*, T*, T*, T*, T*, T*, hipStream_t);                                 \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \

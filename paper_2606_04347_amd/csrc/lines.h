@@ -225,6 +225,163 @@ __device__ __forceinline__ void lines_fft_seq(c2<T>* lds, const c2<T>* tw, const
     seq_transforms<T, N, L, LS, R0, IT, DIR, LF, Op, 0>(lds, tw, op, in);
 }
 
+// ---------------------------------------------------------------- sequential transforms, joint store
+// As lines_fft_seq, but the outputs of the NT transforms are combined per
+// element: the last stage maps elements to threads identically for every
+// transform, so transforms 0..NT-2 leave their results in registers and the
+// last one hands all NT values of element (l, e) to Op::store_joint(l, e, v).
+// LDS use is that of a single transform.
+
+constexpr int ilog2c(int m) {
+    int k = 0;
+    while (m > 1) {
+        m /= 2;
+        ++k;
+    }
+    return k;
+}
+// same rule as NextRadix
+constexpr int next_radix(int m) {
+    const int k = ilog2c(m);
+    return (m % 3 == 0) ? 3 : (k == 1 ? 2 : ((k % 3 == 1 || k == 2) ? 4 : 8));
+}
+constexpr int last_radix(int n) {
+    int sp = 1;
+    for (;;) {
+        const int r = next_radix(n / sp);
+        if (sp * r == n) return r;
+        sp *= r;
+    }
+}
+
+template <typename T, int N, int L, int LS, int R, int DIR, bool LF, int NT, int IT, int S, class Op>
+__device__ __forceinline__ void last_stage_stash(const c2<T>* lds, const c2<T>* tw, const Op& op,
+                                                 c2<T> (&stash)[NT][IT][R]) {
+    constexpr int SP = N / R;
+    constexpr int NB = L * SP;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if ((NB % kThreads == 0) || b < NB) {
+            const int l = LF ? b % L : b / SP, j = LF ? b / L : b % SP;
+            const c2<T>* src = lds + l * LS;
+            c2<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = src[sk(j + r * SP)];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                c2<T> w = tw[r * j];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+            dftR<T, R, DIR>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (S + 1 < NT) {
+                    stash[S][it][r] = v[r];
+                } else {
+                    c2<T> o[NT];
+#pragma unroll
+                    for (int s = 0; s + 1 < NT; ++s) o[s] = stash[s][it][r];
+                    o[NT - 1] = v[r];
+                    op.store_joint(l, j + r * SP, o);
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int N, int L, int LS, int NSP, int DIR, bool LF, int NT, int IT, int RL, int S, class Op>
+__device__ __forceinline__ void middle_and_last_stash(c2<T>* lds, const c2<T>* tw, const Op& op,
+                                                      c2<T> (&stash)[NT][IT][RL]) {
+    constexpr int R = NextRadix<N / NSP>::v;
+    if constexpr (NSP * R == N) {
+        last_stage_stash<T, N, L, LS, R, DIR, LF, NT, IT, S, Op>(lds, tw, op, stash);
+    } else {
+        stage<T, N, L, LS, R, NSP, DIR>(lds, tw);
+        middle_and_last_stash<T, N, L, LS, NSP * R, DIR, LF, NT, IT, RL, S, Op>(lds, tw, op, stash);
+    }
+}
+
+template <typename T, int N, int L, int LS, int R0, int ITI, int DIR, bool LF, class Op, int S, int ITL, int RL>
+__device__ __forceinline__ void seq_joint_transforms(c2<T>* lds, const c2<T>* tw, const Op& op,
+                                                     const typename Op::In (&in)[ITI][R0],
+                                                     c2<T> (&stash)[Op::NT][ITL][RL]) {
+    constexpr int NT = Op::NT;
+    constexpr int NR = N / R0;
+    constexpr int NB = L * NR;
+    if constexpr (R0 == N) {
+        // single stage: a thread owns whole lines (ITL == ITI, RL == N)
+#pragma unroll
+        for (int it = 0; it < ITI; ++it) {
+            const int l = threadIdx.x + it * kThreads;
+            if (l < L) {
+                c2<T> v[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, r, in[it][r]);
+                dftR<T, R0, DIR>(v);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    if constexpr (S + 1 < NT) {
+                        stash[S][it][r] = v[r];
+                    } else {
+                        c2<T> o[NT];
+#pragma unroll
+                        for (int s = 0; s + 1 < NT; ++s) o[s] = stash[s][it][r];
+                        o[NT - 1] = v[r];
+                        op.store_joint(l, r, o);
+                    }
+                }
+            }
+        }
+    } else {
+        if constexpr (S > 0) __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITI; ++it) {
+            const int b = threadIdx.x + it * kThreads;
+            if (b < NB) {
+                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+                c2<T> v[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, j + r * NR, in[it][r]);
+                dftR<T, R0, DIR>(v);
+                c2<T>* dst = lds + l * LS;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) dst[sk(j * R0 + r)] = v[r];
+            }
+        }
+        __syncthreads();
+        middle_and_last_stash<T, N, L, LS, R0, DIR, LF, NT, ITL, RL, S, Op>(lds, tw, op, stash);
+    }
+    if constexpr (S + 1 < NT)
+        seq_joint_transforms<T, N, L, LS, R0, ITI, DIR, LF, Op, S + 1, ITL, RL>(lds, tw, op, in, stash);
+}
+
+// SeqJointOp concept: NT, In, load, input<S> as for lines_fft_seq, and
+// store_joint(int l, int e, const c2<T>* v /* NT values */).
+template <typename T, int N, int L, int DIR, bool LF, class Op>
+__device__ __forceinline__ void lines_fft_seq_joint(c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int LS = line_stride<N>();
+    constexpr int R0 = NextRadix<N>::v;
+    constexpr int NR = N / R0;
+    constexpr int NB = L * NR;
+    constexpr int ITI = (NB + kThreads - 1) / kThreads;
+    constexpr int RL = (R0 == N) ? N : last_radix(N);
+    constexpr int ITL = (R0 == N) ? ITI : (L * (N / RL) + kThreads - 1) / kThreads;
+    typename Op::In in[ITI][R0];
+#pragma unroll
+    for (int it = 0; it < ITI; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if (b < NB) {
+            const int l = (R0 == N) ? b : (LF ? b % L : b / NR), j = (R0 == N) ? 0 : (LF ? b / L : b % NR);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) op.load(l, j + r * NR, in[it][r]);
+        }
+    }
+    c2<T> stash[Op::NT][ITL][RL];
+    seq_joint_transforms<T, N, L, LS, R0, ITI, DIR, LF, Op, 0, ITL, RL>(lds, tw, op, in, stash);
+}
+
 // ---------------------------------------------------------------- joint transforms
 // NS transforms per line held together in LDS (slot s of line l at row
 // s * L + l); the last stage finishes element (l, e) of every slot in one

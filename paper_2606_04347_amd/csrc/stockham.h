@@ -89,13 +89,6 @@ template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(c2<T>
 __host__ __device__ __forceinline__ constexpr int sk(int e) { return e + (e >> 4); }
 template <int N> constexpr int line_stride() { return N + (N >> 4) + 1; }
 
-// Round-robin dispatch puts block b on XCD b % 8; renumber so that each XCD
-// works on one contiguous range of tiles (neighbouring tiles share L2 lines).
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
-    return x * q + min(x, r) + k;
-}
-
 // One radix-R Stockham stage on L lines of length N in LDS (line stride LS).
 template <typename T, int N, int L, int LS, int R, int NS, int DIR>
 __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {

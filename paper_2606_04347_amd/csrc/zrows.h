@@ -78,27 +78,58 @@ __device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const
     }
 }
 
-// Inverse: half-spectrum rows src -> real rows dst, times scale.  DZ: take
-// i kz X_k instead of X_k (kz = az * derivative index of k, Nyquist bin 0).
-// The imaginary parts of the k = 0 and k = M bins are ignored.  On entry the
-// LDS rows are free.
+// ---- inverse, in three steps so that a kernel with several outputs can fetch
+// the next input while the current one is transformed.
+template <int NR> constexpr int z_fetch_count() { return (z_rows<NR>() * (NR / 2 + 1) + kThreads - 1) / kThreads; }
+
+// Half-spectrum rows of a tile (nl <= L rows of M + 1 values) into registers;
+// element idx = threadIdx.x + p * kThreads of the row-major tile.
+template <typename T, int NR>
+__device__ __forceinline__ void zrow_fetch(c2<T> (&pre)[z_fetch_count<NR>()], const c2<T>* src, int nl) {
+    constexpr int MS = NR / 2 + 1;
+    constexpr int TOT = z_rows<NR>() * MS;
+#pragma unroll
+    for (int p = 0; p < z_fetch_count<NR>(); ++p) {
+        const int idx = threadIdx.x + p * kThreads;
+        pre[p] = (idx < TOT && idx / MS < nl) ? src[idx] : mk<T>(0, 0);
+    }
+}
+
+// Registers -> LDS rows, times i kz (kz = az * derivative index of k, Nyquist
+// bin 0) if DZ.  The LDS rows must be free (callers barrier first).
 template <typename T, int NR, bool DZ>
-__device__ __forceinline__ void zrow_inverse(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
-                                             const c2<T>* src, T* dst_rows, int nl, T scale, double az) {
+__device__ __forceinline__ void zrow_put(c2<T>* lds, const c2<T> (&pre)[z_fetch_count<NR>()], double az) {
+    constexpr int MS = NR / 2 + 1;
+    constexpr int TOT = z_rows<NR>() * MS;
+    constexpr int LS = z_row_stride<NR>();
+#pragma unroll
+    for (int p = 0; p < z_fetch_count<NR>(); ++p) {
+        const int idx = threadIdx.x + p * kThreads;
+        if (idx < TOT) {
+            const int r = idx / MS, k = idx % MS;
+            c2<T> v = pre[p];
+            if constexpr (DZ) {
+                const T kz = (T)(az * (double)der_index(k, NR));
+                v = mk<T>(-kz * v.y, kz * v.x);
+            }
+            lds[r * LS + sk(k)] = v;
+        }
+    }
+}
+
+// LDS rows of X (written by zrow_put, not yet behind a barrier) -> pack ->
+// inverse half-length transform -> Op::store(row, 0, n, z_n) with z_n the
+// unscaled pair (x_{2n}, x_{2n+1}).  The imaginary parts of the k = 0 and
+// k = M bins are ignored.
+template <typename T, int NR, class Op>
+__device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
+                                                 const Op& op) {
     constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
     constexpr int LS = z_row_stride<NR>();
-    for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
-        const int r = idx / (M + 1), k = idx % (M + 1);
-        c2<T> v = (r < nl) ? src[idx] : mk<T>(0, 0);
-        if constexpr (DZ) {
-            const T kz = (T)(az * (double)der_index(k, NR));
-            v = mk<T>(-kz * v.y, kz * v.x);
-        }
-        lds[r * LS + sk(k)] = v;
-    }
     __syncthreads();
-    // each thread owns the pair (k, M - k), so the update is in place without a barrier
+    // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) w^{-k}; each thread owns
+    // the pair (k, M - k), so the update is in place without a barrier
     constexpr int HP = M / 2 + 1;
     for (int idx = threadIdx.x; idx < L * HP; idx += kThreads) {
         const int r = idx / HP, k = idx % HP;
@@ -120,17 +151,26 @@ __device__ __forceinline__ void zrow_inverse(c2<T>* lds, const c2<T>* stw, const
         }
     }
     __syncthreads();
-    c2<T>* dst = reinterpret_cast<c2<T>*>(dst_rows);
     if constexpr (NextRadix<M>::v == M) {
         stockham<T, M, L, LS, 1, +1>(lds, stw);
         for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
             const int r = idx / M, n = idx % M;
-            if (r < nl) dst[idx] = cscale(lds[r * LS + sk(n)], scale);
+            op.store(r, 0, n, lds[r * LS + sk(n)]);
         }
     } else {
-        // the last stage writes the real pairs (x_{2n}, x_{2n+1}) = z_n straight to the rows
-        lines_fft_from_lds<T, M, L, LS, +1, false>(lds, stw, RowPairStore<T, M>{dst, nl, scale});
+        lines_fft_from_lds<T, M, L, LS, +1, false>(lds, stw, op);
     }
+}
+
+// Inverse: half-spectrum rows src -> real rows dst, times scale.  On entry the
+// LDS rows are free.
+template <typename T, int NR, bool DZ>
+__device__ __forceinline__ void zrow_inverse(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
+                                             const c2<T>* src, T* dst_rows, int nl, T scale, double az) {
+    c2<T> pre[z_fetch_count<NR>()];
+    zrow_fetch<T, NR>(pre, src, nl);
+    zrow_put<T, NR, DZ>(lds, pre, az);
+    zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, NR / 2>{reinterpret_cast<c2<T>*>(dst_rows), nl, scale});
 }
 
 }  // namespace stk

@@ -29,7 +29,7 @@ EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_get_stat
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_status_string", "etd_last_error")
 PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
-              "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines")
+              "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover")
 N_PASS_SLOTS = 16
 
 
