@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--err-steps", type=int, default=100,
                     help="FP32 vs FP64 GPU gap after this many steps (0 = skip)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances)")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (a reference kernel of known size "
                          "for hardware byte counters)")
@@ -136,6 +139,60 @@ def precision_gap(ci, nsteps):
             "g_at_max_u_gap": float(g.reshape(-1)[int(np.argmax(e))])}
 
 
+def batch_measure(steps, warmup):
+    """Uneven batch of 48 coupled FP32 ETDRK2 instances (32 x 64^3, 12 x 96^3,
+    4 x 128^3 = 27,394,048 points) in one plan: the autotuned schedule against
+    sequential eager launches of the same plan and against one plan per
+    instance replaying its own graph."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    t0 = time.time()
+    cis = inputs.batch_sweep()
+    log(f"batch inputs {time.time() - t0:.1f}s")
+    npts = sum(int(ci.phi0.size) for ci in cis)
+
+    def build(sel):
+        plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32) for ci in sel])
+        for i, ci in enumerate(sel):
+            plan.set_state(i, torch.as_tensor(ci.phi0, dtype=torch.float32, device="cuda"),
+                           torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
+        return plan
+
+    base_steps = max(2, (steps // 4) & ~1)
+    plan = build(cis)
+    ms_eager = timed_steps(plan, base_steps, warmup) / base_steps
+    mode, branches, tune = plan.autotune(trial_steps=10)
+    ms_tuned = timed_steps(plan, steps, warmup) / steps
+    plan.close()
+    # one plan per instance, each replaying its own two-step graph, launched in turn
+    plans = [build([ci]) for ci in cis]
+    for p in plans:
+        p.set_schedule(etd.EXEC_GRAPH, 1)
+        p.step(2)
+    torch.cuda.synchronize()
+    s = plans[0].stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(base_steps // 2):
+        for p in plans:
+            p.step(2)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_graphs = e0.elapsed_time(e1) / base_steps
+    for p in plans:
+        p.close()
+    rate = lambda ms: npts / (ms * 1e-3)
+    return {"workload": "32 x 64^3 + 12 x 96^3 + 4 x 128^3 coupled ETDRK2 FP32 instances in one plan "
+                        f"({npts} points), per-instance seeds, coefficients and tau in {{5e-5, 1e-4}}",
+            "value": rate(ms_tuned), "unit": "grid-pt steps/s", "ms_per_step": ms_tuned, "steps": steps,
+            "schedule": {"mode": "graph" if mode == etd.EXEC_GRAPH else "eager", "branches": branches},
+            "autotune_ms_per_step": tune,
+            "eager_sequential": {"value": rate(ms_eager), "ms_per_step": ms_eager, "steps": base_steps},
+            "per_instance_graphs": {"value": rate(ms_graphs), "ms_per_step": ms_graphs, "steps": base_steps},
+            "speedup_vs_eager": ms_eager / ms_tuned, "speedup_vs_per_instance_graphs": ms_graphs / ms_tuned}
+
+
 def cpu_baseline(ci):
     """The FP64 oracle, as it stands, timed on one ETDRK2 step of the workload."""
     from oracle import core
@@ -206,6 +263,11 @@ def main():
         out["fp64"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
                        "roofline": res["fp64"]["roofline"]}
         out["fp32_over_fp64"] = res["fp32"]["value"] / res["fp64"]["value"]
+    if not a.no_batch:
+        out["batched"] = batch_measure(a.batch_steps, a.warmup)
+        log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "
+            f"x{out['batched']['speedup_vs_eager']:.2f} vs eager, "
+            f"x{out['batched']['speedup_vs_per_instance_graphs']:.2f} vs per-instance graphs")
     if a.err_steps > 0:
         out["fp32_vs_fp64"] = precision_gap(ci, a.err_steps)
         log(f"fp32 vs fp64 after {a.err_steps} steps: {out['fp32_vs_fp64']}")

@@ -242,6 +242,47 @@ typedef enum {
 etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double* out);
 
 /* Static strings; never NULL. */
+/* Execution schedule of etd_step over all instances of a plan (a batch of
+ * uneven instances, e.g. many 64^3, 96^3 and 128^3 vesicles in one plan).
+ *   ETD_EXEC_EAGER  every kernel is launched from the host, one instance
+ *                   after another, on the plan's stream (the default).
+ *   ETD_EXEC_GRAPH  two steps of all instances are captured once into a HIP
+ *                   graph and replayed.  Inside the graph the instances are
+ *                   spread round-robin over `branches` (1..64) concurrent
+ *                   branches forked from and joined back to the plan's
+ *                   stream, so small instances overlap on the device.  An odd
+ *                   remaining step runs eagerly.  The captured graphs are
+ *                   dropped by etd_set_state and etd_set_schedule and are
+ *                   recaptured when the band-rebuild pattern of the two
+ *                   captured steps changes.  Pass timing forces eager steps.
+ * Results are identical under every schedule (the instances are
+ * independent and every kernel runs the same arithmetic). */
+typedef enum { ETD_EXEC_EAGER = 0, ETD_EXEC_GRAPH = 1 } etd_exec_mode;
+typedef struct {
+    int mode;       /* etd_exec_mode */
+    int branches;   /* concurrent capture branches (graph mode) */
+} etd_schedule;
+etd_status etd_set_schedule(etd_plan_t plan, const etd_schedule* sched);
+etd_status etd_get_schedule(etd_plan_t plan, etd_schedule* out);
+
+/* Schedule autotuner.  Times trial_steps (rounded up to even, >= 2) steps
+ * of each candidate -- eager, then graph with 1, 2, 4, 8, 16 and 32 branches
+ * (those not above the instance count) -- after two untimed warm-up steps
+ * each, on the current states; then restores every instance exactly from a
+ * device snapshot taken first (state fields, spectrum, derivatives, band
+ * mask, device scalars, step counter), sets the fastest schedule and returns
+ * it in *chosen (may be NULL).  ms_out (may be NULL) receives the per-step
+ * milliseconds of the 7 candidates in that order (negative for a candidate
+ * not tried).  cache_path (may be NULL) names a JSON file of earlier choices
+ * keyed by the device architecture and the sorted multiset of (model,
+ * scheme, precision, grid) of the instances: a hit selects the cached
+ * schedule without trials (ms_out entries then negative); a miss appends the
+ * new choice.  Every instance must have a state.  Allocates the snapshot
+ * (about the size of the state) for the duration of the call.  Synchronizes. */
+#define ETD_AUTOTUNE_CANDIDATES 7
+etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path, etd_schedule* chosen,
+                        double* ms_out);
+
 const char* etd_status_string(etd_status s);
 const char* etd_last_error(etd_plan_t plan);   /* plan may be NULL: last global error */
 

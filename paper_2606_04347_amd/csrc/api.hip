@@ -8,14 +8,12 @@
 #include <string>
 #include <vector>
 
-#include "etd.h"
-#include "fft.h"
 #include "fused.h"
-#include "kernels.h"
+#include "plan.h"
 
 using namespace etd;
 
-namespace {
+namespace etd {
 
 std::string g_last_error = "";
 
@@ -25,116 +23,9 @@ etd_status fail(std::string* sink, etd_status st, const std::string& msg) {
     return st;
 }
 
-// device scalar slots
-enum Slot {
-    S_INTPHI = 0, S_MASS = 1, S_Q0 = 2, S_MPS = 3 /* 2 values */, S_TMP = 5,
-    S_DIAG = 8 /* 7 */, S_ENERGY = 16 /* 7 */, S_GERSH = 24, S_ABS = 25, S_COUNT = 32
-};
-
-struct Instance {
-    etd_instance_desc d{};
-    etd_coupled_params cp{};
-    etd_fixed_params fp{};
-    GridK g{};
-    bool f32 = false;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
-    FFTTables<float> tf;
-    FFTTables<double> td;
-    // coupled buffers (element type float or double)
-    void *phiA = nullptr, *phiB = nullptr, *u = nullptr, *ut = nullptr, *lap = nullptr, *gx = nullptr,
-         *gy = nullptr, *gz = nullptr, *P = nullptr, *Q = nullptr, *gp = nullptr, *vx = nullptr, *vy = nullptr,
-         *vz = nullptr, *psi = nullptr;
-    void *Sphi = nullptr, *St = nullptr, *Sra = nullptr, *Sa = nullptr, *Sb = nullptr, *Sgu = nullptr,
-         *Stmp = nullptr;
-    // fixed buffers (double unless noted)
-    double *G = nullptr, *sg = nullptr, *isg = nullptr, *U = nullptr, *w = nullptr, *R0 = nullptr, *R1 = nullptr,
-           *vv = nullptr, *t1 = nullptr, *t2 = nullptr, *acc = nullptr, *q = nullptr, *mq = nullptr,
-           *psid = nullptr;
-    float *qf = nullptr, *psif = nullptr;   // FP32-FFT variant of the nonlocal term
-    // shared
-    uint8_t* mask = nullptr;
-    int32_t* band_idx = nullptr;
-    int64_t* band_cnt = nullptr;   // band_blocks + 1 entries, then the total
-    int64_t* band_total = nullptr;
-    double* scal = nullptr;
-    double* part = nullptr;
-    double* fd = nullptr;          // per-axis FD symbol tables 4/h^2 sin^2(pi i / N)
-    CoupledK K{};
-    FixedK FK{};
-    double A0 = 0.0;
-    long step = 0;
-    bool has_state = false;
-    bool band_active = false;
-    // fixed-model constants
-    double C = 0, Bmbp = 0, Bes = 0, rho = 0, a = 0, b = 0;
-    std::vector<double> ch1, ch2;   // Chebyshev coefficients of phi1(tau x), phi2(tau x) on [a, b]
-};
-
-}  // namespace
+}  // namespace etd
 
 namespace {
-
-// Event pairs around FFT pass launches (etd_pass_timing).
-struct EventHook : PassHook {
-    struct Rec {
-        int kind;
-        double bytes;
-        hipEvent_t e0, e1;
-    };
-    std::vector<hipEvent_t> pool;
-    size_t used = 0;
-    std::vector<Rec> recs;
-    hipEvent_t take() {
-        if (used == pool.size()) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            pool.push_back(e);
-        }
-        return pool[used++];
-    }
-    hipEvent_t pending = nullptr;
-    void begin(int, hipStream_t s) override {
-        pending = take();
-        if (pending) (void)hipEventRecord(pending, s);
-    }
-    void end(int kind, double bytes, hipStream_t s) override {
-        hipEvent_t e1 = take();
-        if (!pending || !e1) return;
-        (void)hipEventRecord(e1, s);
-        recs.push_back({kind, bytes, pending, e1});
-        pending = nullptr;
-    }
-    void reset() {
-        used = 0;
-        recs.clear();
-        pending = nullptr;
-    }
-    ~EventHook() override {
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-}  // namespace
-
-struct etd_plan {
-    std::vector<Instance> inst;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    std::string err;
-    EventHook hook;
-    bool timing = false;
-};
-
-namespace {
-
-#define HIPCHK(plan, call)                                                                              \
-    do {                                                                                                \
-        hipError_t e_ = (call);                                                                         \
-        if (e_ != hipSuccess)                                                                           \
-            return fail(plan ? &plan->err : nullptr, ETD_E_HIP,                                         \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                             \
-    } while (0)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -468,8 +359,7 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     return remainder_etd<T>(I, v, st, EtdArgs<T>{nullptr, v.Sra, v.Sgu}, s);
 }
 
-template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I) {
-    hipStream_t s = plan->stream;
+template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     CoupledView<T> v(I);
@@ -563,8 +453,7 @@ void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, doub
     }
 }
 
-etd_status step_fixed(etd_plan* plan, Instance& I) {
-    hipStream_t s = plan->stream;
+etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     const GridK& g = I.g;
     const long n = g.nreal();
     etd_status st;
@@ -662,6 +551,11 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
 }  // namespace
 
 // =================================================================== C ABI
+etd_status etd::step_instance(etd_plan* plan, Instance& I, hipStream_t s) {
+    if (I.d.model == ETD_COUPLED) return I.f32 ? step_coupled<float>(plan, I, s) : step_coupled<double>(plan, I, s);
+    return step_fixed(plan, I, s);
+}
+
 extern "C" {
 
 const char* etd_status_string(etd_status s) {
@@ -724,6 +618,7 @@ etd_status etd_plan_destroy(etd_plan_t plan) {
     if (!plan) return ETD_OK;
     if (plan->timing) fft_set_pass_hook(nullptr);
     (void)hipStreamSynchronize(plan->stream);
+    release_schedule(plan);
     for (Instance& I : plan->inst)
         for (void* p : I.allocs) (void)hipFree(p);
     delete plan;
@@ -743,6 +638,7 @@ etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const voi
     if (st != ETD_OK) return st;
     I.step = 0;
     I.has_state = true;
+    drop_graphs(plan);   // captured kernel arguments (A0, Chebyshev coefficients) may have changed
     return ETD_OK;
 }
 
@@ -777,16 +673,7 @@ etd_status etd_step(etd_plan_t plan, int nsteps) {
     if (nsteps < 0) return fail(&plan->err, ETD_E_ARG, "nsteps must be >= 0");
     for (Instance& I : plan->inst)
         if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "step before set_state");
-    for (int k = 0; k < nsteps; ++k) {
-        for (Instance& I : plan->inst) {
-            etd_status st;
-            if (I.d.model == ETD_COUPLED) st = I.f32 ? step_coupled<float>(plan, I) : step_coupled<double>(plan, I);
-            else st = step_fixed(plan, I);
-            if (st != ETD_OK) return st;
-            ++I.step;
-        }
-    }
-    return ETD_OK;
+    return run_steps(plan, nsteps);
 }
 
 etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out) {

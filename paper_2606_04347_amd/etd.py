@@ -27,7 +27,11 @@ Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
 
 EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
-           "etd_pass_timing", "etd_plan_query", "etd_status_string", "etd_last_error")
+           "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
+           "etd_status_string", "etd_last_error")
+EXEC_EAGER, EXEC_GRAPH = 0, 1
+AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
+                       ("graph", 32))
 PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
               "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover")
 N_PASS_SLOTS = 16
@@ -62,6 +66,10 @@ class PassTimes(C.Structure):
                 ("bytes", C.c_double * N_PASS_SLOTS)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("mode", C.c_int), ("branches", C.c_int)]
+
+
 class Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("int_phi", C.c_double), ("mass", C.c_double), ("Q", C.c_double),
                 ("umin", C.c_double), ("umax", C.c_double), ("bound", C.c_double),
@@ -91,6 +99,9 @@ def lib():
         L.etd_spectral_apply.argtypes = [vp, i, i, vp, vp, i]
         L.etd_plan_query.argtypes = [vp, i, i, C.POINTER(d)]
         L.etd_pass_timing.argtypes = [vp, i, C.POINTER(PassTimes)]
+        L.etd_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
+        L.etd_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
+        L.etd_autotune.argtypes = [vp, i, C.c_char_p, C.POINTER(Schedule), C.POINTER(d)]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -269,6 +280,25 @@ class Plan:
         v = C.c_double(0.0)
         self._c(lib().etd_plan_query(self._ptr, i, int(what), C.byref(v)))
         return v.value
+
+    def set_schedule(self, mode, branches=1):
+        """Step schedule: EXEC_EAGER, or EXEC_GRAPH with `branches` concurrent capture branches."""
+        self._c(lib().etd_set_schedule(self._ptr, C.byref(Schedule(int(mode), int(branches)))))
+
+    def get_schedule(self):
+        s = Schedule()
+        self._c(lib().etd_get_schedule(self._ptr, C.byref(s)))
+        return s.mode, s.branches
+
+    def autotune(self, trial_steps=10, cache_path=None):
+        """Time the candidate schedules, keep the fastest; returns (mode, branches, {candidate: ms/step})."""
+        s = Schedule()
+        ms = (C.c_double * len(AUTOTUNE_CANDIDATES))()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._c(lib().etd_autotune(self._ptr, int(trial_steps), path, C.byref(s), ms))
+        times = {f"{m}{b if m == 'graph' else ''}": ms[k] for k, (m, b) in enumerate(AUTOTUNE_CANDIDATES)
+                 if ms[k] >= 0}
+        return s.mode, s.branches, times
 
     def close(self):
         if getattr(self, "_ptr", None) and self._ptr.value:

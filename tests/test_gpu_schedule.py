@@ -1,0 +1,128 @@
+"""GPU: batched plans of uneven instances under the eager and HIP-graph step
+schedules, and the schedule autotuner.  The instances are independent and
+every kernel runs the same arithmetic under every schedule, so the states
+must agree bit for bit."""
+import json
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, needs_gpu, report, torch
+from paper_2606_04347_amd import etd, inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def batch():
+    """Coupled instances of three sizes, schemes and precisions (one with the
+    narrow band rebuilt every 3 steps, so the captured rebuild pattern
+    changes from graph to graph) and two fixed-membrane instances."""
+    out = []
+    for n, scheme, prec, kw in (((16, 16, 16), etd.ETDRK2, etd.FP64, {}),
+                                ((24, 24, 24), etd.ETD1, etd.FP64, {}),
+                                ((32, 32, 32), etd.ETDRK2, etd.FP32,
+                                 dict(band_threshold=0.995, band_rebuild_every=3)),
+                                ((16, 24, 32), etd.ETDRK2, etd.FP32, {})):
+        ci = inputs.coupled_membrane(n=n, seed=31, tau=1e-4)
+        out.append(("c", ci, etd.coupled_instance(ci, scheme=scheme, precision=prec, **kw), prec))
+    fi = inputs.fixed_membrane(dim=2, n=32, tau=0.01, instance=7)
+    out.append(("f", fi, etd.fixed_instance(fi, scheme=etd.ETDRK2), etd.FP64))
+    fi3 = inputs.fixed_membrane(dim=3, n=16, eps_pm_in_h=2.0, tau=0.02, instance=8)
+    out.append(("f", fi3, etd.fixed_instance(fi3, scheme=etd.ETD1, precision=etd.FP32), etd.FP64))
+    return out
+
+
+def make_plan(b):
+    plan = etd.Plan([x[2] for x in b])
+    for i, (kind, src, _, prec) in enumerate(b):
+        if kind == "c":
+            dt = torch.float64 if prec == etd.FP64 else torch.float32
+            plan.set_state(i, dev(src.phi0, dt), dev(src.u0, dt))
+        else:
+            plan.set_state(i, dev(src.g), dev(src.u0))
+    return plan
+
+
+def states(plan, n):
+    return [tuple(host(t) for t in plan.get_state(i)) for i in range(n)]
+
+
+def assert_same(sa, sb):
+    for i, ((a0, a1), (b0, b1)) in enumerate(zip(sa, sb)):
+        assert np.isfinite(a0).all() and np.isfinite(a1).all(), f"instance {i} is not finite"
+        assert np.array_equal(a0, b0) and np.array_equal(a1, b1), f"instance {i} differs"
+
+
+@pytest.mark.parametrize("branches", [1, 3, 8])
+def test_graph_schedule_matches_eager(branches):
+    b = batch()
+    ref = make_plan(b)
+    ref.step(5)
+    want = states(ref, len(b))
+    ref.close()
+    plan = make_plan(b)
+    plan.set_schedule(etd.EXEC_GRAPH, branches)
+    assert plan.get_schedule() == (etd.EXEC_GRAPH, branches)
+    plan.step(3)          # one graph (captured) + one eager step
+    plan.step(2)          # odd buffer parity: a second graph is captured
+    got = states(plan, len(b))
+    assert_same(got, want)
+    for i in range(len(b)):
+        assert plan.diagnostics(i)["step"] == 5
+    # a second run of the same length from a fresh state replays cached graphs
+    for i, (kind, src, _, prec) in enumerate(b):
+        if kind == "c":
+            dt = torch.float64 if prec == etd.FP64 else torch.float32
+            plan.set_state(i, dev(src.phi0, dt), dev(src.u0, dt))
+        else:
+            plan.set_state(i, dev(src.g), dev(src.u0))
+    plan.step(3)
+    plan.step(2)
+    assert_same(states(plan, len(b)), want)
+    plan.close()
+
+
+def test_schedule_rejects_bad_arguments():
+    b = batch()[:1]
+    plan = make_plan(b)
+    with pytest.raises(etd.EtdError):
+        plan.set_schedule(2, 1)
+    with pytest.raises(etd.EtdError):
+        plan.set_schedule(etd.EXEC_GRAPH, 0)
+    with pytest.raises(etd.EtdError):
+        plan.set_schedule(etd.EXEC_GRAPH, 65)
+    assert plan.get_schedule() == (etd.EXEC_EAGER, 1)
+    plan.close()
+
+
+def test_autotune_restores_state_and_uses_cache(tmp_path):
+    b = batch()
+    plan = make_plan(b)
+    plan.step(2)
+    before = states(plan, len(b))
+    a0 = [plan.query(i, etd.Q_A0) for i in range(4)]
+    cache = tmp_path / "sched.json"
+    mode, branches, times = plan.autotune(trial_steps=4, cache_path=str(cache))
+    report("autotune", mode=mode, branches=branches, **{k: round(v, 4) for k, v in times.items()})
+    assert mode in (etd.EXEC_EAGER, etd.EXEC_GRAPH) and branches >= 1
+    assert "eager" in times and "graph1" in times
+    assert plan.get_schedule() == (mode, branches)
+    assert_same(states(plan, len(b)), before)
+    assert [plan.query(i, etd.Q_A0) for i in range(4)] == a0
+    for i in range(len(b)):
+        assert plan.diagnostics(i)["step"] == 2
+    rec = json.loads(cache.read_text())
+    assert len(rec) == 1 and list(rec.values())[0] == {"mode": mode, "branches": branches}
+    # a second plan of the same mix takes the cached choice without trials
+    other = make_plan(b)
+    m2, b2, t2 = other.autotune(trial_steps=4, cache_path=str(cache))
+    assert (m2, b2) == (mode, branches) and t2 == {}
+    other.close()
+    # the tuned plan keeps stepping exactly like a plan that was never tuned
+    ref = make_plan(b)
+    ref.step(2)
+    plan.step(2)
+    ref.step(2)
+    assert_same(states(plan, len(b)), states(ref, len(b)))
+    plan.close()
+    ref.close()
