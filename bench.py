@@ -38,6 +38,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--err-steps", type=int, default=100,
                     help="FP32 vs FP64 GPU gap after this many steps (0 = skip)")
+    ap.add_argument("--no-band", action="store_true",
+                    help="skip the 512^3 narrow-band measurement")
+    ap.add_argument("--band-n", type=int, default=512)
+    ap.add_argument("--band-steps", type=int, default=50)
+    ap.add_argument("--no-fixed", action="store_true",
+                    help="skip the 128^3 fixed-membrane measurement")
+    ap.add_argument("--fixed-n", type=int, default=128)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -108,6 +115,91 @@ def roofline(passes, pass_steps, n, precision):
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind, n, precision),
             "kernel": kind, "launches_per_step": p["launches"] / pass_steps,
             "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+
+
+FFT_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
+             "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover")
+
+
+def ledger(passes, pass_steps, npts, ms_per_step):
+    """Per-kind and whole-step algorithmic bytes from the pass-timed steps."""
+    kinds = {k: {"launches_per_step": v["launches"] / pass_steps, "ms_per_step": v["ms"] / pass_steps,
+                 "bytes_per_step": v["bytes"] / pass_steps,
+                 "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
+             for k, v in passes.items() if v["launches"]}
+    tot_b = sum(v["bytes"] for v in passes.values()) / pass_steps
+    tot_ms = sum(v["ms"] for v in passes.values()) / pass_steps
+    return {"bytes_per_step": tot_b, "bytes_per_point_step": tot_b / npts,
+            "kernel_ms_per_step": tot_ms,
+            "achieved_GBps_kernel_time": tot_b / (tot_ms * 1e-3) / 1e9,
+            "achieved_GBps_wall": tot_b / (ms_per_step * 1e-3) / 1e9,
+            "frac_wall": tot_b / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kinds": kinds}
+
+
+def band_measure(n, steps, warmup):
+    """Coupled FP32 ETDRK2 at n^3 with the narrow band |2 phi - 1| < 0.995
+    rebuilt every 10 steps: throughput, and the band kernels, the stencil
+    kernels and the FFT passes timed separately over 10 steps."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    t0 = time.time()
+    ci = inputs.coupled_membrane(n=n, tau=1e-4)
+    log(f"band inputs {n}^3 {time.time() - t0:.1f}s")
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32, band_threshold=0.995,
+                                         band_rebuild_every=10))
+    plan.set_state(0, torch.as_tensor(ci.phi0, dtype=torch.float32, device="cuda"),
+                   torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
+    del ci
+    ms = timed_steps(plan, steps, warmup) / steps
+    plan.pass_timing(True)
+    plan.step(10)
+    passes = plan.pass_timing(False)
+    d = plan.diagnostics(0)
+    plan.close()
+    npts = n ** 3
+    group = lambda ks: sum(passes[k]["ms"] for k in ks) / 10
+    return {"workload": f"coupled ETDRK2 FP32, {n}^3 grid, eps=3h, tau=1e-4, narrow band |2 phi - 1| < 0.995 "
+                        "rebuilt every 10 steps", "grid": [n, n, n], "steps": steps,
+            "value": npts / (ms * 1e-3), "unit": "grid-pt steps/s", "ms_per_step": ms,
+            "band_points": d["band_count"], "band_fraction": d["band_count"] / npts,
+            "ms_per_step_by_group": {"fft_passes": group(FFT_KINDS), "band_flags_and_compaction": group(("band",)),
+                                     "stencils_R1_P2": group(("r1_stencil", "p2_stencil")),
+                                     "pointwise_and_reductions": group(("pointwise", "reduce"))},
+            "band_kernels_per_rebuild_ms": passes["band"]["ms"] / max(1, passes["band"]["launches"]),
+            "ledger": ledger(passes, 10, npts, ms)}
+
+
+def fixed_measure(n, warmup):
+    """Fixed-membrane ETDRK2 at n^3 on [-1, 1)^3 (sphere R = 0.5, eps = 2h,
+    M = 200, tau = 0.02, 48 steps to T = 0.96), FP64 and FP32-FFT paths:
+    throughput, the maximum bound, energy and mass."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    fi = inputs.fixed_membrane(dim=3, n=n, eps_pm_in_h=2.0, tau=0.02)
+    nsteps = 48
+    out = {"workload": f"fixed-membrane ETDRK2, {n}^3 grid on [-1,1)^3, sphere R=0.5, eps=2h, M=200, tau=0.02, "
+                       f"{nsteps} steps (T=0.96)", "grid": [n, n, n]}
+    for prec, name in ((etd.FP64, "fp64"), (etd.FP32, "fp32_fft")):
+        plan = etd.Plan(etd.fixed_instance(fi, scheme=etd.ETDRK2, precision=prec))
+        plan.set_state(0, torch.as_tensor(fi.g, device="cuda"), torch.as_tensor(fi.u0, device="cuda"))
+        e0 = plan.energy(0)["E"]
+        mass0 = plan.diagnostics(0)["mass"]
+        ms = timed_steps(plan, nsteps, 0) / nsteps
+        d = plan.diagnostics(0)
+        e1 = plan.energy(0)["E"]
+        plan.pass_timing(True)
+        plan.step(2)
+        passes = plan.pass_timing(False)
+        out[name] = {"value": n ** 3 / (ms * 1e-3), "unit": "grid-pt steps/s", "ms_per_step": ms,
+                     "steps": nsteps, "B": plan.query(0, etd.Q_B), "cheb_degree": plan.query(0, etd.Q_CHEB_DEG),
+                     "umin": d["umin"], "umax": d["umax"], "max_abs_2u_minus_1": d["bound"],
+                     "energy_start": e0, "energy_end": e1, "mass_start": mass0, "mass_end": d["mass"],
+                     "ledger": ledger(passes, 2, n ** 3, ms)}
+        plan.close()
+    return out
 
 
 def precision_gap(ci, nsteps):
@@ -238,7 +330,8 @@ def main():
             continue
         ms, passes = run_precision(ci, prec, dt, a.steps, a.warmup, pass_steps)
         res[name] = dict(ms_per_step=ms / a.steps, value=npts * a.steps / (ms * 1e-3),
-                         roofline=roofline(passes, pass_steps, n, name))
+                         roofline=roofline(passes, pass_steps, n, name),
+                         ledger=ledger(passes, pass_steps, npts, ms / a.steps))
         log(f"{name}: {ms / a.steps:.3f} ms/step, {res[name]['value']:.3e} pt-steps/s, "
             f"dominant {res[name]['roofline']['kernel']} {res[name]['roofline']['achieved']:.0f} GB/s")
     out = {
@@ -258,11 +351,20 @@ def main():
                                "perturbed-sphere vesicle (real harmonics l<=4), FP32 path",
                    "grid": [n, n, n], "scheme": "ETDRK2", "precision": "fp32"},
         "roofline": res["fp32"]["roofline"],
+        "ledger": res["fp32"]["ledger"],
     }
     if "fp64" in res:
         out["fp64"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
-                       "roofline": res["fp64"]["roofline"]}
+                       "roofline": res["fp64"]["roofline"], "ledger": res["fp64"]["ledger"]}
         out["fp32_over_fp64"] = res["fp32"]["value"] / res["fp64"]["value"]
+    if not a.no_band:
+        out["band"] = band_measure(a.band_n, a.band_steps, a.warmup)
+        log(f"band {a.band_n}^3: {out['band']['ms_per_step']:.3f} ms/step, {out['band']['band_points']} band points, "
+            f"{out['band']['ms_per_step_by_group']}")
+    if not a.no_fixed:
+        out["fixed"] = fixed_measure(a.fixed_n, a.warmup)
+        log(f"fixed {a.fixed_n}^3: fp64 {out['fixed']['fp64']['ms_per_step']:.3f} ms/step, "
+            f"fp32-fft {out['fixed']['fp32_fft']['ms_per_step']:.3f} ms/step")
     if not a.no_batch:
         out["batched"] = batch_measure(a.batch_steps, a.warmup)
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "

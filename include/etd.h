@@ -202,8 +202,8 @@ typedef enum {
 etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op, const void* in, void* out,
                               etd_dtype dtype);
 
-/* Per-pass timing of the FFT kernels (a measurement aid).  enable != 0 starts
- * a measurement: every FFT pass launched afterwards by calls on this plan is
+/* Per-pass timing of the step's kernels (a measurement aid).  enable != 0
+ * starts a measurement: every kernel launched afterwards by steps of this plan is
  * bracketed by HIP events recorded on the plan's stream.  enable == 0 stops
  * it, synchronizes, and fills out (may be NULL) per pass kind: the number of
  * launches, their summed event-timed duration in ms, and the algorithmic bytes
@@ -217,8 +217,12 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
  *   9 forward x lines of two spectra with the ETD combine
  *  10 last forward axis times 1/mu and back ((-Delta_h)^{-1})
  *  11 z-row c2r of a G U increment with the recovery of U in the store
- *  12..15 unused. */
-#define ETD_PASS_KINDS 16
+ * and the other kernels of a step (same hook, same bracketing):
+ *  12 narrow-band flags and compaction   13 R1 remainder (stencil)
+ *  14 R2 remainder P2 (stencil)          15 coupled pointwise kernels
+ *  16 FP64 reductions                    17 fixed model: Chebyshev / L stencils
+ *  18 fixed model: pointwise kernels     19 unused. */
+#define ETD_PASS_KINDS 20
 typedef struct {
     int64_t launches[ETD_PASS_KINDS];
     double total_ms[ETD_PASS_KINDS];

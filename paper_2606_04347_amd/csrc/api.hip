@@ -29,6 +29,15 @@ namespace {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Launch a non-FFT kernel under the pass-timing hook (kind: PassKind; bytes:
+// algorithmic bytes it moves).
+template <typename F> void timed_kernel(int kind, double bytes, hipStream_t s, F&& launch) {
+    (void)timed_pass(kind, bytes, s, [&] {
+        launch();
+        return hipSuccess;
+    });
+}
+
 etd_status validate(const etd_instance_desc& d, std::string& msg) {
     if (d.model != ETD_COUPLED && d.model != ETD_FIXED_MEMBRANE) { msg = "unknown model"; return ETD_E_ARG; }
     if (d.scheme != ETD_ETD1 && d.scheme != ETD_ETDRK2) { msg = "unknown scheme"; return ETD_E_ARG; }
@@ -351,11 +360,15 @@ template <typename T>
 hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, EtdStage st, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
-    coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, s);
-    reduce_sum<T>(g.nreal(), v.P, g.cell, I.part, I.scal + S_MASS, s);
+    const long n = g.nreal();
+    const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
+    timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] { coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, s); });
+    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.P, g.cell, I.part, I.scal + S_MASS, s); });
     hipError_t e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s);
     if (e != hipSuccess) return e;
-    coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
+    timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
+        coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
+    });
     return remainder_etd<T>(I, v, st, EtdArgs<T>{nullptr, v.Sra, v.Sgu}, s);
 }
 
@@ -368,27 +381,38 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     const uint8_t* mask = nullptr;
     if (I.d.band_threshold > 0.0) {
         if (I.step % I.d.band_rebuild_every == 0) {
-            band_flags<T>(n, v.phiA, I.d.band_threshold, I.mask, s);
-            band_compact(n, I.mask, I.band_cnt, I.band_idx, n, I.band_total, s);
+            timed_kernel(PASS_BAND, (sizeof(T) + 2.0) * n, s, [&] {
+                band_flags<T>(n, v.phiA, I.d.band_threshold, I.mask, s);
+                band_compact(n, I.mask, I.band_cnt, I.band_idx, n, I.band_total, s);
+            });
         }
         mask = I.mask;
     }
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
-    reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
-    coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q, s);
+    const double fb = (double)sizeof(T) * n;   // one real field
+    const double mb = mask ? (double)n : 0.0;
+    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s); });
+    timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
+        coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
+                            s);
+    });
     if (!rk2) {
         HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, s));
     } else {
         HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, s));
         HIPCHK(plan, phi_and_derivs<T>(I, v, v.St, v.phiB, s));
-        reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s);
-        coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
-                            s);
+        timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s); });
+        timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
+            coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P,
+                                v.Q, s);
+        });
         HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, s));
     }
     // phi^{n+1} and its derivatives (kept for the next step), g+ and the velocity
     HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiB, s));
-    coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
+    timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
+        coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
+    });
     // ---- g u stages with g = g(phi^{n+1})
     // The spectral g u values are kept as increments D over FFT(g+ u^n), so the
     // inverse transforms carry only the per-step change; g+ u^n is added back in
@@ -402,8 +426,10 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
         HIPCHK(plan, c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, v.u, I.K.thr, s));   // U^{n+1}
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
-        mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);
-        mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+        timed_kernel(PASS_POINT, 5.0 * fb, s, [&] {
+            mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);
+            mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+        });
     }
     std::swap(I.phiA, I.phiB);
     HIPCHK(plan, hipGetLastError());
@@ -426,12 +452,15 @@ etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStrea
 etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipStream_t s) {
     const GridK& g = I.g;
     const long n = g.nreal();
-    fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, s);
-    reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s);
+    const double fb = 8.0 * n;
+    timed_kernel(PASS_FIXED_POINT, 4.0 * fb, s, [&] { fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, s); });
+    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s); });
     etd_status st = fixed_nonlocal(plan, I, I.q, s);
     if (st != ETD_OK) return st;
-    if (!I.f32) fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
-    else fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
+    timed_kernel(PASS_FIXED_POINT, 3.0 * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
+        if (!I.f32) fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
+        else fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
+    });
     return ETD_OK;
 }
 
@@ -441,13 +470,18 @@ void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, doub
     double* tk = I.t1;       // T_1 v, then rotating with t2
     double* tkm1 = I.t2;
     // first: T_1 v = Atil v; acc = c0/2 v + c1 T_1 v
-    fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
-                    0.5 * c[0], 1, s);
+    const double fb = 8.0 * g.nreal();
+    timed_kernel(PASS_FIXED_STENCIL, 5.0 * fb, s, [&] {
+        fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
+                        0.5 * c[0], 1, s);
+    });
     const double* prev = v;
     for (size_t k = 2; k < c.size(); ++k) {
         // T_k = 2 Atil T_{k-1} - T_{k-2}; written over the T_{k-2} buffer (prev == v at k = 2)
         double* out = (k == 2) ? tkm1 : const_cast<double*>(prev);
-        fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
+        timed_kernel(PASS_FIXED_STENCIL, 7.0 * fb, s, [&] {
+            fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
+        });
         prev = tk;
         tk = out;
     }
@@ -458,23 +492,31 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     const long n = g.nreal();
     etd_status st;
     // w = sg U;  v = R(U) - L w;  w~ = w + tau phi1(tau L) v
-    mul(n, I.sg, I.U, I.w, s);
+    const double fb = 8.0 * n;
+    timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { mul(n, I.sg, I.U, I.w, s); });
     if ((st = fixed_R(plan, I, I.U, I.R0, s)) != ETD_OK) return st;
-    fixed_L_apply(g, I.FK, I.G, I.isg, I.w, I.vv, s);
-    axpby(n, 1.0, I.R0, -1.0, I.vv, I.vv, s);
+    timed_kernel(PASS_FIXED_STENCIL, 4.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.G, I.isg, I.w, I.vv, s); });
+    timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R0, -1.0, I.vv, I.vv, s); });
     cheb_apply(I, I.ch1, I.vv, I.acc, s);
-    axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);             // w = w~
-    mul(n, I.isg, I.w, I.U, s);                               // U = w~ / sg  (ETD1 result / predictor)
+    timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
+        axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);   // w = w~
+        mul(n, I.isg, I.w, I.U, s);                     // U = w~ / sg  (ETD1 result / predictor)
+    });
     if (I.d.scheme == ETD_ETDRK2) {
         if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
-        axpby(n, 1.0, I.R1, -1.0, I.R0, I.vv, s);
+        timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R1, -1.0, I.R0, I.vv, s); });
         cheb_apply(I, I.ch2, I.vv, I.acc, s);
-        axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
-        mul(n, I.isg, I.w, I.U, s);
+        timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
+            axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
+            mul(n, I.isg, I.w, I.U, s);
+        });
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
-        mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
-        mass_project_apply<double>(n, I.G, I.U, I.d.recover_threshold, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+        timed_kernel(PASS_FIXED_POINT, 5.0 * fb, s, [&] {
+            mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
+            mass_project_apply<double>(n, I.G, I.U, I.d.recover_threshold, g.cell, I.scal + S_Q0, I.scal + S_MPS,
+                                       s);
+        });
     }
     HIPCHK(plan, hipGetLastError());
     return ETD_OK;

@@ -47,7 +47,15 @@ enum PassKind {
     PASS_X_ETD = 9,        // forward x lines of two spectra + ETD combine
     PASS_LAPINV = 10,      // last forward axis, times 1/mu, inverse along the same axis
     PASS_Z_RECOVER = 11,   // z rows c2r of an increment with the recovery of U
-    PASS_KIND_COUNT = 16
+    // kernels other than FFT passes (timed through the same hook)
+    PASS_BAND = 12,        // narrow-band flags and compaction
+    PASS_R1 = 13,          // R1 remainder (stencil of u and g(phi))
+    PASS_P2 = 14,          // R2 remainder P2 (stencil of u, g, v)
+    PASS_POINT = 15,       // coupled pointwise kernels (velocity, q and g u, mass projection)
+    PASS_REDUCE = 16,      // FP64 reductions
+    PASS_FIXED_STENCIL = 17,   // fixed model: Chebyshev recurrence and L apply (stencils)
+    PASS_FIXED_POINT = 18,     // fixed model: pointwise kernels
+    PASS_KIND_COUNT = 20
 };
 struct PassHook {
     virtual void begin(int kind, hipStream_t s) = 0;
