@@ -2,6 +2,7 @@
 // schedules of both models, Chebyshev set-up, energies and diagnostics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -270,7 +271,8 @@ etd_status setup_fixed(etd_plan* P, Instance& I) {
 
 etd_status setup_common(etd_plan* P, Instance& I) {
     ALLOC(I.scal, S_COUNT * sizeof(double));
-    ALLOC(I.part, (size_t)kRedBlocks * 8 * sizeof(double));
+    // reduction partials: the fixed reduction grid, or one per z-row tile of the fused z pass
+    ALLOC(I.part, std::max((size_t)kRedBlocks * 8, (size_t)I.g.nx * I.g.ny) * sizeof(double));
     HIPCHK(P, hipMemset(I.scal, 0, S_COUNT * sizeof(double)));
     // eigenvalues of the periodic second difference per axis, mu_d(i) = (4/h^2) sin^2(pi i / N)
     const GridK& g = I.g;
@@ -322,7 +324,9 @@ template <typename T>
 hipError_t phi_and_derivs(const Instance& I, CoupledView<T>& v, const c2<T>* S, T* phi, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
-    if (g.nx > 1) return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, s);
+    if (g.nx > 1)
+        return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, I.part,
+                               I.scal + S_INTPHI, s);
     hipError_t e = fft_c2r_3d<T>(g, t, S, v.Stmp, phi, s);
     if (e != hipSuccess) return e;
     const SpecOp ops[4] = {SPEC_NEG_K2, SPEC_IKX, SPEC_IKY, SPEC_IKZ};
@@ -334,13 +338,12 @@ hipError_t phi_and_derivs(const Instance& I, CoupledView<T>& v, const c2<T>* S, 
     return hipGetLastError();
 }
 
-// Forward transforms of the remainder pair (P, Q) and the ETD combine of the
-// stage: fused into the x pass on three-dimensional grids.
+// Two-dimensional grids: forward transforms of the remainder pair (P, Q)
+// and the ETD combine of the stage as a separate spectral kernel.
 template <typename T>
-hipError_t remainder_etd(const Instance& I, CoupledView<T>& v, EtdStage st, const EtdArgs<T>& a, hipStream_t s) {
+hipError_t remainder_etd_2d(const Instance& I, CoupledView<T>& v, EtdStage st, const EtdArgs<T>& a, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
-    if (g.nx > 1) return fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, s);
     hipError_t e = fft_r2c_3d<T>(g, t, v.P, v.Sa, s);
     if (e != hipSuccess) return e;
     if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
@@ -353,23 +356,53 @@ hipError_t remainder_etd(const Instance& I, CoupledView<T>& v, EtdStage st, cons
     return hipGetLastError();
 }
 
-// One u stage up to the increment spectrum: q = g (u - ubar) (masked) -> P,
-// g u -> Q; m = h^3 sum q; psi = (-Delta_h)^{-1} q; P = P2(u); then the
-// transforms of (P2, g u) and the combine into Sgu (D) and Sra.
+// One phi stage from the remainder pair (P, Q): the combined spectrum a.out
+// and, in real space, phi_out with its derivatives (gx, gy, gz, lap).  On
+// three-dimensional grids the x pass of the pair also runs the inverse x
+// transforms of the derivative pipeline.
 template <typename T>
-hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, EtdStage st, hipStream_t s) {
+hipError_t phi_stage(const Instance& I, CoupledView<T>& v, EtdStage st, const EtdArgs<T>& a, T* phi_out,
+                     hipStream_t s) {
+    const GridK& g = I.g;
+    const FFTTables<T>& t = tables<T>(I);
+    if (g.nx > 1) {
+        hipError_t e = fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
+        if (e != hipSuccess) return e;
+        return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, I.part,
+                                  I.scal + S_INTPHI, s);
+    }
+    hipError_t e = remainder_etd_2d<T>(I, v, st, a, s);
+    if (e != hipSuccess) return e;
+    return phi_and_derivs<T>(I, v, a.out, phi_out, s);
+}
+
+// One u stage: q = g (u - ubar) (masked) -> P, g u -> Q; m = h^3 sum q;
+// psi = (-Delta_h)^{-1} q; P = P2(u); then the transforms of (P2, g u), the
+// combine into the increment D (Sgu; stored if store_D) and Sra, and the
+// recovery out = rec(g+ u^n + F^-1 D).
+template <typename T>
+hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, EtdStage st, bool store_D,
+                   T* out, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] { coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, s); });
-    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.P, g.cell, I.part, I.scal + S_MASS, s); });
+    timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] {
+        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, I.part, I.scal + S_MASS, s);
+    });
     hipError_t e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s);
     if (e != hipSuccess) return e;
     timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
         coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
     });
-    return remainder_etd<T>(I, v, st, EtdArgs<T>{nullptr, v.Sra, v.Sgu}, s);
+    const EtdArgs<T> a{nullptr, v.Sra, v.Sgu};
+    if (g.nx > 1) {
+        e = fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, store_D, v.Sa, nullptr, nullptr, s);
+        if (e != hipSuccess) return e;
+        return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, s);
+    }
+    if ((e = remainder_etd_2d<T>(I, v, st, a, s)) != hipSuccess) return e;
+    return c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, out, I.K.thr, s);
 }
 
 template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipStream_t s) {
@@ -391,25 +424,28 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
     const double fb = (double)sizeof(T) * n;   // one real field
     const double mb = mask ? (double)n : 0.0;
-    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s); });
+    // the integral of phi^n: formed by the z pass that produced phi^n on
+    // three-dimensional grids (previous step or set_state), here otherwise
+    if (g.nx == 1)
+        timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s); });
     timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
         coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
                             s);
     });
     if (!rk2) {
-        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, s));
+        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s));
     } else {
-        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, s));
-        HIPCHK(plan, phi_and_derivs<T>(I, v, v.St, v.phiB, s));
-        timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s); });
+        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
+        if (g.nx == 1)
+            timed_kernel(PASS_REDUCE, fb, s,
+                         [&] { reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s); });
         timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
             coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P,
                                 v.Q, s);
         });
-        HIPCHK(plan, remainder_etd<T>(I, v, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, s));
+        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s));
     }
-    // phi^{n+1} and its derivatives (kept for the next step), g+ and the velocity
-    HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiB, s));
+    // phi^{n+1} and its derivatives are kept for the next step; g+ and the velocity
     timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
         coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
     });
@@ -417,13 +453,12 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // The spectral g u values are kept as increments D over FFT(g+ u^n), so the
     // inverse transforms carry only the per-step change; g+ u^n is added back in
     // real space inside the recovery (same scheme, smaller rounding in FP32).
-    HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, s));      // Sgu = GU~^ - FFT(g+ u^n), Sra = R2(u^n)^
-    HIPCHK(plan, c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, v.ut, I.K.thr, s));   // U~
     if (!rk2) {
+        HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, false, v.ut, s));     // U^{n+1}
         std::swap(I.u, I.ut);
     } else {
-        HIPCHK(plan, u_stage<T>(I, v, v.ut, mask, ETD_STAGE_U2, s));
-        HIPCHK(plan, c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, v.u, I.K.thr, s));   // U^{n+1}
+        HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, true, v.ut, s));      // U~
+        HIPCHK(plan, u_stage<T>(I, v, v.ut, mask, ETD_STAGE_U2, false, v.u, s));     // U^{n+1}
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
         timed_kernel(PASS_POINT, 5.0 * fb, s, [&] {
@@ -546,8 +581,8 @@ template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, 
     load_field<T>(n, u, dt, v.u, s);
     HIPCHK(plan, fft_r2c_3d<T>(g, tables<T>(I), v.phiA, v.Sphi, s));
     // phi^0 from its spectrum (as every later phi^n is), with its derivatives
-    HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiA, s));
-    reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
+    HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiA, s));   // 3D: also the integral of phi
+    if (g.nx == 1) reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
     gloc_field<T>(n, v.phiA, v.gp, s);
     mass_project_sums<T>(n, v.gp, v.u, I.K.thr, I.part, I.scal + S_MPS, s);
     double host[3] = {0, 0, 0};
@@ -752,7 +787,7 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
             CoupledView<T> v(I);
             const FFTTables<T>& t = tables<T>(I);
             gloc_field<T>(n, v.phiA, v.gp, s);
-            coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, s);
+            coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, nullptr, nullptr, s);
             HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
             spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
             HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s));

@@ -1,6 +1,7 @@
 // Coupled-model kernels: spectral multipliers and ETD combines (Section 3.2,
 // Section 3.3) and the real-space remainders R1, R2 (Section 3.1) with the
 // second-order FD operators of Section 2.1.
+#include "blocksum.h"
 #include "etd_point.h"
 
 namespace etd {
@@ -65,7 +66,7 @@ __global__ void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const Wave w = wave(g, i, nullptr);
-        etd_combine<ST, T>(K, w.k2, i, P[i], Q[i], a);
+        a.out[i] = etd_combine<ST, T>(K, w.k2, i, P[i], Q[i], a);
     }
 }
 
@@ -171,13 +172,20 @@ __global__ void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const 
 
 template <typename T>
 __global__ void k_q_gu(long n, T ubar, const T* __restrict__ u, const T* __restrict__ G,
-                       const uint8_t* __restrict__ mask, T* __restrict__ q, T* __restrict__ gu) {
+                       const uint8_t* __restrict__ mask, T* __restrict__ q, T* __restrict__ gu, double* part) {
+    Neu acc;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const T uc = u[i], Gc = G[i];
         T qq = Gc * (uc - ubar);
         if (mask) qq = mask[i] ? qq : (T)0;
         q[i] = qq;
         gu[i] = Gc * uc;
+        acc.add((double)qq);
+    }
+    if (part) {
+        __shared__ double sh[kBlock];
+        const double tot = block_sum_256(acc.val(), sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
     }
 }
 
@@ -298,9 +306,10 @@ void coupled_velocity(const GridK& g, const CoupledK& K, const T* po, const T* p
 }
 template <typename T>
 void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* G, const uint8_t* mask, T* q, T* gu,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_q_gu<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g.nreal(), (T)K.ubar, u, G, mask, q,
-                       gu);
+                  double* part, double* mass_out, hipStream_t s) {
+    const int nb = grid_for(g.nreal());
+    hipLaunchKernelGGL(k_q_gu<T>, dim3(nb), dim3(kBlock), 0, s, g.nreal(), (T)K.ubar, u, G, mask, q, gu, part);
+    if (part) reduce_final_sum(part, nb, g.cell, mass_out, s);
 }
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
@@ -341,7 +350,7 @@ void set_delta(long n, double* x, hipStream_t s) {
     template void coupled_velocity<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
                                       const T*, T*, T*, T*, T*, hipStream_t);                                     \
     template void coupled_q_gu<T>(const GridK&, const CoupledK&, const T*, const T*, const uint8_t*, T*, T*,      \
-                                  hipStream_t);                                                                   \
+                                  double*, double*, hipStream_t);                                                 \
     template void coupled_P2_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
                                       const T*, const T*, const double*, const uint8_t*, T*, hipStream_t);        \
     template void recover_increment<T>(long, const T*, const T*, const T*, T*, double, hipStream_t);

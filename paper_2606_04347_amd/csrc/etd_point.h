@@ -41,9 +41,12 @@ template <typename T> struct EtdArgs {
     c2<T>* out;          // PHI*: new phi hat;  U*: increment D (U2 reads and updates it)
 };
 
+// Returns the stage's output value at i (PHI*: the new phi hat, U*: the
+// increment D); the stage-1 remainder is stored into a.ra here, the output is
+// left to the caller.
 template <int ST, typename T>
-__device__ __forceinline__ void etd_combine(const CoupledK& K, double k2, long i, c2<T> p, c2<T> q,
-                                            const EtdArgs<T>& a) {
+__device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long i, c2<T> p, c2<T> q,
+                                             const EtdArgs<T>& a) {
     if constexpr (ST == ETD_STAGE_PHI1) {
         // R = P - c1 k^2 Q;  phi~ = e^{-tau l} phi^n + tau phi1(tau l) R
         const double z = K.tau * lphi(K, k2);
@@ -51,14 +54,14 @@ __device__ __forceinline__ void etd_combine(const CoupledK& K, double k2, long i
         const c2<T> f = a.prev[i];
         const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
         a.ra[i] = R;
-        a.out[i] = mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
+        return mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
     } else if constexpr (ST == ETD_STAGE_PHI2) {
         // phi^{n+1} = phi~ + tau phi2(tau l) (R~ - R)
         const double z = K.tau * lphi(K, k2);
         const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.c1 * k2);
         const c2<T> t = a.prev[i], ra = a.ra[i];
         const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
-        a.out[i] = mk<T>(t.x + te2 * dx, t.y + te2 * dy);
+        return mk<T>(t.x + te2 * dx, t.y + te2 * dy);
     } else if constexpr (ST == ETD_STAGE_U1) {
         // R = P + eps_u B1 k^2 GU;  D = tau phi1(tau l_u) (R - l_u GU)  (GU~ - GU^n)
         const double l = lu(K, k2);
@@ -66,14 +69,14 @@ __device__ __forceinline__ void etd_combine(const CoupledK& K, double k2, long i
         const T te1 = (T)(K.tau * phi1d(z)), ck = (T)(K.eps_u * K.B1 * k2), lt = (T)l;
         const c2<T> R = mk<T>(p.x + ck * q.x, p.y + ck * q.y);
         a.ra[i] = R;
-        a.out[i] = mk<T>(te1 * (R.x - lt * q.x), te1 * (R.y - lt * q.y));
+        return mk<T>(te1 * (R.x - lt * q.x), te1 * (R.y - lt * q.y));
     } else {
         // D <- D + tau phi2(tau l_u) (R~ - R)
         const double z = K.tau * lu(K, k2);
         const T te2 = (T)(K.tau * phi2d(z)), ck = (T)(K.eps_u * K.B1 * k2);
         const c2<T> d = a.out[i], ra = a.ra[i];
         const T dx = (p.x + ck * q.x) - ra.x, dy = (p.y + ck * q.y) - ra.y;
-        a.out[i] = mk<T>(d.x + te2 * dx, d.y + te2 * dy);
+        return mk<T>(d.x + te2 * dx, d.y + te2 * dy);
     }
 }
 

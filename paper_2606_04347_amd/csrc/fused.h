@@ -11,17 +11,31 @@ namespace etd {
 // and spectral Laplacian lap (Section 3.2), in three passes: inverse x lines
 // (S -> S, i kx S, -kx^2 S), inverse y lines (3 -> 4 spectra), z rows c2r
 // (4 spectra -> 5 real fields).  W0..W3: complex work arrays (nspec each); S
-// is preserved.
+// is preserved.  With int_out != null the z pass also forms the integral
+// int_out[0] = h^3 sum phi (block partials in part, nx * ny / 8 doubles at
+// most, then a fixed-order final sum).
 template <typename T>
 hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, hipStream_t s);
+                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, double* part, double* int_out,
+                        hipStream_t s);
+
+// The y and z passes of derivs_fused, for spectra already through the
+// inverse x pass (W0 = X^-1 S, W1 = X^-1 i kx S, W2 = X^-1 (-kx^2) S); W3 work.
+template <typename T>
+hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
+                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s);
 
 // Forward transforms of two real fields P, Q (into the work spectra WP, WQ)
-// and, in the epilogue of the last (x) pass, the ETD combine of the given
-// stage (etd_point.h) with p = FFT P, q = FFT Q.
+// and, in the last (x) pass, the ETD combine of the given stage (etd_point.h)
+// with p = FFT P, q = FFT Q; its output goes to a.out if store_out.  The same
+// pass then runs the inverse x transforms of that output the next passes
+// need: after a phi stage (S, i kx S, -kx^2 S) -> (X0, X1, X2) (continue
+// with derivs_fused_yz), after a u stage the plain inverse -> X0 (continue
+// with c2r_recover_yz).  X0..X2 may alias WP / WQ.
 template <typename T>
 hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, const T* P,
-                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, hipStream_t s);
+                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0,
+                        c2<T>* X1, c2<T>* X2, hipStream_t s);
 
 // psi = (-Delta_h)^{-1} q through the FD symbol mu (zero mean mode): forward
 // transform, then the last forward axis is multiplied by 1/mu and inverted in
@@ -38,5 +52,9 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
 template <typename T>
 hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
                        T* out, double thr, hipStream_t s);
+// The y and z passes of c2r_recover for W = X^-1 D (W is overwritten).
+template <typename T>
+hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const T* u_old, const T* G, T* out,
+                          double thr, hipStream_t s);
 
 }  // namespace etd

@@ -8,6 +8,7 @@
 // line (x already in real space) kz is.
 #include "fused.h"
 
+#include "blocksum.h"
 #include "zrows.h"
 
 namespace etd {
@@ -38,7 +39,9 @@ template <typename T> __device__ __forceinline__ c2<T> times_ik(T k, c2<T> v) { 
 
 // ------------------------------------------------------------------ derivative pipeline
 // Inverse x lines at fixed (ky, kz):  A = X^-1 S,  B = X^-1 (i kx S),  C = X^-1 (-kx^2 S).
-template <typename T, int L> struct DerivXOp {
+// LSRC > 0: S is read from the LDS (line l at l * LSRC, natural order, left
+// there by an earlier phase of the kernel) instead of global memory.
+template <typename T, int L, int LSRC = 0> struct DerivXOp {
     static constexpr int NT = 3;
     struct In {
         c2<T> s;
@@ -52,8 +55,12 @@ template <typename T, int L> struct DerivXOp {
     int n;
     double a;   // pi / X_x
     __device__ __forceinline__ void load(int l, int e, In& in) const {
-        const long b = t->base[l];
-        in.s = b >= 0 ? S[b + (long)e * es] : mk<T>(0, 0);
+        if constexpr (LSRC > 0) {
+            in.s = S[l * LSRC + sk(e)];
+        } else {
+            const long b = t->base[l];
+            in.s = b >= 0 ? S[b + (long)e * es] : mk<T>(0, 0);
+        }
     }
     template <int K> __device__ __forceinline__ c2<T> input(int, int e, const In& in) const {
         if constexpr (K == 0) {
@@ -70,6 +77,24 @@ template <typename T, int L> struct DerivXOp {
         if (b < 0) return;
         c2<T>* dst = K == 0 ? A : (K == 1 ? B : C);
         dst[b + (long)e * es] = v;
+    }
+};
+
+// Plain inverse x lines of a spectrum left in the LDS by an earlier phase.
+template <typename T, int L, int LSRC> struct InvXFromLds {
+    static constexpr int NT = 1;
+    struct In {
+        c2<T> s;
+    };
+    const LineTile<L>* t;
+    const c2<T>* S;   // LDS
+    c2<T>* W;
+    long es;
+    __device__ __forceinline__ void load(int l, int e, In& in) const { in.s = S[l * LSRC + sk(e)]; }
+    template <int K> __device__ __forceinline__ c2<T> input(int, int, const In& in) const { return in.s; }
+    template <int K> __device__ __forceinline__ void store(int l, int e, c2<T> v) const {
+        const long b = t->base[l];
+        if (b >= 0) W[b + (long)e * es] = v;
     }
 };
 
@@ -150,6 +175,24 @@ __global__ __launch_bounds__(kThreads) void k_deriv_y(GridK g, c2<T>* A, c2<T>* 
         lds, stw, DerivYOp<T, L>{&tile, A, B, C, D, (long)g.nzh, g.ny, kPi / g.X[1], kPi / g.X[2]});
 }
 
+// RowPairStore that also accumulates the stored values (FP64, compensated).
+template <typename T, int M> struct SumRowPairStore {
+    static constexpr int NS = 1;
+    c2<T>* dst;
+    int nl;
+    T scale;
+    Neu& acc;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        if (l < nl) {
+            const c2<T> w = cscale(v, scale);
+            dst[(long)l * M + e] = w;
+            acc.add((double)w.x);
+            acc.add((double)w.y);
+        }
+    }
+};
+
 // z rows c2r of the y-pass outputs: phi = Z^-1 A, gz = Z^-1 (i kz A), gx = Z^-1 B,
 // gy = Z^-1 D, lap = Z^-1 C.
 template <typename T> struct DerivZArgs {
@@ -167,7 +210,7 @@ template <typename T> struct DerivZArgs {
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<T>* __restrict__ twh,
                                                       const c2<T>* __restrict__ twf, long nrows, T scale,
-                                                      double az) {
+                                                      double az, double* part) {
     constexpr int L = z_rows<NR>();
     constexpr int MS = NR / 2 + 1;
     constexpr int M = NR / 2;
@@ -183,7 +226,8 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<
     c2<T> pre[z_fetch_count<NR>()];
     zrow_fetch<T, NR>(pre, z.A + si, nl);
     zrow_put<T, NR, false>(lds, pre, az);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.phi));
+    Neu acc;   // this thread's share of sum phi over the tile
+    zrow_inverse_lds<T, NR>(lds, stw, twf, SumRowPairStore<T, M>{reinterpret_cast<c2<T>*>(z.phi + ro), nl, scale, acc});
     __syncthreads();
     zrow_put<T, NR, true>(lds, pre, az);
     zrow_fetch<T, NR>(pre, z.B + si, nl);
@@ -199,6 +243,13 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.lap));
+    if (part) {
+        // block partial of sum phi over this tile, for the integral of phi the
+        // next R1 evaluation needs
+        __syncthreads();
+        const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    }
 }
 
 // z rows c2r of an increment spectrum D with the recovery of U in the store
@@ -302,9 +353,14 @@ __global__ __launch_bounds__(kThreads) void k_y_pair(GridK g, c2<T>* X0, c2<T>* 
 
 // forward x lines of P and Q (both fetched up front, transformed one after
 // the other); the epilogue forms k^2 in FP64 (same association as the
-// standalone combine) and applies the ETD combine
-template <int ST, typename T, int L> struct EtdXOp {
+// standalone combine), applies the ETD combine, stores the stage output if
+// asked and leaves it in the LDS (each last-stage thread writes back exactly
+// the LDS entries it has read, so no barrier is needed before the write).
+template <int ST, typename T, int L, int LS> struct EtdXOp {
     static constexpr int NT = 2;
+    // FP64 fetches P and Q up front (measured faster); FP32 reads each in its
+    // own transform (fewer registers, higher occupancy)
+    static constexpr bool kCache = sizeof(T) == 8;
     struct In {
         c2<T> p, q;
     };
@@ -316,27 +372,42 @@ template <int ST, typename T, int L> struct EtdXOp {
     double ax, ay, az;
     const CoupledK* K;
     EtdArgs<T> a;
+    c2<T>* lds;
+    int store_out;
     __device__ __forceinline__ void load(int l, int e, In& in) const {
-        const long b = t->base[l];
-        in.p = b >= 0 ? P[b + (long)e * es] : mk<T>(0, 0);
-        in.q = b >= 0 ? Q[b + (long)e * es] : mk<T>(0, 0);
+        if constexpr (kCache) {
+            const long b = t->base[l];
+            in.p = b >= 0 ? P[b + (long)e * es] : mk<T>(0, 0);
+            in.q = b >= 0 ? Q[b + (long)e * es] : mk<T>(0, 0);
+        }
     }
-    template <int K> __device__ __forceinline__ c2<T> input(int, int, const In& in) const {
-        return K == 0 ? in.p : in.q;
+    template <int K> __device__ __forceinline__ c2<T> input(int l, int e, const In& in) const {
+        if constexpr (kCache) return K == 0 ? in.p : in.q;
+        const long b = t->base[l];
+        return b >= 0 ? (K == 0 ? P : Q)[b + (long)e * es] : mk<T>(0, 0);
     }
     __device__ __forceinline__ void store_joint(int l, int e, const c2<T>* v) const {
         const long b = t->base[l];
-        if (b < 0) return;
-        const double lx = ax * lam_index(e, nx), ly = ay * lam_index(t->o[l], ny), lz = az * t->c[l];
-        const double k2 = lx * lx + ly * ly + lz * lz;
-        etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a);
+        c2<T> r = mk<T>(0, 0);
+        if (b >= 0) {
+            const double lx = ax * lam_index(e, nx), ly = ay * lam_index(t->o[l], ny), lz = az * t->c[l];
+            const double k2 = lx * lx + ly * ly + lz * lz;
+            r = etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a);
+            if (store_out) a.out[b + (long)e * es] = r;
+        }
+        lds[l * LS + sk(e)] = r;
     }
 };
 
+// Forward x pass of the remainder pair with the ETD combine, then, on the
+// combined spectrum still in the LDS, the inverse x transforms the next
+// passes need: the derivative triple (S, i kx S, -kx^2 S) -> (X0, X1, X2)
+// after a phi stage, the plain inverse -> X0 after a u stage.
 template <int ST, typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
-                                                    EtdArgs<T> a, const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block<T, N, 1>();
+                                                    EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
+                                                    const c2<T>* __restrict__ tw) {
+    constexpr int L = lines_per_block_8<T, N, 1>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
@@ -345,9 +416,19 @@ __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c
     load_table<T>(stw, tw, N);
     tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
     __syncthreads();
-    lines_fft_seq_joint<T, N, L, -1, true>(lds, stw,
-                                           EtdXOp<ST, T, L>{&tile, P, Q, (long)g.ny * g.nzh, g.nx, g.ny,
-                                                            kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K, a});
+    const long es = (long)g.ny * g.nzh;
+    lines_fft_seq_joint<T, N, L, -1, true>(
+        lds, stw,
+        EtdXOp<ST, T, L, LS>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K, a, lds,
+                             store_out});
+    __syncthreads();
+    if constexpr (ST == ETD_STAGE_PHI1 || ST == ETD_STAGE_PHI2) {
+        lines_fft_seq<T, N, L, +1, true, DerivXOp<T, L, LS>, true>(
+            lds, stw, DerivXOp<T, L, LS>{&tile, lds, X0, X1, X2, es, g.nx, kPi / g.X[0]});
+    } else {
+        lines_fft_seq<T, N, L, +1, true, InvXFromLds<T, L, LS>, true>(lds, stw,
+                                                                       InvXFromLds<T, L, LS>{&tile, lds, X0, es});
+    }
 }
 
 // ------------------------------------------------------------------ (-Delta_h)^{-1}
@@ -382,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void k_lapinv_lines(c2<T>* X, const c2<T>
                                                            const double* __restrict__ fde,
                                                            const double* __restrict__ fdo,
                                                            const double* __restrict__ fdc) {
-    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int L = lines_per_block_8<T, N, 1>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
@@ -425,15 +506,18 @@ template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A,
     return hipGetLastError();
 }
 template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z, const c2<T>* twh,
-                                                        const c2<T>* twf, hipStream_t s) {
+                                                        const c2<T>* twf, double* part, double* int_out,
+                                                        hipStream_t s) {
     constexpr int L = z_rows<NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_deriv_z<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
-    hipLaunchKernelGGL((k_deriv_z<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, z, twh, twf,
-                       nrows, scale, kPi / g.X[2]);
+    const int nb = (int)((nrows + L - 1) / L);
+    hipLaunchKernelGGL((k_deriv_z<T, NR>), dim3(nb), dim3(kThreads), smem, s, z, twh, twf, nrows, scale,
+                       kPi / g.X[2], int_out ? part : nullptr);
+    if (int_out) reduce_final_sum(part, nb, g.cell, int_out, s);
     return hipGetLastError();
 }
 template <typename T, int NR>
@@ -472,19 +556,20 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
 }
 template <int ST, typename T, int N>
 hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
-                        const c2<T>* tw, hipStream_t s) {
-    constexpr int L = lines_per_block<T, N, 1>();
+                        int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
+    constexpr int L = lines_per_block_8<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
     static std::once_flag flag;
     set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_x_etd<ST, T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, tw);
+    hipLaunchKernelGGL((k_x_etd<ST, T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, store_out, X0, X1,
+                       X2, tw);
     return hipGetLastError();
 }
 template <typename T, int N>
 hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostride, long es, const double* fde,
                          const double* fdo, const double* fdc, hipStream_t s) {
-    constexpr int L = lines_per_block<T, N, 1>();
+    constexpr int L = lines_per_block_8<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
     static std::once_flag flag;
     set_smem_limit(k_lapinv_lines<T, N>, smem, flag);
@@ -497,10 +582,10 @@ hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostr
 
 template <int ST, typename T>
 hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
-                          const c2<T>* tw, hipStream_t s) {
+                          int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
     switch (g.nx) {
 #define CASE(n) \
-    case n: return launch_x_etd<ST, T, n>(g, K, P, Q, a, tw, s);
+    case n: return launch_x_etd<ST, T, n>(g, K, P, Q, a, store_out, X0, X1, X2, tw, s);
         ETD_FFT_SIZES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -510,22 +595,12 @@ hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, con
 }  // namespace
 
 template <typename T>
-hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, hipStream_t s) {
+hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
+                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
-    hipError_t e = timed_pass(PASS_X_DERIV, 4.0 * cb, s, [&]() -> hipError_t {
-        switch (g.nx) {
-#define CASE(n) \
-    case n: return launch_deriv_x<T, n>(g, S, W0, W1, W2, t.tx, s);
-            ETD_FFT_SIZES(CASE)
-#undef CASE
-            default: return hipErrorInvalidValue;
-        }
-    });
-    if (e != hipSuccess) return e;
-    e = timed_pass(PASS_Y_DERIV, 7.0 * cb, s, [&]() -> hipError_t {
+    hipError_t e = timed_pass(PASS_Y_DERIV, 7.0 * cb, s, [&]() -> hipError_t {
         switch (g.ny) {
 #define CASE(n) \
     case n: return launch_deriv_y<T, n>(g, W0, W1, W2, W3, t.ty, s);
@@ -539,7 +614,7 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
     return timed_pass(PASS_Z_DERIV, 4.0 * cb + 5.0 * rb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_deriv_z<T, n>(g, z, t.tzh, t.tzf, s);
+    case n: return launch_deriv_z<T, n>(g, z, t.tzh, t.tzf, part, int_out, s);
             ETD_FFT_SIZES(CASE)
 #undef CASE
             default: return hipErrorInvalidValue;
@@ -548,8 +623,28 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
 }
 
 template <typename T>
+hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
+                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, double* part, double* int_out,
+                        hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    hipError_t e = timed_pass(PASS_X_DERIV, 4.0 * cb, s, [&]() -> hipError_t {
+        switch (g.nx) {
+#define CASE(n) \
+    case n: return launch_deriv_x<T, n>(g, S, W0, W1, W2, t.tx, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, part, int_out, s);
+}
+
+template <typename T>
 hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, const T* P,
-                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, hipStream_t s) {
+                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0,
+                        c2<T>* X1, c2<T>* X2, hipStream_t s) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
@@ -573,14 +668,21 @@ hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K
         }
     });
     if (e != hipSuccess) return e;
-    // spectra the combine moves besides the two inputs
-    const double extra = (stage == ETD_STAGE_U1) ? 2.0 : 3.0;
+    // spectra read and written besides the two inputs: the combine's own
+    // (prev, ra, out as the stage uses them) and the inverse x outputs
+    const bool phi = stage == ETD_STAGE_PHI1 || stage == ETD_STAGE_PHI2;
+    double extra = phi ? 3.0 : 1.0;
+    if (stage == ETD_STAGE_PHI1) extra += 1.0 + (store_out ? 1.0 : 0.0);       // prev, ra, out
+    else if (stage == ETD_STAGE_PHI2) extra += 2.0 + (store_out ? 1.0 : 0.0);  // prev, ra, out
+    else if (stage == ETD_STAGE_U1) extra += 1.0 + (store_out ? 1.0 : 0.0);    // ra, out
+    else extra += 2.0 + (store_out ? 1.0 : 0.0);                               // out (read), ra, out
+    const int so = store_out ? 1 : 0;
     return timed_pass(PASS_X_ETD, (2.0 + extra) * cb, s, [&]() -> hipError_t {
         switch (stage) {
-            case ETD_STAGE_PHI1: return dispatch_x_etd<ETD_STAGE_PHI1, T>(g, K, WP, WQ, a, t.tx, s);
-            case ETD_STAGE_PHI2: return dispatch_x_etd<ETD_STAGE_PHI2, T>(g, K, WP, WQ, a, t.tx, s);
-            case ETD_STAGE_U1: return dispatch_x_etd<ETD_STAGE_U1, T>(g, K, WP, WQ, a, t.tx, s);
-            case ETD_STAGE_U2: return dispatch_x_etd<ETD_STAGE_U2, T>(g, K, WP, WQ, a, t.tx, s);
+            case ETD_STAGE_PHI1: return dispatch_x_etd<ETD_STAGE_PHI1, T>(g, K, WP, WQ, a, so, X0, X1, X2, t.tx, s);
+            case ETD_STAGE_PHI2: return dispatch_x_etd<ETD_STAGE_PHI2, T>(g, K, WP, WQ, a, so, X0, X1, X2, t.tx, s);
+            case ETD_STAGE_U1: return dispatch_x_etd<ETD_STAGE_U1, T>(g, K, WP, WQ, a, so, X0, X1, X2, t.tx, s);
+            case ETD_STAGE_U2: return dispatch_x_etd<ETD_STAGE_U2, T>(g, K, WP, WQ, a, so, X0, X1, X2, t.tx, s);
         }
         return hipErrorInvalidValue;
     });
@@ -627,15 +729,10 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
 }
 
 template <typename T>
-hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
-                       T* out, double thr, hipStream_t s) {
-    const c2<T>* cur = D;
-    hipError_t e = hipSuccess;
-    if (g.nx > 1) {
-        if ((e = fft_pass_x<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
-        cur = W;
-    }
-    if ((e = fft_pass_y<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
+hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const T* u_old, const T* G, T* out,
+                          double thr, hipStream_t s) {
+    hipError_t e = fft_pass_y<T>(g, t, +1, W, W, s);
+    if (e != hipSuccess) return e;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
     return timed_pass(PASS_Z_RECOVER, cb + 3.0 * rb, s, [&]() -> hipError_t {
@@ -649,13 +746,43 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
     });
 }
 
+template <typename T>
+hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
+                       T* out, double thr, hipStream_t s) {
+    const c2<T>* cur = D;
+    hipError_t e = hipSuccess;
+    if (g.nx > 1) {
+        if ((e = fft_pass_x<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
+    } else {
+        // two-dimensional grid: the y pass reads D and writes W
+        if ((e = fft_pass_y<T>(g, t, +1, cur, W, s)) != hipSuccess) return e;
+        const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+        const double rb = sizeof(T) * (double)g.nreal();
+        return timed_pass(PASS_Z_RECOVER, cb + 3.0 * rb, s, [&]() -> hipError_t {
+            switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, t.tzh, t.tzf, s);
+                ETD_FFT_SIZES(CASE)
+#undef CASE
+                default: return hipErrorInvalidValue;
+            }
+        });
+    }
+    return c2r_recover_yz<T>(g, t, W, u_old, G, out, thr, s);
+}
+
 #define INST(T)                                                                                                   \
     template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
                                        const T*, T*, double, hipStream_t);                                        \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
-                                        c2<T>*, T*, T*, T*, T*, T*, hipStream_t);                                 \
+                                        c2<T>*, T*, T*, T*, T*, T*, double*, double*, hipStream_t);               \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
-                                        const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, hipStream_t);                \
+                                        const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*,        \
+                                        c2<T>*, hipStream_t);                                                     \
+    template hipError_t derivs_fused_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, c2<T>*, c2<T>*, c2<T>*, T*, \
+                                           T*, T*, T*, T*, double*, double*, hipStream_t);                        \
+    template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
+                                          double, hipStream_t);                                                   \
     template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
                                         hipStream_t);
 INST(float)

@@ -48,9 +48,12 @@ void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* 
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* phi_old, const T* phi_new, const T* gx,
                       const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, hipStream_t s);
+// q = g+ (u - ubar) (masked), gu = g+ u; with part != null also the mass
+// mass_out[0] = cell * sum q (block partials in part, then a fixed-order final
+// sum; part holds at least kRedBlocks * 4 doubles).
 template <typename T>
 void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const uint8_t* mask, T* q,
-                  T* gu, hipStream_t s);
+                  T* gu, double* part, double* mass_out, hipStream_t s);
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const T* vx, const T* vy,
                       const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s);
@@ -60,6 +63,9 @@ void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, d
 
 // ------------------------------------------------------------------ reductions (FP64, deterministic)
 constexpr int kRedBlocks = 2048;
+
+// out[0] = scale * sum of part[0..nb) (Neumaier-compensated, fixed order).
+void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s);
 
 // out[0] = scale * sum_i x_i  (Neumaier-compensated, fixed order).  part: kRedBlocks doubles.
 template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s);

@@ -205,7 +205,9 @@ __device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, cons
     if constexpr (S + 1 < Op::NT) seq_transforms<T, N, L, LS, R0, IT, DIR, LF, Op, S + 1>(lds, tw, op, in);
 }
 
-template <typename T, int N, int L, int DIR, bool LF, class Op>
+// SYNC: barrier between the loads and the first LDS writes, for an Op whose
+// load() reads the LDS (a transform of data left there by an earlier phase).
+template <typename T, int N, int L, int DIR, bool LF, class Op, bool SYNC = false>
 __device__ __forceinline__ void lines_fft_seq(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int LS = line_stride<N>();
     constexpr int R0 = NextRadix<N>::v;
@@ -222,6 +224,7 @@ __device__ __forceinline__ void lines_fft_seq(c2<T>* lds, const c2<T>* tw, const
             for (int r = 0; r < R0; ++r) op.load(l, j + r * NR, in[it][r]);
         }
     }
+    if constexpr (SYNC) __syncthreads();
     seq_transforms<T, N, L, LS, R0, IT, DIR, LF, Op, 0>(lds, tw, op, in);
 }
 
@@ -469,10 +472,16 @@ template <typename T, int N, int L, int NS> constexpr size_t lines_smem() {
 }
 
 // Lines per workgroup: coalescing wants >= 8 consecutive lines; keep the LDS
-// of one workgroup near 64 KiB so several fit in a CU.
+// of one workgroup near 64 KiB so several fit in a CU.  lines_per_block_8
+// caps the tile at 8 lines, for register-heavy kernels (more resident
+// workgroups per CU outweigh the shorter contiguous runs there; measured).
 template <typename T, int N, int NS> constexpr int lines_per_block() {
     constexpr size_t per_line = sizeof(c2<T>) * NS * line_stride<N>();
     return per_line * 16 <= 72 * 1024 ? 16 : (per_line * 8 <= 80 * 1024 ? 8 : 4);
+}
+template <typename T, int N, int NS> constexpr int lines_per_block_8() {
+    constexpr int L = lines_per_block<T, N, NS>();
+    return L > 8 ? 8 : L;
 }
 
 }  // namespace stk

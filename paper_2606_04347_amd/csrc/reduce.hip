@@ -4,6 +4,7 @@
 // in a fixed tree.  Stage 2: one workgroup combines the kRedBlocks partials in
 // the same fixed order.  Same inputs and sizes therefore give bitwise-equal
 // results run to run; the totals stay on the device for later kernels.
+#include "blocksum.h"
 #include "kernels.h"
 
 namespace etd {
@@ -12,33 +13,44 @@ namespace {
 
 constexpr int kB = 256;
 
-struct Neu {
-    double s = 0.0, c = 0.0;
-    __device__ __forceinline__ void add(double x) {
-        const double t = s + x;
-        if (fabs(s) >= fabs(x)) c += (s - t) + x;
-        else c += (x - t) + s;
-        s = t;
-    }
-    __device__ __forceinline__ double val() const { return s + c; }
-};
 
 // F: __device__ void operator()(long i, double* sums, double* maxes) const (accumulates in place:
 // sums are plain per-element values to add, maxes are per-element values to max)
 template <int NS, int NM, class F>
 __global__ __launch_bounds__(kB) void k_reduce(F f, long n, double* part) {
-    Neu acc[NS > 0 ? NS : 1];
-    double mx[NM > 0 ? NM : 1];
-    for (int j = 0; j < NM; ++j) mx[j] = -INFINITY;
-    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
-        double s[NS > 0 ? NS : 1], m[NM > 0 ? NM : 1];
-        f(i, s, m);
-        for (int j = 0; j < NS; ++j) acc[j].add(s[j]);
-        for (int j = 0; j < NM; ++j) mx[j] = fmax(mx[j], m[j]);
+    // U interleaved accumulator sets per thread (element i + u * stride goes to
+    // set u), so U independent loads and compensated adds are in flight; the
+    // sets are combined in a fixed order
+    constexpr int U = (NS + NM <= 2) ? 4 : 1;
+    Neu acc[U][NS > 0 ? NS : 1];
+    double mx[U][NM > 0 ? NM : 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        for (int j = 0; j < NM; ++j) mx[u][j] = -INFINITY;
+    const long stride = (long)gridDim.x * kB;
+    for (long i0 = (long)blockIdx.x * kB + threadIdx.x; i0 < n; i0 += U * stride) {
+        double s[U][NS > 0 ? NS : 1], m[U][NM > 0 ? NM : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * stride < n) f(i0 + u * stride, s[u], m[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * stride < n) {
+                for (int j = 0; j < NS; ++j) acc[u][j].add(s[u][j]);
+                for (int j = 0; j < NM; ++j) mx[u][j] = fmax(mx[u][j], m[u][j]);
+            }
+    }
+#pragma unroll
+    for (int u = 1; u < U; ++u) {
+        for (int j = 0; j < NS; ++j) {
+            acc[0][j].add(acc[u][j].s);
+            acc[0][j].add(acc[u][j].c);
+        }
+        for (int j = 0; j < NM; ++j) mx[0][j] = fmax(mx[0][j], mx[u][j]);
     }
     __shared__ double sh[kB];
     for (int j = 0; j < NS + NM; ++j) {
-        sh[threadIdx.x] = (j < NS) ? acc[j].val() : mx[j - NS];
+        sh[threadIdx.x] = (j < NS) ? acc[0][j].val() : mx[0][j - NS];
         __syncthreads();
         for (int w = kB / 2; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) {
@@ -252,6 +264,10 @@ struct GershF {
 };
 
 }  // namespace
+
+void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_final<1, 0>), dim3(1), dim3(kB), 0, s, part, nb, out, scale);
+}
 
 template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s) {
     run_reduce<1, 0>(SumF<T>{x}, n, scale, part, out, s);
