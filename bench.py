@@ -87,19 +87,29 @@ def run_precision(ci, prec, dt, steps, warmup, pass_steps):
     return ms, passes
 
 
-def measured_traffic(kind, n, precision):
-    """HBM bytes per launch of a pass kind from the committed counter summary
-    (profiles/traffic_fp32_256cubed.json: calibrated FETCH_SIZE + WRITE_SIZE),
-    only while the FFT source is the one the counters were taken on."""
+def kernel_source_hash():
+    """sha256 over the library's kernel sources (file names and contents)."""
+    import glob
     import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_04347_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind, n, precision):
+    """HBM bytes per launch of a kernel kind from the committed counter summary
+    (profiles/traffic_fp32_256cubed.json: calibrated FETCH_SIZE + WRITE_SIZE),
+    only while the kernel sources are the ones the counters were taken on."""
     path = os.path.join(ROOT, "profiles", "traffic_fp32_256cubed.json")
-    src = os.path.join(ROOT, "paper_2606_04347_amd", "csrc", "fft.hip")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    if rec.get("fft_source_sha256") != h or rec.get("grid") != n or rec.get("precision") != precision:
+    if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("grid") != n or \
+            rec.get("precision") != precision:
         return None
     p = rec.get("passes", {}).get(kind)
     return p["bytes_per_launch"] if p else None
