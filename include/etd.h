@@ -120,8 +120,9 @@ typedef struct {
 /* Create a plan for n_instances independent instances advanced together by
  * etd_step.  hip_stream is a hipStream_t (NULL = default stream).  Validates
  * every descriptor before touching HIP; then allocates device workspace and
- * forms the per-plan constants (for the fixed model: C, B, the Gershgorin
- * bound of H and the Chebyshev coefficients of phi1 and phi2).
+ * forms the per-plan constants (for the fixed model C and B; the Gershgorin
+ * bound of H and the Chebyshev coefficients of phi1 and phi2 depend on g and
+ * are formed by etd_set_state).
  * Errors: ETD_E_ARG, ETD_E_SIZE, ETD_E_HIP, ETD_E_NOMEM.  On error *out is NULL. */
 etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void* hip_stream,
                            etd_plan_t* out);
