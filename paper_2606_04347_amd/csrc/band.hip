@@ -13,7 +13,7 @@ constexpr int kB = 256;
 constexpr int kItems = 16;
 constexpr long kTile = (long)kB * kItems;
 
-template <typename T> __global__ void k_flags(long n, const T* __restrict__ phi, double thr, uint8_t* __restrict__ f) {
+template <typename T> __global__ __launch_bounds__(kB) void k_flags(long n, const T* __restrict__ phi, double thr, uint8_t* __restrict__ f) {
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB)
         f[i] = fabs(2.0 * (double)phi[i] - 1.0) < thr ? 1 : 0;
 }
@@ -33,7 +33,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
     return incl - v;
 }
 
-__global__ void k_tile_counts(long n, const uint8_t* __restrict__ f, int64_t* cnt) {
+__global__ __launch_bounds__(kB) void k_tile_counts(long n, const uint8_t* __restrict__ f, int64_t* cnt) {
     __shared__ int sh[kB];
     const long base = (long)blockIdx.x * kTile + (long)threadIdx.x * kItems;
     int c = 0;
@@ -47,7 +47,7 @@ __global__ void k_tile_counts(long n, const uint8_t* __restrict__ f, int64_t* cn
 }
 
 // exclusive scan of nt tile counts in one workgroup; cnt[nt] receives the total
-__global__ void k_scan_tiles(int64_t* cnt, long nt, int64_t* total_dev) {
+__global__ __launch_bounds__(kB) void k_scan_tiles(int64_t* cnt, long nt, int64_t* total_dev) {
     __shared__ int64_t sh[kB];
     __shared__ int64_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -74,7 +74,7 @@ __global__ void k_scan_tiles(int64_t* cnt, long nt, int64_t* total_dev) {
     }
 }
 
-__global__ void k_scatter(long n, const uint8_t* __restrict__ f, const int64_t* __restrict__ off, int32_t* out,
+__global__ __launch_bounds__(kB) void k_scatter(long n, const uint8_t* __restrict__ f, const int64_t* __restrict__ off, int32_t* out,
                           int64_t capacity) {
     __shared__ int sh[kB];
     if (off[gridDim.x] > capacity) return;     // the whole band must fit, else nothing is written

@@ -40,7 +40,7 @@ __device__ __forceinline__ Wave wave(const GridK& g, long idx, const double* fd)
 
 
 template <typename T>
-__global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const double* __restrict__ fd) {
+__global__ __launch_bounds__(kBlock) void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const double* __restrict__ fd) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const Wave w = wave(g, i, op == SPEC_INV_FD ? fd : nullptr);
@@ -53,7 +53,7 @@ __global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const
             const T m = (T)(w.mu > 0.0 ? 1.0 / w.mu : 0.0);
             r = mk<T>(m * a.x, m * a.y);
         } else {
-            const T k = (T)w.kd[op - 1];   // i k a = (-k a.y, k a.x)
+            const T k = (T)(op == SPEC_IKX ? w.kd[0] : (op == SPEC_IKY ? w.kd[1] : w.kd[2]));   // i k a = (-k a.y, k a.x)
             r = mk<T>(-k * a.y, k * a.x);
         }
         out[i] = r;
@@ -62,7 +62,7 @@ __global__ void k_spec_apply(GridK g, int op, const c2<T>* in, c2<T>* out, const
 
 // One ETD combine (etd_point.h) per half-spectrum entry: p = P[i], q = Q[i].
 template <int ST, typename T>
-__global__ void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q, EtdArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q, EtdArgs<T> a) {
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const Wave w = wave(g, i, nullptr);
@@ -71,26 +71,67 @@ __global__ void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2
 }
 
 // ----------------------------------------------------------------- real space
-struct Nbr {
+// The stencil kernels give each thread four consecutive z points (every
+// supported Nz is a multiple of 4): one vector load per field and neighbour
+// row serves four points, and the index decode is paid once per quad.
+template <typename T> struct Q4 {
+    T v[4];
+};
+template <typename T> __device__ __forceinline__ Q4<T> ld4(const T* p) {
+    Q4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        r.v[0] = a.x;
+        r.v[1] = a.y;
+        r.v[2] = a.z;
+        r.v[3] = a.w;
+    } else {
+        const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+        r.v[0] = a.x;
+        r.v[1] = a.y;
+        r.v[2] = b.x;
+        r.v[3] = b.y;
+    }
+    return r;
+}
+template <typename T> __device__ __forceinline__ void st4(T* p, const Q4<T>& r) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else {
+        reinterpret_cast<double2*>(p)[0] = make_double2(r.v[0], r.v[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(r.v[2], r.v[3]);
+    }
+}
+
+// Quad q (points 4q .. 4q+3, one z row): its first point c, the first points
+// of the x and y neighbour quads, and the z neighbours before and after it
+// (all periodic).
+struct QuadNbr {
     long c, xm, xp, ym, yp, zm, zp;
 };
-__device__ __forceinline__ Nbr neighbours(const GridK& g, long i) {
-    const unsigned u = (unsigned)i;     // grids hold fewer than 2^31 points
-    const unsigned t = u / (unsigned)g.nz;
-    const int iz = (int)(u - t * (unsigned)g.nz);
-    const unsigned ix_ = t / (unsigned)g.ny;
-    const int iy = (int)(t - ix_ * (unsigned)g.ny);
+__device__ __forceinline__ QuadNbr quad_neighbours(const GridK& g, long q) {
+    const unsigned nz4 = (unsigned)g.nz >> 2;
+    const unsigned uq = (unsigned)q;   // grids hold fewer than 2^31 points
+    const unsigned row = uq / nz4;
+    const int iz = (int)(uq - row * nz4) * 4;
+    const unsigned ix_ = row / (unsigned)g.ny;
+    const int iy = (int)(row - ix_ * (unsigned)g.ny);
     const int ix = (int)ix_;
-    const long sx = (long)g.ny * g.nz, sy = g.nz;
-    Nbr n;
-    n.c = i;
-    n.xp = i + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
-    n.xm = i + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
-    n.yp = i + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
-    n.ym = i + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
-    n.zp = i + ((iz + 1 < g.nz) ? 1 : -(long)(g.nz - 1));
-    n.zm = i + ((iz > 0) ? -1 : (long)(g.nz - 1));
+    const long sx = (long)g.ny * g.nz, sy = g.nz, r0 = (long)row * g.nz;
+    QuadNbr n;
+    n.c = r0 + iz;
+    n.xp = n.c + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
+    n.xm = n.c + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
+    n.yp = n.c + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
+    n.ym = n.c + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
+    n.zm = r0 + (iz > 0 ? iz - 1 : g.nz - 1);
+    n.zp = r0 + (iz + 4 < g.nz ? iz + 4 : 0);
     return n;
+}
+
+// mask bytes of a quad (4-byte aligned: the quad's first point is a multiple of 4)
+__device__ __forceinline__ unsigned ld_mask4(const uint8_t* mask, long c) {
+    return *reinterpret_cast<const unsigned*>(mask + c);
 }
 
 template <typename T> __device__ __forceinline__ T gloc(T p) {
@@ -108,12 +149,12 @@ __device__ __forceinline__ T lapS_axis(T um, T uc, T up, T gm, T gc, T gp, T ih2
 }
 
 template <typename T>
-__global__ void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const T* __restrict__ lap,
+__global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const T* __restrict__ lap,
                            const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
                            const T* __restrict__ u, const uint8_t* __restrict__ mask,
                            const double* __restrict__ int_phi, double A0, T* __restrict__ P, T* __restrict__ Q,
                            int tpb) {
-    const long n = g.nreal();
+    const long nq = g.nreal() / 4;
     const T e2 = (T)(K.eps_phi * K.eps_phi);
     const T c1 = (T)K.c1, A1 = (T)K.A1, A2 = (T)K.A2;
     const T cW = (T)(K.kappa / (K.mu * K.eps_phi * K.eps_phi * K.eps_phi * K.eps_phi));
@@ -124,33 +165,46 @@ __global__ void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const
     const T u0 = (T)K.u0;
     const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
     const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
-    // a block takes tpb consecutive tiles of kBlock points, blocks in XCD-contiguous
+    // a block takes tpb consecutive tiles of kBlock quads, blocks in XCD-contiguous
     // order, so that the y and x neighbour rows of a tile are read through the same L2
     const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
     for (int it = 0; it < tpb; ++it) {
-        const long i = (t0 + it) * kBlock + threadIdx.x;
-        if (i >= n) return;
-        const Nbr nb = neighbours(g, i);
-        const T p = phi[i], L = lap[i];
-        const T a = gx[i], b = gy[i], c = gz[i];
-        const T gn = sqrt(a * a + b * b + c * c);
-        const T uc = u[i];
-        const T gc = gloc(p);
-        T S = lapS_axis(u[nb.xm], uc, u[nb.xp], gloc(phi[nb.xm]), gc, gloc(phi[nb.xp]), ihx);
-        S += lapS_axis(u[nb.ym], uc, u[nb.yp], gloc(phi[nb.ym]), gc, gloc(phi[nb.yp]), ihy);
-        S += lapS_axis(u[nb.zm], uc, u[nb.zp], gloc(phi[nb.zm]), gc, gloc(phi[nb.zp]), ihz);
-        const T wp = Wp(p), wpp = Wpp(p);
-        const T q1 = wp - A1 * p;
-        T p1 = c1 * (wpp - A2) * (L - A1 * p / e2) - (cW * wpp + cs) * q1;
-        T surf = cl * (eu * S - gc * Wp(uc) * ieu) * gn - area * gn + ca * (uc + u0) * gn * (ep * L - wp * iep);
-        if (mask) surf = mask[i] ? surf : (T)0;
-        P[i] = p1 + surf;
-        Q[i] = q1;
+        const long q = (t0 + it) * kBlock + threadIdx.x;
+        if (q >= nq) return;
+        const QuadNbr nb = quad_neighbours(g, q);
+        const Q4<T> p = ld4(phi + nb.c), L = ld4(lap + nb.c), a = ld4(gx + nb.c), b = ld4(gy + nb.c),
+                    c = ld4(gz + nb.c), uu = ld4(u + nb.c);
+        const Q4<T> pxm = ld4(phi + nb.xm), pxp = ld4(phi + nb.xp), pym = ld4(phi + nb.ym), pyp = ld4(phi + nb.yp);
+        const Q4<T> uxm = ld4(u + nb.xm), uxp = ld4(u + nb.xp), uym = ld4(u + nb.ym), uyp = ld4(u + nb.yp);
+        const T pzm = phi[nb.zm], pzp = phi[nb.zp], uzm = u[nb.zm], uzp = u[nb.zp];
+        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0u;
+        Q4<T> oP, oQ;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T pc = p.v[k], uc = uu.v[k];
+            const T gn = sqrt(a.v[k] * a.v[k] + b.v[k] * b.v[k] + c.v[k] * c.v[k]);
+            const T gc = gloc(pc);
+            const T zpm = k > 0 ? p.v[k - 1] : pzm, zpp = k < 3 ? p.v[k + 1] : pzp;
+            const T zum = k > 0 ? uu.v[k - 1] : uzm, zup = k < 3 ? uu.v[k + 1] : uzp;
+            T S = lapS_axis(uxm.v[k], uc, uxp.v[k], gloc(pxm.v[k]), gc, gloc(pxp.v[k]), ihx);
+            S += lapS_axis(uym.v[k], uc, uyp.v[k], gloc(pym.v[k]), gc, gloc(pyp.v[k]), ihy);
+            S += lapS_axis(zum, uc, zup, gloc(zpm), gc, gloc(zpp), ihz);
+            const T wp = Wp(pc), wpp = Wpp(pc);
+            const T q1 = wp - A1 * pc;
+            const T p1 = c1 * (wpp - A2) * (L.v[k] - A1 * pc / e2) - (cW * wpp + cs) * q1;
+            T surf = cl * (eu * S - gc * Wp(uc) * ieu) * gn - area * gn +
+                     ca * (uc + u0) * gn * (ep * L.v[k] - wp * iep);
+            if (mask) surf = ((mk >> (8 * k)) & 0xffu) ? surf : (T)0;
+            oP.v[k] = p1 + surf;
+            oQ.v[k] = q1;
+        }
+        st4(P + nb.c, oP);
+        st4(Q + nb.c, oQ);
     }
 }
 
 template <typename T>
-__global__ void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const T* __restrict__ pn,
+__global__ __launch_bounds__(kBlock) void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const T* __restrict__ pn,
                            const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
                            T* __restrict__ gp, T* __restrict__ vx, T* __restrict__ vy, T* __restrict__ vz) {
     const long n = g.nreal();
@@ -171,7 +225,7 @@ __global__ void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const 
 }
 
 template <typename T>
-__global__ void k_q_gu(long n, T ubar, const T* __restrict__ u, const T* __restrict__ G,
+__global__ __launch_bounds__(kBlock) void k_q_gu(long n, T ubar, const T* __restrict__ u, const T* __restrict__ G,
                        const uint8_t* __restrict__ mask, T* __restrict__ q, T* __restrict__ gu, double* part) {
     Neu acc;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
@@ -190,40 +244,52 @@ __global__ void k_q_gu(long n, T ubar, const T* __restrict__ u, const T* __restr
 }
 
 template <typename T>
-__global__ void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u, const T* __restrict__ G,
+__global__ __launch_bounds__(kBlock) void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u, const T* __restrict__ G,
                            const T* __restrict__ vx, const T* __restrict__ vy, const T* __restrict__ vz,
                            const T* __restrict__ psi, const double* __restrict__ m, const uint8_t* __restrict__ mask,
                            T* __restrict__ P, int tpb) {
-    const long n = g.nreal();
+    const long nq = g.nreal() / 4;
     const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), B2 = (T)K.B2, gam = (T)K.gamma;
     const T Mm = (T)(K.M * m[0]);
     const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
     const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
     const T i2hx = (T)(g.nx > 1 ? 0.5 / g.h[0] : 0.0), i2hy = (T)(0.5 / g.h[1]), i2hz = (T)(0.5 / g.h[2]);
-    // a block takes tpb consecutive tiles of kBlock points, blocks in XCD-contiguous
-    // order, so that the y and x neighbour rows of a tile are read through the same L2
     const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
     for (int it = 0; it < tpb; ++it) {
-        const long i = (t0 + it) * kBlock + threadIdx.x;
-        if (i >= n) return;
-        const Nbr nb = neighbours(g, i);
-        const T uc = u[i], Gc = G[i];
-        T S = lapS_axis(u[nb.xm], uc, u[nb.xp], G[nb.xm], Gc, G[nb.xp], ihx);
-        S += lapS_axis(u[nb.ym], uc, u[nb.yp], G[nb.ym], Gc, G[nb.yp], ihy);
-        S += lapS_axis(u[nb.zm], uc, u[nb.zp], G[nb.zm], Gc, G[nb.zp], ihz);
-        const T div = (G[nb.xp] * u[nb.xp] * vx[nb.xp] - G[nb.xm] * u[nb.xm] * vx[nb.xm]) * i2hx +
-                      (G[nb.yp] * u[nb.yp] * vy[nb.yp] - G[nb.ym] * u[nb.ym] * vy[nb.ym]) * i2hy +
-                      (G[nb.zp] * u[nb.zp] * vz[nb.zp] - G[nb.zm] * u[nb.zm] * vz[nb.zm]) * i2hz;
-        T p2 = eu * S + B2 * Gc * uc - Gc * Wp(uc) * ieu - gam * Gc * psi[i] - Mm * Gc - div;
-        if (mask) p2 = mask[i] ? p2 : (T)0;
-        P[i] = p2;
+        const long q = (t0 + it) * kBlock + threadIdx.x;
+        if (q >= nq) return;
+        const QuadNbr nb = quad_neighbours(g, q);
+        const Q4<T> uu = ld4(u + nb.c), GG = ld4(G + nb.c), ps = ld4(psi + nb.c), wz = ld4(vz + nb.c);
+        const Q4<T> uxm = ld4(u + nb.xm), uxp = ld4(u + nb.xp), uym = ld4(u + nb.ym), uyp = ld4(u + nb.yp);
+        const Q4<T> Gxm = ld4(G + nb.xm), Gxp = ld4(G + nb.xp), Gym = ld4(G + nb.ym), Gyp = ld4(G + nb.yp);
+        const Q4<T> vxm = ld4(vx + nb.xm), vxp = ld4(vx + nb.xp), vym = ld4(vy + nb.ym), vyp = ld4(vy + nb.yp);
+        const T uzm = u[nb.zm], uzp = u[nb.zp], Gzm = G[nb.zm], Gzp = G[nb.zp], vzm = vz[nb.zm], vzp = vz[nb.zp];
+        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0u;
+        Q4<T> oP;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T uc = uu.v[k], Gc = GG.v[k];
+            const T zum = k > 0 ? uu.v[k - 1] : uzm, zup = k < 3 ? uu.v[k + 1] : uzp;
+            const T zGm = k > 0 ? GG.v[k - 1] : Gzm, zGp = k < 3 ? GG.v[k + 1] : Gzp;
+            const T zvm = k > 0 ? wz.v[k - 1] : vzm, zvp = k < 3 ? wz.v[k + 1] : vzp;
+            T S = lapS_axis(uxm.v[k], uc, uxp.v[k], Gxm.v[k], Gc, Gxp.v[k], ihx);
+            S += lapS_axis(uym.v[k], uc, uyp.v[k], Gym.v[k], Gc, Gyp.v[k], ihy);
+            S += lapS_axis(zum, uc, zup, zGm, Gc, zGp, ihz);
+            const T div = (Gxp.v[k] * uxp.v[k] * vxp.v[k] - Gxm.v[k] * uxm.v[k] * vxm.v[k]) * i2hx +
+                          (Gyp.v[k] * uyp.v[k] * vyp.v[k] - Gym.v[k] * uym.v[k] * vym.v[k]) * i2hy +
+                          (zGp * zup * zvp - zGm * zum * zvm) * i2hz;
+            T p2 = eu * S + B2 * Gc * uc - Gc * Wp(uc) * ieu - gam * Gc * ps.v[k] - Mm * Gc - div;
+            if (mask) p2 = ((mk >> (8 * k)) & 0xffu) ? p2 : (T)0;
+            oP.v[k] = p2;
+        }
+        st4(P + nb.c, oP);
     }
 }
 
 // Recovery of U from GU = g+ u_old + d (Section 3.3 after Algorithm 1):
 // U = GU / G = u_old + d / G where G > thr, U = GU elsewhere.  out may alias u_old.
 template <typename T>
-__global__ void k_recover_inc(long n, const T* u_old, const T* __restrict__ d, const T* __restrict__ G, T* out,
+__global__ __launch_bounds__(kBlock) void k_recover_inc(long n, const T* u_old, const T* __restrict__ d, const T* __restrict__ G, T* out,
                               T thr) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const T Gc = G[i], uo = u_old[i], dd = d[i];
@@ -231,15 +297,15 @@ __global__ void k_recover_inc(long n, const T* u_old, const T* __restrict__ d, c
     }
 }
 
-template <typename TI, typename TO> __global__ void k_convert(long n, const TI* __restrict__ in, TO* __restrict__ out) {
+template <typename TI, typename TO> __global__ __launch_bounds__(kBlock) void k_convert(long n, const TI* __restrict__ in, TO* __restrict__ out) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) out[i] = (TO)in[i];
 }
 
-template <typename T> __global__ void k_gloc(long n, const T* __restrict__ phi, T* __restrict__ G) {
+template <typename T> __global__ __launch_bounds__(kBlock) void k_gloc(long n, const T* __restrict__ phi, T* __restrict__ G) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) G[i] = gloc(phi[i]);
 }
 
-__global__ void k_delta(long n, double* x) {
+__global__ __launch_bounds__(kBlock) void k_delta(long n, double* x) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) x[i] = (i == 0) ? 1.0 : 0.0;
 }
 
@@ -294,7 +360,7 @@ template <typename T>
 void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
                       const T* gz, const T* u, const uint8_t* mask, const double* int_phi, double A0, T* P, T* Q,
                       hipStream_t s) {
-    const TileGrid tg = tiles_for(g.nreal());
+    const TileGrid tg = tiles_for(g.nreal() / 4);   // one thread per quad of z points
     hipLaunchKernelGGL(k_R1_point<T>, dim3(tg.blocks), dim3(kBlock), 0, s, g, K, phi, lap, gx, gy, gz, u, mask, int_phi,
                        A0, P, Q, tg.tpb);
 }
@@ -314,7 +380,7 @@ void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* G, con
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
                       const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s) {
-    const TileGrid tg = tiles_for(g.nreal());
+    const TileGrid tg = tiles_for(g.nreal() / 4);   // one thread per quad of z points
     hipLaunchKernelGGL(k_P2_point<T>, dim3(tg.blocks), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, psi, m, mask, P,
                        tg.tpb);
 }

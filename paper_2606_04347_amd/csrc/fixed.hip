@@ -15,7 +15,7 @@ int grid_for(long n) {
     return (int)(b < 1 ? 1 : b);
 }
 
-__global__ void k_prep(long n, const double* __restrict__ G, double* __restrict__ sg, double* __restrict__ isg) {
+__global__ __launch_bounds__(kB) void k_prep(long n, const double* __restrict__ G, double* __restrict__ sg, double* __restrict__ isg) {
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
         const double s = sqrt(G[i]);
         sg[i] = s;
@@ -27,7 +27,7 @@ __device__ __forceinline__ double f_ind(double s) { return 3.0 * s * s - 2.0 * s
 __device__ __forceinline__ double fp_ind(double s) { return 6.0 * s * (1.0 - s); }
 __device__ __forceinline__ double Wp(double s) { return 36.0 * (s * s - s) * (2.0 * s - 1.0); }
 
-__global__ void k_nonlocal_arg(long n, FixedK K, const double* __restrict__ G, const double* __restrict__ U,
+__global__ __launch_bounds__(kB) void k_nonlocal_arg(long n, FixedK K, const double* __restrict__ G, const double* __restrict__ U,
                                double* __restrict__ q, double* __restrict__ mq) {
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
         const double f = f_ind(U[i]);
@@ -38,7 +38,7 @@ __global__ void k_nonlocal_arg(long n, FixedK K, const double* __restrict__ G, c
 }
 
 template <typename TP>
-__global__ void k_remainder(long n, FixedK K, const double* __restrict__ sg, const double* __restrict__ U,
+__global__ __launch_bounds__(kB) void k_remainder(long n, FixedK K, const double* __restrict__ sg, const double* __restrict__ U,
                             const TP* __restrict__ psi, const double* __restrict__ m, double* __restrict__ R) {
     const double Mm = K.M * m[0];
     const double ieu = 1.0 / K.eps_u;
@@ -79,7 +79,7 @@ __device__ __forceinline__ double H_apply(const GridK& g, long i, const double* 
     return -isg[i] * acc;
 }
 
-__global__ void k_cheb(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg, double a,
+__global__ __launch_bounds__(kB) void k_cheb(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg, double a,
                        double b, double alpha, double beta, const double* __restrict__ x, const double* xprev,
                        double* y, double* acc, double c, double c0, int first) {
     const long n = g.nreal();
@@ -94,18 +94,18 @@ __global__ void k_cheb(GridK g, FixedK K, const double* __restrict__ G, const do
     }
 }
 
-__global__ void k_L(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg,
+__global__ __launch_bounds__(kB) void k_L(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg,
                     const double* __restrict__ x, double* __restrict__ out) {
     const long n = g.nreal();
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB)
         out[i] = K.B * x[i] + K.eps_u * H_apply(g, i, G, isg, x);
 }
 
-__global__ void k_axpby(long n, double a, const double* x, double b, const double* y, double* out) {
+__global__ __launch_bounds__(kB) void k_axpby(long n, double a, const double* x, double b, const double* y, double* out) {
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) out[i] = a * x[i] + b * y[i];
 }
 
-__global__ void k_mul(long n, const double* x, const double* y, double* out) {
+__global__ __launch_bounds__(kB) void k_mul(long n, const double* x, const double* y, double* out) {
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) out[i] = x[i] * y[i];
 }
 

@@ -220,7 +220,7 @@ template <typename T> struct MassF {
 };
 
 template <typename T>
-__global__ void k_mass_apply(long n, const T* __restrict__ G, T* U, double thr, double cell, const double* Q0,
+__global__ __launch_bounds__(kB) void k_mass_apply(long n, const T* __restrict__ G, T* U, double thr, double cell, const double* Q0,
                              const double* sums) {
     const double den = cell * sums[1];
     const double c = den > 0.0 ? (Q0[0] - cell * sums[0]) / den : 0.0;
