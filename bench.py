@@ -129,6 +129,8 @@ def roofline(passes, pass_steps, n, precision):
 
 FFT_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
              "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover")
+# z passes with the R1 / P2 stencils formed in their load
+FUSED_STENCIL_KINDS = ("z_r2c_r1", "z_r2c_p2")
 
 
 def ledger(passes, pass_steps, npts, ms_per_step):
@@ -176,6 +178,7 @@ def band_measure(n, steps, warmup):
             "band_points": d["band_count"], "band_fraction": d["band_count"] / npts,
             "ms_per_step_by_group": {"fft_passes": group(FFT_KINDS), "band_flags_and_compaction": group(("band",)),
                                      "stencils_R1_P2": group(("r1_stencil", "p2_stencil")),
+                                     "z_r2c_with_R1_P2": group(FUSED_STENCIL_KINDS),
                                      "pointwise_and_reductions": group(("pointwise", "reduce"))},
             "band_kernels_per_rebuild_ms": passes["band"]["ms"] / max(1, passes["band"]["launches"]),
             "ledger": ledger(passes, 10, npts, ms)}

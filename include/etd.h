@@ -222,8 +222,11 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
  *  12 narrow-band flags and compaction   13 R1 remainder (stencil)
  *  14 R2 remainder P2 (stencil)          15 coupled pointwise kernels
  *  16 FP64 reductions                    17 fixed model: Chebyshev / L stencils
- *  18 fixed model: pointwise kernels     19 unused. */
-#define ETD_PASS_KINDS 20
+ *  18 fixed model: pointwise kernels
+ *  19 z-row r2c of the R1 pair with R1 formed in the load
+ *  20 z-row r2c of the (P2, g u) pair with P2 formed in the load
+ *  21..23 unused. */
+#define ETD_PASS_KINDS 24
 typedef struct {
     int64_t launches[ETD_PASS_KINDS];
     double total_ms[ETD_PASS_KINDS];

@@ -356,30 +356,40 @@ hipError_t remainder_etd_2d(const Instance& I, CoupledView<T>& v, EtdStage st, c
     return hipGetLastError();
 }
 
-// One phi stage from the remainder pair (P, Q): the combined spectrum a.out
-// and, in real space, phi_out with its derivatives (gx, gy, gz, lap).  On
-// three-dimensional grids the x pass of the pair also runs the inverse x
-// transforms of the derivative pipeline.
+// One phi stage: R1 at (phi_in, its derivatives, u^n), the ETD combine into
+// the spectrum a.out and, in real space, phi_out with its derivatives (gx,
+// gy, gz, lap; on three-dimensional grids also the integral of phi_out).  On
+// three-dimensional grids R1 is formed in the load of the z pass and the x
+// pass of the pair also runs the inverse x transforms of the derivatives.
 template <typename T>
-hipError_t phi_stage(const Instance& I, CoupledView<T>& v, EtdStage st, const EtdArgs<T>& a, T* phi_out,
-                     hipStream_t s) {
+hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, const uint8_t* mask, EtdStage st,
+                     const EtdArgs<T>& a, T* phi_out, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     if (g.nx > 1) {
-        hipError_t e = fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
+        const R1Fields<T> f{phi_in, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0};
+        hipError_t e = r1_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
         if (e != hipSuccess) return e;
         return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, I.part,
                                   I.scal + S_INTPHI, s);
     }
+    const long n = g.nreal();
+    const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
+    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, phi_in, g.cell, I.part, I.scal + S_INTPHI, s); });
+    timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
+        coupled_R1_point<T>(g, I.K, phi_in, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
+                            s);
+    });
     hipError_t e = remainder_etd_2d<T>(I, v, st, a, s);
     if (e != hipSuccess) return e;
     return phi_and_derivs<T>(I, v, a.out, phi_out, s);
 }
 
-// One u stage: q = g (u - ubar) (masked) -> P, g u -> Q; m = h^3 sum q;
-// psi = (-Delta_h)^{-1} q; P = P2(u); then the transforms of (P2, g u), the
-// combine into the increment D (Sgu; stored if store_D) and Sra, and the
-// recovery out = rec(g+ u^n + F^-1 D).
+// One u stage: q = g (u - ubar) (masked) -> P; m = h^3 sum q;
+// psi = (-Delta_h)^{-1} q; P2(u) and g+ u; their transforms, the combine into
+// the increment D (Sgu; stored if store_D) and Sra, and the recovery
+// out = rec(g+ u^n + F^-1 D).  On three-dimensional grids P2 and g+ u are
+// formed in the load of the z pass.
 template <typename T>
 hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* mask, EtdStage st, bool store_D,
                    T* out, hipStream_t s) {
@@ -387,20 +397,22 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const FFTTables<T>& t = tables<T>(I);
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] {
-        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, I.part, I.scal + S_MASS, s);
+    const bool fused = g.nx > 1;
+    timed_kernel(PASS_POINT, (fused ? 3.0 : 4.0) * fb + mb, s, [&] {
+        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, fused ? nullptr : v.Q, I.part, I.scal + S_MASS, s);
     });
     hipError_t e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s);
     if (e != hipSuccess) return e;
-    timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
-        coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
-    });
     const EtdArgs<T> a{nullptr, v.Sra, v.Sgu};
-    if (g.nx > 1) {
-        e = fwd_pair_etd<T>(g, t, I.K, st, v.P, v.Q, v.Sa, v.Sb, a, store_D, v.Sa, nullptr, nullptr, s);
+    if (fused) {
+        const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
+        e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
         if (e != hipSuccess) return e;
         return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, s);
     }
+    timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
+        coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
+    });
     if ((e = remainder_etd_2d<T>(I, v, st, a, s)) != hipSuccess) return e;
     return c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, out, I.K.thr, s);
 }
@@ -422,28 +434,13 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
         mask = I.mask;
     }
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
+    // and (three-dimensional grids) the device scalar the integral of phi^n
     const double fb = (double)sizeof(T) * n;   // one real field
-    const double mb = mask ? (double)n : 0.0;
-    // the integral of phi^n: formed by the z pass that produced phi^n on
-    // three-dimensional grids (previous step or set_state), here otherwise
-    if (g.nx == 1)
-        timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s); });
-    timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
-        coupled_R1_point<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
-                            s);
-    });
     if (!rk2) {
-        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s));
     } else {
-        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
-        if (g.nx == 1)
-            timed_kernel(PASS_REDUCE, fb, s,
-                         [&] { reduce_sum<T>(n, v.phiB, g.cell, I.part, I.scal + S_INTPHI, s); });
-        timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
-            coupled_R1_point<T>(g, I.K, v.phiB, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P,
-                                v.Q, s);
-        });
-        HIPCHK(plan, phi_stage<T>(I, v, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s));
     }
     // phi^{n+1} and its derivatives are kept for the next step; g+ and the velocity
     timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {

@@ -3,6 +3,7 @@
 // second-order FD operators of Section 2.1.
 #include "blocksum.h"
 #include "etd_point.h"
+#include "remainders.h"
 
 namespace etd {
 
@@ -134,37 +135,15 @@ __device__ __forceinline__ unsigned ld_mask4(const uint8_t* mask, long c) {
     return *reinterpret_cast<const unsigned*>(mask + c);
 }
 
-template <typename T> __device__ __forceinline__ T gloc(T p) {
-    const T a = p * p - p;
-    return (T)18 * a * a;
-}
-template <typename T> __device__ __forceinline__ T Wp(T s) { return (T)36 * (s * s - s) * ((T)2 * s - (T)1); }
-template <typename T> __device__ __forceinline__ T Wpp(T s) { return (T)36 * ((T)6 * s * s - (T)6 * s + (T)1); }
-
-// D^-(g_{i+1/2} D^+ u) along one axis, g at the three points given
 template <typename T>
-__device__ __forceinline__ T lapS_axis(T um, T uc, T up, T gm, T gc, T gp, T ih2) {
-    const T ghp = (T)0.5 * (gc + gp), ghm = (T)0.5 * (gm + gc);
-    return (ghp * (up - uc) - ghm * (uc - um)) * ih2;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi, const T* __restrict__ lap,
-                           const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
-                           const T* __restrict__ u, const uint8_t* __restrict__ mask,
-                           const double* __restrict__ int_phi, double A0, T* __restrict__ P, T* __restrict__ Q,
-                           int tpb) {
+__global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const T* __restrict__ phi,
+                                                     const T* __restrict__ lap, const T* __restrict__ gx,
+                                                     const T* __restrict__ gy, const T* __restrict__ gz,
+                                                     const T* __restrict__ u, const uint8_t* __restrict__ mask,
+                                                     const double* __restrict__ int_phi, double A0,
+                                                     T* __restrict__ P, T* __restrict__ Q, int tpb) {
     const long nq = g.nreal() / 4;
-    const T e2 = (T)(K.eps_phi * K.eps_phi);
-    const T c1 = (T)K.c1, A1 = (T)K.A1, A2 = (T)K.A2;
-    const T cW = (T)(K.kappa / (K.mu * K.eps_phi * K.eps_phi * K.eps_phi * K.eps_phi));
-    const T cs = (T)(K.lambda_surf / (K.mu * K.eps_phi * K.eps_phi));
-    const T cl = (T)(K.lambda_line / K.mu), ca = (T)(K.alpha / K.mu);
-    const T area = (T)((K.M_area / K.mu) * (int_phi[0] - A0));
-    const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), ep = (T)K.eps_phi, iep = (T)(1.0 / K.eps_phi);
-    const T u0 = (T)K.u0;
-    const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
-    const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
+    const R1Const<T> kc(g, K, int_phi[0], A0);
     // a block takes tpb consecutive tiles of kBlock quads, blocks in XCD-contiguous
     // order, so that the y and x neighbour rows of a tile are read through the same L2
     const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
@@ -177,26 +156,16 @@ __global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const 
         const Q4<T> pxm = ld4(phi + nb.xm), pxp = ld4(phi + nb.xp), pym = ld4(phi + nb.ym), pyp = ld4(phi + nb.yp);
         const Q4<T> uxm = ld4(u + nb.xm), uxp = ld4(u + nb.xp), uym = ld4(u + nb.ym), uyp = ld4(u + nb.yp);
         const T pzm = phi[nb.zm], pzp = phi[nb.zp], uzm = u[nb.zm], uzp = u[nb.zp];
-        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0u;
+        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0xffffffffu;
         Q4<T> oP, oQ;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const T pc = p.v[k], uc = uu.v[k];
-            const T gn = sqrt(a.v[k] * a.v[k] + b.v[k] * b.v[k] + c.v[k] * c.v[k]);
-            const T gc = gloc(pc);
-            const T zpm = k > 0 ? p.v[k - 1] : pzm, zpp = k < 3 ? p.v[k + 1] : pzp;
-            const T zum = k > 0 ? uu.v[k - 1] : uzm, zup = k < 3 ? uu.v[k + 1] : uzp;
-            T S = lapS_axis(uxm.v[k], uc, uxp.v[k], gloc(pxm.v[k]), gc, gloc(pxp.v[k]), ihx);
-            S += lapS_axis(uym.v[k], uc, uyp.v[k], gloc(pym.v[k]), gc, gloc(pyp.v[k]), ihy);
-            S += lapS_axis(zum, uc, zup, gloc(zpm), gc, gloc(zpp), ihz);
-            const T wp = Wp(pc), wpp = Wpp(pc);
-            const T q1 = wp - A1 * pc;
-            const T p1 = c1 * (wpp - A2) * (L.v[k] - A1 * pc / e2) - (cW * wpp + cs) * q1;
-            T surf = cl * (eu * S - gc * Wp(uc) * ieu) * gn - area * gn +
-                     ca * (uc + u0) * gn * (ep * L.v[k] - wp * iep);
-            if (mask) surf = ((mk >> (8 * k)) & 0xffu) ? surf : (T)0;
-            oP.v[k] = p1 + surf;
-            oQ.v[k] = q1;
+            const T un[6] = {uxm.v[k], uxp.v[k], uym.v[k], uyp.v[k], k > 0 ? uu.v[k - 1] : uzm,
+                             k < 3 ? uu.v[k + 1] : uzp};
+            const T pn[6] = {pxm.v[k], pxp.v[k], pym.v[k], pyp.v[k], k > 0 ? p.v[k - 1] : pzm,
+                             k < 3 ? p.v[k + 1] : pzp};
+            r1_point(kc, p.v[k], L.v[k], a.v[k], b.v[k], c.v[k], uu.v[k], un, pn, ((mk >> (8 * k)) & 0xffu) != 0,
+                     &oP.v[k], &oQ.v[k]);
         }
         st4(P + nb.c, oP);
         st4(Q + nb.c, oQ);
@@ -233,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_q_gu(long n, T ubar, const T* __rest
         T qq = Gc * (uc - ubar);
         if (mask) qq = mask[i] ? qq : (T)0;
         q[i] = qq;
-        gu[i] = Gc * uc;
+        if (gu) gu[i] = Gc * uc;
         acc.add((double)qq);
     }
     if (part) {
@@ -244,16 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_q_gu(long n, T ubar, const T* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u, const T* __restrict__ G,
-                           const T* __restrict__ vx, const T* __restrict__ vy, const T* __restrict__ vz,
-                           const T* __restrict__ psi, const double* __restrict__ m, const uint8_t* __restrict__ mask,
-                           T* __restrict__ P, int tpb) {
+__global__ __launch_bounds__(kBlock) void k_P2_point(GridK g, CoupledK K, const T* __restrict__ u,
+                                                     const T* __restrict__ G, const T* __restrict__ vx,
+                                                     const T* __restrict__ vy, const T* __restrict__ vz,
+                                                     const T* __restrict__ psi, const double* __restrict__ m,
+                                                     const uint8_t* __restrict__ mask, T* __restrict__ P, int tpb) {
     const long nq = g.nreal() / 4;
-    const T eu = (T)K.eps_u, ieu = (T)(1.0 / K.eps_u), B2 = (T)K.B2, gam = (T)K.gamma;
-    const T Mm = (T)(K.M * m[0]);
-    const T ihx = (T)(g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0);
-    const T ihy = (T)(1.0 / (g.h[1] * g.h[1])), ihz = (T)(1.0 / (g.h[2] * g.h[2]));
-    const T i2hx = (T)(g.nx > 1 ? 0.5 / g.h[0] : 0.0), i2hy = (T)(0.5 / g.h[1]), i2hz = (T)(0.5 / g.h[2]);
+    const P2Const<T> kc(g, K, m[0]);
     const long t0 = (long)xcd_remap(blockIdx.x, gridDim.x) * tpb;
     for (int it = 0; it < tpb; ++it) {
         const long q = (t0 + it) * kBlock + threadIdx.x;
@@ -264,23 +230,17 @@ __global__ __launch_bounds__(kBlock) void k_P2_point(GridK g, CoupledK K, const 
         const Q4<T> Gxm = ld4(G + nb.xm), Gxp = ld4(G + nb.xp), Gym = ld4(G + nb.ym), Gyp = ld4(G + nb.yp);
         const Q4<T> vxm = ld4(vx + nb.xm), vxp = ld4(vx + nb.xp), vym = ld4(vy + nb.ym), vyp = ld4(vy + nb.yp);
         const T uzm = u[nb.zm], uzp = u[nb.zp], Gzm = G[nb.zm], Gzp = G[nb.zp], vzm = vz[nb.zm], vzp = vz[nb.zp];
-        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0u;
+        const unsigned mk = mask ? ld_mask4(mask, nb.c) : 0xffffffffu;
         Q4<T> oP;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const T uc = uu.v[k], Gc = GG.v[k];
-            const T zum = k > 0 ? uu.v[k - 1] : uzm, zup = k < 3 ? uu.v[k + 1] : uzp;
-            const T zGm = k > 0 ? GG.v[k - 1] : Gzm, zGp = k < 3 ? GG.v[k + 1] : Gzp;
-            const T zvm = k > 0 ? wz.v[k - 1] : vzm, zvp = k < 3 ? wz.v[k + 1] : vzp;
-            T S = lapS_axis(uxm.v[k], uc, uxp.v[k], Gxm.v[k], Gc, Gxp.v[k], ihx);
-            S += lapS_axis(uym.v[k], uc, uyp.v[k], Gym.v[k], Gc, Gyp.v[k], ihy);
-            S += lapS_axis(zum, uc, zup, zGm, Gc, zGp, ihz);
-            const T div = (Gxp.v[k] * uxp.v[k] * vxp.v[k] - Gxm.v[k] * uxm.v[k] * vxm.v[k]) * i2hx +
-                          (Gyp.v[k] * uyp.v[k] * vyp.v[k] - Gym.v[k] * uym.v[k] * vym.v[k]) * i2hy +
-                          (zGp * zup * zvp - zGm * zum * zvm) * i2hz;
-            T p2 = eu * S + B2 * Gc * uc - Gc * Wp(uc) * ieu - gam * Gc * ps.v[k] - Mm * Gc - div;
-            if (mask) p2 = ((mk >> (8 * k)) & 0xffu) ? p2 : (T)0;
-            oP.v[k] = p2;
+            const T un[6] = {uxm.v[k], uxp.v[k], uym.v[k], uyp.v[k], k > 0 ? uu.v[k - 1] : uzm,
+                             k < 3 ? uu.v[k + 1] : uzp};
+            const T Gn[6] = {Gxm.v[k], Gxp.v[k], Gym.v[k], Gyp.v[k], k > 0 ? GG.v[k - 1] : Gzm,
+                             k < 3 ? GG.v[k + 1] : Gzp};
+            const T vn[6] = {vxm.v[k], vxp.v[k], vym.v[k], vyp.v[k], k > 0 ? wz.v[k - 1] : vzm,
+                             k < 3 ? wz.v[k + 1] : vzp};
+            oP.v[k] = p2_point(kc, uu.v[k], GG.v[k], ps.v[k], un, Gn, vn, ((mk >> (8 * k)) & 0xffu) != 0);
         }
         st4(P + nb.c, oP);
     }

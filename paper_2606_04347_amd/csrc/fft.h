@@ -55,7 +55,9 @@ enum PassKind {
     PASS_REDUCE = 16,      // FP64 reductions
     PASS_FIXED_STENCIL = 17,   // fixed model: Chebyshev recurrence and L apply (stencils)
     PASS_FIXED_POINT = 18,     // fixed model: pointwise kernels
-    PASS_KIND_COUNT = 20
+    PASS_Z_R2C_R1 = 19,    // z rows r2c of (P1, W'(phi) - A1 phi) formed in the load (R1 fused)
+    PASS_Z_R2C_P2 = 20,    // z rows r2c of (P2, g u) formed in the load (P2 fused)
+    PASS_KIND_COUNT = 24
 };
 struct PassHook {
     virtual void begin(int kind, hipStream_t s) = 0;

@@ -37,6 +37,34 @@ hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K
                         const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0,
                         c2<T>* X1, c2<T>* X2, hipStream_t s);
 
+// Sources of R1 (Section 3.1) at phi and u: phi, its spectral Laplacian and
+// gradient, u, the band mask (nullable), the device scalar h^3 sum phi and A0.
+template <typename T> struct R1Fields {
+    const T *phi, *lap, *gx, *gy, *gz, *u;
+    const uint8_t* mask;
+    const double* int_phi;
+    double A0;
+};
+// Sources of P2 (Section 3.1): u, G = g+, the velocity, psi = (-Delta_h)^{-1} q,
+// the band mask (nullable) and the device scalar m = h^3 sum q.
+template <typename T> struct P2Fields {
+    const T *u, *G, *vx, *vy, *vz, *psi;
+    const uint8_t* mask;
+    const double* m;
+};
+
+// fwd_pair_etd with the pair (P1, W'(phi) - A1 phi) formed from its sources
+// in the load of the z pass (no R1 fields written or read back).
+template <typename T>
+hipError_t r1_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, const R1Fields<T>& f, EtdStage stage,
+                  c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
+                  hipStream_t s);
+// fwd_pair_etd with the pair (P2, g+ u) formed in the load of the z pass
+// (u stages: X0 receives the inverse x transform of the increment).
+template <typename T>
+hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, const P2Fields<T>& f, EtdStage stage,
+                  c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0, hipStream_t s);
+
 // psi = (-Delta_h)^{-1} q through the FD symbol mu (zero mean mode): forward
 // transform, then the last forward axis is multiplied by 1/mu and inverted in
 // the same pass.  fd: per-axis symbol tables [x (nx) | y (ny) | z (nzh)].

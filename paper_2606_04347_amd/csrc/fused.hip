@@ -9,6 +9,7 @@
 #include "fused.h"
 
 #include "blocksum.h"
+#include "remainders.h"
 #include "zrows.h"
 
 namespace etd {
@@ -317,6 +318,161 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q,
     zrow_forward<T, NR>(lds, stw, twf, Q + row0 * NR, WQ + row0 * MS, nl);
 }
 
+// ------------------------------------------------------------------ z r2c with R1 / P2 producers
+// Row geometry of a z tile (rows row0 .. row0 + L - 1): first point of each
+// row and of its x and y neighbour rows (periodic).
+template <int L> struct RowTile {
+    long c[L], xm[L], xp[L], ym[L], yp[L];
+};
+template <int L> __device__ __forceinline__ void row_tile_setup(RowTile<L>& t, const GridK& g, long row0) {
+    if (threadIdx.x < L) {
+        const long r = min(row0 + (long)threadIdx.x, (long)g.nx * g.ny - 1);
+        const int ix = (int)(r / g.ny), iy = (int)(r % g.ny);
+        const long sx = (long)g.ny * g.nz, sy = g.nz;
+        const long c = r * g.nz;
+        t.c[threadIdx.x] = c;
+        t.xp[threadIdx.x] = c + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
+        t.xm[threadIdx.x] = c + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
+        t.yp[threadIdx.x] = c + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
+        t.ym[threadIdx.x] = c + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
+    }
+}
+template <typename T> __device__ __forceinline__ c2<T> ld2(const T* p) { return *reinterpret_cast<const c2<T>*>(p); }
+
+// (P1, W'(phi) - A1 phi) at the point pair (2e, 2e + 1) of row l: the R1
+// remainder formed where the z transform loads it.
+template <typename T, int L> struct R1PairLoad {
+    static constexpr int NS = 2;
+    const RowTile<L>* rt;
+    int nl, nz;
+    const T *phi, *lap, *gx, *gy, *gz, *u;
+    const uint8_t* mask;
+    R1Const<T> k;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        if (l >= nl) {
+            v[0] = v[1] = mk<T>(0, 0);
+            return;
+        }
+        const long c = rt->c[l], o = 2 * (long)e;
+        const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o), a = ld2(gx + c + o), b = ld2(gy + c + o),
+                    cz = ld2(gz + c + o), uu = ld2(u + c + o);
+        const c2<T> pxm = ld2(phi + rt->xm[l] + o), pxp = ld2(phi + rt->xp[l] + o), pym = ld2(phi + rt->ym[l] + o),
+                    pyp = ld2(phi + rt->yp[l] + o);
+        const c2<T> uxm = ld2(u + rt->xm[l] + o), uxp = ld2(u + rt->xp[l] + o), uym = ld2(u + rt->ym[l] + o),
+                    uyp = ld2(u + rt->yp[l] + o);
+        const long zm = c + (o > 0 ? o - 1 : nz - 1), zp = c + (o + 2 < nz ? o + 2 : 0);
+        const T pzm = phi[zm], pzp = phi[zp], uzm = u[zm], uzp = u[zp];
+        bool b0 = true, b1 = true;
+        if (mask) {
+            b0 = mask[c + o] != 0;
+            b1 = mask[c + o + 1] != 0;
+        }
+        T P0, Q0, P1, Q1;
+        {
+            const T un[6] = {uxm.x, uxp.x, uym.x, uyp.x, uzm, uu.y};
+            const T pn[6] = {pxm.x, pxp.x, pym.x, pyp.x, pzm, p.y};
+            r1_point(k, p.x, L2.x, a.x, b.x, cz.x, uu.x, un, pn, b0, &P0, &Q0);
+        }
+        {
+            const T un[6] = {uxm.y, uxp.y, uym.y, uyp.y, uu.x, uzp};
+            const T pn[6] = {pxm.y, pxp.y, pym.y, pyp.y, p.x, pzp};
+            r1_point(k, p.y, L2.y, a.y, b.y, cz.y, uu.y, un, pn, b1, &P1, &Q1);
+        }
+        v[0] = mk<T>(P0, P1);
+        v[1] = mk<T>(Q0, Q1);
+    }
+    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
+};
+
+// (P2, g+ u) at the point pair (2e, 2e + 1) of row l.
+template <typename T, int L> struct P2PairLoad {
+    static constexpr int NS = 2;
+    const RowTile<L>* rt;
+    int nl, nz;
+    const T *u, *G, *vx, *vy, *vz, *psi;
+    const uint8_t* mask;
+    P2Const<T> k;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        if (l >= nl) {
+            v[0] = v[1] = mk<T>(0, 0);
+            return;
+        }
+        const long c = rt->c[l], o = 2 * (long)e;
+        const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o), ps = ld2(psi + c + o), wz = ld2(vz + c + o);
+        const c2<T> uxm = ld2(u + rt->xm[l] + o), uxp = ld2(u + rt->xp[l] + o), uym = ld2(u + rt->ym[l] + o),
+                    uyp = ld2(u + rt->yp[l] + o);
+        const c2<T> Gxm = ld2(G + rt->xm[l] + o), Gxp = ld2(G + rt->xp[l] + o), Gym = ld2(G + rt->ym[l] + o),
+                    Gyp = ld2(G + rt->yp[l] + o);
+        const c2<T> vxm = ld2(vx + rt->xm[l] + o), vxp = ld2(vx + rt->xp[l] + o), vym = ld2(vy + rt->ym[l] + o),
+                    vyp = ld2(vy + rt->yp[l] + o);
+        const long zm = c + (o > 0 ? o - 1 : nz - 1), zp = c + (o + 2 < nz ? o + 2 : 0);
+        const T uzm = u[zm], uzp = u[zp], Gzm = G[zm], Gzp = G[zp], vzm = vz[zm], vzp = vz[zp];
+        bool b0 = true, b1 = true;
+        if (mask) {
+            b0 = mask[c + o] != 0;
+            b1 = mask[c + o + 1] != 0;
+        }
+        T P0, P1;
+        {
+            const T un[6] = {uxm.x, uxp.x, uym.x, uyp.x, uzm, uu.y};
+            const T Gn[6] = {Gxm.x, Gxp.x, Gym.x, Gyp.x, Gzm, GG.y};
+            const T vn[6] = {vxm.x, vxp.x, vym.x, vyp.x, vzm, wz.y};
+            P0 = p2_point(k, uu.x, GG.x, ps.x, un, Gn, vn, b0);
+        }
+        {
+            const T un[6] = {uxm.y, uxp.y, uym.y, uyp.y, uu.x, uzp};
+            const T Gn[6] = {Gxm.y, Gxp.y, Gym.y, Gyp.y, GG.x, Gzp};
+            const T vn[6] = {vxm.y, vxp.y, vym.y, vyp.y, wz.x, vzp};
+            P1 = p2_point(k, uu.y, GG.y, ps.y, un, Gn, vn, b1);
+        }
+        v[0] = mk<T>(P0, P1);
+        v[1] = mk<T>(GG.x * uu.x, GG.y * uu.y);
+    }
+    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
+};
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gx,
+                                                       const T* gy, const T* gz, const T* u, const uint8_t* mask,
+                                                       const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
+                                                       const c2<T>* __restrict__ twh,
+                                                       const c2<T>* __restrict__ twf, long nrows) {
+    constexpr int L = z_rows<NR>();
+    constexpr int MS = NR / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ RowTile<L> rt;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    row_tile_setup<L>(rt, g, row0);
+    __syncthreads();
+    const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gx, gy, gz, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
+    zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
+                                                       const T* vy, const T* vz, const T* psi, const double* m,
+                                                       const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
+                                                       const c2<T>* __restrict__ twh,
+                                                       const c2<T>* __restrict__ twf, long nrows) {
+    constexpr int L = z_rows<NR>();
+    constexpr int MS = NR / 2 + 1;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ RowTile<L> rt;
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    row_tile_setup<L>(rt, g, row0);
+    __syncthreads();
+    const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0])};
+    zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+}
+
 // two spectra through the same plain line transform, one after the other
 // (each read by its own transform)
 template <typename T, int L> struct PairOp {
@@ -533,6 +689,30 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
                        out, twh, twf, nrows, scale, (T)thr);
     return hipGetLastError();
 }
+template <typename T, int NR>
+hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, c2<T>* WP, c2<T>* WQ,
+                       const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem2<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    hipLaunchKernelGGL((k_z_r2c_r1<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
+                       f.lap, f.gx, f.gy, f.gz, f.u, f.mask, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
+    return hipGetLastError();
+}
+template <typename T, int NR>
+hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ,
+                       const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem2<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_p2<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    hipLaunchKernelGGL((k_z_r2c_p2<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.u,
+                       f.G, f.vx, f.vy, f.vz, f.psi, f.m, f.mask, WP, WQ, twh, twf, nrows);
+    return hipGetLastError();
+}
 template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows<NR>();
@@ -641,24 +821,16 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
     return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, part, int_out, s);
 }
 
+namespace {
+
+// forward y pass of both spectra, then the x pass with the ETD combine and
+// the inverse x transforms (fused.h, fwd_pair_etd)
 template <typename T>
-hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, const T* P,
-                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0,
-                        c2<T>* X1, c2<T>* X2, hipStream_t s) {
-    if (g.nx < 2) return hipErrorInvalidValue;
+hipError_t pair_yx_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, c2<T>* WP,
+                       c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
+                       hipStream_t s) {
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
-    const double rb = sizeof(T) * (double)g.nreal();
-    hipError_t e = timed_pass(PASS_Z_R2C_PAIR, 2.0 * (cb + rb), s, [&]() -> hipError_t {
-        switch (g.nz) {
-#define CASE(n) \
-    case n: return launch_z_pair<T, n>(g, P, Q, WP, WQ, t.tzh, t.tzf, s);
-            ETD_FFT_SIZES(CASE)
-#undef CASE
-            default: return hipErrorInvalidValue;
-        }
-    });
-    if (e != hipSuccess) return e;
-    e = timed_pass(PASS_Y_PAIR, 4.0 * cb, s, [&]() -> hipError_t {
+    hipError_t e = timed_pass(PASS_Y_PAIR, 4.0 * cb, s, [&]() -> hipError_t {
         switch (g.ny) {
 #define CASE(n) \
     case n: return launch_y_pair<T, n>(g, WP, WQ, t.ty, s);
@@ -686,6 +858,69 @@ hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K
         }
         return hipErrorInvalidValue;
     });
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, EtdStage stage, const T* P,
+                        const T* Q, c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0,
+                        c2<T>* X1, c2<T>* X2, hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    hipError_t e = timed_pass(PASS_Z_R2C_PAIR, 2.0 * (cb + rb), s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_pair<T, n>(g, P, Q, WP, WQ, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    return pair_yx_etd<T>(g, t, K, stage, WP, WQ, a, store_out, X0, X1, X2, s);
+}
+
+template <typename T>
+hipError_t r1_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, const R1Fields<T>& f, EtdStage stage,
+                  c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
+                  hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    const double mb = f.mask ? (double)g.nreal() : 0.0;
+    hipError_t e = timed_pass(PASS_Z_R2C_R1, 6.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_r1<T, n>(g, K, f, WP, WQ, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    return pair_yx_etd<T>(g, t, K, stage, WP, WQ, a, store_out, X0, X1, X2, s);
+}
+
+template <typename T>
+hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, const P2Fields<T>& f, EtdStage stage,
+                  c2<T>* WP, c2<T>* WQ, const EtdArgs<T>& a, bool store_out, c2<T>* X0, hipStream_t s) {
+    if (g.nx < 2) return hipErrorInvalidValue;
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    const double mb = f.mask ? (double)g.nreal() : 0.0;
+    hipError_t e = timed_pass(PASS_Z_R2C_P2, 6.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_p2<T, n>(g, K, f, WP, WQ, t.tzh, t.tzf, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    return pair_yx_etd<T>(g, t, K, stage, WP, WQ, a, store_out, X0, nullptr, nullptr, s);
 }
 
 template <typename T>
@@ -772,6 +1007,11 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
 }
 
 #define INST(T)                                                                                                   \
+    template hipError_t r1_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const R1Fields<T>&,         \
+                                  EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*, c2<T>*,      \
+                                  hipStream_t);                                                                   \
+    template hipError_t p2_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const P2Fields<T>&,         \
+                                  EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, hipStream_t);        \
     template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
                                        const T*, T*, double, hipStream_t);                                        \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \

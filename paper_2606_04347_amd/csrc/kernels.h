@@ -48,7 +48,7 @@ void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* 
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* phi_old, const T* phi_new, const T* gx,
                       const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, hipStream_t s);
-// q = g+ (u - ubar) (masked), gu = g+ u; with part != null also the mass
+// q = g+ (u - ubar) (masked), gu = g+ u (gu may be null); with part != null also the mass
 // mass_out[0] = cell * sum q (block partials in part, then a fixed-order final
 // sum; part holds at least kRedBlocks * 4 doubles).
 template <typename T>

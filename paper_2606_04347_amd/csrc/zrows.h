@@ -78,6 +78,48 @@ __device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const
     }
 }
 
+// Forward of two fields at once: Op::NS == 2 and Op::load(l, e, v[2]) gives
+// the pairs (x_{2e}, x_{2e+1}) of both fields in row l (0 for rows l >= nl),
+// so one read of the sources feeds both transforms; field s goes through LDS
+// rows s * L + l; dst0 / dst1 receive the half-spectrum rows.
+template <typename T, int NR> constexpr size_t z_smem2() {
+    return sizeof(c2<T>) * (size_t)(2 * z_rows<NR>() * z_row_stride<NR>() + NR / 2);
+}
+template <typename T, int NR, class Op>
+__device__ __forceinline__ void zrow_forward2(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
+                                              const Op& op, c2<T>* dst0, c2<T>* dst1, int nl) {
+    constexpr int M = NR / 2;
+    constexpr int L = z_rows<NR>();
+    constexpr int LS = z_row_stride<NR>();
+    if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
+        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+            const int r = idx / M, n = idx % M;
+            c2<T> v[2];
+            op.load(r, n, v);
+            lds[r * LS + sk(n)] = v[0];
+            lds[(L + r) * LS + sk(n)] = v[1];
+        }
+        __syncthreads();
+        stockham<T, M, 2 * L, LS, 1, -1>(lds, stw);
+    } else {
+        lines_fft_to_lds<T, M, L, LS, 2, -1, false>(lds, stw, op);
+    }
+    const T half = (T)0.5;
+    for (int idx = threadIdx.x; idx < 2 * L * (M + 1); idx += kThreads) {
+        const int rr = idx / (M + 1), k = idx % (M + 1);
+        const int r = rr % L;
+        if (r < nl) {
+            const c2<T>* row = lds + rr * LS;
+            const c2<T> zk = row[sk(k == M ? 0 : k)];
+            const c2<T> zc = cconj(row[sk(k == 0 ? 0 : M - k)]);
+            const c2<T> ev = cadd(zk, zc);
+            const c2<T> od = csub(zk, zc);
+            const c2<T> wod = cmul(twf[k], od);
+            (rr < L ? dst0 : dst1)[r * (M + 1) + k] = mk<T>(half * (ev.x + wod.y), half * (ev.y - wod.x));
+        }
+    }
+}
+
 // ---- inverse, in three steps so that a kernel with several outputs can fetch
 // the next input while the current one is transformed.
 template <int NR> constexpr int z_fetch_count() { return (z_rows<NR>() * (NR / 2 + 1) + kThreads - 1) / kThreads; }
