@@ -130,7 +130,7 @@ def roofline(passes, pass_steps, n, precision):
 FFT_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
              "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover")
 # z passes with the R1 / P2 stencils formed in their load
-FUSED_STENCIL_KINDS = ("z_r2c_r1", "z_r2c_p2")
+FUSED_STENCIL_KINDS = ("z_r2c_r1", "z_r2c_p2", "z_r2c_q")
 
 
 def ledger(passes, pass_steps, npts, ms_per_step):

@@ -225,7 +225,8 @@ etd_status etd_spectral_apply(etd_plan_t plan, int instance, etd_spectral_op op,
  *  18 fixed model: pointwise kernels
  *  19 z-row r2c of the R1 pair with R1 formed in the load
  *  20 z-row r2c of the (P2, g u) pair with P2 formed in the load
- *  21..23 unused. */
+ *  21 z-row r2c of q = g (u - ubar) formed in the load, with its sum
+ *  22..23 unused. */
 #define ETD_PASS_KINDS 24
 typedef struct {
     int64_t launches[ETD_PASS_KINDS];

@@ -361,9 +361,11 @@ hipError_t remainder_etd_2d(const Instance& I, CoupledView<T>& v, EtdStage st, c
 // gy, gz, lap; on three-dimensional grids also the integral of phi_out).  On
 // three-dimensional grids R1 is formed in the load of the z pass and the x
 // pass of the pair also runs the inverse x transforms of the derivatives.
+// With vel (three-dimensional grids, the last stage of a step) the final
+// derivative pass also writes g+ and the velocity at phi_out.
 template <typename T>
 hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, const uint8_t* mask, EtdStage st,
-                     const EtdArgs<T>& a, T* phi_out, hipStream_t s) {
+                     const EtdArgs<T>& a, T* phi_out, hipStream_t s, const VelocityArgs<T>* vel = nullptr) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     if (g.nx > 1) {
@@ -371,7 +373,7 @@ hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, cons
         hipError_t e = r1_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
         if (e != hipSuccess) return e;
         return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, I.part,
-                                  I.scal + S_INTPHI, s);
+                                  I.scal + S_INTPHI, s, vel);
     }
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
@@ -397,19 +399,21 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const FFTTables<T>& t = tables<T>(I);
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    const bool fused = g.nx > 1;
-    timed_kernel(PASS_POINT, (fused ? 3.0 : 4.0) * fb + mb, s, [&] {
-        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, fused ? nullptr : v.Q, I.part, I.scal + S_MASS, s);
-    });
-    hipError_t e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s);
-    if (e != hipSuccess) return e;
     const EtdArgs<T> a{nullptr, v.Sra, v.Sgu};
-    if (fused) {
+    hipError_t e = hipSuccess;
+    if (g.nx > 1) {
+        // q formed in the load of the nonlocal transform (with m); P2 and g+ u in the load of the pair
+        e = lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, I.part, I.scal + S_MASS, s);
+        if (e != hipSuccess) return e;
         const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
         if (e != hipSuccess) return e;
         return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, s);
     }
+    timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] {
+        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, I.part, I.scal + S_MASS, s);
+    });
+    if ((e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s)) != hipSuccess) return e;
     timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
         coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
     });
@@ -436,16 +440,24 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
     // and (three-dimensional grids) the device scalar the integral of phi^n
     const double fb = (double)sizeof(T) * n;   // one real field
+    // g+ and the velocity at phi^{n+1}: on three-dimensional grids in the last
+    // derivative pass, else a pointwise kernel after it
+    const VelocityArgs<T> va{v.phiA, v.gp, v.vx, v.vy, v.vz, I.K.tau, I.K.thr};
+    const VelocityArgs<T>* vel = g.nx > 1 ? &va : nullptr;
     if (!rk2) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s,
+                                  vel));
     } else {
         HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s,
+                                  vel));
     }
-    // phi^{n+1} and its derivatives are kept for the next step; g+ and the velocity
-    timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
-        coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
-    });
+    // phi^{n+1} and its derivatives are kept for the next step
+    if (!vel) {
+        timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
+            coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
+        });
+    }
     // ---- g u stages with g = g(phi^{n+1})
     // The spectral g u values are kept as increments D over FFT(g+ u^n), so the
     // inverse transforms carry only the per-step change; g+ u^n is added back in

@@ -179,18 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_velocity(GridK g, CoupledK K, const 
     const long n = g.nreal();
     const T itau = (T)(1.0 / K.tau);
     const T thr = (T)K.thr;
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const T p = pn[i];
-        const T G = gloc(p);
-        const T a = gx[i], b = gy[i], c = gz[i];
-        const T gn2 = a * a + b * b + c * c;
-        const bool sel = (G > thr) && (gn2 > (T)0);
-        const T dt = (p - po[i]) * itau;
-        gp[i] = G;
-        vx[i] = sel ? (-dt * a) / gn2 : (T)0;
-        vy[i] = sel ? (-dt * b) / gn2 : (T)0;
-        vz[i] = sel ? (-dt * c) / gn2 : (T)0;
-    }
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
+        velocity_point(itau, thr, pn[i], po[i], gx[i], gy[i], gz[i], &gp[i], &vx[i], &vy[i], &vz[i]);
 }
 
 template <typename T>

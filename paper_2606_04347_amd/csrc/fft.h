@@ -57,6 +57,7 @@ enum PassKind {
     PASS_FIXED_POINT = 18,     // fixed model: pointwise kernels
     PASS_Z_R2C_R1 = 19,    // z rows r2c of (P1, W'(phi) - A1 phi) formed in the load (R1 fused)
     PASS_Z_R2C_P2 = 20,    // z rows r2c of (P2, g u) formed in the load (P2 fused)
+    PASS_Z_R2C_Q = 21,     // z rows r2c of q = g (u - ubar) formed in the load, with its sum
     PASS_KIND_COUNT = 24
 };
 struct PassHook {

@@ -19,11 +19,24 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
                         c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, double* part, double* int_out,
                         hipStream_t s);
 
+// g+ and the velocity of the u equation (Section 3.1) from phi^{n+1} (the
+// field being formed), phi^n = po and the step tau; thr the support threshold.
+template <typename T> struct VelocityArgs {
+    const T* po;
+    T* G;
+    T* vx;
+    T* vy;
+    T* vz;
+    double tau, thr;
+};
+
 // The y and z passes of derivs_fused, for spectra already through the
 // inverse x pass (W0 = X^-1 S, W1 = X^-1 i kx S, W2 = X^-1 (-kx^2) S); W3 work.
+// With vel != null the z pass also writes g+ and the velocity at the new phi.
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s);
+                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s,
+                           const VelocityArgs<T>* vel = nullptr);
 
 // Forward transforms of two real fields P, Q (into the work spectra WP, WQ)
 // and, in the last (x) pass, the ETD combine of the given stage (etd_point.h)
@@ -72,6 +85,13 @@ hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
 template <typename T>
 hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
                         hipStream_t s);
+// The same for q = G (u - ubar) on the band (mask nullable) formed in the load
+// of the z pass, which also forms mass_out[0] = h^d sum q (block partials in
+// part, at most nx * ny / 8 doubles, then a fixed-order final sum).
+template <typename T>
+hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* fd, double ubar, const T* u,
+                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, double* part, double* mass_out,
+                          hipStream_t s);
 
 // U from an increment spectrum D of G U (Section 3.3 after Algorithm 1):
 // d = F^-1 D, out = u_old + d / G where G > thr, G u_old + d elsewhere; the

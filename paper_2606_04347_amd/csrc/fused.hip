@@ -208,10 +208,44 @@ template <typename T> struct DerivZArgs {
     T* lap;
 };
 
-template <typename T, int NR>
-__global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<T>* __restrict__ twh,
-                                                      const c2<T>* __restrict__ twf, long nrows, T scale,
-                                                      double az, double* part) {
+// Store of the gy output with g+ and the velocity of the u equation formed
+// there (velocity_point): phi, gz and gx of the same points were stored by
+// this thread in the earlier transforms of the tile (every transform of a
+// tile maps outputs to threads identically) and are read back, phi^n is read.
+template <typename T, int M> struct VelocityPairStore {
+    static constexpr int NS = 1;
+    c2<T>* gy;          // each: first row of the tile, as pairs
+    const c2<T>* phi;
+    const c2<T>* gz;
+    const c2<T>* gx;
+    const c2<T>* po;
+    c2<T>* G;
+    c2<T>* vx;
+    c2<T>* vy;
+    c2<T>* vz;
+    int nl;
+    T scale, itau, thr;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+        if (l >= nl) return;
+        const long i = (long)l * M + e;
+        const c2<T> b = cscale(v, scale);
+        gy[i] = b;
+        const c2<T> p = phi[i], o = po[i], a = gx[i], c = gz[i];
+        c2<T> g, x, y, w;
+        velocity_point(itau, thr, p.x, o.x, a.x, b.x, c.x, &g.x, &x.x, &y.x, &w.x);
+        velocity_point(itau, thr, p.y, o.y, a.y, b.y, c.y, &g.y, &x.y, &y.y, &w.y);
+        G[i] = g;
+        vx[i] = x;
+        vy[i] = y;
+        vz[i] = w;
+    }
+};
+
+template <typename T, int NR, bool VEL>
+__global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityArgs<T> va,
+                                                      const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
+                                                      long nrows, T scale, double az, double* part) {
     constexpr int L = z_rows<NR>();
     constexpr int MS = NR / 2 + 1;
     constexpr int M = NR / 2;
@@ -240,7 +274,16 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, const c2<
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_fetch<T, NR>(pre, z.C + si, nl);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gy));
+    if constexpr (VEL) {
+        auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
+        auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
+        zrow_inverse_lds<T, NR>(lds, stw, twf,
+                                VelocityPairStore<T, M>{pw(z.gy), pr(z.phi), pr(z.gz), pr(z.gx), pr(va.po), pw(va.G),
+                                                        pw(va.vx), pw(va.vy), pw(va.vz), nl, scale,
+                                                        (T)(1.0 / va.tau), (T)va.thr});
+    } else {
+        zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gy));
+    }
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.lap));
@@ -430,6 +473,57 @@ template <typename T, int L> struct P2PairLoad {
     }
     __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
 };
+
+// q = g+ (u - ubar) on the band (Section 3.1, the nonlocal argument) at the
+// point pair (2e, 2e + 1) of row l, accumulated into this thread's share of
+// the mass sum.
+template <typename T, int M> struct QPairLoad {
+    static constexpr int NS = 1;
+    const T* u;      // first row of the tile
+    const T* G;
+    const uint8_t* mask;
+    int nl;
+    T ubar;
+    Neu& acc;
+    __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
+        if (l >= nl) {
+            v[0] = mk<T>(0, 0);
+            return;
+        }
+        const long i = (long)l * 2 * M + 2 * e;
+        const c2<T> uu = ld2(u + i), GG = ld2(G + i);
+        T q0 = GG.x * (uu.x - ubar), q1 = GG.y * (uu.y - ubar);
+        if (mask) {
+            q0 = mask[i] ? q0 : (T)0;
+            q1 = mask[i + 1] ? q1 : (T)0;
+        }
+        acc.add((double)q0);
+        acc.add((double)q1);
+        v[0] = mk<T>(q0, q1);
+    }
+    __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
+};
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W,
+                                                      const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
+                                                      long nrows, double* part) {
+    constexpr int L = z_rows<NR>();
+    extern __shared__ unsigned char smem_raw[];
+    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+    c2<T>* stw = lds + L * z_row_stride<NR>();
+    load_table<T>(stw, twh, NR / 2);
+    const long row0 = (long)blockIdx.x * L;
+    const int nl = (int)min((long)L, nrows - row0);
+    const long ro = row0 * NR;
+    Neu acc;
+    zrow_forward_op<T, NR>(lds, stw, twf,
+                           QPairLoad<T, NR / 2>{u + ro, G + ro, mask ? mask + ro : nullptr, nl, ubar, acc},
+                           W + row0 * (NR / 2 + 1), nl);
+    __syncthreads();
+    const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
 
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gx,
@@ -661,18 +755,29 @@ template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A,
     hipLaunchKernelGGL((k_deriv_y<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, A, B, C, D, tw);
     return hipGetLastError();
 }
-template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z, const c2<T>* twh,
+template <typename T, int NR, bool VEL>
+void launch_deriv_z_k(int nb, size_t smem, const DerivZArgs<T>& z, const VelocityArgs<T>& va, const c2<T>* twh,
+                      const c2<T>* twf, long nrows, T scale, double az, double* part, hipStream_t s) {
+    static std::once_flag flag;
+    set_smem_limit(k_deriv_z<T, NR, VEL>, smem, flag);
+    hipLaunchKernelGGL((k_deriv_z<T, NR, VEL>), dim3(nb), dim3(kThreads), smem, s, z, va, twh, twf, nrows, scale,
+                       az, part);
+}
+template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z,
+                                                        const VelocityArgs<T>* vel, const c2<T>* twh,
                                                         const c2<T>* twf, double* part, double* int_out,
                                                         hipStream_t s) {
     constexpr int L = z_rows<NR>();
     const size_t smem = z_smem<T, NR>();
-    static std::once_flag flag;
-    set_smem_limit(k_deriv_z<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     const int nb = (int)((nrows + L - 1) / L);
-    hipLaunchKernelGGL((k_deriv_z<T, NR>), dim3(nb), dim3(kThreads), smem, s, z, twh, twf, nrows, scale,
-                       kPi / g.X[2], int_out ? part : nullptr);
+    if (vel)
+        launch_deriv_z_k<T, NR, true>(nb, smem, z, *vel, twh, twf, nrows, scale, kPi / g.X[2],
+                                      int_out ? part : nullptr, s);
+    else
+        launch_deriv_z_k<T, NR, false>(nb, smem, z, VelocityArgs<T>{}, twh, twf, nrows, scale, kPi / g.X[2],
+                                       int_out ? part : nullptr, s);
     if (int_out) reduce_final_sum(part, nb, g.cell, int_out, s);
     return hipGetLastError();
 }
@@ -689,6 +794,21 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
                        out, twh, twf, nrows, scale, (T)thr);
     return hipGetLastError();
 }
+template <typename T, int NR>
+hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W, const c2<T>* twh,
+                      const c2<T>* twf, double* part, double* mass_out, hipStream_t s) {
+    constexpr int L = z_rows<NR>();
+    const size_t smem = z_smem<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_q<T, NR>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    const int nb = (int)((nrows + L - 1) / L);
+    hipLaunchKernelGGL((k_z_r2c_q<T, NR>), dim3(nb), dim3(kThreads), smem, s, u, G, mask, ubar, W, twh, twf, nrows,
+                       part);
+    reduce_final_sum(part, nb, g.cell, mass_out, s);
+    return hipGetLastError();
+}
+
 template <typename T, int NR>
 hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, c2<T>* WP, c2<T>* WQ,
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
@@ -776,7 +896,8 @@ hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, con
 
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s) {
+                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s,
+                           const VelocityArgs<T>* vel) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
@@ -791,10 +912,12 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
     });
     if (e != hipSuccess) return e;
     const DerivZArgs<T> z{W0, W1, W2, W3, phi, gx, gy, gz, lap};
-    return timed_pass(PASS_Z_DERIV, 4.0 * cb + 5.0 * rb, s, [&]() -> hipError_t {
+    // with the velocity: phi^n read, g+ and v written (the read-back of phi,
+    // gz, gx is served by the cache)
+    return timed_pass(PASS_Z_DERIV, 4.0 * cb + (vel ? 10.0 : 5.0) * rb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_deriv_z<T, n>(g, z, t.tzh, t.tzf, part, int_out, s);
+    case n: return launch_deriv_z<T, n>(g, z, vel, t.tzh, t.tzf, part, int_out, s);
             ETD_FFT_SIZES(CASE)
 #undef CASE
             default: return hipErrorInvalidValue;
@@ -818,7 +941,7 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
         }
     });
     if (e != hipSuccess) return e;
-    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, part, int_out, s);
+    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, part, int_out, s, nullptr);
 }
 
 namespace {
@@ -923,12 +1046,14 @@ hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
     return pair_yx_etd<T>(g, t, K, stage, WP, WQ, a, store_out, X0, nullptr, nullptr, s);
 }
 
+namespace {
+
+// the passes of (-Delta_h)^{-1} after the forward z pass: W holds the z
+// transform of q; psi receives the result
 template <typename T>
-hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
-                        hipStream_t s) {
+hipError_t lapinv_after_z(const GridK& g, const FFTTables<T>& t, const double* fd, c2<T>* W, T* psi, hipStream_t s) {
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
-    hipError_t e = fft_pass_z<T>(g, t, true, q, W, (T)1, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     const double* fdx = fd;
     const double* fdy = fd + g.nx;
     const double* fdz = fd + g.nx + g.ny;
@@ -961,6 +1086,36 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
     }
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     return fft_pass_z<T>(g, t, false, W, psi, scale, s);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
+                        hipStream_t s) {
+    hipError_t e = fft_pass_z<T>(g, t, true, q, W, (T)1, s);
+    if (e != hipSuccess) return e;
+    return lapinv_after_z<T>(g, t, fd, W, psi, s);
+}
+
+template <typename T>
+hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* fd, double ubar, const T* u,
+                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, double* part, double* mass_out,
+                          hipStream_t s) {
+    const double cb = 2.0 * sizeof(T) * (double)g.nspec();
+    const double rb = sizeof(T) * (double)g.nreal();
+    const double mb = mask ? (double)g.nreal() : 0.0;
+    hipError_t e = timed_pass(PASS_Z_R2C_Q, 2.0 * rb + mb + cb, s, [&]() -> hipError_t {
+        switch (g.nz) {
+#define CASE(n) \
+    case n: return launch_z_q<T, n>(g, u, G, mask, (T)ubar, W, t.tzh, t.tzf, part, mass_out, s);
+            ETD_FFT_SIZES(CASE)
+#undef CASE
+            default: return hipErrorInvalidValue;
+        }
+    });
+    if (e != hipSuccess) return e;
+    return lapinv_after_z<T>(g, t, fd, W, psi, s);
 }
 
 template <typename T>
@@ -1020,11 +1175,14 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
                                         const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*,        \
                                         c2<T>*, hipStream_t);                                                     \
     template hipError_t derivs_fused_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, c2<T>*, c2<T>*, c2<T>*, T*, \
-                                           T*, T*, T*, T*, double*, double*, hipStream_t);                        \
+                                           T*, T*, T*, T*, double*, double*, hipStream_t,                         \
+                                           const VelocityArgs<T>*);                                               \
     template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
                                           double, hipStream_t);                                                   \
     template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
-                                        hipStream_t);
+                                        hipStream_t);                                                             \
+    template hipError_t lapinv_q_fused<T>(const GridK&, const FFTTables<T>&, const double*, double, const T*,     \
+                                          const T*, const uint8_t*, c2<T>*, T*, double*, double*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -45,23 +45,27 @@ template <typename T, int M> struct RowPairStore {
 // Forward: real rows src (nl <= L of them) -> half-spectrum rows dst (stride
 // M + 1).  stw: the M twiddles in LDS.  On entry the LDS rows are free; on
 // exit they still hold Z (callers barrier before reusing them).
-template <typename T, int NR>
-__device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
-                                             const T* src_rows, c2<T>* dst, int nl) {
+// Forward of one field whose pairs come from Op::load(l, e, v) (NS == 1; 0
+// for rows l >= nl): a field read from memory (RowPairLoad) or formed in the
+// load.
+template <typename T, int NR, class Op>
+__device__ __forceinline__ void zrow_forward_op(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
+                                                const Op& op, c2<T>* dst, int nl) {
     constexpr int M = NR / 2;
     constexpr int L = z_rows<NR>();
     constexpr int LS = z_row_stride<NR>();
-    const c2<T>* src = reinterpret_cast<const c2<T>*>(src_rows);
     if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
         for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
             const int r = idx / M, n = idx % M;
-            lds[r * LS + sk(n)] = (r < nl) ? src[idx] : mk<T>(0, 0);
+            c2<T> v[1];
+            op.load(r, n, v);
+            lds[r * LS + sk(n)] = v[0];
         }
         __syncthreads();
         stockham<T, M, L, LS, 1, -1>(lds, stw);
     } else {
-        // first stage straight from the real rows
-        lines_fft_to_lds<T, M, L, LS, 1, -1, false>(lds, stw, RowPairLoad<T, M>{src, nl});
+        // first stage straight from the loads
+        lines_fft_to_lds<T, M, L, LS, 1, -1, false>(lds, stw, op);
     }
     const T half = (T)0.5;
     for (int idx = threadIdx.x; idx < L * (M + 1); idx += kThreads) {
@@ -76,6 +80,13 @@ __device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const
             dst[idx] = mk<T>(half * (ev.x + wod.y), half * (ev.y - wod.x));
         }
     }
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
+                                             const T* src_rows, c2<T>* dst, int nl) {
+    zrow_forward_op<T, NR>(lds, stw, twf, RowPairLoad<T, NR / 2>{reinterpret_cast<const c2<T>*>(src_rows), nl}, dst,
+                           nl);
 }
 
 // Forward of two fields at once: Op::NS == 2 and Op::load(l, e, v[2]) gives

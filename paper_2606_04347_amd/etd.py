@@ -35,7 +35,7 @@ AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), (
 PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
               "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover",
               "band", "r1_stencil", "p2_stencil", "pointwise", "reduce", "fixed_stencil", "fixed_pointwise",
-              "z_r2c_r1", "z_r2c_p2")
+              "z_r2c_r1", "z_r2c_p2", "z_r2c_q")
 N_PASS_SLOTS = 24
 
 
