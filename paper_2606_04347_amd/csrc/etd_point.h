@@ -30,7 +30,9 @@ __device__ __forceinline__ double phi2d(double z) {
 
 // FP32 forms for the FP32 path: the argument z = tau l(k^2) is formed in FP64
 // and rounded, the exponential parts in FP32 (series with compile-time
-// coefficients 1/(j+k)! for |z| < 0.1, 7 terms, truncation < 3e-12).
+// coefficients 1/(j+k)! for |z| < 0.1, 7 terms, truncation < 3e-12); the
+// quotients of the closed forms by the hardware reciprocal (1 ulp) and a
+// multiply.
 template <int K>
 __device__ __forceinline__ float phi_taylor_f(float z) {
     constexpr double f0 = (K == 1) ? 1.0 : 0.5;   // 1 / k!
@@ -42,9 +44,11 @@ __device__ __forceinline__ float phi_taylor_f(float z) {
     const float y = -z;
     return c0 + y * (c1 + y * (c2 + y * (c3 + y * (c4 + y * (c5 + y * c6)))));
 }
-__device__ __forceinline__ float phi1f(float z) { return fabsf(z) < 0.1f ? phi_taylor_f<1>(z) : -expm1f(-z) / z; }
+__device__ __forceinline__ float phi1f(float z) {
+    return fabsf(z) < 0.1f ? phi_taylor_f<1>(z) : -expm1f(-z) * __builtin_amdgcn_rcpf(z);
+}
 __device__ __forceinline__ float phi2f(float z) {
-    return fabsf(z) < 0.1f ? phi_taylor_f<2>(z) : (expm1f(-z) + z) / (z * z);
+    return fabsf(z) < 0.1f ? phi_taylor_f<2>(z) : (expm1f(-z) + z) * __builtin_amdgcn_rcpf(z * z);
 }
 
 // linear symbols (eqn:linear_force and the u equation)

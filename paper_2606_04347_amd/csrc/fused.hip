@@ -623,6 +623,7 @@ template <int ST, typename T, int L, int LS> struct EtdXOp {
     const CoupledK* K;
     EtdArgs<T> a;
     c2<T>* lds;
+    const double* kyz;   // ly^2 + lz^2 of each line of the tile
     int store_out;
     __device__ __forceinline__ void load(int l, int e, In& in) const {
         if constexpr (kCache) {
@@ -640,8 +641,8 @@ template <int ST, typename T, int L, int LS> struct EtdXOp {
         const long b = t->base[l];
         c2<T> r = mk<T>(0, 0);
         if (b >= 0) {
-            const double lx = ax * lam_index(e, nx), ly = ay * lam_index(t->o[l], ny), lz = az * t->c[l];
-            const double k2 = lx * lx + ly * ly + lz * lz;
+            const double lx = ax * lam_index(e, nx);
+            const double k2 = lx * lx + kyz[l];
             r = etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a);
             if (store_out) a.out[b + (long)e * es] = r;
         }
@@ -661,16 +662,22 @@ __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
+    __shared__ double kyz[L];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * LS;
     load_table<T>(stw, tw, N);
     tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
+    if (threadIdx.x < L) {   // the entries tile_setup wrote in this thread
+        const double ly = (kPi / g.X[1]) * lam_index(tile.o[threadIdx.x], g.ny);
+        const double lz = (kPi / g.X[2]) * tile.c[threadIdx.x];
+        kyz[threadIdx.x] = ly * ly + lz * lz;
+    }
     __syncthreads();
     const long es = (long)g.ny * g.nzh;
     lines_fft_seq_joint<T, N, L, -1, true>(
         lds, stw,
         EtdXOp<ST, T, L, LS>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K, a, lds,
-                             store_out});
+                             kyz, store_out});
     __syncthreads();
     if constexpr (ST == ETD_STAGE_PHI1 || ST == ETD_STAGE_PHI2) {
         lines_fft_seq<T, N, L, +1, true, DerivXOp<T, L, LS>, true>(

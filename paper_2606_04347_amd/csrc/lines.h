@@ -46,7 +46,7 @@ __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
             dftR<T, R, DIR>(v[s]);
             c2<T>* dst = lds + (s * L + l) * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[sk(j * R + r)] = v[s][r];
+            for (int r = 0; r < R; ++r) dst[sk_add<16 % R == 0>(j * R, sk(j * R), r)] = v[s][r];
         }
     }
     __syncthreads();
@@ -65,7 +65,7 @@ __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, co
         const c2<T>* src = lds + ll * LS;
         c2<T> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[sk(j + r * SP)];
+        for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
 #pragma unroll
         for (int r = 1; r < R; ++r) {
             c2<T> w = tw[r * j];
@@ -196,7 +196,7 @@ __device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, cons
                 dftR<T, R0, DIR>(v);
                 c2<T>* dst = lds + l * LS;
 #pragma unroll
-                for (int r = 0; r < R0; ++r) dst[sk(j * R0 + r)] = v[r];
+                for (int r = 0; r < R0; ++r) dst[sk_add<16 % R0 == 0>(j * R0, sk(j * R0), r)] = v[r];
             }
         }
         __syncthreads();
@@ -270,7 +270,7 @@ __device__ __forceinline__ void last_stage_stash(const c2<T>* lds, const c2<T>* 
             const c2<T>* src = lds + l * LS;
             c2<T> v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = src[sk(j + r * SP)];
+            for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 c2<T> w = tw[r * j];
@@ -350,7 +350,7 @@ __device__ __forceinline__ void seq_joint_transforms(c2<T>* lds, const c2<T>* tw
                 dftR<T, R0, DIR>(v);
                 c2<T>* dst = lds + l * LS;
 #pragma unroll
-                for (int r = 0; r < R0; ++r) dst[sk(j * R0 + r)] = v[r];
+                for (int r = 0; r < R0; ++r) dst[sk_add<16 % R0 == 0>(j * R0, sk(j * R0), r)] = v[r];
             }
         }
         __syncthreads();
@@ -403,7 +403,7 @@ __device__ __forceinline__ void last_stage_joint(const c2<T>* lds, const c2<T>* 
         for (int s = 0; s < NS; ++s) {
             const c2<T>* src = lds + (s * L + l) * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[s][r] = src[sk(j + r * SP)];
+            for (int r = 0; r < R; ++r) v[s][r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 c2<T> w = tw[r * j];

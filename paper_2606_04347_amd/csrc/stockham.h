@@ -89,6 +89,16 @@ template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(c2<T>
 __host__ __device__ __forceinline__ constexpr int sk(int e) { return e + (e >> 4); }
 template <int N> constexpr int line_stride() { return N + (N >> 4) + 1; }
 
+// sk(a + c) = sk(a) + sk(c) whenever (a mod 16) + (c mod 16) < 16 (no carry
+// into the pad count), so the slot of a + c is a constant offset from that of
+// a and the LDS access takes it as an immediate.  NC = true only where the
+// caller's (a, c) satisfy that for every c it passes.
+template <bool NC> __device__ __forceinline__ int sk_add(int a, int ska, int c) {
+    if constexpr (NC) return ska + sk(c);
+    else return sk(a + c);
+}
+constexpr bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
 // One radix-R Stockham stage on L lines of length N in LDS (line stride LS).
 template <typename T, int N, int L, int LS, int R, int NS, int DIR>
 __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
@@ -103,8 +113,9 @@ __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
         if ((NB % kThreads == 0) || b < NB) {
             const int l = b / NR, j = b % NR;
             const c2<T>* src = lds + l * LS;
+            const int skj = sk(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[sk(j + r * NR)];
+            for (int r = 0; r < R; ++r) v[i][r] = src[sk_add<NR % 16 == 0>(j, skj, r * NR)];
             if constexpr (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
@@ -126,8 +137,10 @@ __device__ __forceinline__ void stage(c2<T>* lds, const c2<T>* tw) {
             const int k = j % NS;
             c2<T>* dst = lds + l * LS;
             const int o = (j / NS) * NS * R + k;
+            const int sko = sk(o);
+            // o mod 16 + (r NS) mod 16 < 16 when NS and R are powers of two
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[sk(o + r * NS)] = v[i][r];
+            for (int r = 0; r < R; ++r) dst[sk_add<pow2(NS) && pow2(R)>(o, sko, r * NS)] = v[i][r];
         }
     }
     __syncthreads();
