@@ -212,6 +212,33 @@ def fixed_measure(n, warmup):
                      "energy_start": e0, "energy_end": e1, "mass_start": mass0, "mass_end": d["mass"],
                      "ledger": ledger(passes, 2, n ** 3, ms)}
         plan.close()
+    out["frozen_coupled"] = frozen_measure(n, out["fp64"]["B"], nsteps)
+    return out
+
+
+def frozen_measure(n, B2, nsteps):
+    """The coupled scheme's u stages on the same frozen sphere (ETD_F_FROZEN_MEMBRANE,
+    ETDRK2, B2 = the fixed scheme's B, B1 = 1, tau = 0.02): throughput, bounds
+    and the u part of the coupled energy, beside the localization split above."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    ci = inputs.frozen_sphere(n=n, B2=B2, tau=0.02)
+    out = {"workload": f"coupled u stages on a frozen sphere, {n}^3 on [-1,1)^3, ETDRK2, B2={B2:.6g}, B1=1, "
+                       f"tau=0.02, {nsteps} steps"}
+    for prec, name, dt in ((etd.FP64, "fp64", torch.float64), (etd.FP32, "fp32", torch.float32)):
+        plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=prec, flags=etd.F_FROZEN_MEMBRANE))
+        plan.set_state(0, torch.as_tensor(ci.phi0, dtype=dt, device="cuda"),
+                       torch.as_tensor(ci.u0, dtype=dt, device="cuda"))
+        e = plan.energy(0)
+        e0 = e["E_ok"] + e["E_nonlocal"] + e["E_mass"]
+        ms = timed_steps(plan, nsteps, 0) / nsteps
+        d = plan.diagnostics(0)
+        e = plan.energy(0)
+        out[name] = {"value": n ** 3 / (ms * 1e-3), "unit": "grid-pt steps/s", "ms_per_step": ms, "steps": nsteps,
+                     "umin": d["umin"], "umax": d["umax"], "energy_u_start": e0,
+                     "energy_u_end": e["E_ok"] + e["E_nonlocal"] + e["E_mass"]}
+        plan.close()
     return out
 
 
@@ -377,7 +404,12 @@ def main():
     if not a.no_fixed:
         out["fixed"] = fixed_measure(a.fixed_n, a.warmup)
         log(f"fixed {a.fixed_n}^3: fp64 {out['fixed']['fp64']['ms_per_step']:.3f} ms/step, "
-            f"fp32-fft {out['fixed']['fp32_fft']['ms_per_step']:.3f} ms/step")
+            f"fp32-fft {out['fixed']['fp32_fft']['ms_per_step']:.3f} ms/step, U in "
+            f"[{out['fixed']['fp64']['umin']:.4g}, {out['fixed']['fp64']['umax']:.4g}]")
+        fz = out["fixed"]["frozen_coupled"]
+        log(f"frozen-membrane coupled u stages {a.fixed_n}^3: fp64 {fz['fp64']['ms_per_step']:.3f} ms/step, "
+            f"fp32 {fz['fp32']['ms_per_step']:.3f} ms/step, U in [{fz['fp64']['umin']:.4g}, {fz['fp64']['umax']:.4g}], "
+            f"E_u {fz['fp64']['energy_u_start']:.6g} -> {fz['fp64']['energy_u_end']:.6g}")
     if not a.no_batch:
         out["batched"] = batch_measure(a.batch_steps, a.warmup)
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "

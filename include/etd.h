@@ -99,6 +99,11 @@ typedef struct {
 /* flags */
 #define ETD_F_MASS_PROJECT 0x1u   /* after each step, shift U on {g > recover_threshold}
                                       so that <g U, 1>_h keeps its value from set_state */
+#define ETD_F_FROZEN_MEMBRANE 0x2u /* coupled model only: phi keeps its set_state value and
+                                      each step runs only the g u stages of Algorithm 1
+                                      with g = g(phi) and v = 0 (the stabilized spectral
+                                      scheme of Section 3.1 on a fixed membrane); other
+                                      models reject it with ETD_E_ARG */
 
 /* One simulation instance. */
 typedef struct {

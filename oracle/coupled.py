@@ -33,6 +33,9 @@ Readings (ambiguity register; listed in the design notes):
   * the phi stages freeze u at u^n; the u stages use g(phi^{n+1}) and restart
     from FFT(g(phi^{n+1}) u^n) (Section 3.3);
   * A0 = int phi^0 when ``A0_from_initial``;
+  * ``frozen_membrane``: phi keeps its initial value and only the g u
+    stages run, with g = g(phi^0) and v = 0 (the stabilized scheme of
+    Section 3.1 on a fixed membrane);
   * with a narrow band (mask from |2 phi - 1| < threshold, rebuilt every
     ``band_rebuild_every`` steps from the current phi), P2, the nonlocal input
     g (u - ubar) and the three |grad phi|-weighted terms of P1 are zero off the
@@ -54,12 +57,14 @@ from .core import Grid
 class CoupledOracle:
     def __init__(self, grid: Grid, p, tau: float, scheme: int = 2,
                  recover_threshold: float = 1e-3, band_threshold: float = 0.0,
-                 band_rebuild_every: int = 10, mass_projection: bool = False):
+                 band_rebuild_every: int = 10, mass_projection: bool = False,
+                 frozen_membrane: bool = False):
         self.grid, self.p, self.tau, self.scheme = grid, p, float(tau), int(scheme)
         self.thr = float(recover_threshold)
         self.band_thr = float(band_threshold)
         self.band_every = max(1, int(band_rebuild_every))
         self.mass_projection = bool(mass_projection)
+        self.frozen = bool(frozen_membrane)
         k2 = core.ksq(grid)
         self.k2 = k2
         self.kd = [core.kder(grid, d) for d in range(grid.dim)]
@@ -144,18 +149,24 @@ class CoupledOracle:
         if self.band_thr > 0.0 and self.n % self.band_every == 0:
             self.mask = band_mask(phi_n, self.band_thr)
         u = self.u
-        # phi update, u frozen at u^n
-        R1a = self.R1_hat(self.phi_hat, u)
-        phit_hat = self.E0p * self.phi_hat + tau * self.E1p * R1a
-        if self.scheme == 1:
-            phi_new_hat = phit_hat
+        if self.frozen:
+            # fixed membrane: phi^{n+1} = phi^n, so g+ = g(phi^n) and v = 0
+            phi_new_hat = self.phi_hat
+            g_new = core.g_loc(phi_n)
+            v = [np.zeros_like(u) for _ in range(self.grid.dim)]
         else:
-            R1b = self.R1_hat(phit_hat, u)
-            phi_new_hat = phit_hat + tau * self.E2p * (R1b - R1a)
-        phi_new = core.ifft(phi_new_hat)
-        g_new = core.g_loc(phi_new)
+            # phi update, u frozen at u^n
+            R1a = self.R1_hat(self.phi_hat, u)
+            phit_hat = self.E0p * self.phi_hat + tau * self.E1p * R1a
+            if self.scheme == 1:
+                phi_new_hat = phit_hat
+            else:
+                R1b = self.R1_hat(phit_hat, u)
+                phi_new_hat = phit_hat + tau * self.E2p * (R1b - R1a)
+            phi_new = core.ifft(phi_new_hat)
+            g_new = core.g_loc(phi_new)
+            v = self.velocity(phi_n, phi_new_hat, g_new)
         # g u update with g = g(phi^{n+1})
-        v = self.velocity(phi_n, phi_new_hat, g_new)
         GU0 = core.fft(g_new * u)
         R2a = self.R2_hat(u, g_new, v)
         GUt_hat = self.E0u * GU0 + tau * self.E1u * R2a

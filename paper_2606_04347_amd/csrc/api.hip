@@ -59,6 +59,10 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
         msg = "band_threshold must be finite and >= 0"; return ETD_E_ARG;
     }
     if (d.band_threshold > 0.0 && d.band_rebuild_every < 1) { msg = "band_rebuild_every must be >= 1"; return ETD_E_ARG; }
+    if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE)) { msg = "unknown flag bits"; return ETD_E_ARG; }
+    if ((d.flags & ETD_F_FROZEN_MEMBRANE) && d.model != ETD_COUPLED) {
+        msg = "ETD_F_FROZEN_MEMBRANE applies to the coupled model only"; return ETD_E_ARG;
+    }
     long total = 1;
     for (int k = 0; k < d.grid.dim; ++k) total *= d.grid.n[k];
     if (total >= (1L << 31)) { msg = "grid too large for int32 band indices"; return ETD_E_SIZE; }
@@ -312,6 +316,9 @@ template <typename T> struct CoupledView {
     }
 };
 
+// Grid sum of cell-weighted values into a device scalar slot.
+GridSum grid_sum(const Instance& I, int slot) { return GridSum{I.part, I.scal + slot, I.g.cell}; }
+
 template <typename T> const FFTTables<T>& tables(const Instance& I);
 template <> const FFTTables<float>& tables<float>(const Instance& I) { return I.tf; }
 template <> const FFTTables<double>& tables<double>(const Instance& I) { return I.td; }
@@ -324,9 +331,10 @@ template <typename T>
 hipError_t phi_and_derivs(const Instance& I, CoupledView<T>& v, const c2<T>* S, T* phi, hipStream_t s) {
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
-    if (g.nx > 1)
-        return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, I.part,
-                               I.scal + S_INTPHI, s);
+    if (g.nx > 1) {
+        const GridSum isum = grid_sum(I, S_INTPHI);
+        return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, &isum, s);
+    }
     hipError_t e = fft_c2r_3d<T>(g, t, S, v.Stmp, phi, s);
     if (e != hipSuccess) return e;
     const SpecOp ops[4] = {SPEC_NEG_K2, SPEC_IKX, SPEC_IKY, SPEC_IKZ};
@@ -372,8 +380,9 @@ hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, cons
         const R1Fields<T> f{phi_in, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0};
         hipError_t e = r1_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
         if (e != hipSuccess) return e;
-        return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, I.part,
-                                  I.scal + S_INTPHI, s, vel);
+        const GridSum isum = grid_sum(I, S_INTPHI);
+        return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, &isum, s,
+                                  vel);
     }
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
@@ -403,7 +412,7 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     hipError_t e = hipSuccess;
     if (g.nx > 1) {
         // q formed in the load of the nonlocal transform (with m); P2 and g+ u in the load of the pair
-        e = lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, I.part, I.scal + S_MASS, s);
+        e = lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, grid_sum(I, S_MASS), s);
         if (e != hipSuccess) return e;
         const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
@@ -440,20 +449,22 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // ---- phi stages (u frozen at u^n); phiA holds phi^n, lap/gx/gy/gz its derivatives
     // and (three-dimensional grids) the device scalar the integral of phi^n
     const double fb = (double)sizeof(T) * n;   // one real field
+    // frozen membrane: phi, g+ = g(phi) and v = 0 stay as set_state left them
+    const bool frozen = (I.d.flags & ETD_F_FROZEN_MEMBRANE) != 0;
     // g+ and the velocity at phi^{n+1}: on three-dimensional grids in the last
     // derivative pass, else a pointwise kernel after it
     const VelocityArgs<T> va{v.phiA, v.gp, v.vx, v.vy, v.vz, I.K.tau, I.K.thr};
     const VelocityArgs<T>* vel = g.nx > 1 ? &va : nullptr;
-    if (!rk2) {
+    if (!frozen && !rk2) {
         HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s,
                                   vel));
-    } else {
+    } else if (!frozen) {
         HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
         HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s,
                                   vel));
     }
     // phi^{n+1} and its derivatives are kept for the next step
-    if (!vel) {
+    if (!vel && !frozen) {
         timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
             coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
         });
@@ -475,7 +486,7 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
             mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
         });
     }
-    std::swap(I.phiA, I.phiB);
+    if (!frozen) std::swap(I.phiA, I.phiB);
     HIPCHK(plan, hipGetLastError());
     return ETD_OK;
 }
@@ -593,6 +604,9 @@ template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, 
     HIPCHK(plan, phi_and_derivs<T>(I, v, v.Sphi, v.phiA, s));   // 3D: also the integral of phi
     if (g.nx == 1) reduce_sum<T>(n, v.phiA, g.cell, I.part, I.scal + S_INTPHI, s);
     gloc_field<T>(n, v.phiA, v.gp, s);
+    if (I.d.flags & ETD_F_FROZEN_MEMBRANE) {   // v = 0 for every step
+        for (T* f : {v.vx, v.vy, v.vz}) HIPCHK(plan, hipMemsetAsync(f, 0, n * sizeof(T), s));
+    }
     mass_project_sums<T>(n, v.gp, v.u, I.K.thr, I.part, I.scal + S_MPS, s);
     double host[3] = {0, 0, 0};
     HIPCHK(plan, hipMemcpyAsync(host, I.scal + S_INTPHI, sizeof(double), hipMemcpyDeviceToHost, s));

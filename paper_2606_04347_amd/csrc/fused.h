@@ -11,13 +11,12 @@ namespace etd {
 // and spectral Laplacian lap (Section 3.2), in three passes: inverse x lines
 // (S -> S, i kx S, -kx^2 S), inverse y lines (3 -> 4 spectra), z rows c2r
 // (4 spectra -> 5 real fields).  W0..W3: complex work arrays (nspec each); S
-// is preserved.  With int_out != null the z pass also forms the integral
-// int_out[0] = h^3 sum phi (block partials in part, nx * ny / 8 doubles at
-// most, then a fixed-order final sum).
+// is preserved.  With isum != null the z pass also forms the integral
+// h^3 sum phi into isum->out (block partials in isum->part, nx * ny / 8
+// doubles at most, then a fixed-order final sum).
 template <typename T>
 hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, double* part, double* int_out,
-                        hipStream_t s);
+                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s);
 
 // g+ and the velocity of the u equation (Section 3.1) from phi^{n+1} (the
 // field being formed), phi^n = po and the step tau; thr the support threshold.
@@ -35,7 +34,7 @@ template <typename T> struct VelocityArgs {
 // With vel != null the z pass also writes g+ and the velocity at the new phi.
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s,
+                           T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s,
                            const VelocityArgs<T>* vel = nullptr);
 
 // Forward transforms of two real fields P, Q (into the work spectra WP, WQ)
@@ -86,12 +85,12 @@ template <typename T>
 hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd, const T* q, c2<T>* W, T* psi,
                         hipStream_t s);
 // The same for q = G (u - ubar) on the band (mask nullable) formed in the load
-// of the z pass, which also forms mass_out[0] = h^d sum q (block partials in
-// part, at most nx * ny / 8 doubles, then a fixed-order final sum).
+// of the z pass, which also forms the mass h^d sum q into msum.out (block
+// partials in msum.part, at most nx * ny / 8 doubles, then a fixed-order
+// final sum).
 template <typename T>
 hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* fd, double ubar, const T* u,
-                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, double* part, double* mass_out,
-                          hipStream_t s);
+                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, const GridSum& msum, hipStream_t s);
 
 // U from an increment spectrum D of G U (Section 3.3 after Algorithm 1):
 // d = F^-1 D, out = u_old + d / G where G > thr, G u_old + d elsewhere; the

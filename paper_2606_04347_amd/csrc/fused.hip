@@ -772,20 +772,19 @@ void launch_deriv_z_k(int nb, size_t smem, const DerivZArgs<T>& z, const Velocit
 }
 template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z,
                                                         const VelocityArgs<T>* vel, const c2<T>* twh,
-                                                        const c2<T>* twf, double* part, double* int_out,
-                                                        hipStream_t s) {
+                                                        const c2<T>* twf, const GridSum* isum, hipStream_t s) {
     constexpr int L = z_rows<NR>();
     const size_t smem = z_smem<T, NR>();
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     const int nb = (int)((nrows + L - 1) / L);
+    double* part = isum ? isum->part : nullptr;
     if (vel)
-        launch_deriv_z_k<T, NR, true>(nb, smem, z, *vel, twh, twf, nrows, scale, kPi / g.X[2],
-                                      int_out ? part : nullptr, s);
+        launch_deriv_z_k<T, NR, true>(nb, smem, z, *vel, twh, twf, nrows, scale, kPi / g.X[2], part, s);
     else
-        launch_deriv_z_k<T, NR, false>(nb, smem, z, VelocityArgs<T>{}, twh, twf, nrows, scale, kPi / g.X[2],
-                                       int_out ? part : nullptr, s);
-    if (int_out) reduce_final_sum(part, nb, g.cell, int_out, s);
+        launch_deriv_z_k<T, NR, false>(nb, smem, z, VelocityArgs<T>{}, twh, twf, nrows, scale, kPi / g.X[2], part,
+                                       s);
+    if (isum) reduce_final_sum(isum->part, nb, isum->scale, isum->out, s);
     return hipGetLastError();
 }
 template <typename T, int NR>
@@ -803,7 +802,7 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
 }
 template <typename T, int NR>
 hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W, const c2<T>* twh,
-                      const c2<T>* twf, double* part, double* mass_out, hipStream_t s) {
+                      const c2<T>* twf, const GridSum& msum, hipStream_t s) {
     constexpr int L = z_rows<NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
@@ -811,8 +810,8 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
     const long nrows = (long)g.nx * g.ny;
     const int nb = (int)((nrows + L - 1) / L);
     hipLaunchKernelGGL((k_z_r2c_q<T, NR>), dim3(nb), dim3(kThreads), smem, s, u, G, mask, ubar, W, twh, twf, nrows,
-                       part);
-    reduce_final_sum(part, nb, g.cell, mass_out, s);
+                       msum.part);
+    reduce_final_sum(msum.part, nb, msum.scale, msum.out, s);
     return hipGetLastError();
 }
 
@@ -903,7 +902,7 @@ hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, con
 
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, double* part, double* int_out, hipStream_t s,
+                           T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s,
                            const VelocityArgs<T>* vel) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
@@ -924,7 +923,7 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
     return timed_pass(PASS_Z_DERIV, 4.0 * cb + (vel ? 10.0 : 5.0) * rb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_deriv_z<T, n>(g, z, vel, t.tzh, t.tzf, part, int_out, s);
+    case n: return launch_deriv_z<T, n>(g, z, vel, t.tzh, t.tzf, isum, s);
             ETD_FFT_SIZES(CASE)
 #undef CASE
             default: return hipErrorInvalidValue;
@@ -934,8 +933,7 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
 
 template <typename T>
 hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, double* part, double* int_out,
-                        hipStream_t s) {
+                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     hipError_t e = timed_pass(PASS_X_DERIV, 4.0 * cb, s, [&]() -> hipError_t {
@@ -948,7 +946,7 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
         }
     });
     if (e != hipSuccess) return e;
-    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, part, int_out, s, nullptr);
+    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, isum, s, nullptr);
 }
 
 namespace {
@@ -1107,7 +1105,7 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
 
 template <typename T>
 hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* fd, double ubar, const T* u,
-                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, double* part, double* mass_out,
+                          const T* G, const uint8_t* mask, c2<T>* W, T* psi, const GridSum& msum,
                           hipStream_t s) {
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
@@ -1115,7 +1113,7 @@ hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* f
     hipError_t e = timed_pass(PASS_Z_R2C_Q, 2.0 * rb + mb + cb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_z_q<T, n>(g, u, G, mask, (T)ubar, W, t.tzh, t.tzf, part, mass_out, s);
+    case n: return launch_z_q<T, n>(g, u, G, mask, (T)ubar, W, t.tzh, t.tzf, msum, s);
             ETD_FFT_SIZES(CASE)
 #undef CASE
             default: return hipErrorInvalidValue;
@@ -1177,19 +1175,19 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
     template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
                                        const T*, T*, double, hipStream_t);                                        \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
-                                        c2<T>*, T*, T*, T*, T*, T*, double*, double*, hipStream_t);               \
+                                        c2<T>*, T*, T*, T*, T*, T*, const GridSum*, hipStream_t);                 \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
                                         const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*,        \
                                         c2<T>*, hipStream_t);                                                     \
     template hipError_t derivs_fused_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, c2<T>*, c2<T>*, c2<T>*, T*, \
-                                           T*, T*, T*, T*, double*, double*, hipStream_t,                         \
+                                           T*, T*, T*, T*, const GridSum*, hipStream_t,                           \
                                            const VelocityArgs<T>*);                                               \
     template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
                                           double, hipStream_t);                                                   \
     template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
                                         hipStream_t);                                                             \
     template hipError_t lapinv_q_fused<T>(const GridK&, const FFTTables<T>&, const double*, double, const T*,     \
-                                          const T*, const uint8_t*, c2<T>*, T*, double*, double*, hipStream_t);
+                                          const T*, const uint8_t*, c2<T>*, T*, const GridSum&, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -15,6 +15,14 @@ struct CoupledK {
     double thr;                // recovery threshold on g
 };
 
+// A grid-wide FP64 sum formed by a fused kernel: its workgroups leave block
+// partials in part, a fixed-order final sum writes scale * total to *out.
+struct GridSum {
+    double* part;
+    double* out;
+    double scale;
+};
+
 // ------------------------------------------------------------------ spectral
 enum SpecOp { SPEC_NEG_K2 = 0, SPEC_IKX = 1, SPEC_IKY = 2, SPEC_IKZ = 3, SPEC_INV_FD = 4 };
 

@@ -22,6 +22,7 @@ ETD1, ETDRK2 = 1, 2
 FP64, FP32 = 0, 1
 F64, F32 = 0, 1
 F_MASS_PROJECT = 0x1
+F_FROZEN_MEMBRANE = 0x2
 OP_IDENTITY, OP_LAPLACE, OP_DX, OP_DY, OP_DZ, OP_LAPINV = range(6)
 Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
 

@@ -175,6 +175,41 @@ def fixed_membrane(dim: int = 2, n: int = 64, radius: float = 0.5, eps_pm: float
     return FixedInputs(shape, hl, g, u0, eps_u, gamma, M, ubar, tau)
 
 
+def fixed_patch_study(n: int = 256, eps_u_in_h: float = 5.0, M: float = 600.0, tau: float = 1e-4,
+                      seed: int = DEFAULT_SEED, instance: int = 0, r0: float = 0.4, eps_phi_in_h: float = 10.0,
+                      ubar: float = 0.3, gamma: float = 100.0, patch_fraction: float = 0.35,
+                      mem_threshold: float = 1e-3) -> FixedInputs:
+    """The fixed circle and protein patch of the temporal convergence study
+    (Section 4.1, Tables 1-2) on [-1, 1]^2.
+
+    phi = 0.5 + 0.5 tanh(3 (r0 - r) / eps_phi), r0 = 0.4, eps_phi = 10 h, so
+    g = 18 (phi^2 - phi)^2 = (9/8) sech^4(3 (r0 - r) / eps_phi), used in that
+    form so that g stays strictly positive in float64.  U^0 = 1 on a connected
+    patch Gamma_0 of the membrane region {g >= 1e-3} carrying the fraction
+    0.35 = ubar + 0.05 of its g-mass, 0 elsewhere.  The paper draws Gamma_0
+    at random without fixing how; here it is the annular sector that starts
+    at a seeded uniform angle and grows counter-clockwise: the membrane points
+    in order of their angle from the start (stable order), kept while the
+    running g-sum stays within 0.35 of the total.
+    """
+    shape = (n, n)
+    h = 2.0 / n
+    eps_phi = eps_phi_in_h * h
+    X = mesh(shape, (1.0, 1.0))
+    r = np.sqrt(X[0] * X[0] + X[1] * X[1])
+    g = 1.125 * sech4(3.0 * (r0 - r) / eps_phi)
+    mem = g >= mem_threshold
+    theta0 = math.pi * (1.0 + float(uniform_pm1(seed, instance, 2, (1,))[0]))
+    ang = np.mod(np.arctan2(X[1], X[0]) - theta0, 2.0 * math.pi)
+    idx = np.flatnonzero(mem.ravel())
+    order = idx[np.argsort(ang.ravel()[idx], kind="stable")]
+    csum = np.cumsum(g.ravel()[order])
+    keep = order[csum <= patch_fraction * csum[-1]]
+    u0 = np.zeros(n * n)
+    u0[keep] = 1.0
+    return FixedInputs(shape, (1.0, 1.0), g, u0.reshape(shape), eps_u_in_h * h, gamma, M, ubar, tau)
+
+
 # ----------------------------------------------------------------------------
 # coupled phi/u inputs (3D, [-pi, pi)^3, eps = 3h)
 # ----------------------------------------------------------------------------
@@ -287,6 +322,28 @@ def coupled_membrane(n=256, seed: int = DEFAULT_SEED, instance: int = 0, R0: flo
     for k, v in (overrides or {}).items():
         setattr(p, k, v)
     return CoupledInputs(shape, hl, phi0, u0, p, tau, seed, instance, a)
+
+
+def frozen_sphere(n: int = 128, radius: float = 0.5, eps_pm_in_h: float = 2.0, tau: float = 0.02,
+                  B2: float = 1000.0, seed: int = DEFAULT_SEED, instance: int = 0, u_mean_pm: float = -0.2,
+                  u_amp_pm: float = 0.05, gamma: float = 1.0, M: float = 200.0) -> CoupledInputs:
+    """The sphere of fixed_membrane(dim=3, ...) as coupled-model inputs, for
+    the coupled scheme's u stages on a frozen membrane: phi the [0,1] tanh
+    profile of the same radius and width (so g(phi) is that membrane's g up
+    to rounding), the same U^0 draws, eps_u, gamma, M, ubar, and the
+    stabilizer B2 given (B1 = 1).  The phi-equation coefficients are unused."""
+    shape = (n, n, n)
+    hl = (1.0, 1.0, 1.0)
+    eps_pm = eps_pm_in_h * 2.0 / n
+    X = mesh(shape, hl)
+    r = np.sqrt(sum(x * x for x in X))
+    phi0 = 0.5 * (1.0 + np.tanh((radius - r) / (math.sqrt(2.0) * eps_pm)))
+    upm = u_mean_pm + u_amp_pm * uniform_pm1(seed, instance, 1, shape)
+    u0 = 0.5 * (1.0 + upm)
+    eps_phi = 3.0 * math.sqrt(2.0) * eps_pm
+    p = CoupledParams(eps_phi=eps_phi, eps_u=0.5 * eps_phi, gamma=gamma, M=M, ubar=float(0.5 * (1.0 + u_mean_pm)),
+                      B1=1.0, B2=B2)
+    return CoupledInputs(shape, hl, phi0, u0, p, tau, seed, instance, np.zeros(0))
 
 
 def batch_sweep(seed: int = DEFAULT_SEED + 5000, counts=((64, 32), (96, 12), (128, 4)),

@@ -54,6 +54,7 @@ def _desc(model=etd.COUPLED, shape=(16, 16, 16), tau=1e-4, scheme=2, prec=0):
     (lambda d: setattr(d[0].coupled.contents, "gamma", float("inf")), etd.ETD_E_ARG),
     (lambda d: setattr(d[0], "recover_threshold", -1.0), etd.ETD_E_ARG),
     (lambda d: (setattr(d[0], "band_threshold", 0.995), setattr(d[0], "band_rebuild_every", 0)), etd.ETD_E_ARG),
+    (lambda d: setattr(d[0], "flags", 0x4), etd.ETD_E_ARG),                               # unknown flag bit
 ])
 def test_plan_create_rejects_invalid_descriptors(mutate, status):
     L = etd.lib()
@@ -72,6 +73,9 @@ def test_fixed_membrane_validation():
     p = C.c_void_p()
     assert L.etd_plan_create(d, 1, None, C.byref(p)) == etd.ETD_E_ARG
     d[0].fixed.contents.eps_u = 0.1
+    d[0].flags = etd.F_FROZEN_MEMBRANE          # a coupled-model flag
+    assert L.etd_plan_create(d, 1, None, C.byref(p)) == etd.ETD_E_ARG
+    d[0].flags = 0
     d[0].fixed = C.POINTER(etd.FixedParams)()
     assert L.etd_plan_create(d, 1, None, C.byref(p)) == etd.ETD_E_ARG
 

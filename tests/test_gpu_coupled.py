@@ -21,7 +21,8 @@ def run_pair(ci, scheme, precision, nsteps, **inst_kw):
     o = CoupledOracle(grid, ci.params, ci.tau, scheme,
                       band_threshold=inst_kw.get("band_threshold", 0.0),
                       band_rebuild_every=inst_kw.get("band_rebuild_every", 10),
-                      mass_projection=bool(inst_kw.get("flags", 0) & etd.F_MASS_PROJECT))
+                      mass_projection=bool(inst_kw.get("flags", 0) & etd.F_MASS_PROJECT),
+                      frozen_membrane=bool(inst_kw.get("flags", 0) & etd.F_FROZEN_MEMBRANE))
     o.set_state(ci.phi0, ci.u0)
     plan = etd.Plan(etd.coupled_instance(ci, scheme=scheme, precision=precision, **inst_kw))
     dt = torch.float64 if precision == etd.FP64 else torch.float32
@@ -61,6 +62,21 @@ def test_fp32_step_close_to_oracle(scheme):
     ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
     report("coupled_fp32", scheme=scheme, err_phi=ephi, err_u=eu)
     assert ephi <= 1e-4 and eu <= 1e-4
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+@pytest.mark.parametrize("precision,tol", [(etd.FP64, 1e-12), (etd.FP32, 1e-4)])
+def test_frozen_membrane_matches_oracle(scheme, precision, tol):
+    """ETD_F_FROZEN_MEMBRANE: only the g u stages, with g = g(phi^0), v = 0;
+    phi stays at its set_state value (its spectral round trip)."""
+    ci = make_case((32, 32, 32))
+    o, plan, phi, u = run_pair(ci, scheme, precision, 6, flags=etd.F_FROZEN_MEMBRANE)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_frozen", scheme=scheme, precision=precision, err_phi=ephi, err_u=eu)
+    assert ephi <= (1e-14 if precision == etd.FP64 else 1e-6) and eu <= tol
+    d, od = plan.diagnostics(0), o.diagnostics()
+    assert abs(d["mass"] - od["m"]) <= 10 * tol * max(1.0, abs(od["m"]))
     plan.close()
 
 

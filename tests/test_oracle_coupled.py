@@ -213,6 +213,29 @@ def test_convergence_u_with_frozen_membrane(scheme, lo, hi):
     assert lo <= rates[-1] <= hi, (errs, rates)
 
 
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_frozen_membrane_is_the_phi_free_limit(scheme):
+    """frozen_membrane runs only the g u stages with g = g(phi^0) and v = 0.
+    The same u must come out of the full step when the phi equation is
+    switched off by its coefficients (kappa = lambda_surf = lambda_line =
+    alpha = M_area = 0: l_phi = 0, R1 = 0, so phi stays put and v = 0; that
+    limit's order is pinned above), and with the flag set the u result must
+    not depend on those coefficients at all."""
+    off = dict(kappa=0.0, lambda_surf=0.0, lambda_line=0.0, alpha=0.0, M_area=0.0)
+    ci0, grid = case(n=16, gamma=50.0, M=20.0, **off)
+    ci1, _ = case(n=16, gamma=50.0, M=20.0)
+    limit = oracle_for(ci0, grid, scheme)
+    frozen0 = oracle_for(ci0, grid, scheme, frozen_membrane=True)
+    frozen1 = oracle_for(ci1, grid, scheme, frozen_membrane=True)
+    for o in (limit, frozen0, frozen1):
+        o.run(4)
+    s = np.abs(limit.u).max()
+    assert np.abs(frozen0.u - limit.u).max() <= 1e-14 * s
+    assert np.abs(frozen1.u - limit.u).max() <= 1e-14 * s
+    assert np.array_equal(frozen1.phi_hat, core.fft(ci1.phi0))
+    assert np.abs(frozen1.phi() - limit.phi()).max() <= 1e-14
+
+
 def test_band_list_definition():
     rng = np.random.default_rng(5)
     phi = rng.random((9, 7, 5))
