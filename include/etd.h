@@ -143,6 +143,19 @@ etd_status etd_plan_destroy(etd_plan_t plan);
 etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const void* u,
                          etd_dtype dtype);
 
+/* Set the time step of the next steps of one instance.  Section 3.3 writes
+ * both coupled schemes with a per-step tau_{n+1} (the phi-functions, the
+ * step itself and the velocity's phi_t all take it), and the fixed-membrane
+ * schemes of Section 2.2 step the same way; a sequence of etd_set_tau /
+ * etd_step calls runs the variable-step scheme.  The state is kept.  Fixed
+ * model: the Chebyshev coefficients of phi1(tau L) and phi2(tau L) are
+ * re-formed on the host (no device work; formed by etd_set_state if no
+ * state is loaded yet).  Graphs captured by ETD_EXEC_GRAPH are dropped (they
+ * hold the old step's kernel arguments) and recaptured by the next etd_step.
+ * Does not synchronize.  Errors: ETD_E_ARG (null plan, instance out of
+ * range, tau not finite and > 0). */
+etd_status etd_set_tau(etd_plan_t plan, int instance, double tau);
+
 /* Copy the current state of one instance into device arrays.
  *   coupled: a <- phi^n, u <- u^n;  fixed: a <- g (may be NULL), u <- U^n.
  * Synchronizes; returns ETD_E_NONFINITE if a NaN/Inf was detected. */

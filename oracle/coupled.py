@@ -73,11 +73,17 @@ class CoupledOracle:
             + (p.kappa * (p.A1 + p.A2) + p.lambda_surf * e2) / (p.mu * e2) * k2 \
             + (p.kappa * p.A1 * p.A2 + p.lambda_surf * p.A1 * e2) / (p.mu * e2 * e2)
         self.lu = p.B2 + p.eps_u * p.B1 * k2
+        self.set_tau(tau)
+        self.mask = None
+        self.n = 0
+
+    def set_tau(self, tau):
+        """Step size tau_{n+1} of the next steps (Section 3.3 writes both schemes
+        with a per-step tau: the phi-functions, the step and phi_t take it)."""
+        self.tau = float(tau)
         zt, zu = self.tau * self.lphi, self.tau * self.lu
         self.E0p, self.E1p, self.E2p = core.phi0(zt), core.phi1(zt), core.phi2(zt)
         self.E0u, self.E1u, self.E2u = core.phi0(zu), core.phi1(zu), core.phi2(zu)
-        self.mask = None
-        self.n = 0
 
     # ------------------------------------------------------------------ state
     def set_state(self, phi, u):

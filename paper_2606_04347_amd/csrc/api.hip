@@ -742,6 +742,21 @@ etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const voi
     return ETD_OK;
 }
 
+etd_status etd_set_tau(etd_plan_t plan, int instance, double tau) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!(std::isfinite(tau) && tau > 0.0)) return fail(&plan->err, ETD_E_ARG, "tau must be finite and > 0");
+    Instance& I = plan->inst[instance];
+    I.d.tau = tau;
+    I.K.tau = tau;
+    if (I.d.model == ETD_FIXED_MEMBRANE && I.has_state) {
+        I.ch1 = cheb_coeffs(phi1_host, tau, I.a, I.b);
+        I.ch2 = cheb_coeffs(phi2_host, tau, I.a, I.b);
+    }
+    drop_graphs(plan);
+    return ETD_OK;
+}
+
 etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dtype dtype) {
     etd_status st = check_instance(plan, instance);
     if (st != ETD_OK) return st;

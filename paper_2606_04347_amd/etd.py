@@ -26,7 +26,7 @@ F_FROZEN_MEMBRANE = 0x2
 OP_IDENTITY, OP_LAPLACE, OP_DX, OP_DY, OP_DZ, OP_LAPINV = range(6)
 Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
 
-EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_get_state", "etd_step",
+EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
            "etd_status_string", "etd_last_error")
@@ -94,6 +94,7 @@ def lib():
         L.etd_plan_create.argtypes = [C.POINTER(InstanceDesc), i, vp, C.POINTER(vp)]
         L.etd_plan_destroy.argtypes = [vp]
         L.etd_set_state.argtypes = [vp, i, vp, vp, i]
+        L.etd_set_tau.argtypes = [vp, i, d]
         L.etd_get_state.argtypes = [vp, i, vp, vp, i]
         L.etd_step.argtypes = [vp, i]
         L.etd_energy.argtypes = [vp, i, C.POINTER(d), i]
@@ -223,6 +224,11 @@ class Plan:
     def set_state(self, i, a, u):
         assert a.dtype == u.dtype
         self._c(lib().etd_set_state(self._ptr, i, self._dev(a), self._dev(u), self._dt(a)))
+
+    def set_tau(self, i, tau):
+        """Time step of the next steps of instance i (variable-step scheme)."""
+        self._c(lib().etd_set_tau(self._ptr, i, float(tau)))
+        self.instances[i].tau = float(tau)
 
     def get_state(self, i, dtype=None):
         import torch

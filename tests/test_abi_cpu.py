@@ -87,6 +87,7 @@ def test_null_arguments_and_status_strings():
     d, keep = _desc()
     assert L.etd_plan_create(d, 0, None, C.byref(p)) == etd.ETD_E_ARG
     assert L.etd_step(None, 1) == etd.ETD_E_ARG
+    assert L.etd_set_tau(None, 0, 1e-4) == etd.ETD_E_ARG
     assert L.etd_plan_destroy(None) == etd.ETD_OK
     for s in range(-7, 1):
         assert L.etd_status_string(s)

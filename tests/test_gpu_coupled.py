@@ -80,6 +80,28 @@ def test_frozen_membrane_matches_oracle(scheme, precision, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_variable_step_matches_oracle(scheme):
+    """etd_set_tau between steps (per-step tau_{n+1}, Section 3.3) against the
+    oracle stepping the same tau sequence."""
+    ci = make_case((16, 16, 16))
+    grid = Grid(ci.shape, ci.half_len)
+    o = CoupledOracle(grid, ci.params, ci.tau, scheme)
+    o.set_state(ci.phi0, ci.u0)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=scheme, precision=etd.FP64))
+    plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+    for tau in (1e-4, 2e-4, 5e-5, 3e-4):
+        o.set_tau(tau)
+        o.step()
+        plan.set_tau(0, tau)
+        plan.step(1)
+    phi, u = (host(t) for t in plan.get_state(0))
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_variable_tau", scheme=scheme, err_phi=ephi, err_u=eu)
+    assert ephi <= 1e-12 and eu <= 1e-12
+    plan.close()
+
+
 def test_band_restricted_step_matches_oracle():
     ci = make_case((32, 32, 32))
     o, plan, phi, u = run_pair(ci, etd.ETDRK2, etd.FP64, 12, band_threshold=0.995, band_rebuild_every=10)

@@ -67,6 +67,30 @@ def test_fp64_2d_matches_uspace_oracle(scheme):
     plan.close()
 
 
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_variable_step_matches_uspace_oracle(scheme):
+    """etd_set_tau between steps re-forms the Chebyshev coefficients; the
+    U-space oracle steps the same tau sequence (one exponential per tau)."""
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+    grid, p, _ = oracle_params(fi)
+    seq = (fi.tau, 2 * fi.tau, 0.5 * fi.tau, fi.tau)
+    ex = {t: fixed.UspaceExpo(fi.g, p, grid, t) for t in set(seq)}
+    U = fi.u0.copy()
+    plan = etd.Plan(etd.fixed_instance(fi, scheme=scheme))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    degs = []
+    for t in seq:
+        U = fixed.step(U, fi.g, p, grid, t, scheme, ex[t])
+        plan.set_tau(0, t)
+        degs.append(plan.query(0, etd.Q_CHEB_DEG))
+        plan.step(1)
+    _, u = plan.get_state(0)
+    err = rel_linf(host(u), U)
+    report("fixed_variable_tau", scheme=scheme, err=err, degrees=str(degs))
+    assert err <= 1e-12
+    plan.close()
+
+
 def test_fp64_config1_64x64_etd1_matches_oracle():
     """64^2 config 1 against the eigendecomposition oracle, compared in the
     scheme's own variable w = sqrt(g) U (eqn:ODE_eqn): the dense route is

@@ -213,6 +213,39 @@ def test_convergence_u_with_frozen_membrane(scheme, lo, hi):
     assert lo <= rates[-1] <= hi, (errs, rates)
 
 
+@pytest.mark.parametrize("scheme,lo,hi", [(1, 0.85, 1.25), (2, 1.75, 2.3)])
+def test_variable_step_keeps_the_order(scheme, lo, hi):
+    """Section 3.3 writes both schemes with a per-step tau_{n+1}.  Steps that
+    alternate tau_a = T/(3m) and tau_b = 2 tau_a (m pairs to T), refined by
+    doubling m, keep the scheme's order against a fine uniform run (phi
+    decoupled from u as above, u carried along); a step that kept the old
+    tau's phi-functions would not converge at all."""
+    ci, grid = case(n=16, lambda_line=0.0, alpha=0.0, M_area=0.0)
+    T = 5e-4
+
+    def run(taus):
+        o = CoupledOracle(grid, ci.params, taus[0], scheme)
+        o.set_state(ci.phi0, ci.u0)
+        for t in taus:
+            o.set_tau(t)
+            o.step()
+        return o
+
+    ref = run([T / 512] * 512)
+    errs = []
+    for k in range(4):
+        m = 2 ** (k + 1)
+        o = run([T / (3 * m), 2 * T / (3 * m)] * m)
+        errs.append(np.abs(o.phi() - ref.phi()).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert lo <= rates[-1] <= hi, (errs, rates)
+    # a constant sequence through set_tau is the uniform run, bit for bit
+    a, b = run([T / 8] * 8), oracle_for(ci, grid, scheme)
+    b.set_tau(T / 8)
+    b.run(8)
+    assert np.array_equal(a.phi_hat, b.phi_hat) and np.array_equal(a.u, b.u)
+
+
 @pytest.mark.parametrize("scheme", [1, 2])
 def test_frozen_membrane_is_the_phi_free_limit(scheme):
     """frozen_membrane runs only the g u stages with g = g(phi^0) and v = 0.
