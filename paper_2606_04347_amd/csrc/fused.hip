@@ -650,6 +650,14 @@ template <int ST, typename T, int L, int LS> struct EtdXOp {
     }
 };
 
+// Lines per workgroup of the ETD x pass: 16 in FP32 (runs of 128 contiguous
+// bytes per x element; measured faster than 8 despite the lower occupancy),
+// 8 in FP64 (the register stash of the joint transforms).  The nonlocal line
+// pass measured faster with 8 in both precisions.
+template <typename T, int N> constexpr int xline_tile() {
+    return sizeof(T) == 4 ? lines_per_block<T, N, 1>() : lines_per_block_8<T, N, 1>();
+}
+
 // Forward x pass of the remainder pair with the ETD combine, then, on the
 // combined spectrum still in the LDS, the inverse x transforms the next
 // passes need: the derivative triple (S, i kx S, -kx^2 S) -> (X0, X1, X2)
@@ -658,7 +666,7 @@ template <int ST, typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
                                                     EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
                                                     const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block_8<T, N, 1>();
+    constexpr int L = xline_tile<T, N>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
@@ -863,7 +871,7 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
 template <int ST, typename T, int N>
 hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
                         int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
-    constexpr int L = lines_per_block_8<T, N, 1>();
+    constexpr int L = xline_tile<T, N>();
     const size_t smem = lines_smem<T, N, L, 1>();
     static std::once_flag flag;
     set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
