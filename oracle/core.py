@@ -243,6 +243,61 @@ def lapinv(f: np.ndarray, grid: Grid) -> np.ndarray:
     return ifft(inv * fft(f))
 
 
+def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) -> np.ndarray:
+    """(-Delta_{S,h})^{-1} f assembled and solved on a narrow band.
+
+    Section 2.1 (operator:diff) defines Delta_{S,h} with face coefficients
+    g_{i+1/2} = (g_i + g_{i+1})/2 and its inverse on mean-zero functions,
+    extended to any f by removing the mean; Section 3.2 assembles and solves
+    the nonlocal problem only on the band nodes.  Reading: the unknowns are
+    the nodes with mask != 0; a face enters when both of its nodes are on the
+    band (faces to nodes off the band carry no flux); the mean removed from f
+    and from the solution is the plain mean over the band nodes; the result
+    is 0 off the band.  The band must be connected (else the constrained
+    system below is singular).
+
+    The band matrix A (row i: sum over band neighbours j of w_ij (psi_i -
+    psi_j), w_ij = g_face / h_d^2) is assembled edge by edge; the
+    mean-zero solution comes from the bordered system
+        [A 1; 1^T 0] [psi; lam] = [f_B - mean(f_B); 0]
+    by scipy's sparse direct solver (the library primitive).
+    """
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    m = np.asarray(mask).astype(bool)
+    B = np.flatnonzero(m.ravel())
+    nb = B.size
+    pos = -np.ones(m.size, dtype=np.int64)
+    pos[B] = np.arange(nb)
+    gf = np.asarray(g, dtype=np.float64).ravel()
+    shape = m.shape
+    rows, cols, vals = [], [], []
+    diag = np.zeros(nb)
+    for d, h in enumerate(grid.h):
+        ax = d - grid.dim + len(shape)
+        nbr = np.roll(np.arange(m.size).reshape(shape), -1, axis=ax).ravel()   # node i + e_d (periodic)
+        j = nbr[B]
+        on = m.ravel()[j]
+        a, b = np.arange(nb)[on], pos[j[on]]
+        w = 0.5 * (gf[B[on]] + gf[j[on]]) / (h * h)
+        rows += [a, b]
+        cols += [b, a]
+        vals += [-w, -w]
+        np.add.at(diag, a, w)
+        np.add.at(diag, b, w)
+    A = sp.coo_matrix((np.concatenate(vals + [diag]),
+                       (np.concatenate(rows + [np.arange(nb)]), np.concatenate(cols + [np.arange(nb)]))),
+                      shape=(nb, nb)).tocsr()
+    one = sp.csr_matrix(np.ones((nb, 1)))
+    K = sp.bmat([[A, one], [one.T, None]], format="csc")
+    fb = np.asarray(f, dtype=np.float64).ravel()[B]
+    rhs = np.concatenate([fb - fb.mean(), [0.0]])
+    sol = spla.spsolve(K, rhs)
+    out = np.zeros(m.size)
+    out[B] = sol[:nb]
+    return out.reshape(shape)
+
+
 def lapinv_inf_norm(grid: Grid) -> float:
     """C = ||(-Delta_h)^{-1}||_inf = sum_j |a_j|, a = IDFT(1/mu) (0 at k=0).
 

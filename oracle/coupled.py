@@ -33,6 +33,10 @@ Readings (ambiguity register; listed in the design notes):
   * the phi stages freeze u at u^n; the u stages use g(phi^{n+1}) and restart
     from FFT(g(phi^{n+1}) u^n) (Section 3.3);
   * A0 = int phi^0 when ``A0_from_initial``;
+  * ``surface_nonlocal``: the nonlocal term uses (-Delta_{S,h})^{-1}
+    assembled and solved on the band (core.lapinv_S_band, with g = g+ of
+    the stage) instead of the constant-coefficient (-Delta_h)^{-1}; the
+    energy diagnostic keeps (-Delta_h)^{-1};
   * ``frozen_membrane``: phi keeps its initial value and only the g u
     stages run, with g = g(phi^0) and v = 0 (the stabilized scheme of
     Section 3.1 on a fixed membrane);
@@ -58,13 +62,16 @@ class CoupledOracle:
     def __init__(self, grid: Grid, p, tau: float, scheme: int = 2,
                  recover_threshold: float = 1e-3, band_threshold: float = 0.0,
                  band_rebuild_every: int = 10, mass_projection: bool = False,
-                 frozen_membrane: bool = False):
+                 frozen_membrane: bool = False, surface_nonlocal: bool = False):
         self.grid, self.p, self.tau, self.scheme = grid, p, float(tau), int(scheme)
         self.thr = float(recover_threshold)
         self.band_thr = float(band_threshold)
         self.band_every = max(1, int(band_rebuild_every))
         self.mass_projection = bool(mass_projection)
         self.frozen = bool(frozen_membrane)
+        self.surface = bool(surface_nonlocal)
+        if self.surface and self.band_thr <= 0.0:
+            raise ValueError("the band solve of the nonlocal term needs a band")
         k2 = core.ksq(grid)
         self.k2 = k2
         self.kd = [core.kder(grid, d) for d in range(grid.dim)]
@@ -139,7 +146,7 @@ class CoupledOracle:
         if self.mask is not None:
             q = q * self.mask
         m = grid.cell * float(np.sum(q))
-        psi = core.lapinv(q, grid)
+        psi = core.lapinv_S_band(q, g, self.mask, grid) if self.surface else core.lapinv(q, grid)
         flux = [g * u * vd for vd in v]
         P2 = p.eps_u * S + p.B2 * g * u - g * core.Wp(u) / p.eps_u \
             - p.gamma * g * psi - p.M * g * m - core.div_central(flux, grid)

@@ -269,6 +269,22 @@ def test_frozen_membrane_is_the_phi_free_limit(scheme):
     assert np.abs(frozen1.phi() - limit.phi()).max() <= 1e-14
 
 
+def test_surface_nonlocal_enters_only_through_gamma():
+    """The band solve replaces (-Delta_h)^{-1} in the gamma term of P2 only:
+    with gamma = 0 both runs agree bit for bit, with gamma > 0 they differ."""
+    out = {}
+    for gamma in (0.0, 200.0):
+        ci, grid = case(n=16, gamma=gamma)
+        runs = []
+        for surf in (False, True):
+            o = oracle_for(ci, grid, 2, band_threshold=0.995, band_rebuild_every=2, surface_nonlocal=surf)
+            o.run(3)
+            runs.append(o.u.copy())
+        out[gamma] = runs
+    assert np.array_equal(out[0.0][0], out[0.0][1])
+    assert np.abs(out[200.0][0] - out[200.0][1]).max() > 1e-9
+
+
 def test_band_list_definition():
     rng = np.random.default_rng(5)
     phi = rng.random((9, 7, 5))
