@@ -104,6 +104,14 @@ typedef struct {
                                       with g = g(phi) and v = 0 (the stabilized spectral
                                       scheme of Section 3.1 on a fixed membrane); other
                                       models reject it with ETD_E_ARG */
+#define ETD_F_SURFACE_NONLOCAL 0x4u /* coupled model with a band only: the nonlocal term of
+                                      R2 uses (-Delta_S,h)^{-1} (Section 2.1, operator:diff,
+                                      with g = g+ of the stage) assembled and solved on the
+                                      band (Section 3.2), as etd_surface_lapinv does, in place
+                                      of the constant-coefficient (-Delta_h)^{-1} by FFT.  The
+                                      solve checks convergence on the host, so plans with this
+                                      flag step eagerly under every schedule.  The energy
+                                      diagnostic keeps (-Delta_h)^{-1}. */
 
 /* One simulation instance. */
 typedef struct {
@@ -264,9 +272,32 @@ etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out);
  *   ETD_Q_WORKSPACE  bytes of device workspace held by the instance */
 typedef enum {
     ETD_Q_B = 0, ETD_Q_B_MBP = 1, ETD_Q_B_ES = 2, ETD_Q_C = 3, ETD_Q_RHO = 4,
-    ETD_Q_CHEB_DEG = 5, ETD_Q_A0 = 6, ETD_Q_WORKSPACE = 7
+    ETD_Q_CHEB_DEG = 5, ETD_Q_A0 = 6, ETD_Q_WORKSPACE = 7,
+    ETD_Q_SURF_ITERS = 8,   /* iterations of the last band solve (ETD_F_SURFACE_NONLOCAL) */
+    ETD_Q_SURF_RELRES = 9   /* its final relative residual */
 } etd_query;
 etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double* out);
+
+/* psi = (-Delta_S,h)^{-1} f on a narrow band (Section 2.1: Delta_S,h of
+ * operator:diff with face coefficients g_{i+1/2} = (g_i + g_{i+1})/2, its
+ * inverse on mean-zero grid functions with the mean of f removed; Section
+ * 3.2: assembled and solved only on the band nodes).  Band: the nodes with
+ * mask[i] != 0 (uint8, grid layout, e.g. from etd_narrowband_build's rule);
+ * faces to nodes off the band carry no flux, the band means of f and of psi
+ * are removed, psi = 0 off the band.  The band must be connected (its
+ * constants are then the only null space).  g (> 0 on the band), f and psi
+ * are device arrays in the grid layout of the instance, element type dtype
+ * (psi may alias f).  FP64 conjugate gradients with the Jacobi
+ * preconditioner from psi = 0, until the relative residual is <= tol or
+ * after max_iter iterations; *iters_out and *relres_out (host, nullable)
+ * report the outcome -- not converging is reported there, not as an error.
+ * Uses a workspace of about 44 bytes per grid point, allocated on the first
+ * call and kept by the plan.  Synchronizes.
+ * Errors: ETD_E_ARG (null pointers, dtype, tol not finite and > 0,
+ * max_iter < 1), ETD_E_NOMEM, ETD_E_HIP. */
+etd_status etd_surface_lapinv(etd_plan_t plan, int instance, const void* g, const void* f,
+                              const uint8_t* mask, void* psi, etd_dtype dtype, double tol, int max_iter,
+                              int* iters_out, double* relres_out);
 
 /* Static strings; never NULL. */
 /* Execution schedule of etd_step over all instances of a plan (a batch of

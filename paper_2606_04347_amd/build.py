@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libetd.so")
 ARCH = os.environ.get("ETD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fft.hip", "fused.hip", "coupled.hip", "reduce.hip", "fixed.hip", "band.hip", "api.hip", "schedule.hip"]
+SOURCES = ["fft.hip", "fused.hip", "coupled.hip", "reduce.hip", "fixed.hip", "band.hip", "api.hip", "schedule.hip", "surface.hip"]
 
 
 def hipcc() -> str:

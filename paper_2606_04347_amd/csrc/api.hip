@@ -59,7 +59,12 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
         msg = "band_threshold must be finite and >= 0"; return ETD_E_ARG;
     }
     if (d.band_threshold > 0.0 && d.band_rebuild_every < 1) { msg = "band_rebuild_every must be >= 1"; return ETD_E_ARG; }
-    if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE)) { msg = "unknown flag bits"; return ETD_E_ARG; }
+    if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE | ETD_F_SURFACE_NONLOCAL)) {
+        msg = "unknown flag bits"; return ETD_E_ARG;
+    }
+    if ((d.flags & ETD_F_SURFACE_NONLOCAL) && (d.model != ETD_COUPLED || !(d.band_threshold > 0.0))) {
+        msg = "ETD_F_SURFACE_NONLOCAL needs the coupled model with a band"; return ETD_E_ARG;
+    }
     if ((d.flags & ETD_F_FROZEN_MEMBRANE) && d.model != ETD_COUPLED) {
         msg = "ETD_F_FROZEN_MEMBRANE applies to the coupled model only"; return ETD_E_ARG;
     }
@@ -136,6 +141,15 @@ etd_status dalloc(etd_plan* P, Instance& I, size_t bytes, void** out) {
         if (st_ != ETD_OK) return st_;                                    \
         ptr = reinterpret_cast<decltype(ptr)>(tmp_);                      \
     } while (0)
+
+// Workspace of the band solve, allocated once per instance.
+etd_status ensure_surface(etd_plan* P, Instance& I) {
+    if (I.surf) return ETD_OK;
+    const long n = I.g.nreal();
+    ALLOC(I.surf, surface_work_bytes(n));
+    surface_work_carve(n, I.surf, I.sw);
+    return ETD_OK;
+}
 
 template <typename T> etd_status upload_table(etd_plan* P, Instance& I, int n, const c2<T>** out) {
     std::vector<double> h(2 * (size_t)n);
@@ -229,6 +243,7 @@ etd_status setup_coupled(etd_plan* P, Instance& I) {
     K.lp2 = (p.kappa * (p.A1 + p.A2) + p.lambda_surf * e2) / (p.mu * e2);
     K.lp0 = (p.kappa * p.A1 * p.A2 + p.lambda_surf * p.A1 * e2) / (p.mu * e2 * e2);
     K.thr = I.d.recover_threshold;
+    if (I.d.flags & ETD_F_SURFACE_NONLOCAL) return ensure_surface(P, I);
     return ETD_OK;
 }
 
@@ -410,9 +425,20 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
     const EtdArgs<T> a{nullptr, v.Sra, v.Sgu};
     hipError_t e = hipSuccess;
+    const bool surface = (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
+    // band solve of the nonlocal term: q and m pointwise, psi = (-Delta_S,h)^{-1} q on the band
+    auto surface_psi = [&]() -> hipError_t {
+        timed_kernel(PASS_POINT, 3.0 * fb + mb, s, [&] {
+            coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, nullptr, I.part, I.scal + S_MASS, s);
+        });
+        const double tol = I.f32 ? 1e-9 : 1e-12;
+        return surface_lapinv<T>(g, v.gp, v.P, mask, I.band_idx, I.band_total, v.psi, I.sw, tol, 20000,
+                                 &I.surf_last, s);
+    };
     if (g.nx > 1) {
         // q formed in the load of the nonlocal transform (with m); P2 and g+ u in the load of the pair
-        e = lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, grid_sum(I, S_MASS), s);
+        e = surface ? surface_psi()
+                    : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, grid_sum(I, S_MASS), s);
         if (e != hipSuccess) return e;
         const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
@@ -1006,6 +1032,33 @@ etd_status etd_pass_timing(etd_plan_t plan, int enable, etd_pass_times* out) {
     return ETD_OK;
 }
 
+etd_status etd_surface_lapinv(etd_plan_t plan, int instance, const void* g, const void* f, const uint8_t* mask,
+                              void* psi, etd_dtype dtype, double tol, int max_iter, int* iters_out,
+                              double* relres_out) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!g || !f || !mask || !psi) return fail(&plan->err, ETD_E_ARG, "null pointer");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    if (!(std::isfinite(tol) && tol > 0.0)) return fail(&plan->err, ETD_E_ARG, "tol must be finite and > 0");
+    if (max_iter < 1) return fail(&plan->err, ETD_E_ARG, "max_iter must be >= 1");
+    Instance& I = plan->inst[instance];
+    if ((st = ensure_surface(plan, I)) != ETD_OK) return st;
+    hipStream_t s = plan->stream;
+    const long n = I.g.nreal();
+    const SurfaceWork& w = I.sw;
+    band_compact(n, mask, w.cnt, w.idx, n, w.total, s);
+    SurfaceResult r;
+    hipError_t e = dtype == ETD_F64
+                       ? surface_lapinv<double>(I.g, (const double*)g, (const double*)f, mask, w.idx, w.total,
+                                                (double*)psi, w, tol, max_iter, &r, s)
+                       : surface_lapinv<float>(I.g, (const float*)g, (const float*)f, mask, w.idx, w.total,
+                                               (float*)psi, w, tol, max_iter, &r, s);
+    HIPCHK(plan, e);
+    if (iters_out) *iters_out = r.iters;
+    if (relres_out) *relres_out = r.relres;
+    return ETD_OK;
+}
+
 etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double* out) {
     etd_status st = check_instance(plan, instance);
     if (st != ETD_OK) return st;
@@ -1020,6 +1073,8 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
         case ETD_Q_CHEB_DEG: *out = (double)std::max(I.ch1.size(), I.ch2.size()); break;
         case ETD_Q_A0: *out = I.A0; break;
         case ETD_Q_WORKSPACE: *out = (double)I.bytes; break;
+        case ETD_Q_SURF_ITERS: *out = (double)I.surf_last.iters; break;
+        case ETD_Q_SURF_RELRES: *out = I.surf_last.relres; break;
         default: return fail(&plan->err, ETD_E_ARG, "unknown query");
     }
     return ETD_OK;

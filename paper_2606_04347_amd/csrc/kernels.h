@@ -142,6 +142,31 @@ void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const
 // flags[i] = |2 phi_i - 1| < thr (FP64); counts per block, exclusive scan, stable scatter.
 template <typename T>
 void band_flags(long n, const T* phi, double thr, uint8_t* flags, hipStream_t s);
+// (-Delta_S,h)^{-1} on a narrow band (surface.hip): FP64 Jacobi-preconditioned
+// conjugate gradients over the band list idx[0 .. *total) of mask.  Workspace
+// carved from one device allocation of surface_work_bytes(n) bytes (its own
+// band list buffers idx / cnt / total serve callers without one).
+struct SurfaceWork {
+    double *x = nullptr, *p = nullptr, *r = nullptr, *ap = nullptr, *dinv = nullptr;
+    int32_t* idx = nullptr;
+    int64_t *cnt = nullptr, *total = nullptr;
+    double *part = nullptr, *S = nullptr;
+};
+struct SurfaceResult {
+    int iters = 0;
+    double relres = 0.0;
+    bool converged = false;
+};
+size_t surface_work_bytes(long n);
+void surface_work_carve(long n, void* base, SurfaceWork& w);
+// psi = (-Delta_S,h)^{-1} f on the band (0 off it); stops when the relative
+// residual reaches tol or after max_iter iterations.  Synchronizes the stream
+// every 25 iterations (convergence check); res (nullable) gets the outcome.
+template <typename T>
+hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t* mask, const int32_t* idx,
+                          const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter,
+                          SurfaceResult* res, hipStream_t s);
+
 // Compact flagged indices in ascending order.  blockcnt: scratch of band_blocks(n) + 1 int64.
 long band_blocks(long n);
 void band_compact(long n, const uint8_t* flags, int64_t* blockcnt, int32_t* idx_out, int64_t capacity,

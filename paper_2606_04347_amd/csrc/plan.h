@@ -64,6 +64,10 @@ struct Instance {
     // fixed-model constants
     double C = 0, Bmbp = 0, Bes = 0, rho = 0, a = 0, b = 0;
     std::vector<double> ch1, ch2;   // Chebyshev coefficients of phi1(tau x), phi2(tau x) on [a, b]
+    // band solve of (-Delta_S,h)^{-1} (ETD_F_SURFACE_NONLOCAL, etd_surface_lapinv)
+    void* surf = nullptr;
+    SurfaceWork sw;
+    SurfaceResult surf_last;
 };
 
 

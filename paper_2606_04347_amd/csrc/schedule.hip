@@ -248,7 +248,9 @@ void etd::release_schedule(etd_plan* plan) {
 
 etd_status etd::run_steps(etd_plan* plan, int nsteps) {
     ScheduleState& S = plan->sched;
-    if (S.mode != ETD_EXEC_GRAPH || plan->timing) return eager_steps(plan, nsteps);
+    bool host_checks = false;   // the band solve reads its convergence flag on the host
+    for (const Instance& I : plan->inst) host_checks |= (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
+    if (S.mode != ETD_EXEC_GRAPH || plan->timing || host_checks) return eager_steps(plan, nsteps);
     int k = 0;
     for (; k + 2 <= nsteps; k += 2) {
         const std::string key = graph_key(plan);

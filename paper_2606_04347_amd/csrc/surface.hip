@@ -1,0 +1,325 @@
+// (-Delta_S,h)^{-1} on a narrow band by preconditioned conjugate gradients
+// (Section 2.1 operator:diff and the pseudo-inverse on mean-zero functions;
+// Section 3.2 narrow band).  FP64 throughout.
+//
+// Unknowns: the band nodes (mask != 0), listed in idx[0 .. *total).  Row i of
+// the band matrix A is sum_{j band neighbour} w_ij (psi_i - psi_j) with
+// w_ij = (g_i + g_j) / (2 h_d^2); faces to nodes off the band carry no flux.
+// Right-hand side f_i - mean_band(f); A is symmetric positive semidefinite
+// with the constants of a connected band as its null space, so CG from
+// psi = 0 with the Jacobi preconditioner converges on the mean-zero part;
+// the band mean of the iterate is removed at the end and psi = 0 off the
+// band.
+//
+// Every iteration runs five fixed-grid launches (the partial sums of the two
+// dot products are taken per workgroup in a fixed order and closed by a
+// one-workgroup kernel, so results do not depend on scheduling); the step
+// scalars (alpha, beta, the residual norms, a done flag) live in device
+// memory, and every kernel returns at once when the flag is set.
+#include <algorithm>
+#include <cmath>
+
+#include "blocksum.h"
+#include "kernels.h"
+
+namespace etd {
+namespace {
+
+constexpr int kSbThreads = 256;
+constexpr int kSbBlocks = 512;
+
+enum SbSlot { SB_RZ = 0, SB_PAP, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT };
+enum SbFinal { FIN_MEAN = 0, FIN_INIT, FIN_PAP, FIN_UPDATE, FIN_XMEAN };
+
+struct BandGeom {
+    int nx, ny, nz;
+    double ihx2, ihy2, ihz2;   // 1 / h_d^2
+};
+
+BandGeom band_geom(const GridK& g) {
+    return BandGeom{g.nx, g.ny, g.nz, g.nx > 1 ? 1.0 / (g.h[0] * g.h[0]) : 0.0, 1.0 / (g.h[1] * g.h[1]),
+                    1.0 / (g.h[2] * g.h[2])};
+}
+
+// Calls f(j, 1/h^2) for the periodic axis neighbours j of node i (x only on
+// three-dimensional grids).
+template <class F> __device__ __forceinline__ void for_neighbours(const BandGeom& b, long i, F f) {
+    const long sy = b.nz, sx = (long)b.ny * b.nz;
+    const int z = (int)(i % b.nz);
+    const long t = i / b.nz;
+    const int y = (int)(t % b.ny);
+    const int x = (int)(t / b.ny);
+    f(z + 1 < b.nz ? i + 1 : i + 1 - b.nz, b.ihz2);
+    f(z > 0 ? i - 1 : i - 1 + b.nz, b.ihz2);
+    f(y + 1 < b.ny ? i + sy : i + sy - (long)b.ny * sy, b.ihy2);
+    f(y > 0 ? i - sy : i - sy + (long)b.ny * sy, b.ihy2);
+    if (b.nx > 1) {
+        f(x + 1 < b.nx ? i + sx : i + sx - (long)b.nx * sx, b.ihx2);
+        f(x > 0 ? i - sx : i - sx + (long)b.nx * sx, b.ihx2);
+    }
+}
+
+// Two block partials per workgroup: part[2 blockIdx.x + c].
+__device__ __forceinline__ void store_partials(double a, double b, double* part) {
+    __shared__ double sh[kSbThreads];
+    const double ta = block_sum_256(a, sh);
+    const double tb = block_sum_256(b, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__device__ __forceinline__ bool sb_done(const double* S) { return S[SB_DONE] != 0.0; }
+
+// Jacobi diagonal (its inverse) and the band sum of f.
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __restrict__ G,
+                                                         const T* __restrict__ f, const uint8_t* __restrict__ mask,
+                                                         const int32_t* __restrict__ idx,
+                                                         const int64_t* __restrict__ total, double* dinv,
+                                                         double* part) {
+    const long nb = *total;
+    Neu acc;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        const double gi = (double)G[i];
+        double d = 0.0;
+        for_neighbours(b, i, [&](long j, double ih2) {
+            if (mask[j]) d += 0.5 * (gi + (double)G[j]) * ih2;
+        });
+        dinv[k] = d > 0.0 ? 1.0 / d : 0.0;
+        acc.add((double)f[i]);
+    }
+    store_partials(acc.val(), 0.0, part);
+}
+
+// r = f - mean, z = D^-1 r, p = z, x = 0 (band nodes); partials r.z, r.r.
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_init(const T* __restrict__ f, const int32_t* __restrict__ idx,
+                                                        const int64_t* __restrict__ total,
+                                                        const double* __restrict__ dinv, const double* S, double* x,
+                                                        double* p, double* r, double* part) {
+    const long nb = *total;
+    const double mean = S[SB_MEAN];
+    Neu rz, rr;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        const double rk = (double)f[i] - mean;
+        const double z = rk * dinv[k];
+        r[k] = rk;
+        p[i] = z;
+        x[i] = 0.0;
+        rz.add(rk * z);
+        rr.add(rk * rk);
+    }
+    store_partials(rz.val(), rr.val(), part);
+}
+
+// ap = A p on the band; partial p.ap.
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* __restrict__ G,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const int32_t* __restrict__ idx,
+                                                          const int64_t* __restrict__ total, const double* S,
+                                                          const double* __restrict__ p, double* ap, double* part) {
+    if (sb_done(S)) return;
+    const long nb = *total;
+    Neu pap;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        const double gi = (double)G[i], pi = p[i];
+        double a = 0.0;
+        for_neighbours(b, i, [&](long j, double ih2) {
+            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (pi - p[j]);
+        });
+        ap[k] = a;
+        pap.add(pi * a);
+    }
+    store_partials(pap.val(), 0.0, part);
+}
+
+// x += alpha p, r -= alpha ap; partials r.z, r.r with z = D^-1 r.
+__global__ __launch_bounds__(kSbThreads) void k_sb_update(const int32_t* __restrict__ idx,
+                                                          const int64_t* __restrict__ total,
+                                                          const double* __restrict__ dinv, const double* S,
+                                                          double* x, const double* __restrict__ p, double* r,
+                                                          const double* __restrict__ ap, double* part) {
+    if (sb_done(S)) return;
+    const long nb = *total;
+    const double alpha = S[SB_ALPHA];
+    Neu rz, rr;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        x[i] += alpha * p[i];
+        const double rk = r[k] - alpha * ap[k];
+        r[k] = rk;
+        rz.add(rk * (rk * dinv[k]));
+        rr.add(rk * rk);
+    }
+    store_partials(rz.val(), rr.val(), part);
+}
+
+// p = D^-1 r + beta p.
+__global__ __launch_bounds__(kSbThreads) void k_sb_direction(const int32_t* __restrict__ idx,
+                                                             const int64_t* __restrict__ total,
+                                                             const double* __restrict__ dinv, const double* S,
+                                                             double* p, const double* __restrict__ r) {
+    if (sb_done(S)) return;
+    const long nb = *total;
+    const double beta = S[SB_BETA];
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        p[i] = r[k] * dinv[k] + beta * p[i];
+    }
+}
+
+// band sum of x
+__global__ __launch_bounds__(kSbThreads) void k_sb_xsum(const int32_t* __restrict__ idx,
+                                                        const int64_t* __restrict__ total,
+                                                        const double* __restrict__ x, double* part) {
+    const long nb = *total;
+    Neu acc;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads)
+        acc.add(x[idx[k]]);
+    store_partials(acc.val(), 0.0, part);
+}
+
+// psi = x - mean_band(x) on the band, 0 elsewhere.
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_out(long n, const uint8_t* __restrict__ mask,
+                                                       const double* __restrict__ x, const double* S, T* psi) {
+    const double m = S[SB_XMEAN];
+    for (long i = (long)blockIdx.x * kSbThreads + threadIdx.x; i < n; i += (long)gridDim.x * kSbThreads)
+        psi[i] = mask[i] ? (T)(x[i] - m) : (T)0;
+}
+
+// Closes the partial sums of one kernel (fixed order) and updates the scalars.
+__global__ __launch_bounds__(kSbThreads) void k_sb_final(int mode, const double* __restrict__ part,
+                                                         const int64_t* __restrict__ total, double tol2, double* S) {
+    if ((mode == FIN_PAP || mode == FIN_UPDATE) && sb_done(S)) return;
+    __shared__ double sh[kSbThreads];
+    Neu a, b;
+    for (int k = threadIdx.x; k < kSbBlocks; k += kSbThreads) {
+        a.add(part[2 * k]);
+        b.add(part[2 * k + 1]);
+    }
+    const double sa = block_sum_256(a.val(), sh);
+    const double sb = block_sum_256(b.val(), sh);
+    if (threadIdx.x != 0) return;
+    const double nb = (double)*total;
+    switch (mode) {
+        case FIN_MEAN:
+            S[SB_MEAN] = nb > 0 ? sa / nb : 0.0;
+            break;
+        case FIN_INIT:
+            S[SB_RZ] = sa;
+            S[SB_RR] = sb;
+            S[SB_RR0] = sb;
+            S[SB_ITER] = 0.0;
+            S[SB_DONE] = (sb > 0.0) ? 0.0 : 1.0;
+            break;
+        case FIN_PAP:
+            S[SB_PAP] = sa;
+            if (sa > 0.0) S[SB_ALPHA] = S[SB_RZ] / sa;
+            else S[SB_DONE] = 1.0;
+            break;
+        case FIN_UPDATE:
+            S[SB_BETA] = S[SB_RZ] > 0.0 ? sa / S[SB_RZ] : 0.0;
+            S[SB_RZ] = sa;
+            S[SB_RR] = sb;
+            S[SB_ITER] += 1.0;
+            if (sb <= tol2 * S[SB_RR0]) S[SB_DONE] = 1.0;
+            break;
+        case FIN_XMEAN:
+            S[SB_XMEAN] = nb > 0 ? sa / nb : 0.0;
+            break;
+    }
+}
+
+}  // namespace
+
+// Lays the workspace out from base (256-byte aligned pieces) and returns the
+// bytes it spans; with base == nullptr only the size is computed.
+static size_t surface_layout(long n, char* base, SurfaceWork* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    SurfaceWork t;
+    t.x = (double*)take(n * sizeof(double));
+    t.p = (double*)take(n * sizeof(double));
+    t.r = (double*)take(n * sizeof(double));
+    t.ap = (double*)take(n * sizeof(double));
+    t.dinv = (double*)take(n * sizeof(double));
+    t.idx = (int32_t*)take(n * sizeof(int32_t));
+    t.cnt = (int64_t*)take((band_blocks(n) + 2) * sizeof(int64_t));
+    t.total = (int64_t*)take(sizeof(int64_t));
+    t.part = (double*)take(2 * kSbBlocks * sizeof(double));
+    t.S = (double*)take(16 * sizeof(double));
+    if (w) *w = t;
+    return off;
+}
+
+size_t surface_work_bytes(long n) { return surface_layout(n, nullptr, nullptr); }
+
+void surface_work_carve(long n, void* base, SurfaceWork& w) { surface_layout(n, static_cast<char*>(base), &w); }
+
+template <typename T>
+hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t* mask, const int32_t* idx,
+                          const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter,
+                          SurfaceResult* res, hipStream_t s) {
+    const BandGeom b = band_geom(g);
+    const double tol2 = tol * tol;
+    const dim3 grid(kSbBlocks), blk(kSbThreads);
+    auto fin = [&](int mode) {
+        hipLaunchKernelGGL(k_sb_final, dim3(1), blk, 0, s, mode, w.part, total, tol2, w.S);
+    };
+    hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, G, f, mask, idx, total, w.dinv, w.part);
+    fin(FIN_MEAN);
+    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.p, w.r, w.part);
+    fin(FIN_INIT);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // iterate in chunks; the host reads the done flag between chunks
+    constexpr int kChunk = 25;
+    double done = 0.0;
+    for (int it = 0; it < max_iter && done == 0.0; it += kChunk) {
+        for (int j = 0; j < kChunk && it + j < max_iter; ++j) {
+            hipLaunchKernelGGL(k_sb_matvec<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.p, w.ap, w.part);
+            fin(FIN_PAP);
+            hipLaunchKernelGGL(k_sb_update, grid, blk, 0, s, idx, total, w.dinv, w.S, w.x, w.p, w.r, w.ap, w.part);
+            fin(FIN_UPDATE);
+            hipLaunchKernelGGL(k_sb_direction, grid, blk, 0, s, idx, total, w.dinv, w.S, w.p, w.r);
+        }
+        if ((e = hipMemcpyAsync(&done, w.S + SB_DONE, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sb_xsum, grid, blk, 0, s, idx, total, w.x, w.part);
+    fin(FIN_XMEAN);
+    const long n = g.nreal();
+    const int nbo = (int)std::min<long>(4096, (n + kSbThreads - 1) / kSbThreads);
+    hipLaunchKernelGGL(k_sb_out<T>, dim3(nbo), blk, 0, s, n, mask, w.x, w.S, psi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (res) {
+        double sc[SB_COUNT];
+        if ((e = hipMemcpyAsync(sc, w.S, sizeof sc, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        res->iters = (int)sc[SB_ITER];
+        res->relres = sc[SB_RR0] > 0.0 ? std::sqrt(sc[SB_RR] / sc[SB_RR0]) : 0.0;
+        res->converged = sc[SB_DONE] != 0.0 && (sc[SB_RR0] == 0.0 || sc[SB_RR] <= tol2 * sc[SB_RR0]);
+    }
+    return hipSuccess;
+}
+
+template hipError_t surface_lapinv<float>(const GridK&, const float*, const float*, const uint8_t*, const int32_t*,
+                                          const int64_t*, float*, const SurfaceWork&, double, int, SurfaceResult*,
+                                          hipStream_t);
+template hipError_t surface_lapinv<double>(const GridK&, const double*, const double*, const uint8_t*,
+                                           const int32_t*, const int64_t*, double*, const SurfaceWork&, double, int,
+                                           SurfaceResult*, hipStream_t);
+
+}  // namespace etd

@@ -23,12 +23,14 @@ FP64, FP32 = 0, 1
 F64, F32 = 0, 1
 F_MASS_PROJECT = 0x1
 F_FROZEN_MEMBRANE = 0x2
+F_SURFACE_NONLOCAL = 0x4
 OP_IDENTITY, OP_LAPLACE, OP_DX, OP_DY, OP_DZ, OP_LAPINV = range(6)
-Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE = range(8)
+Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE, Q_SURF_ITERS, Q_SURF_RELRES = range(10)
 
 EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
+           "etd_surface_lapinv",
            "etd_status_string", "etd_last_error")
 EXEC_EAGER, EXEC_GRAPH = 0, 1
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
@@ -106,6 +108,7 @@ def lib():
         L.etd_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
         L.etd_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
         L.etd_autotune.argtypes = [vp, i, C.c_char_p, C.POINTER(Schedule), C.POINTER(d)]
+        L.etd_surface_lapinv.argtypes = [vp, i, vp, vp, vp, vp, i, d, i, C.POINTER(i), C.POINTER(d)]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -229,6 +232,17 @@ class Plan:
         """Time step of the next steps of instance i (variable-step scheme)."""
         self._c(lib().etd_set_tau(self._ptr, i, float(tau)))
         self.instances[i].tau = float(tau)
+
+    def surface_lapinv(self, i, g, f, mask, tol=1e-12, max_iter=20000, psi=None):
+        """psi = (-Delta_S,h)^{-1} f on the band {mask != 0} of instance i's grid;
+        returns (psi, iterations, final relative residual)."""
+        import torch
+        assert g.dtype == f.dtype and mask.dtype == torch.uint8
+        psi = torch.empty_like(f) if psi is None else psi
+        it, rr = C.c_int(0), C.c_double(0.0)
+        self._c(lib().etd_surface_lapinv(self._ptr, i, self._dev(g), self._dev(f), self._dev(mask), self._dev(psi),
+                                         self._dt(f), float(tol), int(max_iter), C.byref(it), C.byref(rr)))
+        return psi, it.value, rr.value
 
     def get_state(self, i, dtype=None):
         import torch

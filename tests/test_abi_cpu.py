@@ -54,7 +54,8 @@ def _desc(model=etd.COUPLED, shape=(16, 16, 16), tau=1e-4, scheme=2, prec=0):
     (lambda d: setattr(d[0].coupled.contents, "gamma", float("inf")), etd.ETD_E_ARG),
     (lambda d: setattr(d[0], "recover_threshold", -1.0), etd.ETD_E_ARG),
     (lambda d: (setattr(d[0], "band_threshold", 0.995), setattr(d[0], "band_rebuild_every", 0)), etd.ETD_E_ARG),
-    (lambda d: setattr(d[0], "flags", 0x4), etd.ETD_E_ARG),                               # unknown flag bit
+    (lambda d: setattr(d[0], "flags", 0x8), etd.ETD_E_ARG),                               # unknown flag bit
+    (lambda d: setattr(d[0], "flags", etd.F_SURFACE_NONLOCAL), etd.ETD_E_ARG),            # band solve without a band
 ])
 def test_plan_create_rejects_invalid_descriptors(mutate, status):
     L = etd.lib()
@@ -88,6 +89,7 @@ def test_null_arguments_and_status_strings():
     assert L.etd_plan_create(d, 0, None, C.byref(p)) == etd.ETD_E_ARG
     assert L.etd_step(None, 1) == etd.ETD_E_ARG
     assert L.etd_set_tau(None, 0, 1e-4) == etd.ETD_E_ARG
+    assert L.etd_surface_lapinv(None, 0, None, None, None, None, 0, 1e-12, 10, None, None) == etd.ETD_E_ARG
     assert L.etd_plan_destroy(None) == etd.ETD_OK
     for s in range(-7, 1):
         assert L.etd_status_string(s)
