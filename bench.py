@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-fixed", action="store_true",
                     help="skip the 128^3 fixed-membrane measurement")
     ap.add_argument("--fixed-n", type=int, default=128)
+    ap.add_argument("--no-surface", action="store_true",
+                    help="skip the band-solve leg ((-Delta_S,h)^{-1} on the band, 256^3)")
+    ap.add_argument("--surface-n", type=int, default=256)
+    ap.add_argument("--surface-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -182,6 +186,34 @@ def band_measure(n, steps, warmup):
                                      "pointwise_and_reductions": group(("pointwise", "reduce"))},
             "band_kernels_per_rebuild_ms": passes["band"]["ms"] / max(1, passes["band"]["launches"]),
             "ledger": ledger(passes, 10, npts, ms)}
+
+
+def surface_measure(n, steps):
+    """Coupled FP32 ETDRK2 at n^3 with the narrow band |2 phi - 1| < 0.995 and
+    the nonlocal term by the band solve of (-Delta_S,h)^{-1}
+    (ETD_F_SURFACE_NONLOCAL): step time, iterations and final relative
+    residual of the last solve, beside the same step with (-Delta_h)^{-1}."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    ci = inputs.coupled_membrane(n=n, tau=1e-4)
+    out = {"workload": f"coupled ETDRK2 FP32, {n}^3 grid, eps=3h, tau=1e-4, band |2 phi - 1| < 0.995, nonlocal "
+                       f"term by the band solve (FP64 Jacobi-PCG, relative residual 1e-9)", "grid": [n, n, n],
+           "steps": steps}
+    for name, flags in (("band_solve", etd.F_SURFACE_NONLOCAL), ("fft_inverse", 0)):
+        plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32, band_threshold=0.995,
+                                             band_rebuild_every=10, flags=flags))
+        plan.set_state(0, torch.as_tensor(ci.phi0, dtype=torch.float32, device="cuda"),
+                       torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
+        ms = timed_steps(plan, steps, 1) / steps
+        r = {"ms_per_step": ms, "value": n ** 3 / (ms * 1e-3), "unit": "grid-pt steps/s"}
+        if flags:
+            r["iterations_last_solve"] = plan.query(0, etd.Q_SURF_ITERS)
+            r["relres_last_solve"] = plan.query(0, etd.Q_SURF_RELRES)
+            r["band_points"] = plan.diagnostics(0)["band_count"]
+        out[name] = r
+        plan.close()
+    return out
 
 
 def fixed_measure(n, warmup):
@@ -410,6 +442,13 @@ def main():
         log(f"frozen-membrane coupled u stages {a.fixed_n}^3: fp64 {fz['fp64']['ms_per_step']:.3f} ms/step, "
             f"fp32 {fz['fp32']['ms_per_step']:.3f} ms/step, U in [{fz['fp64']['umin']:.4g}, {fz['fp64']['umax']:.4g}], "
             f"E_u {fz['fp64']['energy_u_start']:.6g} -> {fz['fp64']['energy_u_end']:.6g}")
+    if not a.no_surface:
+        out["surface"] = surface_measure(a.surface_n, a.surface_steps)
+        sf = out["surface"]
+        log(f"band solve {a.surface_n}^3: {sf['band_solve']['ms_per_step']:.2f} ms/step "
+            f"({sf['band_solve']['iterations_last_solve']:.0f} PCG iterations, relres "
+            f"{sf['band_solve']['relres_last_solve']:.1e}, {sf['band_solve']['band_points']} band points) vs "
+            f"{sf['fft_inverse']['ms_per_step']:.3f} ms/step with (-Delta_h)^-1")
     if not a.no_batch:
         out["batched"] = batch_measure(a.batch_steps, a.warmup)
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "

@@ -253,14 +253,16 @@ def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) ->
     the nodes with mask != 0; a face enters when both of its nodes are on the
     band (faces to nodes off the band carry no flux); the mean removed from f
     and from the solution is the plain mean over the band nodes; the result
-    is 0 off the band.  The band must be connected (else the constrained
-    system below is singular).
+    is 0 off the band.  The band must be connected (else the reduced system
+    below is singular).
 
     The band matrix A (row i: sum over band neighbours j of w_ij (psi_i -
-    psi_j), w_ij = g_face / h_d^2) is assembled edge by edge; the
-    mean-zero solution comes from the bordered system
-        [A 1; 1^T 0] [psi; lam] = [f_B - mean(f_B); 0]
-    by scipy's sparse direct solver (the library primitive).
+    psi_j), w_ij = g_face / h_d^2) is assembled edge by edge.  Its null
+    space on a connected band is the constants and f_B - mean(f_B) lies in
+    its range, so one solution has psi at the first band node fixed to 0:
+    the remaining rows and columns are nonsingular and go to scipy's sparse
+    direct solver (the library primitive); the band mean of that solution is
+    then removed.
     """
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
@@ -288,13 +290,14 @@ def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) ->
     A = sp.coo_matrix((np.concatenate(vals + [diag]),
                        (np.concatenate(rows + [np.arange(nb)]), np.concatenate(cols + [np.arange(nb)]))),
                       shape=(nb, nb)).tocsr()
-    one = sp.csr_matrix(np.ones((nb, 1)))
-    K = sp.bmat([[A, one], [one.T, None]], format="csc")
     fb = np.asarray(f, dtype=np.float64).ravel()[B]
-    rhs = np.concatenate([fb - fb.mean(), [0.0]])
-    sol = spla.spsolve(K, rhs)
+    rhs = fb - fb.mean()
+    sol = np.zeros(nb)
+    if nb > 1:
+        sol[1:] = spla.spsolve(A[1:, 1:].tocsc(), rhs[1:])
+    sol -= sol.mean()
     out = np.zeros(m.size)
-    out[B] = sol[:nb]
+    out[B] = sol
     return out.reshape(shape)
 
 

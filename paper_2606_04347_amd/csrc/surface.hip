@@ -26,7 +26,7 @@ namespace etd {
 namespace {
 
 constexpr int kSbThreads = 256;
-constexpr int kSbBlocks = 512;
+constexpr int kSbBlocks = 4096;
 
 enum SbSlot { SB_RZ = 0, SB_PAP, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT };
 enum SbFinal { FIN_MEAN = 0, FIN_INIT, FIN_PAP, FIN_UPDATE, FIN_XMEAN };

@@ -14,7 +14,9 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
 def shell_case(n, thr=0.995, seed=31):
-    ci = inputs.coupled_membrane(n=n, seed=seed, tau=1e-4)
+    # interface width 1.5 h: a band of a few cells, small enough for the
+    # oracle's sparse direct solve
+    ci = inputs.coupled_membrane(n=n, seed=seed, tau=1e-4, eps_pm_in_h=1.5)
     g = 18.0 * (ci.phi0 * ci.phi0 - ci.phi0) ** 2
     mask = np.abs(2.0 * ci.phi0 - 1.0) < thr
     return ci, g, mask
@@ -73,7 +75,7 @@ def test_band_solve_2d_shell_and_full_band():
 
 @pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
 def test_coupled_step_with_band_solve_matches_oracle(scheme):
-    ci = inputs.coupled_membrane(n=(24, 24, 24), seed=31, tau=1e-4)
+    ci = inputs.coupled_membrane(n=(24, 24, 24), seed=31, tau=1e-4, eps_pm_in_h=1.5)
     grid = Grid(ci.shape, ci.half_len)
     o = CoupledOracle(grid, ci.params, ci.tau, scheme, band_threshold=0.995, band_rebuild_every=2,
                       surface_nonlocal=True)
