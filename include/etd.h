@@ -291,7 +291,7 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
  * preconditioner from psi = 0, until the relative residual is <= tol or
  * after max_iter iterations; *iters_out and *relres_out (host, nullable)
  * report the outcome -- not converging is reported there, not as an error.
- * Uses a workspace of about 44 bytes per grid point, allocated on the first
+ * Uses a workspace of about 60 bytes per grid point, allocated on the first
  * call and kept by the plan.  Synchronizes.
  * Errors: ETD_E_ARG (null pointers, dtype, tol not finite and > 0,
  * max_iter < 1), ETD_E_NOMEM, ETD_E_HIP. */

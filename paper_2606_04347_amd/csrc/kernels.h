@@ -143,11 +143,13 @@ void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const
 template <typename T>
 void band_flags(long n, const T* phi, double thr, uint8_t* flags, hipStream_t s);
 // (-Delta_S,h)^{-1} on a narrow band (surface.hip): FP64 Jacobi-preconditioned
-// conjugate gradients over the band list idx[0 .. *total) of mask.  Workspace
+// conjugate gradients (single-reduction form) over the band list
+// idx[0 .. *total) of mask.  Workspace
 // carved from one device allocation of surface_work_bytes(n) bytes (its own
 // band list buffers idx / cnt / total serve callers without one).
 struct SurfaceWork {
-    double *x = nullptr, *p = nullptr, *r = nullptr, *ap = nullptr, *dinv = nullptr;
+    double *x = nullptr, *u = nullptr;                                                // grid layout
+    double *r = nullptr, *p = nullptr, *s = nullptr, *w = nullptr, *dinv = nullptr;   // band order
     int32_t* idx = nullptr;
     int64_t *cnt = nullptr, *total = nullptr;
     double *part = nullptr, *S = nullptr;

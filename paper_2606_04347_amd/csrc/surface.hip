@@ -11,11 +11,13 @@
 // the band mean of the iterate is removed at the end and psi = 0 off the
 // band.
 //
-// Every iteration runs five fixed-grid launches (the partial sums of the two
-// dot products are taken per workgroup in a fixed order and closed by a
-// one-workgroup kernel, so results do not depend on scheduling); the step
-// scalars (alpha, beta, the residual norms, a done flag) live in device
-// memory, and every kernel returns at once when the flag is set.
+// The iteration is the single-reduction (Chronopoulos-Gear) form of PCG:
+// one vector-update launch, one launch for the product w = A u with all
+// three dot products, and a one-workgroup launch that closes the partial
+// sums (taken per workgroup in a fixed order, so results do not depend on
+// scheduling) and forms the step scalars.  The scalars (alpha, beta, the
+// residual norms, a done flag) live in device memory, and every kernel
+// returns at once when the flag is set.
 #include <algorithm>
 #include <cmath>
 
@@ -28,8 +30,10 @@ namespace {
 constexpr int kSbThreads = 256;
 constexpr int kSbBlocks = 4096;
 
-enum SbSlot { SB_RZ = 0, SB_PAP, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT };
-enum SbFinal { FIN_MEAN = 0, FIN_INIT, FIN_PAP, FIN_UPDATE, FIN_XMEAN };
+enum SbSlot {
+    SB_GAMMA = 0, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT
+};
+enum SbFinal { FIN_MEAN = 0, FIN_START, FIN_STEP, FIN_XMEAN };
 
 struct BandGeom {
     int nx, ny, nz;
@@ -59,14 +63,16 @@ template <class F> __device__ __forceinline__ void for_neighbours(const BandGeom
     }
 }
 
-// Two block partials per workgroup: part[2 blockIdx.x + c].
-__device__ __forceinline__ void store_partials(double a, double b, double* part) {
+// Three block partials per workgroup: part[3 blockIdx.x + c].
+__device__ __forceinline__ void store_partials(double a, double b, double c, double* part) {
     __shared__ double sh[kSbThreads];
     const double ta = block_sum_256(a, sh);
     const double tb = block_sum_256(b, sh);
+    const double tc = block_sum_256(c, sh);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = ta;
-        part[2 * blockIdx.x + 1] = tb;
+        part[3 * blockIdx.x] = ta;
+        part[3 * blockIdx.x + 1] = tb;
+        part[3 * blockIdx.x + 2] = tc;
     }
 }
 
@@ -91,86 +97,76 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
         dinv[k] = d > 0.0 ? 1.0 / d : 0.0;
         acc.add((double)f[i]);
     }
-    store_partials(acc.val(), 0.0, part);
+    store_partials(acc.val(), 0.0, 0.0, part);
 }
 
-// r = f - mean, z = D^-1 r, p = z, x = 0 (band nodes); partials r.z, r.r.
+// r = f - mean, u = D^-1 r, x = 0, p = s = 0 (band nodes); clears the done
+// flag of an earlier solve.
 template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_init(const T* __restrict__ f, const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total,
-                                                        const double* __restrict__ dinv, const double* S, double* x,
-                                                        double* p, double* r, double* part) {
+                                                        const double* __restrict__ dinv, double* S, double* x,
+                                                        double* u, double* r, double* p, double* sv) {
     const long nb = *total;
     const double mean = S[SB_MEAN];
-    Neu rz, rr;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
         const double rk = (double)f[i] - mean;
-        const double z = rk * dinv[k];
         r[k] = rk;
-        p[i] = z;
+        u[i] = rk * dinv[k];
         x[i] = 0.0;
-        rz.add(rk * z);
-        rr.add(rk * rk);
+        p[k] = 0.0;
+        sv[k] = 0.0;
     }
-    store_partials(rz.val(), rr.val(), part);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S[SB_DONE] = 0.0;
 }
 
-// ap = A p on the band; partial p.ap.
+// w = A u on the band; partials (r, u), (w, u), (r, r).
 template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* __restrict__ G,
                                                           const uint8_t* __restrict__ mask,
                                                           const int32_t* __restrict__ idx,
                                                           const int64_t* __restrict__ total, const double* S,
-                                                          const double* __restrict__ p, double* ap, double* part) {
+                                                          const double* __restrict__ u, const double* __restrict__ r,
+                                                          double* w, double* part) {
     if (sb_done(S)) return;
     const long nb = *total;
-    Neu pap;
+    Neu ru, wu, rr;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
-        const double gi = (double)G[i], pi = p[i];
+        const double gi = (double)G[i], ui = u[i];
         double a = 0.0;
         for_neighbours(b, i, [&](long j, double ih2) {
-            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (pi - p[j]);
+            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (ui - u[j]);
         });
-        ap[k] = a;
-        pap.add(pi * a);
-    }
-    store_partials(pap.val(), 0.0, part);
-}
-
-// x += alpha p, r -= alpha ap; partials r.z, r.r with z = D^-1 r.
-__global__ __launch_bounds__(kSbThreads) void k_sb_update(const int32_t* __restrict__ idx,
-                                                          const int64_t* __restrict__ total,
-                                                          const double* __restrict__ dinv, const double* S,
-                                                          double* x, const double* __restrict__ p, double* r,
-                                                          const double* __restrict__ ap, double* part) {
-    if (sb_done(S)) return;
-    const long nb = *total;
-    const double alpha = S[SB_ALPHA];
-    Neu rz, rr;
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
-        const long i = idx[k];
-        x[i] += alpha * p[i];
-        const double rk = r[k] - alpha * ap[k];
-        r[k] = rk;
-        rz.add(rk * (rk * dinv[k]));
+        w[k] = a;
+        const double rk = r[k];
+        ru.add(rk * ui);
+        wu.add(a * ui);
         rr.add(rk * rk);
     }
-    store_partials(rz.val(), rr.val(), part);
+    store_partials(ru.val(), wu.val(), rr.val(), part);
 }
 
-// p = D^-1 r + beta p.
-__global__ __launch_bounds__(kSbThreads) void k_sb_direction(const int32_t* __restrict__ idx,
-                                                             const int64_t* __restrict__ total,
-                                                             const double* __restrict__ dinv, const double* S,
-                                                             double* p, const double* __restrict__ r) {
+// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = D^-1 r.
+__global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __restrict__ idx,
+                                                           const int64_t* __restrict__ total,
+                                                           const double* __restrict__ dinv, const double* S,
+                                                           double* x, double* u, double* r, double* p, double* sv,
+                                                           const double* __restrict__ w) {
     if (sb_done(S)) return;
     const long nb = *total;
-    const double beta = S[SB_BETA];
+    const double alpha = S[SB_ALPHA], beta = S[SB_BETA];
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
-        p[i] = r[k] * dinv[k] + beta * p[i];
+        const double pk = u[i] + beta * p[k];
+        const double sk = w[k] + beta * sv[k];
+        p[k] = pk;
+        sv[k] = sk;
+        x[i] += alpha * pk;
+        const double rk = r[k] - alpha * sk;
+        r[k] = rk;
+        u[i] = rk * dinv[k];
     }
 }
 
@@ -182,7 +178,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_xsum(const int32_t* __restric
     Neu acc;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads)
         acc.add(x[idx[k]]);
-    store_partials(acc.val(), 0.0, part);
+    store_partials(acc.val(), 0.0, 0.0, part);
 }
 
 // psi = x - mean_band(x) on the band, 0 elsewhere.
@@ -194,43 +190,52 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_out(long n, const uint8_t* __
         psi[i] = mask[i] ? (T)(x[i] - m) : (T)0;
 }
 
-// Closes the partial sums of one kernel (fixed order) and updates the scalars.
+// Closes the partial sums of one kernel (fixed order) and updates the step
+// scalars of the single-reduction (Chronopoulos-Gear) form of PCG:
+//   gamma = (r, u), delta = (w, u), beta = gamma / gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old).
 __global__ __launch_bounds__(kSbThreads) void k_sb_final(int mode, const double* __restrict__ part,
                                                          const int64_t* __restrict__ total, double tol2, double* S) {
-    if ((mode == FIN_PAP || mode == FIN_UPDATE) && sb_done(S)) return;
+    if ((mode == FIN_START || mode == FIN_STEP) && sb_done(S)) return;
     __shared__ double sh[kSbThreads];
-    Neu a, b;
+    Neu a, b, c;
     for (int k = threadIdx.x; k < kSbBlocks; k += kSbThreads) {
-        a.add(part[2 * k]);
-        b.add(part[2 * k + 1]);
+        a.add(part[3 * k]);
+        b.add(part[3 * k + 1]);
+        c.add(part[3 * k + 2]);
     }
     const double sa = block_sum_256(a.val(), sh);
     const double sb = block_sum_256(b.val(), sh);
+    const double sc = block_sum_256(c.val(), sh);
     if (threadIdx.x != 0) return;
     const double nb = (double)*total;
     switch (mode) {
         case FIN_MEAN:
             S[SB_MEAN] = nb > 0 ? sa / nb : 0.0;
             break;
-        case FIN_INIT:
-            S[SB_RZ] = sa;
-            S[SB_RR] = sb;
-            S[SB_RR0] = sb;
+        case FIN_START:
+            S[SB_GAMMA] = sa;
+            S[SB_RR] = sc;
+            S[SB_RR0] = sc;
             S[SB_ITER] = 0.0;
-            S[SB_DONE] = (sb > 0.0) ? 0.0 : 1.0;
-            break;
-        case FIN_PAP:
-            S[SB_PAP] = sa;
-            if (sa > 0.0) S[SB_ALPHA] = S[SB_RZ] / sa;
+            S[SB_BETA] = 0.0;
+            if (sc > 0.0 && sb > 0.0) S[SB_ALPHA] = sa / sb;
             else S[SB_DONE] = 1.0;
             break;
-        case FIN_UPDATE:
-            S[SB_BETA] = S[SB_RZ] > 0.0 ? sa / S[SB_RZ] : 0.0;
-            S[SB_RZ] = sa;
-            S[SB_RR] = sb;
+        case FIN_STEP: {
             S[SB_ITER] += 1.0;
-            if (sb <= tol2 * S[SB_RR0]) S[SB_DONE] = 1.0;
+            S[SB_RR] = sc;
+            const double beta = S[SB_GAMMA] > 0.0 ? sa / S[SB_GAMMA] : 0.0;
+            const double denom = sb - beta * sa / S[SB_ALPHA];
+            if (sc <= tol2 * S[SB_RR0] || !(denom > 0.0)) {
+                S[SB_DONE] = 1.0;
+                break;
+            }
+            S[SB_BETA] = beta;
+            S[SB_ALPHA] = sa / denom;
+            S[SB_GAMMA] = sa;
             break;
+        }
         case FIN_XMEAN:
             S[SB_XMEAN] = nb > 0 ? sa / nb : 0.0;
             break;
@@ -250,14 +255,16 @@ static size_t surface_layout(long n, char* base, SurfaceWork* w) {
     };
     SurfaceWork t;
     t.x = (double*)take(n * sizeof(double));
-    t.p = (double*)take(n * sizeof(double));
+    t.u = (double*)take(n * sizeof(double));
     t.r = (double*)take(n * sizeof(double));
-    t.ap = (double*)take(n * sizeof(double));
+    t.p = (double*)take(n * sizeof(double));
+    t.s = (double*)take(n * sizeof(double));
+    t.w = (double*)take(n * sizeof(double));
     t.dinv = (double*)take(n * sizeof(double));
     t.idx = (int32_t*)take(n * sizeof(int32_t));
     t.cnt = (int64_t*)take((band_blocks(n) + 2) * sizeof(int64_t));
     t.total = (int64_t*)take(sizeof(int64_t));
-    t.part = (double*)take(2 * kSbBlocks * sizeof(double));
+    t.part = (double*)take(3 * kSbBlocks * sizeof(double));
     t.S = (double*)take(16 * sizeof(double));
     if (w) *w = t;
     return off;
@@ -277,22 +284,25 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     auto fin = [&](int mode) {
         hipLaunchKernelGGL(k_sb_final, dim3(1), blk, 0, s, mode, w.part, total, tol2, w.S);
     };
+    auto matvec = [&]() {
+        hipLaunchKernelGGL(k_sb_matvec<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.u, w.r, w.w, w.part);
+    };
     hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, G, f, mask, idx, total, w.dinv, w.part);
     fin(FIN_MEAN);
-    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.p, w.r, w.part);
-    fin(FIN_INIT);
+    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.u, w.r, w.p, w.s);
+    matvec();
+    fin(FIN_START);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // iterate in chunks; the host reads the done flag between chunks
+    // three launches per iteration; the host reads the done flag every 25
     constexpr int kChunk = 25;
     double done = 0.0;
     for (int it = 0; it < max_iter && done == 0.0; it += kChunk) {
         for (int j = 0; j < kChunk && it + j < max_iter; ++j) {
-            hipLaunchKernelGGL(k_sb_matvec<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.p, w.ap, w.part);
-            fin(FIN_PAP);
-            hipLaunchKernelGGL(k_sb_update, grid, blk, 0, s, idx, total, w.dinv, w.S, w.x, w.p, w.r, w.ap, w.part);
-            fin(FIN_UPDATE);
-            hipLaunchKernelGGL(k_sb_direction, grid, blk, 0, s, idx, total, w.dinv, w.S, w.p, w.r);
+            hipLaunchKernelGGL(k_sb_vectors, grid, blk, 0, s, idx, total, w.dinv, w.S, w.x, w.u, w.r, w.p, w.s,
+                               w.w);
+            matvec();
+            fin(FIN_STEP);
         }
         if ((e = hipMemcpyAsync(&done, w.S + SB_DONE, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
             return e;
@@ -310,7 +320,7 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
         res->iters = (int)sc[SB_ITER];
         res->relres = sc[SB_RR0] > 0.0 ? std::sqrt(sc[SB_RR] / sc[SB_RR0]) : 0.0;
-        res->converged = sc[SB_DONE] != 0.0 && (sc[SB_RR0] == 0.0 || sc[SB_RR] <= tol2 * sc[SB_RR0]);
+        res->converged = sc[SB_RR0] == 0.0 || sc[SB_RR] <= tol2 * sc[SB_RR0];
     }
     return hipSuccess;
 }
