@@ -104,14 +104,18 @@ typedef struct {
                                       with g = g(phi) and v = 0 (the stabilized spectral
                                       scheme of Section 3.1 on a fixed membrane); other
                                       models reject it with ETD_E_ARG */
-#define ETD_F_SURFACE_NONLOCAL 0x4u /* coupled model with a band only: the nonlocal term of
-                                      R2 uses (-Delta_S,h)^{-1} (Section 2.1, operator:diff,
-                                      with g = g+ of the stage) assembled and solved on the
-                                      band (Section 3.2), as etd_surface_lapinv does, in place
-                                      of the constant-coefficient (-Delta_h)^{-1} by FFT.  The
-                                      solve checks convergence on the host, so plans with this
-                                      flag step eagerly under every schedule.  The energy
-                                      diagnostic keeps (-Delta_h)^{-1}. */
+#define ETD_F_SURFACE_NONLOCAL 0x4u /* needs band_threshold > 0: the nonlocal term uses
+                                      (-Delta_S,h)^{-1} (Section 2.1, operator:diff) assembled
+                                      and solved on a band (Section 3.2), as etd_surface_lapinv
+                                      does, in place of the constant-coefficient (-Delta_h)^{-1}
+                                      by FFT.  Coupled model: in R2, with g = g+ of the stage
+                                      and the band |2 phi - 1| < band_threshold.  Fixed model:
+                                      in R_phi, with the fixed g and the band
+                                      {g >= band_threshold} (the paper's delta), built by
+                                      etd_set_state; FP64 on both of its paths.  The solve
+                                      checks convergence on the host, so plans with this flag
+                                      step eagerly under every schedule.  The energy
+                                      diagnostics keep (-Delta_h)^{-1}. */
 
 /* One simulation instance. */
 typedef struct {

@@ -243,29 +243,13 @@ def lapinv(f: np.ndarray, grid: Grid) -> np.ndarray:
     return ifft(inv * fft(f))
 
 
-def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) -> np.ndarray:
-    """(-Delta_{S,h})^{-1} f assembled and solved on a narrow band.
-
-    Section 2.1 (operator:diff) defines Delta_{S,h} with face coefficients
-    g_{i+1/2} = (g_i + g_{i+1})/2 and its inverse on mean-zero functions,
-    extended to any f by removing the mean; Section 3.2 assembles and solves
-    the nonlocal problem only on the band nodes.  Reading: the unknowns are
-    the nodes with mask != 0; a face enters when both of its nodes are on the
-    band (faces to nodes off the band carry no flux); the mean removed from f
-    and from the solution is the plain mean over the band nodes; the result
-    is 0 off the band.  The band must be connected (else the reduced system
-    below is singular).
-
-    The band matrix A (row i: sum over band neighbours j of w_ij (psi_i -
-    psi_j), w_ij = g_face / h_d^2) is assembled edge by edge.  Its null
-    space on a connected band is the constants and f_B - mean(f_B) lies in
-    its range, so one solution has psi at the first band node fixed to 0:
-    the remaining rows and columns are nonsingular and go to scipy's sparse
-    direct solver (the library primitive); the band mean of that solution is
-    then removed.
-    """
+def band_matrix(g: np.ndarray, mask: np.ndarray, grid: Grid):
+    """Band nodes B (flat indices, ascending) and the band matrix A of
+    -Delta_{S,h} (operator:diff, Section 2.1) restricted to them: row i is
+    sum over band neighbours j of w_ij (psi_i - psi_j), w_ij = (g_i + g_j) /
+    (2 h_d^2); faces with a node off the band are left out.  Assembled edge
+    by edge (each face once, along +e_d, periodic)."""
     import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
     m = np.asarray(mask).astype(bool)
     B = np.flatnonzero(m.ravel())
     nb = B.size
@@ -290,6 +274,32 @@ def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) ->
     A = sp.coo_matrix((np.concatenate(vals + [diag]),
                        (np.concatenate(rows + [np.arange(nb)]), np.concatenate(cols + [np.arange(nb)]))),
                       shape=(nb, nb)).tocsr()
+    return B, A
+
+
+def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) -> np.ndarray:
+    """(-Delta_{S,h})^{-1} f assembled and solved on a narrow band.
+
+    Section 2.1 (operator:diff) defines Delta_{S,h} with face coefficients
+    g_{i+1/2} = (g_i + g_{i+1})/2 and its inverse on mean-zero functions,
+    extended to any f by removing the mean; Section 3.2 assembles and solves
+    the nonlocal problem only on the band nodes.  Reading: the unknowns are
+    the nodes with mask != 0; a face enters when both of its nodes are on the
+    band (faces to nodes off the band carry no flux); the mean removed from f
+    and from the solution is the plain mean over the band nodes; the result
+    is 0 off the band.  The band must be connected (else the reduced system
+    below is singular).
+
+    With A = band_matrix(...): its null space on a connected band is the
+    constants and f_B - mean(f_B) lies in its range, so one solution has psi
+    at the first band node fixed to 0: the remaining rows and columns are
+    nonsingular and go to scipy's sparse direct solver (the library
+    primitive); the band mean of that solution is then removed.
+    """
+    import scipy.sparse.linalg as spla
+    m = np.asarray(mask).astype(bool)
+    B, A = band_matrix(g, m, grid)
+    nb = B.size
     fb = np.asarray(f, dtype=np.float64).ravel()[B]
     rhs = fb - fb.mean()
     sol = np.zeros(nb)
@@ -298,7 +308,20 @@ def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) ->
     sol -= sol.mean()
     out = np.zeros(m.size)
     out[B] = sol
-    return out.reshape(shape)
+    return out.reshape(m.shape)
+
+
+def lapinv_S_band_inf_norm(g: np.ndarray, mask: np.ndarray, grid: Grid) -> float:
+    """C = ||(-Delta_{S,h})^{-1}||_inf on a band (the constant of the MBP
+    condition, Section 2.1) by a dense computation: the operator is
+    X = A^+ (I - 11^T / nb) (Moore-Penrose inverse of the band matrix after
+    the mean removal, numpy's pinv the library primitive), C its largest
+    absolute row sum.  Small bands only (dense nb x nb)."""
+    B, A = band_matrix(g, mask, grid)
+    nb = B.size
+    Ad = A.toarray()
+    X = np.linalg.pinv(Ad) @ (np.eye(nb) - np.full((nb, nb), 1.0 / nb))
+    return float(np.abs(X).sum(axis=1).max())
 
 
 def lapinv_inf_norm(grid: Grid) -> float:

@@ -46,6 +46,9 @@ class FixedParams:
     ubar: float
     B: float
     nonlocal_with_ubar: bool = False
+    # > 0: the nonlocal term by (-Delta_{S,h})^{-1} solved on the band
+    # {g >= band_delta} (Section 3.2; core.lapinv_S_band) instead of (-Delta_h)^{-1}
+    band_delta: float = 0.0
 
 
 def B_mbp(eps_u, gamma, M, C, vol):
@@ -71,7 +74,10 @@ def nonlocal_arg(U, g, p: FixedParams):
 def R_phi(U, g, p: FixedParams, grid: Grid) -> np.ndarray:
     """Nonlinear remainder R(U) of the localization split."""
     sg = np.sqrt(g)
-    psi = core.lapinv(nonlocal_arg(U, g, p), grid)
+    if p.band_delta > 0.0:
+        psi = core.lapinv_S_band(nonlocal_arg(U, g, p), g, g >= p.band_delta, grid)
+    else:
+        psi = core.lapinv(nonlocal_arg(U, g, p), grid)
     mf = mass_f(U, g, p, grid)
     fp = core.fp_ind(U)
     return (p.B * sg * U - sg * core.Wp(U) / p.eps_u

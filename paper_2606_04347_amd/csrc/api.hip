@@ -62,8 +62,8 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
     if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE | ETD_F_SURFACE_NONLOCAL)) {
         msg = "unknown flag bits"; return ETD_E_ARG;
     }
-    if ((d.flags & ETD_F_SURFACE_NONLOCAL) && (d.model != ETD_COUPLED || !(d.band_threshold > 0.0))) {
-        msg = "ETD_F_SURFACE_NONLOCAL needs the coupled model with a band"; return ETD_E_ARG;
+    if ((d.flags & ETD_F_SURFACE_NONLOCAL) && !(d.band_threshold > 0.0)) {
+        msg = "ETD_F_SURFACE_NONLOCAL needs a band (band_threshold > 0)"; return ETD_E_ARG;
     }
     if ((d.flags & ETD_F_FROZEN_MEMBRANE) && d.model != ETD_COUPLED) {
         msg = "ETD_F_FROZEN_MEMBRANE applies to the coupled model only"; return ETD_E_ARG;
@@ -263,6 +263,13 @@ etd_status setup_fixed(etd_plan* P, Instance& I) {
         ALLOC(I.Sb, ns * sizeof(float2));
         ALLOC(I.Sgu, ns * sizeof(float2));
         if ((st = make_tables<float>(P, I, I.tf)) != ETD_OK) return st;
+    }
+    if (I.d.flags & ETD_F_SURFACE_NONLOCAL) {   // band {g >= band_threshold}, listed at set_state
+        ALLOC(I.mask, nr);
+        ALLOC(I.band_idx, nr * sizeof(int32_t));
+        ALLOC(I.band_cnt, (band_blocks((long)nr) + 2) * sizeof(int64_t));
+        ALLOC(I.band_total, sizeof(int64_t));
+        if ((st = ensure_surface(P, I)) != ETD_OK) return st;
     }
     const etd_fixed_params& p = I.fp;
     I.FK.eps_u = p.eps_u; I.FK.gamma = p.gamma; I.FK.ubar = p.ubar; I.FK.M = p.M;
@@ -519,9 +526,14 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
 
 // ------------------------------------------------------------------ fixed step
 // psi = (-Delta_h)^{-1} q  (FP64, or FP32 transforms on the FP32-FFT path)
+// With ETD_F_SURFACE_NONLOCAL: psi = (-Delta_S,h)^{-1} q on the band {g >= delta}
+// (FP64 band solve on both paths).
 etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStream_t s) {
     const GridK& g = I.g;
-    if (!I.f32) {
+    if (I.d.flags & ETD_F_SURFACE_NONLOCAL) {
+        HIPCHK(plan, surface_lapinv<double>(g, I.G, q, I.mask, I.band_idx, I.band_total, I.psid, I.sw, 1e-12, 20000,
+                                            &I.surf_last, s));
+    } else if (!I.f32) {
         HIPCHK(plan, lapinv_fused<double>(g, I.td, I.fd, q, (double2*)I.Sa, I.psid, s));
     } else {
         convert<double, float>(g.nreal(), q, I.qf, s);
@@ -539,8 +551,10 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     etd_status st = fixed_nonlocal(plan, I, I.q, s);
     if (st != ETD_OK) return st;
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
-        if (!I.f32) fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
-        else fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
+        if (!I.f32 || (I.d.flags & ETD_F_SURFACE_NONLOCAL))
+            fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
+        else
+            fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
     });
     return ETD_OK;
 }
@@ -663,6 +677,11 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
     const double gmin = -dg[3];
     if (!(gmin > 0.0) || dg[6] > 0.0 || !std::isfinite(host[0]))
         return fail(&plan->err, ETD_E_ARG, "g must be finite and strictly positive");
+    if (I.d.flags & ETD_F_SURFACE_NONLOCAL) {
+        band_ge<double>(n, I.G, I.d.band_threshold, I.mask, s);
+        band_compact(n, I.mask, I.band_cnt, I.band_idx, n, I.band_total, s);
+        HIPCHK(plan, hipGetLastError());
+    }
     I.rho = host[0];
     I.a = I.FK.B;
     I.b = I.FK.B + I.FK.eps_u * I.rho;

@@ -159,6 +159,8 @@ struct SurfaceResult {
     double relres = 0.0;
     bool converged = false;
 };
+// mask[i] = G[i] >= delta (the band {g >= delta} of Section 3.2).
+template <typename T> void band_ge(long n, const T* G, double delta, uint8_t* mask, hipStream_t s);
 size_t surface_work_bytes(long n);
 void surface_work_carve(long n, void* base, SurfaceWork& w);
 // psi = (-Delta_S,h)^{-1} f on the band (0 off it); stops when the relative

@@ -242,7 +242,20 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_final(int mode, const double*
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_band_ge(long n, const T* __restrict__ G, double delta,
+                                                        uint8_t* mask) {
+    for (long i = (long)blockIdx.x * kSbThreads + threadIdx.x; i < n; i += (long)gridDim.x * kSbThreads)
+        mask[i] = (double)G[i] >= delta ? 1 : 0;
+}
+
 }  // namespace
+
+template <typename T> void band_ge(long n, const T* G, double delta, uint8_t* mask, hipStream_t s) {
+    const int nb = (int)std::min<long>(4096, (n + kSbThreads - 1) / kSbThreads);
+    hipLaunchKernelGGL(k_band_ge<T>, dim3(nb), dim3(kSbThreads), 0, s, n, G, delta, mask);
+}
+template void band_ge<double>(long, const double*, double, uint8_t*, hipStream_t);
 
 // Lays the workspace out from base (256-byte aligned pieces) and returns the
 // bytes it spans; with base == nullptr only the size is computed.

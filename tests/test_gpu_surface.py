@@ -93,3 +93,29 @@ def test_coupled_step_with_band_solve_matches_oracle(scheme):
     assert ephi <= 1e-12 and eu <= 1e-10
     assert plan.query(0, etd.Q_SURF_RELRES) <= 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("scheme,precision", [(etd.ETD1, etd.FP64), (etd.ETDRK2, etd.FP64), (etd.ETDRK2, etd.FP32)])
+def test_fixed_step_with_band_solve_matches_oracle(scheme, precision):
+    """The fixed-membrane step with R_phi's nonlocal term by the band solve on
+    {g >= 1e-3} (both of its paths take the FP64 solve) against the U-space
+    oracle with the same band."""
+    from oracle import fixed
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+    grid = Grid(fi.shape, fi.half_len)
+    B = fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, core.lapinv_inf_norm(grid), grid.volume)
+    p = fixed.FixedParams(fi.eps_u, fi.gamma, fi.M, fi.ubar, B, False, 1e-3)
+    ex = fixed.UspaceExpo(fi.g, p, grid, fi.tau)
+    U = fi.u0.copy()
+    for _ in range(5):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, scheme, ex)
+    plan = etd.Plan(etd.fixed_instance(fi, scheme=scheme, precision=precision, band_threshold=1e-3,
+                                       flags=etd.F_SURFACE_NONLOCAL))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    plan.step(5)
+    _, u = plan.get_state(0)
+    err = rel_linf(host(u), U)
+    report("fixed_surface_nonlocal", scheme=scheme, precision=precision, err=err,
+           iters=plan.query(0, etd.Q_SURF_ITERS))
+    assert err <= 1e-11
+    plan.close()

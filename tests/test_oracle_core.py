@@ -219,6 +219,33 @@ def test_surface_band_inverse_on_a_shell_by_loops():
     assert abs((p1 * c2)[mask].sum() - (c1 * p2)[mask].sum()) <= 1e-10 * abs((p1 * c2)[mask].sum())
 
 
+def test_surface_band_inverse_norm():
+    """C = ||(-Delta_S,h)^{-1}||_inf on a band: with g = 1 on the whole grid it
+    is the circulant C of (-Delta_h)^{-1}; on a shell with variable g the
+    dense X = A^+ (I - 11^T/nb) agrees column by column with the band solve
+    applied to unit vectors."""
+    grid = Grid((8, 8), (1.0, 1.25))
+    full = np.ones((8, 8), dtype=bool)
+    C = core.lapinv_S_band_inf_norm(np.ones((8, 8)), full, grid)
+    assert abs(C - core.lapinv_inf_norm(grid)) <= 1e-12 * C
+    shape = (12, 10)
+    grid = Grid(shape, (1.0, 1.0))
+    X = np.meshgrid(*[np.arange(n) - (n - 1) / 2 for n in shape], indexing="ij")
+    r = np.sqrt(X[0] ** 2 + X[1] ** 2)
+    mask = (r > 2.0) & (r < 4.2)
+    g = 1e-3 + np.random.default_rng(13).random(shape)
+    B = np.flatnonzero(mask.ravel())
+    cols = []
+    for j in B:
+        e = np.zeros(mask.size)
+        e[j] = 1.0
+        cols.append(core.lapinv_S_band(e.reshape(shape), g, mask, grid).ravel()[B])
+    Xs = np.array(cols).T
+    C_cols = float(np.abs(Xs).sum(axis=1).max())
+    C = core.lapinv_S_band_inf_norm(g, mask, grid)
+    assert abs(C - C_cols) <= 1e-9 * C
+
+
 def test_lapinv_norm_values():
     # values quoted for the 64^2 [-1,1)^2 and 128^3 [-1,1)^3 grids
     assert abs(core.lapinv_inf_norm(Grid((64, 64), (1.0, 1.0))) - 0.16784) < 5e-6

@@ -287,3 +287,31 @@ def test_uspace_expo_exact_for_constant_remainder_with_tiny_g():
     lhs = (U1.reshape(-1) - E0 @ fi.u0.reshape(-1))
     rhs = np.linalg.solve(Lt, (np.eye(n) - E0) @ c.reshape(-1))
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_band_nonlocal_enters_only_through_gamma():
+    """band_delta > 0 replaces (-Delta_h)^{-1} by the band solve in the gamma
+    term of R_phi only: with gamma = 0 the remainders agree bit for bit."""
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+    grid = Grid(fi.shape, fi.half_len)
+    U = fi.u0
+    out = {}
+    for gamma in (0.0, 5.0):
+        r = [fixed.R_phi(U, fi.g, fixed.FixedParams(fi.eps_u, gamma, fi.M, fi.ubar, 100.0, False, d), grid)
+             for d in (0.0, 1e-3)]
+        out[gamma] = r
+    assert np.array_equal(out[0.0][0], out[0.0][1])
+    assert np.abs(out[5.0][0] - out[5.0][1]).max() > 1e-6
+
+
+def test_band_inverse_norm_of_the_config1_circle():
+    """C of the band inverse for the 64^2 circle of config 1 on {g >= 1e-3},
+    by the dense oracle, beside the circulant C of (-Delta_h)^{-1}: the band
+    operator has much weaker coefficients (g <= 9/8, small at the band edge),
+    so its inverse is larger; both are finite and positive."""
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    grid = Grid(fi.shape, fi.half_len)
+    Cb = core.lapinv_S_band_inf_norm(fi.g, fi.g >= 1e-3, grid)
+    C = core.lapinv_inf_norm(grid)
+    print(f"C band {Cb:.6g}, C periodic {C:.6g}")
+    assert np.isfinite(Cb) and Cb > C > 0
