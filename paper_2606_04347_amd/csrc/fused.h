@@ -57,8 +57,9 @@ template <typename T> struct R1Fields {
     const double* int_phi;
     double A0;
 };
-// Sources of P2 (Section 3.1): u, G = g+, the velocity, psi = (-Delta_h)^{-1} q,
-// the band mask (nullable) and the device scalar m = h^3 sum q.
+// Sources of P2 (Section 3.1): u, G = g+, the velocity, psi = the nonlocal
+// inverse of q ((-Delta_h)^{-1} by FFT, or the band solve), the band mask
+// (nullable) and the device scalar m = h^3 sum q.
 template <typename T> struct P2Fields {
     const T *u, *G, *vx, *vy, *vz, *psi;
     const uint8_t* mask;
