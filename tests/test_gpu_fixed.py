@@ -195,3 +195,20 @@ def test_fixed_128cubed_tau_sweep_bound_and_energy():
     report("fixed3d_tau_sweep", errs=" ".join(f"{e:.3e}" for e in errs), fp32_gap=max(gaps))
     assert all(e1 < e0 for e0, e1 in zip(errs, errs[1:]))
     assert max(gaps) <= 1e-5
+
+
+def test_config1_200_steps_with_mass_projection():
+    """Config 1 (64^2 circle, ETD1, tau = 0.01, B = B_MBP, 200 steps) with the
+    per-step FP64 mean correction (ETD_F_MASS_PROJECT): <g U, 1>_h keeps its
+    initial value and U stays in [0, 1]."""
+    fi = inputs.fixed_membrane(dim=2, n=64)
+    plan = etd.Plan(etd.fixed_instance(fi, scheme=etd.ETD1, flags=etd.F_MASS_PROJECT))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    Q0 = plan.diagnostics(0)["Q"]
+    for _ in range(4):
+        plan.step(50)
+        d = plan.diagnostics(0)
+        assert abs(d["Q"] - Q0) <= 1e-12 * abs(Q0), (d["Q"], Q0)
+        assert d["umin"] >= 0.0 and d["umax"] <= 1.0
+    report("fixed_config1_mass", Q=Q0, drift=abs(d["Q"] - Q0) / abs(Q0), umin=d["umin"], umax=d["umax"])
+    plan.close()
