@@ -17,17 +17,31 @@ struct Neu {
     __device__ __forceinline__ double val() const { return s + c; }
 };
 
-// Sum of v over the 256 threads of a workgroup in a fixed tree order; every
-// thread returns the total.  sh: 256 doubles of LDS, free on entry; ends
+// Sum of v over the 256 threads of a workgroup in a fixed order; every
+// thread returns the total.  Each 64-wide wavefront folds its values with a
+// butterfly of lane exchanges (xor distances 32 ... 1, so every lane holds
+// the wavefront sum), the four wavefront sums meet in LDS and are added in
+// wavefront order.  sh: at least 4 doubles of LDS, free on entry; ends
 // behind a barrier.
 __device__ __forceinline__ double block_sum_256(double v, double* sh) {
-    sh[threadIdx.x] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wave] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// Largest v over the 256 threads (same pattern); every thread returns it.
+__device__ __forceinline__ double block_max_256(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[wave] = v;
+    __syncthreads();
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
     __syncthreads();
     return r;
 }

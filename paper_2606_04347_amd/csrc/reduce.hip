@@ -48,25 +48,16 @@ __global__ __launch_bounds__(kB) void k_reduce(F f, long n, double* part) {
         }
         for (int j = 0; j < NM; ++j) mx[0][j] = fmax(mx[0][j], mx[u][j]);
     }
-    __shared__ double sh[kB];
+    __shared__ double sh[4];
     for (int j = 0; j < NS + NM; ++j) {
-        sh[threadIdx.x] = (j < NS) ? acc[0][j].val() : mx[0][j - NS];
-        __syncthreads();
-        for (int w = kB / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                const double a = sh[threadIdx.x], b = sh[threadIdx.x + w];
-                sh[threadIdx.x] = (j < NS) ? a + b : fmax(a, b);
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(long)blockIdx.x * (NS + NM) + j] = sh[0];
-        __syncthreads();
+        const double r = (j < NS) ? block_sum_256(acc[0][j].val(), sh) : block_max_256(mx[0][j - NS], sh);
+        if (threadIdx.x == 0) part[(long)blockIdx.x * (NS + NM) + j] = r;
     }
 }
 
 template <int NS, int NM>
 __global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb, double* out, double scale) {
-    __shared__ double sh[kB];
+    __shared__ double sh[4];
     for (int j = 0; j < NS + NM; ++j) {
         Neu acc;
         double mx = -INFINITY;
@@ -75,17 +66,8 @@ __global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb,
             if (j < NS) acc.add(v);
             else mx = fmax(mx, v);
         }
-        sh[threadIdx.x] = (j < NS) ? acc.val() : mx;
-        __syncthreads();
-        for (int w = kB / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                const double a = sh[threadIdx.x], b = sh[threadIdx.x + w];
-                sh[threadIdx.x] = (j < NS) ? a + b : fmax(a, b);
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[j] = (j < NS) ? scale * sh[0] : sh[0];
-        __syncthreads();
+        const double r = (j < NS) ? block_sum_256(acc.val(), sh) : block_max_256(mx, sh);
+        if (threadIdx.x == 0) out[j] = (j < NS) ? scale * r : r;
     }
 }
 
