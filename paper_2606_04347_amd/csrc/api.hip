@@ -326,11 +326,15 @@ etd_status check_instance(etd_plan* plan, int instance) {
 }
 
 // ------------------------------------------------------------------ coupled step
+// Three-dimensional grids keep only |grad phi| (gn, in the gx buffer): the
+// fused derivative pass reduces the gradient to its norm, the only form R1
+// and the energy use; two-dimensional grids keep the components gx, gy, gz.
 template <typename T> struct CoupledView {
-    T *phiA, *phiB, *u, *ut, *lap, *gx, *gy, *gz, *P, *Q, *gp, *vx, *vy, *vz, *psi;
+    T *phiA, *phiB, *u, *ut, *lap, *gx, *gy, *gz, *gn, *P, *Q, *gp, *vx, *vy, *vz, *psi;
     c2<T> *Sphi, *St, *Sra, *Sa, *Sb, *Sgu, *Stmp;
     explicit CoupledView(Instance& I) {
         phiA = (T*)I.phiA; phiB = (T*)I.phiB; u = (T*)I.u; ut = (T*)I.ut; lap = (T*)I.lap; gx = (T*)I.gx;
+        gn = (T*)I.gx;
         gy = (T*)I.gy; gz = (T*)I.gz; P = (T*)I.P; Q = (T*)I.Q; gp = (T*)I.gp; vx = (T*)I.vx; vy = (T*)I.vy;
         vz = (T*)I.vz; psi = (T*)I.psi;
         Sphi = (c2<T>*)I.Sphi; St = (c2<T>*)I.St; Sra = (c2<T>*)I.Sra; Sa = (c2<T>*)I.Sa; Sb = (c2<T>*)I.Sb;
@@ -345,7 +349,9 @@ template <typename T> const FFTTables<T>& tables(const Instance& I);
 template <> const FFTTables<float>& tables<float>(const Instance& I) { return I.tf; }
 template <> const FFTTables<double>& tables<double>(const Instance& I) { return I.td; }
 
-// phi and its spectral derivatives from a spectrum: out phi, lap, gx, gy, gz.
+// phi and its spectral derivatives from a spectrum: out phi, lap and the
+// gradient (its norm in the gx buffer on three-dimensional grids, the
+// components gx, gy, gz on two-dimensional ones).
 // Three-dimensional grids take the fused three-pass pipeline with the work
 // spectra Sa, Sb, Sgu, Stmp (S must be none of them); two-dimensional grids
 // take one c2r per field.
@@ -355,7 +361,7 @@ hipError_t phi_and_derivs(const Instance& I, CoupledView<T>& v, const c2<T>* S, 
     const FFTTables<T>& t = tables<T>(I);
     if (g.nx > 1) {
         const GridSum isum = grid_sum(I, S_INTPHI);
-        return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gx, v.gy, v.gz, v.lap, &isum, s);
+        return derivs_fused<T>(g, t, S, v.Sa, v.Sb, v.Sgu, v.Stmp, phi, v.gn, v.lap, &isum, s);
     }
     hipError_t e = fft_c2r_3d<T>(g, t, S, v.Stmp, phi, s);
     if (e != hipSuccess) return e;
@@ -387,8 +393,9 @@ hipError_t remainder_etd_2d(const Instance& I, CoupledView<T>& v, EtdStage st, c
 }
 
 // One phi stage: R1 at (phi_in, its derivatives, u^n), the ETD combine into
-// the spectrum a.out and, in real space, phi_out with its derivatives (gx,
-// gy, gz, lap; on three-dimensional grids also the integral of phi_out).  On
+// the spectrum a.out and, in real space, phi_out with its derivatives (lap
+// and the gradient, its norm only on three-dimensional grids, where the
+// integral of phi_out is formed too).  On
 // three-dimensional grids R1 is formed in the load of the z pass and the x
 // pass of the pair also runs the inverse x transforms of the derivatives.
 // With vel (three-dimensional grids, the last stage of a step) the final
@@ -399,12 +406,11 @@ hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, cons
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     if (g.nx > 1) {
-        const R1Fields<T> f{phi_in, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0};
+        const R1Fields<T> f{phi_in, v.lap, v.gn, v.u, mask, I.scal + S_INTPHI, I.A0};
         hipError_t e = r1_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
         if (e != hipSuccess) return e;
         const GridSum isum = grid_sum(I, S_INTPHI);
-        return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gx, v.gy, v.gz, v.lap, &isum, s,
-                                  vel);
+        return derivs_fused_yz<T>(g, t, v.Sa, v.Sb, v.Sgu, v.Stmp, phi_out, v.gn, v.lap, &isum, s, vel);
     }
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
@@ -874,8 +880,9 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
             HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
             spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
             HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s));
-            reduce_energy_coupled<T>(g, I.K, v.phiA, v.lap, v.gx, v.gy, v.gz, v.u, v.psi, v.P, I.part,
-                                     I.scal + S_ENERGY, s);
+            const bool norm_only = g.nx > 1;   // gx holds |grad phi|
+            reduce_energy_coupled<T>(g, I.K, v.phiA, v.lap, v.gx, norm_only ? nullptr : v.gy,
+                                     norm_only ? nullptr : v.gz, v.u, v.psi, v.P, I.part, I.scal + S_ENERGY, s);
             return ETD_OK;
         };
         st = I.f32 ? run(0.0f) : run(0.0);

@@ -164,7 +164,8 @@ __global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const 
                              k < 3 ? uu.v[k + 1] : uzp};
             const T pn[6] = {pxm.v[k], pxp.v[k], pym.v[k], pyp.v[k], k > 0 ? p.v[k - 1] : pzm,
                              k < 3 ? p.v[k + 1] : pzp};
-            r1_point(kc, p.v[k], L.v[k], a.v[k], b.v[k], c.v[k], uu.v[k], un, pn, ((mk >> (8 * k)) & 0xffu) != 0,
+            const T gn = sqrt(a.v[k] * a.v[k] + b.v[k] * b.v[k] + c.v[k] * c.v[k]);
+            r1_point(kc, p.v[k], L.v[k], gn, uu.v[k], un, pn, ((mk >> (8 * k)) & 0xffu) != 0,
                      &oP.v[k], &oQ.v[k]);
         }
         st4(P + nb.c, oP);

@@ -7,16 +7,17 @@
 
 namespace etd {
 
-// From the half spectrum S of phi: phi, its spectral gradient (gx, gy, gz)
-// and spectral Laplacian lap (Section 3.2), in three passes: inverse x lines
-// (S -> S, i kx S, -kx^2 S), inverse y lines (3 -> 4 spectra), z rows c2r
-// (4 spectra -> 5 real fields).  W0..W3: complex work arrays (nspec each); S
-// is preserved.  With isum != null the z pass also forms the integral
-// h^3 sum phi into isum->out (block partials in isum->part, nx * ny / 8
-// doubles at most, then a fixed-order final sum).
+// From the half spectrum S of phi: phi, the norm gn = |grad phi| of its
+// spectral gradient and its spectral Laplacian lap (Section 3.2), in three
+// passes: inverse x lines (S -> S, i kx S, -kx^2 S), inverse y lines (3 -> 4
+// spectra), z rows c2r (4 spectra -> phi, the three gradient components kept
+// in registers and reduced to gn, lap).  W0..W3: complex work arrays (nspec
+// each); S is preserved.  With isum != null the z pass also forms the
+// integral h^3 sum phi into isum->out (block partials in isum->part,
+// nx * ny / 8 doubles at most, then a fixed-order final sum).
 template <typename T>
 hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s);
+                        c2<T>* W3, T* phi, T* gn, T* lap, const GridSum* isum, hipStream_t s);
 
 // g+ and the velocity of the u equation (Section 3.1) from phi^{n+1} (the
 // field being formed), phi^n = po and the step tau; thr the support threshold.
@@ -34,8 +35,7 @@ template <typename T> struct VelocityArgs {
 // With vel != null the z pass also writes g+ and the velocity at the new phi.
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s,
-                           const VelocityArgs<T>* vel = nullptr);
+                           T* gn, T* lap, const GridSum* isum, hipStream_t s, const VelocityArgs<T>* vel = nullptr);
 
 // Forward transforms of two real fields P, Q (into the work spectra WP, WQ)
 // and, in the last (x) pass, the ETD combine of the given stage (etd_point.h)
@@ -50,9 +50,10 @@ hipError_t fwd_pair_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K
                         c2<T>* X1, c2<T>* X2, hipStream_t s);
 
 // Sources of R1 (Section 3.1) at phi and u: phi, its spectral Laplacian and
-// gradient, u, the band mask (nullable), the device scalar h^3 sum phi and A0.
+// gradient norm, u, the band mask (nullable), the device scalar h^3 sum phi
+// and A0.
 template <typename T> struct R1Fields {
-    const T *phi, *lap, *gx, *gy, *gz, *u;
+    const T *phi, *lap, *gn, *u;   // gn = |grad phi|
     const uint8_t* mask;
     const double* int_phi;
     double A0;

@@ -195,29 +195,53 @@ template <typename T, int M> struct SumRowPairStore {
 };
 
 // z rows c2r of the y-pass outputs: phi = Z^-1 A, gz = Z^-1 (i kz A), gx = Z^-1 B,
-// gy = Z^-1 D, lap = Z^-1 C.
+// gy = Z^-1 D, lap = Z^-1 C.  Of the gradient only its norm gn = |grad phi|
+// leaves the pass (R1 sees the gradient through its norm alone); with the
+// velocity also g+ and v.
 template <typename T> struct DerivZArgs {
     const c2<T>* A;
     const c2<T>* B;
     const c2<T>* C;
     const c2<T>* D;
     T* phi;
-    T* gx;
-    T* gy;
-    T* gz;
+    T* gn;
     T* lap;
 };
 
-// Store of the gy output with g+ and the velocity of the u equation formed
-// there (velocity_point): phi, gz and gx of the same points were stored by
-// this thread in the earlier transforms of the tile (every transform of a
-// tile maps outputs to threads identically) and are read back, phi^n is read.
-template <typename T, int M> struct VelocityPairStore {
+// Keeps, slot by slot in registers (lines.h, IndexedOf), either the gradient
+// component of this thread's outputs (KEEP, needed for the velocity) or the
+// running sum of squares of the components.
+template <typename T, int K, bool KEEP> struct GradStash {
     static constexpr int NS = 1;
-    c2<T>* gy;          // each: first row of the tile, as pairs
+    static constexpr bool kIndexed = true;
+    c2<T> (&st)[K];
+    bool first;         // this transform starts the sums
+    T scale;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store_at(int slot, int, int, c2<T> v) const {
+        const c2<T> w = cscale(v, scale);
+        if constexpr (KEEP) {
+            st[slot] = w;
+        } else {
+            const c2<T> w2 = mk<T>(w.x * w.x, w.y * w.y);
+            st[slot] = first ? w2 : mk<T>(st[slot].x + w2.x, st[slot].y + w2.y);
+        }
+    }
+};
+
+// The last gradient component gy: gn = |grad phi| is stored, from the sum of
+// squares so far (sq) or, with VEL, from the kept gz and gx, with which it
+// also forms g+ and the velocity of the u equation (velocity_point) from
+// phi (stored by this thread in the first transform of the tile and read
+// back) and phi^n.
+template <typename T, int M, int K, bool VEL> struct GradNormStore {
+    static constexpr int NS = 1;
+    static constexpr bool kIndexed = true;
+    const c2<T> (&sq)[K];   // !VEL
+    const c2<T> (&kz)[K];   // VEL
+    const c2<T> (&kx)[K];   // VEL
+    c2<T>* gn;              // each: first row of the tile, as pairs
     const c2<T>* phi;
-    const c2<T>* gz;
-    const c2<T>* gx;
     const c2<T>* po;
     c2<T>* G;
     c2<T>* vx;
@@ -226,19 +250,23 @@ template <typename T, int M> struct VelocityPairStore {
     int nl;
     T scale, itau, thr;
     __device__ __forceinline__ void load(int, int, c2<T>*) const {}
-    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+    __device__ __forceinline__ void store_at(int slot, int l, int e, c2<T> v) const {
         if (l >= nl) return;
         const long i = (long)l * M + e;
         const c2<T> b = cscale(v, scale);
-        gy[i] = b;
-        const c2<T> p = phi[i], o = po[i], a = gx[i], c = gz[i];
-        c2<T> g, x, y, w;
-        velocity_point(itau, thr, p.x, o.x, a.x, b.x, c.x, &g.x, &x.x, &y.x, &w.x);
-        velocity_point(itau, thr, p.y, o.y, a.y, b.y, c.y, &g.y, &x.y, &y.y, &w.y);
-        G[i] = g;
-        vx[i] = x;
-        vy[i] = y;
-        vz[i] = w;
+        if constexpr (VEL) {
+            const c2<T> p = phi[i], o = po[i], a = kx[slot], c = kz[slot];
+            gn[i] = mk<T>(sqrt(c.x * c.x + a.x * a.x + b.x * b.x), sqrt(c.y * c.y + a.y * a.y + b.y * b.y));
+            c2<T> g, x, y, w;
+            velocity_point(itau, thr, p.x, o.x, a.x, b.x, c.x, &g.x, &x.x, &y.x, &w.x);
+            velocity_point(itau, thr, p.y, o.y, a.y, b.y, c.y, &g.y, &x.y, &y.y, &w.y);
+            G[i] = g;
+            vx[i] = x;
+            vy[i] = y;
+            vz[i] = w;
+        } else {
+            gn[i] = mk<T>(sqrt(sq[slot].x + b.x * b.x), sqrt(sq[slot].y + b.y * b.y));
+        }
     }
 };
 
@@ -249,6 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityA
     constexpr int L = z_rows<NR>();
     constexpr int MS = NR / 2 + 1;
     constexpr int M = NR / 2;
+    constexpr int K = z_out_slots<NR>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -256,37 +285,36 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityA
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
     const long si = row0 * MS, ro = row0 * NR;
-    auto out = [&](T* f) { return RowPairStore<T, M>{reinterpret_cast<c2<T>*>(f + ro), nl, scale}; };
+    auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
+    auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
     // each input is fetched into registers while the previous output is transformed
     c2<T> pre[z_fetch_count<NR>()];
     zrow_fetch<T, NR>(pre, z.A + si, nl);
     zrow_put<T, NR, false>(lds, pre, az);
     Neu acc;   // this thread's share of sum phi over the tile
-    zrow_inverse_lds<T, NR>(lds, stw, twf, SumRowPairStore<T, M>{reinterpret_cast<c2<T>*>(z.phi + ro), nl, scale, acc});
+    zrow_inverse_lds<T, NR>(lds, stw, twf, SumRowPairStore<T, M>{pw(z.phi), nl, scale, acc});
+    // gradient components in registers: gz and gx with VEL, else their sum of squares
+    c2<T> kz[K], kx[K];
     __syncthreads();
     zrow_put<T, NR, true>(lds, pre, az);
     zrow_fetch<T, NR>(pre, z.B + si, nl);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gz));
+    zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{kz, true, scale});
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_fetch<T, NR>(pre, z.D + si, nl);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gx));
+    zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{VEL ? kx : kz, false, scale});
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_fetch<T, NR>(pre, z.C + si, nl);
-    if constexpr (VEL) {
-        auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
-        auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
-        zrow_inverse_lds<T, NR>(lds, stw, twf,
-                                VelocityPairStore<T, M>{pw(z.gy), pr(z.phi), pr(z.gz), pr(z.gx), pr(va.po), pw(va.G),
-                                                        pw(va.vx), pw(va.vy), pw(va.vz), nl, scale,
-                                                        (T)(1.0 / va.tau), (T)va.thr});
-    } else {
-        zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.gy));
-    }
+    zrow_inverse_lds<T, NR>(
+        lds, stw, twf,
+        GradNormStore<T, M, K, VEL>{kz, kz, kx, pw(z.gn), pr(z.phi), VEL ? pr(va.po) : nullptr,
+                                    VEL ? pw(va.G) : nullptr, VEL ? pw(va.vx) : nullptr, VEL ? pw(va.vy) : nullptr,
+                                    VEL ? pw(va.vz) : nullptr, nl, scale, (T)(VEL ? 1.0 / va.tau : 0.0),
+                                    (T)va.thr});
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, out(z.lap));
+    zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, M>{pw(z.lap), nl, scale});
     if (part) {
         // block partial of sum phi over this tile, for the integral of phi the
         // next R1 evaluation needs
@@ -388,7 +416,7 @@ template <typename T, int L> struct R1PairLoad {
     static constexpr int NS = 2;
     const RowTile<L>* rt;
     int nl, nz;
-    const T *phi, *lap, *gx, *gy, *gz, *u;
+    const T *phi, *lap, *gn, *u;
     const uint8_t* mask;
     R1Const<T> k;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
@@ -397,8 +425,7 @@ template <typename T, int L> struct R1PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o), a = ld2(gx + c + o), b = ld2(gy + c + o),
-                    cz = ld2(gz + c + o), uu = ld2(u + c + o);
+        const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o), gg = ld2(gn + c + o), uu = ld2(u + c + o);
         const c2<T> pxm = ld2(phi + rt->xm[l] + o), pxp = ld2(phi + rt->xp[l] + o), pym = ld2(phi + rt->ym[l] + o),
                     pyp = ld2(phi + rt->yp[l] + o);
         const c2<T> uxm = ld2(u + rt->xm[l] + o), uxp = ld2(u + rt->xp[l] + o), uym = ld2(u + rt->ym[l] + o),
@@ -414,12 +441,12 @@ template <typename T, int L> struct R1PairLoad {
         {
             const T un[6] = {uxm.x, uxp.x, uym.x, uyp.x, uzm, uu.y};
             const T pn[6] = {pxm.x, pxp.x, pym.x, pyp.x, pzm, p.y};
-            r1_point(k, p.x, L2.x, a.x, b.x, cz.x, uu.x, un, pn, b0, &P0, &Q0);
+            r1_point(k, p.x, L2.x, gg.x, uu.x, un, pn, b0, &P0, &Q0);
         }
         {
             const T un[6] = {uxm.y, uxp.y, uym.y, uyp.y, uu.x, uzp};
             const T pn[6] = {pxm.y, pxp.y, pym.y, pyp.y, p.x, pzp};
-            r1_point(k, p.y, L2.y, a.y, b.y, cz.y, uu.y, un, pn, b1, &P1, &Q1);
+            r1_point(k, p.y, L2.y, gg.y, uu.y, un, pn, b1, &P1, &Q1);
         }
         v[0] = mk<T>(P0, P1);
         v[1] = mk<T>(Q0, Q1);
@@ -526,8 +553,8 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, co
 }
 
 template <typename T, int NR>
-__global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gx,
-                                                       const T* gy, const T* gz, const T* u, const uint8_t* mask,
+__global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
+                                                       const T* u, const uint8_t* mask,
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
@@ -542,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, cons
     const int nl = (int)min((long)L, nrows - row0);
     row_tile_setup<L>(rt, g, row0);
     __syncthreads();
-    const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gx, gy, gz, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
+    const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
     zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
 }
 
@@ -832,7 +859,7 @@ hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, 
     set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     hipLaunchKernelGGL((k_z_r2c_r1<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
-                       f.lap, f.gx, f.gy, f.gz, f.u, f.mask, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
+                       f.lap, f.gn, f.u, f.mask, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
     return hipGetLastError();
 }
 template <typename T, int NR>
@@ -910,8 +937,7 @@ hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, con
 
 template <typename T>
 hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<T>* W1, c2<T>* W2, c2<T>* W3, T* phi,
-                           T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s,
-                           const VelocityArgs<T>* vel) {
+                           T* gn, T* lap, const GridSum* isum, hipStream_t s, const VelocityArgs<T>* vel) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
@@ -925,10 +951,10 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
         }
     });
     if (e != hipSuccess) return e;
-    const DerivZArgs<T> z{W0, W1, W2, W3, phi, gx, gy, gz, lap};
-    // with the velocity: phi^n read, g+ and v written (the read-back of phi,
-    // gz, gx is served by the cache)
-    return timed_pass(PASS_Z_DERIV, 4.0 * cb + (vel ? 10.0 : 5.0) * rb, s, [&]() -> hipError_t {
+    const DerivZArgs<T> z{W0, W1, W2, W3, phi, gn, lap};
+    // phi, |grad phi| and lap written; with the velocity also phi^n read and
+    // g+ and v written (the read-back of phi is served by the cache)
+    return timed_pass(PASS_Z_DERIV, 4.0 * cb + (vel ? 8.0 : 3.0) * rb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
     case n: return launch_deriv_z<T, n>(g, z, vel, t.tzh, t.tzf, isum, s);
@@ -941,7 +967,7 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
 
 template <typename T>
 hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c2<T>* W0, c2<T>* W1, c2<T>* W2,
-                        c2<T>* W3, T* phi, T* gx, T* gy, T* gz, T* lap, const GridSum* isum, hipStream_t s) {
+                        c2<T>* W3, T* phi, T* gn, T* lap, const GridSum* isum, hipStream_t s) {
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     hipError_t e = timed_pass(PASS_X_DERIV, 4.0 * cb, s, [&]() -> hipError_t {
@@ -954,7 +980,7 @@ hipError_t derivs_fused(const GridK& g, const FFTTables<T>& t, const c2<T>* S, c
         }
     });
     if (e != hipSuccess) return e;
-    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gx, gy, gz, lap, isum, s, nullptr);
+    return derivs_fused_yz<T>(g, t, W0, W1, W2, W3, phi, gn, lap, isum, s, nullptr);
 }
 
 namespace {
@@ -1026,7 +1052,7 @@ hipError_t r1_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
     const double mb = f.mask ? (double)g.nreal() : 0.0;
-    hipError_t e = timed_pass(PASS_Z_R2C_R1, 6.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
+    hipError_t e = timed_pass(PASS_Z_R2C_R1, 4.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
     case n: return launch_z_r1<T, n>(g, K, f, WP, WQ, t.tzh, t.tzf, s);
@@ -1183,12 +1209,12 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
     template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
                                        const T*, T*, double, hipStream_t);                                        \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
-                                        c2<T>*, T*, T*, T*, T*, T*, const GridSum*, hipStream_t);                 \
+                                        c2<T>*, T*, T*, T*, const GridSum*, hipStream_t);                         \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
                                         const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*,        \
                                         c2<T>*, hipStream_t);                                                     \
     template hipError_t derivs_fused_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, c2<T>*, c2<T>*, c2<T>*, T*, \
-                                           T*, T*, T*, T*, const GridSum*, hipStream_t,                           \
+                                           T*, T*, const GridSum*, hipStream_t,                                   \
                                            const VelocityArgs<T>*);                                               \
     template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
                                           double, hipStream_t);                                                   \

@@ -87,6 +87,7 @@ void reduce_diag(const GridK& g, const T* phi, const double* gfix, const T* u, d
 
 // Coupled energy sums: out = [sum(|grad phi|^2/2 + W(phi)/eps^2), sum (lap - W'(phi)/eps^2)^2,
 // sum phi, sum g_half (D+ u)^2 (edges), sum g W(u), sum psi q, sum q]  (unscaled).
+// gy = gz = nullptr: gx holds |grad phi|.
 template <typename T>
 void reduce_energy_coupled(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx,
                            const T* gy, const T* gz, const T* u, const T* psi, const T* q, double* part,

@@ -20,6 +20,8 @@
 //   __device__ void store(int l, int s, int e, c2<T> v) const; // output of slot s at element e
 #pragma once
 
+#include <type_traits>
+
 #include "stockham.h"
 
 namespace etd {
@@ -78,12 +80,53 @@ __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, co
     }
 }
 
-// Stages from span NSP on; the last one goes to Op::store.
+// Ops with kIndexed (NS == 1) take each last-stage output through
+// store_at(slot, l, e, v), slot = it R + r its compile-time position among the
+// outputs of this thread.  Every transform of one line set maps outputs to
+// threads the same way, so such an Op can carry per-point values in
+// registers from one transform of the set to the next.
+template <class Op, class = void> struct IndexedOf {
+    static constexpr bool v = false;
+};
+template <class Op> struct IndexedOf<Op, std::enable_if_t<Op::kIndexed>> {
+    static constexpr bool v = true;
+};
+
+template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
+__device__ __forceinline__ void last_stage_indexed(const c2<T>* lds, const c2<T>* tw, const Op& op) {
+    constexpr int SP = N / R;
+    constexpr int NB = L * SP;
+    constexpr int IT = (NB + kThreads - 1) / kThreads;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if ((NB % kThreads == 0) || b < NB) {
+            const int l = LF ? b % L : b / SP, j = LF ? b / L : b % SP;
+            const c2<T>* src = lds + l * LS;
+            c2<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                c2<T> w = tw[r * j];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+            dftR<T, R, DIR>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) op.store_at(it * R + r, l, j + r * SP, v[r]);
+        }
+    }
+}
+
+// Stages from span NSP on; the last one goes to Op::store (Op::store_at for
+// an indexed Op).
 template <typename T, int N, int LL, int LS, int NSP, int DIR, bool LF, class Op>
 __device__ __forceinline__ void middle_and_last(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int R = NextRadix<N / NSP>::v;
     if constexpr (NSP * R == N) {
-        last_stage<T, N, LL / Op::NS, LS, R, DIR, LF, Op>(lds, tw, op);
+        if constexpr (IndexedOf<Op>::v) last_stage_indexed<T, N, LL, LS, R, DIR, LF, Op>(lds, tw, op);
+        else last_stage<T, N, LL / Op::NS, LS, R, DIR, LF, Op>(lds, tw, op);
     } else {
         stage<T, N, LL, LS, R, NSP, DIR>(lds, tw);
         middle_and_last<T, N, LL, LS, NSP * R, DIR, LF, Op>(lds, tw, op);

@@ -166,7 +166,8 @@ template <typename T> struct EnergyCoupledF {
     const T *phi, *lap, *gx, *gy, *gz, *u, *psi, *q;
     __device__ void operator()(long i, double* s, double*) const {
         const double p = (double)phi[i];
-        const double a = (double)gx[i], b = (double)gy[i], c = (double)gz[i];
+        // gy == nullptr: gx holds |grad phi|
+        const double a = (double)gx[i], b = gy ? (double)gy[i] : 0.0, c = gz ? (double)gz[i] : 0.0;
         s[0] = 0.5 * (a * a + b * b + c * c) + W_d(p) / e2;
         const double w = (double)lap[i] - Wp_d(p) / e2;
         s[1] = w * w;

@@ -48,12 +48,12 @@ template <typename T> struct R1Const {
 };
 
 // P1 (into *P) and W'(phi) - A1 phi (into *Q) at one point: centre values
-// (phi, its spectral Laplacian L and gradient (a, b, c), u), the six
-// neighbours of u and phi (x-, x+, y-, y+, z-, z+), and the band flag.
+// (phi, its spectral Laplacian L, the norm gn = |grad phi| of its spectral
+// gradient, u), the six neighbours of u and phi (x-, x+, y-, y+, z-, z+), and
+// the band flag.  P1 sees the gradient only through its norm.
 template <typename T>
-__device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T a, T b, T c, T uc, const T (&un)[6],
+__device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
                                          const T (&pn)[6], bool band, T* P, T* Q) {
-    const T gn = sqrt(a * a + b * b + c * c);
     const T gc = gloc(pc);
     T S = lapS_axis(un[0], uc, un[1], gloc(pn[0]), gc, gloc(pn[1]), k.ihx);
     S += lapS_axis(un[2], uc, un[3], gloc(pn[2]), gc, gloc(pn[3]), k.ihy);

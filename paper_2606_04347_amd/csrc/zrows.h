@@ -206,12 +206,33 @@ __device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, c
     __syncthreads();
     if constexpr (NextRadix<M>::v == M) {
         stockham<T, M, L, LS, 1, +1>(lds, stw);
-        for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
-            const int r = idx / M, n = idx % M;
-            op.store(r, 0, n, lds[r * LS + sk(n)]);
+        if constexpr (IndexedOf<Op>::v) {
+            constexpr int P = (L * M + kThreads - 1) / kThreads;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int idx = threadIdx.x + p * kThreads;
+                if (idx < L * M) op.store_at(p, idx / M, idx % M, lds[(idx / M) * LS + sk(idx % M)]);
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
+                const int r = idx / M, n = idx % M;
+                op.store(r, 0, n, lds[r * LS + sk(n)]);
+            }
         }
     } else {
         lines_fft_from_lds<T, M, L, LS, +1, false>(lds, stw, op);
+    }
+}
+
+// Outputs per thread of zrow_inverse_lds: the slots an indexed store op
+// (lines.h, IndexedOf) is given, 0 .. z_out_slots - 1.
+template <int NR> constexpr int z_out_slots() {
+    constexpr int M = NR / 2, L = z_rows<NR>();
+    if constexpr (NextRadix<M>::v == M) {
+        return (L * M + kThreads - 1) / kThreads;
+    } else {
+        constexpr int R = last_radix(M);
+        return ((L * (M / R) + kThreads - 1) / kThreads) * R;
     }
 }
 
