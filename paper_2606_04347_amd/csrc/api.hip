@@ -220,9 +220,13 @@ etd_status setup_coupled(etd_plan* P, Instance& I) {
     const size_t nr = (size_t)g.nreal(), ns = (size_t)g.nspec();
     const size_t es = I.f32 ? sizeof(float) : sizeof(double);
     const size_t cs = 2 * es;
-    void** reals[] = {&I.phiA, &I.phiB, &I.u, &I.ut, &I.lap, &I.gx, &I.gy, &I.gz, &I.P, &I.Q, &I.gp, &I.vx,
-                      &I.vy, &I.vz, &I.psi};
+    void** reals[] = {&I.phiA, &I.phiB, &I.u, &I.ut, &I.lap, &I.gx, &I.P, &I.Q, &I.gp, &I.vx, &I.vy, &I.vz,
+                      &I.psi};
     for (void** r : reals) ALLOC(*r, nr * es);
+    if (I.g.nx == 1) {   // two-dimensional grids keep all gradient components
+        ALLOC(I.gy, nr * es);
+        ALLOC(I.gz, nr * es);
+    }
     void** specs[] = {&I.Sphi, &I.St, &I.Sra, &I.Sa, &I.Sb, &I.Sgu, &I.Stmp};
     for (void** r : specs) ALLOC(*r, ns * cs);
     ALLOC(I.mask, nr);

@@ -184,7 +184,8 @@ etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
     v.parts.clear();
     v.parts.push_back({I.scal, sizeof(double) * S_COUNT});
     if (I.d.model == ETD_COUPLED) {
-        for (void* p : {I.phiA, I.u, I.lap, I.gx, I.gy, I.gz}) v.parts.push_back({p, n * es});
+        for (void* p : {I.phiA, I.u, I.lap, I.gx, I.gy, I.gz})
+            if (p) v.parts.push_back({p, n * es});   // gy, gz exist on two-dimensional grids only
         v.parts.push_back({I.Sphi, 2 * es * (size_t)I.g.nspec()});
         if (I.mask) v.parts.push_back({I.mask, n});
         if (I.band_total) v.parts.push_back({I.band_total, sizeof(int64_t)});
