@@ -395,17 +395,18 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q,
 template <int L> struct RowTile {
     long c[L], xm[L], xp[L], ym[L], yp[L];
 };
+// Every row of the tile (L can exceed the workgroup: 512 rows of Nz = 8).
 template <int L> __device__ __forceinline__ void row_tile_setup(RowTile<L>& t, const GridK& g, long row0) {
-    if (threadIdx.x < L) {
-        const long r = min(row0 + (long)threadIdx.x, (long)g.nx * g.ny - 1);
+    for (int l = threadIdx.x; l < L; l += kThreads) {
+        const long r = min(row0 + (long)l, (long)g.nx * g.ny - 1);
         const int ix = (int)(r / g.ny), iy = (int)(r % g.ny);
         const long sx = (long)g.ny * g.nz, sy = g.nz;
         const long c = r * g.nz;
-        t.c[threadIdx.x] = c;
-        t.xp[threadIdx.x] = c + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
-        t.xm[threadIdx.x] = c + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
-        t.yp[threadIdx.x] = c + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
-        t.ym[threadIdx.x] = c + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
+        t.c[l] = c;
+        t.xp[l] = c + ((ix + 1 < g.nx) ? sx : -(long)(g.nx - 1) * sx);
+        t.xm[l] = c + ((ix > 0) ? -sx : (long)(g.nx - 1) * sx);
+        t.yp[l] = c + ((iy + 1 < g.ny) ? sy : -(long)(g.ny - 1) * sy);
+        t.ym[l] = c + ((iy > 0) ? -sy : (long)(g.ny - 1) * sy);
     }
 }
 template <typename T> __device__ __forceinline__ c2<T> ld2(const T* p) { return *reinterpret_cast<const c2<T>*>(p); }
