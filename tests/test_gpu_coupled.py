@@ -36,7 +36,8 @@ def run_pair(ci, scheme, precision, nsteps, **inst_kw):
 @pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
 @pytest.mark.parametrize("shape,nsteps", [((16, 16, 16), 1), ((16, 16, 16), 5), ((24, 16, 32), 3),
                                           ((48, 48, 48), 2), ((64, 96, 128), 1), ((96, 64, 192), 1),
-                                          ((16, 24, 512), 1), ((384, 8, 16), 1), ((8, 512, 8), 1)])
+                                          ((16, 24, 512), 1), ((384, 8, 16), 1), ((8, 512, 8), 1),
+                                          ((8, 8, 8), 2), ((512, 8, 12), 1)])
 def test_fp64_step_matches_oracle(shape, nsteps, scheme):
     ci = make_case(shape)
     o, plan, phi, u = run_pair(ci, scheme, etd.FP64, nsteps)
