@@ -58,12 +58,26 @@ def test_fp64_step_matches_oracle(shape, nsteps, scheme):
 
 
 @pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
-def test_fp32_step_close_to_oracle(scheme):
-    ci = make_case((32, 32, 32))
-    o, plan, phi, u = run_pair(ci, scheme, etd.FP32, 20)
-    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
-    report("coupled_fp32", scheme=scheme, err_phi=ephi, err_u=eu)
-    assert ephi <= 1e-4 and eu <= 1e-4
+@pytest.mark.parametrize("shape,nsteps", [((32, 32, 32), 20), ((96, 64, 192), 3), ((8, 512, 8), 3),
+                                          ((512, 8, 12), 1)])
+def test_fp32_step_close_to_oracle(scheme, shape, nsteps):
+    """FP32 path against the FP64 oracle.  The recovery U = GU / G divides by
+    a G that is tiny away from the membrane, where rounding of GU is
+    amplified, so u is compared on {g > 1e-2} (g from the oracle's phi);
+    phi everywhere.  The 512 x 8 x 12 grid (dx = 2 pi / 512 beside
+    dy = 2 pi / 8) is unstable at tau = 1e-4 even in exact arithmetic (the
+    oracle's u grows thirtyfold a step and overflows by step 3), so it runs
+    one step only."""
+    ci = make_case(shape)
+    o, plan, phi, u = run_pair(ci, scheme, etd.FP32, nsteps)
+    po = o.phi()
+    sel = 18.0 * (po * po - po) ** 2 > 1e-2
+    ephi = rel_linf(phi, po)
+    eu_sel = float(np.abs(u - o.u)[sel].max() / np.abs(o.u).max())
+    report("coupled_fp32", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi,
+           err_u_g_gt_1e_2=eu_sel, err_u_all=rel_linf(u, o.u))
+    assert np.isfinite(phi).all() and np.isfinite(u).all()
+    assert ephi <= 1e-4 and eu_sel <= 1e-4
     plan.close()
 
 
