@@ -207,10 +207,12 @@ def surface_measure(n, steps):
                        torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
         ms = timed_steps(plan, steps, 1) / steps
         r = {"ms_per_step": ms, "value": n ** 3 / (ms * 1e-3), "unit": "grid-pt steps/s"}
+        d = plan.diagnostics(0)
+        r["umin"], r["umax"], r["mass"] = d["umin"], d["umax"], d["mass"]   # the state stays finite and bounded
         if flags:
             r["iterations_last_solve"] = plan.query(0, etd.Q_SURF_ITERS)
             r["relres_last_solve"] = plan.query(0, etd.Q_SURF_RELRES)
-            r["band_points"] = plan.diagnostics(0)["band_count"]
+            r["band_points"] = d["band_count"]
         out[name] = r
         plan.close()
     return out
@@ -448,7 +450,8 @@ def main():
         log(f"band solve {a.surface_n}^3: {sf['band_solve']['ms_per_step']:.2f} ms/step "
             f"({sf['band_solve']['iterations_last_solve']:.0f} PCG iterations, relres "
             f"{sf['band_solve']['relres_last_solve']:.1e}, {sf['band_solve']['band_points']} band points) vs "
-            f"{sf['fft_inverse']['ms_per_step']:.3f} ms/step with (-Delta_h)^-1")
+            f"{sf['fft_inverse']['ms_per_step']:.3f} ms/step with (-Delta_h)^-1; U in [{sf['band_solve']['umin']:.4g}, "
+            f"{sf['band_solve']['umax']:.4g}] vs [{sf['fft_inverse']['umin']:.4g}, {sf['fft_inverse']['umax']:.4g}]")
     if not a.no_batch:
         out["batched"] = batch_measure(a.batch_steps, a.warmup)
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "
