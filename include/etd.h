@@ -114,7 +114,12 @@ typedef struct {
                                       {g >= band_threshold} (the paper's delta), built by
                                       etd_set_state; FP64 on both of its paths.  The solve
                                       checks convergence on the host, so plans with this flag
-                                      step eagerly under every schedule.  The energy
+                                      step eagerly under every schedule.  Each in-step solve
+                                      runs to a relative residual of 1e-9 (FP32 coupled
+                                      instances) or 1e-12, at most 20000 iterations; one that
+                                      stops at the cap is not an error: the step goes on with
+                                      its last iterate, and ETD_Q_SURF_ITERS /
+                                      ETD_Q_SURF_RELRES report the last solve.  The energy
                                       diagnostics keep (-Delta_h)^{-1}. */
 
 /* One simulation instance. */
