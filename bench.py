@@ -49,8 +49,10 @@ def parse():
                     help="skip the band-solve leg ((-Delta_S,h)^{-1} on the band, 256^3)")
     ap.add_argument("--surface-n", type=int, default=256)
     ap.add_argument("--surface-steps", type=int, default=4)
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances); off by "
+                         "default while a host-side abort seen once in this leg is unexplained")
+    ap.add_argument("--no-batch", action="store_true", help="leave the uneven-batch measurement out (the default)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (a reference kernel of known size "
@@ -452,7 +454,7 @@ def main():
             f"{sf['band_solve']['relres_last_solve']:.1e}, {sf['band_solve']['band_points']} band points) vs "
             f"{sf['fft_inverse']['ms_per_step']:.3f} ms/step with (-Delta_h)^-1; U in [{sf['band_solve']['umin']:.4g}, "
             f"{sf['band_solve']['umax']:.4g}] vs [{sf['fft_inverse']['umin']:.4g}, {sf['fft_inverse']['umax']:.4g}]")
-    if not a.no_batch:
+    if a.batch and not a.no_batch:
         out["batched"] = batch_measure(a.batch_steps, a.warmup)
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "
             f"x{out['batched']['speedup_vs_eager']:.2f} vs eager, "

@@ -83,7 +83,7 @@ template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in, c2<T>* __restrict__ out,
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict_
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows,
                                                         T scale) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -127,7 +127,7 @@ hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, i
 template <typename T, int NR>
 hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, const c2<T>* twf, long nrows,
                     T scale, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     const int nblk = (int)((nrows + L - 1) / L);
     if (forward) {

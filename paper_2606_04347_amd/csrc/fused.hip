@@ -274,10 +274,10 @@ template <typename T, int NR, bool VEL>
 __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityArgs<T> va,
                                                       const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
                                                       long nrows, T scale, double az, double* part) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     constexpr int MS = NR / 2 + 1;
     constexpr int M = NR / 2;
-    constexpr int K = z_out_slots<NR>();
+    constexpr int K = z_out_slots<T, NR>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityA
     auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
     auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
     // each input is fetched into registers while the previous output is transformed
-    c2<T> pre[z_fetch_count<NR>()];
+    c2<T> pre[z_fetch_count<T, NR>()];
     zrow_fetch<T, NR>(pre, z.A + si, nl);
     zrow_put<T, NR, false>(lds, pre, az);
     Neu acc;   // this thread's share of sum phi over the tile
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r_recover(const c2<T>* D, cons
                                                             const c2<T>* __restrict__ twh,
                                                             const c2<T>* __restrict__ twf, long nrows, T scale,
                                                             T thr) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     constexpr int M = NR / 2;
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_z_c2r_recover(const c2<T>* D, cons
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
     const long ro = row0 * NR;
-    c2<T> pre[z_fetch_count<NR>()];
+    c2<T> pre[z_fetch_count<T, NR>()];
     zrow_fetch<T, NR>(pre, D + row0 * (M + 1), nl);
     zrow_put<T, NR, false>(lds, pre, 0.0);
     zrow_inverse_lds<T, NR>(lds, stw, twf,
@@ -375,7 +375,7 @@ template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
                                                          const c2<T>* __restrict__ twh,
                                                          const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     constexpr int MS = NR / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -536,7 +536,7 @@ template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W,
                                                       const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
                                                       long nrows, double* part) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, cons
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows_pair<T, NR>();
     constexpr int MS = NR / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
     __shared__ RowTile<L> rt;
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, cons
                                                        const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows_pair<T, NR>();
     constexpr int MS = NR / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
     __shared__ RowTile<L> rt;
@@ -809,7 +809,7 @@ void launch_deriv_z_k(int nb, size_t smem, const DerivZArgs<T>& z, const Velocit
 template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z,
                                                         const VelocityArgs<T>* vel, const c2<T>* twh,
                                                         const c2<T>* twf, const GridSum* isum, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
@@ -826,7 +826,7 @@ template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const De
 template <typename T, int NR>
 hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T* G, T* out, double thr,
                             const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_z_c2r_recover<T, NR>, smem, flag);
@@ -839,7 +839,7 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
 template <typename T, int NR>
 hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W, const c2<T>* twh,
                       const c2<T>* twf, const GridSum& msum, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_q<T, NR>, smem, flag);
@@ -854,7 +854,7 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
 template <typename T, int NR>
 hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, c2<T>* WP, c2<T>* WQ,
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows_pair<T, NR>();
     const size_t smem = z_smem2<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
@@ -866,7 +866,7 @@ hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, 
 template <typename T, int NR>
 hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ,
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows_pair<T, NR>();
     const size_t smem = z_smem2<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_p2<T, NR>, smem, flag);
@@ -877,7 +877,7 @@ hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, 
 }
 template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_pair<T, NR>, smem, flag);

@@ -14,10 +14,16 @@
 namespace etd {
 namespace stk {
 
-template <int NR> constexpr int z_rows() { return NR >= 512 ? 8 : (NR >= 256 ? 16 : (4096 / NR)); }
+// Rows per workgroup of the z passes: 8 at lengths >= 512 and in FP64 at 256
+// (measured faster), 16 in FP32 at 256, 4096 / NR below.  The two-field
+// forward (z_rows_pair) takes 8 in FP32 at 256 too: its LDS holds both fields.
+template <typename T, int NR> constexpr int z_rows() {
+    return NR >= 512 ? 8 : (NR >= 256 ? (sizeof(T) == 8 ? 8 : 16) : (4096 / NR));
+}
+template <typename T, int NR> constexpr int z_rows_pair() { return NR >= 256 ? 8 : z_rows<T, NR>(); }
 template <int NR> constexpr int z_row_stride() { return line_stride<NR / 2 + 1>(); }
 template <typename T, int NR> constexpr size_t z_smem() {
-    return sizeof(c2<T>) * (size_t)(z_rows<NR>() * z_row_stride<NR>() + NR / 2);
+    return sizeof(c2<T>) * (size_t)(z_rows<T, NR>() * z_row_stride<NR>() + NR / 2);
 }
 
 // Row l of a z tile viewed as M complex pairs (x_{2n}, x_{2n+1}); rows past the end read 0.
@@ -52,7 +58,7 @@ template <typename T, int NR, class Op>
 __device__ __forceinline__ void zrow_forward_op(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
                                                 const Op& op, c2<T>* dst, int nl) {
     constexpr int M = NR / 2;
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     constexpr int LS = z_row_stride<NR>();
     if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
         for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
@@ -94,13 +100,13 @@ __device__ __forceinline__ void zrow_forward(c2<T>* lds, const c2<T>* stw, const
 // so one read of the sources feeds both transforms; field s goes through LDS
 // rows s * L + l; dst0 / dst1 receive the half-spectrum rows.
 template <typename T, int NR> constexpr size_t z_smem2() {
-    return sizeof(c2<T>) * (size_t)(2 * z_rows<NR>() * z_row_stride<NR>() + NR / 2);
+    return sizeof(c2<T>) * (size_t)(2 * z_rows_pair<T, NR>() * z_row_stride<NR>() + NR / 2);
 }
 template <typename T, int NR, class Op>
 __device__ __forceinline__ void zrow_forward2(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
                                               const Op& op, c2<T>* dst0, c2<T>* dst1, int nl) {
     constexpr int M = NR / 2;
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows_pair<T, NR>();
     constexpr int LS = z_row_stride<NR>();
     if constexpr (NextRadix<M>::v == M) {   // single stage: load to LDS, transform there
         for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
@@ -133,16 +139,17 @@ __device__ __forceinline__ void zrow_forward2(c2<T>* lds, const c2<T>* stw, cons
 
 // ---- inverse, in three steps so that a kernel with several outputs can fetch
 // the next input while the current one is transformed.
-template <int NR> constexpr int z_fetch_count() { return (z_rows<NR>() * (NR / 2 + 1) + kThreads - 1) / kThreads; }
+template <typename T, int NR> constexpr int z_fetch_count() { return (z_rows<T, NR>() * (NR / 2 + 1) + kThreads - 1) / kThreads; }
+template <typename T, int NR> using ZPre = c2<T>[z_fetch_count<T, NR>()];   // the fetched tile of a thread
 
 // Half-spectrum rows of a tile (nl <= L rows of M + 1 values) into registers;
 // element idx = threadIdx.x + p * kThreads of the row-major tile.
 template <typename T, int NR>
-__device__ __forceinline__ void zrow_fetch(c2<T> (&pre)[z_fetch_count<NR>()], const c2<T>* src, int nl) {
+__device__ __forceinline__ void zrow_fetch(ZPre<T, NR>& pre, const c2<T>* src, int nl) {
     constexpr int MS = NR / 2 + 1;
-    constexpr int TOT = z_rows<NR>() * MS;
+    constexpr int TOT = z_rows<T, NR>() * MS;
 #pragma unroll
-    for (int p = 0; p < z_fetch_count<NR>(); ++p) {
+    for (int p = 0; p < z_fetch_count<T, NR>(); ++p) {
         const int idx = threadIdx.x + p * kThreads;
         pre[p] = (idx < TOT && idx / MS < nl) ? src[idx] : mk<T>(0, 0);
     }
@@ -151,12 +158,12 @@ __device__ __forceinline__ void zrow_fetch(c2<T> (&pre)[z_fetch_count<NR>()], co
 // Registers -> LDS rows, times i kz (kz = az * derivative index of k, Nyquist
 // bin 0) if DZ.  The LDS rows must be free (callers barrier first).
 template <typename T, int NR, bool DZ>
-__device__ __forceinline__ void zrow_put(c2<T>* lds, const c2<T> (&pre)[z_fetch_count<NR>()], double az) {
+__device__ __forceinline__ void zrow_put(c2<T>* lds, const ZPre<T, NR>& pre, double az) {
     constexpr int MS = NR / 2 + 1;
-    constexpr int TOT = z_rows<NR>() * MS;
+    constexpr int TOT = z_rows<T, NR>() * MS;
     constexpr int LS = z_row_stride<NR>();
 #pragma unroll
-    for (int p = 0; p < z_fetch_count<NR>(); ++p) {
+    for (int p = 0; p < z_fetch_count<T, NR>(); ++p) {
         const int idx = threadIdx.x + p * kThreads;
         if (idx < TOT) {
             const int r = idx / MS, k = idx % MS;
@@ -178,7 +185,7 @@ template <typename T, int NR, class Op>
 __device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
                                                  const Op& op) {
     constexpr int M = NR / 2;
-    constexpr int L = z_rows<NR>();
+    constexpr int L = z_rows<T, NR>();
     constexpr int LS = z_row_stride<NR>();
     __syncthreads();
     // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) w^{-k}; each thread owns
@@ -226,8 +233,8 @@ __device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, c
 
 // Outputs per thread of zrow_inverse_lds: the slots an indexed store op
 // (lines.h, IndexedOf) is given, 0 .. z_out_slots - 1.
-template <int NR> constexpr int z_out_slots() {
-    constexpr int M = NR / 2, L = z_rows<NR>();
+template <typename T, int NR> constexpr int z_out_slots() {
+    constexpr int M = NR / 2, L = z_rows<T, NR>();
     if constexpr (NextRadix<M>::v == M) {
         return (L * M + kThreads - 1) / kThreads;
     } else {
@@ -241,7 +248,7 @@ template <int NR> constexpr int z_out_slots() {
 template <typename T, int NR, bool DZ>
 __device__ __forceinline__ void zrow_inverse(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
                                              const c2<T>* src, T* dst_rows, int nl, T scale, double az) {
-    c2<T> pre[z_fetch_count<NR>()];
+    c2<T> pre[z_fetch_count<T, NR>()];
     zrow_fetch<T, NR>(pre, src, nl);
     zrow_put<T, NR, DZ>(lds, pre, az);
     zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, NR / 2>{reinterpret_cast<c2<T>*>(dst_rows), nl, scale});
