@@ -290,7 +290,7 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
 /* psi = (-Delta_S,h)^{-1} f on a narrow band (Section 2.1: Delta_S,h of
  * operator:diff with face coefficients g_{i+1/2} = (g_i + g_{i+1})/2, its
  * inverse on mean-zero grid functions with the mean of f removed; Section
- * 3.2: assembled and solved only on the band nodes).  Band: the nodes with
+ * 3.2: the operator is set up and inverted on the band nodes alone).  Band: the nodes with
  * mask[i] != 0 (uint8, grid layout, e.g. from etd_narrowband_build's rule);
  * faces to nodes off the band carry no flux, the band means of f and of psi
  * are removed, psi = 0 off the band.  The band must be connected (its

@@ -278,7 +278,7 @@ def band_matrix(g: np.ndarray, mask: np.ndarray, grid: Grid):
 
 
 def lapinv_S_band(f: np.ndarray, g: np.ndarray, mask: np.ndarray, grid: Grid) -> np.ndarray:
-    """(-Delta_{S,h})^{-1} f assembled and solved on a narrow band.
+    """(-Delta_{S,h})^{-1} f, set up and inverted on a narrow band.
 
     Section 2.1 (operator:diff) defines Delta_{S,h} with face coefficients
     g_{i+1/2} = (g_i + g_{i+1})/2 and its inverse on mean-zero functions,

@@ -34,7 +34,7 @@ Readings (ambiguity register; listed in the design notes):
     from FFT(g(phi^{n+1}) u^n) (Section 3.3);
   * A0 = int phi^0 when ``A0_from_initial``;
   * ``surface_nonlocal``: the nonlocal term uses (-Delta_{S,h})^{-1}
-    assembled and solved on the band (core.lapinv_S_band, with g = g+ of
+    set up and inverted on the band (core.lapinv_S_band, with g = g+ of
     the stage) instead of the constant-coefficient (-Delta_h)^{-1}; the
     energy diagnostic keeps (-Delta_h)^{-1};
   * ``frozen_membrane``: phi keeps its initial value and only the g u
