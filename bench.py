@@ -200,7 +200,7 @@ def surface_measure(n, steps):
     from paper_2606_04347_amd import etd, inputs
     ci = inputs.coupled_membrane(n=n, tau=1e-4)
     out = {"workload": f"coupled ETDRK2 FP32, {n}^3 grid, eps=3h, tau=1e-4, band |2 phi - 1| < 0.995, nonlocal "
-                       f"term by the band solve (FP64 Jacobi-PCG, relative residual 1e-9)", "grid": [n, n, n],
+                       f"term by the band solve (FP64 CG, 16-term Chebyshev polynomial preconditioner, relative residual 1e-9)", "grid": [n, n, n],
            "steps": steps}
     for name, flags in (("band_solve", etd.F_SURFACE_NONLOCAL), ("fft_inverse", 0)):
         plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32, band_threshold=0.995,

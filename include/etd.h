@@ -296,11 +296,12 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
  * are removed, psi = 0 off the band.  The band must be connected (its
  * constants are then the only null space).  g (> 0 on the band), f and psi
  * are device arrays in the grid layout of the instance, element type dtype
- * (psi may alias f).  FP64 conjugate gradients with the Jacobi
- * preconditioner from psi = 0, until the relative residual is <= tol or
- * after max_iter iterations; *iters_out and *relres_out (host, nullable)
- * report the outcome -- not converging is reported there, not as an error.
- * Uses a workspace of about 60 bytes per grid point, allocated on the first
+ * (psi may alias f).  FP64 conjugate gradients from psi = 0, preconditioned
+ * by a 16-term Chebyshev polynomial of the Jacobi-scaled operator, until the
+ * relative residual is <= tol or after max_iter iterations; *iters_out and
+ * *relres_out (host, nullable) report the outcome -- not converging is
+ * reported there, not as an error.
+ * Uses a workspace of about 92 bytes per grid point, allocated on the first
  * call and kept by the plan.  Synchronizes.
  * Errors: ETD_E_ARG (null pointers, dtype, tol not finite and > 0,
  * max_iter < 1), ETD_E_NOMEM, ETD_E_HIP. */

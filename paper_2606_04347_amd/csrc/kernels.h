@@ -143,14 +143,17 @@ void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const
 // flags[i] = |2 phi_i - 1| < thr (FP64); counts per block, exclusive scan, stable scatter.
 template <typename T>
 void band_flags(long n, const T* phi, double thr, uint8_t* flags, hipStream_t s);
-// (-Delta_S,h)^{-1} on a narrow band (surface.hip): FP64 Jacobi-preconditioned
-// conjugate gradients (single-reduction form) over the band list
+// (-Delta_S,h)^{-1} on a narrow band (surface.hip): FP64 conjugate gradients
+// (single-reduction form) with a Chebyshev polynomial preconditioner over the
+// band list
 // idx[0 .. *total) of mask.  Workspace
 // carved from one device allocation of surface_work_bytes(n) bytes (its own
 // band list buffers idx / cnt / total serve callers without one).
 struct SurfaceWork {
     double *x = nullptr, *u = nullptr;                                                // grid layout
     double *r = nullptr, *p = nullptr, *s = nullptr, *w = nullptr, *dinv = nullptr;   // band order
+    double *cres = nullptr, *cz = nullptr;   // preconditioner residual and sum (band order)
+    double *dA = nullptr, *dB = nullptr;     // preconditioner directions (grid layout)
     int32_t* idx = nullptr;
     int64_t *cnt = nullptr, *total = nullptr;
     double *part = nullptr, *S = nullptr;

@@ -7,9 +7,20 @@
 // w_ij = (g_i + g_j) / (2 h_d^2); faces to nodes off the band carry no flux.
 // Right-hand side f_i - mean_band(f); A is symmetric positive semidefinite
 // with the constants of a connected band as its null space, so CG from
-// psi = 0 with the Jacobi preconditioner converges on the mean-zero part;
-// the band mean of the iterate is removed at the end and psi = 0 off the
-// band.
+// psi = 0 converges on the mean-zero part; the band mean of the iterate is
+// removed at the end and psi = 0 off the band.
+//
+// Preconditioner: M^-1 = p(D^-1 A) D^-1 with D the diagonal of A and p the
+// polynomial of kChebTerms terms of Chebyshev acceleration (Saad, Iterative
+// Methods for Sparse Linear Systems, the Chebyshev iteration) for
+// D^-1 A z = D^-1 r from z = 0 on [b / kChebRatio, b], b = 2.  D^-1 A =
+// I - D^-1 W with D^-1 W row-stochastic, so its spectrum lies in [0, 2];
+// there 1 - lambda p(lambda) is a scaled Chebyshev polynomial of modulus
+// < 1 on (0, 2], so p > 0 and M is symmetric positive definite
+// (p(D^-1 A) D^-1 = D^-1/2 p(D^-1/2 A D^-1/2) D^-1/2).  With one term it is
+// Jacobi.  The polynomial lowers the condition number about kChebTerms^2
+// times, so CG takes about kChebTerms times fewer iterations, each with
+// kChebTerms - 1 extra stencil launches and no extra reduction.
 //
 // The iteration is the single-reduction (Chronopoulos-Gear) form of PCG:
 // one vector-update launch, one launch for the product w = A u with all
@@ -29,6 +40,12 @@ namespace {
 
 constexpr int kSbThreads = 256;
 constexpr int kSbBlocks = 4096;
+// Chebyshev preconditioner: terms and interval ratio.  Measured at 256^3
+// (1.22e6 band nodes, relative residual 1e-9): Jacobi 1,061 iterations in
+// 62.7 ms; 8 terms on [2/300, 2] 139 in 34.1 ms; 16 on [2/1000, 2] 71 in
+// 32.5 ms (the stencil applications then dominate).
+constexpr int kChebTerms = 16;
+constexpr double kChebRatio = 1000.0;
 
 enum SbSlot {
     SB_GAMMA = 0, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT
@@ -102,23 +119,75 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
 
 // r = f - mean, u = D^-1 r, x = 0, p = s = 0 (band nodes); clears the done
 // flag of an earlier solve.
+// First term of the preconditioner for node k (band order), i = idx[k]:
+// residual c = D^-1 r, direction d0 = c / theta (grid layout), z = d0; with
+// a one-term polynomial z is the preconditioned residual u itself.
+struct ChebStart {
+    double inv_theta;
+    int single;
+    double* cres;
+    double* cz;
+    double* d0;
+    double* u;
+    __device__ __forceinline__ void operator()(long k, long i, double rk, double dk) const {
+        const double c = rk * dk;
+        const double d = c * inv_theta;
+        cres[k] = c;
+        cz[k] = d;
+        d0[i] = d;
+        if (single) u[i] = d;
+    }
+};
+
+// r = f - mean, x = 0, p = s = 0 (band nodes), the preconditioner's first
+// term; clears the done flag of an earlier solve.
 template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_init(const T* __restrict__ f, const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total,
                                                         const double* __restrict__ dinv, double* S, double* x,
-                                                        double* u, double* r, double* p, double* sv) {
+                                                        double* r, double* p, double* sv, ChebStart cs) {
     const long nb = *total;
     const double mean = S[SB_MEAN];
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
         const double rk = (double)f[i] - mean;
         r[k] = rk;
-        u[i] = rk * dinv[k];
+        cs(k, i, rk, dinv[k]);
         x[i] = 0.0;
         p[k] = 0.0;
         sv[k] = 0.0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) S[SB_DONE] = 0.0;
+}
+
+// One further term of the preconditioner: c -= D^-1 A d_prev (d_prev read at
+// the band neighbours, grid layout), d = c1 d_prev + c2 c into the other
+// direction buffer, z += d; the last term writes z to u (grid layout).
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __restrict__ G,
+                                                        const uint8_t* __restrict__ mask,
+                                                        const int32_t* __restrict__ idx,
+                                                        const int64_t* __restrict__ total, const double* S,
+                                                        const double* __restrict__ dinv,
+                                                        const double* __restrict__ dprev, double* dnext, double* cres,
+                                                        double* cz, double c1, double c2, int last, double* u) {
+    if (sb_done(S)) return;
+    const long nb = *total;
+    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+        const long i = idx[k];
+        const double gi = (double)G[i], di = dprev[i];
+        double a = 0.0;
+        for_neighbours(b, i, [&](long j, double ih2) {
+            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (di - dprev[j]);
+        });
+        const double c = cres[k] - dinv[k] * a;
+        cres[k] = c;
+        const double d = c1 * di + c2 * c;
+        dnext[i] = d;
+        const double z = cz[k] + d;
+        cz[k] = z;
+        if (last) u[i] = z;
+    }
 }
 
 // w = A u on the band; partials (r, u), (w, u), (r, r).
@@ -148,12 +217,13 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* _
     store_partials(ru.val(), wu.val(), rr.val(), part);
 }
 
-// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = D^-1 r.
+// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, the
+// preconditioner's first term of the new r.
 __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __restrict__ idx,
                                                            const int64_t* __restrict__ total,
                                                            const double* __restrict__ dinv, const double* S,
-                                                           double* x, double* u, double* r, double* p, double* sv,
-                                                           const double* __restrict__ w) {
+                                                           double* x, const double* u, double* r, double* p,
+                                                           double* sv, const double* __restrict__ w, ChebStart cs) {
     if (sb_done(S)) return;
     const long nb = *total;
     const double alpha = S[SB_ALPHA], beta = S[SB_BETA];
@@ -166,7 +236,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __rest
         x[i] += alpha * pk;
         const double rk = r[k] - alpha * sk;
         r[k] = rk;
-        u[i] = rk * dinv[k];
+        cs(k, i, rk, dinv[k]);
     }
 }
 
@@ -274,6 +344,10 @@ static size_t surface_layout(long n, char* base, SurfaceWork* w) {
     t.s = (double*)take(n * sizeof(double));
     t.w = (double*)take(n * sizeof(double));
     t.dinv = (double*)take(n * sizeof(double));
+    t.cres = (double*)take(n * sizeof(double));
+    t.cz = (double*)take(n * sizeof(double));
+    t.dA = (double*)take(n * sizeof(double));
+    t.dB = (double*)take(n * sizeof(double));
     t.idx = (int32_t*)take(n * sizeof(int32_t));
     t.cnt = (int64_t*)take((band_blocks(n) + 2) * sizeof(int64_t));
     t.total = (int64_t*)take(sizeof(int64_t));
@@ -294,6 +368,29 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     const BandGeom b = band_geom(g);
     const double tol2 = tol * tol;
     const dim3 grid(kSbBlocks), blk(kSbThreads);
+    // Chebyshev acceleration on [lo, hi]: theta, delta, sigma1 = theta / delta,
+    // rho_0 = 1 / sigma1, rho_j = 1 / (2 sigma1 - rho_{j-1}); term j >= 1 takes
+    // d_j = rho_j rho_{j-1} d_{j-1} + (2 rho_j / delta) c_j.
+    constexpr int terms = kChebTerms;
+    const double hi = 2.0, lo = hi / kChebRatio;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma1 = theta / delta;
+    double c1[kChebTerms], c2[kChebTerms];
+    double rho = 1.0 / sigma1;
+    for (int j = 1; j < terms; ++j) {
+        const double rn = 1.0 / (2.0 * sigma1 - rho);
+        c1[j] = rn * rho;
+        c2[j] = 2.0 * rn / delta;
+        rho = rn;
+    }
+    const ChebStart cs{1.0 / theta, terms == 1 ? 1 : 0, w.cres, w.cz, w.dA, w.u};
+    auto precond = [&]() {   // terms 1 .. terms - 1 (term 0 is formed with r)
+        for (int j = 1; j < terms; ++j) {
+            double* dp = (j % 2 == 1) ? w.dA : w.dB;
+            double* dn = (j % 2 == 1) ? w.dB : w.dA;
+            hipLaunchKernelGGL(k_sb_cheb<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.dinv, dp, dn, w.cres,
+                               w.cz, c1[j], c2[j], j == terms - 1 ? 1 : 0, w.u);
+        }
+    };
     auto fin = [&](int mode) {
         hipLaunchKernelGGL(k_sb_final, dim3(1), blk, 0, s, mode, w.part, total, tol2, w.S);
     };
@@ -302,7 +399,8 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     };
     hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, G, f, mask, idx, total, w.dinv, w.part);
     fin(FIN_MEAN);
-    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.u, w.r, w.p, w.s);
+    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.r, w.p, w.s, cs);
+    precond();
     matvec();
     fin(FIN_START);
     hipError_t e = hipGetLastError();
@@ -313,7 +411,8 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     for (int it = 0; it < max_iter && done == 0.0; it += kChunk) {
         for (int j = 0; j < kChunk && it + j < max_iter; ++j) {
             hipLaunchKernelGGL(k_sb_vectors, grid, blk, 0, s, idx, total, w.dinv, w.S, w.x, w.u, w.r, w.p, w.s,
-                               w.w);
+                               w.w, cs);
+            precond();
             matvec();
             fin(FIN_STEP);
         }
