@@ -117,8 +117,6 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
     store_partials(acc.val(), 0.0, 0.0, part);
 }
 
-// r = f - mean, u = D^-1 r, x = 0, p = s = 0 (band nodes); clears the done
-// flag of an earlier solve.
 // First term of the preconditioner for node k (band order), i = idx[k]:
 // residual c = D^-1 r, direction d0 = c / theta (grid layout), z = d0; with
 // a one-term polynomial z is the preconditioned residual u itself.
