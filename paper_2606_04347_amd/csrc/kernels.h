@@ -154,6 +154,7 @@ struct SurfaceWork {
     double *r = nullptr, *p = nullptr, *s = nullptr, *w = nullptr, *dinv = nullptr;   // band order
     double *cres = nullptr, *cz = nullptr;   // preconditioner residual and sum (band order)
     double *dA = nullptr, *dB = nullptr;     // preconditioner directions (grid layout)
+    double* gm = nullptr;                    // g on the band, -1 off it (grid layout, element type of g)
     int32_t* idx = nullptr;
     int64_t *cnt = nullptr, *total = nullptr;
     double *part = nullptr, *S = nullptr;

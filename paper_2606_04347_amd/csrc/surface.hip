@@ -96,9 +96,18 @@ __device__ __forceinline__ void store_partials(double a, double b, double c, dou
 __device__ __forceinline__ bool sb_done(const double* S) { return S[SB_DONE] != 0.0; }
 
 // Jacobi diagonal (its inverse) and the band sum of f.
+// gm = g on the band, -1 off it (g >= 0 everywhere): one gather per
+// neighbour tells both whether the face enters and its coefficient.
 template <typename T>
-__global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __restrict__ G,
-                                                         const T* __restrict__ f, const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(kSbThreads) void k_sb_gm(long n, const T* __restrict__ G,
+                                                      const uint8_t* __restrict__ mask, T* __restrict__ gm) {
+    for (long i = (long)blockIdx.x * kSbThreads + threadIdx.x; i < n; i += (long)gridDim.x * kSbThreads)
+        gm[i] = mask[i] ? G[i] : (T)-1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __restrict__ gm,
+                                                         const T* __restrict__ f,
                                                          const int32_t* __restrict__ idx,
                                                          const int64_t* __restrict__ total, double* dinv,
                                                          double* part) {
@@ -106,10 +115,11 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
     Neu acc;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
-        const double gi = (double)G[i];
+        const double gi = (double)gm[i];
         double d = 0.0;
         for_neighbours(b, i, [&](long j, double ih2) {
-            if (mask[j]) d += 0.5 * (gi + (double)G[j]) * ih2;
+            const T gj = gm[j];
+            if (gj >= (T)0) d += 0.5 * (gi + (double)gj) * ih2;
         });
         dinv[k] = d > 0.0 ? 1.0 / d : 0.0;
         acc.add((double)f[i]);
@@ -162,8 +172,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_init(const T* __restrict__ f,
 // the band neighbours, grid layout), d = c1 d_prev + c2 c into the other
 // direction buffer, z += d; the last term writes z to u (grid layout).
 template <typename T>
-__global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __restrict__ G,
-                                                        const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __restrict__ gm,
                                                         const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total, const double* S,
                                                         const double* __restrict__ dinv,
@@ -173,10 +182,11 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __r
     const long nb = *total;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
-        const double gi = (double)G[i], di = dprev[i];
+        const double gi = (double)gm[i], di = dprev[i];
         double a = 0.0;
         for_neighbours(b, i, [&](long j, double ih2) {
-            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (di - dprev[j]);
+            const T gj = gm[j];
+            if (gj >= (T)0) a += 0.5 * (gi + (double)gj) * ih2 * (di - dprev[j]);
         });
         const double c = cres[k] - dinv[k] * a;
         cres[k] = c;
@@ -190,8 +200,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __r
 
 // w = A u on the band; partials (r, u), (w, u), (r, r).
 template <typename T>
-__global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* __restrict__ G,
-                                                          const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* __restrict__ gm,
                                                           const int32_t* __restrict__ idx,
                                                           const int64_t* __restrict__ total, const double* S,
                                                           const double* __restrict__ u, const double* __restrict__ r,
@@ -201,10 +210,11 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* _
     Neu ru, wu, rr;
     for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
         const long i = idx[k];
-        const double gi = (double)G[i], ui = u[i];
+        const double gi = (double)gm[i], ui = u[i];
         double a = 0.0;
         for_neighbours(b, i, [&](long j, double ih2) {
-            if (mask[j]) a += 0.5 * (gi + (double)G[j]) * ih2 * (ui - u[j]);
+            const T gj = gm[j];
+            if (gj >= (T)0) a += 0.5 * (gi + (double)gj) * ih2 * (ui - u[j]);
         });
         w[k] = a;
         const double rk = r[k];
@@ -346,6 +356,7 @@ static size_t surface_layout(long n, char* base, SurfaceWork* w) {
     t.cz = (double*)take(n * sizeof(double));
     t.dA = (double*)take(n * sizeof(double));
     t.dB = (double*)take(n * sizeof(double));
+    t.gm = (double*)take(n * sizeof(double));
     t.idx = (int32_t*)take(n * sizeof(int32_t));
     t.cnt = (int64_t*)take((band_blocks(n) + 2) * sizeof(int64_t));
     t.total = (int64_t*)take(sizeof(int64_t));
@@ -381,11 +392,12 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
         rho = rn;
     }
     const ChebStart cs{1.0 / theta, terms == 1 ? 1 : 0, w.cres, w.cz, w.dA, w.u};
+    T* gm = reinterpret_cast<T*>(w.gm);   // n values of T in a slot of n doubles
     auto precond = [&]() {   // terms 1 .. terms - 1 (term 0 is formed with r)
         for (int j = 1; j < terms; ++j) {
             double* dp = (j % 2 == 1) ? w.dA : w.dB;
             double* dn = (j % 2 == 1) ? w.dB : w.dA;
-            hipLaunchKernelGGL(k_sb_cheb<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.dinv, dp, dn, w.cres,
+            hipLaunchKernelGGL(k_sb_cheb<T>, grid, blk, 0, s, b, gm, idx, total, w.S, w.dinv, dp, dn, w.cres,
                                w.cz, c1[j], c2[j], j == terms - 1 ? 1 : 0, w.u);
         }
     };
@@ -393,9 +405,12 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
         hipLaunchKernelGGL(k_sb_final, dim3(1), blk, 0, s, mode, w.part, total, tol2, w.S);
     };
     auto matvec = [&]() {
-        hipLaunchKernelGGL(k_sb_matvec<T>, grid, blk, 0, s, b, G, mask, idx, total, w.S, w.u, w.r, w.w, w.part);
+        hipLaunchKernelGGL(k_sb_matvec<T>, grid, blk, 0, s, b, gm, idx, total, w.S, w.u, w.r, w.w, w.part);
     };
-    hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, G, f, mask, idx, total, w.dinv, w.part);
+    const long n = g.nreal();
+    const int nbo = (int)std::min<long>(4096, (n + kSbThreads - 1) / kSbThreads);
+    hipLaunchKernelGGL(k_sb_gm<T>, dim3(nbo), blk, 0, s, n, G, mask, gm);
+    hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, gm, f, idx, total, w.dinv, w.part);
     fin(FIN_MEAN);
     hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.r, w.p, w.s, cs);
     precond();
@@ -403,7 +418,8 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     fin(FIN_START);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // three launches per iteration; the host reads the done flag every 25
+    // 3 + kChebTerms - 1 launches per iteration; the host reads the done flag
+    // every 25 iterations
     constexpr int kChunk = 25;
     double done = 0.0;
     for (int it = 0; it < max_iter && done == 0.0; it += kChunk) {
@@ -420,8 +436,6 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     }
     hipLaunchKernelGGL(k_sb_xsum, grid, blk, 0, s, idx, total, w.x, w.part);
     fin(FIN_XMEAN);
-    const long n = g.nreal();
-    const int nbo = (int)std::min<long>(4096, (n + kSbThreads - 1) / kSbThreads);
     hipLaunchKernelGGL(k_sb_out<T>, dim3(nbo), blk, 0, s, n, mask, w.x, w.S, psi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (res) {
