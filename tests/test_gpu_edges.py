@@ -1,0 +1,84 @@
+"""GPU: degenerate inputs of the coupled step through the C ABI: zero steps,
+an empty narrow band (the list and a band-restricted step), and a grid with
+no membrane (phi = 0, so g = 0 and every surface term vanishes), each
+against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, needs_gpu, rel_linf, report, torch
+from oracle import band as oband
+from oracle.core import Grid
+from oracle.coupled import CoupledOracle
+from paper_2606_04347_amd import etd, inputs
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def case(shape=(16, 16, 16)):
+    return inputs.coupled_membrane(n=shape, seed=31, tau=1e-4)
+
+
+def test_zero_steps_keep_the_state_and_negative_counts_are_rejected():
+    ci = case()
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2))
+    plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+    before = [host(t) for t in plan.get_state(0)]
+    plan.step(0)
+    after = [host(t) for t in plan.get_state(0)]
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    assert plan.diagnostics(0)["step"] == 0
+    with pytest.raises(etd.EtdError) as ei:
+        plan.step(-1)
+    assert ei.value.status == etd.ETD_E_ARG
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
+def test_empty_narrow_band_list(precision):
+    ci = case()
+    dt = torch.float64 if precision == etd.FP64 else torch.float32
+    phi = torch.zeros(ci.shape, dtype=dt, device="cuda")     # |2 phi - 1| = 1 everywhere
+    plan = etd.Plan(etd.coupled_instance(ci, precision=precision))
+    assert len(plan.narrowband(0, phi, 0.995)) == 0
+    assert len(plan.narrowband(0, phi, 0.995, capacity=0)) == 0
+    plan.close()
+
+
+def run_pair(ci, phi0, nsteps, **kw):
+    o = CoupledOracle(Grid(ci.shape, ci.half_len), ci.params, ci.tau, etd.ETDRK2,
+                      band_threshold=kw.get("band_threshold", 0.0), band_rebuild_every=kw.get("band_rebuild_every", 10))
+    o.set_state(phi0, ci.u0)
+    o.run(nsteps)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, **kw))
+    plan.set_state(0, dev(phi0), dev(ci.u0))
+    plan.step(nsteps)
+    phi, u = (host(t) for t in plan.get_state(0))
+    d = plan.diagnostics(0)
+    plan.close()
+    return o, phi, u, d
+
+
+def test_step_with_an_empty_band_matches_oracle():
+    """A threshold no point meets: the band is empty at set_state and at the
+    rebuild after step 2, and the band-restricted surface terms vanish."""
+    ci = case()
+    assert len(oband.band_list(ci.phi0, 1e-9)) == 0
+    o, phi, u, d = run_pair(ci, ci.phi0, 3, band_threshold=1e-9, band_rebuild_every=2)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("edge_empty_band", err_phi=ephi, err_u=eu, band=d["band_count"])
+    assert d["band_count"] == 0
+    assert ephi <= 1e-12 and eu <= 1e-12
+
+
+@pytest.mark.parametrize("level", [0.0, 1.0])
+def test_no_membrane_matches_oracle(level):
+    """phi constant at a pure phase: g = 0 and grad phi = 0 everywhere, so the
+    recovery takes its G <= threshold branch at every point."""
+    ci = case()
+    phi0 = np.full(ci.shape, level)
+    o, phi, u, d = run_pair(ci, phi0, 2)
+    ephi = float(np.abs(phi - o.phi()).max())
+    eu = rel_linf(u, o.u)
+    report("edge_no_membrane", level=level, abs_err_phi=ephi, err_u=eu)
+    assert np.isfinite(u).all() and np.isfinite(phi).all()
+    assert ephi <= 1e-13 and eu <= 1e-12
