@@ -82,3 +82,27 @@ def test_no_membrane_matches_oracle(level):
     report("edge_no_membrane", level=level, abs_err_phi=ephi, err_u=eu)
     assert np.isfinite(u).all() and np.isfinite(phi).all()
     assert ephi <= 1e-13 and eu <= 1e-12
+
+
+@pytest.mark.parametrize("bad", ["zero", "negative", "nan"])
+def test_fixed_set_state_rejects_g_not_positive_and_finite(bad):
+    fi = inputs.fixed_membrane(dim=2, n=16, eps_pm=0.0625)
+    g = fi.g.copy()
+    g.flat[7] = {"zero": 0.0, "negative": -1e-3, "nan": np.nan}[bad]
+    plan = etd.Plan(etd.fixed_instance(fi, scheme=etd.ETD1))
+    with pytest.raises(etd.EtdError) as ei:
+        plan.set_state(0, dev(g), dev(fi.u0))
+    assert ei.value.status == etd.ETD_E_ARG
+    plan.set_state(0, dev(fi.g), dev(fi.u0))   # the plan stays usable
+    plan.step(1)
+    plan.close()
+
+
+def test_nonfinite_state_is_reported():
+    ci = case()
+    u0 = ci.u0.copy()
+    u0.flat[123] = np.nan
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2))
+    plan.set_state(0, dev(ci.phi0), dev(u0))
+    assert plan.diagnostics(0)["nonfinite"] == 1
+    plan.close()
