@@ -84,7 +84,9 @@ __global__ __launch_bounds__(kB) void k_cheb(GridK g, FixedK K, const double* __
                        double* y, double* acc, double c, double c0, int first) {
     const long n = g.nreal();
     const double s2 = 2.0 / (b - a), sh = (b + a) / (b - a);
-    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    // workgroups renumbered so each XCD walks a contiguous range of rows: the
+    // y and x neighbours of a point are then mostly read through the same L2
+    for (long i = (long)xcd_remap(blockIdx.x, gridDim.x) * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
         const double xi = x[i];
         const double Lx = K.B * xi + K.eps_u * H_apply(g, i, G, isg, x);
         double yi = alpha * (s2 * Lx - sh * xi);
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(kB) void k_cheb(GridK g, FixedK K, const double* __
 __global__ __launch_bounds__(kB) void k_L(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg,
                     const double* __restrict__ x, double* __restrict__ out) {
     const long n = g.nreal();
-    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB)
+    for (long i = (long)xcd_remap(blockIdx.x, gridDim.x) * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB)
         out[i] = K.B * x[i] + K.eps_u * H_apply(g, i, G, isg, x);
 }
 
