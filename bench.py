@@ -382,7 +382,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU slab "
-              "decomposition is a design note, not part of this build.", file=sys.stderr)
+              "decomposition is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
 
