@@ -316,3 +316,117 @@ def test_coupled_nonlocal_energy_parseval():
     nz = mu > 0
     pars = grid.cell * np.sum(np.abs(Q[nz]) ** 2 / mu[nz]) / q.size
     assert abs(e["E_nonlocal"] - 0.5 * ci.params.gamma * pars) <= 1e-12 * abs(e["E_nonlocal"])
+
+
+@pytest.mark.parametrize("m", [(1, 0, 0), (0, 1, 2)])
+def test_velocity_of_a_translating_wave(m):
+    """The membrane velocity v = -phi_t grad phi / |grad phi|^2 (defined with
+    eqn:model_OK) of a rigidly translating profile phi = psi(x.n - c t) is
+    exactly c n wherever grad phi != 0.  The oracle forms phi_t as a quotient of
+    two states tau apart and grad phi spectrally, so on the travelling wave
+    phi = 0.5 + 0.4 sin(m.x - c |m| t) (band limited: its spectral gradient is
+    exact) its v tends to c n, n = m / |m|, at first order in tau, and has no
+    component across n.  Compared where |cos| > 0.3, away from the points
+    where grad phi vanishes."""
+    n, X = 16, math.pi
+    grid = Grid((n, n, n), (X, X, X))
+    ci, _ = case(n=n, half_len=X)
+    mv = np.array(m, dtype=np.float64)
+    nrm = float(np.linalg.norm(mv))
+    nhat = mv / nrm
+    c = 0.7
+    x = inputs.mesh(grid.n, grid.half_len)
+    s = sum(mv[d] * x[d] for d in range(3))
+    errs = []
+    for tau in (2e-3, 1e-3, 5e-4):
+        o = CoupledOracle(grid, ci.params, tau, 2)
+        phase_new = s - c * nrm * tau
+        phi_old = 0.5 + 0.4 * np.sin(s)
+        phi_new = 0.5 + 0.4 * np.sin(phase_new)
+        v = o.velocity(phi_old, core.fft(phi_new), core.g_loc(phi_new))
+        sel = np.abs(np.cos(phase_new)) > 0.3
+        along = sum(v[d] * nhat[d] for d in range(3))
+        across = [v[d] - along * nhat[d] for d in range(3)]
+        assert max(np.abs(a[sel]).max() for a in across) <= 1e-10 * c
+        errs.append(float(np.abs(along[sel] - c).max()))
+    assert errs[-1] <= 2.0 * c * c * nrm * 5e-4, errs
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((rates > 0.9) & (rates < 1.1)), (errs, rates)
+
+
+def _band_limited_perturbation(grid):
+    """A smooth perturbation made of a few low Fourier modes, the mean
+    included (no Nyquist content)."""
+    x, y, z = inputs.mesh(grid.n, grid.half_len)
+    return 0.25 + np.cos(x) * np.sin(2.0 * y) + 0.5 * np.cos(3.0 * z + 1.0) + 0.3 * np.sin(x + y - 2.0 * z)
+
+
+def _directional_derivative(fun, e=1e-5):
+    return (fun(e) - fun(-e)) / (2.0 * e)
+
+
+def test_phi_energy_first_variation_is_the_model_force():
+    """The coupled energy components of the phi equation, pinned by their first
+    variation against eqn:model_force: with w = Delta phi - W'(phi)/eps^2,
+      d/de E_surf(phi + e psi) = <-lambda_surf w, psi>_h        (tension term),
+      d/de E_bend(phi + e psi) = <kappa (Delta - W''/eps^2) w, psi>_h (bending term),
+      d/de E_area(phi + e psi) = M_area (int phi - A0) <1, psi>_h,
+    the first two being minus the tension and bending forces of
+    eqn:model_force, which is their L2 gradient flow.  Spectral derivatives;
+    psi has no Nyquist content, where the discrete gradient and Laplacian
+    symbols differ."""
+    ci, grid = case(n=16, half_len=math.pi, eps_h=2.0)
+    p = ci.params
+    o = oracle_for(ci, grid)
+    o.A0 = grid.cell * float(np.sum(ci.phi0)) - 0.3      # away from the constraint, so its force is not 0
+    psi = _band_limited_perturbation(grid)
+    phi = ci.phi0
+    e2 = p.eps_phi ** 2
+
+    def energy_at(e):
+        o.phi_hat = core.fft(phi + e * psi)
+        return o.energy()
+
+    w = core.spectral_lap(phi, grid) - core.Wp(phi) / e2
+    dsurf = -p.lambda_surf * w
+    dbend = p.kappa * (core.spectral_lap(w, grid) - core.Wpp(phi) * w / e2)
+    darea = p.M_area * (grid.cell * float(np.sum(phi)) - o.A0) * np.ones_like(phi)
+    for name, dE in (("E_surf", dsurf), ("E_bend", dbend), ("E_area", darea)):
+        num = _directional_derivative(lambda e: energy_at(e)[name])
+        ref = core.inner(dE, psi, grid)
+        assert abs(num - ref) <= 1e-7 * abs(ref), (name, num, ref)
+
+
+def test_ok_energy_first_variation_is_the_model_ok_rhs():
+    """E_OK + E_nonlocal + E_mass as a functional of u at fixed g, pinned by its
+    first variation: eqn:model_OK is the L2 gradient flow of the membrane OK
+    energy (eqn:mem_OK_energy, with u - ubar in the nonlocal and mass terms
+    as eqn:model_OK writes them) plus advection, so with v = 0
+      d/de E(u + e psi) = -<RHS of eqn:model_OK, psi>_h."""
+    ci, grid = case(n=16, half_len=math.pi, eps_h=2.0)
+    p = ci.params
+    o = oracle_for(ci, grid)
+    psi = _band_limited_perturbation(grid)
+    u = ci.u0 + 0.2
+    g = core.g_loc(ci.phi0)
+    zero = [np.zeros(grid.n)] * 3
+
+    def energy_at(e):
+        o.u = u + e * psi
+        en = o.energy()
+        return en["E_ok"] + en["E_nonlocal"] + en["E_mass"]
+
+    num = _directional_derivative(energy_at)
+    ref = -core.inner(direct_u_rhs(u, g, zero, p, grid), psi, grid)
+    assert abs(num - ref) <= 1e-7 * abs(ref), (num, ref)
+    # each term on its own
+    parts = dict(E_ok=p.eps_u * -core.lap_S(u, g, grid) + g * core.Wp(u) / p.eps_u,
+                 E_nonlocal=p.gamma * g * core.lapinv(g * (u - p.ubar), grid),
+                 E_mass=p.M * g * grid.cell * float(np.sum(g * (u - p.ubar))))
+    for name, dE in parts.items():
+        def one(e, name=name):
+            o.u = u + e * psi
+            return o.energy()[name]
+        num = _directional_derivative(one)
+        ref = core.inner(dE, psi, grid)
+        assert abs(num - ref) <= 1e-7 * abs(ref), (name, num, ref)

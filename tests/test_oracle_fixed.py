@@ -315,3 +315,20 @@ def test_band_inverse_norm_of_the_config1_circle():
     C = core.lapinv_inf_norm(grid)
     print(f"C band {Cb:.6g}, C periodic {C:.6g}")
     assert np.isfinite(Cb) and Cb > C > 0
+
+
+def test_stabilizer_constants_of_the_64sq_circle():
+    """eqn:cond_MBP and eqn:cond_ES evaluated by hand for the 64^2 circle
+    (eps_pm = 0.0625 so eps_u = 3 sqrt(2) 0.0625 / 2 = 0.1325825, gamma = 1,
+    M = 600, |Omega| = 4, C = ||(-Delta_h)^{-1}||_inf = 0.1678365 on
+    [-1, 1)^2, L_W'' = 36, L_f'' = 6, L_f' = 3/2, L_g = 9/8):
+      B_MBP = 36/eps_u + (gamma C + M |Omega|) L_f'' L_g
+            = 271.5290 + 2400.1678 * 6.75 = 16,472.66
+      B_ES  = 36/eps_u + (gamma C / 2 + M |Omega| / 2) (L_f'' + L_f'^2) L_g
+            = 271.5290 + 1200.0839 * 9.28125 = 11,409.81"""
+    fi = inputs.fixed_membrane(dim=2, n=64, eps_pm=0.0625)
+    grid = Grid(fi.shape, fi.half_len)
+    C = core.lapinv_inf_norm(grid)
+    assert abs(C - 0.1678365) < 1e-6
+    assert abs(fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, C, grid.volume) - 16472.66) < 0.01
+    assert abs(fixed.B_es(fi.eps_u, fi.gamma, fi.M, C, grid.volume) - 11409.81) < 0.01
