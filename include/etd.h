@@ -156,7 +156,11 @@ etd_status etd_plan_destroy(etd_plan_t plan);
  *   coupled: a = phi^0, u = u^0 (Algorithm 1 inputs);
  *   fixed:   a = g (fixed localization field, every value > 0), u = U^0.
  * dtype gives the element type of a and u.  Copies on the plan's stream;
- * the caller may reuse the arrays after the stream reaches this point. */
+ * the caller may reuse the arrays after the stream reaches this point.
+ * Synchronizes.  A state holding a NaN or Inf is accepted: it is the
+ * detected non-finite state of etd_step below (etd_get_state then reports
+ * ETD_E_NONFINITE).  The fixed model's g must be finite and > 0 everywhere
+ * (ETD_E_ARG otherwise). */
 etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const void* u,
                          etd_dtype dtype);
 
@@ -175,11 +179,20 @@ etd_status etd_set_tau(etd_plan_t plan, int instance, double tau);
 
 /* Copy the current state of one instance into device arrays.
  *   coupled: a <- phi^n, u <- u^n;  fixed: a <- g (may be NULL), u <- U^n.
- * Synchronizes; returns ETD_E_NONFINITE if a NaN/Inf was detected. */
+ * Synchronizes.  The state is copied in every case; the return value is
+ * ETD_E_NONFINITE once a non-finite value has been detected (see etd_step). */
 etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dtype dtype);
 
 /* Advance every instance by nsteps time steps (ETD1 or ETDRK2 as planned).
- * Asynchronous.  Steps after a detected non-finite state are no-ops. */
+ * Asynchronous.  Non-finite values are detected on the device, per
+ * instance, by the FP64 sums every step forms (coupled: h^d sum phi after
+ * each phi stage and the mass of each u stage; fixed: the mass m_f of each
+ * remainder evaluation), and by etd_set_state on its inputs.  From then on
+ * the instance's steps leave its state (phi, u / U) as it is, also under a
+ * captured graph schedule: the kernels that write the state read the flag
+ * first.  Values written by the step in which the detection happens, before
+ * that point, remain.  Reported by etd_get_state and etd_diagnostics
+ * (ETD_E_NONFINITE); cleared by etd_set_state.  Other instances step on. */
 etd_status etd_step(etd_plan_t plan, int nsteps);
 
 /* Energy of one instance, FP64, written to host_out (synchronizes).

@@ -347,7 +347,8 @@ template <typename T> struct CoupledView {
 };
 
 // Grid sum of cell-weighted values into a device scalar slot.
-GridSum grid_sum(const Instance& I, int slot) { return GridSum{I.part, I.scal + slot, I.g.cell}; }
+GridSum grid_sum(const Instance& I, int slot) { return GridSum{I.part, I.scal + slot, I.g.cell, I.scal + S_HALT}; }
+double* halt_flag(const Instance& I) { return I.scal + S_HALT; }
 
 template <typename T> const FFTTables<T>& tables(const Instance& I);
 template <> const FFTTables<float>& tables<float>(const Instance& I) { return I.tf; }
@@ -388,10 +389,10 @@ hipError_t remainder_etd_2d(const Instance& I, CoupledView<T>& v, EtdStage st, c
     if (e != hipSuccess) return e;
     if ((e = fft_r2c_3d<T>(g, t, v.Q, v.Sb, s)) != hipSuccess) return e;
     switch (st) {
-        case ETD_STAGE_PHI1: spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, s); break;
-        case ETD_STAGE_PHI2: spec_etd_phi2<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, s); break;
-        case ETD_STAGE_U1: spec_etd_u1<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, s); break;
-        case ETD_STAGE_U2: spec_etd_u2<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, s); break;
+        case ETD_STAGE_PHI1: spec_etd_phi1<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, a.halt, s); break;
+        case ETD_STAGE_PHI2: spec_etd_phi2<T>(g, I.K, v.Sa, v.Sb, a.prev, a.ra, a.out, a.halt, s); break;
+        case ETD_STAGE_U1: spec_etd_u1<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, a.halt, s); break;
+        case ETD_STAGE_U2: spec_etd_u2<T>(g, I.K, v.Sa, v.Sb, a.out, a.ra, a.halt, s); break;
     }
     return hipGetLastError();
 }
@@ -418,7 +419,9 @@ hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, cons
     }
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<T>(n, phi_in, g.cell, I.part, I.scal + S_INTPHI, s); });
+    timed_kernel(PASS_REDUCE, fb, s, [&] {
+        reduce_sum<T>(n, phi_in, g.cell, I.part, I.scal + S_INTPHI, s, halt_flag(I));
+    });
     timed_kernel(PASS_R1, 8.0 * fb + mb, s, [&] {
         coupled_R1_point<T>(g, I.K, phi_in, v.lap, v.gx, v.gy, v.gz, v.u, mask, I.scal + S_INTPHI, I.A0, v.P, v.Q,
                             s);
@@ -440,13 +443,13 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const FFTTables<T>& t = tables<T>(I);
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    const EtdArgs<T> a{nullptr, v.Sra, v.Sgu};
+    const EtdArgs<T> a{nullptr, v.Sra, v.Sgu, halt_flag(I)};
     hipError_t e = hipSuccess;
     const bool surface = (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
     // band solve of the nonlocal term: q and m pointwise, psi = (-Delta_S,h)^{-1} q on the band
     auto surface_psi = [&]() -> hipError_t {
         timed_kernel(PASS_POINT, 3.0 * fb + mb, s, [&] {
-            coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, nullptr, I.part, I.scal + S_MASS, s);
+            coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, nullptr, I.part, I.scal + S_MASS, halt_flag(I), s);
         });
         const double tol = I.f32 ? 1e-9 : 1e-12;
         return surface_lapinv<T>(g, v.gp, v.P, mask, I.band_idx, I.band_total, v.psi, I.sw, tol, 20000,
@@ -460,17 +463,17 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
         const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
         if (e != hipSuccess) return e;
-        return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, s);
+        return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, halt_flag(I), s);
     }
     timed_kernel(PASS_POINT, 4.0 * fb + mb, s, [&] {
-        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, I.part, I.scal + S_MASS, s);
+        coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, v.Q, I.part, I.scal + S_MASS, halt_flag(I), s);
     });
     if ((e = lapinv_fused<T>(g, t, I.fd, v.P, v.Sa, v.psi, s)) != hipSuccess) return e;
     timed_kernel(PASS_P2, 7.0 * fb + mb, s, [&] {
         coupled_P2_point<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, v.psi, I.scal + S_MASS, mask, v.P, s);
     });
     if ((e = remainder_etd_2d<T>(I, v, st, a, s)) != hipSuccess) return e;
-    return c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, out, I.K.thr, s);
+    return c2r_recover<T>(g, t, v.Sgu, v.Stmp, v.u, v.gp, out, I.K.thr, halt_flag(I), s);
 }
 
 template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipStream_t s) {
@@ -498,18 +501,20 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // derivative pass, else a pointwise kernel after it
     const VelocityArgs<T> va{v.phiA, v.gp, v.vx, v.vy, v.vz, I.K.tau, I.K.thr};
     const VelocityArgs<T>* vel = g.nx > 1 ? &va : nullptr;
+    const double* halt = halt_flag(I);
     if (!frozen && !rk2) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi}, v.phiB, s,
-                                  vel));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi, halt}, v.phiB,
+                                  s, vel));
     } else if (!frozen) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St}, v.phiB, s));
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi}, v.phiB, s,
-                                  vel));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St, halt}, v.phiB,
+                                  s));
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi, halt}, v.phiB,
+                                  s, vel));
     }
     // phi^{n+1} and its derivatives are kept for the next step
     if (!vel && !frozen) {
         timed_kernel(PASS_POINT, 9.0 * fb, s, [&] {
-            coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, s);
+            coupled_velocity<T>(g, I.K, v.phiA, v.phiB, v.gx, v.gy, v.gz, v.gp, v.vx, v.vy, v.vz, halt, s);
         });
     }
     // ---- g u stages with g = g(phi^{n+1})
@@ -526,7 +531,7 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     if (I.d.flags & ETD_F_MASS_PROJECT) {
         timed_kernel(PASS_POINT, 5.0 * fb, s, [&] {
             mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);
-            mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, s);
+            mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, halt, s);
         });
     }
     if (!frozen) std::swap(I.phiA, I.phiB);
@@ -557,7 +562,9 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     const long n = g.nreal();
     const double fb = 8.0 * n;
     timed_kernel(PASS_FIXED_POINT, 4.0 * fb, s, [&] { fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, s); });
-    timed_kernel(PASS_REDUCE, fb, s, [&] { reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s); });
+    timed_kernel(PASS_REDUCE, fb, s, [&] {
+        reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s, halt_flag(I));
+    });
     etd_status st = fixed_nonlocal(plan, I, I.q, s);
     if (st != ETD_OK) return st;
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
@@ -605,7 +612,7 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     cheb_apply(I, I.ch1, I.vv, I.acc, s);
     timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
         axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);   // w = w~
-        mul(n, I.isg, I.w, I.U, s);                     // U = w~ / sg  (ETD1 result / predictor)
+        mul(n, I.isg, I.w, I.U, s, halt_flag(I));       // U = w~ / sg  (ETD1 result / predictor)
     });
     if (I.d.scheme == ETD_ETDRK2) {
         if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
@@ -613,14 +620,14 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
         cheb_apply(I, I.ch2, I.vv, I.acc, s);
         timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
             axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
-            mul(n, I.isg, I.w, I.U, s);
+            mul(n, I.isg, I.w, I.U, s, halt_flag(I));
         });
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
         timed_kernel(PASS_FIXED_POINT, 5.0 * fb, s, [&] {
             mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
             mass_project_apply<double>(n, I.G, I.U, I.d.recover_threshold, g.cell, I.scal + S_Q0, I.scal + S_MPS,
-                                       s);
+                                       halt_flag(I), s);
         });
     }
     HIPCHK(plan, hipGetLastError());
@@ -647,6 +654,7 @@ template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, 
     const GridK& g = I.g;
     const long n = g.nreal();
     CoupledView<T> v(I);
+    HIPCHK(plan, hipMemsetAsync(halt_flag(I), 0, sizeof(double), s));   // a new state: steps run again
     load_field<T>(n, a, dt, v.phiA, s);
     load_field<T>(n, u, dt, v.u, s);
     HIPCHK(plan, fft_r2c_3d<T>(g, tables<T>(I), v.phiA, v.Sphi, s));
@@ -665,6 +673,12 @@ template <typename T> etd_status set_state_coupled(etd_plan* plan, Instance& I, 
     I.A0 = I.cp.A0_from_initial ? host[0] : I.cp.A0;
     const double Q0 = host[1] * g.cell;
     HIPCHK(plan, hipMemcpy(I.scal + S_Q0, &Q0, sizeof(double), hipMemcpyHostToDevice));
+    // a NaN or Inf anywhere in phi or u reaches the integral of phi or <g u, 1>
+    // (phi through its transform): such a state is kept, and every step is a no-op
+    if (!std::isfinite(host[0]) || !std::isfinite(host[1])) {
+        const double one = 1.0;
+        HIPCHK(plan, hipMemcpy(halt_flag(I), &one, sizeof(double), hipMemcpyHostToDevice));
+    }
     return ETD_OK;
 }
 
@@ -672,6 +686,7 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
     hipStream_t s = plan->stream;
     const GridK& g = I.g;
     const long n = g.nreal();
+    HIPCHK(plan, hipMemsetAsync(halt_flag(I), 0, sizeof(double), s));   // a new state: steps run again
     load_field<double>(n, a, dt, I.G, s);
     load_field<double>(n, u, dt, I.U, s);
     fixed_prep(g, I.G, I.sg, I.isg, s);
@@ -700,6 +715,10 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
     I.ch2 = cheb_coeffs(phi2_host, I.d.tau, I.a, I.b);
     const double Q0 = host[1] * g.cell;
     HIPCHK(plan, hipMemcpy(I.scal + S_Q0, &Q0, sizeof(double), hipMemcpyHostToDevice));
+    if (!std::isfinite(host[1])) {   // U not finite (g is checked above): keep it, steps are no-ops
+        const double one = 1.0;
+        HIPCHK(plan, hipMemcpy(halt_flag(I), &one, sizeof(double), hipMemcpyHostToDevice));
+    }
     return ETD_OK;
 }
 
@@ -833,8 +852,13 @@ etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dt
         if (a) store_field<double>(n, I.G, dtype, a, s);
         store_field<double>(n, I.U, dtype, u, s);
     }
+    double halt = 0.0;
     HIPCHK(plan, hipGetLastError());
+    HIPCHK(plan, hipMemcpyAsync(&halt, halt_flag(I), sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(plan, hipStreamSynchronize(s));
+    if (halt != 0.0)
+        return fail(&plan->err, ETD_E_NONFINITE,
+                    "non-finite state: the steps since it was detected left the state as it was");
     return ETD_OK;
 }
 
@@ -880,7 +904,7 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
             CoupledView<T> v(I);
             const FFTTables<T>& t = tables<T>(I);
             gloc_field<T>(n, v.phiA, v.gp, s);
-            coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, nullptr, nullptr, s);
+            coupled_q_gu<T>(g, I.K, v.u, v.gp, nullptr, v.P, v.Q, nullptr, nullptr, nullptr, s);
             HIPCHK(plan, fft_r2c_3d<T>(g, t, v.P, v.Sa, s));
             spec_apply<T>(g, SPEC_INV_FD, v.Sa, v.Sa, I.fd, s);
             HIPCHK(plan, fft_c2r_3d<T>(g, t, v.Sa, v.Stmp, v.psi, s));
@@ -925,9 +949,10 @@ etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* out) {
     } else {
         reduce_diag<double>(g, nullptr, I.G, I.U, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
     }
-    double d[7];
+    double d[7], halt = 0.0;
     int64_t bc = 0;
     HIPCHK(plan, hipMemcpyAsync(d, I.scal + S_DIAG, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipMemcpyAsync(&halt, halt_flag(I), sizeof(double), hipMemcpyDeviceToHost, s));
     if (I.d.model == ETD_COUPLED && I.d.band_threshold > 0.0 && I.band_total)
         HIPCHK(plan, hipMemcpyAsync(&bc, I.band_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(plan, hipStreamSynchronize(s));
@@ -939,7 +964,7 @@ etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* out) {
     out->umax = d[4];
     out->bound = d[5];
     out->band_count = bc;
-    out->nonfinite = d[6] > 0.0 ? 1 : 0;
+    out->nonfinite = (d[6] > 0.0 || halt != 0.0) ? 1 : 0;
     out->b_warning = (I.d.model == ETD_FIXED_MEMBRANE && I.FK.B < I.Bmbp) ? 1 : 0;
     if (out->nonfinite) return fail(&plan->err, ETD_E_NONFINITE, "non-finite state");
     return ETD_OK;

@@ -64,6 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_spec_apply(GridK g, int op, const c2
 // One ETD combine (etd_point.h) per half-spectrum entry: p = P[i], q = Q[i].
 template <int ST, typename T>
 __global__ __launch_bounds__(kBlock) void k_etd(GridK g, CoupledK K, const c2<T>* __restrict__ P, const c2<T>* __restrict__ Q, EtdArgs<T> a) {
+    if (halted(a.halt)) return;
     const long n = g.nspec();
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
         const Wave w = wave(g, i, nullptr);
@@ -176,10 +177,12 @@ __global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const T* __restrict__ pn,
                            const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
-                           T* __restrict__ gp, T* __restrict__ vx, T* __restrict__ vy, T* __restrict__ vz) {
+                           T* __restrict__ gp, T* __restrict__ vx, T* __restrict__ vy, T* __restrict__ vz,
+                           const double* halt) {
+    if (halted(halt)) return;
     const long n = g.nreal();
     const T itau = (T)(1.0 / K.tau);
-    const T thr = (T)K.thr;
+    const double thr = K.thr;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock)
         velocity_point(itau, thr, pn[i], po[i], gx[i], gy[i], gz[i], &gp[i], &vx[i], &vy[i], &vz[i]);
 }
@@ -237,17 +240,6 @@ __global__ __launch_bounds__(kBlock) void k_P2_point(GridK g, CoupledK K, const 
     }
 }
 
-// Recovery of U from GU = g+ u_old + d (Section 3.3 after Algorithm 1):
-// U = GU / G = u_old + d / G where G > thr, U = GU elsewhere.  out may alias u_old.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_recover_inc(long n, const T* u_old, const T* __restrict__ d, const T* __restrict__ G, T* out,
-                              T thr) {
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const T Gc = G[i], uo = u_old[i], dd = d[i];
-        out[i] = (Gc > thr) ? uo + dd / Gc : Gc * uo + dd;
-    }
-}
-
 template <typename TI, typename TO> __global__ __launch_bounds__(kBlock) void k_convert(long n, const TI* __restrict__ in, TO* __restrict__ out) {
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) out[i] = (TO)in[i];
 }
@@ -285,27 +277,27 @@ void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, const do
 }
 template <typename T>
 void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* ph, c2<T>* RA,
-                   c2<T>* out, hipStream_t s) {
+                   c2<T>* out, const double* halt, hipStream_t s) {
     hipLaunchKernelGGL((k_etd<ETD_STAGE_PHI1, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q,
-                       EtdArgs<T>{ph, RA, out});
+                       EtdArgs<T>{ph, RA, out, halt});
 }
 template <typename T>
 void spec_etd_phi2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* pt,
-                   const c2<T>* RA, c2<T>* out, hipStream_t s) {
+                   const c2<T>* RA, c2<T>* out, const double* halt, hipStream_t s) {
     hipLaunchKernelGGL((k_etd<ETD_STAGE_PHI2, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, Q,
-                       EtdArgs<T>{pt, const_cast<c2<T>*>(RA), out});
+                       EtdArgs<T>{pt, const_cast<c2<T>*>(RA), out, halt});
 }
 template <typename T>
 void spec_etd_u1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GU0, c2<T>* D, c2<T>* RA,
-                 hipStream_t s) {
+                 const double* halt, hipStream_t s) {
     hipLaunchKernelGGL((k_etd<ETD_STAGE_U1, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GU0,
-                       EtdArgs<T>{nullptr, RA, D});
+                       EtdArgs<T>{nullptr, RA, D, halt});
 }
 template <typename T>
 void spec_etd_u2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GB, c2<T>* D, const c2<T>* RA,
-                 hipStream_t s) {
+                 const double* halt, hipStream_t s) {
     hipLaunchKernelGGL((k_etd<ETD_STAGE_U2, T>), dim3(grid_for(g.nspec())), dim3(kBlock), 0, s, g, K, P, GB,
-                       EtdArgs<T>{nullptr, const_cast<c2<T>*>(RA), D});
+                       EtdArgs<T>{nullptr, const_cast<c2<T>*>(RA), D, halt});
 }
 template <typename T>
 void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
@@ -317,16 +309,16 @@ void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* 
 }
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* po, const T* pn, const T* gx, const T* gy,
-                      const T* gz, T* gp, T* vx, T* vy, T* vz, hipStream_t s) {
+                      const T* gz, T* gp, T* vx, T* vy, T* vz, const double* halt, hipStream_t s) {
     hipLaunchKernelGGL(k_velocity<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, po, pn, gx, gy, gz, gp, vx,
-                       vy, vz);
+                       vy, vz, halt);
 }
 template <typename T>
 void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* G, const uint8_t* mask, T* q, T* gu,
-                  double* part, double* mass_out, hipStream_t s) {
+                  double* part, double* mass_out, double* halt, hipStream_t s) {
     const int nb = grid_for(g.nreal());
     hipLaunchKernelGGL(k_q_gu<T>, dim3(nb), dim3(kBlock), 0, s, g.nreal(), (T)K.ubar, u, G, mask, q, gu, part);
-    if (part) reduce_final_sum(part, nb, g.cell, mass_out, s);
+    if (part) reduce_final_sum(part, nb, g.cell, mass_out, s, halt);
 }
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
@@ -334,10 +326,6 @@ void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* G,
     const TileGrid tg = tiles_for(g.nreal() / 4);   // one thread per quad of z points
     hipLaunchKernelGGL(k_P2_point<T>, dim3(tg.blocks), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, psi, m, mask, P,
                        tg.tpb);
-}
-template <typename T>
-void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s) {
-    hipLaunchKernelGGL(k_recover_inc<T>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, u_old, d, G, out, (T)thr);
 }
 template <typename TI, typename TO> void convert(long n, const TI* in, TO* out, hipStream_t s) {
     hipLaunchKernelGGL((k_convert<TI, TO>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out);
@@ -354,23 +342,22 @@ void set_delta(long n, double* x, hipStream_t s) {
     template void gloc_field<T>(long, const T*, T*, hipStream_t);                                                 \
     template void spec_apply<T>(const GridK&, SpecOp, const c2<T>*, c2<T>*, const double*, hipStream_t);         \
     template void spec_etd_phi1<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \
-                                   c2<T>*, c2<T>*, hipStream_t);                                                  \
+                                   c2<T>*, c2<T>*, const double*, hipStream_t);                                   \
     template void spec_etd_phi2<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, const c2<T>*,       \
-                                   const c2<T>*, c2<T>*, hipStream_t);                                            \
+                                   const c2<T>*, c2<T>*, const double*, hipStream_t);                             \
     template void spec_etd_u1<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, c2<T>*, c2<T>*,       \
-                                 hipStream_t);                                                                    \
+                                 const double*, hipStream_t);                                                     \
     template void spec_etd_u2<T>(const GridK&, const CoupledK&, const c2<T>*, const c2<T>*, c2<T>*,               \
-                                 const c2<T>*, hipStream_t);                                                      \
+                                 const c2<T>*, const double*, hipStream_t);                                       \
     template void coupled_R1_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
                                       const T*, const T*, const uint8_t*, const double*, double, T*, T*,          \
                                       hipStream_t);                                                               \
     template void coupled_velocity<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
-                                      const T*, T*, T*, T*, T*, hipStream_t);                                     \
+                                      const T*, T*, T*, T*, T*, const double*, hipStream_t);                      \
     template void coupled_q_gu<T>(const GridK&, const CoupledK&, const T*, const T*, const uint8_t*, T*, T*,      \
-                                  double*, double*, hipStream_t);                                                 \
+                                  double*, double*, double*, hipStream_t);                                        \
     template void coupled_P2_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
-                                      const T*, const T*, const double*, const uint8_t*, T*, hipStream_t);        \
-    template void recover_increment<T>(long, const T*, const T*, const T*, T*, double, hipStream_t);
+                                      const T*, const T*, const double*, const uint8_t*, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -1,9 +1,8 @@
 // Pointwise ETD combines of the coupled scheme in Fourier space (Section 3.3,
 // Algorithm 1), shared by the standalone spectral kernels and the epilogue of
-// the fused forward x pass.  The arguments z = tau l(k^2) are formed in FP64;
-// the phi-function values in FP64 on the FP64 path and in FP32 on the FP32
-// path (a few ulp of FP32 against FP64-formed and rounded values; the FP64
-// transcendentals cost a large share of the fused x pass).
+// the fused forward x pass.  The arguments z = tau l(k^2) and the
+// phi-function values are formed in FP64 on both paths (a series branch for
+// small z); the FP32 path rounds the finished multipliers to FP32.
 #pragma once
 
 #include "kernels.h"
@@ -28,29 +27,6 @@ __device__ __forceinline__ double phi2d(double z) {
     return fabs(z) < 0.1 ? phi_taylor(z, 2) : (expm1(-z) + z) / (z * z);
 }
 
-// FP32 forms for the FP32 path: the argument z = tau l(k^2) is formed in FP64
-// and rounded, the exponential parts in FP32 (series with compile-time
-// coefficients 1/(j+k)! for |z| < 0.1, 7 terms, truncation < 3e-12); the
-// quotients of the closed forms by the hardware reciprocal (1 ulp) and a
-// multiply.
-template <int K>
-__device__ __forceinline__ float phi_taylor_f(float z) {
-    constexpr double f0 = (K == 1) ? 1.0 : 0.5;   // 1 / k!
-    constexpr float c0 = (float)f0, c1 = (float)(f0 / (K + 1)), c2 = (float)(f0 / ((K + 1) * (K + 2))),
-                    c3 = (float)(f0 / ((K + 1) * (K + 2) * (K + 3))),
-                    c4 = (float)(f0 / ((K + 1) * (K + 2) * (K + 3) * (K + 4))),
-                    c5 = (float)(f0 / ((K + 1) * (K + 2) * (K + 3) * (K + 4) * (K + 5))),
-                    c6 = (float)(f0 / ((K + 1) * (K + 2) * (K + 3) * (K + 4) * (K + 5) * (K + 6)));
-    const float y = -z;
-    return c0 + y * (c1 + y * (c2 + y * (c3 + y * (c4 + y * (c5 + y * c6)))));
-}
-__device__ __forceinline__ float phi1f(float z) {
-    return fabsf(z) < 0.1f ? phi_taylor_f<1>(z) : -expm1f(-z) * __builtin_amdgcn_rcpf(z);
-}
-__device__ __forceinline__ float phi2f(float z) {
-    return fabsf(z) < 0.1f ? phi_taylor_f<2>(z) : (expm1f(-z) + z) * __builtin_amdgcn_rcpf(z * z);
-}
-
 // linear symbols (eqn:linear_force and the u equation)
 __device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K.lp4 * k2 + K.lp2) * k2 + K.lp0; }
 __device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
@@ -64,6 +40,7 @@ template <typename T> struct EtdArgs {
     const c2<T>* prev;   // PHI1: phi^n hat;  PHI2: phi~ hat
     c2<T>* ra;           // stage-1 remainder R(.)^ (written by *1, read by *2)
     c2<T>* out;          // PHI*: new phi hat;  U*: increment D (U2 reads and updates it)
+    const double* halt = nullptr;   // the instance's halt flag: the combine is skipped once it is set
 };
 
 // Returns the stage's output value at i (PHI*: the new phi hat, U*: the
@@ -75,15 +52,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     if constexpr (ST == ETD_STAGE_PHI1) {
         // R = P - c1 k^2 Q;  phi~ = e^{-tau l} phi^n + tau phi1(tau l) R
         const double z = K.tau * lphi(K, k2);
-        T e0, te1;
-        if constexpr (sizeof(T) == 4) {
-            const float zf = (float)z;
-            e0 = expf(-zf);
-            te1 = (float)K.tau * phi1f(zf);
-        } else {
-            e0 = exp(-z);
-            te1 = K.tau * phi1d(z);
-        }
+        const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z));
         const T ck = (T)(K.c1 * k2);
         const c2<T> f = a.prev[i];
         const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
@@ -92,9 +61,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     } else if constexpr (ST == ETD_STAGE_PHI2) {
         // phi^{n+1} = phi~ + tau phi2(tau l) (R~ - R)
         const double z = K.tau * lphi(K, k2);
-        T te2;
-        if constexpr (sizeof(T) == 4) te2 = (float)K.tau * phi2f((float)z);
-        else te2 = K.tau * phi2d(z);
+        const T te2 = (T)(K.tau * phi2d(z));
         const T ck = (T)(K.c1 * k2);
         const c2<T> t = a.prev[i], ra = a.ra[i];
         const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
@@ -103,9 +70,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
         // R = P + eps_u B1 k^2 GU;  D = tau phi1(tau l_u) (R - l_u GU)  (GU~ - GU^n)
         const double l = lu(K, k2);
         const double z = K.tau * l;
-        T te1;
-        if constexpr (sizeof(T) == 4) te1 = (float)K.tau * phi1f((float)z);
-        else te1 = K.tau * phi1d(z);
+        const T te1 = (T)(K.tau * phi1d(z));
         const T ck = (T)(K.eps_u * K.B1 * k2), lt = (T)l;
         const c2<T> R = mk<T>(p.x + ck * q.x, p.y + ck * q.y);
         a.ra[i] = R;
@@ -113,9 +78,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     } else {
         // D <- D + tau phi2(tau l_u) (R~ - R)
         const double z = K.tau * lu(K, k2);
-        T te2;
-        if constexpr (sizeof(T) == 4) te2 = (float)K.tau * phi2f((float)z);
-        else te2 = K.tau * phi2d(z);
+        const T te2 = (T)(K.tau * phi2d(z));
         const T ck = (T)(K.eps_u * K.B1 * k2);
         const c2<T> d = a.out[i], ra = a.ra[i];
         const T dx = (p.x + ck * q.x) - ra.x, dy = (p.y + ck * q.y) - ra.y;

@@ -107,7 +107,9 @@ __global__ __launch_bounds__(kB) void k_axpby(long n, double a, const double* x,
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) out[i] = a * x[i] + b * y[i];
 }
 
-__global__ __launch_bounds__(kB) void k_mul(long n, const double* x, const double* y, double* out) {
+__global__ __launch_bounds__(kB) void k_mul(long n, const double* x, const double* y, double* out,
+                                          const double* halt) {
+    if (halted(halt)) return;
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) out[i] = x[i] * y[i];
 }
 
@@ -142,8 +144,8 @@ void fixed_L_apply(const GridK& g, const FixedK& K, const double* G, const doubl
 void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kB), 0, s, n, a, x, b, y, out);
 }
-void mul(long n, const double* x, const double* y, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(kB), 0, s, n, x, y, out);
+void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt) {
+    hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(kB), 0, s, n, x, y, out, halt);
 }
 
 }  // namespace etd

@@ -97,13 +97,14 @@ hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* f
 // U from an increment spectrum D of G U (Section 3.3 after Algorithm 1):
 // d = F^-1 D, out = u_old + d / G where G > thr, G u_old + d elsewhere; the
 // recovery runs in the store of the z c2r pass.  W: complex work array (D is
-// preserved); out may alias u_old.
+// preserved); out may alias u_old.  Once *halt != 0 (halt nullable) the pass
+// writes out = u_old instead.
 template <typename T>
 hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
-                       T* out, double thr, hipStream_t s);
+                       T* out, double thr, const double* halt, hipStream_t s);
 // The y and z passes of c2r_recover for W = X^-1 D (W is overwritten).
 template <typename T>
 hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const T* u_old, const T* G, T* out,
-                          double thr, hipStream_t s);
+                          double thr, const double* halt, hipStream_t s);
 
 }  // namespace etd

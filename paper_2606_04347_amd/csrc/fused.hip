@@ -206,6 +206,9 @@ template <typename T> struct DerivZArgs {
     T* phi;
     T* gn;
     T* lap;
+    const double* halt;   // nullable: once set, the pass writes nothing, except that
+                          // with the velocity it copies phi^n into phi (the buffer
+                          // that becomes the state)
 };
 
 // Keeps, slot by slot in registers (lines.h, IndexedOf), either the gradient
@@ -248,7 +251,8 @@ template <typename T, int M, int K, bool VEL> struct GradNormStore {
     c2<T>* vy;
     c2<T>* vz;
     int nl;
-    T scale, itau, thr;
+    T scale, itau;
+    double thr;   // support threshold, compared in FP64
     __device__ __forceinline__ void load(int, int, c2<T>*) const {}
     __device__ __forceinline__ void store_at(int slot, int l, int e, c2<T> v) const {
         if (l >= nl) return;
@@ -278,6 +282,13 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityA
     constexpr int MS = NR / 2 + 1;
     constexpr int M = NR / 2;
     constexpr int K = z_out_slots<T, NR>();
+    if (halted(z.halt)) {
+        if constexpr (VEL) {
+            const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
+            for (long i = r0 + threadIdx.x; i < r1; i += kThreads) z.phi[i] = va.po[i];
+        }
+        return;
+    }
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -311,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityA
         GradNormStore<T, M, K, VEL>{kz, kz, kx, pw(z.gn), pr(z.phi), VEL ? pr(va.po) : nullptr,
                                     VEL ? pw(va.G) : nullptr, VEL ? pw(va.vx) : nullptr, VEL ? pw(va.vy) : nullptr,
                                     VEL ? pw(va.vz) : nullptr, nl, scale, (T)(VEL ? 1.0 / va.tau : 0.0),
-                                    (T)va.thr});
+                                    va.thr});
     __syncthreads();
     zrow_put<T, NR, false>(lds, pre, az);
     zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, M>{pw(z.lap), nl, scale});
@@ -333,7 +344,8 @@ template <typename T, int M> struct RecoverStore {
     const c2<T>* G;
     c2<T>* out;
     int nl;
-    T scale, thr;
+    T scale;
+    double thr;   // the recovery threshold, compared in FP64 on both paths
     __device__ __forceinline__ void load(int, int, c2<T>*) const {}
     __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
         if (l >= nl) return;
@@ -341,8 +353,8 @@ template <typename T, int M> struct RecoverStore {
         const c2<T> u = uo[i], g = G[i];
         const T d0 = v.x * scale, d1 = v.y * scale;
         c2<T> r;
-        r.x = (g.x > thr) ? u.x + d0 / g.x : g.x * u.x + d0;
-        r.y = (g.y > thr) ? u.y + d1 / g.y : g.y * u.y + d1;
+        r.x = ((double)g.x > thr) ? u.x + d0 / g.x : g.x * u.x + d0;
+        r.y = ((double)g.y > thr) ? u.y + d1 / g.y : g.y * u.y + d1;
         out[i] = r;
     }
 };
@@ -351,9 +363,16 @@ template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_c2r_recover(const c2<T>* D, const T* uo, const T* G, T* out,
                                                             const c2<T>* __restrict__ twh,
                                                             const c2<T>* __restrict__ twf, long nrows, T scale,
-                                                            T thr) {
+                                                            double thr, const double* halt) {
     constexpr int L = z_rows<T, NR>();
     constexpr int M = NR / 2;
+    if (halted(halt)) {   // U keeps its value: out = u_old
+        if (out != uo) {
+            const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
+            for (long i = r0 + threadIdx.x; i < r1; i += kThreads) out[i] = uo[i];
+        }
+        return;
+    }
     extern __shared__ unsigned char smem_raw[];
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + L * z_row_stride<NR>();
@@ -694,6 +713,7 @@ template <int ST, typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
                                                     EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
                                                     const c2<T>* __restrict__ tw) {
+    if (halted(a.halt)) return;   // the state spectrum keeps its value
     constexpr int L = xline_tile<T, N>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
@@ -820,12 +840,12 @@ template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const De
     else
         launch_deriv_z_k<T, NR, false>(nb, smem, z, VelocityArgs<T>{}, twh, twf, nrows, scale, kPi / g.X[2], part,
                                        s);
-    if (isum) reduce_final_sum(isum->part, nb, isum->scale, isum->out, s);
+    if (isum) reduce_final_sum(isum->part, nb, isum->scale, isum->out, s, isum->halt);
     return hipGetLastError();
 }
 template <typename T, int NR>
 hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T* G, T* out, double thr,
-                            const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+                            const double* halt, const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
     static std::once_flag flag;
@@ -833,7 +853,7 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     hipLaunchKernelGGL((k_z_c2r_recover<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, D, uo, G,
-                       out, twh, twf, nrows, scale, (T)thr);
+                       out, twh, twf, nrows, scale, thr, halt);
     return hipGetLastError();
 }
 template <typename T, int NR>
@@ -847,7 +867,7 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
     const int nb = (int)((nrows + L - 1) / L);
     hipLaunchKernelGGL((k_z_r2c_q<T, NR>), dim3(nb), dim3(kThreads), smem, s, u, G, mask, ubar, W, twh, twf, nrows,
                        msum.part);
-    reduce_final_sum(msum.part, nb, msum.scale, msum.out, s);
+    reduce_final_sum(msum.part, nb, msum.scale, msum.out, s, msum.halt);
     return hipGetLastError();
 }
 
@@ -952,7 +972,7 @@ hipError_t derivs_fused_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W0, c2<
         }
     });
     if (e != hipSuccess) return e;
-    const DerivZArgs<T> z{W0, W1, W2, W3, phi, gn, lap};
+    const DerivZArgs<T> z{W0, W1, W2, W3, phi, gn, lap, isum ? isum->halt : nullptr};
     // phi, |grad phi| and lap written; with the velocity also phi^n read and
     // g+ and v written (the read-back of phi is served by the cache)
     return timed_pass(PASS_Z_DERIV, 4.0 * cb + (vel ? 8.0 : 3.0) * rb, s, [&]() -> hipError_t {
@@ -1160,7 +1180,7 @@ hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* f
 
 template <typename T>
 hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const T* u_old, const T* G, T* out,
-                          double thr, hipStream_t s) {
+                          double thr, const double* halt, hipStream_t s) {
     hipError_t e = fft_pass_y<T>(g, t, +1, W, W, s);
     if (e != hipSuccess) return e;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
@@ -1168,7 +1188,7 @@ hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const
     return timed_pass(PASS_Z_RECOVER, cb + 3.0 * rb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, t.tzh, t.tzf, s);
+    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, halt, t.tzh, t.tzf, s);
             ETD_FFT_SIZES(CASE)
 #undef CASE
             default: return hipErrorInvalidValue;
@@ -1178,7 +1198,7 @@ hipError_t c2r_recover_yz(const GridK& g, const FFTTables<T>& t, c2<T>* W, const
 
 template <typename T>
 hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2<T>* W, const T* u_old, const T* G,
-                       T* out, double thr, hipStream_t s) {
+                       T* out, double thr, const double* halt, hipStream_t s) {
     const c2<T>* cur = D;
     hipError_t e = hipSuccess;
     if (g.nx > 1) {
@@ -1191,14 +1211,14 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
         return timed_pass(PASS_Z_RECOVER, cb + 3.0 * rb, s, [&]() -> hipError_t {
             switch (g.nz) {
 #define CASE(n) \
-    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, t.tzh, t.tzf, s);
+    case n: return launch_z_recover<T, n>(g, W, u_old, G, out, thr, halt, t.tzh, t.tzf, s);
                 ETD_FFT_SIZES(CASE)
 #undef CASE
                 default: return hipErrorInvalidValue;
             }
         });
     }
-    return c2r_recover_yz<T>(g, t, W, u_old, G, out, thr, s);
+    return c2r_recover_yz<T>(g, t, W, u_old, G, out, thr, halt, s);
 }
 
 #define INST(T)                                                                                                   \
@@ -1208,7 +1228,7 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
     template hipError_t p2_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const P2Fields<T>&,         \
                                   EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, hipStream_t);        \
     template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
-                                       const T*, T*, double, hipStream_t);                                        \
+                                       const T*, T*, double, const double*, hipStream_t);                         \
     template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
                                         c2<T>*, T*, T*, T*, const GridSum*, hipStream_t);                         \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
@@ -1218,7 +1238,7 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
                                            T*, T*, const GridSum*, hipStream_t,                                   \
                                            const VelocityArgs<T>*);                                               \
     template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
-                                          double, hipStream_t);                                                   \
+                                          double, const double*, hipStream_t);                                    \
     template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
                                         hipStream_t);                                                             \
     template hipError_t lapinv_q_fused<T>(const GridK&, const FFTTables<T>&, const double*, double, const T*,     \

@@ -21,7 +21,14 @@ struct GridSum {
     double* part;
     double* out;
     double scale;
+    double* halt = nullptr;   // set to 1 when the total is not finite (nullable)
 };
+
+// Kernels that write a step's state take the instance's halt flag (a device
+// scalar, nullable): once it is non-zero they leave the state as it is, so
+// the steps after a non-finite value was detected are no-ops, also inside a
+// captured graph.
+__device__ __forceinline__ bool halted(const double* halt) { return halt && *halt != 0.0; }
 
 // ------------------------------------------------------------------ spectral
 enum SpecOp { SPEC_NEG_K2 = 0, SPEC_IKX = 1, SPEC_IKY = 2, SPEC_IKZ = 3, SPEC_INV_FD = 4 };
@@ -32,21 +39,22 @@ template <typename T>
 void spec_apply(const GridK& g, SpecOp op, const c2<T>* in, c2<T>* out, const double* fd, hipStream_t s);
 
 // phi stage 1: R = P - c1 k^2 Q  -> RA;  out = E0 phi_hat + tau E1 R.
+// Each combine is a no-op once *halt != 0 (nullable).
 template <typename T>
 void spec_etd_phi1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* phi_hat,
-                   c2<T>* RA, c2<T>* out, hipStream_t s);
+                   c2<T>* RA, c2<T>* out, const double* halt, hipStream_t s);
 // phi stage 2: out = phit + tau E2 ((P - c1 k^2 Q) - RA).
 template <typename T>
 void spec_etd_phi2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const c2<T>* phit,
-                   const c2<T>* RA, c2<T>* out, hipStream_t s);
+                   const c2<T>* RA, c2<T>* out, const double* halt, hipStream_t s);
 // u stage 1: RA = P + eps_u B1 k^2 GU0;  D = GU~^ - GU0 = tau phi1(tau l_u) (RA - l_u GU0).
 template <typename T>
 void spec_etd_u1(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GU0, c2<T>* D, c2<T>* RA,
-                 hipStream_t s);
+                 const double* halt, hipStream_t s);
 // u stage 2: D <- D + tau E2u ((P + eps_u B1 k^2 GB) - RA).
 template <typename T>
 void spec_etd_u2(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* GB, c2<T>* D,
-                 const c2<T>* RA, hipStream_t s);
+                 const c2<T>* RA, const double* halt, hipStream_t s);
 
 // ------------------------------------------------------------------ real space, coupled
 template <typename T>
@@ -55,28 +63,28 @@ void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* 
                       T* Q, hipStream_t s);
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* phi_old, const T* phi_new, const T* gx,
-                      const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, hipStream_t s);
+                      const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, const double* halt, hipStream_t s);
 // q = g+ (u - ubar) (masked), gu = g+ u (gu may be null); with part != null also the mass
 // mass_out[0] = cell * sum q (block partials in part, then a fixed-order final
-// sum; part holds at least kRedBlocks * 4 doubles).
+// sum; part holds at least kRedBlocks * 4 doubles); a mass that is not finite
+// sets *halt (nullable).
 template <typename T>
 void coupled_q_gu(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const uint8_t* mask, T* q,
-                  T* gu, double* part, double* mass_out, hipStream_t s);
+                  T* gu, double* part, double* mass_out, double* halt, hipStream_t s);
 template <typename T>
 void coupled_P2_point(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const T* vx, const T* vy,
                       const T* vz, const T* psi, const double* m, const uint8_t* mask, T* P, hipStream_t s);
-// out = u_old + d / G where G > thr, G u_old + d elsewhere (out may alias u_old)
-template <typename T>
-void recover_increment(long n, const T* u_old, const T* d, const T* G, T* out, double thr, hipStream_t s);
 
 // ------------------------------------------------------------------ reductions (FP64, deterministic)
 constexpr int kRedBlocks = 2048;
 
-// out[0] = scale * sum of part[0..nb) (Neumaier-compensated, fixed order).
-void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s);
+// out[0] = scale * sum of part[0..nb) (Neumaier-compensated, fixed order); a
+// total that is not finite sets *halt to 1 (halt nullable).
+void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s, double* halt = nullptr);
 
 // out[0] = scale * sum_i x_i  (Neumaier-compensated, fixed order).  part: kRedBlocks doubles.
-template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s);
+template <typename T>
+void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s, double* halt = nullptr);
 
 // Diagnostics of a state: out = [h^d sum phi, h^d sum g (u - ubar), h^d sum g u, min u, max u,
 // max |2u - 1|, nonfinite count].  phi may be null (then g is taken from gfix, the fixed membrane).
@@ -128,7 +136,8 @@ void fixed_L_apply(const GridK& g, const FixedK& K, const double* gg, const doub
                    double* out, hipStream_t s);
 // elementwise helpers
 void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
-void mul(long n, const double* x, const double* y, double* out, hipStream_t s);
+// out = x * y; a no-op once *halt != 0 (halt nullable)
+void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt = nullptr);
 // Fixed energy sums: out = [sum g_half (D+U)^2 (edges), sum g W(U), sum psi q, sum g (f(U) - ubar)] (unscaled)
 void reduce_energy_fixed(const GridK& g, const FixedK& K, const double* gg, const double* U, const double* psi,
                          const double* q, double* part, double* out, hipStream_t s);
@@ -137,7 +146,7 @@ template <typename T>
 void mass_project_sums(long n, const T* G, const T* U, double thr, double* part, double* out, hipStream_t s);
 template <typename T>
 void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const double* Q0,
-                        const double* sums, hipStream_t s);
+                        const double* sums, const double* halt, hipStream_t s);
 
 // ------------------------------------------------------------------ narrow band
 // flags[i] = |2 phi_i - 1| < thr (FP64); counts per block, exclusive scan, stable scatter.

@@ -23,7 +23,8 @@ etd_status fail(std::string* sink, etd_status st, const std::string& msg);
 // device scalar slots
 enum Slot {
     S_INTPHI = 0, S_MASS = 1, S_Q0 = 2, S_MPS = 3 /* 2 values */, S_TMP = 5,
-    S_DIAG = 8 /* 7 */, S_ENERGY = 16 /* 7 */, S_GERSH = 24, S_ABS = 25, S_COUNT = 32
+    S_DIAG = 8 /* 7 */, S_ENERGY = 16 /* 7 */, S_GERSH = 24, S_ABS = 25,
+    S_HALT = 26 /* 1 once a non-finite value was seen: later steps are no-ops */, S_COUNT = 32
 };
 
 struct Instance {

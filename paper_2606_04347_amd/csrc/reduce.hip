@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kB) void k_reduce(F f, long n, double* part) {
 }
 
 template <int NS, int NM>
-__global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb, double* out, double scale) {
+__global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb, double* out, double scale,
+                                                   double* halt) {
     __shared__ double sh[4];
     for (int j = 0; j < NS + NM; ++j) {
         Neu acc;
@@ -67,14 +68,18 @@ __global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb,
             else mx = fmax(mx, v);
         }
         const double r = (j < NS) ? block_sum_256(acc.val(), sh) : block_max_256(mx, sh);
-        if (threadIdx.x == 0) out[j] = (j < NS) ? scale * r : r;
+        if (threadIdx.x == 0) {
+            out[j] = (j < NS) ? scale * r : r;
+            if (halt && j < NS && !isfinite(r)) *halt = 1.0;
+        }
     }
 }
 
 template <int NS, int NM, class F>
-void run_reduce(const F& f, long n, double scale, double* part, double* out, hipStream_t s) {
+void run_reduce(const F& f, long n, double scale, double* part, double* out, hipStream_t s,
+                double* halt = nullptr) {
     hipLaunchKernelGGL((k_reduce<NS, NM, F>), dim3(kRedBlocks), dim3(kB), 0, s, f, n, part);
-    hipLaunchKernelGGL((k_reduce_final<NS, NM>), dim3(1), dim3(kB), 0, s, part, kRedBlocks, out, scale);
+    hipLaunchKernelGGL((k_reduce_final<NS, NM>), dim3(1), dim3(kB), 0, s, part, kRedBlocks, out, scale, halt);
 }
 
 struct AbsSumF {
@@ -204,7 +209,8 @@ template <typename T> struct MassF {
 
 template <typename T>
 __global__ __launch_bounds__(kB) void k_mass_apply(long n, const T* __restrict__ G, T* U, double thr, double cell, const double* Q0,
-                             const double* sums) {
+                             const double* sums, const double* halt) {
+    if (halted(halt)) return;
     const double den = cell * sums[1];
     const double c = den > 0.0 ? (Q0[0] - cell * sums[0]) / den : 0.0;
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
@@ -248,12 +254,13 @@ struct GershF {
 
 }  // namespace
 
-void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_reduce_final<1, 0>), dim3(1), dim3(kB), 0, s, part, nb, out, scale);
+void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s, double* halt) {
+    hipLaunchKernelGGL((k_reduce_final<1, 0>), dim3(1), dim3(kB), 0, s, part, nb, out, scale, halt);
 }
 
-template <typename T> void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s) {
-    run_reduce<1, 0>(SumF<T>{x}, n, scale, part, out, s);
+template <typename T>
+void reduce_sum(long n, const T* x, double scale, double* part, double* out, hipStream_t s, double* halt) {
+    run_reduce<1, 0>(SumF<T>{x}, n, scale, part, out, s, halt);
 }
 
 void reduce_abs_sum(long n, const double* x, double* part, double* out, hipStream_t s) {
@@ -291,14 +298,14 @@ void mass_project_sums(long n, const T* G, const T* U, double thr, double* part,
 
 template <typename T>
 void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const double* Q0, const double* sums,
-                        hipStream_t s) {
+                        const double* halt, hipStream_t s) {
     long b = (n + kB - 1) / kB;
     if (b > 8192) b = 8192;
-    hipLaunchKernelGGL(k_mass_apply<T>, dim3((int)b), dim3(kB), 0, s, n, G, U, thr, cell, Q0, sums);
+    hipLaunchKernelGGL(k_mass_apply<T>, dim3((int)b), dim3(kB), 0, s, n, G, U, thr, cell, Q0, sums, halt);
 }
 
 #define INST(T)                                                                                                 \
-    template void reduce_sum<T>(long, const T*, double, double*, double*, hipStream_t);                        \
+    template void reduce_sum<T>(long, const T*, double, double*, double*, hipStream_t, double*);               \
     template void reduce_diag<T>(const GridK&, const T*, const double*, const T*, double, bool, double*,        \
                                  double*, hipStream_t);                                                         \
     template void reduce_energy_coupled<T>(const GridK&, const CoupledK&, const T*, const T*, const T*,         \
@@ -306,7 +313,7 @@ void mass_project_apply(long n, const T* G, T* U, double thr, double cell, const
                                            hipStream_t);                                                        \
     template void mass_project_sums<T>(long, const T*, const T*, double, double*, double*, hipStream_t);       \
     template void mass_project_apply<T>(long, const T*, T*, double, double, const double*, const double*,      \
-                                        hipStream_t);
+                                        const double*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

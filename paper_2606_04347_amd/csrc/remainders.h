@@ -106,10 +106,10 @@ __device__ __forceinline__ T p2_point(const P2Const<T>& k, T uc, T Gc, T ps, con
 // (phi_t = (phi^{n+1} - phi^n) / tau) on {g+ > thr, |grad phi| > 0}, 0
 // elsewhere (Section 3.1, the advection velocity of the u equation).
 template <typename T>
-__device__ __forceinline__ void velocity_point(T itau, T thr, T p, T po, T a, T b, T c, T* G, T* vx, T* vy, T* vz) {
+__device__ __forceinline__ void velocity_point(T itau, double thr, T p, T po, T a, T b, T c, T* G, T* vx, T* vy, T* vz) {
     const T g = gloc(p);
     const T gn2 = a * a + b * b + c * c;
-    const bool sel = (g > thr) && (gn2 > (T)0);
+    const bool sel = ((double)g > thr) && (gn2 > (T)0);   // threshold decided in FP64
     const T dt = (p - po) * itau;
     *G = g;
     *vx = sel ? (-dt * a) / gn2 : (T)0;

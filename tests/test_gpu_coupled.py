@@ -3,7 +3,7 @@ ABI against the FP64 oracle on the same seeded inputs."""
 import numpy as np
 import pytest
 
-from gpu_util import dev, host, needs_gpu, rel_linf, report, torch
+from gpu_util import dev, host, needs_gpu, recovery_flips, rel_linf, report, torch, u_gap_outside_flips
 from oracle import band as oband
 from oracle.core import Grid
 from oracle.coupled import CoupledOracle
@@ -61,24 +61,90 @@ def test_fp64_step_matches_oracle(shape, nsteps, scheme):
 @pytest.mark.parametrize("shape,nsteps", [((32, 32, 32), 20), ((96, 64, 192), 3), ((8, 512, 8), 3),
                                           ((512, 8, 12), 1)])
 def test_fp32_step_close_to_oracle(scheme, shape, nsteps):
-    """FP32 path against the FP64 oracle.  The recovery U = GU / G divides by
-    a G that is tiny away from the membrane, where rounding of GU is
-    amplified, so u is compared on {g > 1e-2} (g from the oracle's phi);
-    phi everywhere.  The 512 x 8 x 12 grid (dx = 2 pi / 512 beside
-    dy = 2 pi / 8) is unstable at tau = 1e-4 even in exact arithmetic (the
-    oracle's u grows thirtyfold a step and overflows by step 3), so it runs
-    one step only."""
+    """FP32 path against the FP64 oracle, step by step.  phi within 1e-4
+    (relative L-inf) everywhere; u within 1e-4 everywhere except at the
+    points where the two paths' G fell on opposite sides of the recovery
+    threshold in some step (counted, at most 1e-4 of the grid) and their
+    two-cell neighbourhood; g u within 1e-4 everywhere -- or, where rounding
+    the state to FP32 alone moves the oracle's u further (rounding_floor:
+    the 8 x 512 x 8 grid), within twice that.  The 512 x 8 x 12
+    grid (dx = 2 pi / 512 beside dy = 2 pi / 8) is unstable at tau = 1e-4
+    even in exact arithmetic (the oracle's u grows thirtyfold a step and
+    overflows by step 3), so it runs one step only."""
     ci = make_case(shape)
-    o, plan, phi, u = run_pair(ci, scheme, etd.FP32, nsteps)
+    grid = Grid(ci.shape, ci.half_len)
+    o = CoupledOracle(grid, ci.params, ci.tau, scheme)
+    o.set_state(ci.phi0, ci.u0)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=scheme, precision=etd.FP32))
+    plan.set_state(0, dev(ci.phi0, torch.float32), dev(ci.u0, torch.float32))
+    flips = np.zeros(ci.shape, dtype=bool)
+    for _ in range(nsteps):
+        o.step()
+        plan.step(1)
+        phi = host(plan.get_state(0, torch.float32)[0])
+        flips |= recovery_flips(phi, o.phi())
+    phi, u = (host(t) for t in plan.get_state(0))
     po = o.phi()
-    sel = 18.0 * (po * po - po) ** 2 > 1e-2
     ephi = rel_linf(phi, po)
-    eu_sel = float(np.abs(u - o.u)[sel].max() / np.abs(o.u).max())
-    report("coupled_fp32", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi,
-           err_u_g_gt_1e_2=eu_sel, err_u_all=rel_linf(u, o.u))
+    eu, near, egu, eall = u_gap_outside_flips(u, o.u, po, flips)
+    tol = 1e-4
+    if eu > tol or egu > tol:
+        tol = max(tol, 2.0 * rounding_floor(ci, scheme, nsteps))
+    report("coupled_fp32", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi, err_u=eu,
+           flips=int(flips.sum()), near=near, err_gu=egu, err_u_all=eall, tol_u=tol)
     assert np.isfinite(phi).all() and np.isfinite(u).all()
-    assert ephi <= 1e-4 and eu_sel <= 1e-4
+    assert ephi <= 1e-4 and eu <= tol and egu <= tol
+    assert flips.sum() <= max(1, 1e-4 * flips.size)
     plan.close()
+
+
+def rounding_floor(ci, scheme, nsteps):
+    """What rounding the state alone does to the oracle's u: the relative
+    L-inf change of u (and of g u) when the velocity v = -phi_t grad phi /
+    |grad phi|^2 (defined with eqn:model_OK) is formed from phi^n and
+    phi^{n+1} rounded to FP32.  phi_t is a difference quotient of two states
+    tau apart, so a rounding of 6e-8 becomes 6e-4 in phi_t, and where |grad
+    phi| is small v carries it further.  On grids whose cells are far from
+    cubic (8 x 512 x 8: the membrane spans a fraction of an x or z cell) this
+    alone moves u by more than 1e-4 within three steps; no FP32 state can do
+    better there."""
+    from oracle import core
+    grid = Grid(ci.shape, ci.half_len)
+    ref = CoupledOracle(grid, ci.params, ci.tau, scheme)
+    per = CoupledOracle(grid, ci.params, ci.tau, scheme)
+    ref.set_state(ci.phi0, ci.u0)
+    per.set_state(ci.phi0, ci.u0)
+    vel = per.velocity
+
+    def vel32(phi_old, phi_new_hat, g_new):
+        r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+        return vel(r32(phi_old), core.fft(r32(core.ifft(phi_new_hat))), g_new)
+
+    per.velocity = vel32
+    ref.run(nsteps)
+    per.run(nsteps)
+    d = np.abs(per.u - ref.u)
+    g = core.g_loc(ref.phi())
+    return max(float(d.max() / np.abs(ref.u).max()), float((g * d).max() / np.abs(g * ref.u).max()))
+
+
+def test_fp64_step_matches_naive_dft_oracle():
+    """The oracle with its own exact-index DFT (no library transform anywhere
+    in the reference): ETDRK2 on a 24 x 16 x 32 grid (radix-3 length) and
+    ETD1 at 16^3, FP64 within 1e-12."""
+    from oracle import core
+    mode = core.get_dft_mode()
+    core.set_dft_mode("naive")
+    try:
+        for shape, scheme, nsteps in (((24, 16, 32), etd.ETDRK2, 2), ((16, 16, 16), etd.ETD1, 3)):
+            ci = make_case(shape)
+            o, plan, phi, u = run_pair(ci, scheme, etd.FP64, nsteps)
+            ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+            report("coupled_fp64_naive_dft", shape=str(shape), scheme=scheme, err_phi=ephi, err_u=eu)
+            assert ephi <= 1e-12 and eu <= 1e-12
+            plan.close()
+    finally:
+        core.set_dft_mode(mode)
 
 
 @pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])

@@ -106,3 +106,83 @@ def test_nonfinite_state_is_reported():
     plan.set_state(0, dev(ci.phi0), dev(u0))
     assert plan.diagnostics(0)["nonfinite"] == 1
     plan.close()
+
+
+def raw_get_state(plan, i=0):
+    """etd_get_state through the C ABI: (status, a, u) as FP64 host arrays,
+    without raising on a non-OK status."""
+    import ctypes as C
+    shape = tuple(plan.instances[i].shape)
+    a = torch.empty(shape, dtype=torch.float64, device="cuda")
+    u = torch.empty_like(a)
+    st = etd.lib().etd_get_state(plan._ptr, i, C.c_void_p(a.data_ptr()), C.c_void_p(u.data_ptr()), etd.F64)
+    return st, host(a), host(u)
+
+
+def same(x, y):
+    return np.array_equal(x, y, equal_nan=True)
+
+
+@pytest.mark.parametrize("schedule", [etd.EXEC_EAGER, etd.EXEC_GRAPH])
+@pytest.mark.parametrize("model", ["coupled_fp64", "coupled_fp32", "fixed"])
+def test_steps_after_a_nonfinite_state_are_no_ops(model, schedule):
+    """A NaN loaded by etd_set_state is the detected non-finite state: every
+    later step leaves (phi, u) / U as they are, eagerly and under a captured
+    graph, etd_get_state returns ETD_E_NONFINITE with the state copied out,
+    and a finite etd_set_state clears it."""
+    if model == "fixed":
+        fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+        plan = etd.Plan(etd.fixed_instance(fi, scheme=etd.ETDRK2))
+        a0, u_ok = fi.g, fi.u0
+    else:
+        ci = case()
+        prec = etd.FP64 if model == "coupled_fp64" else etd.FP32
+        plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=prec))
+        a0, u_ok = ci.phi0, ci.u0
+    dt = torch.float32 if model == "coupled_fp32" else torch.float64
+    u_bad = u_ok.copy()
+    u_bad.flat[123] = np.nan
+    plan.set_schedule(schedule, 1)
+    plan.set_state(0, dev(a0, dt), dev(u_bad, dt))
+    st0, a_set, u_set = raw_get_state(plan)
+    assert st0 == etd.ETD_E_NONFINITE
+    assert np.isnan(u_set.flat[123]) and np.isfinite(np.delete(u_set.ravel(), 123)).all()
+    plan.step(3)
+    plan.step(1)
+    st, a, u = raw_get_state(plan)
+    report("nonfinite_noop", model=model, schedule=schedule, status=st)
+    assert st == etd.ETD_E_NONFINITE
+    assert same(a, a_set) and same(u, u_set)
+    assert plan.diagnostics(0)["nonfinite"] == 1
+    # a finite state clears the flag and the steps run again
+    plan.set_state(0, dev(a0, dt), dev(u_ok, dt))
+    st1, _, u1 = raw_get_state(plan)
+    plan.step(2)
+    st2, _, u2 = raw_get_state(plan)
+    assert st1 == etd.ETD_OK and st2 == etd.ETD_OK and not np.array_equal(u1, u2)
+    plan.close()
+
+
+def test_nonfinite_values_arising_in_a_step_freeze_the_state():
+    """The 512 x 8 x 12 grid (dx = 2 pi / 512 beside dy = 2 pi / 8) is
+    unstable at tau = 1e-4: u grows by orders of magnitude a step until it
+    overflows.  The step's own FP64 sums detect the first non-finite value;
+    from the next step on the state no longer changes."""
+    ci = inputs.coupled_membrane(n=(512, 8, 12), seed=31, tau=1e-4)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP64))
+    plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+    detected = None
+    for k in range(1, 60):
+        plan.step(1)
+        st, a, u = raw_get_state(plan)
+        if st == etd.ETD_E_NONFINITE:
+            detected = k
+            break
+        assert st == etd.ETD_OK
+    report("nonfinite_in_step", detected_at_step=detected)
+    assert detected is not None
+    assert not (np.isfinite(a).all() and np.isfinite(u).all())
+    plan.step(3)
+    st2, a2, u2 = raw_get_state(plan)
+    assert st2 == etd.ETD_E_NONFINITE and same(a2, a) and same(u2, u)
+    plan.close()
