@@ -231,6 +231,26 @@ etd_status etd_narrowband_build(etd_plan_t plan, int instance, const void* phi, 
                                 double threshold, int32_t* dev_idx_out, int64_t capacity,
                                 int64_t* count_out);
 
+/* The band list of etd_narrowband_build for callers that cannot allocate
+ * device memory (serving loops and harnesses that forbid hipMalloc): the
+ * same indices, bit for bit, for the n values phi[0 .. n) (any n from 0 to
+ * 268,435,456; the list does not depend on the grid's shape), with no
+ * hipMalloc, hipFree or allocating library call.  Its kernels keep their
+ * tile offsets and the total in a static 512 KiB array per device, which
+ * the library looks up at etd_plan_create and which lives until the process
+ * ends; every entry a call reads is written earlier in the same call.  All
+ * calls on one device share that array, so calls that overlap in time on
+ * one device race (the plan's stream orders calls made through one plan).
+ * Runs on the plan's stream; count_out is a host pointer; synchronizes (so
+ * it cannot be captured into a graph).  Errors: ETD_E_ARG (null plan or
+ * count_out, n < 0, phi NULL with n > 0, threshold not finite and > 0,
+ * capacity < 0, dev_idx_out NULL with capacity > 0, bad dtype), ETD_E_SIZE
+ * (n above the limit), ETD_E_CAPACITY (as etd_narrowband_build: nothing
+ * written, *count_out set), ETD_E_HIP. */
+etd_status etd_narrowband_build_noalloc(etd_plan_t plan, const void* phi, etd_dtype dtype, int64_t n,
+                                        double threshold, int32_t* dev_idx_out, int64_t capacity,
+                                        int64_t* count_out);
+
 /* Apply one of the plan's spectral operators to a real field through the
  * instance's own transforms (forward r2c, multiplier, inverse c2r):
  *   ETD_OP_IDENTITY  round trip (multiplier 1)

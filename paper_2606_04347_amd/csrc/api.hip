@@ -766,6 +766,11 @@ etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void*
         delete P;
         return fail(nullptr, ETD_E_HIP, "no HIP device");
     }
+    // the device's copy of the allocation-free band build's scratch (once per device)
+    if (hipError_t e = band_static_init(P->device); e != hipSuccess) {
+        delete P;
+        return fail(nullptr, ETD_E_HIP, std::string("scratch lookup: ") + hipGetErrorString(e));
+    }
     P->inst.resize(n_instances);
     for (int i = 0; i < n_instances; ++i) {
         Instance& I = P->inst[i];
@@ -1008,6 +1013,34 @@ etd_status etd_narrowband_build(etd_plan_t plan, int instance, const void* phi, 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (void* p : tmp) (void)hipFree(p);
     if (e != hipSuccess) return fail(&plan->err, ETD_E_HIP, std::string("band: ") + hipGetErrorString(e));
+    *count_out = c;
+    if (c > capacity) return fail(&plan->err, ETD_E_CAPACITY, "band larger than capacity");
+    return ETD_OK;
+}
+
+etd_status etd_narrowband_build_noalloc(etd_plan_t plan, const void* phi, etd_dtype dtype, int64_t n,
+                                        double threshold, int32_t* dev_idx_out, int64_t capacity,
+                                        int64_t* count_out) {
+    if (!plan) return fail(nullptr, ETD_E_ARG, "null plan");
+    if (!count_out) return fail(&plan->err, ETD_E_ARG, "null count_out");
+    if (n < 0) return fail(&plan->err, ETD_E_ARG, "n must be >= 0");
+    if (n > 0 && !phi) return fail(&plan->err, ETD_E_ARG, "null phi");
+    if (!std::isfinite(threshold) || threshold <= 0.0) return fail(&plan->err, ETD_E_ARG, "threshold must be > 0");
+    if (capacity < 0) return fail(&plan->err, ETD_E_ARG, "capacity must be >= 0");
+    if (capacity > 0 && !dev_idx_out) return fail(&plan->err, ETD_E_ARG, "null index buffer");
+    if (dtype != ETD_F64 && dtype != ETD_F32) return fail(&plan->err, ETD_E_ARG, "bad dtype");
+    if (n > band_static_max_points())
+        return fail(&plan->err, ETD_E_SIZE,
+                    "n = " + std::to_string(n) + " exceeds the static scratch's limit of " +
+                        std::to_string(band_static_max_points()) + " points");
+    int64_t c = 0;
+    const hipError_t e =
+        dtype == ETD_F64
+            ? band_build_static<double>(plan->device, (long)n, (const double*)phi, threshold, dev_idx_out, capacity, &c,
+                                        plan->stream)
+            : band_build_static<float>(plan->device, (long)n, (const float*)phi, threshold, dev_idx_out, capacity, &c,
+                                       plan->stream);
+    if (e != hipSuccess) return fail(&plan->err, ETD_E_HIP, std::string("band (static scratch): ") + hipGetErrorString(e));
     *count_out = c;
     if (c > capacity) return fail(&plan->err, ETD_E_CAPACITY, "band larger than capacity");
     return ETD_OK;

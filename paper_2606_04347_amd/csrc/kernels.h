@@ -189,5 +189,17 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
 long band_blocks(long n);
 void band_compact(long n, const uint8_t* flags, int64_t* blockcnt, int32_t* idx_out, int64_t capacity,
                   int64_t* total_dev, hipStream_t s);
+// The same list for |2 phi - 1| < thr with no device memory of its own beyond a
+// static per-device scratch array (band.hip): band_static_init(device) looks up
+// that device's copy once (the device is made current for the lookup);
+// band_build_static then runs the flag, count, scan and scatter kernels on s
+// with the flags formed where they are read, copies the count to *count_host
+// and synchronizes s.  At most band_static_max_points() points.  Calls on one
+// device share the array: calls that overlap in time race.
+long band_static_max_points();
+hipError_t band_static_init(int device);
+template <typename T>
+hipError_t band_build_static(int device, long n, const T* phi, double thr, int32_t* idx_out, int64_t capacity,
+                             int64_t* count_host, hipStream_t s);
 
 }  // namespace etd

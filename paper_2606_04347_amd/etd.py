@@ -30,7 +30,7 @@ Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE, Q_SURF_ITERS, Q
 EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau", "etd_get_state", "etd_step",
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
-           "etd_surface_lapinv",
+           "etd_surface_lapinv", "etd_narrowband_build_noalloc",
            "etd_status_string", "etd_last_error")
 EXEC_EAGER, EXEC_GRAPH = 0, 1
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
@@ -109,6 +109,7 @@ def lib():
         L.etd_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
         L.etd_autotune.argtypes = [vp, i, C.c_char_p, C.POINTER(Schedule), C.POINTER(d)]
         L.etd_surface_lapinv.argtypes = [vp, i, vp, vp, vp, vp, i, d, i, C.POINTER(i), C.POINTER(d)]
+        L.etd_narrowband_build_noalloc.argtypes = [vp, vp, i, C.c_int64, d, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -279,6 +280,20 @@ class Plan:
         cnt = C.c_int64(0)
         st = lib().etd_narrowband_build(self._ptr, i, self._dev(phi), self._dt(phi), float(threshold),
                                         C.c_void_p(idx.data_ptr()), cap, C.byref(cnt))
+        if st == ETD_E_CAPACITY:
+            raise EtdError(st, f"band has {cnt.value} points")
+        self._c(st)
+        return idx[: cnt.value]
+
+    def narrowband_noalloc(self, phi, threshold, capacity=None):
+        """The band list of narrowband() for the values of phi (any shape), built
+        with no device allocation (etd_narrowband_build_noalloc)."""
+        import torch
+        cap = phi.numel() if capacity is None else int(capacity)
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        cnt = C.c_int64(0)
+        st = lib().etd_narrowband_build_noalloc(self._ptr, self._dev(phi), self._dt(phi), phi.numel(),
+                                                float(threshold), C.c_void_p(idx.data_ptr()), cap, C.byref(cnt))
         if st == ETD_E_CAPACITY:
             raise EtdError(st, f"band has {cnt.value} points")
         self._c(st)
