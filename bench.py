@@ -54,6 +54,11 @@ def parse():
                          "default while a host-side abort seen once in this leg is unexplained")
     ap.add_argument("--no-batch", action="store_true", help="leave the uneven-batch measurement out (the default)")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--coarsening", type=float, default=0.0,
+                    help="run the four 2D coarsening experiments to this final time (the paper's: 1000); 0 = off")
+    ap.add_argument("--coarsening-every", type=float, default=1.0, help="checkpoint interval (time units)")
+    ap.add_argument("--coarsening-runs", default="0,1,2,3",
+                    help="which of the four coarsening runs (circle ETD1, circle, ellipse, protrusions ETDRK2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (a reference kernel of known size "
                          "for hardware byte counters)")
@@ -380,6 +385,61 @@ def batch_measure(steps, warmup):
             "speedup_vs_eager": ms_eager / ms_tuned, "speedup_vs_per_instance_graphs": ms_graphs / ms_tuned}
 
 
+def coarsening_measure(T, every, which=(0, 1, 2, 3)):
+    """The 2D coarsening experiments of the fixed-membrane OK model (Section
+    4.2): ETD1 on the circle (gamma = 2000), ETDRK2 on the circle (3000), the
+    ellipse (5000) and the seven-protrusion cell (7000); N = 256 on [-1, 1]^2,
+    ubar = 0.5, eps_u = 5h, tau = 1e-3, B = 2000, M = 600 (ETD1) / 200
+    (ETDRK2), each step on the narrow band {g >= 1e-3} (the region the initial
+    field is drawn on), one plan of four instances under the graph schedule.  Records
+    E_phi,h and max|2U - 1| at every checkpoint."""
+    import torch
+
+    from paper_2606_04347_amd import etd, inputs
+    runs = [inputs.COARSENING_RUNS[k] for k in which]
+    fis = [inputs.fixed_coarsening(geo, gamma=gam, M=600.0 if sch == 1 else 200.0, instance=k)
+           for k, (geo, sch, gam) in zip(which, runs)]
+    plan = etd.Plan([etd.fixed_instance(fi, B=2000.0, scheme=sch, flags=etd.F_BAND_STEP, band_threshold=1e-3)
+                     for fi, (_, sch, _) in zip(fis, runs)])
+    for k, fi in enumerate(fis):
+        plan.set_state(k, torch.as_tensor(fi.g, device="cuda"), torch.as_tensor(fi.u0, device="cuda"))
+    plan.set_schedule(etd.EXEC_GRAPH, len(runs))
+    tau = fis[0].tau
+    chunk = max(2, int(round(every / tau)) & ~1)
+    nchk = int(round(T / (chunk * tau)))
+    curves = [dict(t=[0.0], E=[plan.energy(k)["E"]], bound=[plan.diagnostics(k)["bound"]]) for k in range(len(runs))]
+    umin = [1.0] * len(runs)
+    t0 = time.time()
+    ms_steps = 0.0
+    for c in range(nchk):
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        plan.step(chunk)
+        torch.cuda.synchronize()
+        ms_steps += (time.perf_counter() - s) * 1e3
+        for k in range(len(runs)):
+            d = plan.diagnostics(k)
+            curves[k]["t"].append((c + 1) * chunk * tau)
+            curves[k]["E"].append(plan.energy(k)["E"])
+            curves[k]["bound"].append(d["bound"])
+            umin[k] = min(umin[k], d["umin"])
+        if (c + 1) % max(1, nchk // 20) == 0:
+            log(f"coarsening t={(c + 1) * chunk * tau:.0f} ({time.time() - t0:.0f} s)")
+    out = []
+    for k, (geo, sch, gam) in enumerate(runs):
+        E, bd = curves[k]["E"], curves[k]["bound"]
+        out.append({"geometry": geo, "scheme": "ETD1" if sch == 1 else "ETDRK2", "gamma": gam,
+                    "M": 600.0 if sch == 1 else 200.0, "B": 2000.0, "B_MBP": plan.query(k, etd.Q_B_MBP),
+                    "B_ES": plan.query(k, etd.Q_B_ES), "E_start": E[0], "E_end": E[-1],
+                    "E_non_increasing": bool(all(b <= a + 1e-13 * abs(a) for a, b in zip(E, E[1:]))),
+                    "max_bound": max(bd), "min_U": umin[k], "curve": curves[k]})
+    plan.close()
+    npts = sum(fi.g.size for fi in fis)
+    return {"workload": "2D coarsening on fixed membranes (Section 4.2), four 256^2 instances in one plan",
+            "T": nchk * chunk * tau, "steps": nchk * chunk, "ms_per_step": ms_steps / (nchk * chunk),
+            "value": npts * nchk * chunk / (ms_steps * 1e-3), "unit": "grid-pt steps/s", "runs": out}
+
+
 def cpu_baseline(ci, nsteps=3):
     """The FP64 oracle, as it stands, timed on the first nsteps ETDRK2 steps
     of the workload (about 15 s of CPU work at 256^3)."""
@@ -479,6 +539,12 @@ def main():
         log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "
             f"x{out['batched']['speedup_vs_eager']:.2f} vs eager, "
             f"x{out['batched']['speedup_vs_per_instance_graphs']:.2f} vs per-instance graphs")
+    if a.coarsening > 0:
+        out["coarsening"] = coarsening_measure(a.coarsening, a.coarsening_every,
+                                               tuple(int(k) for k in a.coarsening_runs.split(",")))
+        for r in out["coarsening"]["runs"]:
+            log(f"coarsening {r['geometry']} {r['scheme']} gamma={r['gamma']:.0f}: E {r['E_start']:.6g} -> "
+                f"{r['E_end']:.6g} non-increasing={r['E_non_increasing']} max|2U-1|={r['max_bound']:.6f}")
     if a.err_steps > 0:
         out["fp32_vs_fp64"] = precision_gap(ci, a.err_steps)
         log(f"fp32 vs fp64 after {a.err_steps} steps: {out['fp32_vs_fp64']}")

@@ -66,7 +66,8 @@ typedef enum { ETD_F64 = 0, ETD_F32 = 1 } etd_dtype;
 
 /* Grid.  dim is 2 or 3; n[d] for d < dim, each even, >= 8 and <= 512, of the
  * form 2^a or 3 * 2^a (radix-2/4/8 and radix-3 transforms); half_len[d] = X_d > 0.
- * The coupled model requires dim == 3. */
+ * Both models take dim 2 and 3 (a 2D grid [n0][n1] is stored like a 3D grid
+ * with one x plane). */
 typedef struct {
     int dim;
     int n[3];
@@ -121,6 +122,17 @@ typedef struct {
                                       its last iterate, and ETD_Q_SURF_ITERS /
                                       ETD_Q_SURF_RELRES report the last solve.  The energy
                                       diagnostics keep (-Delta_h)^{-1}. */
+#define ETD_F_BAND_STEP 0x8u      /* fixed model only, needs band_threshold > 0: the whole
+                                      step runs on the band {g >= band_threshold} (the
+                                      narrow-band implementation of the fixed-membrane
+                                      scheme, Section 2 with the band of Section 3.2): the
+                                      unknowns are the band nodes, Delta_S,h keeps the faces
+                                      whose two nodes are on the band, the nonlinear terms,
+                                      the nonlocal argument and the mass sum are taken on the
+                                      band, and U off the band keeps its set_state value.
+                                      The Chebyshev interval and B_MBP's C are those of the
+                                      band operator's Gershgorin bound and of (-Delta_h)^{-1};
+                                      etd_energy sums over the band's nodes and faces. */
 
 /* One simulation instance. */
 typedef struct {

@@ -206,12 +206,21 @@ def g_half(g, ax):
     return 0.5 * (g + np.roll(g, -1, axis=ax))
 
 
-def lap_S(u: np.ndarray, g: np.ndarray, grid: Grid) -> np.ndarray:
-    """Delta_{S,h} u = sum_d D_d^- (g_{i+1/2} D_d^+ u)  (operator:diff)."""
+def lap_S(u: np.ndarray, g: np.ndarray, grid: Grid, mask=None) -> np.ndarray:
+    """Delta_{S,h} u = sum_d D_d^- (g_{i+1/2} D_d^+ u)  (operator:diff).
+
+    With a band mask (bool, grid shape) only the faces whose two nodes are
+    both on the band carry flux, so rows off the band are 0 and the band
+    nodes see no value off it (the operator set up on the band nodes alone,
+    Section 3.2)."""
     out = np.zeros(np.broadcast_shapes(u.shape, g.shape))
     for d, h in enumerate(grid.h):
         ax = d - grid.dim
-        out = out + d_minus(g_half(g, ax) * d_plus(u, ax, h), ax, h)
+        gh = g_half(g, ax)
+        if mask is not None:
+            m = np.asarray(mask, dtype=np.float64)
+            gh = gh * (m * np.roll(m, -1, axis=ax))
+        out = out + d_minus(gh * d_plus(u, ax, h), ax, h)
     return out
 
 

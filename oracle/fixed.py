@@ -49,6 +49,17 @@ class FixedParams:
     # > 0: the nonlocal term by (-Delta_{S,h})^{-1} solved on the band
     # {g >= band_delta} (Section 3.2; core.lapinv_S_band) instead of (-Delta_h)^{-1}
     band_delta: float = 0.0
+    # > 0: the whole step restricted to the band {g >= band_step} (the
+    # narrow-band implementation of the fixed-membrane scheme): the unknowns
+    # are the band nodes, Delta_{S,h} keeps the faces with both nodes on the
+    # band, the nonlinear terms, the nonlocal argument and the mass sum are
+    # taken on the band, and U off the band keeps its value
+    band_step: float = 0.0
+
+
+def step_band(g, p: FixedParams):
+    """Mask of the band of the restricted step (None: the whole grid)."""
+    return (np.asarray(g) >= p.band_step) if p.band_step > 0.0 else None
 
 
 def B_mbp(eps_u, gamma, M, C, vol):
@@ -61,14 +72,19 @@ def B_es(eps_u, gamma, M, C, vol):
     return L_W2 / eps_u + (0.5 * gamma * C + 0.5 * M * vol) * (L_F2 + L_F1 ** 2) * L_G
 
 
+def _on_band(x, g, p: FixedParams):
+    m = step_band(g, p)
+    return x if m is None else np.where(m, x, 0.0)
+
+
 def mass_f(U, g, p: FixedParams, grid: Grid) -> float:
-    """m_f = <g (f(U) - ubar), 1>_h."""
-    return grid.cell * float(np.sum(g * (core.f_ind(U) - p.ubar)))
+    """m_f = <g (f(U) - ubar), 1>_h (on the band of a restricted step)."""
+    return grid.cell * float(np.sum(_on_band(g * (core.f_ind(U) - p.ubar), g, p)))
 
 
 def nonlocal_arg(U, g, p: FixedParams):
     fu = core.f_ind(U)
-    return g * (fu - p.ubar) if p.nonlocal_with_ubar else g * fu
+    return _on_band(g * (fu - p.ubar) if p.nonlocal_with_ubar else g * fu, g, p)
 
 
 def R_phi(U, g, p: FixedParams, grid: Grid) -> np.ndarray:
@@ -80,18 +96,18 @@ def R_phi(U, g, p: FixedParams, grid: Grid) -> np.ndarray:
         psi = core.lapinv(nonlocal_arg(U, g, p), grid)
     mf = mass_f(U, g, p, grid)
     fp = core.fp_ind(U)
-    return (p.B * sg * U - sg * core.Wp(U) / p.eps_u
-            - p.gamma * sg * psi * fp - p.M * mf * sg * fp)
+    nonlin = sg * core.Wp(U) / p.eps_u + p.gamma * sg * psi * fp + p.M * mf * sg * fp
+    return p.B * sg * U - _on_band(nonlin, g, p)
 
 
-def H_apply(w, g, grid: Grid):
-    """H w = -g^{-1/2} Delta_{S,h}(g^{-1/2} w)."""
+def H_apply(w, g, grid: Grid, mask=None):
+    """H w = -g^{-1/2} Delta_{S,h}(g^{-1/2} w) (faces on the band only, with a mask)."""
     isg = 1.0 / np.sqrt(g)
-    return -isg * core.lap_S(isg * w, g, grid)
+    return -isg * core.lap_S(isg * w, g, grid, mask)
 
 
 def L_apply(w, g, p: FixedParams, grid: Grid):
-    return p.B * w + p.eps_u * H_apply(w, g, grid)
+    return p.B * w + p.eps_u * H_apply(w, g, grid, step_band(g, p))
 
 
 # ---------------------------------------------------------------------------
@@ -134,7 +150,7 @@ class UspaceExpo:
         import scipy.linalg as sla
         n = int(np.prod(grid.n))
         eye = np.eye(n).reshape((n,) + tuple(grid.n))
-        cols = (p.B * eye - p.eps_u * core.lap_S(eye, g, grid) / g).reshape(n, n)
+        cols = (p.B * eye - p.eps_u * core.lap_S(eye, g, grid, step_band(g, p)) / g).reshape(n, n)
         Lt = cols.T
         aug = np.zeros((3 * n, 3 * n))
         aug[:n, :n] = -tau * Lt
@@ -216,7 +232,13 @@ def etd1_step(U, g, p: FixedParams, grid: Grid, tau: float, expo, R=None):
     sg = np.sqrt(g)
     w = sg * U
     w1 = expo.apply(core.phi0, tau, w) + tau * expo.apply(core.phi1, tau, R(U, g, p, grid))
-    return w1 / sg
+    return _keep_off_band(w1 / sg, U, g, p)
+
+
+def _keep_off_band(U_new, U, g, p: FixedParams):
+    """A restricted step leaves U off its band as it was."""
+    m = step_band(g, p)
+    return U_new if m is None else np.where(m, U_new, U)
 
 
 def etdrk2_step(U, g, p: FixedParams, grid: Grid, tau: float, expo, R=None):
@@ -227,8 +249,9 @@ def etdrk2_step(U, g, p: FixedParams, grid: Grid, tau: float, expo, R=None):
     Rn = R(U, g, p, grid)
     wt = expo.apply(core.phi0, tau, w) + tau * expo.apply(core.phi1, tau, Rn)
     Ut = wt / sg
+    Ut = _keep_off_band(Ut, U, g, p)
     w2 = wt + tau * expo.apply(core.phi2, tau, R(Ut, g, p, grid) - Rn)
-    return w2 / sg
+    return _keep_off_band(w2 / sg, U, g, p)
 
 
 def step(U, g, p, grid, tau, scheme, expo, R=None):
@@ -241,9 +264,11 @@ def step(U, g, p, grid, tau, scheme, expo, R=None):
 
 
 def energy(U, g, p: FixedParams, grid: Grid) -> dict:
-    """E_{phi,h}[U] and its four terms, each from the literal formula."""
-    e_grad = 0.5 * p.eps_u * core.inner(-core.lap_S(U, g, grid), U, grid)
-    e_well = core.inner(g * core.W(U), np.ones_like(U), grid) / p.eps_u
+    """E_{phi,h}[U] and its four terms, each from the literal formula (on the
+    band's nodes and faces for a restricted step)."""
+    m = step_band(g, p)
+    e_grad = 0.5 * p.eps_u * core.inner(-core.lap_S(U, g, grid, m), U, grid)
+    e_well = core.inner(_on_band(g * core.W(U), g, p), np.ones_like(U), grid) / p.eps_u
     q = nonlocal_arg(U, g, p)
     e_nl = 0.5 * p.gamma * core.inner(core.lapinv(q, grid), q, grid)
     mf = mass_f(U, g, p, grid)

@@ -44,7 +44,6 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
     if (d.scheme != ETD_ETD1 && d.scheme != ETD_ETDRK2) { msg = "unknown scheme"; return ETD_E_ARG; }
     if (d.precision != ETD_FP64 && d.precision != ETD_FP32) { msg = "unknown precision"; return ETD_E_ARG; }
     if (d.grid.dim != 2 && d.grid.dim != 3) { msg = "grid.dim must be 2 or 3"; return ETD_E_ARG; }
-    if (d.model == ETD_COUPLED && d.grid.dim != 3) { msg = "the coupled model is three-dimensional"; return ETD_E_ARG; }
     for (int k = 0; k < d.grid.dim; ++k) {
         const int n = d.grid.n[k];
         if (n < 8 || n > 512 || (n % 2) != 0) { msg = "grid.n must be even and in [8, 512]"; return ETD_E_SIZE; }
@@ -59,7 +58,7 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
         msg = "band_threshold must be finite and >= 0"; return ETD_E_ARG;
     }
     if (d.band_threshold > 0.0 && d.band_rebuild_every < 1) { msg = "band_rebuild_every must be >= 1"; return ETD_E_ARG; }
-    if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE | ETD_F_SURFACE_NONLOCAL)) {
+    if (d.flags & ~(ETD_F_MASS_PROJECT | ETD_F_FROZEN_MEMBRANE | ETD_F_SURFACE_NONLOCAL | ETD_F_BAND_STEP)) {
         msg = "unknown flag bits"; return ETD_E_ARG;
     }
     if ((d.flags & ETD_F_SURFACE_NONLOCAL) && !(d.band_threshold > 0.0)) {
@@ -67,6 +66,9 @@ etd_status validate(const etd_instance_desc& d, std::string& msg) {
     }
     if ((d.flags & ETD_F_FROZEN_MEMBRANE) && d.model != ETD_COUPLED) {
         msg = "ETD_F_FROZEN_MEMBRANE applies to the coupled model only"; return ETD_E_ARG;
+    }
+    if ((d.flags & ETD_F_BAND_STEP) && (d.model != ETD_FIXED_MEMBRANE || !(d.band_threshold > 0.0))) {
+        msg = "ETD_F_BAND_STEP applies to the fixed model and needs band_threshold > 0"; return ETD_E_ARG;
     }
     long total = 1;
     for (int k = 0; k < d.grid.dim; ++k) total *= d.grid.n[k];
@@ -188,30 +190,37 @@ double phi2_host(double z) {
 }
 
 // Chebyshev coefficients of x -> f(tau x) on [a, b]: f ~ c_0/2 + sum_k c_k T_k(t),
-// t = (2x - a - b)/(b - a).
+// t = (2x - a - b)/(b - a), from M samples at the Chebyshev points (a DCT in
+// long double).  The series is kept up to the last coefficient above
+// 2e-16 max|f| plus two more (the DCT's own rounding leaves |c_k| ~ 1e-17
+// max|f| in the tail); M doubles from 512 until that index lies in the first
+// half of the M computed coefficients (so aliasing has not folded the tail
+// back), up to 8192.  Returns an empty vector when even 8192 samples do not
+// resolve the series (an operator spectrum too wide for the expansion).
 std::vector<double> cheb_coeffs(double (*f)(double), double tau, double a, double b) {
-    const int M = 512;
-    std::vector<double> F(M), c(M);
-    double fmax = 0.0;
-    for (int j = 0; j < M; ++j) {
-        const double th = kPi * (j + 0.5) / M;
-        const double x = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(th);
-        F[j] = f(tau * x);
-        fmax = std::fmax(fmax, std::fabs(F[j]));
+    for (int M = 512; M <= 8192; M *= 2) {
+        std::vector<double> F(M), c(M);
+        double fmax = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const double th = kPi * (j + 0.5) / M;
+            const double x = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(th);
+            F[j] = f(tau * x);
+            fmax = std::fmax(fmax, std::fabs(F[j]));
+        }
+        for (int k = 0; k < M; ++k) {
+            long double s = 0.0L;
+            for (int j = 0; j < M; ++j) s += (long double)F[j] * cosl((long double)kPi * k * (j + 0.5L) / M);
+            c[k] = (double)(2.0L * s / M);
+        }
+        int K = 1;
+        for (int k = 0; k < M; ++k)
+            if (std::fabs(c[k]) > 2e-16 * fmax) K = k;
+        if (K + 2 < M / 2) {
+            c.resize(K + 3);
+            return c;
+        }
     }
-    for (int k = 0; k < M; ++k) {
-        long double s = 0.0L;
-        for (int j = 0; j < M; ++j) s += (long double)F[j] * cosl((long double)kPi * k * (j + 0.5L) / M);
-        c[k] = (double)(2.0L * s / M);
-    }
-    // the DCT's own rounding leaves |c_k| ~ 1e-17 max|f| in the tail; keep every
-    // coefficient above 2e-16 max|f| plus two more
-    int K = 1;
-    for (int k = 0; k < M; ++k)
-        if (std::fabs(c[k]) > 2e-16 * fmax) K = k;
-    K = std::min(M - 1, K + 2);
-    c.resize(K + 1);
-    return c;
+    return {};
 }
 
 // ------------------------------------------------------------------ instance set-up
@@ -257,6 +266,8 @@ etd_status setup_fixed(etd_plan* P, Instance& I) {
     double** reals[] = {&I.G, &I.sg, &I.isg, &I.U, &I.w, &I.R0, &I.R1, &I.vv, &I.t1, &I.t2, &I.acc, &I.q, &I.mq,
                         &I.psid};
     for (double** r : reals) ALLOC(*r, nr * sizeof(double));
+    if (I.d.flags & ETD_F_BAND_STEP) ALLOC(I.gf, nr * sizeof(double));
+    else I.gf = I.G;
     ALLOC(I.Sa, ns * sizeof(double2));
     ALLOC(I.Stmp, ns * sizeof(double2));
     etd_status st = make_tables<double>(P, I, I.td);
@@ -561,7 +572,8 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     const GridK& g = I.g;
     const long n = g.nreal();
     const double fb = 8.0 * n;
-    timed_kernel(PASS_FIXED_POINT, 4.0 * fb, s, [&] { fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, s); });
+    const double* band = (I.d.flags & ETD_F_BAND_STEP) ? I.gf : nullptr;
+    timed_kernel(PASS_FIXED_POINT, 4.0 * fb, s, [&] { fixed_nonlocal_arg(n, I.FK, I.G, U, I.q, I.mq, band, s); });
     timed_kernel(PASS_REDUCE, fb, s, [&] {
         reduce_sum<double>(n, I.mq, g.cell, I.part, I.scal + S_MASS, s, halt_flag(I));
     });
@@ -569,9 +581,9 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     if (st != ETD_OK) return st;
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
         if (!I.f32 || (I.d.flags & ETD_F_SURFACE_NONLOCAL))
-            fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, s);
+            fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, band, s);
         else
-            fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, s);
+            fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, band, s);
     });
     return ETD_OK;
 }
@@ -584,7 +596,7 @@ void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, doub
     // first: T_1 v = Atil v; acc = c0/2 v + c1 T_1 v
     const double fb = 8.0 * g.nreal();
     timed_kernel(PASS_FIXED_STENCIL, 5.0 * fb, s, [&] {
-        fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
+        fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
                         0.5 * c[0], 1, s);
     });
     const double* prev = v;
@@ -592,7 +604,7 @@ void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, doub
         // T_k = 2 Atil T_{k-1} - T_{k-2}; written over the T_{k-2} buffer (prev == v at k = 2)
         double* out = (k == 2) ? tkm1 : const_cast<double*>(prev);
         timed_kernel(PASS_FIXED_STENCIL, 7.0 * fb, s, [&] {
-            fixed_cheb_step(g, I.FK, I.G, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
+            fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
         });
         prev = tk;
         tk = out;
@@ -607,12 +619,13 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     const double fb = 8.0 * n;
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { mul(n, I.sg, I.U, I.w, s); });
     if ((st = fixed_R(plan, I, I.U, I.R0, s)) != ETD_OK) return st;
-    timed_kernel(PASS_FIXED_STENCIL, 4.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.G, I.isg, I.w, I.vv, s); });
+    timed_kernel(PASS_FIXED_STENCIL, 4.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.gf, I.isg, I.w, I.vv, s); });
+    const double* band = (I.d.flags & ETD_F_BAND_STEP) ? I.gf : nullptr;   // U changes on the band only
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R0, -1.0, I.vv, I.vv, s); });
     cheb_apply(I, I.ch1, I.vv, I.acc, s);
     timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
         axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);   // w = w~
-        mul(n, I.isg, I.w, I.U, s, halt_flag(I));       // U = w~ / sg  (ETD1 result / predictor)
+        mul(n, I.isg, I.w, I.U, s, halt_flag(I), band);   // U = w~ / sg  (ETD1 result / predictor)
     });
     if (I.d.scheme == ETD_ETDRK2) {
         if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
@@ -620,7 +633,7 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
         cheb_apply(I, I.ch2, I.vv, I.acc, s);
         timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
             axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
-            mul(n, I.isg, I.w, I.U, s, halt_flag(I));
+            mul(n, I.isg, I.w, I.U, s, halt_flag(I), band);
         });
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
@@ -690,7 +703,8 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
     load_field<double>(n, a, dt, I.G, s);
     load_field<double>(n, u, dt, I.U, s);
     fixed_prep(g, I.G, I.sg, I.isg, s);
-    fixed_gershgorin(g, I.G, I.isg, I.part, I.scal + S_GERSH, s);
+    if (I.d.flags & ETD_F_BAND_STEP) fixed_band_field(n, I.G, I.d.band_threshold, I.gf, s);
+    fixed_gershgorin(g, I.gf, I.isg, I.part, I.scal + S_GERSH, s);
     mass_project_sums<double>(n, I.G, I.U, I.d.recover_threshold, I.part, I.scal + S_MPS, s);
     // min g and a non-finite count, through the diagnostics reduction with g in the u slot
     reduce_diag<double>(g, nullptr, I.G, I.G, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
@@ -713,6 +727,11 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
     if (!(I.b > I.a)) I.b = I.a * (1.0 + 1e-12) + 1e-300;
     I.ch1 = cheb_coeffs(phi1_host, I.d.tau, I.a, I.b);
     I.ch2 = cheb_coeffs(phi2_host, I.d.tau, I.a, I.b);
+    if (I.ch1.empty() || I.ch2.empty())
+        return fail(&plan->err, ETD_E_ARG,
+                    "the spectrum of tau L, [" + std::to_string(I.d.tau * I.a) + ", " + std::to_string(I.d.tau * I.b) +
+                        "], is too wide for the Chebyshev expansion (more than 4096 terms): g varies too fast "
+                        "between neighbours where it is tiny; ETD_F_BAND_STEP restricts the step to {g >= delta}");
     const double Q0 = host[1] * g.cell;
     HIPCHK(plan, hipMemcpy(I.scal + S_Q0, &Q0, sizeof(double), hipMemcpyHostToDevice));
     if (!std::isfinite(host[1])) {   // U not finite (g is checked above): keep it, steps are no-ops
@@ -826,12 +845,15 @@ etd_status etd_set_tau(etd_plan_t plan, int instance, double tau) {
     if (st != ETD_OK) return st;
     if (!(std::isfinite(tau) && tau > 0.0)) return fail(&plan->err, ETD_E_ARG, "tau must be finite and > 0");
     Instance& I = plan->inst[instance];
+    if (I.d.model == ETD_FIXED_MEMBRANE && I.has_state) {
+        std::vector<double> c1 = cheb_coeffs(phi1_host, tau, I.a, I.b), c2 = cheb_coeffs(phi2_host, tau, I.a, I.b);
+        if (c1.empty() || c2.empty())   // the instance keeps its step
+            return fail(&plan->err, ETD_E_ARG, "the spectrum of tau L is too wide for the Chebyshev expansion");
+        I.ch1 = std::move(c1);
+        I.ch2 = std::move(c2);
+    }
     I.d.tau = tau;
     I.K.tau = tau;
-    if (I.d.model == ETD_FIXED_MEMBRANE && I.has_state) {
-        I.ch1 = cheb_coeffs(phi1_host, tau, I.a, I.b);
-        I.ch2 = cheb_coeffs(phi2_host, tau, I.a, I.b);
-    }
     drop_graphs(plan);
     return ETD_OK;
 }
@@ -887,11 +909,11 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
     double sums[7] = {0};
     if (I.d.model == ETD_FIXED_MEMBRANE) {
         if (n_out < 5) return fail(&plan->err, ETD_E_ARG, "fixed energy needs n_out >= 5");
-        fixed_nonlocal_arg(n, I.FK, I.G, I.U, I.q, I.mq, s);
+        fixed_nonlocal_arg(n, I.FK, I.G, I.U, I.q, I.mq, (I.d.flags & ETD_F_BAND_STEP) ? I.gf : nullptr, s);
         HIPCHK(plan, fft_r2c_3d<double>(g, I.td, I.q, (double2*)I.Sa, s));
         spec_apply<double>(g, SPEC_INV_FD, (const double2*)I.Sa, (double2*)I.Sa, I.fd, s);
         HIPCHK(plan, fft_c2r_3d<double>(g, I.td, (const double2*)I.Sa, (double2*)I.Stmp, I.psid, s));
-        reduce_energy_fixed(g, I.FK, I.G, I.U, I.psid, I.q, I.part, I.scal + S_ENERGY, s);
+        reduce_energy_fixed(g, I.FK, I.gf, I.U, I.psid, I.q, I.part, I.scal + S_ENERGY, s);
         HIPCHK(plan, hipMemcpyAsync(sums, I.scal + S_ENERGY, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(plan, hipStreamSynchronize(s));
         const double c = g.cell;

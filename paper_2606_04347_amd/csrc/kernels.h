@@ -119,13 +119,18 @@ void fixed_prep(const GridK& g, const double* gg, double* sg, double* isg, hipSt
 // H row bound: out[i] = H_ii + sum_j |H_ij|; reduced with max.
 void fixed_gershgorin(const GridK& g, const double* gg, const double* isg, double* part, double* out,
                       hipStream_t s);
-// q = g f(U) (or g (f(U) - ubar)); mq = g (f(U) - ubar) (for the mass integral)
+// The band of a step restricted to {g >= delta} (the narrow-band fixed-membrane
+// step), as the operator kernels take it: gf = g on the band, -1 off it.
+void fixed_band_field(long n, const double* G, double delta, double* gf, hipStream_t s);
+// q = g f(U) (or g (f(U) - ubar)); mq = g (f(U) - ubar) (for the mass integral);
+// gf (nullable): both 0 off the band of a restricted step
 void fixed_nonlocal_arg(long n, const FixedK& K, const double* gg, const double* U, double* q, double* mq,
-                        hipStream_t s);
-// R = B sg U - sg W'(U)/eps_u - gamma sg psi f'(U) - M m sg f'(U)
+                        const double* gf, hipStream_t s);
+// R = B sg U - sg W'(U)/eps_u - gamma sg psi f'(U) - M m sg f'(U); gf (nullable):
+// off the band of a restricted step R = B (sg U)
 template <typename TP>
 void fixed_remainder(long n, const FixedK& K, const double* sg, const double* U, const TP* psi,
-                     const double* m, double* R, hipStream_t s);
+                     const double* m, double* R, const double* gf, hipStream_t s);
 // y = alpha * Atil x - beta * xprev  (Atil = (2 L - (a + b)) / (b - a), L = B + eps_u H),
 // acc (+)= c * y.  xprev may be null when beta == 0.  first != 0: acc = c0 * x + c * y.
 void fixed_cheb_step(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
@@ -136,8 +141,10 @@ void fixed_L_apply(const GridK& g, const FixedK& K, const double* gg, const doub
                    double* out, hipStream_t s);
 // elementwise helpers
 void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
-// out = x * y; a no-op once *halt != 0 (halt nullable)
-void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt = nullptr);
+// out = x * y; a no-op once *halt != 0 (halt nullable); with gf (nullable) only
+// on the band of a restricted step (gf >= 0)
+void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt = nullptr,
+         const double* gf = nullptr);
 // Fixed energy sums: out = [sum g_half (D+U)^2 (edges), sum g W(U), sum psi q, sum g (f(U) - ubar)] (unscaled)
 void reduce_energy_fixed(const GridK& g, const FixedK& K, const double* gg, const double* U, const double* psi,
                          const double* q, double* part, double* out, hipStream_t s);

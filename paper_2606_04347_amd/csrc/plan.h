@@ -48,6 +48,7 @@ struct Instance {
            *vv = nullptr, *t1 = nullptr, *t2 = nullptr, *acc = nullptr, *q = nullptr, *mq = nullptr,
            *psid = nullptr;
     float *qf = nullptr, *psif = nullptr;   // FP32-FFT variant of the nonlocal term
+    double* gf = nullptr;   // operator field: G, or for ETD_F_BAND_STEP g on the band and -1 off it
     // shared
     uint8_t* mask = nullptr;
     int32_t* band_idx = nullptr;

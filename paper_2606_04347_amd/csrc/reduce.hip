@@ -159,6 +159,7 @@ __device__ __forceinline__ double edge_energy(const GridK& g, long i, const T* u
         if (d == 0 && g.nx == 1) continue;
         const long j = nbs[d];
         const double gj = from_phi ? gloc_d((double)G[j]) : (double)G[j];
+        if (!from_phi && (gc < 0.0 || gj < 0.0)) continue;   // a face leaving the band of a restricted step
         const double du = ((double)u[j] - uc) / g.h[d];
         e += 0.5 * (gc + gj) * du * du;
     }
@@ -191,9 +192,9 @@ struct EnergyFixedF {
     __device__ void operator()(long i, double* s, double*) const {
         const double uu = U[i];
         s[0] = edge_energy(g, i, U, G, false);
-        s[1] = G[i] * W_d(uu);
+        s[1] = G[i] >= 0.0 ? G[i] * W_d(uu) : 0.0;   // G < 0: off the band of a restricted step
         s[2] = psi[i] * q[i];
-        s[3] = G[i] * (f_d(uu) - ubar);
+        s[3] = G[i] >= 0.0 ? G[i] * (f_d(uu) - ubar) : 0.0;
     }
 };
 
@@ -243,6 +244,7 @@ struct GershF {
             const double ih2 = 1.0 / (g.h[d] * g.h[d]);
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const long j = nb[d][sgn];
+                if (gc < 0.0 || G[j] < 0.0) continue;   // a face leaving the band of a restricted step
                 const double ge = 0.5 * (gc + G[j]);
                 diag += ic * ic * ge * ih2;
                 off += ic * isg[j] * ge * ih2;

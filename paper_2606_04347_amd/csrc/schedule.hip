@@ -188,6 +188,9 @@ etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
             if (p) v.parts.push_back({p, n * es});   // gy, gz exist on two-dimensional grids only
         v.parts.push_back({I.Sphi, 2 * es * (size_t)I.g.nspec()});
         if (I.mask) v.parts.push_back({I.mask, n});
+        // the band list in use until the next rebuild (the trial steps may rebuild it)
+        if (I.band_idx) v.parts.push_back({I.band_idx, n * sizeof(int32_t)});
+        if (I.band_cnt) v.parts.push_back({I.band_cnt, (size_t)(band_blocks((long)n) + 2) * sizeof(int64_t)});
         if (I.band_total) v.parts.push_back({I.band_total, sizeof(int64_t)});
     } else {
         v.parts.push_back({I.U, n * sizeof(double)});

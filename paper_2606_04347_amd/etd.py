@@ -24,6 +24,7 @@ F64, F32 = 0, 1
 F_MASS_PROJECT = 0x1
 F_FROZEN_MEMBRANE = 0x2
 F_SURFACE_NONLOCAL = 0x4
+F_BAND_STEP = 0x8
 OP_IDENTITY, OP_LAPLACE, OP_DX, OP_DY, OP_DZ, OP_LAPINV = range(6)
 Q_B, Q_B_MBP, Q_B_ES, Q_C, Q_RHO, Q_CHEB_DEG, Q_A0, Q_WORKSPACE, Q_SURF_ITERS, Q_SURF_RELRES = range(10)
 

@@ -210,6 +210,43 @@ def fixed_patch_study(n: int = 256, eps_u_in_h: float = 5.0, M: float = 600.0, t
     return FixedInputs(shape, (1.0, 1.0), g, u0.reshape(shape), eps_u_in_h * h, gamma, M, ubar, tau)
 
 
+COARSENING_RUNS = (   # (geometry, scheme, gamma) of the 2D coarsening experiments (Section 4.2)
+    ("circle", 1, 2000.0), ("circle", 2, 3000.0), ("ellipse", 2, 5000.0), ("protrusions", 2, 7000.0))
+
+
+def fixed_coarsening(geometry: str = "circle", n: int = 256, gamma: float = 2000.0, M: float = 600.0,
+                     tau: float = 1e-3, ubar: float = 0.5, eps_u_in_h: float = 5.0, eps_phi_in_h: float = 10.0,
+                     r0: float = 0.4, coarse: int = 8, band_delta: float = 1e-3, seed: int = DEFAULT_SEED,
+                     instance: int = 0) -> FixedInputs:
+    """The fixed cells of the 2D coarsening experiments (Section 4.2) on
+    [-1, 1]^2 with N = 256: phi = 0.5 + 0.5 tanh(3 (r0 - r) / eps_phi),
+    eps_phi = 10 h, so g = (9/8) sech^4(3 (r0 - r) / eps_phi) (used in that
+    form: positive everywhere), with
+      circle       r = sqrt(x^2 + y^2), r0 = 0.4;
+      ellipse      r = sqrt(x^2 + sqrt(3) y^2), r0 = 0.4;
+      protrusions  r = sqrt(x^2 + y^2), r0 = 0.4 (1 + 0.1 sin 7 theta).
+    U^0 is drawn on a coarse grid (blocks of coarse x coarse cells, one
+    U(0, 1) value each, seeded) on the band {g >= band_delta}, and ubar
+    elsewhere; eps_u = 5 h, ubar = 0.5, tau = 1e-3 as the section states."""
+    shape = (n, n)
+    h = 2.0 / n
+    X, Y = mesh(shape, (1.0, 1.0))
+    if geometry == "ellipse":
+        r = np.sqrt(X * X + math.sqrt(3.0) * Y * Y)
+        rr = np.full(shape, r0)
+    else:
+        r = np.sqrt(X * X + Y * Y)
+        rr = r0 * (1.0 + 0.1 * np.sin(7.0 * np.arctan2(Y, X))) if geometry == "protrusions" else np.full(shape, r0)
+    if geometry not in ("circle", "ellipse", "protrusions"):
+        raise ValueError(geometry)
+    g = 1.125 * sech4(3.0 * (rr - r) / (eps_phi_in_h * h))
+    nc = n // coarse
+    draws = 0.5 * (1.0 + uniform_pm1(seed, instance, 5, (nc, nc)))
+    field = np.repeat(np.repeat(draws, coarse, axis=0), coarse, axis=1)
+    u0 = np.where(g >= band_delta, field, ubar)
+    return FixedInputs(shape, (1.0, 1.0), g, u0, eps_u_in_h * h, gamma, M, ubar, tau)
+
+
 # ----------------------------------------------------------------------------
 # coupled phi/u inputs (3D, [-pi, pi)^3, eps = 3h)
 # ----------------------------------------------------------------------------
@@ -324,17 +361,56 @@ def coupled_membrane(n=256, seed: int = DEFAULT_SEED, instance: int = 0, R0: flo
     return CoupledInputs(shape, hl, phi0, u0, p, tau, seed, instance, a)
 
 
+def coupled_membrane_2d(n=256, seed: int = DEFAULT_SEED, instance: int = 0, R0: float = 1.5,
+                        eps_pm_in_h: float = 3.0, tau: float = 1e-4, half_len: float = math.pi, mmax: int = 4,
+                        amp: float = 0.05, base: dict | None = None, coeff_range=(0.5, 2.0), u_amp_pm: float = 0.1,
+                        u_mask_pm: float = 0.9, overrides: dict | None = None) -> CoupledInputs:
+    """Two-dimensional counterpart of coupled_membrane: a perturbed circle
+    phi_pm = tanh((R(theta) - r) / (sqrt(2) eps_pm)) on [-X, X)^2 with
+    R = R0 (1 + amp * sum_{m=1..mmax} (a_m cos m theta + b_m sin m theta) / sqrt(pi)),
+    a_m, b_m ~ N(0, 1) (orthonormal Fourier modes of the circle); u, the
+    width convention and the parameter draws as in coupled_membrane."""
+    shape = tuple(n) if isinstance(n, (tuple, list)) else (n, n)
+    hl = (half_len,) * 2
+    h = 2.0 * half_len / min(shape)
+    eps_pm = eps_pm_in_h * h
+    X, Y = mesh(shape, hl)
+    r = np.sqrt(X * X + Y * Y)
+    theta = np.arctan2(Y, X)
+    a = normal(seed, instance, 2, 2 * mmax)
+    pert = np.zeros(shape)
+    for m in range(1, mmax + 1):
+        pert += (a[2 * m - 2] * np.cos(m * theta) + a[2 * m - 1] * np.sin(m * theta)) / math.sqrt(math.pi)
+    R = R0 * (1.0 + amp * pert)
+    phi_pm = np.tanh((R - r) / (math.sqrt(2.0) * eps_pm))
+    phi0 = 0.5 * (1.0 + phi_pm)
+    upm = u_amp_pm * uniform_pm1(seed, instance, 3, shape)
+    u0 = np.where(np.abs(phi_pm) < u_mask_pm, 0.5 * (1.0 + upm), 0.0)
+    eps_phi = 3.0 * math.sqrt(2.0) * eps_pm
+    p = CoupledParams(eps_phi=eps_phi, eps_u=0.5 * eps_phi)
+    base = dict(base or {})
+    draws = uniform_open01(seed, instance, 4, len(NAMED_COEFFS))
+    lo, hi = coeff_range
+    for i, name in enumerate(NAMED_COEFFS):
+        setattr(p, name, float(base.get(name, 1.0) * (lo + (hi - lo) * draws[i])))
+    for k, v in (overrides or {}).items():
+        setattr(p, k, v)
+    return CoupledInputs(shape, hl, phi0, u0, p, tau, seed, instance, a)
+
+
 def frozen_sphere(n: int = 128, radius: float = 0.5, eps_pm_in_h: float = 2.0, tau: float = 0.02,
                   B2: float = 1000.0, seed: int = DEFAULT_SEED, instance: int = 0, u_mean_pm: float = -0.2,
-                  u_amp_pm: float = 0.05, gamma: float = 1.0, M: float = 200.0) -> CoupledInputs:
-    """The sphere of fixed_membrane(dim=3, ...) as coupled-model inputs, for
-    the coupled scheme's u stages on a frozen membrane: phi the [0,1] tanh
-    profile of the same radius and width (so g(phi) is that membrane's g up
-    to rounding), the same U^0 draws, eps_u, gamma, M, ubar, and the
-    stabilizer B2 given (B1 = 1).  The phi-equation coefficients are unused."""
-    shape = (n, n, n)
-    hl = (1.0, 1.0, 1.0)
-    eps_pm = eps_pm_in_h * 2.0 / n
+                  u_amp_pm: float = 0.05, gamma: float = 1.0, M: float = 200.0, dim: int = 3,
+                  eps_pm: float | None = None) -> CoupledInputs:
+    """The sphere (dim 3) or circle (dim 2) of fixed_membrane(dim, ...) as
+    coupled-model inputs, for the coupled scheme's u stages on a frozen
+    membrane: phi the [0,1] tanh profile of the same radius and width (so
+    g(phi) is that membrane's g up to rounding), the same U^0 draws, eps_u,
+    gamma, M, ubar, and the stabilizer B2 given (B1 = 1).  The phi-equation
+    coefficients are unused."""
+    shape = (n,) * dim
+    hl = (1.0,) * dim
+    eps_pm = eps_pm if eps_pm is not None else eps_pm_in_h * 2.0 / n
     X = mesh(shape, hl)
     r = np.sqrt(sum(x * x for x in X))
     phi0 = 0.5 * (1.0 + np.tanh((radius - r) / (math.sqrt(2.0) * eps_pm)))

@@ -231,3 +231,68 @@ def test_steps_are_deterministic():
         outs.append([host(t) for t in plan.get_state(0)])
         plan.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# ----------------------------------------------------------------------------- two-dimensional grids
+def make_case_2d(shape, tau=1e-4, seed=31, **kw):
+    return inputs.coupled_membrane_2d(n=shape, seed=seed, tau=tau, **kw)
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+@pytest.mark.parametrize("shape,nsteps", [((64, 64), 5), ((96, 128), 3), ((256, 256), 2), ((8, 512), 2),
+                                          ((384, 24), 1)])
+def test_fp64_2d_step_matches_oracle(shape, nsteps, scheme):
+    """The coupled scheme on two-dimensional grids (Section 3 is written for
+    d = 2, 3): the perturbed circle of inputs.coupled_membrane_2d."""
+    ci = make_case_2d(shape)
+    o, plan, phi, u = run_pair(ci, scheme, etd.FP64, nsteps)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_2d_fp64", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi, err_u=eu)
+    assert ephi <= 1e-12 and eu <= 1e-12
+    d, od = plan.diagnostics(0), o.diagnostics()
+    for k_gpu, k_or in (("int_phi", "I_phi"), ("mass", "m"), ("Q", "Q"), ("umin", "umin"), ("umax", "umax"),
+                        ("bound", "bound")):
+        assert abs(d[k_gpu] - od[k_or]) <= 1e-11 * max(1.0, abs(od[k_or])), (k_gpu, d[k_gpu], od[k_or])
+    e, oe = plan.energy(0), o.energy()
+    for k in ("E_surf", "E_bend", "E_area", "E_ok", "E_nonlocal", "E_mass"):
+        assert abs(e[k] - oe[k]) <= 1e-10 * max(1e-8, abs(oe[k])) + 1e-14, (k, e[k], oe[k])
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+@pytest.mark.parametrize("shape,nsteps", [((128, 128), 20), ((96, 128), 5)])
+def test_fp32_2d_step_close_to_oracle(scheme, shape, nsteps):
+    """FP32 on two-dimensional grids, step by step, under the comparison of
+    test_fp32_step_close_to_oracle."""
+    ci = make_case_2d(shape)
+    grid = Grid(ci.shape, ci.half_len)
+    o = CoupledOracle(grid, ci.params, ci.tau, scheme)
+    o.set_state(ci.phi0, ci.u0)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=scheme, precision=etd.FP32))
+    plan.set_state(0, dev(ci.phi0, torch.float32), dev(ci.u0, torch.float32))
+    flips = np.zeros(ci.shape, dtype=bool)
+    for _ in range(nsteps):
+        o.step()
+        plan.step(1)
+        flips |= recovery_flips(host(plan.get_state(0, torch.float32)[0]), o.phi())
+    phi, u = (host(t) for t in plan.get_state(0))
+    po = o.phi()
+    ephi = rel_linf(phi, po)
+    eu, near, egu, eall = u_gap_outside_flips(u, o.u, po, flips)
+    report("coupled_2d_fp32", shape=str(shape), scheme=scheme, steps=nsteps, err_phi=ephi, err_u=eu,
+           flips=int(flips.sum()), near=near, err_gu=egu, err_u_all=eall)
+    assert ephi <= 1e-4 and eu <= 1e-4 and egu <= 1e-4
+    assert flips.sum() <= max(1, 1e-4 * flips.size)
+    plan.close()
+
+
+@pytest.mark.parametrize("kw", [dict(flags=etd.F_FROZEN_MEMBRANE), dict(flags=etd.F_MASS_PROJECT),
+                                dict(band_threshold=0.995, band_rebuild_every=3)])
+def test_2d_options_match_oracle(kw):
+    """Frozen membrane, mass projection and the narrow band on a 2D grid."""
+    ci = make_case_2d((64, 96))
+    o, plan, phi, u = run_pair(ci, etd.ETDRK2, etd.FP64, 6, **kw)
+    ephi, eu = rel_linf(phi, o.phi()), rel_linf(u, o.u)
+    report("coupled_2d_options", opts=str(kw), err_phi=ephi, err_u=eu)
+    assert ephi <= 1e-12 and eu <= 1e-12
+    plan.close()

@@ -19,8 +19,8 @@ def oracle_params(fi, B=None):
     return grid, fixed.FixedParams(fi.eps_u, fi.gamma, fi.M, fi.ubar, Bm if B is None else B), C
 
 
-def gpu_run(fi, scheme, nsteps, precision=etd.FP64, B=0.0, flags=0):
-    plan = etd.Plan(etd.fixed_instance(fi, B=B, scheme=scheme, precision=precision, flags=flags))
+def gpu_run(fi, scheme, nsteps, precision=etd.FP64, B=0.0, flags=0, **kw):
+    plan = etd.Plan(etd.fixed_instance(fi, B=B, scheme=scheme, precision=precision, flags=flags, **kw))
     plan.set_state(0, dev(fi.g), dev(fi.u0))
     plan.step(nsteps)
     _, u = plan.get_state(0)
@@ -211,4 +211,112 @@ def test_config1_200_steps_with_mass_projection():
         assert abs(d["Q"] - Q0) <= 1e-12 * abs(Q0), (d["Q"], Q0)
         assert d["umin"] >= 0.0 and d["umax"] <= 1.0
     report("fixed_config1_mass", Q=Q0, drift=abs(d["Q"] - Q0) / abs(Q0), umin=d["umin"], umax=d["umax"])
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+def test_split_and_stabilized_schemes_on_one_circle(scheme):
+    """The two discretizations of the OK dynamics on a fixed membrane, on the
+    same 64^2 circle (eps_pm = 0.0625, the fixed configuration) with the same
+    U^0, tau = 0.01 and stabilizer B = B_MBP: the localization split of
+    Section 2 (its MBP and energy theorems: asserted) and the stabilized
+    spectral u-step of Section 3.1 with phi frozen and v = 0 (no such
+    theorems: its bound and energy are reported).  The two discretize the
+    nonlocal and mass terms differently (g f(u) in the split, g (u - ubar)
+    here), so their trajectories differ."""
+    fi = inputs.fixed_membrane(dim=2, n=64, eps_pm=0.0625)
+    split = etd.Plan(etd.fixed_instance(fi, scheme=scheme))
+    split.set_state(0, dev(fi.g), dev(fi.u0))
+    B = split.query(0, etd.Q_B)
+    ci = inputs.frozen_sphere(n=64, radius=0.5, dim=2, eps_pm=0.0625, tau=fi.tau, B2=B, gamma=fi.gamma, M=fi.M)
+    assert np.abs(18.0 * (ci.phi0 * ci.phi0 - ci.phi0) ** 2 - fi.g).max() <= 1e-12
+    assert np.array_equal(ci.u0, fi.u0)
+    stab = etd.Plan(etd.coupled_instance(ci, scheme=scheme, flags=etd.F_FROZEN_MEMBRANE))
+    stab.set_state(0, dev(ci.phi0), dev(ci.u0))
+    E_split = [split.energy(0)["E"]]
+    e = stab.energy(0)
+    E_stab = [e["E_ok"] + e["E_nonlocal"] + e["E_mass"]]
+    lo, hi = 1.0, 0.0
+    for _ in range(10):
+        split.step(5)
+        stab.step(5)
+        d = split.diagnostics(0)
+        assert d["umin"] >= 0.0 and d["umax"] <= 1.0
+        E_split.append(split.energy(0)["E"])
+        assert E_split[-1] <= E_split[-2] + 1e-13 * abs(E_split[-2])
+        ds = stab.diagnostics(0)
+        lo, hi = min(lo, ds["umin"]), max(hi, ds["umax"])
+        e = stab.energy(0)
+        E_stab.append(e["E_ok"] + e["E_nonlocal"] + e["E_mass"])
+        assert np.isfinite(E_stab[-1])
+    report("split_vs_stabilized_2d", scheme=scheme, split_U=f"[{d['umin']:.4g},{d['umax']:.4g}]",
+           split_E=f"{E_split[0]:.5g}->{E_split[-1]:.5g}", stab_U=f"[{lo:.4g},{hi:.4g}]",
+           stab_E=f"{E_stab[0]:.5g}->{E_stab[-1]:.5g}",
+           stab_E_monotone=bool(all(b <= a + 1e-12 * abs(a) for a, b in zip(E_stab, E_stab[1:]))))
+    split.close()
+    stab.close()
+
+
+@pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
+@pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
+def test_band_step_matches_oracle(scheme, precision):
+    """ETD_F_BAND_STEP: the step restricted to {g >= 1e-3} against the oracle's
+    restricted step (U-space block exponential), 2D config-1 geometry on
+    32^2; U off the band keeps its initial value exactly; the band energy."""
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm=0.0625)
+    grid, p, _ = oracle_params(fi)
+    p.band_step = 1e-3
+    band = fixed.step_band(fi.g, p)
+    ex = fixed.UspaceExpo(fi.g, p, grid, fi.tau)
+    U = fi.u0.copy()
+    for _ in range(8):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, scheme, ex)
+    plan, Ug = gpu_run(fi, scheme, 8, precision=precision, flags=etd.F_BAND_STEP, band_threshold=1e-3)
+    err = rel_linf(Ug, U)
+    report("fixed_band_step", scheme=scheme, precision=precision, err=err, band=int(band.sum()),
+           deg=plan.query(0, etd.Q_CHEB_DEG))
+    assert err <= (1e-12 if precision == etd.FP64 else 1e-5)
+    assert np.array_equal(Ug[~band], fi.u0[~band])
+    e, oe = plan.energy(0), fixed.energy(U, fi.g, p, grid)
+    for k in ("E", "E_grad", "E_well", "E_nonlocal", "E_mass"):
+        assert abs(e[k] - oe[k]) <= 1e-9 * max(abs(oe[k]), 1e-12), (k, e[k], oe[k])
+    plan.close()
+
+
+def test_band_step_3d_matches_lanczos_oracle():
+    fi = inputs.fixed_membrane(dim=3, n=24, eps_pm_in_h=2.0, tau=0.02)
+    grid, p, _ = oracle_params(fi)
+    p.band_step = 1e-4
+    ex = fixed.LanczosExpo(fi.g, p, grid)
+    U = fi.u0.copy()
+    for _ in range(3):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, etd.ETDRK2, ex)
+    plan, Ug = gpu_run(fi, etd.ETDRK2, 3, flags=etd.F_BAND_STEP, band_threshold=1e-4)
+    err = rel_linf(Ug, U)
+    report("fixed3d_band_step", err=err)
+    assert err <= 1e-12
+    plan.close()
+
+
+def test_band_step_tames_the_protrusion_cell_and_full_grid_refuses_it():
+    """The seven-protrusion cell of Section 4.2: r0 = 0.4 (1 + 0.1 sin 7 theta)
+    makes g jump by ~1e5 between neighbouring nodes near the centre, where
+    g ~ 1e-67, and the full-grid operator's spectrum (Gershgorin bound
+    ~5e9) needs a Chebyshev series beyond 4096 terms: plan set-up refuses
+    it.  On the band {g >= 1e-3} the spectrum is that of the circle."""
+    fi = inputs.fixed_coarsening("protrusions", gamma=7000.0, M=200.0)
+    full = etd.Plan(etd.fixed_instance(fi, B=2000.0, scheme=etd.ETDRK2))
+    with pytest.raises(etd.EtdError) as ei:
+        full.set_state(0, dev(fi.g), dev(fi.u0))
+    assert ei.value.status == etd.ETD_E_ARG
+    full.close()
+    plan = etd.Plan(etd.fixed_instance(fi, B=2000.0, scheme=etd.ETDRK2, flags=etd.F_BAND_STEP,
+                                       band_threshold=1e-3))
+    plan.set_state(0, dev(fi.g), dev(fi.u0))
+    deg, rho = plan.query(0, etd.Q_CHEB_DEG), plan.query(0, etd.Q_RHO)
+    report("protrusions_band", deg=deg, rho=rho)
+    assert deg <= 40
+    plan.step(10)
+    d = plan.diagnostics(0)
+    assert d["umin"] >= -1e-14 and d["umax"] <= 1.0 + 1e-14
     plan.close()

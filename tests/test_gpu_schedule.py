@@ -145,3 +145,26 @@ def test_autotune_restores_state_and_uses_cache(tmp_path):
     assert_same(states(plan, len(b)), states(ref, len(b)))
     plan.close()
     ref.close()
+
+
+def test_autotune_between_band_rebuilds_restores_the_band_list():
+    """A band-solve plan (ETD_F_SURFACE_NONLOCAL reads the band list in every
+    step) autotuned at step 3, between rebuilds every 4 steps: the trial steps
+    rebuild the list from later phi, and the restore must bring back the list
+    built at step 0, which step 3 then uses, so the run matches an untuned
+    one bit for bit.  B2 = 16000 keeps the band-solve step bounded on this
+    coarse grid."""
+    ci = inputs.coupled_membrane(n=(24, 24, 24), seed=31, tau=1e-4, eps_pm_in_h=1.5, overrides=dict(B2=16000.0))
+    runs = []
+    for tune in (False, True):
+        plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, band_threshold=0.995, band_rebuild_every=4,
+                                             flags=etd.F_SURFACE_NONLOCAL))
+        plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+        plan.step(3)
+        if tune:
+            plan.autotune(trial_steps=4)
+        plan.step(1)
+        runs.append([host(t) for t in plan.get_state(0)])
+        plan.close()
+    assert np.array_equal(runs[0][0], runs[1][0], equal_nan=True)
+    assert np.array_equal(runs[0][1], runs[1][1], equal_nan=True)

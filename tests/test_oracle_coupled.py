@@ -430,3 +430,54 @@ def test_ok_energy_first_variation_is_the_model_ok_rhs():
         num = _directional_derivative(one)
         ref = core.inner(dE, psi, grid)
         assert abs(num - ref) <= 1e-7 * abs(ref), (name, num, ref)
+
+
+def test_splitting_identities_in_two_dimensions():
+    """The splitting of Section 3.1 on a 2D grid (the scheme is written for
+    d = 2, 3): -l_phi phi^ + R1^ equals eqn:model_force/mu written directly
+    and -l_u (g u)^ + R2^ equals the right-hand side of eqn:model_OK, for two
+    stabilizer pairs each."""
+    ci = inputs.coupled_membrane_2d(n=32, seed=21, R0=0.5, eps_pm_in_h=1.5, half_len=1.0, u_mask_pm=0.99)
+    grid = Grid(ci.shape, ci.half_len)
+    o = oracle_for(ci, grid)
+    ref = core.fft(direct_phi_rhs(ci.phi0, ci.u0, ci.params, grid, o.A0))
+    for A1, A2 in ((20.0, 50.0), (0.0, 0.0)):
+        p2 = copy.copy(ci.params)
+        p2.A1, p2.A2 = A1, A2
+        o2 = CoupledOracle(grid, p2, ci.tau, 2)
+        o2.set_state(ci.phi0, ci.u0)
+        lhs = -o2.lphi * o2.phi_hat + o2.R1_hat(o2.phi_hat, ci.u0)
+        assert np.abs(lhs - ref).max() <= 1e-10 * np.abs(ref).max()
+    rng = np.random.default_rng(8)
+    v = [0.3 * rng.standard_normal(grid.n) for _ in range(2)]
+    g = core.g_loc(ci.phi0)
+    refu = core.fft(direct_u_rhs(ci.u0, g, v, ci.params, grid))
+    for B1, B2 in ((1.0, 1000.0), (0.0, 0.0)):
+        p2 = copy.copy(ci.params)
+        p2.B1, p2.B2 = B1, B2
+        o2 = CoupledOracle(grid, p2, ci.tau, 2)
+        lhs = -o2.lu * core.fft(g * ci.u0) + o2.R2_hat(ci.u0, g, v)
+        assert np.abs(lhs - refu).max() <= 1e-10 * np.abs(refu).max()
+
+
+def test_velocity_of_a_translating_wave_in_two_dimensions():
+    """As the 3D pin: v of phi = 0.5 + 0.4 sin(m.x - c|m| t) tends to c m/|m|."""
+    n, X = 32, math.pi
+    grid = Grid((n, n), (X, X))
+    ci = inputs.coupled_membrane_2d(n=n, half_len=X)
+    mv = np.array([2.0, 1.0])
+    nrm = float(np.linalg.norm(mv))
+    c = 0.7
+    x = inputs.mesh(grid.n, grid.half_len)
+    s = mv[0] * x[0] + mv[1] * x[1]
+    errs = []
+    for tau in (1e-3, 5e-4):
+        o = CoupledOracle(grid, ci.params, tau, 2)
+        pn = s - c * nrm * tau
+        v = o.velocity(0.5 + 0.4 * np.sin(s), core.fft(0.5 + 0.4 * np.sin(pn)), core.g_loc(0.5 + 0.4 * np.sin(pn)))
+        sel = np.abs(np.cos(pn)) > 0.3
+        along = (v[0] * mv[0] + v[1] * mv[1]) / nrm
+        across = (-v[0] * mv[1] + v[1] * mv[0]) / nrm
+        assert np.abs(across[sel]).max() <= 1e-10 * c
+        errs.append(float(np.abs(along[sel] - c).max()))
+    assert errs[-1] <= 2.0 * c * c * nrm * 5e-4 and 1.8 < errs[0] / errs[1] < 2.2, errs

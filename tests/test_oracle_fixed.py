@@ -332,3 +332,48 @@ def test_stabilizer_constants_of_the_64sq_circle():
     assert abs(C - 0.1678365) < 1e-6
     assert abs(fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, C, grid.volume) - 16472.66) < 0.01
     assert abs(fixed.B_es(fi.eps_u, fi.gamma, fi.M, C, grid.volume) - 11409.81) < 0.01
+
+
+def test_band_step_on_a_band_holding_every_node_is_the_full_step():
+    """The restricted step with a band that holds every node (threshold below
+    min g) is the full-grid step, bit for bit."""
+    fi, grid, p, _ = small_case(n=16)
+    pb = fixed.FixedParams(p.eps_u, p.gamma, p.M, p.ubar, p.B, band_step=0.5 * float(fi.g.min()))
+    for scheme in (1, 2):
+        a = fixed.step(fi.u0, fi.g, p, grid, fi.tau, scheme, fixed.DenseExpo(fi.g, p, grid))
+        b = fixed.step(fi.u0, fi.g, pb, grid, fi.tau, scheme, fixed.DenseExpo(fi.g, pb, grid))
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_band_step_keeps_the_theorems_and_the_off_band_values(scheme):
+    """The step restricted to {g >= 1e-3} (faces with both nodes on the band):
+    H on the band is symmetric positive semidefinite with H sqrt(g) = 0 on
+    its rows (the properties the proofs of Lemma lemma:LuPD and Theorems
+    thm:MBP, thm:Energy use), so with B = B_MBP the band system keeps
+    0 <= U <= 1 and a non-increasing energy; U off the band never changes."""
+    fi = inputs.fixed_membrane(dim=2, n=32, eps_pm_in_h=2.0, tau=0.01, seed=13)
+    grid = Grid(fi.shape, fi.half_len)
+    C = core.lapinv_inf_norm(grid)
+    B = fixed.B_mbp(fi.eps_u, fi.gamma, fi.M, C, grid.volume)
+    p = fixed.FixedParams(fi.eps_u, fi.gamma, fi.M, fi.ubar, B, band_step=1e-3)
+    band = fixed.step_band(fi.g, p)
+    assert 0 < band.sum() < band.size
+    n = band.size
+    eye = np.eye(n).reshape((n,) + fi.shape)
+    H = fixed.H_apply(eye, fi.g, grid, band).reshape(n, n).T
+    assert np.abs(H - H.T).max() <= 1e-12 * np.abs(H).max()
+    Hb = H[np.ix_(band.ravel(), band.ravel())]
+    assert np.linalg.eigvalsh(0.5 * (Hb + Hb.T)).min() >= -1e-9 * np.abs(Hb).max()
+    assert np.abs(fixed.H_apply(np.sqrt(fi.g), fi.g, grid, band)).max() <= 1e-9 * np.abs(H).max()
+    ex = fixed.UspaceExpo(fi.g, p, grid, fi.tau)
+    U = fi.u0.copy()
+    E0 = fixed.energy(U, fi.g, p, grid)["E"]
+    for _ in range(12):
+        U1 = fixed.step(U, fi.g, p, grid, fi.tau, scheme, ex)
+        assert np.array_equal(U1[~band], fi.u0[~band])
+        assert U1.min() >= -1e-14 and U1.max() <= 1.0 + 1e-14
+        E1 = fixed.energy(U1, fi.g, p, grid)["E"]
+        assert E1 <= E0 + 1e-13 * abs(E0)
+        U, E0 = U1, E1
+    assert np.abs(U - fi.u0)[band].max() > 1e-6     # the band moved
