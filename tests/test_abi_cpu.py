@@ -45,7 +45,7 @@ def _desc(model=etd.COUPLED, shape=(16, 16, 16), tau=1e-4, scheme=2, prec=0):
     (lambda d: setattr(d[0], "grid", etd.make_grid((15, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
     (lambda d: setattr(d[0], "grid", etd.make_grid((20, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
     (lambda d: setattr(d[0], "grid", etd.make_grid((1024, 16, 16), (1, 1, 1))), etd.ETD_E_SIZE),
-    (lambda d: setattr(d[0], "grid", etd.make_grid((16, 16), (1, 1))), etd.ETD_E_ARG),   # coupled is 3D
+    (lambda d: setattr(d[0], "grid", etd.make_grid((16, 15), (1, 1))), etd.ETD_E_SIZE),   # odd 2D length
     (lambda d: setattr(d[0].grid, "dim", 4), etd.ETD_E_ARG),
     (lambda d: setattr(d[0], "model", 7), etd.ETD_E_ARG),
     (lambda d: setattr(d[0], "scheme", 3), etd.ETD_E_ARG),
@@ -54,7 +54,8 @@ def _desc(model=etd.COUPLED, shape=(16, 16, 16), tau=1e-4, scheme=2, prec=0):
     (lambda d: setattr(d[0].coupled.contents, "gamma", float("inf")), etd.ETD_E_ARG),
     (lambda d: setattr(d[0], "recover_threshold", -1.0), etd.ETD_E_ARG),
     (lambda d: (setattr(d[0], "band_threshold", 0.995), setattr(d[0], "band_rebuild_every", 0)), etd.ETD_E_ARG),
-    (lambda d: setattr(d[0], "flags", 0x8), etd.ETD_E_ARG),                               # unknown flag bit
+    (lambda d: setattr(d[0], "flags", 0x10), etd.ETD_E_ARG),                              # unknown flag bit
+    (lambda d: setattr(d[0], "flags", etd.F_BAND_STEP), etd.ETD_E_ARG),                   # fixed model only
     (lambda d: setattr(d[0], "flags", etd.F_SURFACE_NONLOCAL), etd.ETD_E_ARG),            # band solve without a band
 ])
 def test_plan_create_rejects_invalid_descriptors(mutate, status):
