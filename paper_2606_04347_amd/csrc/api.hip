@@ -467,11 +467,12 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
                                  &I.surf_last, s);
     };
     if (g.nx > 1) {
-        // q formed in the load of the nonlocal transform (with m); P2 and g+ u in the load of the pair
+        // q formed in the load of the nonlocal transform (with m), whose last (z)
+        // pass runs inside the P2 pass; P2 and g+ u in the load of the pair
         e = surface ? surface_psi()
-                    : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Sa, v.psi, grid_sum(I, S_MASS), s);
+                    : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Stmp, nullptr, grid_sum(I, S_MASS), s);
         if (e != hipSuccess) return e;
-        const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS};
+        const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS, surface ? nullptr : v.Stmp};
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
         if (e != hipSuccess) return e;
         return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, halt_flag(I), s);

@@ -27,6 +27,28 @@ __device__ __forceinline__ double phi2d(double z) {
     return fabs(z) < 0.1 ? phi_taylor(z, 2) : (expm1(-z) + z) / (z * z);
 }
 
+// The FP32 path forms the same values in FP64 from a single exponential
+// e = e^{-z}: phi1 = (1 - e)/z and phi2 = (z - 1 + e)/z^2 for z >= 0.1, the
+// series below.  The cancellation there costs at most a factor ~1/(1 - e^{-0.1})
+// = 10.5 (phi1) or ~2/0.1^2 = 200 (phi2) of FP64 precision, below 1e-13
+// relative: far under the FP32 rounding of the result.
+struct PhiE {
+    double e0, p1, p2;
+};
+template <int K> __device__ __forceinline__ PhiE phi_one_exp(double z) {
+    PhiE r;
+    r.e0 = exp(-z);
+    if (fabs(z) < 0.1) {
+        if constexpr (K & 1) r.p1 = phi_taylor(z, 1);
+        if constexpr (K & 2) r.p2 = phi_taylor(z, 2);
+    } else {
+        const double iz = 1.0 / z;
+        if constexpr (K & 1) r.p1 = (1.0 - r.e0) * iz;
+        if constexpr (K & 2) r.p2 = ((z - 1.0) + r.e0) * (iz * iz);
+    }
+    return r;
+}
+
 // linear symbols (eqn:linear_force and the u equation)
 __device__ __forceinline__ double lphi(const CoupledK& K, double k2) { return (K.lp4 * k2 + K.lp2) * k2 + K.lp0; }
 __device__ __forceinline__ double lu(const CoupledK& K, double k2) { return K.B2 + K.eps_u * K.B1 * k2; }
@@ -52,7 +74,15 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     if constexpr (ST == ETD_STAGE_PHI1) {
         // R = P - c1 k^2 Q;  phi~ = e^{-tau l} phi^n + tau phi1(tau l) R
         const double z = K.tau * lphi(K, k2);
-        const T e0 = (T)exp(-z), te1 = (T)(K.tau * phi1d(z));
+        T e0, te1;
+        if constexpr (sizeof(T) == 4) {
+            const PhiE f = phi_one_exp<1>(z);
+            e0 = (T)f.e0;
+            te1 = (T)(K.tau * f.p1);
+        } else {
+            e0 = exp(-z);
+            te1 = K.tau * phi1d(z);
+        }
         const T ck = (T)(K.c1 * k2);
         const c2<T> f = a.prev[i];
         const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
@@ -61,7 +91,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     } else if constexpr (ST == ETD_STAGE_PHI2) {
         // phi^{n+1} = phi~ + tau phi2(tau l) (R~ - R)
         const double z = K.tau * lphi(K, k2);
-        const T te2 = (T)(K.tau * phi2d(z));
+        const T te2 = (T)(K.tau * (sizeof(T) == 4 ? phi_one_exp<2>(z).p2 : phi2d(z)));
         const T ck = (T)(K.c1 * k2);
         const c2<T> t = a.prev[i], ra = a.ra[i];
         const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
@@ -70,7 +100,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
         // R = P + eps_u B1 k^2 GU;  D = tau phi1(tau l_u) (R - l_u GU)  (GU~ - GU^n)
         const double l = lu(K, k2);
         const double z = K.tau * l;
-        const T te1 = (T)(K.tau * phi1d(z));
+        const T te1 = (T)(K.tau * (sizeof(T) == 4 ? phi_one_exp<1>(z).p1 : phi1d(z)));
         const T ck = (T)(K.eps_u * K.B1 * k2), lt = (T)l;
         const c2<T> R = mk<T>(p.x + ck * q.x, p.y + ck * q.y);
         a.ra[i] = R;
@@ -78,7 +108,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
     } else {
         // D <- D + tau phi2(tau l_u) (R~ - R)
         const double z = K.tau * lu(K, k2);
-        const T te2 = (T)(K.tau * phi2d(z));
+        const T te2 = (T)(K.tau * (sizeof(T) == 4 ? phi_one_exp<2>(z).p2 : phi2d(z)));
         const T ck = (T)(K.eps_u * K.B1 * k2);
         const c2<T> d = a.out[i], ra = a.ra[i];
         const T dx = (p.x + ck * q.x) - ra.x, dy = (p.y + ck * q.y) - ra.y;

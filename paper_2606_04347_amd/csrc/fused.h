@@ -60,11 +60,15 @@ template <typename T> struct R1Fields {
 };
 // Sources of P2 (Section 3.1): u, G = g+, the velocity, psi = the nonlocal
 // inverse of q ((-Delta_h)^{-1} by FFT, or the band solve), the band mask
-// (nullable) and the device scalar m = h^3 sum q.
+// (nullable) and the device scalar m = h^3 sum q.  With psi_hat != null,
+// psi is taken from that spectrum instead (psi's half spectrum after the
+// inverse x and y passes, the output of lapinv_q_fused with psi == null):
+// the z pass of P2 runs psi's inverse z transform into its LDS first.
 template <typename T> struct P2Fields {
     const T *u, *G, *vx, *vy, *vz, *psi;
     const uint8_t* mask;
     const double* m;
+    const c2<T>* psi_hat = nullptr;
 };
 
 // fwd_pair_etd with the pair (P1, W'(phi) - A1 phi) formed from its sources
@@ -89,7 +93,9 @@ hipError_t lapinv_fused(const GridK& g, const FFTTables<T>& t, const double* fd,
 // The same for q = G (u - ubar) on the band (mask nullable) formed in the load
 // of the z pass, which also forms the mass h^d sum q into msum.out (block
 // partials in msum.part, at most nx * ny / 8 doubles, then a fixed-order
-// final sum).
+// final sum).  With psi == null (three-dimensional grids) the last (z) pass
+// is left out: W holds psi's half spectrum after the inverse x and y passes,
+// for P2Fields::psi_hat.
 template <typename T>
 hipError_t lapinv_q_fused(const GridK& g, const FFTTables<T>& t, const double* fd, double ubar, const T* u,
                           const T* G, const uint8_t* mask, c2<T>* W, T* psi, const GridSum& msum, hipStream_t s);

@@ -445,6 +445,17 @@ template <typename T, int L> struct R1PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
+        if (mask && mask[c + o] == 0 && mask[c + o + 1] == 0) {
+            // both points off the band: the |grad phi|-weighted terms are 0, so
+            // P1 needs phi and its Laplacian alone (no u, no stencil)
+            const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o);
+            T P0, Q0, P1, Q1;
+            r1_core(k, p.x, L2.x, &P0, &Q0);
+            r1_core(k, p.y, L2.y, &P1, &Q1);
+            v[0] = mk<T>(P0, P1);
+            v[1] = mk<T>(Q0, Q1);
+            return;
+        }
         const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o), gg = ld2(gn + c + o), uu = ld2(u + c + o);
         const c2<T> pxm = ld2(phi + rt->xm[l] + o), pxp = ld2(phi + rt->xp[l] + o), pym = ld2(phi + rt->ym[l] + o),
                     pyp = ld2(phi + rt->yp[l] + o);
@@ -474,7 +485,9 @@ template <typename T, int L> struct R1PairLoad {
     __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
 };
 
-// (P2, g+ u) at the point pair (2e, 2e + 1) of row l.
+// (P2, g+ u) at the point pair (2e, 2e + 1) of row l; psi from memory, or
+// with psl != null from the pairs of the tile's rows in the LDS (row l at
+// l * NR / 2).
 template <typename T, int L> struct P2PairLoad {
     static constexpr int NS = 2;
     const RowTile<L>* rt;
@@ -482,13 +495,22 @@ template <typename T, int L> struct P2PairLoad {
     const T *u, *G, *vx, *vy, *vz, *psi;
     const uint8_t* mask;
     P2Const<T> k;
+    const c2<T>* psl;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
         if (l >= nl) {
             v[0] = v[1] = mk<T>(0, 0);
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o), ps = ld2(psi + c + o), wz = ld2(vz + c + o);
+        if (mask && mask[c + o] == 0 && mask[c + o + 1] == 0) {
+            // both points off the band: P2 is 0 there; g+ u alone is formed
+            const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o);
+            v[0] = mk<T>(0, 0);
+            v[1] = mk<T>(GG.x * uu.x, GG.y * uu.y);
+            return;
+        }
+        const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o), wz = ld2(vz + c + o);
+        const c2<T> ps = psl ? psl[l * (nz / 2) + e] : ld2(psi + c + o);
         const c2<T> uxm = ld2(u + rt->xm[l] + o), uxp = ld2(u + rt->xp[l] + o), uym = ld2(u + rt->ym[l] + o),
                     uyp = ld2(u + rt->yp[l] + o);
         const c2<T> Gxm = ld2(G + rt->xm[l] + o), Gxp = ld2(G + rt->xp[l] + o), Gym = ld2(G + rt->ym[l] + o),
@@ -593,24 +615,49 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, cons
     zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
 }
 
-template <typename T, int NR>
+// The pairs of an inverse z transform kept in the LDS (row l at l * M).
+template <typename T, int M> struct LdsPairStore {
+    static constexpr int NS = 1;
+    c2<T>* dst;
+    T scale;
+    __device__ __forceinline__ void load(int, int, c2<T>*) const {}
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const { dst[l * M + e] = cscale(v, scale); }
+};
+
+// Dynamic LDS of the P2 z pass: the two-field forward, and with psi from its
+// spectrum (PSI_HAT) the tile's psi pairs after it.
+template <typename T, int NR, bool PSI_HAT> constexpr size_t z_smem_p2() {
+    return z_smem2<T, NR>() + (PSI_HAT ? sizeof(c2<T>) * (size_t)z_rows_pair<T, NR>() * (NR / 2) : 0);
+}
+
+template <typename T, int NR, bool PSI_HAT>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
-                                                       const T* vy, const T* vz, const T* psi, const double* m,
+                                                       const T* vy, const T* vz, const T* psi,
+                                                       const c2<T>* psi_hat, T psi_scale, const double* m,
                                                        const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
     constexpr int L = z_rows_pair<T, NR>();
     constexpr int MS = NR / 2 + 1;
+    constexpr int M = NR / 2;
     extern __shared__ unsigned char smem_raw[];
     __shared__ RowTile<L> rt;
     c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
     c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
+    c2<T>* psl = PSI_HAT ? stw + M : nullptr;   // the tile's psi pairs
+    load_table<T>(stw, twh, M);
     const long row0 = (long)blockIdx.x * L;
     const int nl = (int)min((long)L, nrows - row0);
     row_tile_setup<L>(rt, g, row0);
+    if constexpr (PSI_HAT) {
+        // psi of the tile's rows: inverse z transform of its spectrum into the LDS
+        c2<T> pre[z_fetch_count<T, NR, L>()];
+        zrow_fetch<T, NR, L>(pre, psi_hat + row0 * MS, nl);
+        zrow_put<T, NR, false, L>(lds, pre, 0.0);
+        zrow_inverse_lds<T, NR, LdsPairStore<T, M>, L>(lds, stw, twf, LdsPairStore<T, M>{psl, psi_scale});
+    }
     __syncthreads();
-    const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0])};
+    const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0]), psl};
     zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
 }
 
@@ -887,12 +934,22 @@ template <typename T, int NR>
 hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ,
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows_pair<T, NR>();
-    const size_t smem = z_smem2<T, NR>();
-    static std::once_flag flag;
-    set_smem_limit(k_z_r2c_p2<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
-    hipLaunchKernelGGL((k_z_r2c_p2<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.u,
-                       f.G, f.vx, f.vy, f.vz, f.psi, f.m, f.mask, WP, WQ, twh, twf, nrows);
+    const dim3 grid((int)((nrows + L - 1) / L));
+    const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
+    if (f.psi_hat) {
+        const size_t smem = z_smem_p2<T, NR, true>();
+        static std::once_flag flag;
+        set_smem_limit(k_z_r2c_p2<T, NR, true>, smem, flag);
+        hipLaunchKernelGGL((k_z_r2c_p2<T, NR, true>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
+                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
+    } else {
+        const size_t smem = z_smem_p2<T, NR, false>();
+        static std::once_flag flag;
+        set_smem_limit(k_z_r2c_p2<T, NR, false>, smem, flag);
+        hipLaunchKernelGGL((k_z_r2c_p2<T, NR, false>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
+                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
+    }
     return hipGetLastError();
 }
 template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
@@ -1093,7 +1150,9 @@ hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
     const double mb = f.mask ? (double)g.nreal() : 0.0;
-    hipError_t e = timed_pass(PASS_Z_R2C_P2, 6.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
+    // with psi from its spectrum the pass reads that spectrum in place of psi
+    hipError_t e = timed_pass(PASS_Z_R2C_P2, (f.psi_hat ? 5.0 * rb + cb : 6.0 * rb) + mb + 2.0 * cb, s,
+                              [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
     case n: return launch_z_p2<T, n>(g, K, f, WP, WQ, t.tzh, t.tzf, s);
@@ -1144,6 +1203,8 @@ hipError_t lapinv_after_z(const GridK& g, const FFTTables<T>& t, const double* f
         });
         if (e != hipSuccess) return e;
     }
+    // psi == null (three-dimensional grids): the z pass is left to the P2 pass
+    if (!psi) return g.nx > 1 ? hipSuccess : hipErrorInvalidValue;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     return fft_pass_z<T>(g, t, false, W, psi, scale, s);
 }

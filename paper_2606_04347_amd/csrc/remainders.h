@@ -51,6 +51,14 @@ template <typename T> struct R1Const {
 // (phi, its spectral Laplacian L, the norm gn = |grad phi| of its spectral
 // gradient, u), the six neighbours of u and phi (x-, x+, y-, y+, z-, z+), and
 // the band flag.  P1 sees the gradient only through its norm.
+// The part of P1 and Q that does not involve u or |grad phi| (a point off the band).
+template <typename T> __device__ __forceinline__ void r1_core(const R1Const<T>& k, T pc, T L, T* P, T* Q) {
+    const T wp = Wp(pc), wpp = Wpp(pc);
+    const T q1 = wp - k.A1 * pc;
+    *P = k.c1 * (wpp - k.A2) * (L - k.A1 * pc / k.e2) - (k.cW * wpp + k.cs) * q1;
+    *Q = q1;
+}
+
 template <typename T>
 __device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
                                          const T (&pn)[6], bool band, T* P, T* Q) {

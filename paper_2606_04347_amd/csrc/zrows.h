@@ -138,18 +138,22 @@ __device__ __forceinline__ void zrow_forward2(c2<T>* lds, const c2<T>* stw, cons
 }
 
 // ---- inverse, in three steps so that a kernel with several outputs can fetch
-// the next input while the current one is transformed.
-template <typename T, int NR> constexpr int z_fetch_count() { return (z_rows<T, NR>() * (NR / 2 + 1) + kThreads - 1) / kThreads; }
-template <typename T, int NR> using ZPre = c2<T>[z_fetch_count<T, NR>()];   // the fetched tile of a thread
+// the next input while the current one is transformed.  L: rows of the tile
+// (z_rows by default; the two-field passes take z_rows_pair).
+template <typename T, int NR, int L = z_rows<T, NR>()> constexpr int z_fetch_count() {
+    return (L * (NR / 2 + 1) + kThreads - 1) / kThreads;
+}
+template <typename T, int NR, int L = z_rows<T, NR>()>
+using ZPre = c2<T>[z_fetch_count<T, NR, L>()];   // the fetched tile of a thread
 
 // Half-spectrum rows of a tile (nl <= L rows of M + 1 values) into registers;
 // element idx = threadIdx.x + p * kThreads of the row-major tile.
-template <typename T, int NR>
-__device__ __forceinline__ void zrow_fetch(ZPre<T, NR>& pre, const c2<T>* src, int nl) {
+template <typename T, int NR, int L = z_rows<T, NR>()>
+__device__ __forceinline__ void zrow_fetch(ZPre<T, NR, L>& pre, const c2<T>* src, int nl) {
     constexpr int MS = NR / 2 + 1;
-    constexpr int TOT = z_rows<T, NR>() * MS;
+    constexpr int TOT = L * MS;
 #pragma unroll
-    for (int p = 0; p < z_fetch_count<T, NR>(); ++p) {
+    for (int p = 0; p < z_fetch_count<T, NR, L>(); ++p) {
         const int idx = threadIdx.x + p * kThreads;
         pre[p] = (idx < TOT && idx / MS < nl) ? src[idx] : mk<T>(0, 0);
     }
@@ -157,13 +161,13 @@ __device__ __forceinline__ void zrow_fetch(ZPre<T, NR>& pre, const c2<T>* src, i
 
 // Registers -> LDS rows, times i kz (kz = az * derivative index of k, Nyquist
 // bin 0) if DZ.  The LDS rows must be free (callers barrier first).
-template <typename T, int NR, bool DZ>
-__device__ __forceinline__ void zrow_put(c2<T>* lds, const ZPre<T, NR>& pre, double az) {
+template <typename T, int NR, bool DZ, int L = z_rows<T, NR>()>
+__device__ __forceinline__ void zrow_put(c2<T>* lds, const ZPre<T, NR, L>& pre, double az) {
     constexpr int MS = NR / 2 + 1;
-    constexpr int TOT = z_rows<T, NR>() * MS;
+    constexpr int TOT = L * MS;
     constexpr int LS = z_row_stride<NR>();
 #pragma unroll
-    for (int p = 0; p < z_fetch_count<T, NR>(); ++p) {
+    for (int p = 0; p < z_fetch_count<T, NR, L>(); ++p) {
         const int idx = threadIdx.x + p * kThreads;
         if (idx < TOT) {
             const int r = idx / MS, k = idx % MS;
@@ -181,11 +185,10 @@ __device__ __forceinline__ void zrow_put(c2<T>* lds, const ZPre<T, NR>& pre, dou
 // inverse half-length transform -> Op::store(row, 0, n, z_n) with z_n the
 // unscaled pair (x_{2n}, x_{2n+1}).  The imaginary parts of the k = 0 and
 // k = M bins are ignored.
-template <typename T, int NR, class Op>
+template <typename T, int NR, class Op, int L = z_rows<T, NR>()>
 __device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, const c2<T>* __restrict__ twf,
                                                  const Op& op) {
     constexpr int M = NR / 2;
-    constexpr int L = z_rows<T, NR>();
     constexpr int LS = z_row_stride<NR>();
     __syncthreads();
     // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) w^{-k}; each thread owns
