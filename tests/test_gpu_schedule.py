@@ -168,3 +168,49 @@ def test_autotune_between_band_rebuilds_restores_the_band_list():
         plan.close()
     assert np.array_equal(runs[0][0], runs[1][0], equal_nan=True)
     assert np.array_equal(runs[0][1], runs[1][1], equal_nan=True)
+
+
+@pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
+def test_uneven_batch_matches_oracle(precision):
+    """An uneven batch shaped like the sweep's instance mix -- grid lengths 32,
+    48 (radix 3) and a 96-length axis, per-instance seeds, coefficients and
+    tau in {5e-5, 1e-4} (inputs.batch_sweep's draws) -- stepped under the
+    graph schedule with concurrent branches, each instance against the FP64
+    oracle: within 1e-12 (FP64) or under the FP32 comparison of
+    test_gpu_coupled (flip set counted, u and g u within 1e-4)."""
+    from gpu_util import recovery_flips, rel_linf, u_gap_outside_flips
+    from oracle.core import Grid
+    from oracle.coupled import CoupledOracle
+    cis = inputs.batch_sweep(counts=((32, 2), (48, 1), ((16, 96, 16), 1)))
+    assert {ci.tau for ci in cis} <= {5e-5, 1e-4}
+    plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=precision) for ci in cis])
+    dt = torch.float64 if precision == etd.FP64 else torch.float32
+    for i, ci in enumerate(cis):
+        plan.set_state(i, dev(ci.phi0, dt), dev(ci.u0, dt))
+    plan.set_schedule(etd.EXEC_GRAPH, 2)
+    oracles = []
+    for ci in cis:
+        o = CoupledOracle(Grid(ci.shape, ci.half_len), ci.params, ci.tau, etd.ETDRK2)
+        o.set_state(ci.phi0, ci.u0)
+        oracles.append(o)
+    flips = [np.zeros(ci.shape, dtype=bool) for ci in cis]
+    nsteps = 4
+    for k in range(nsteps // 2):       # two steps per replay: compare every second step
+        plan.step(2)
+        for i, o in enumerate(oracles):
+            o.run(2)
+            if precision == etd.FP32:
+                flips[i] |= recovery_flips(host(plan.get_state(i, torch.float32)[0]), o.phi())
+    for i, (ci, o) in enumerate(zip(cis, oracles)):
+        phi, u = (host(t) for t in plan.get_state(i))
+        ephi = rel_linf(phi, o.phi())
+        if precision == etd.FP64:
+            eu = rel_linf(u, o.u)
+            report("batch_oracle", precision=precision, shape=str(ci.shape), tau=ci.tau, err_phi=ephi, err_u=eu)
+            assert ephi <= 1e-12 and eu <= 1e-12
+        else:
+            eu, near, egu, _ = u_gap_outside_flips(u, o.u, o.phi(), flips[i])
+            report("batch_oracle", precision=precision, shape=str(ci.shape), tau=ci.tau, err_phi=ephi, err_u=eu,
+                   err_gu=egu, flips=int(flips[i].sum()))
+            assert ephi <= 1e-4 and eu <= 1e-4 and egu <= 1e-4
+    plan.close()
