@@ -116,8 +116,10 @@ typedef struct {
                                       etd_set_state; FP64 on both of its paths.  The solve
                                       checks convergence on the host, so plans with this flag
                                       step eagerly under every schedule.  Each in-step solve
-                                      runs to a relative residual of 1e-9 (FP32 coupled
-                                      instances) or 1e-12, at most 20000 iterations; one that
+                                      starts from the previous solve's result (the first one
+                                      after etd_set_state from 0) and runs to a residual of
+                                      1e-9 (FP32 coupled instances) or 1e-12 relative to the
+                                      right-hand side, at most 20000 iterations; one that
                                       stops at the cap is not an error: the step goes on with
                                       its last iterate, and ETD_Q_SURF_ITERS /
                                       ETD_Q_SURF_RELRES report the last solve.  The energy
@@ -343,7 +345,8 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
  * are device arrays in the grid layout of the instance, element type dtype
  * (psi may alias f).  FP64 conjugate gradients from psi = 0, preconditioned
  * by a 16-term Chebyshev polynomial of the Jacobi-scaled operator, until the
- * relative residual is <= tol or after max_iter iterations; *iters_out and
+ * residual relative to f - mean_band(f) is <= tol or after max_iter
+ * iterations (f constant on the band: psi = 0 at once); *iters_out and
  * *relres_out (host, nullable) report the outcome -- not converging is
  * reported there, not as an error.
  * Uses a workspace of about 92 bytes per grid point, allocated on the first

@@ -144,12 +144,14 @@ etd_status dalloc(etd_plan* P, Instance& I, size_t bytes, void** out) {
         ptr = reinterpret_cast<decltype(ptr)>(tmp_);                      \
     } while (0)
 
-// Workspace of the band solve, allocated once per instance.
+// Workspace of the band solve, allocated once per instance; its iterate
+// starts at 0 (the first warm-started solve starts cold).
 etd_status ensure_surface(etd_plan* P, Instance& I) {
     if (I.surf) return ETD_OK;
     const long n = I.g.nreal();
     ALLOC(I.surf, surface_work_bytes(n));
     surface_work_carve(n, I.surf, I.sw);
+    HIPCHK(P, hipMemsetAsync(I.sw.x, 0, sizeof(double) * (size_t)n, P->stream));
     return ETD_OK;
 }
 
@@ -463,7 +465,7 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
             coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, nullptr, I.part, I.scal + S_MASS, halt_flag(I), s);
         });
         const double tol = I.f32 ? 1e-9 : 1e-12;
-        return surface_lapinv<T>(g, v.gp, v.P, mask, I.band_idx, I.band_total, v.psi, I.sw, tol, 20000,
+        return surface_lapinv<T>(g, v.gp, v.P, mask, I.band_idx, I.band_total, v.psi, I.sw, tol, 20000, true,
                                  &I.surf_last, s);
     };
     if (g.nx > 1) {
@@ -559,7 +561,7 @@ etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStrea
     const GridK& g = I.g;
     if (I.d.flags & ETD_F_SURFACE_NONLOCAL) {
         HIPCHK(plan, surface_lapinv<double>(g, I.G, q, I.mask, I.band_idx, I.band_total, I.psid, I.sw, 1e-12, 20000,
-                                            &I.surf_last, s));
+                                            true, &I.surf_last, s));
     } else if (!I.f32) {
         HIPCHK(plan, lapinv_fused<double>(g, I.td, I.fd, q, (double2*)I.Sa, I.psid, s));
     } else {
@@ -835,6 +837,8 @@ etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const voi
     else
         st = set_state_fixed(plan, I, a, u, dtype);
     if (st != ETD_OK) return st;
+    // the band solves of a new state start cold, so a run depends on its state alone
+    if (I.surf) HIPCHK(plan, hipMemsetAsync(I.sw.x, 0, sizeof(double) * (size_t)I.g.nreal(), plan->stream));
     I.step = 0;
     I.has_state = true;
     drop_graphs(plan);   // captured kernel arguments (A0, Chebyshev coefficients) may have changed
@@ -1161,9 +1165,9 @@ etd_status etd_surface_lapinv(etd_plan_t plan, int instance, const void* g, cons
     SurfaceResult r;
     hipError_t e = dtype == ETD_F64
                        ? surface_lapinv<double>(I.g, (const double*)g, (const double*)f, mask, w.idx, w.total,
-                                                (double*)psi, w, tol, max_iter, &r, s)
+                                                (double*)psi, w, tol, max_iter, false, &r, s)
                        : surface_lapinv<float>(I.g, (const float*)g, (const float*)f, mask, w.idx, w.total,
-                                               (float*)psi, w, tol, max_iter, &r, s);
+                                               (float*)psi, w, tol, max_iter, false, &r, s);
     HIPCHK(plan, e);
     if (iters_out) *iters_out = r.iters;
     if (relres_out) *relres_out = r.relres;

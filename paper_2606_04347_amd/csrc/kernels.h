@@ -184,12 +184,15 @@ struct SurfaceResult {
 template <typename T> void band_ge(long n, const T* G, double delta, uint8_t* mask, hipStream_t s);
 size_t surface_work_bytes(long n);
 void surface_work_carve(long n, void* base, SurfaceWork& w);
-// psi = (-Delta_S,h)^{-1} f on the band (0 off it); stops when the relative
-// residual reaches tol or after max_iter iterations.  Synchronizes the stream
-// every 25 iterations (convergence check); res (nullable) gets the outcome.
+// psi = (-Delta_S,h)^{-1} f on the band (0 off it); stops when the residual
+// relative to f - mean_band(f) reaches tol or after max_iter iterations.
+// warm: start from w.x as the previous solve left it (its result on its band,
+// 0 elsewhere; all 0 before the first solve), else from 0.  Synchronizes the
+// stream every 25 iterations (convergence check); res (nullable) gets the
+// outcome.
 template <typename T>
 hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t* mask, const int32_t* idx,
-                          const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter,
+                          const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter, bool warm,
                           SurfaceResult* res, hipStream_t s);
 
 // Compact flagged indices in ascending order.  blockcnt: scratch of band_blocks(n) + 1 int64.

@@ -195,6 +195,7 @@ etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
     } else {
         v.parts.push_back({I.U, n * sizeof(double)});
     }
+    if (I.surf) v.parts.push_back({I.sw.x, n * sizeof(double)});   // the start of the next band solve
     size_t total = 0;
     for (const auto& pr : v.parts) total += (pr.second + 255) & ~(size_t)255;
     if (hipMalloc(&v.base, total) != hipSuccess) {

@@ -48,9 +48,9 @@ constexpr int kChebTerms = 16;
 constexpr double kChebRatio = 1000.0;
 
 enum SbSlot {
-    SB_GAMMA = 0, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_COUNT
+    SB_GAMMA = 0, SB_RR, SB_RR0, SB_ALPHA, SB_BETA, SB_DONE, SB_ITER, SB_MEAN, SB_XMEAN, SB_BB, SB_COUNT
 };
-enum SbFinal { FIN_MEAN = 0, FIN_START, FIN_STEP, FIN_XMEAN };
+enum SbFinal { FIN_MEAN = 0, FIN_BNORM, FIN_START, FIN_STEP, FIN_XMEAN };
 
 struct BandGeom {
     int nx, ny, nz;
@@ -77,6 +77,23 @@ template <class F> __device__ __forceinline__ void for_neighbours(const BandGeom
     if (b.nx > 1) {
         f(x + 1 < b.nx ? i + sx : i + sx - (long)b.nx * sx, b.ihx2);
         f(x > 0 ? i - sx : i - sx + (long)b.nx * sx, b.ihx2);
+    }
+}
+
+// Calls f(k) for the band positions k < nb of this workgroup.  The band is
+// cut into eight contiguous ranges of 256-position chunks, one per XCD
+// (workgroup b is dispatched to XCD b % 8), whose workgroups take the chunks
+// of their range in turn: the band neighbours of a node along y and x lie a
+// few chunks away in band order, so they are mostly read through the L2 of
+// the same XCD, in this launch and the next.
+template <class F> __device__ __forceinline__ void band_for(long nb, F f) {
+    static_assert(kSbBlocks % 8 == 0, "whole workgroups per XCD");
+    const long chunks = (nb + kSbThreads - 1) / kSbThreads;
+    const int x = (int)(blockIdx.x & 7u), per = (int)(gridDim.x >> 3);
+    const long c1 = (x + 1) * chunks / 8;
+    for (long c = x * chunks / 8 + (long)(blockIdx.x >> 3); c < c1; c += per) {
+        const long k = c * kSbThreads + threadIdx.x;
+        if (k < nb) f(k);
     }
 }
 
@@ -113,7 +130,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
                                                          double* part) {
     const long nb = *total;
     Neu acc;
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+    band_for(nb, [&](long k) {
         const long i = idx[k];
         const double gi = (double)gm[i];
         double d = 0.0;
@@ -123,7 +140,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
         });
         dinv[k] = d > 0.0 ? 1.0 / d : 0.0;
         acc.add((double)f[i]);
-    }
+    });
     store_partials(acc.val(), 0.0, 0.0, part);
 }
 
@@ -147,24 +164,42 @@ struct ChebStart {
     }
 };
 
-// r = f - mean, x = 0, p = s = 0 (band nodes), the preconditioner's first
-// term; clears the done flag of an earlier solve.
+// b = f - mean; cold start: x = 0, r = b; warm start: x as the last solve
+// left it (its result on its band, 0 elsewhere), r = b - A x.  p = s = 0
+// (band nodes), the preconditioner's first term; partials of (b, b); clears
+// the done flag of an earlier solve.
 template <typename T>
-__global__ __launch_bounds__(kSbThreads) void k_sb_init(const T* __restrict__ f, const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(kSbThreads) void k_sb_init(BandGeom bg, const T* __restrict__ gm, const T* __restrict__ f,
+                                                        const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total,
                                                         const double* __restrict__ dinv, double* S, double* x,
-                                                        double* r, double* p, double* sv, ChebStart cs) {
+                                                        double* r, double* p, double* sv, ChebStart cs, int warm,
+                                                        double* part) {
     const long nb = *total;
     const double mean = S[SB_MEAN];
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+    Neu bb;
+    band_for(nb, [&](long k) {
         const long i = idx[k];
-        const double rk = (double)f[i] - mean;
+        const double bk = (double)f[i] - mean;
+        double rk = bk;
+        if (warm) {
+            const double gi = (double)gm[i], xi = x[i];
+            double a = 0.0;
+            for_neighbours(bg, i, [&](long j, double ih2) {
+                const T gj = gm[j];
+                if (gj >= (T)0) a += 0.5 * (gi + (double)gj) * ih2 * (xi - x[j]);
+            });
+            rk = bk - a;
+        } else {
+            x[i] = 0.0;
+        }
+        bb.add(bk * bk);
         r[k] = rk;
         cs(k, i, rk, dinv[k]);
-        x[i] = 0.0;
         p[k] = 0.0;
         sv[k] = 0.0;
-    }
+    });
+    store_partials(bb.val(), 0.0, 0.0, part);
     if (blockIdx.x == 0 && threadIdx.x == 0) S[SB_DONE] = 0.0;
 }
 
@@ -180,7 +215,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __r
                                                         double* cz, double c1, double c2, int last, double* u) {
     if (sb_done(S)) return;
     const long nb = *total;
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+    band_for(nb, [&](long k) {
         const long i = idx[k];
         const double gi = (double)gm[i], di = dprev[i];
         double a = 0.0;
@@ -195,7 +230,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __r
         const double z = cz[k] + d;
         cz[k] = z;
         if (last) u[i] = z;
-    }
+    });
 }
 
 // w = A u on the band; partials (r, u), (w, u), (r, r).
@@ -208,7 +243,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* _
     if (sb_done(S)) return;
     const long nb = *total;
     Neu ru, wu, rr;
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+    band_for(nb, [&](long k) {
         const long i = idx[k];
         const double gi = (double)gm[i], ui = u[i];
         double a = 0.0;
@@ -221,7 +256,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* _
         ru.add(rk * ui);
         wu.add(a * ui);
         rr.add(rk * rk);
-    }
+    });
     store_partials(ru.val(), wu.val(), rr.val(), part);
 }
 
@@ -235,7 +270,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __rest
     if (sb_done(S)) return;
     const long nb = *total;
     const double alpha = S[SB_ALPHA], beta = S[SB_BETA];
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads) {
+    band_for(nb, [&](long k) {
         const long i = idx[k];
         const double pk = u[i] + beta * p[k];
         const double sk = w[k] + beta * sv[k];
@@ -245,7 +280,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __rest
         const double rk = r[k] - alpha * sk;
         r[k] = rk;
         cs(k, i, rk, dinv[k]);
-    }
+    });
 }
 
 // band sum of x
@@ -254,18 +289,22 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_xsum(const int32_t* __restric
                                                         const double* __restrict__ x, double* part) {
     const long nb = *total;
     Neu acc;
-    for (long k = (long)blockIdx.x * kSbThreads + threadIdx.x; k < nb; k += (long)kSbBlocks * kSbThreads)
-        acc.add(x[idx[k]]);
+    band_for(nb, [&](long k) { acc.add(x[idx[k]]); });
     store_partials(acc.val(), 0.0, 0.0, part);
 }
 
-// psi = x - mean_band(x) on the band, 0 elsewhere.
+// psi = x - mean_band(x) on the band, 0 elsewhere; x keeps the same values
+// (in FP64), the start of a warm-started next solve.
 template <typename T>
-__global__ __launch_bounds__(kSbThreads) void k_sb_out(long n, const uint8_t* __restrict__ mask,
-                                                       const double* __restrict__ x, const double* S, T* psi) {
+__global__ __launch_bounds__(kSbThreads) void k_sb_out(long n, const uint8_t* __restrict__ mask, double* x,
+                                                       const double* S, T* psi) {
     const double m = S[SB_XMEAN];
-    for (long i = (long)blockIdx.x * kSbThreads + threadIdx.x; i < n; i += (long)gridDim.x * kSbThreads)
-        psi[i] = mask[i] ? (T)(x[i] - m) : (T)0;
+    const bool zero = !(S[SB_BB] > 0.0);   // b = 0: the solution is 0 whatever x started from
+    for (long i = (long)blockIdx.x * kSbThreads + threadIdx.x; i < n; i += (long)gridDim.x * kSbThreads) {
+        const double v = (mask[i] && !zero) ? x[i] - m : 0.0;
+        x[i] = v;
+        psi[i] = (T)v;
+    }
 }
 
 // Closes the partial sums of one kernel (fixed order) and updates the step
@@ -291,13 +330,18 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_final(int mode, const double*
         case FIN_MEAN:
             S[SB_MEAN] = nb > 0 ? sa / nb : 0.0;
             break;
+        case FIN_BNORM:
+            S[SB_BB] = sa;
+            break;
         case FIN_START:
+            // the tolerance is relative to |b|, so a warm start stops where a
+            // cold one would
             S[SB_GAMMA] = sa;
             S[SB_RR] = sc;
-            S[SB_RR0] = sc;
+            S[SB_RR0] = S[SB_BB];
             S[SB_ITER] = 0.0;
             S[SB_BETA] = 0.0;
-            if (sc > 0.0 && sb > 0.0) S[SB_ALPHA] = sa / sb;
+            if (S[SB_BB] > 0.0 && sc > tol2 * S[SB_BB] && sb > 0.0) S[SB_ALPHA] = sa / sb;
             else S[SB_DONE] = 1.0;
             break;
         case FIN_STEP: {
@@ -373,7 +417,7 @@ void surface_work_carve(long n, void* base, SurfaceWork& w) { surface_layout(n, 
 template <typename T>
 hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t* mask, const int32_t* idx,
                           const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter,
-                          SurfaceResult* res, hipStream_t s) {
+                          bool warm, SurfaceResult* res, hipStream_t s) {
     const BandGeom b = band_geom(g);
     const double tol2 = tol * tol;
     const dim3 grid(kSbBlocks), blk(kSbThreads);
@@ -412,7 +456,9 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     hipLaunchKernelGGL(k_sb_gm<T>, dim3(nbo), blk, 0, s, n, G, mask, gm);
     hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, gm, f, idx, total, w.dinv, w.part);
     fin(FIN_MEAN);
-    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, f, idx, total, w.dinv, w.S, w.x, w.r, w.p, w.s, cs);
+    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, b, gm, f, idx, total, w.dinv, w.S, w.x, w.r, w.p, w.s, cs,
+                       warm ? 1 : 0, w.part);
+    fin(FIN_BNORM);
     precond();
     matvec();
     fin(FIN_START);
@@ -450,10 +496,10 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
 }
 
 template hipError_t surface_lapinv<float>(const GridK&, const float*, const float*, const uint8_t*, const int32_t*,
-                                          const int64_t*, float*, const SurfaceWork&, double, int, SurfaceResult*,
-                                          hipStream_t);
+                                          const int64_t*, float*, const SurfaceWork&, double, int, bool,
+                                          SurfaceResult*, hipStream_t);
 template hipError_t surface_lapinv<double>(const GridK&, const double*, const double*, const uint8_t*,
                                            const int32_t*, const int64_t*, double*, const SurfaceWork&, double, int,
-                                           SurfaceResult*, hipStream_t);
+                                           bool, SurfaceResult*, hipStream_t);
 
 }  // namespace etd

@@ -122,3 +122,23 @@ def test_fixed_step_with_band_solve_matches_oracle(scheme, precision):
            iters=plan.query(0, etd.Q_SURF_ITERS))
     assert err <= 1e-11
     plan.close()
+
+
+def test_band_solve_warm_start_depends_on_the_state_alone():
+    """Each band solve of a step starts from the previous solve's result; a new
+    state (etd_set_state) starts cold again, so stepping the same state twice
+    gives the same trajectory bit for bit, and the warm-started solves stop at
+    the same relative residual as a cold one."""
+    ci = inputs.coupled_membrane(n=(24, 24, 24), seed=31, tau=1e-4, eps_pm_in_h=1.5)
+    plan = etd.Plan(etd.coupled_instance(ci, scheme=etd.ETDRK2, band_threshold=0.995, band_rebuild_every=2,
+                                         flags=etd.F_SURFACE_NONLOCAL))
+    runs = []
+    for _ in range(2):
+        plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+        plan.step(3)
+        runs.append([host(t) for t in plan.get_state(0)] + [plan.query(0, etd.Q_SURF_ITERS)])
+        assert plan.query(0, etd.Q_SURF_RELRES) <= 1e-12
+    report("surface_warm_start", iters_last=runs[0][2])
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]
+    plan.close()
