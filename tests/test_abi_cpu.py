@@ -94,3 +94,36 @@ def test_null_arguments_and_status_strings():
     assert L.etd_plan_destroy(None) == etd.ETD_OK
     for s in range(-7, 1):
         assert L.etd_status_string(s)
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """Every structure and array length the binding marshals has the size and
+    field offsets the header gives it, as a C compiler lays them out (so no
+    call can write past a buffer the binding allocated)."""
+    import json
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"etd_grid": etd.Grid, "etd_coupled_params": etd.CoupledParams, "etd_fixed_params": etd.FixedParams,
+               "etd_instance_desc": etd.InstanceDesc, "etd_pass_times": etd.PassTimes,
+               "etd_schedule": etd.Schedule, "etd_diag": etd.Diag}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "etd.h"', 'int main(void) {', 'printf("{");']
+    for cname, cls in structs.items():
+        lines.append(f'printf("\\"{cname}\\": [%zu", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf(", %zu", offsetof({cname}, {fname}));')
+        lines.append('printf("], ");')
+    lines.append('printf("\\"pass_kinds\\": %d, \\"autotune\\": %d}", ETD_PASS_KINDS, ETD_AUTOTUNE_CANDIDATES);')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = json.loads(subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout)
+    for cname, cls in structs.items():
+        want = [C.sizeof(cls)] + [getattr(cls, f).offset for f, _ in cls._fields_]
+        assert got[cname] == want, cname
+    assert got["pass_kinds"] == etd.N_PASS_SLOTS
+    assert got["autotune"] == len(etd.AUTOTUNE_CANDIDATES)
