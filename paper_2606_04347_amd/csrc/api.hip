@@ -268,6 +268,10 @@ etd_status setup_fixed(etd_plan* P, Instance& I) {
     double** reals[] = {&I.G, &I.sg, &I.isg, &I.U, &I.w, &I.R0, &I.R1, &I.vv, &I.t1, &I.t2, &I.acc, &I.q, &I.mq,
                         &I.psid};
     for (double** r : reals) ALLOC(*r, nr * sizeof(double));
+    if (fixed_cheb_pair_supported(g)) {
+        ALLOC(I.t3, nr * sizeof(double));
+        ALLOC(I.t4, nr * sizeof(double));
+    }
     if (I.d.flags & ETD_F_BAND_STEP) ALLOC(I.gf, nr * sizeof(double));
     else I.gf = I.G;
     ALLOC(I.Sa, ns * sizeof(double2));
@@ -591,26 +595,42 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     return ETD_OK;
 }
 
-// acc = f(tau L) v by the Chebyshev recurrence (coefficients c)
+// acc = f(tau L) v by the Chebyshev recurrence (coefficients c); v is only read
 void cheb_apply(Instance& I, const std::vector<double>& c, const double* v, double* acc, hipStream_t s) {
     const GridK& g = I.g;
-    double* tk = I.t1;       // T_1 v, then rotating with t2
-    double* tkm1 = I.t2;
     // first: T_1 v = Atil v; acc = c0/2 v + c1 T_1 v
     const double fb = 8.0 * g.nreal();
     timed_kernel(PASS_FIXED_STENCIL, 5.0 * fb, s, [&] {
-        fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, tk, acc, c.size() > 1 ? c[1] : 0.0,
+        fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 1.0, 0.0, v, nullptr, I.t1, acc, c.size() > 1 ? c[1] : 0.0,
                         0.5 * c[0], 1, s);
     });
-    const double* prev = v;
-    for (size_t k = 2; k < c.size(); ++k) {
-        // T_k = 2 Atil T_{k-1} - T_{k-2}; written over the T_{k-2} buffer (prev == v at k = 2)
-        double* out = (k == 2) ? tkm1 : const_cast<double*>(prev);
+    // T_k = 2 Atil T_{k-1} - T_{k-2}, acc += c_k T_k
+    const double* prev = v;   // T_{k-2}
+    double* cur = I.t1;       // T_{k-1}
+    size_t k = 2;
+    if (I.t3) {   // two terms per pass, into two buffers that hold neither input
+        double* const pool[4] = {I.t1, I.t2, I.t3, I.t4};
+        for (; k + 1 < c.size(); k += 2) {
+            double* o[2] = {nullptr, nullptr};
+            int m = 0;
+            for (double* b : pool)
+                if (b != cur && b != prev && m < 2) o[m++] = b;
+            timed_kernel(PASS_FIXED_STENCIL, 8.0 * fb, s, [&] {
+                fixed_cheb_pair(g, I.FK, I.gf, I.isg, I.a, I.b, 2.0, 1.0, cur, prev, o[0], o[1], acc, c[k], c[k + 1],
+                                s);
+            });
+            prev = o[0];
+            cur = o[1];
+        }
+    }
+    for (; k < c.size(); ++k) {
+        // one term, written over the T_{k-2} buffer (never over v)
+        double* out = (prev == v) ? (cur == I.t1 ? I.t2 : I.t1) : const_cast<double*>(prev);
         timed_kernel(PASS_FIXED_STENCIL, 7.0 * fb, s, [&] {
-            fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 2.0, 1.0, tk, prev, out, acc, c[k], 0.0, 0, s);
+            fixed_cheb_step(g, I.FK, I.gf, I.isg, I.a, I.b, 2.0, 1.0, cur, prev, out, acc, c[k], 0.0, 0, s);
         });
-        prev = tk;
-        tk = out;
+        prev = cur;
+        cur = out;
     }
 }
 

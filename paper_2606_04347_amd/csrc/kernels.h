@@ -136,6 +136,13 @@ void fixed_remainder(long n, const FixedK& K, const double* sg, const double* U,
 void fixed_cheb_step(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
                      double alpha, double beta, const double* x, const double* xprev, double* y, double* acc,
                      double c, double c0, int first, hipStream_t s);
+// Two terms at once (3D grids, fixed_cheb_pair_supported): y1 = alpha Atil x -
+// beta xprev, y2 = alpha Atil y1 - beta x, acc += c1 y1, then acc += c2 y2.
+// y1, y2 must not alias x, xprev or each other.
+bool fixed_cheb_pair_supported(const GridK& g);
+void fixed_cheb_pair(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
+                     double alpha, double beta, const double* x, const double* xprev, double* y1, double* y2,
+                     double* acc, double c1, double c2, hipStream_t s);
 // out = L x
 void fixed_L_apply(const GridK& g, const FixedK& K, const double* gg, const double* isg, const double* x,
                    double* out, hipStream_t s);

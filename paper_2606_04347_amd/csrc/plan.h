@@ -46,6 +46,7 @@ struct Instance {
     // fixed buffers (double unless noted)
     double *G = nullptr, *sg = nullptr, *isg = nullptr, *U = nullptr, *w = nullptr, *R0 = nullptr, *R1 = nullptr,
            *vv = nullptr, *t1 = nullptr, *t2 = nullptr, *acc = nullptr, *q = nullptr, *mq = nullptr,
+           *t3 = nullptr, *t4 = nullptr,   // two-term recurrence passes (3D grids)
            *psid = nullptr;
     float *qf = nullptr, *psif = nullptr;   // FP32-FFT variant of the nonlocal term
     double* gf = nullptr;   // operator field: G, or for ETD_F_BAND_STEP g on the band and -1 off it

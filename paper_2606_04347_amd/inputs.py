@@ -144,7 +144,7 @@ class FixedInputs:
     tau: float
 
 
-def fixed_membrane(dim: int = 2, n: int = 64, radius: float = 0.5, eps_pm: float | None = None,
+def fixed_membrane(dim: int = 2, n: int | tuple = 64, radius: float = 0.5, eps_pm: float | None = None,
                    eps_pm_in_h: float | None = None, seed: int = DEFAULT_SEED, instance: int = 0,
                    u_mean_pm: float = -0.2, u_amp_pm: float = 0.05, gamma: float = 1.0,
                    M: float | None = None, tau: float = 0.01, half_len: float = 1.0) -> FixedInputs:
@@ -155,10 +155,13 @@ def fixed_membrane(dim: int = 2, n: int = 64, radius: float = 0.5, eps_pm: float
     which is used directly so that g stays strictly positive in float64
     (the tanh route saturates to phi = 1 exactly far from the membrane).
     u_pm = u_mean_pm + u_amp_pm * U(-1, 1), mapped u = (1 + u_pm)/2.
+    n: the points per axis, or one count per axis; eps_pm_in_h counts the
+    coarsest spacing, so the interface is resolved along every axis.
     """
-    shape = (n,) * dim
+    shape = (n,) * dim if isinstance(n, int) else tuple(n)
+    assert len(shape) == dim
     hl = (half_len,) * dim
-    h = 2.0 * half_len / n
+    h = 2.0 * half_len / min(shape)
     if eps_pm is None:
         eps_pm = (eps_pm_in_h * h) if eps_pm_in_h is not None else 0.0625
     X = mesh(shape, hl)

@@ -126,6 +126,25 @@ def test_fp64_3d_matches_lanczos_oracle(scheme):
     plan.close()
 
 
+@pytest.mark.parametrize("n", [12, (16, 24, 48)])
+def test_fp64_3d_two_term_passes_on_ragged_tiles(n):
+    """On 3D grids the recurrence runs two terms per pass over tiles of 8 x
+    planes, 16 y rows and 32 z nodes: 12^3 has a ragged x segment and y and z
+    tiles wider than the grid (their halos wrap more than once), 16 x 24 x 48
+    ragged y and z tiles.  ETDRK2 against the Lanczos oracle."""
+    fi = inputs.fixed_membrane(dim=3, n=n, eps_pm_in_h=2.0, tau=0.02)
+    grid, p, _ = oracle_params(fi)
+    ex = fixed.LanczosExpo(fi.g, p, grid)
+    U = fi.u0.copy()
+    for _ in range(2):
+        U = fixed.step(U, fi.g, p, grid, fi.tau, etd.ETDRK2, ex)
+    plan, Ug = gpu_run(fi, etd.ETDRK2, 2)
+    err = rel_linf(Ug, U)
+    report("fixed3d_pair", n=str(n), err=err, degree=plan.query(0, etd.Q_CHEB_DEG))
+    assert err <= 1e-12
+    plan.close()
+
+
 @pytest.mark.parametrize("scheme", [etd.ETD1, etd.ETDRK2])
 def test_mbp_and_energy_decay_on_gpu(scheme):
     """Theorems thm:MBP and thm:Energy on the 64^2 configuration, 200 steps."""
