@@ -50,7 +50,7 @@ def test_fp64_256cubed_step_matches_oracle(workload):
     assert abs(d["mass"] - od["m"]) <= 1e-11 * max(1.0, abs(od["m"]))
 
 
-@pytest.mark.parametrize("n", [128])
+@pytest.mark.parametrize("n", [128, 256])
 def test_fp64_trajectory_matches_stored_oracle(n):
     """200 FP64 ETDRK2 steps against the oracle's trajectory, sampled after
     steps 1, 100 and 200 (relative to the oracle's full-grid maxima), with the
