@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device copies (a reference kernel of known size "
                          "for hardware byte counters)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn the counter CSVs of a FETCH_SIZE and a WRITE_SIZE pass "
+                         "(rocprofv3 --pmc, both with --copy-calibration) into "
+                         "profiles/traffic_fp32_256cubed.json and exit")
     return ap.parse_args()
 
 
@@ -124,6 +128,64 @@ def measured_traffic(kind, n, precision):
         return None
     p = rec.get("passes", {}).get(kind)
     return p["bytes_per_launch"] if p else None
+
+
+# kernel name -> pass kind of the ledger (the FP32 instantiations are read)
+KERNEL_KINDS = (("k_x_etd<", "pair_x_etd"), ("k_y_pair<", "pair_y_lines"), ("k_fft_ylines<", "fft_y_lines"),
+                ("k_fft_xlines<", "fft_x_lines"), ("k_deriv_y<", "deriv_y"), ("k_deriv_x<", "deriv_x"),
+                ("k_deriv_z<", "deriv_z_c2r"), ("k_lapinv_lines<", "lapinv_lines"),
+                ("k_z_c2r_recover<", "z_c2r_recover"), ("k_z_r2c_r1<", "z_r2c_r1"), ("k_z_r2c_p2<", "z_r2c_p2"),
+                ("k_z_r2c_q<", "z_r2c_q"), ("k_z_r2c_pair<", "pair_z_r2c"), ("k_fft_z_r2c<", "fft_z_r2c"),
+                ("k_fft_z_c2r<", "fft_z_c2r"))
+COPY_BYTES = 64 * 2 ** 20 * 4      # one --copy-calibration copy: 256 MiB read, 256 MiB written
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    """Per-kind HBM bytes per launch from a FETCH_SIZE and a WRITE_SIZE counter
+    pass (KiB per dispatch), each scaled by what the counter reads for the
+    calibration copy of COPY_BYTES."""
+    import csv
+
+    def per_kernel(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+
+    def calib(d):
+        vals = [v for k, vs in d.items() if "copyBuffer" in k for v in vs]
+        vals = [v for v in vals if v > 0.25 * COPY_BYTES / 1024]   # the 256 MiB copies only
+        return (COPY_BYTES / 1024) / (sum(vals) / len(vals)) if vals else None
+
+    ff, wf = calib(fetch), calib(write)
+    if ff is None or wf is None:
+        raise SystemExit("no calibration copy in the counter CSVs (run them with --copy-calibration); copy-like "
+                         f"kernels seen: {sorted(k for k in fetch if 'copy' in k.lower())}")
+    rec = {"kernel_source_sha256": kernel_source_hash(), "grid": 256, "precision": "fp32",
+           "calibration": {"copy_bytes": COPY_BYTES, "fetch_factor": ff, "write_factor": wf}, "passes": {}}
+    for name in fetch:
+        if "float" not in name or name not in write:
+            continue
+        kind = next((k for pat, k in KERNEL_KINDS if pat in name), None)
+        if kind is None:
+            continue
+        fk = sum(fetch[name]) / len(fetch[name])
+        wk = sum(write[name]) / len(write[name])
+        p = rec["passes"].setdefault(kind, {"fetch_kib": 0.0, "write_kib": 0.0, "n": 0})
+        m = len(fetch[name])
+        p["fetch_kib"] = (p["fetch_kib"] * p["n"] + fk * m) / (p["n"] + m)
+        p["write_kib"] = (p["write_kib"] * p["n"] + wk * m) / (p["n"] + m)
+        p["n"] += m
+    for p in rec["passes"].values():
+        p["bytes_per_launch"] = 1024.0 * (p["fetch_kib"] * ff + p["write_kib"] * wf)
+    path = os.path.join(ROOT, "profiles", "traffic_fp32_256cubed.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(path)
 
 
 def roofline(passes, pass_steps, n, precision):
@@ -459,6 +521,9 @@ def cpu_baseline(ci, nsteps=3):
 
 def main():
     a = parse()
+    if a.summarize_traffic:
+        summarize_traffic(*a.summarize_traffic)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU slab "
               "decomposition is designed but not implemented.", file=sys.stderr)
