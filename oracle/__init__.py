@@ -15,7 +15,7 @@ Modules
   band     narrow-band index lists and the recovery step
 
 Every function is pinned by a CPU test against something other than
-itself (brute force, closed forms, theorems of the paper, invariants);
-the coupled dynamics beyond those pins are "parity unpinned" as noted in
-the coupled module's header.
+itself (brute force, closed forms, theorems of the paper, invariants,
+first variations of the energies); the coupled module's header lists its
+pins.
 """

@@ -45,9 +45,13 @@ Readings (ambiguity register; listed in the design notes):
     g (u - ubar) and the three |grad phi|-weighted terms of P1 are zero off the
     band.
 
-Parity of the coupled dynamics beyond the pinned pieces (splitting
-identities, exact linear part, symmetry, decoupled-limit convergence) is
-"parity unpinned": the paper prints no values for them.
+Pins (tests/test_oracle_coupled.py): the splitting identities of R1 and R2
+against the model equations written directly, the exact per-mode solution
+for constant remainders, the small-tau limits of both stages, symmetry, the
+decoupled-limit orders, the velocity of a translating wave, and the energy
+terms through their first variations.  The paper prints no coupled
+trajectory values, so long runs are held against this oracle, not against
+printed numbers.
 """
 from __future__ import annotations
 
