@@ -197,6 +197,31 @@ etd_status etd_set_tau(etd_plan_t plan, int instance, double tau);
  * ETD_E_NONFINITE once a non-finite value has been detected (see etd_step). */
 etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dtype dtype);
 
+/* Checkpoint of one instance in host memory: everything a step carries over
+ * to the next (coupled, Algorithm 1: the spectrum of phi^n, phi^n and the
+ * fields derived from it, u^n, the band mask and list in use, the device
+ * scalars; fixed, eqn:ETD1 / eqn:ETDRK2: g and U^n with the device scalars;
+ * the band solve's starting iterate when ETD_F_SURFACE_NONLOCAL is set), the
+ * step counter and A0.  etd_set_state / etd_get_state carry phi^n and u^n
+ * alone, and a run restarted from them differs from the original in
+ * rounding (the spectrum is re-formed from phi^n) and in A0; a run resumed
+ * with etd_checkpoint_load continues bit for bit as the saved one would.
+ *   etd_checkpoint_size: *bytes (host) receives the size of the image.
+ *   etd_checkpoint_save: writes the image into host[0 .. bytes); needs a
+ *     state (ETD_E_STATE) and bytes >= the size (ETD_E_CAPACITY).
+ *   etd_checkpoint_load: reads an image saved from an instance with the same
+ *     model, scheme, precision, grid, flags and band settings (ETD_E_ARG
+ *     otherwise; nothing is changed); the instance keeps its own tau (call
+ *     etd_set_tau to continue a variable-step run).
+ * The image is the library's own binary layout (a header, then the device
+ * buffers in a fixed order), valid for the library build that wrote it.
+ * Save and load synchronize.  Errors: ETD_E_ARG (null pointers, instance
+ * out of range, a foreign or mismatched image), ETD_E_STATE, ETD_E_CAPACITY,
+ * ETD_E_HIP. */
+etd_status etd_checkpoint_size(etd_plan_t plan, int instance, size_t* bytes);
+etd_status etd_checkpoint_save(etd_plan_t plan, int instance, void* host, size_t bytes);
+etd_status etd_checkpoint_load(etd_plan_t plan, int instance, const void* host, size_t bytes);
+
 /* Advance every instance by nsteps time steps (ETD1 or ETDRK2 as planned).
  * Asynchronous.  Non-finite values are detected on the device, per
  * instance, by the FP64 sums every step forms (coupled: h^d sum phi after

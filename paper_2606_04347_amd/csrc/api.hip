@@ -914,6 +914,138 @@ etd_status etd_get_state(etd_plan_t plan, int instance, void* a, void* u, etd_dt
     return ETD_OK;
 }
 
+// ------------------------------------------------------------------ checkpoints
+namespace {
+
+constexpr char kCkptMagic[8] = {'E', 'T', 'D', 'C', 'K', 'P', 'T', '1'};
+constexpr int kCkptMaxParts = 24;
+
+struct CkptHeader {
+    char magic[8];
+    int32_t model, scheme, precision, nx, ny, nz;
+    uint32_t flags;
+    int32_t nparts;
+    double band_threshold, recover_threshold;
+    int32_t band_rebuild_every, pad;
+    int64_t step;
+    double A0;
+    uint64_t part_bytes[kCkptMaxParts];
+};
+
+// carried_state, plus g for the fixed model (its derived fields are
+// recomputed from it by the load)
+std::vector<std::pair<void*, size_t>> ckpt_parts(const Instance& I) {
+    std::vector<std::pair<void*, size_t>> parts = carried_state(I);
+    if (I.d.model == ETD_FIXED_MEMBRANE) parts.push_back({I.G, (size_t)I.g.nreal() * sizeof(double)});
+    return parts;
+}
+
+size_t ckpt_bytes(const std::vector<std::pair<void*, size_t>>& parts) {
+    size_t b = sizeof(CkptHeader);
+    for (const auto& p : parts) b += p.second;
+    return b;
+}
+
+CkptHeader ckpt_header(const Instance& I, const std::vector<std::pair<void*, size_t>>& parts) {
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+    h.model = I.d.model;
+    h.scheme = I.d.scheme;
+    h.precision = I.d.precision;
+    h.nx = I.g.nx;
+    h.ny = I.g.ny;
+    h.nz = I.g.nz;
+    h.flags = I.d.flags;
+    h.nparts = (int32_t)parts.size();
+    h.band_threshold = I.d.band_threshold;
+    h.recover_threshold = I.d.recover_threshold;
+    h.band_rebuild_every = I.d.band_rebuild_every;
+    h.step = I.step;
+    h.A0 = I.A0;
+    for (size_t k = 0; k < parts.size() && k < (size_t)kCkptMaxParts; ++k) h.part_bytes[k] = parts[k].second;
+    return h;
+}
+
+etd_status ckpt_copy_in(etd_plan* plan, const std::vector<std::pair<void*, size_t>>& parts, const char* src) {
+    src += sizeof(CkptHeader);
+    for (const auto& p : parts) {
+        HIPCHK(plan, hipMemcpyAsync(p.first, src, p.second, hipMemcpyHostToDevice, plan->stream));
+        src += p.second;
+    }
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    return ETD_OK;
+}
+
+}  // namespace
+
+etd_status etd_checkpoint_size(etd_plan_t plan, int instance, size_t* bytes) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!bytes) return fail(&plan->err, ETD_E_ARG, "null output");
+    *bytes = ckpt_bytes(ckpt_parts(plan->inst[instance]));
+    return ETD_OK;
+}
+
+etd_status etd_checkpoint_save(etd_plan_t plan, int instance, void* host, size_t bytes) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!host) return fail(&plan->err, ETD_E_ARG, "null host buffer");
+    const Instance& I = plan->inst[instance];
+    if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "checkpoint before set_state");
+    const auto parts = ckpt_parts(I);
+    if (parts.size() > (size_t)kCkptMaxParts) return fail(&plan->err, ETD_E_ARG, "checkpoint: too many buffers");
+    if (bytes < ckpt_bytes(parts)) return fail(&plan->err, ETD_E_CAPACITY, "checkpoint buffer too small");
+    const CkptHeader h = ckpt_header(I, parts);
+    char* dst = static_cast<char*>(host);
+    std::memcpy(dst, &h, sizeof h);
+    dst += sizeof h;
+    for (const auto& p : parts) {
+        HIPCHK(plan, hipMemcpyAsync(dst, p.first, p.second, hipMemcpyDeviceToHost, plan->stream));
+        dst += p.second;
+    }
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    return ETD_OK;
+}
+
+etd_status etd_checkpoint_load(etd_plan_t plan, int instance, const void* host, size_t bytes) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!host) return fail(&plan->err, ETD_E_ARG, "null host buffer");
+    Instance& I = plan->inst[instance];
+    if (bytes < sizeof(CkptHeader)) return fail(&plan->err, ETD_E_ARG, "checkpoint image too small");
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof h);
+    // the instance's buffers before any state is set: the same list as after
+    const auto parts = ckpt_parts(I);
+    CkptHeader want = ckpt_header(I, parts);
+    if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0)
+        return fail(&plan->err, ETD_E_ARG, "not a checkpoint image of this library");
+    bool same = h.model == want.model && h.scheme == want.scheme && h.precision == want.precision &&
+                h.nx == want.nx && h.ny == want.ny && h.nz == want.nz && h.flags == want.flags &&
+                h.nparts == want.nparts && h.band_threshold == want.band_threshold &&
+                h.recover_threshold == want.recover_threshold && h.band_rebuild_every == want.band_rebuild_every;
+    for (int k = 0; same && k < h.nparts && k < kCkptMaxParts; ++k) same = h.part_bytes[k] == want.part_bytes[k];
+    if (!same) return fail(&plan->err, ETD_E_ARG, "checkpoint of a different instance configuration");
+    if (bytes < ckpt_bytes(parts)) return fail(&plan->err, ETD_E_ARG, "checkpoint image truncated");
+    const char* src = static_cast<const char*>(host);
+    // the saved buffers in place, then set_state from the saved state (the
+    // fields it derives from phi or g, the schedule reset), then the saved
+    // buffers again over everything set_state recomputed
+    if ((st = ckpt_copy_in(plan, parts, src)) != ETD_OK) return st;
+    if (I.d.model == ETD_COUPLED)
+        st = I.f32 ? set_state_coupled<float>(plan, I, I.phiA, I.u, ETD_F32)
+                   : set_state_coupled<double>(plan, I, I.phiA, I.u, ETD_F64);
+    else
+        st = set_state_fixed(plan, I, I.G, I.U, ETD_F64);
+    if (st != ETD_OK) return st;
+    if ((st = ckpt_copy_in(plan, parts, src)) != ETD_OK) return st;
+    I.step = h.step;
+    I.A0 = h.A0;
+    I.has_state = true;
+    drop_graphs(plan);
+    return ETD_OK;
+}
+
 etd_status etd_step(etd_plan_t plan, int nsteps) {
     if (!plan) return fail(nullptr, ETD_E_ARG, "null plan");
     if (nsteps < 0) return fail(&plan->err, ETD_E_ARG, "nsteps must be >= 0");

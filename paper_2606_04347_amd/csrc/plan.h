@@ -6,6 +6,7 @@
 
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "etd.h"
@@ -132,6 +133,12 @@ etd_status run_steps(etd_plan* plan, int nsteps);
 // Drop the captured graphs (after set_state or a schedule change) / release everything.
 void drop_graphs(etd_plan* plan);
 void release_schedule(etd_plan* plan);
+// Device buffers (address, bytes) whose contents a step carries over to the
+// next one, besides the host-side step counter and A0 (schedule.hip): what a
+// snapshot or a checkpoint holds.  The fields computed from g alone (fixed
+// model) and the buffers every step writes before it reads them are not
+// among them.
+std::vector<std::pair<void*, size_t>> carried_state(const Instance& I);
 
 }  // namespace etd
 

@@ -178,24 +178,33 @@ struct Snapshot {
     double A0 = 0.0;
 };
 
-etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
+}  // namespace
+
+std::vector<std::pair<void*, size_t>> etd::carried_state(const Instance& I) {
     const size_t n = (size_t)I.g.nreal();
     const size_t es = I.d.model == ETD_COUPLED ? (I.f32 ? sizeof(float) : sizeof(double)) : sizeof(double);
-    v.parts.clear();
-    v.parts.push_back({I.scal, sizeof(double) * S_COUNT});
+    std::vector<std::pair<void*, size_t>> parts;
+    parts.push_back({I.scal, sizeof(double) * S_COUNT});
     if (I.d.model == ETD_COUPLED) {
         for (void* p : {I.phiA, I.u, I.lap, I.gx, I.gy, I.gz})
-            if (p) v.parts.push_back({p, n * es});   // gy, gz exist on two-dimensional grids only
-        v.parts.push_back({I.Sphi, 2 * es * (size_t)I.g.nspec()});
-        if (I.mask) v.parts.push_back({I.mask, n});
-        // the band list in use until the next rebuild (the trial steps may rebuild it)
-        if (I.band_idx) v.parts.push_back({I.band_idx, n * sizeof(int32_t)});
-        if (I.band_cnt) v.parts.push_back({I.band_cnt, (size_t)(band_blocks((long)n) + 2) * sizeof(int64_t)});
-        if (I.band_total) v.parts.push_back({I.band_total, sizeof(int64_t)});
+            if (p) parts.push_back({p, n * es});   // gy, gz exist on two-dimensional grids only
+        parts.push_back({I.Sphi, 2 * es * (size_t)I.g.nspec()});
+        if (I.mask) parts.push_back({I.mask, n});
+        // the band list in use until the next rebuild
+        if (I.band_idx) parts.push_back({I.band_idx, n * sizeof(int32_t)});
+        if (I.band_cnt) parts.push_back({I.band_cnt, (size_t)(band_blocks((long)n) + 2) * sizeof(int64_t)});
+        if (I.band_total) parts.push_back({I.band_total, sizeof(int64_t)});
     } else {
-        v.parts.push_back({I.U, n * sizeof(double)});
+        parts.push_back({I.U, n * sizeof(double)});
     }
-    if (I.surf) v.parts.push_back({I.sw.x, n * sizeof(double)});   // the start of the next band solve
+    if (I.surf) parts.push_back({I.sw.x, n * sizeof(double)});   // the start of the next band solve
+    return parts;
+}
+
+namespace {
+
+etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
+    v.parts = carried_state(I);
     size_t total = 0;
     for (const auto& pr : v.parts) total += (pr.second + 255) & ~(size_t)255;
     if (hipMalloc(&v.base, total) != hipSuccess) {

@@ -32,6 +32,7 @@ EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau"
            "etd_energy", "etd_diagnostics", "etd_narrowband_build", "etd_spectral_apply",
            "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
            "etd_surface_lapinv", "etd_narrowband_build_noalloc",
+           "etd_checkpoint_size", "etd_checkpoint_save", "etd_checkpoint_load",
            "etd_status_string", "etd_last_error")
 EXEC_EAGER, EXEC_GRAPH = 0, 1
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
@@ -111,6 +112,9 @@ def lib():
         L.etd_autotune.argtypes = [vp, i, C.c_char_p, C.POINTER(Schedule), C.POINTER(d)]
         L.etd_surface_lapinv.argtypes = [vp, i, vp, vp, vp, vp, i, d, i, C.POINTER(i), C.POINTER(d)]
         L.etd_narrowband_build_noalloc.argtypes = [vp, vp, i, C.c_int64, d, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.etd_checkpoint_size.argtypes = [vp, i, C.POINTER(C.c_size_t)]
+        L.etd_checkpoint_save.argtypes = [vp, i, vp, C.c_size_t]
+        L.etd_checkpoint_load.argtypes = [vp, i, vp, C.c_size_t]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -254,6 +258,21 @@ class Plan:
         u = torch.empty_like(a)
         self._c(lib().etd_get_state(self._ptr, i, self._dev(a), self._dev(u), self._dt(a)))
         return a, u
+
+    def checkpoint(self, i):
+        """The instance's checkpoint image (etd_checkpoint_save) as a numpy uint8 array."""
+        import numpy as np
+        n = C.c_size_t(0)
+        self._c(lib().etd_checkpoint_size(self._ptr, i, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._c(lib().etd_checkpoint_save(self._ptr, i, C.c_void_p(buf.ctypes.data), n.value))
+        return buf
+
+    def load_checkpoint(self, i, image):
+        """Resume instance i from an image of checkpoint() (etd_checkpoint_load)."""
+        import numpy as np
+        buf = np.ascontiguousarray(image, dtype=np.uint8)
+        self._c(lib().etd_checkpoint_load(self._ptr, i, C.c_void_p(buf.ctypes.data), buf.nbytes))
 
     def step(self, nsteps=1):
         self._c(lib().etd_step(self._ptr, int(nsteps)))

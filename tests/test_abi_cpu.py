@@ -91,6 +91,10 @@ def test_null_arguments_and_status_strings():
     assert L.etd_step(None, 1) == etd.ETD_E_ARG
     assert L.etd_set_tau(None, 0, 1e-4) == etd.ETD_E_ARG
     assert L.etd_surface_lapinv(None, 0, None, None, None, None, 0, 1e-12, 10, None, None) == etd.ETD_E_ARG
+    n = C.c_size_t(0)
+    assert L.etd_checkpoint_size(None, 0, C.byref(n)) == etd.ETD_E_ARG
+    assert L.etd_checkpoint_save(None, 0, None, 0) == etd.ETD_E_ARG
+    assert L.etd_checkpoint_load(None, 0, None, 0) == etd.ETD_E_ARG
     assert L.etd_plan_destroy(None) == etd.ETD_OK
     for s in range(-7, 1):
         assert L.etd_status_string(s)
