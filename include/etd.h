@@ -260,6 +260,23 @@ typedef struct {
 /* Compute and return the diagnostics of one instance (synchronizes). */
 etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* host_out);
 
+/* Per-step diagnostics ring (the etd_diag fields of etd_diagnostics,
+ * recorded on the device after every step, so a long run can be followed
+ * without a synchronization per step; also under a captured graph schedule).
+ * etd_diag_ring_enable keeps the last `capacity` steps of the instance (0
+ * turns the ring off and frees it; at most 2^24); it synchronizes and drops
+ * captured graphs.  Each step then adds one reduction pass over its state.
+ * etd_set_state and etd_checkpoint_load start the record again.
+ * etd_diag_ring_read copies the most recent min(recorded, capacity,
+ * max_entries) entries, oldest first, into host_out; *recorded receives the
+ * number of steps recorded since the record started (the older ones beyond
+ * the capacity are gone).  Synchronizes.  Errors: ETD_E_ARG (null plan or
+ * output, instance out of range, capacity or max_entries out of range),
+ * ETD_E_STATE (read with the ring off), ETD_E_NOMEM, ETD_E_HIP. */
+etd_status etd_diag_ring_enable(etd_plan_t plan, int instance, int capacity);
+etd_status etd_diag_ring_read(etd_plan_t plan, int instance, etd_diag* host_out, int max_entries,
+                              int64_t* recorded);
+
 /* Narrow band of Section 3.2 for a phase field phi (device array, grid layout
  * of the instance): the ascending C-order linear indices i with
  * |2 phi_i - 1| < threshold, decided in FP64, written as int32 to dev_idx_out.

@@ -767,9 +767,32 @@ etd_status set_state_fixed(etd_plan* plan, Instance& I, const void* a, const voi
 }  // namespace
 
 // =================================================================== C ABI
+namespace {
+// The instance's diagnostics sums of its current state into S_DIAG.
+void diag_sums(Instance& I, hipStream_t s) {
+    const GridK& g = I.g;
+    if (I.d.model == ETD_COUPLED) {
+        if (I.f32) reduce_diag<float>(g, (const float*)I.phiA, nullptr, (const float*)I.u, I.cp.ubar, false, I.part,
+                                      I.scal + S_DIAG, s);
+        else reduce_diag<double>(g, (const double*)I.phiA, nullptr, (const double*)I.u, I.cp.ubar, false, I.part,
+                                 I.scal + S_DIAG, s);
+    } else {
+        reduce_diag<double>(g, nullptr, I.G, I.U, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
+    }
+}
+}  // namespace
+
 etd_status etd::step_instance(etd_plan* plan, Instance& I, hipStream_t s) {
-    if (I.d.model == ETD_COUPLED) return I.f32 ? step_coupled<float>(plan, I, s) : step_coupled<double>(plan, I, s);
-    return step_fixed(plan, I, s);
+    etd_status st = I.d.model == ETD_COUPLED ? (I.f32 ? step_coupled<float>(plan, I, s)
+                                                       : step_coupled<double>(plan, I, s))
+                                             : step_fixed(plan, I, s);
+    if (st != ETD_OK || !I.ring) return st;
+    // the ring entry of this step, on the step's stream (so also inside a captured graph)
+    diag_sums(I, s);
+    const bool band = I.d.model == ETD_COUPLED && I.d.band_threshold > 0.0 && I.band_total;
+    diag_ring_push(I.scal + S_DIAG, halt_flag(I), band ? I.band_total : nullptr, I.ring, I.ring_cap, I.ring_meta, s);
+    HIPCHK(plan, hipGetLastError());
+    return ETD_OK;
 }
 
 extern "C" {
@@ -859,6 +882,8 @@ etd_status etd_set_state(etd_plan_t plan, int instance, const void* a, const voi
     if (st != ETD_OK) return st;
     // the band solves of a new state start cold, so a run depends on its state alone
     if (I.surf) HIPCHK(plan, hipMemsetAsync(I.sw.x, 0, sizeof(double) * (size_t)I.g.nreal(), plan->stream));
+    // the diagnostics ring records the steps of the new state
+    if (I.ring_meta) HIPCHK(plan, hipMemsetAsync(I.ring_meta, 0, 2 * sizeof(int64_t), plan->stream));
     I.step = 0;
     I.has_state = true;
     drop_graphs(plan);   // captured kernel arguments (A0, Chebyshev coefficients) may have changed
@@ -1041,6 +1066,10 @@ etd_status etd_checkpoint_load(etd_plan_t plan, int instance, const void* host, 
     if ((st = ckpt_copy_in(plan, parts, src)) != ETD_OK) return st;
     I.step = h.step;
     I.A0 = h.A0;
+    if (I.ring_meta) {   // the diagnostics ring records the resumed steps
+        const int64_t meta[2] = {0, h.step};
+        HIPCHK(plan, hipMemcpy(I.ring_meta, meta, sizeof meta, hipMemcpyHostToDevice));
+    }
     I.has_state = true;
     drop_graphs(plan);
     return ETD_OK;
@@ -1117,6 +1146,64 @@ etd_status etd_energy(etd_plan_t plan, int instance, double* host_out, int n_out
     return ETD_OK;
 }
 
+etd_status etd_diag_ring_enable(etd_plan_t plan, int instance, int capacity) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (capacity < 0 || capacity > (1 << 24)) return fail(&plan->err, ETD_E_ARG, "capacity must be in 0 .. 2^24");
+    Instance& I = plan->inst[instance];
+    HIPCHK(plan, hipStreamSynchronize(plan->stream));
+    for (void* p : {(void*)I.ring, (void*)I.ring_meta}) {
+        if (!p) continue;
+        (void)hipFree(p);
+        I.allocs.erase(std::remove(I.allocs.begin(), I.allocs.end(), p), I.allocs.end());
+    }
+    I.ring = nullptr;
+    I.ring_meta = nullptr;
+    I.ring_cap = 0;
+    drop_graphs(plan);   // captured steps include the push, or not
+    if (capacity == 0) return ETD_OK;
+    etd_plan* P = plan;
+    ALLOC(I.ring, (size_t)capacity * kDiagRingFields * sizeof(double));
+    ALLOC(I.ring_meta, 2 * sizeof(int64_t));
+    I.ring_cap = capacity;
+    const int64_t meta[2] = {0, I.step};
+    HIPCHK(plan, hipMemcpy(I.ring_meta, meta, sizeof meta, hipMemcpyHostToDevice));
+    return ETD_OK;
+}
+
+etd_status etd_diag_ring_read(etd_plan_t plan, int instance, etd_diag* host_out, int max_entries,
+                              int64_t* recorded) {
+    etd_status st = check_instance(plan, instance);
+    if (st != ETD_OK) return st;
+    if (!recorded || (max_entries > 0 && !host_out) || max_entries < 0)
+        return fail(&plan->err, ETD_E_ARG, "null output or negative max_entries");
+    const Instance& I = plan->inst[instance];
+    if (!I.ring) return fail(&plan->err, ETD_E_STATE, "diagnostics ring not enabled");
+    hipStream_t s = plan->stream;
+    int64_t meta[2] = {0, 0};
+    std::vector<double> ring((size_t)I.ring_cap * kDiagRingFields);
+    HIPCHK(plan, hipMemcpyAsync(meta, I.ring_meta, sizeof meta, hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipMemcpyAsync(ring.data(), I.ring, ring.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(plan, hipStreamSynchronize(s));
+    *recorded = meta[0];
+    const int64_t n = std::min<int64_t>({meta[0], (int64_t)I.ring_cap, (int64_t)max_entries});
+    for (int64_t k = 0; k < n; ++k) {   // the last n entries, oldest first
+        const double* e = ring.data() + (size_t)((meta[0] - n + k) % I.ring_cap) * kDiagRingFields;
+        etd_diag& o = host_out[k];
+        o.step = (int64_t)e[0];
+        o.int_phi = I.d.model == ETD_COUPLED ? e[1] : 0.0;
+        o.mass = e[2];
+        o.Q = e[3];
+        o.umin = e[4];
+        o.umax = e[5];
+        o.bound = e[6];
+        o.band_count = (int64_t)e[7];
+        o.nonfinite = e[8] != 0.0 ? 1 : 0;
+        o.b_warning = (I.d.model == ETD_FIXED_MEMBRANE && I.FK.B < I.Bmbp) ? 1 : 0;
+    }
+    return ETD_OK;
+}
+
 etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* out) {
     etd_status st = check_instance(plan, instance);
     if (st != ETD_OK) return st;
@@ -1124,15 +1211,7 @@ etd_status etd_diagnostics(etd_plan_t plan, int instance, etd_diag* out) {
     if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "diagnostics before set_state");
     if (!out) return fail(&plan->err, ETD_E_ARG, "null output");
     hipStream_t s = plan->stream;
-    const GridK& g = I.g;
-    if (I.d.model == ETD_COUPLED) {
-        if (I.f32) reduce_diag<float>(g, (const float*)I.phiA, nullptr, (const float*)I.u, I.cp.ubar, false, I.part,
-                                      I.scal + S_DIAG, s);
-        else reduce_diag<double>(g, (const double*)I.phiA, nullptr, (const double*)I.u, I.cp.ubar, false, I.part,
-                                 I.scal + S_DIAG, s);
-    } else {
-        reduce_diag<double>(g, nullptr, I.G, I.U, I.fp.ubar, true, I.part, I.scal + S_DIAG, s);
-    }
+    diag_sums(I, s);
     double d[7], halt = 0.0;
     int64_t bc = 0;
     HIPCHK(plan, hipMemcpyAsync(d, I.scal + S_DIAG, 7 * sizeof(double), hipMemcpyDeviceToHost, s));

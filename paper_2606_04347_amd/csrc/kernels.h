@@ -202,6 +202,14 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
                           const int64_t* total, T* psi, const SurfaceWork& w, double tol, int max_iter, bool warm,
                           SurfaceResult* res, hipStream_t s);
 
+// Per-step diagnostics ring: one entry (kDiagRingFields doubles: step, the
+// seven diagnostics sums of reduce_diag with the minimum's sign restored,
+// band count, non-finite flag) pushed into slot meta[0] mod cap, meta[0]
+// then incremented; the step is meta[1] + meta[0] + 1.  One thread.
+constexpr int kDiagRingFields = 9;
+void diag_ring_push(const double* diag, const double* halt, const int64_t* band_total, double* ring, int cap,
+                    int64_t* meta, hipStream_t s);
+
 // Compact flagged indices in ascending order.  blockcnt: scratch of band_blocks(n) + 1 int64.
 long band_blocks(long n);
 void band_compact(long n, const uint8_t* flags, int64_t* blockcnt, int32_t* idx_out, int64_t capacity,

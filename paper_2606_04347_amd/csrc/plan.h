@@ -72,6 +72,11 @@ struct Instance {
     void* surf = nullptr;
     SurfaceWork sw;
     SurfaceResult surf_last;
+    // per-step diagnostics ring (etd_diag_ring_enable): ring_cap entries of
+    // kDiagRingFields doubles; ring_meta = {entries pushed, step before the first}
+    double* ring = nullptr;
+    int ring_cap = 0;
+    int64_t* ring_meta = nullptr;
 };
 
 

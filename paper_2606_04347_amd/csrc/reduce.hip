@@ -256,6 +256,30 @@ struct GershF {
 
 }  // namespace
 
+namespace {
+__global__ void k_diag_ring_push(const double* __restrict__ diag, const double* halt, const int64_t* band_total,
+                                 double* ring, int cap, int64_t* meta) {
+    if (threadIdx.x != 0) return;
+    const int64_t c = meta[0];
+    double* e = ring + (long)(c % cap) * kDiagRingFields;
+    e[0] = (double)(meta[1] + c + 1);
+    e[1] = diag[0];
+    e[2] = diag[1];
+    e[3] = diag[2];
+    e[4] = -diag[3];
+    e[5] = diag[4];
+    e[6] = diag[5];
+    e[7] = band_total ? (double)band_total[0] : 0.0;
+    e[8] = (diag[6] > 0.0 || (halt && halt[0] != 0.0)) ? 1.0 : 0.0;
+    meta[0] = c + 1;
+}
+}  // namespace
+
+void diag_ring_push(const double* diag, const double* halt, const int64_t* band_total, double* ring, int cap,
+                    int64_t* meta, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_ring_push, dim3(1), dim3(64), 0, s, diag, halt, band_total, ring, cap, meta);
+}
+
 void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s, double* halt) {
     hipLaunchKernelGGL((k_reduce_final<1, 0>), dim3(1), dim3(kB), 0, s, part, nb, out, scale, halt);
 }

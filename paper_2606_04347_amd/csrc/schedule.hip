@@ -205,6 +205,10 @@ namespace {
 
 etd_status take_snapshot(etd_plan* plan, Instance& I, Snapshot& v) {
     v.parts = carried_state(I);
+    if (I.ring) {   // the trial steps push ring entries too
+        v.parts.push_back({I.ring, (size_t)I.ring_cap * kDiagRingFields * sizeof(double)});
+        v.parts.push_back({I.ring_meta, 2 * sizeof(int64_t)});
+    }
     size_t total = 0;
     for (const auto& pr : v.parts) total += (pr.second + 255) & ~(size_t)255;
     if (hipMalloc(&v.base, total) != hipSuccess) {

@@ -33,6 +33,7 @@ EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau"
            "etd_pass_timing", "etd_plan_query", "etd_set_schedule", "etd_get_schedule", "etd_autotune",
            "etd_surface_lapinv", "etd_narrowband_build_noalloc",
            "etd_checkpoint_size", "etd_checkpoint_save", "etd_checkpoint_load",
+           "etd_diag_ring_enable", "etd_diag_ring_read",
            "etd_status_string", "etd_last_error")
 EXEC_EAGER, EXEC_GRAPH = 0, 1
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
@@ -115,6 +116,8 @@ def lib():
         L.etd_checkpoint_size.argtypes = [vp, i, C.POINTER(C.c_size_t)]
         L.etd_checkpoint_save.argtypes = [vp, i, vp, C.c_size_t]
         L.etd_checkpoint_load.argtypes = [vp, i, vp, C.c_size_t]
+        L.etd_diag_ring_enable.argtypes = [vp, i, i]
+        L.etd_diag_ring_read.argtypes = [vp, i, C.POINTER(Diag), i, C.POINTER(C.c_int64)]
         L.etd_status_string.argtypes = [i]
         L.etd_status_string.restype = C.c_char_p
         L.etd_last_error.argtypes = [vp]
@@ -292,6 +295,22 @@ class Plan:
         if st not in (ETD_OK, ETD_E_NONFINITE):
             self._c(st)
         return out
+
+    def diag_ring(self, i, capacity):
+        """Record the diagnostics of the last `capacity` steps on the device (0: off)."""
+        self._c(lib().etd_diag_ring_enable(self._ptr, i, int(capacity)))
+        if not hasattr(self, "_ring_cap"):
+            self._ring_cap = {}
+        self._ring_cap[i] = int(capacity)
+
+    def read_diag_ring(self, i, max_entries=1 << 20):
+        """(entries oldest first as dicts, steps recorded since the record started)."""
+        n = int(max_entries)
+        buf = (Diag * max(n, 1))()
+        rec = C.c_int64(0)
+        self._c(lib().etd_diag_ring_read(self._ptr, i, buf, n, C.byref(rec)))
+        k = min(rec.value, n, getattr(self, "_ring_cap", {}).get(i, 0))
+        return [{f: getattr(buf[j], f) for f, _ in Diag._fields_} for j in range(k)], rec.value
 
     def narrowband(self, i, phi, threshold, capacity=None):
         import torch

@@ -95,6 +95,8 @@ def test_null_arguments_and_status_strings():
     assert L.etd_checkpoint_size(None, 0, C.byref(n)) == etd.ETD_E_ARG
     assert L.etd_checkpoint_save(None, 0, None, 0) == etd.ETD_E_ARG
     assert L.etd_checkpoint_load(None, 0, None, 0) == etd.ETD_E_ARG
+    assert L.etd_diag_ring_enable(None, 0, 8) == etd.ETD_E_ARG
+    assert L.etd_diag_ring_read(None, 0, None, 0, None) == etd.ETD_E_ARG
     assert L.etd_plan_destroy(None) == etd.ETD_OK
     for s in range(-7, 1):
         assert L.etd_status_string(s)

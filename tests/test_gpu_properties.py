@@ -189,3 +189,42 @@ def test_checkpoint_rejects_a_different_instance():
         a.load_checkpoint(0, bad)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("mode", [etd.EXEC_EAGER, etd.EXEC_GRAPH])
+def test_diagnostics_ring_records_every_step(mode):
+    """A ring of 6 entries over 9 steps (4 eager, then 5 under the schedule
+    tested): the last 6 entries hold steps 4..9, each equal to etd_diagnostics
+    of a second plan stepped one step at a time; set_state starts the record
+    again."""
+    ci = inputs.coupled_membrane(n=32, seed=31, tau=5e-5)
+    kw = dict(scheme=etd.ETDRK2, band_threshold=0.995, band_rebuild_every=3)
+    ref = etd.Plan(etd.coupled_instance(ci, **kw))
+    ref.set_state(0, dev(ci.phi0), dev(ci.u0))
+    want = []
+    for _ in range(9):
+        ref.step(1)
+        want.append(ref.diagnostics(0))
+    ref.close()
+    plan = etd.Plan(etd.coupled_instance(ci, **kw))
+    plan.diag_ring(0, 6)
+    plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+    plan.step(4)
+    plan.set_schedule(mode, 1)
+    plan.step(5)
+    got, rec = plan.read_diag_ring(0)
+    assert rec == 9 and [d["step"] for d in got] == [4, 5, 6, 7, 8, 9]
+    for d, w in zip(got, want[3:]):
+        assert d["nonfinite"] == 0
+        for k in ("step", "int_phi", "mass", "Q", "umin", "umax", "bound", "band_count", "nonfinite"):
+            assert d[k] == w[k], (d["step"], k, d[k], w[k])
+    plan.set_state(0, dev(ci.phi0), dev(ci.u0))
+    plan.set_schedule(etd.EXEC_EAGER, 1)
+    plan.step(2)
+    got, rec = plan.read_diag_ring(0, max_entries=1)
+    assert rec == 2 and [d["step"] for d in got] == [2]
+    plan.diag_ring(0, 0)
+    with pytest.raises(etd.EtdError) as ei:
+        plan.read_diag_ring(0)
+    assert ei.value.status == etd.ETD_E_STATE
+    plan.close()
