@@ -514,9 +514,30 @@ def cpu_baseline(ci, nsteps=3):
     o.run(nsteps)
     dt = time.perf_counter() - t0
     npts = int(ci.phi0.size)
-    return {"value": nsteps * npts / dt, "unit": "grid-pt steps/s", "cores": core.get_threads(), "kind": "oracle",
-            "sample": f"the first {nsteps} ETDRK2 steps of the {ci.shape[0]}^3 workload (FP64 numpy/scipy.fft, "
-                      f"{core.get_threads()} threads), {dt:.1f} s"}
+    out = {"value": nsteps * npts / dt, "unit": "grid-pt steps/s", "cores": core.get_threads(), "kind": "oracle",
+           "sample": f"the first {nsteps} ETDRK2 steps of the {ci.shape[0]}^3 workload (FP64 numpy/scipy.fft, "
+                     f"{core.get_threads()} threads), {dt:.1f} s"}
+    # context beside it: one thread, and the oracle's own exact-index DFT, on
+    # smaller grids of the same workload family (one step each, a few seconds)
+    from paper_2606_04347_amd import inputs
+    threads, mode = core.get_threads(), core.get_dft_mode()
+    for key, n, nthr, dft in (("single_thread", 128, 1, "library"), ("naive_dft", 64, threads, "naive")):
+        core.set_threads(nthr)
+        core.set_dft_mode(dft)
+        cs = inputs.coupled_membrane(n=n, tau=ci.tau)
+        o = CoupledOracle(Grid(cs.shape, cs.half_len), cs.params, cs.tau, 2)
+        o.set_state(cs.phi0, cs.u0)
+        t0 = time.perf_counter()
+        o.run(1)
+        dt = time.perf_counter() - t0
+        # the naive DFT is a matrix product per axis: BLAS threads, not the FFT workers
+        cores = nthr if dft == "library" else int(os.environ.get("OMP_NUM_THREADS", "0") or os.cpu_count() or 1)
+        out[key] = {"value": n ** 3 / dt, "unit": "grid-pt steps/s", "cores": cores,
+                    "sample": f"one ETDRK2 step at {n}^3 ({dft} DFT, {cores} thread{'s' if cores > 1 else ''}), "
+                              f"{dt:.1f} s"}
+    core.set_threads(threads)
+    core.set_dft_mode(mode)
+    return out
 
 
 def main():
