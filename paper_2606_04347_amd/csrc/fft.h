@@ -23,6 +23,11 @@ bool fft_length_supported(int n);
 
 // Raises the dynamic-LDS limit of one kernel instantiation once (each launcher
 // instantiation owns its flag).
+// LDS of one gfx950 workgroup; every dynamic tile is checked against it at
+// compile time (the static tile tables of a kernel come on top; a launch
+// asking for more than the device holds fails rather than overrunning).
+constexpr size_t kLdsBytes = 160 * 1024;
+
 template <typename K> void set_smem_limit(K kernel, size_t bytes, std::once_flag& flag) {
     std::call_once(flag, [&] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),

@@ -114,6 +114,7 @@ hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, i
                           long estride, hipStream_t s) {
     constexpr int L = strided_lines<T, N>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     auto kern = XLINES ? k_fft_xlines<T, N, DIR> : k_fft_ylines<T, N, DIR>;
     static std::once_flag flag;
     set_smem_limit(kern, smem, flag);
@@ -129,6 +130,7 @@ hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, c
                     T scale, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
+    static_assert(z_smem<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     const int nblk = (int)((nrows + L - 1) / L);
     if (forward) {
         auto kern = k_fft_z_r2c<T, NR>;

@@ -849,6 +849,7 @@ template <typename T, int N> hipError_t launch_deriv_x(const GridK& g, const c2<
                                                        const c2<T>* tw, hipStream_t s) {
     constexpr int L = lines_per_block<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_deriv_x<T, N>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
@@ -859,6 +860,7 @@ template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A,
                                                        const c2<T>* tw, hipStream_t s) {
     constexpr int L = lines_per_block<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_deriv_y<T, N>, smem, flag);
     const int ntiles = (g.nx * g.nzh + L - 1) / L;
@@ -878,6 +880,7 @@ template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const De
                                                         const c2<T>* twf, const GridSum* isum, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
+    static_assert(z_smem<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     const int nb = (int)((nrows + L - 1) / L);
@@ -895,6 +898,7 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
                             const double* halt, const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
+    static_assert(z_smem<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_z_c2r_recover<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
@@ -908,6 +912,7 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
                       const c2<T>* twf, const GridSum& msum, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
+    static_assert(z_smem<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_q<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
@@ -923,6 +928,7 @@ hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, 
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows_pair<T, NR>();
     const size_t smem = z_smem2<T, NR>();
+    static_assert(z_smem2<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
@@ -939,12 +945,14 @@ hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, 
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
     if (f.psi_hat) {
         const size_t smem = z_smem_p2<T, NR, true>();
+        static_assert(z_smem_p2<T, NR, true>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, true>, smem, flag);
         hipLaunchKernelGGL((k_z_r2c_p2<T, NR, true>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
                            f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
     } else {
         const size_t smem = z_smem_p2<T, NR, false>();
+        static_assert(z_smem_p2<T, NR, false>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, false>, smem, flag);
         hipLaunchKernelGGL((k_z_r2c_p2<T, NR, false>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
@@ -956,6 +964,7 @@ template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* 
                                                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows<T, NR>();
     const size_t smem = z_smem<T, NR>();
+    static_assert(z_smem<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_pair<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
@@ -967,6 +976,7 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
                                                       hipStream_t s) {
     constexpr int L = lines_per_block<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_y_pair<T, N>, smem, flag);
     const int ntiles = (g.nx * g.nzh + L - 1) / L;
@@ -978,6 +988,7 @@ hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const
                         int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
     constexpr int L = xline_tile<T, N>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
@@ -990,6 +1001,7 @@ hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostr
                          const double* fdo, const double* fdc, hipStream_t s) {
     constexpr int L = lines_per_block_8<T, N, 1>();
     const size_t smem = lines_smem<T, N, L, 1>();
+    static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
     set_smem_limit(k_lapinv_lines<T, N>, smem, flag);
     const int nlines = C * nouter;
