@@ -419,25 +419,30 @@ typedef enum { ETD_EXEC_EAGER = 0, ETD_EXEC_GRAPH = 1 } etd_exec_mode;
 typedef struct {
     int mode;       /* etd_exec_mode */
     int branches;   /* concurrent capture branches (graph mode) */
+    int xlines;     /* lines per workgroup of the ETD x pass of FP32 coupled
+                       instances on 3D grids: 0 or 16 (the default tile), 8
+                       (twice the workgroups; the same arithmetic, so the same
+                       results bit for bit) */
 } etd_schedule;
 etd_status etd_set_schedule(etd_plan_t plan, const etd_schedule* sched);
 etd_status etd_get_schedule(etd_plan_t plan, etd_schedule* out);
 
 /* Schedule autotuner.  Times trial_steps (rounded up to even, >= 2) steps
  * of each candidate -- eager, then graph with 1, 2, 4, 8, 16 and 32 branches
- * (those not above the instance count) -- after two untimed warm-up steps
- * each, on the current states; then restores every instance exactly from a
- * device snapshot taken first (state fields, spectrum, derivatives, band
- * mask, device scalars, step counter), sets the fastest schedule and returns
- * it in *chosen (may be NULL).  ms_out (may be NULL) receives the per-step
- * milliseconds of the 7 candidates in that order (negative for a candidate
- * not tried).  cache_path (may be NULL) names a JSON file of earlier choices
+ * (those not above the instance count), then the fastest of these with the
+ * 8-line ETD x tile (when an FP32 coupled 3D instance takes that pass) --
+ * after two untimed warm-up steps each, on the current states; then restores
+ * every instance exactly from a device snapshot taken first (state fields,
+ * spectrum, derivatives, band mask and list, device scalars, step counter),
+ * sets the fastest schedule and returns it in *chosen (may be NULL).  ms_out
+ * (may be NULL) receives the per-step milliseconds of the 8 candidates in
+ * that order (negative for a candidate not tried).  cache_path (may be NULL) names a JSON file of earlier choices
  * keyed by the device architecture and the sorted multiset of (model,
  * scheme, precision, grid) of the instances: a hit selects the cached
  * schedule without trials (ms_out entries then negative); a miss appends the
  * new choice.  Every instance must have a state.  Allocates the snapshot
  * (about the size of the state) for the duration of the call.  Synchronizes. */
-#define ETD_AUTOTUNE_CANDIDATES 7
+#define ETD_AUTOTUNE_CANDIDATES 8
 etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path, etd_schedule* chosen,
                         double* ms_out);
 

@@ -460,7 +460,7 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const FFTTables<T>& t = tables<T>(I);
     const long n = g.nreal();
     const double fb = (double)sizeof(T) * n, mb = mask ? (double)n : 0.0;
-    const EtdArgs<T> a{nullptr, v.Sra, v.Sgu, halt_flag(I)};
+    const EtdArgs<T> a{nullptr, v.Sra, v.Sgu, halt_flag(I), I.xlines};
     hipError_t e = hipSuccess;
     const bool surface = (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
     // band solve of the nonlocal term: q and m pointwise, psi = (-Delta_S,h)^{-1} q on the band
@@ -521,12 +521,12 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     const VelocityArgs<T>* vel = g.nx > 1 ? &va : nullptr;
     const double* halt = halt_flag(I);
     if (!frozen && !rk2) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi, halt}, v.phiB,
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi, halt, I.xlines}, v.phiB,
                                   s, vel));
     } else if (!frozen) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St, halt}, v.phiB,
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St, halt, I.xlines}, v.phiB,
                                   s));
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi, halt}, v.phiB,
+        HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi, halt, I.xlines}, v.phiB,
                                   s, vel));
     }
     // phi^{n+1} and its derivatives are kept for the next step

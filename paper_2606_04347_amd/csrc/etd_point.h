@@ -63,6 +63,7 @@ template <typename T> struct EtdArgs {
     c2<T>* ra;           // stage-1 remainder R(.)^ (written by *1, read by *2)
     c2<T>* out;          // PHI*: new phi hat;  U*: increment D (U2 reads and updates it)
     const double* halt = nullptr;   // the instance's halt flag: the combine is skipped once it is set
+    int lines = 0;                  // FP32 ETD x pass: lines per workgroup (0 or 16: 16, 8: 8)
 };
 
 // Returns the stage's output value at i (PHI*: the new phi hat, U*: the

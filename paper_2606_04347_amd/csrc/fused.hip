@@ -756,12 +756,11 @@ template <typename T, int N> constexpr int xline_tile() {
 // combined spectrum still in the LDS, the inverse x transforms the next
 // passes need: the derivative triple (S, i kx S, -kx^2 S) -> (X0, X1, X2)
 // after a phi stage, the plain inverse -> X0 after a u stage.
-template <int ST, typename T, int N>
+template <int ST, typename T, int N, int L>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
                                                     EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
                                                     const c2<T>* __restrict__ tw) {
     if (halted(a.halt)) return;   // the state spectrum keeps its value
-    constexpr int L = xline_tile<T, N>();
     constexpr int LS = line_stride<N>();
     extern __shared__ unsigned char smem_raw[];
     __shared__ LineTile<L> tile;
@@ -983,18 +982,28 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
     hipLaunchKernelGGL((k_y_pair<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, X0, X1, tw);
     return hipGetLastError();
 }
-template <int ST, typename T, int N>
+template <int ST, typename T, int N, int L>
 hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
                         int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
-    constexpr int L = xline_tile<T, N>();
     const size_t smem = lines_smem<T, N, L, 1>();
     static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
     static std::once_flag flag;
-    set_smem_limit(k_x_etd<ST, T, N>, smem, flag);
+    set_smem_limit(k_x_etd<ST, T, N, L>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_x_etd<ST, T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, store_out, X0, X1,
-                       X2, tw);
+    hipLaunchKernelGGL((k_x_etd<ST, T, N, L>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, store_out, X0,
+                       X1, X2, tw);
     return hipGetLastError();
+}
+// The tile of the ETD x pass at length N: xline_tile, or 8 lines where the
+// FP32 default is 16 and the schedule asks for 8 (a.lines, autotuned).
+template <int ST, typename T, int N>
+hipError_t launch_x_etd_tiled(const GridK& g, const CoupledK& K, const c2<T>* P, const c2<T>* Q, const EtdArgs<T>& a,
+                              int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
+    constexpr int L = xline_tile<T, N>();
+    if constexpr (sizeof(T) == 4 && L == 16) {
+        if (a.lines == 8) return launch_x_etd<ST, T, N, 8>(g, K, P, Q, a, store_out, X0, X1, X2, tw, s);
+    }
+    return launch_x_etd<ST, T, N, L>(g, K, P, Q, a, store_out, X0, X1, X2, tw, s);
 }
 template <typename T, int N>
 hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostride, long es, const double* fde,
@@ -1016,7 +1025,7 @@ hipError_t dispatch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, con
                           int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2, const c2<T>* tw, hipStream_t s) {
     switch (g.nx) {
 #define CASE(n) \
-    case n: return launch_x_etd<ST, T, n>(g, K, P, Q, a, store_out, X0, X1, X2, tw, s);
+    case n: return launch_x_etd_tiled<ST, T, n>(g, K, P, Q, a, store_out, X0, X1, X2, tw, s);
         ETD_FFT_SIZES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

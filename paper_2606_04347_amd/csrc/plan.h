@@ -76,6 +76,7 @@ struct Instance {
     // kDiagRingFields doubles; ring_meta = {entries pushed, step before the first}
     double* ring = nullptr;
     int ring_cap = 0;
+    int xlines = 0;   // FP32 ETD x pass tile of this instance (the plan's schedule)
     int64_t* ring_meta = nullptr;
 };
 
@@ -124,6 +125,7 @@ struct EventHook : PassHook {
 struct ScheduleState {
     int mode = 0;       // etd_exec_mode
     int branches = 1;
+    int xlines = 0;     // FP32 ETD x pass tile: 0 (default) or 8 lines
     hipStream_t cap = nullptr;         // capture origin (default priority)
     std::vector<hipStream_t> side;     // capture branches (default priority)
     std::vector<hipEvent_t> join;      // one per branch

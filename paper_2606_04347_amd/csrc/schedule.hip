@@ -135,11 +135,15 @@ bool cache_lookup(const std::string& path, const std::string& key, etd_schedule*
     const std::string tag = "\"" + key + "\": {";
     const size_t p = txt.find(tag);
     if (p == std::string::npos) return false;
-    int mode = -1, branches = -1;
-    if (sscanf(txt.c_str() + p + tag.size(), " \"mode\": %d, \"branches\": %d", &mode, &branches) != 2) return false;
+    int mode = -1, branches = -1, xlines = 0;
+    const int got = sscanf(txt.c_str() + p + tag.size(), " \"mode\": %d, \"branches\": %d, \"xlines\": %d", &mode,
+                           &branches, &xlines);
+    if (got < 2) return false;   // entries without the tile field keep the default tile
     if ((mode != ETD_EXEC_EAGER && mode != ETD_EXEC_GRAPH) || branches < 1 || branches > 64) return false;
+    if (xlines != 0 && xlines != 8 && xlines != 16) return false;
     out->mode = mode;
     out->branches = branches;
+    out->xlines = xlines;
     return true;
 }
 
@@ -153,8 +157,9 @@ void cache_store(const std::string& path, const std::string& key, const etd_sche
             txt = ss.str();
         }
     }
-    char entry[64];
-    snprintf(entry, sizeof entry, "{\"mode\": %d, \"branches\": %d}", s.mode, s.branches);
+    char entry[96];
+    snprintf(entry, sizeof entry, "{\"mode\": %d, \"branches\": %d, \"xlines\": %d}", s.mode, s.branches,
+             s.xlines);
     const std::string line = "\"" + key + "\": " + entry;
     const size_t close = txt.rfind('}');
     if (close == std::string::npos || txt.find(':') == std::string::npos) {
@@ -299,10 +304,14 @@ etd_status etd_set_schedule(etd_plan_t plan, const etd_schedule* sched) {
         return fail(&plan->err, ETD_E_ARG, "schedule mode must be ETD_EXEC_EAGER or ETD_EXEC_GRAPH");
     if (sched->branches < 1 || sched->branches > 64)
         return fail(&plan->err, ETD_E_ARG, "schedule branches must be in 1..64");
+    if (sched->xlines != 0 && sched->xlines != 8 && sched->xlines != 16)
+        return fail(&plan->err, ETD_E_ARG, "schedule xlines must be 0, 8 or 16");
     HIPCHK(plan, hipStreamSynchronize(plan->stream));
     drop_graphs(plan);
     plan->sched.mode = sched->mode;
     plan->sched.branches = sched->branches;
+    plan->sched.xlines = sched->xlines == 16 ? 0 : sched->xlines;
+    for (Instance& I : plan->inst) I.xlines = plan->sched.xlines;
     return ETD_OK;
 }
 
@@ -310,6 +319,7 @@ etd_status etd_get_schedule(etd_plan_t plan, etd_schedule* out) {
     if (!plan || !out) return fail(plan ? &plan->err : nullptr, ETD_E_ARG, "null argument");
     out->mode = plan->sched.mode;
     out->branches = plan->sched.branches;
+    out->xlines = plan->sched.xlines;
     return ETD_OK;
 }
 
@@ -319,10 +329,15 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
     if (trial_steps < 0) return fail(&plan->err, ETD_E_ARG, "trial_steps must be >= 0");
     for (const Instance& I : plan->inst)
         if (!I.has_state) return fail(&plan->err, ETD_E_STATE, "autotune before set_state");
-    const etd_schedule cand[ETD_AUTOTUNE_CANDIDATES] = {{ETD_EXEC_EAGER, 1}, {ETD_EXEC_GRAPH, 1},
-                                                         {ETD_EXEC_GRAPH, 2},  {ETD_EXEC_GRAPH, 4},
-                                                         {ETD_EXEC_GRAPH, 8},  {ETD_EXEC_GRAPH, 16},
-                                                         {ETD_EXEC_GRAPH, 32}};
+    // the schedules, then the fastest of them with 8-line tiles in the FP32
+    // ETD x pass (only where an instance takes that pass)
+    etd_schedule cand[ETD_AUTOTUNE_CANDIDATES] = {{ETD_EXEC_EAGER, 1, 0}, {ETD_EXEC_GRAPH, 1, 0},
+                                                   {ETD_EXEC_GRAPH, 2, 0},  {ETD_EXEC_GRAPH, 4, 0},
+                                                   {ETD_EXEC_GRAPH, 8, 0},  {ETD_EXEC_GRAPH, 16, 0},
+                                                   {ETD_EXEC_GRAPH, 32, 0}, {ETD_EXEC_EAGER, 1, 8}};
+    bool tile_knob = false;
+    for (const Instance& I : plan->inst)
+        tile_knob = tile_knob || (I.d.model == ETD_COUPLED && I.f32 && I.g.nx > 1);
     if (ms_out)
         for (int c = 0; c < ETD_AUTOTUNE_CANDIDATES; ++c) ms_out[c] = -1.0;
     hipDeviceProp_t prop;
@@ -350,7 +365,7 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
             return st;
         }
     }
-    const etd_schedule old{plan->sched.mode, plan->sched.branches};
+    const etd_schedule old{plan->sched.mode, plan->sched.branches, plan->sched.xlines};
     double best_ms = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     etd_status st = ETD_OK;
@@ -358,6 +373,11 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
         st = fail(&plan->err, ETD_E_HIP, "autotune: hipEventCreate failed");
     for (int c = 0; c < ETD_AUTOTUNE_CANDIDATES && st == ETD_OK; ++c) {
         if (cand[c].mode == ETD_EXEC_GRAPH && cand[c].branches > 1 && cand[c].branches > ninst) continue;
+        if (cand[c].xlines == 8) {   // the last candidate: the best schedule so far, 8-line tiles
+            if (!tile_knob) continue;
+            cand[c].mode = best.mode;
+            cand[c].branches = best.branches;
+        }
         if ((st = etd_set_schedule(plan, &cand[c])) != ETD_OK) break;
         if ((st = run_steps(plan, 2)) != ETD_OK) break;   // warm-up (captures the graph)
         float ms = 0.f;

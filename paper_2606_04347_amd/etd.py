@@ -37,7 +37,7 @@ EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau"
            "etd_status_string", "etd_last_error")
 EXEC_EAGER, EXEC_GRAPH = 0, 1
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
-                       ("graph", 32))
+                       ("graph", 32), ("best_xlines", 8))
 PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
               "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover",
               "band", "r1_stencil", "p2_stencil", "pointwise", "reduce", "fixed_stencil", "fixed_pointwise",
@@ -75,7 +75,7 @@ class PassTimes(C.Structure):
 
 
 class Schedule(C.Structure):
-    _fields_ = [("mode", C.c_int), ("branches", C.c_int)]
+    _fields_ = [("mode", C.c_int), ("branches", C.c_int), ("xlines", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -358,14 +358,21 @@ class Plan:
         self._c(lib().etd_plan_query(self._ptr, i, int(what), C.byref(v)))
         return v.value
 
-    def set_schedule(self, mode, branches=1):
-        """Step schedule: EXEC_EAGER, or EXEC_GRAPH with `branches` concurrent capture branches."""
-        self._c(lib().etd_set_schedule(self._ptr, C.byref(Schedule(int(mode), int(branches)))))
+    def set_schedule(self, mode, branches=1, xlines=0):
+        """Step schedule: EXEC_EAGER, or EXEC_GRAPH with `branches` concurrent capture branches;
+        xlines: the FP32 ETD x-pass tile (0 or 16: default, 8)."""
+        self._c(lib().etd_set_schedule(self._ptr, C.byref(Schedule(int(mode), int(branches), int(xlines)))))
 
     def get_schedule(self):
+        """(mode, branches); the tile is get_xlines()."""
         s = Schedule()
         self._c(lib().etd_get_schedule(self._ptr, C.byref(s)))
         return s.mode, s.branches
+
+    def get_xlines(self):
+        s = Schedule()
+        self._c(lib().etd_get_schedule(self._ptr, C.byref(s)))
+        return s.xlines
 
     def autotune(self, trial_steps=10, cache_path=None):
         """Time the candidate schedules, keep the fastest; returns (mode, branches, {candidate: ms/step})."""

@@ -110,7 +110,9 @@ def test_schedule_rejects_bad_arguments():
         plan.set_schedule(etd.EXEC_GRAPH, 0)
     with pytest.raises(etd.EtdError):
         plan.set_schedule(etd.EXEC_GRAPH, 65)
-    assert plan.get_schedule() == (etd.EXEC_EAGER, 1)
+    with pytest.raises(etd.EtdError):
+        plan.set_schedule(etd.EXEC_EAGER, 1, xlines=4)
+    assert plan.get_schedule() == (etd.EXEC_EAGER, 1) and plan.get_xlines() == 0
     plan.close()
 
 
@@ -131,7 +133,8 @@ def test_autotune_restores_state_and_uses_cache(tmp_path):
     for i in range(len(b)):
         assert plan.diagnostics(i)["step"] == 2
     rec = json.loads(cache.read_text())
-    assert len(rec) == 1 and list(rec.values())[0] == {"mode": mode, "branches": branches}
+    assert len(rec) == 1 and list(rec.values())[0] == {"mode": mode, "branches": branches,
+                                                       "xlines": plan.get_xlines()}
     # a second plan of the same mix takes the cached choice without trials
     other = make_plan(b)
     m2, b2, t2 = other.autotune(trial_steps=4, cache_path=str(cache))
@@ -214,3 +217,20 @@ def test_uneven_batch_matches_oracle(precision):
                    err_gu=egu, flips=int(flips[i].sum()))
             assert ephi <= 1e-4 and eu <= 1e-4 and egu <= 1e-4
     plan.close()
+
+
+@pytest.mark.parametrize("mode", [etd.EXEC_EAGER, etd.EXEC_GRAPH])
+def test_eight_line_etd_tile_steps_alike(mode):
+    """The FP32 ETD x pass with 8 instead of 16 lines per workgroup (the
+    autotuner's tile candidate) runs the same per-line arithmetic: the states
+    agree bit for bit with the default tile."""
+    b = batch()
+    runs = []
+    for xl in (0, 8):
+        plan = make_plan(b)
+        plan.set_schedule(mode, 2, xlines=xl)
+        assert plan.get_xlines() == xl
+        plan.step(4)
+        runs.append(states(plan, len(b)))
+        plan.close()
+    assert_same(runs[1], runs[0])
