@@ -15,10 +15,13 @@ namespace etd {
 namespace stk {
 
 // Rows per workgroup of the z passes: 8 at lengths >= 512 and in FP64 at 256
-// (measured faster), 16 in FP32 at 256, 4096 / NR below.  The two-field
-// forward (z_rows_pair) takes 8 in FP32 at 256 too: its LDS holds both fields.
+// (measured faster), 16 in FP32 at 256 and below (4096 / NR for the shortest
+// rows): at 64^3 the 64-row tiles of 4096 / NR left 64 workgroups per pass,
+// and 16 rows took the FP32 step from 0.246 to 0.199 ms (96^3: 0.344 to
+// 0.292).  The two-field forward (z_rows_pair) takes 8 in FP32 at 256 too:
+// its LDS holds both fields.
 template <typename T, int NR> constexpr int z_rows() {
-    return NR >= 512 ? 8 : (NR >= 256 ? (sizeof(T) == 8 ? 8 : 16) : (4096 / NR));
+    return NR >= 512 ? 8 : (NR >= 256 ? (sizeof(T) == 8 ? 8 : 16) : (4096 / NR > 16 ? 16 : 4096 / NR));
 }
 template <typename T, int NR> constexpr int z_rows_pair() { return NR >= 256 ? 8 : z_rows<T, NR>(); }
 template <int NR> constexpr int z_row_stride() { return line_stride<NR / 2 + 1>(); }
