@@ -25,6 +25,18 @@
  *     reported (ETD_E_ARG / ETD_E_SIZE / ETD_E_STATE) even without a GPU.
  *   - A plan is not thread safe; distinct plans on distinct streams are
  *     independent.
+ *
+ * Environment (read once per process)
+ *   ETD_LOG             host log to stderr: 0 (default) quiet, 1 every error
+ *                       status with its message, 2 also plan creation, graph
+ *                       captures and the autotuner's trials and choice.
+ *   ETD_ROCTX           1 (default): roctx ranges around each step and its
+ *                       stages (etd.phi1 / etd.phi2 / etd.u1 / etd.u2, the
+ *                       band rebuild and band solve, the two fixed-membrane
+ *                       stages), visible to rocprofv3 --marker-trace; they
+ *                       span the host enqueue of the stage.  0 turns them off.
+ *   ETD_AUTOTUNE_CACHE  the schedule cache of etd_autotune when its
+ *                       cache_path argument is NULL or empty.
  */
 #ifndef ETD_H
 #define ETD_H
@@ -386,7 +398,8 @@ etd_status etd_plan_query(etd_plan_t plan, int instance, etd_query what, double*
  * constants are then the only null space).  g (> 0 on the band), f and psi
  * are device arrays in the grid layout of the instance, element type dtype
  * (psi may alias f).  FP64 conjugate gradients from psi = 0, preconditioned
- * by a 16-term Chebyshev polynomial of the Jacobi-scaled operator, until the
+ * by a 16-term Chebyshev polynomial of the Jacobi-scaled operator (its
+ * vectors stored in the precision of dtype, its arithmetic FP64), until the
  * residual relative to f - mean_band(f) is <= tol or after max_iter
  * iterations (f constant on the band: psi = 0 at once); *iters_out and
  * *relres_out (host, nullable) report the outcome -- not converging is
@@ -436,8 +449,8 @@ etd_status etd_get_schedule(etd_plan_t plan, etd_schedule* out);
  * spectrum, derivatives, band mask and list, device scalars, step counter),
  * sets the fastest schedule and returns it in *chosen (may be NULL).  ms_out
  * (may be NULL) receives the per-step milliseconds of the 8 candidates in
- * that order (negative for a candidate not tried).  cache_path (may be NULL) names a JSON file of earlier choices
- * keyed by the device architecture and the sorted multiset of (model,
+ * that order (negative for a candidate not tried).  cache_path (NULL or empty: the environment's
+ * ETD_AUTOTUNE_CACHE, else no cache) names a JSON file of earlier choices keyed by the device architecture and the sorted multiset of (model,
  * scheme, precision, grid) of the instances: a hit selects the cached
  * schedule without trials (ms_out entries then negative); a miss appends the
  * new choice.  Every instance must have a state.  Allocates the snapshot

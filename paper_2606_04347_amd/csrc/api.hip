@@ -2,9 +2,13 @@
 // schedules of both models, Chebyshev set-up, energies and diagnostics.
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -18,10 +22,43 @@ namespace etd {
 
 std::string g_last_error = "";
 
+namespace {
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+}  // namespace
+
+int log_level() {
+    static const int level = std::min(2, std::max(0, env_int("ETD_LOG", 0)));
+    return level;
+}
+
+void log_msg(int level, const char* fmt, ...) {
+    if (level > log_level()) return;
+    std::fprintf(stderr, "[etd] ");
+    va_list ap;
+    va_start(ap, fmt);
+    std::vfprintf(stderr, fmt, ap);
+    va_end(ap);
+    std::fputc('\n', stderr);
+}
+
 etd_status fail(std::string* sink, etd_status st, const std::string& msg) {
     g_last_error = msg;
     if (sink) *sink = msg;
+    log_msg(1, "error %d: %s", (int)st, msg.c_str());
     return st;
+}
+
+StageRange::StageRange(const char* name) {
+    static const bool enabled = env_int("ETD_ROCTX", 1) != 0;
+    on_ = enabled;
+    if (on_) roctxRangePushA(name);
+}
+
+StageRange::~StageRange() {
+    if (on_) roctxRangePop();
 }
 
 }  // namespace etd
@@ -465,6 +502,7 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     const bool surface = (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
     // band solve of the nonlocal term: q and m pointwise, psi = (-Delta_S,h)^{-1} q on the band
     auto surface_psi = [&]() -> hipError_t {
+        StageRange r("etd.band_solve");
         timed_kernel(PASS_POINT, 3.0 * fb + mb, s, [&] {
             coupled_q_gu<T>(g, I.K, uu, v.gp, mask, v.P, nullptr, I.part, I.scal + S_MASS, halt_flag(I), s);
         });
@@ -503,6 +541,7 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     const uint8_t* mask = nullptr;
     if (I.d.band_threshold > 0.0) {
         if (I.step % I.d.band_rebuild_every == 0) {
+            StageRange r("etd.band_rebuild");
             timed_kernel(PASS_BAND, (sizeof(T) + 2.0) * n, s, [&] {
                 band_flags<T>(n, v.phiA, I.d.band_threshold, I.mask, s);
                 band_compact(n, I.mask, I.band_cnt, I.band_idx, n, I.band_total, s);
@@ -521,11 +560,16 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     const VelocityArgs<T>* vel = g.nx > 1 ? &va : nullptr;
     const double* halt = halt_flag(I);
     if (!frozen && !rk2) {
+        StageRange r("etd.phi (S1 S4)");
         HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.Sphi, halt, I.xlines}, v.phiB,
                                   s, vel));
     } else if (!frozen) {
-        HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St, halt, I.xlines}, v.phiB,
-                                  s));
+        {
+            StageRange r("etd.phi1 (S1 S2)");
+            HIPCHK(plan, phi_stage<T>(I, v, v.phiA, mask, ETD_STAGE_PHI1, EtdArgs<T>{v.Sphi, v.Sra, v.St, halt, I.xlines},
+                                      v.phiB, s));
+        }
+        StageRange r("etd.phi2 (S3 S4)");
         HIPCHK(plan, phi_stage<T>(I, v, v.phiB, mask, ETD_STAGE_PHI2, EtdArgs<T>{v.St, v.Sra, v.Sphi, halt, I.xlines}, v.phiB,
                                   s, vel));
     }
@@ -540,13 +584,19 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
     // inverse transforms carry only the per-step change; g+ u^n is added back in
     // real space inside the recovery (same scheme, smaller rounding in FP32).
     if (!rk2) {
+        StageRange r("etd.u1 (S5 S6)");
         HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, false, v.ut, s));     // U^{n+1}
         std::swap(I.u, I.ut);
     } else {
-        HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, true, v.ut, s));      // U~
+        {
+            StageRange r("etd.u1 (S5 S6)");
+            HIPCHK(plan, u_stage<T>(I, v, v.u, mask, ETD_STAGE_U1, true, v.ut, s));      // U~
+        }
+        StageRange r("etd.u2 (S7 S8)");
         HIPCHK(plan, u_stage<T>(I, v, v.ut, mask, ETD_STAGE_U2, false, v.u, s));     // U^{n+1}
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
+        StageRange r("etd.mass_project");
         timed_kernel(PASS_POINT, 5.0 * fb, s, [&] {
             mass_project_sums<T>(n, v.gp, (T*)I.u, I.K.thr, I.part, I.scal + S_MPS, s);
             mass_project_apply<T>(n, v.gp, (T*)I.u, I.K.thr, g.cell, I.scal + S_Q0, I.scal + S_MPS, halt, s);
@@ -564,6 +614,7 @@ template <typename T> etd_status step_coupled(etd_plan* plan, Instance& I, hipSt
 etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStream_t s) {
     const GridK& g = I.g;
     if (I.d.flags & ETD_F_SURFACE_NONLOCAL) {
+        StageRange r("etd.band_solve");
         HIPCHK(plan, surface_lapinv<double>(g, I.G, q, I.mask, I.band_idx, I.band_total, I.psid, I.sw, 1e-12, 20000,
                                             true, &I.surf_last, s));
     } else if (!I.f32) {
@@ -640,6 +691,7 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     etd_status st;
     // w = sg U;  v = R(U) - L w;  w~ = w + tau phi1(tau L) v
     const double fb = 8.0 * n;
+    StageRange r1("etd.fixed.stage1");
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { mul(n, I.sg, I.U, I.w, s); });
     if ((st = fixed_R(plan, I, I.U, I.R0, s)) != ETD_OK) return st;
     timed_kernel(PASS_FIXED_STENCIL, 4.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.gf, I.isg, I.w, I.vv, s); });
@@ -651,6 +703,7 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
         mul(n, I.isg, I.w, I.U, s, halt_flag(I), band);   // U = w~ / sg  (ETD1 result / predictor)
     });
     if (I.d.scheme == ETD_ETDRK2) {
+        StageRange r2("etd.fixed.stage2");
         if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
         timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R1, -1.0, I.R0, I.vv, s); });
         cheb_apply(I, I.ch2, I.vv, I.acc, s);
@@ -783,6 +836,7 @@ void diag_sums(Instance& I, hipStream_t s) {
 }  // namespace
 
 etd_status etd::step_instance(etd_plan* plan, Instance& I, hipStream_t s) {
+    StageRange r("etd.step");
     etd_status st = I.d.model == ETD_COUPLED ? (I.f32 ? step_coupled<float>(plan, I, s)
                                                        : step_coupled<double>(plan, I, s))
                                              : step_fixed(plan, I, s);
@@ -855,6 +909,18 @@ etd_status etd_plan_create(const etd_instance_desc* inst, int n_instances, void*
         }
     }
     *out = P;
+    if (log_level() >= 2) {
+        size_t bytes = 0;
+        for (const Instance& I : P->inst) bytes += I.bytes;
+        log_msg(2, "plan %p: %d instance(s), %.1f MiB of device memory", (void*)P, n_instances,
+                bytes / 1048576.0);
+        for (int i = 0; i < n_instances; ++i) {
+            const Instance& I = P->inst[i];
+            log_msg(2, "  instance %d: %s %s %s %dx%dx%d tau %g band %g", i,
+                    I.d.model == ETD_COUPLED ? "coupled" : "fixed", I.d.scheme == ETD_ETDRK2 ? "ETDRK2" : "ETD1",
+                    I.f32 ? "fp32" : "fp64", I.g.nx, I.g.ny, I.g.nz, I.d.tau, I.d.band_threshold);
+        }
+    }
     return ETD_OK;
 }
 

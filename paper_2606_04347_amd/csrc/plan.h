@@ -18,8 +18,28 @@ namespace etd {
 // Last error message of any plan (etd_last_error(NULL)).
 extern std::string g_last_error;
 
-// Record msg as the last error (and in *sink) and return st.
+// Record msg as the last error (and in *sink) and return st; with ETD_LOG >= 1
+// the message also goes to stderr.
 etd_status fail(std::string* sink, etd_status st, const std::string& msg);
+
+// Host logging to stderr.  ETD_LOG, read once per process: 0 (default) quiet,
+// 1 errors, 2 also plan creation, graph captures and autotuner decisions.
+int log_level();
+void log_msg(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// A roctx range (rocprofv3 --marker-trace) around one stage of a step on the
+// host: it spans the enqueue of the stage's kernels (under graph capture, the
+// capture).  ETD_ROCTX=0 turns the ranges off.
+class StageRange {
+  public:
+    explicit StageRange(const char* name);
+    ~StageRange();
+    StageRange(const StageRange&) = delete;
+    StageRange& operator=(const StageRange&) = delete;
+
+  private:
+    bool on_;
+};
 
 // device scalar slots
 enum Slot {

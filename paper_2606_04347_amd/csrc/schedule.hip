@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -106,6 +107,9 @@ etd_status capture_two_steps(etd_plan* plan, hipGraphExec_t* out) {
             bad = fail(&plan->err, ETD_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     }
     if (graph) (void)hipGraphDestroy(graph);
+    if (bad == ETD_OK)
+        log_msg(2, "plan %p: captured two steps of %zu instance(s) on %d branch(es)", (void*)plan, plan->inst.size(),
+                nb);
     return bad;
 }
 
@@ -344,7 +348,14 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
     HIPCHK(plan, hipGetDeviceProperties(&prop, plan->device));
     const std::string key = std::string(prop.gcnArchName) + "|" + instance_signature(plan);
     etd_schedule best{ETD_EXEC_EAGER, 1};
+    // the cache file: the argument, else the environment's ETD_AUTOTUNE_CACHE
+    if (!cache_path || !*cache_path) {
+        const char* env = std::getenv("ETD_AUTOTUNE_CACHE");
+        cache_path = (env && *env) ? env : nullptr;
+    }
     if (cache_path && cache_lookup(cache_path, key, &best)) {
+        log_msg(2, "autotune %s: cached mode %d, %d branch(es), %d-line x tile (%s)", key.c_str(), best.mode,
+                best.branches, best.xlines ? best.xlines : 16, cache_path);
         etd_status st = etd_set_schedule(plan, &best);
         if (st == ETD_OK && chosen) *chosen = best;
         return st;
@@ -388,6 +399,8 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
             st = fail(&plan->err, ETD_E_HIP, "autotune: event timing");
         if (st != ETD_OK) break;
         const double per = ms / trial;
+        log_msg(2, "autotune candidate %d (mode %d, %d branch(es), %d-line x tile): %.4f ms/step", c, cand[c].mode,
+                cand[c].branches, cand[c].xlines ? cand[c].xlines : 16, per);
         if (ms_out) ms_out[c] = per;
         if (best_ms < 0.0 || per < best_ms) {
             best_ms = per;
@@ -412,6 +425,8 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
     st = etd_set_schedule(plan, &best);
     if (st != ETD_OK) return st;
     if (chosen) *chosen = best;
+    log_msg(2, "autotune %s: chose mode %d, %d branch(es), %d-line x tile", key.c_str(), best.mode, best.branches,
+            best.xlines ? best.xlines : 16);
     if (cache_path) cache_store(cache_path, key, best);
     return ETD_OK;
 }

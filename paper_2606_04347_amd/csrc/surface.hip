@@ -1,6 +1,7 @@
 // (-Delta_S,h)^{-1} on a narrow band by preconditioned conjugate gradients
 // (Section 2.1 operator:diff and the pseudo-inverse on mean-zero functions;
-// Section 3.2 narrow band).  FP64 throughout.
+// Section 3.2 narrow band).  FP64 iteration; the preconditioner's vectors
+// are stored in the precision of the fields (ChebStart).
 //
 // Unknowns: the band nodes (mask != 0), listed in idx[0 .. *total).  Row i of
 // the band matrix A is sum_{j band neighbour} w_ij (psi_i - psi_j) with
@@ -126,7 +127,7 @@ template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __restrict__ gm,
                                                          const T* __restrict__ f,
                                                          const int32_t* __restrict__ idx,
-                                                         const int64_t* __restrict__ total, double* dinv,
+                                                         const int64_t* __restrict__ total, T* dinv,
                                                          double* part) {
     const long nb = *total;
     Neu acc;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
             const T gj = gm[j];
             if (gj >= (T)0) d += 0.5 * (gi + (double)gj) * ih2;
         });
-        dinv[k] = d > 0.0 ? 1.0 / d : 0.0;
+        dinv[k] = (T)(d > 0.0 ? 1.0 / d : 0.0);
         acc.add((double)f[i]);
     });
     store_partials(acc.val(), 0.0, 0.0, part);
@@ -147,19 +148,26 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_setup(BandGeom b, const T* __
 // First term of the preconditioner for node k (band order), i = idx[k]:
 // residual c = D^-1 r, direction d0 = c / theta (grid layout), z = d0; with
 // a one-term polynomial z is the preconditioned residual u itself.
-struct ChebStart {
+// The preconditioner's vectors (D^-1, the Chebyshev residual, sum and
+// directions) are stored in P: FP32 for FP32 fields, where the solve takes
+// a residual of 1e-9 at most, FP64 otherwise; their arithmetic is FP64 and
+// u, the preconditioned residual handed to the iteration, is FP64.  A
+// preconditioner only steers the search directions (the residual the
+// iteration stops on is updated in FP64), so its rounding changes the
+// iteration count, not the residual reached.
+template <typename P> struct ChebStart {
     double inv_theta;
     int single;
-    double* cres;
-    double* cz;
-    double* d0;
+    P* cres;
+    P* cz;
+    P* d0;
     double* u;
     __device__ __forceinline__ void operator()(long k, long i, double rk, double dk) const {
         const double c = rk * dk;
         const double d = c * inv_theta;
-        cres[k] = c;
-        cz[k] = d;
-        d0[i] = d;
+        cres[k] = (P)c;
+        cz[k] = (P)d;
+        d0[i] = (P)d;
         if (single) u[i] = d;
     }
 };
@@ -172,8 +180,8 @@ template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_init(BandGeom bg, const T* __restrict__ gm, const T* __restrict__ f,
                                                         const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total,
-                                                        const double* __restrict__ dinv, double* S, double* x,
-                                                        double* r, double* p, double* sv, ChebStart cs, int warm,
+                                                        const T* __restrict__ dinv, double* S, double* x,
+                                                        double* r, double* p, double* sv, ChebStart<T> cs, int warm,
                                                         double* part) {
     const long nb = *total;
     const double mean = S[SB_MEAN];
@@ -195,7 +203,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_init(BandGeom bg, const T* __
         }
         bb.add(bk * bk);
         r[k] = rk;
-        cs(k, i, rk, dinv[k]);
+        cs(k, i, rk, (double)dinv[k]);
         p[k] = 0.0;
         sv[k] = 0.0;
     });
@@ -210,25 +218,25 @@ template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_cheb(BandGeom b, const T* __restrict__ gm,
                                                         const int32_t* __restrict__ idx,
                                                         const int64_t* __restrict__ total, const double* S,
-                                                        const double* __restrict__ dinv,
-                                                        const double* __restrict__ dprev, double* dnext, double* cres,
-                                                        double* cz, double c1, double c2, int last, double* u) {
+                                                        const T* __restrict__ dinv, const T* __restrict__ dprev,
+                                                        T* dnext, T* cres, T* cz, double c1, double c2, int last,
+                                                        double* u) {
     if (sb_done(S)) return;
     const long nb = *total;
     band_for(nb, [&](long k) {
         const long i = idx[k];
-        const double gi = (double)gm[i], di = dprev[i];
+        const double gi = (double)gm[i], di = (double)dprev[i];
         double a = 0.0;
         for_neighbours(b, i, [&](long j, double ih2) {
             const T gj = gm[j];
-            if (gj >= (T)0) a += 0.5 * (gi + (double)gj) * ih2 * (di - dprev[j]);
+            if (gj >= (T)0) a += 0.5 * (gi + (double)gj) * ih2 * (di - (double)dprev[j]);
         });
-        const double c = cres[k] - dinv[k] * a;
-        cres[k] = c;
+        const double c = (double)cres[k] - (double)dinv[k] * a;
+        cres[k] = (T)c;
         const double d = c1 * di + c2 * c;
-        dnext[i] = d;
-        const double z = cz[k] + d;
-        cz[k] = z;
+        dnext[i] = (T)d;
+        const double z = (double)cz[k] + d;
+        cz[k] = (T)z;
         if (last) u[i] = z;
     });
 }
@@ -262,11 +270,12 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_matvec(BandGeom b, const T* _
 
 // p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, the
 // preconditioner's first term of the new r.
+template <typename T>
 __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __restrict__ idx,
                                                            const int64_t* __restrict__ total,
-                                                           const double* __restrict__ dinv, const double* S,
+                                                           const T* __restrict__ dinv, const double* S,
                                                            double* x, const double* u, double* r, double* p,
-                                                           double* sv, const double* __restrict__ w, ChebStart cs) {
+                                                           double* sv, const double* __restrict__ w, ChebStart<T> cs) {
     if (sb_done(S)) return;
     const long nb = *total;
     const double alpha = S[SB_ALPHA], beta = S[SB_BETA];
@@ -279,7 +288,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_vectors(const int32_t* __rest
         x[i] += alpha * pk;
         const double rk = r[k] - alpha * sk;
         r[k] = rk;
-        cs(k, i, rk, dinv[k]);
+        cs(k, i, rk, (double)dinv[k]);
     });
 }
 
@@ -435,14 +444,20 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
         c2[j] = 2.0 * rn / delta;
         rho = rn;
     }
-    const ChebStart cs{1.0 / theta, terms == 1 ? 1 : 0, w.cres, w.cz, w.dA, w.u};
-    T* gm = reinterpret_cast<T*>(w.gm);   // n values of T in a slot of n doubles
+    // n values of T in slots of n doubles: g on the band and the preconditioner's vectors
+    T* gm = reinterpret_cast<T*>(w.gm);
+    T* dinv = reinterpret_cast<T*>(w.dinv);
+    T* cres = reinterpret_cast<T*>(w.cres);
+    T* cz = reinterpret_cast<T*>(w.cz);
+    T* dA = reinterpret_cast<T*>(w.dA);
+    T* dB = reinterpret_cast<T*>(w.dB);
+    const ChebStart<T> cs{1.0 / theta, terms == 1 ? 1 : 0, cres, cz, dA, w.u};
     auto precond = [&]() {   // terms 1 .. terms - 1 (term 0 is formed with r)
         for (int j = 1; j < terms; ++j) {
-            double* dp = (j % 2 == 1) ? w.dA : w.dB;
-            double* dn = (j % 2 == 1) ? w.dB : w.dA;
-            hipLaunchKernelGGL(k_sb_cheb<T>, grid, blk, 0, s, b, gm, idx, total, w.S, w.dinv, dp, dn, w.cres,
-                               w.cz, c1[j], c2[j], j == terms - 1 ? 1 : 0, w.u);
+            T* dp = (j % 2 == 1) ? dA : dB;
+            T* dn = (j % 2 == 1) ? dB : dA;
+            hipLaunchKernelGGL(k_sb_cheb<T>, grid, blk, 0, s, b, gm, idx, total, w.S, dinv, dp, dn, cres, cz, c1[j],
+                               c2[j], j == terms - 1 ? 1 : 0, w.u);
         }
     };
     auto fin = [&](int mode) {
@@ -454,9 +469,9 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     const long n = g.nreal();
     const int nbo = (int)std::min<long>(4096, (n + kSbThreads - 1) / kSbThreads);
     hipLaunchKernelGGL(k_sb_gm<T>, dim3(nbo), blk, 0, s, n, G, mask, gm);
-    hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, gm, f, idx, total, w.dinv, w.part);
+    hipLaunchKernelGGL(k_sb_setup<T>, grid, blk, 0, s, b, gm, f, idx, total, dinv, w.part);
     fin(FIN_MEAN);
-    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, b, gm, f, idx, total, w.dinv, w.S, w.x, w.r, w.p, w.s, cs,
+    hipLaunchKernelGGL(k_sb_init<T>, grid, blk, 0, s, b, gm, f, idx, total, dinv, w.S, w.x, w.r, w.p, w.s, cs,
                        warm ? 1 : 0, w.part);
     fin(FIN_BNORM);
     precond();
@@ -470,7 +485,7 @@ hipError_t surface_lapinv(const GridK& g, const T* G, const T* f, const uint8_t*
     double done = 0.0;
     for (int it = 0; it < max_iter && done == 0.0; it += kChunk) {
         for (int j = 0; j < kChunk && it + j < max_iter; ++j) {
-            hipLaunchKernelGGL(k_sb_vectors, grid, blk, 0, s, idx, total, w.dinv, w.S, w.x, w.u, w.r, w.p, w.s,
+            hipLaunchKernelGGL(k_sb_vectors<T>, grid, blk, 0, s, idx, total, dinv, w.S, w.x, w.u, w.r, w.p, w.s,
                                w.w, cs);
             precond();
             matvec();

@@ -375,7 +375,8 @@ class Plan:
         return s.xlines
 
     def autotune(self, trial_steps=10, cache_path=None):
-        """Time the candidate schedules, keep the fastest; returns (mode, branches, {candidate: ms/step})."""
+        """Time the candidate schedules, keep the fastest; returns (mode, branches, {candidate: ms/step}).
+        cache_path None: the ETD_AUTOTUNE_CACHE file of the environment, if set."""
         s = Schedule()
         ms = (C.c_double * len(AUTOTUNE_CANDIDATES))()
         path = None if cache_path is None else os.fsencode(cache_path)

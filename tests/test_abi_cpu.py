@@ -133,3 +133,24 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         assert got[cname] == want, cname
     assert got["pass_kinds"] == etd.N_PASS_SLOTS
     assert got["autotune"] == len(etd.AUTOTUNE_CANDIDATES)
+
+
+def test_etd_log_reports_errors_on_stderr():
+    """ETD_LOG=1 sends every error status with its message to stderr; the
+    default is quiet (each run in a fresh process: the level is read once)."""
+    import subprocess
+    import sys
+    code = ("import ctypes as C\n"
+            "from paper_2606_04347_amd import etd\n"
+            "p = C.c_void_p()\n"
+            "assert etd.lib().etd_plan_create(None, 1, None, C.byref(p)) == etd.ETD_E_ARG\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = {}
+    for level in ("0", "1"):
+        env = dict(os.environ, ETD_LOG=level)
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        outs[level] = r.stderr
+    assert "[etd]" not in outs["0"]
+    assert f"[etd] error {etd.ETD_E_ARG}: need at least one instance descriptor" in outs["1"]

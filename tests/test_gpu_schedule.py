@@ -150,6 +150,24 @@ def test_autotune_restores_state_and_uses_cache(tmp_path):
     ref.close()
 
 
+def test_autotune_cache_from_the_environment(tmp_path, monkeypatch):
+    """With no cache_path, etd_autotune keeps its choice in the file that
+    ETD_AUTOTUNE_CACHE names, and a second plan of the same mix reads it back
+    without trials."""
+    b = batch()[:2]
+    cache = tmp_path / "env_sched.json"
+    monkeypatch.setenv("ETD_AUTOTUNE_CACHE", str(cache))
+    plan = make_plan(b)
+    mode, branches, times = plan.autotune(trial_steps=2)
+    plan.close()
+    assert times and cache.exists()
+    rec = json.loads(cache.read_text())
+    assert list(rec.values()) == [{"mode": mode, "branches": branches, "xlines": 0}]
+    other = make_plan(b)
+    assert other.autotune(trial_steps=2) == (mode, branches, {})
+    other.close()
+
+
 def test_autotune_between_band_rebuilds_restores_the_band_list():
     """A band-solve plan (ETD_F_SURFACE_NONLOCAL reads the band list in every
     step) autotuned at step 3, between rebuilds every 4 steps: the trial steps
