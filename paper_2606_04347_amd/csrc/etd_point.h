@@ -66,12 +66,33 @@ template <typename T> struct EtdArgs {
     int lines = 0;                  // FP32 ETD x pass: lines per workgroup (0 or 16: 16, 8: 8)
 };
 
+// The values a combine reads at its index besides p and q: PHI1 phi^n hat;
+// PHI2 phi~ hat and R; U2 D and R (U1 none).  Loaded apart from the combine
+// so a caller can issue the loads of several indices before the first of
+// their stores.
+template <typename T> struct CombineIn {
+    c2<T> a, b;
+};
+template <int ST, typename T> __device__ __forceinline__ CombineIn<T> combine_load(const EtdArgs<T>& a, long i) {
+    CombineIn<T> c;
+    if constexpr (ST == ETD_STAGE_PHI1) {
+        c.a = a.prev[i];
+    } else if constexpr (ST == ETD_STAGE_PHI2) {
+        c.a = a.prev[i];
+        c.b = a.ra[i];
+    } else if constexpr (ST == ETD_STAGE_U2) {
+        c.a = a.out[i];
+        c.b = a.ra[i];
+    }
+    return c;
+}
+
 // Returns the stage's output value at i (PHI*: the new phi hat, U*: the
-// increment D); the stage-1 remainder is stored into a.ra here, the output is
-// left to the caller.
+// increment D) from the values combine_load read at i; the stage-1
+// remainder is stored into a.ra here, the output is left to the caller.
 template <int ST, typename T>
 __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long i, c2<T> p, c2<T> q,
-                                             const EtdArgs<T>& a) {
+                                             const EtdArgs<T>& a, const CombineIn<T>& in) {
     if constexpr (ST == ETD_STAGE_PHI1) {
         // R = P - c1 k^2 Q;  phi~ = e^{-tau l} phi^n + tau phi1(tau l) R
         const double z = K.tau * lphi(K, k2);
@@ -85,7 +106,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
             te1 = K.tau * phi1d(z);
         }
         const T ck = (T)(K.c1 * k2);
-        const c2<T> f = a.prev[i];
+        const c2<T> f = in.a;
         const c2<T> R = mk<T>(p.x - ck * q.x, p.y - ck * q.y);
         a.ra[i] = R;
         return mk<T>(e0 * f.x + te1 * R.x, e0 * f.y + te1 * R.y);
@@ -94,7 +115,7 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
         const double z = K.tau * lphi(K, k2);
         const T te2 = (T)(K.tau * (sizeof(T) == 4 ? phi_one_exp<2>(z).p2 : phi2d(z)));
         const T ck = (T)(K.c1 * k2);
-        const c2<T> t = a.prev[i], ra = a.ra[i];
+        const c2<T> t = in.a, ra = in.b;
         const T dx = (p.x - ck * q.x) - ra.x, dy = (p.y - ck * q.y) - ra.y;
         return mk<T>(t.x + te2 * dx, t.y + te2 * dy);
     } else if constexpr (ST == ETD_STAGE_U1) {
@@ -111,10 +132,15 @@ __device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long 
         const double z = K.tau * lu(K, k2);
         const T te2 = (T)(K.tau * (sizeof(T) == 4 ? phi_one_exp<2>(z).p2 : phi2d(z)));
         const T ck = (T)(K.eps_u * K.B1 * k2);
-        const c2<T> d = a.out[i], ra = a.ra[i];
+        const c2<T> d = in.a, ra = in.b;
         const T dx = (p.x + ck * q.x) - ra.x, dy = (p.y + ck * q.y) - ra.y;
         return mk<T>(d.x + te2 * dx, d.y + te2 * dy);
     }
+}
+template <int ST, typename T>
+__device__ __forceinline__ c2<T> etd_combine(const CoupledK& K, double k2, long i, c2<T> p, c2<T> q,
+                                             const EtdArgs<T>& a) {
+    return etd_combine<ST, T>(K, k2, i, p, q, a, combine_load<ST, T>(a, i));
 }
 
 }  // namespace etd

@@ -106,6 +106,7 @@ template <typename T, int L, int LSRC> struct InvXFromLds {
 // extra registers cost more occupancy than the early loads gain).
 template <typename T, int L> struct DerivYOp {
     static constexpr int NT = 4;
+    static constexpr bool kFetchAll = false;   // the loop of the first stage (measured faster)
     struct In {
         c2<T> a;
     };
@@ -253,13 +254,37 @@ template <typename T, int M, int K, bool VEL> struct GradNormStore {
     int nl;
     T scale, itau;
     double thr;   // support threshold, compared in FP64
+    // with VEL, phi and phi^n at the output, fetched before the butterfly
+    // that makes it (rows past the tile's end read row 0, unused); FP32 only
+    // (in FP64 the registers they hold cost more than the overlap gains)
+    static constexpr bool kPrefetch = VEL && sizeof(T) == 4;
+    struct Pre {
+        c2<T> p, o;
+    };
+    __device__ __forceinline__ void prefetch(int l, int e, Pre& pr) const {
+        if constexpr (kPrefetch) {
+            const long i = (long)(l < nl ? l : 0) * M + e;
+            pr.p = phi[i];
+            pr.o = po[i];
+        }
+    }
     __device__ __forceinline__ void load(int, int, c2<T>*) const {}
     __device__ __forceinline__ void store_at(int slot, int l, int e, c2<T> v) const {
+        Pre pr{};
+        if constexpr (VEL) {
+            if (l < nl) {
+                pr.p = phi[(long)l * M + e];
+                pr.o = po[(long)l * M + e];
+            }
+        }
+        store_at(slot, l, e, v, pr);
+    }
+    __device__ __forceinline__ void store_at(int slot, int l, int e, c2<T> v, const Pre& pr) const {
         if (l >= nl) return;
         const long i = (long)l * M + e;
         const c2<T> b = cscale(v, scale);
         if constexpr (VEL) {
-            const c2<T> p = phi[i], o = po[i], a = kx[slot], c = kz[slot];
+            const c2<T> p = pr.p, o = pr.o, a = kx[slot], c = kz[slot];
             gn[i] = mk<T>(sqrt(c.x * c.x + a.x * a.x + b.x * b.x), sqrt(c.y * c.y + a.y * a.y + b.y * b.y));
             c2<T> g, x, y, w;
             velocity_point(itau, thr, p.x, o.x, a.x, b.x, c.x, &g.x, &x.x, &y.x, &w.x);
@@ -346,11 +371,22 @@ template <typename T, int M> struct RecoverStore {
     int nl;
     T scale;
     double thr;   // the recovery threshold, compared in FP64 on both paths
+    // u_old and G at the output, fetched before the butterfly that makes it
+    // (rows past the tile's end read row 0, unused)
+    static constexpr bool kPrefetch = true;
+    struct Pre {
+        c2<T> u, g;
+    };
+    __device__ __forceinline__ void prefetch(int l, int, int e, Pre& p) const {
+        const long i = (long)(l < nl ? l : 0) * M + e;
+        p.u = uo[i];
+        p.g = G[i];
+    }
     __device__ __forceinline__ void load(int, int, c2<T>*) const {}
-    __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const {
+    __device__ __forceinline__ void store(int l, int, int e, c2<T> v, const Pre& p) const {
         if (l >= nl) return;
         const long i = (long)l * M + e;
-        const c2<T> u = uo[i], g = G[i];
+        const c2<T> u = p.u, g = p.g;
         const T d0 = v.x * scale, d1 = v.y * scale;
         c2<T> r;
         r.x = ((double)g.x > thr) ? u.x + d0 / g.x : g.x * u.x + d0;
@@ -546,7 +582,7 @@ template <typename T, int L> struct P2PairLoad {
 // q = g+ (u - ubar) on the band (Section 3.1, the nonlocal argument) at the
 // point pair (2e, 2e + 1) of row l, accumulated into this thread's share of
 // the mass sum.
-template <typename T, int M> struct QPairLoad {
+template <typename T, int M, bool BAND> struct QPairLoad {
     static constexpr int NS = 1;
     const T* u;      // first row of the tile
     const T* G;
@@ -555,17 +591,16 @@ template <typename T, int M> struct QPairLoad {
     T ubar;
     Neu& acc;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
-        if (l >= nl) {
-            v[0] = mk<T>(0, 0);
-            return;
-        }
-        const long i = (long)l * 2 * M + 2 * e;
+        // rows past the tile's end read row 0 and give 0: every load is unconditional
+        const bool ok = l < nl;
+        const long i = (long)(ok ? l : 0) * 2 * M + 2 * e;
         const c2<T> uu = ld2(u + i), GG = ld2(G + i);
         T q0 = GG.x * (uu.x - ubar), q1 = GG.y * (uu.y - ubar);
-        if (mask) {
+        if constexpr (BAND) {
             q0 = mask[i] ? q0 : (T)0;
             q1 = mask[i + 1] ? q1 : (T)0;
         }
+        if (!ok) q0 = q1 = (T)0;
         acc.add((double)q0);
         acc.add((double)q1);
         v[0] = mk<T>(q0, q1);
@@ -586,9 +621,12 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, co
     const int nl = (int)min((long)L, nrows - row0);
     const long ro = row0 * NR;
     Neu acc;
-    zrow_forward_op<T, NR>(lds, stw, twf,
-                           QPairLoad<T, NR / 2>{u + ro, G + ro, mask ? mask + ro : nullptr, nl, ubar, acc},
-                           W + row0 * (NR / 2 + 1), nl);
+    if (mask)
+        zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, true>{u + ro, G + ro, mask + ro, nl, ubar, acc},
+                               W + row0 * (NR / 2 + 1), nl);
+    else
+        zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, false>{u + ro, G + ro, nullptr, nl, ubar, acc},
+                               W + row0 * (NR / 2 + 1), nl);
     __syncthreads();
     const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -700,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_y_pair(GridK g, c2<T>* X0, c2<T>* 
 // standalone combine), applies the ETD combine, stores the stage output if
 // asked and leaves it in the LDS (each last-stage thread writes back exactly
 // the LDS entries it has read, so no barrier is needed before the write).
-template <int ST, typename T, int L, int LS> struct EtdXOp {
+template <int ST, typename T, int L, int LS, bool PF> struct EtdXOp {
     static constexpr int NT = 2;
     // FP64 fetches P and Q up front (measured faster); FP32 reads each in its
     // own transform (fewer registers, higher occupancy)
@@ -731,13 +769,30 @@ template <int ST, typename T, int L, int LS> struct EtdXOp {
         const long b = t->base[l];
         return b >= 0 ? (K == 0 ? P : Q)[b + (long)e * es] : mk<T>(0, 0);
     }
+    // PF: the spectra the combine reads at (l, e) are fetched by the last
+    // stage before its transform (Pre), so a thread's fetches overlap; off
+    // at length 512, where the registers they take cost occupancy
+    static constexpr bool kPrefetch = PF;
+    using Pre = CombineIn<T>;
+    __device__ __forceinline__ void prefetch(int l, int e, Pre& pre) const {
+        // a line past the tile's end (base < 0) reads line 0 instead, in
+        // bounds, and discards it: the loads stay unconditional
+        const long b = t->base[l];
+        pre = combine_load<ST, T>(a, (b >= 0 ? b : 0) + (long)e * es);
+    }
     __device__ __forceinline__ void store_joint(int l, int e, const c2<T>* v) const {
+        const long b = t->base[l];
+        Pre pre{};
+        if (b >= 0) pre = combine_load<ST, T>(a, b + (long)e * es);
+        store_joint(l, e, v, pre);
+    }
+    __device__ __forceinline__ void store_joint(int l, int e, const c2<T>* v, const Pre& pre) const {
         const long b = t->base[l];
         c2<T> r = mk<T>(0, 0);
         if (b >= 0) {
             const double lx = ax * lam_index(e, nx);
             const double k2 = lx * lx + kyz[l];
-            r = etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a);
+            r = etd_combine<ST, T>(*K, k2, b + (long)e * es, v[0], v[1], a, pre);
             if (store_out) a.out[b + (long)e * es] = r;
         }
         lds[l * LS + sk(e)] = r;
@@ -778,8 +833,8 @@ __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c
     const long es = (long)g.ny * g.nzh;
     lines_fft_seq_joint<T, N, L, -1, true>(
         lds, stw,
-        EtdXOp<ST, T, L, LS>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K, a, lds,
-                             kyz, store_out});
+        EtdXOp<ST, T, L, LS, (N <= 256)>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K,
+                                         a, lds, kyz, store_out});
     __syncthreads();
     if constexpr (ST == ETD_STAGE_PHI1 || ST == ETD_STAGE_PHI2) {
         lines_fft_seq<T, N, L, +1, true, DerivXOp<T, L, LS>, true>(

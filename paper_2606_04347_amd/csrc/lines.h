@@ -28,11 +28,50 @@ namespace etd {
 namespace stk {
 
 // First stage (span 1, radix R): global -> registers -> DFT -> LDS.
+// When the values of all of a thread's butterflies fit in 32 registers, every
+// load is issued before the first transform, so one memory latency covers
+// them all (a loop over butterflies waits for each one's loads in turn).
+// Larger sets (FP64, length 512, two fields) keep the loop: there the extra
+// registers cost more occupancy than the overlap gains (measured).
 template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
 __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
     constexpr int NS = Op::NS;
     constexpr int NR = N / R;
     constexpr int NB = L * NR;
+    constexpr int IT = (NB + kThreads - 1) / kThreads;
+    if constexpr (IT * NS * R * sizeof(c2<T>) <= 32 * 4) {
+        c2<T> v[IT][NS][R];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int b = threadIdx.x + it * kThreads;
+            if ((NB % kThreads == 0) || b < NB) {
+                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    c2<T> x[NS];
+                    op.load(l, j + r * NR, x);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) v[it][s][r] = x[s];
+                }
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int b = threadIdx.x + it * kThreads;
+            if ((NB % kThreads == 0) || b < NB) {
+                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    dftR<T, R, DIR>(v[it][s]);
+                    c2<T>* dst = lds + (s * L + l) * LS;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) dst[sk_add<16 % R == 0>(j * R, sk(j * R), r)] = v[it][s][r];
+                }
+            }
+        }
+        __syncthreads();
+        return;
+    }
     for (int b = threadIdx.x; b < NB; b += kThreads) {
         const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
         c2<T> v[NS][R];
@@ -54,6 +93,22 @@ __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
     __syncthreads();
 }
 
+// The epilogue's own global reads: a store Op may declare a type Pre, a
+// prefetch and kPrefetch (true to use them); the last stage of a transform then issues the prefetches of a
+// butterfly's R outputs before the butterfly and hands each output its Pre
+// (last_stage: prefetch(l, s, e, Pre&), store(l, s, e, v, pre);
+// last_stage_indexed: prefetch(l, e, Pre&), store_at(slot, l, e, v, pre);
+// joint transforms: prefetch(l, e, Pre&), store_joint(l, e, v, pre)), so
+// a thread's fetches overlap instead of each waiting in turn.
+template <class Op, class = void> struct PrefetchOf {
+    static constexpr bool v = false;
+    struct Pre {};
+};
+template <class Op> struct PrefetchOf<Op, std::void_t<typename Op::Pre>> {
+    static constexpr bool v = Op::kPrefetch;
+    using Pre = typename Op::Pre;
+};
+
 // Last stage (span SP = N / R): LDS -> twiddles -> DFT -> Op::store.
 template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
 __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, const Op& op) {
@@ -61,22 +116,55 @@ __device__ __forceinline__ void last_stage(const c2<T>* lds, const c2<T>* tw, co
     constexpr int SP = N / R;
     constexpr int LL = L * NS;
     constexpr int NB = LL * SP;
-    for (int b = threadIdx.x; b < NB; b += kThreads) {
-        const int ll = LF ? b % LL : b / SP, j = LF ? b / LL : b % SP;
-        const int s = ll / L, l = ll % L;
-        const c2<T>* src = lds + ll * LS;
-        c2<T> v[R];
+    constexpr int IT = (NB + kThreads - 1) / kThreads;
+    if constexpr (!PrefetchOf<Op>::v) {   // a loop: fewer registers than the unrolled form
+        for (int b = threadIdx.x; b < NB; b += kThreads) {
+            const int ll = LF ? b % LL : b / SP, j = LF ? b / LL : b % SP;
+            const int s = ll / L, l = ll % L;
+            const c2<T>* src = lds + ll * LS;
+            c2<T> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
+            for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-            c2<T> w = tw[r * j];
-            if constexpr (DIR > 0) w.y = -w.y;
-            v[r] = cmul(v[r], w);
+            for (int r = 1; r < R; ++r) {
+                c2<T> w = tw[r * j];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+            dftR<T, R, DIR>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) op.store(l, s, j + r * SP, v[r]);
         }
-        dftR<T, R, DIR>(v);
+        return;
+    }
 #pragma unroll
-        for (int r = 0; r < R; ++r) op.store(l, s, j + r * SP, v[r]);
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if ((NB % kThreads == 0) || b < NB) {
+            const int ll = LF ? b % LL : b / SP, j = LF ? b / LL : b % SP;
+            const int s = ll / L, l = ll % L;
+            typename PrefetchOf<Op>::Pre pre[R];
+            if constexpr (PrefetchOf<Op>::v) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) op.prefetch(l, s, j + r * SP, pre[r]);
+            }
+            const c2<T>* src = lds + ll * LS;
+            c2<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = src[sk_add<SP % 16 == 0>(j, sk(j), r * SP)];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                c2<T> w = tw[r * j];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+            dftR<T, R, DIR>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (PrefetchOf<Op>::v) op.store(l, s, j + r * SP, v[r], pre[r]);
+                else op.store(l, s, j + r * SP, v[r]);
+            }
+        }
     }
 }
 
@@ -102,6 +190,11 @@ __device__ __forceinline__ void last_stage_indexed(const c2<T>* lds, const c2<T>
         const int b = threadIdx.x + it * kThreads;
         if ((NB % kThreads == 0) || b < NB) {
             const int l = LF ? b % L : b / SP, j = LF ? b / L : b % SP;
+            typename PrefetchOf<Op>::Pre pre[R];
+            if constexpr (PrefetchOf<Op>::v) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) op.prefetch(l, j + r * SP, pre[r]);
+            }
             const c2<T>* src = lds + l * LS;
             c2<T> v[R];
 #pragma unroll
@@ -114,7 +207,10 @@ __device__ __forceinline__ void last_stage_indexed(const c2<T>* lds, const c2<T>
             }
             dftR<T, R, DIR>(v);
 #pragma unroll
-            for (int r = 0; r < R; ++r) op.store_at(it * R + r, l, j + r * SP, v[r]);
+            for (int r = 0; r < R; ++r) {
+                if constexpr (PrefetchOf<Op>::v) op.store_at(it * R + r, l, j + r * SP, v[r], pre[r]);
+                else op.store_at(it * R + r, l, j + r * SP, v[r]);
+            }
         }
     }
 }
@@ -208,6 +304,53 @@ template <typename T, class Op, int S> struct SlotStore {
     __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const { op.template store<S>(l, e, v); }
 };
 
+// An Op may declare kFetchAll = false to keep the first stage's loop
+// (a register-heavy Op whose occupancy the early loads would lower).
+template <class Op, class = void> struct FetchAllOf {
+    static constexpr bool v = true;
+};
+template <class Op> struct FetchAllOf<Op, std::enable_if_t<!Op::kFetchAll>> {
+    static constexpr bool v = false;
+};
+
+// First stage of transform S of a sequential Op: the inputs of the thread's
+// IT butterflies (all of them fetched before the first transform when they
+// fit in 32 registers, as in first_stage), radix R0, into the LDS.
+template <typename T, int N, int L, int LS, int R0, int IT, bool LF, int S, int DIR, class Op>
+__device__ __forceinline__ void first_stage_inputs(c2<T>* lds, const Op& op, const typename Op::In (&in)[IT][R0]) {
+    constexpr int NR = N / R0;
+    constexpr int NB = L * NR;
+    constexpr bool kAll = FetchAllOf<Op>::v && IT * R0 * sizeof(c2<T>) <= 32 * 4;
+    c2<T> v[kAll ? IT : 1][R0];
+    if constexpr (kAll) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int b = threadIdx.x + it * kThreads;
+            if ((NB % kThreads == 0) || b < NB) {
+                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[it][r] = op.template input<S>(l, j + r * NR, in[it][r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = threadIdx.x + it * kThreads;
+        if ((kAll && NB % kThreads == 0) || b < NB) {
+            const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
+            c2<T>* w = v[kAll ? it : 0];
+            if constexpr (!kAll) {
+#pragma unroll
+                for (int r = 0; r < R0; ++r) w[r] = op.template input<S>(l, j + r * NR, in[it][r]);
+            }
+            dftR<T, R0, DIR>(w);
+            c2<T>* dst = lds + l * LS;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) dst[sk_add<16 % R0 == 0>(j * R0, sk(j * R0), r)] = w[r];
+        }
+    }
+}
+
 template <typename T, int N, int L, int LS, int R0, int IT, int DIR, bool LF, class Op, int S>
 __device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, const Op& op,
                                                const typename Op::In (&in)[IT][R0]) {
@@ -228,20 +371,7 @@ __device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, cons
         }
     } else {
         if constexpr (S > 0) __syncthreads();   // the previous transform's last stage has read the LDS
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int b = threadIdx.x + it * kThreads;
-            if (b < NB) {
-                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
-                c2<T> v[R0];
-#pragma unroll
-                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, j + r * NR, in[it][r]);
-                dftR<T, R0, DIR>(v);
-                c2<T>* dst = lds + l * LS;
-#pragma unroll
-                for (int r = 0; r < R0; ++r) dst[sk_add<16 % R0 == 0>(j * R0, sk(j * R0), r)] = v[r];
-            }
-        }
+        first_stage_inputs<T, N, L, LS, R0, IT, LF, S, DIR>(lds, op, in);
         __syncthreads();
         middle_and_last<T, N, L, LS, R0, DIR, LF>(lds, tw, SlotStore<T, Op, S>{op});
     }
@@ -300,16 +430,28 @@ constexpr int last_radix(int n) {
     }
 }
 
+template <typename T, class Op, class P>
+__device__ __forceinline__ void store_joint_with(const Op& op, int l, int e, const c2<T>* o, const P& pre) {
+    if constexpr (PrefetchOf<Op>::v) op.store_joint(l, e, o, pre);
+    else op.store_joint(l, e, o);
+}
+
 template <typename T, int N, int L, int LS, int R, int DIR, bool LF, int NT, int IT, int S, class Op>
 __device__ __forceinline__ void last_stage_stash(const c2<T>* lds, const c2<T>* tw, const Op& op,
                                                  c2<T> (&stash)[NT][IT][R]) {
     constexpr int SP = N / R;
     constexpr int NB = L * SP;
+    constexpr bool kPre = (S + 1 == NT) && PrefetchOf<Op>::v;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = threadIdx.x + it * kThreads;
         if ((NB % kThreads == 0) || b < NB) {
             const int l = LF ? b % L : b / SP, j = LF ? b / L : b % SP;
+            typename PrefetchOf<Op>::Pre pre[R];
+            if constexpr (kPre) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) op.prefetch(l, j + r * SP, pre[r]);
+            }
             const c2<T>* src = lds + l * LS;
             c2<T> v[R];
 #pragma unroll
@@ -330,7 +472,7 @@ __device__ __forceinline__ void last_stage_stash(const c2<T>* lds, const c2<T>* 
 #pragma unroll
                     for (int s = 0; s + 1 < NT; ++s) o[s] = stash[s][it][r];
                     o[NT - 1] = v[r];
-                    op.store_joint(l, j + r * SP, o);
+                    store_joint_with<T>(op, l, j + r * SP, o, pre[r]);
                 }
             }
         }
@@ -375,27 +517,16 @@ __device__ __forceinline__ void seq_joint_transforms(c2<T>* lds, const c2<T>* tw
 #pragma unroll
                         for (int s = 0; s + 1 < NT; ++s) o[s] = stash[s][it][r];
                         o[NT - 1] = v[r];
-                        op.store_joint(l, r, o);
+                        typename PrefetchOf<Op>::Pre pre{};
+                        if constexpr (PrefetchOf<Op>::v) op.prefetch(l, r, pre);
+                        store_joint_with<T>(op, l, r, o, pre);
                     }
                 }
             }
         }
     } else {
         if constexpr (S > 0) __syncthreads();
-#pragma unroll
-        for (int it = 0; it < ITI; ++it) {
-            const int b = threadIdx.x + it * kThreads;
-            if (b < NB) {
-                const int l = LF ? b % L : b / NR, j = LF ? b / L : b % NR;
-                c2<T> v[R0];
-#pragma unroll
-                for (int r = 0; r < R0; ++r) v[r] = op.template input<S>(l, j + r * NR, in[it][r]);
-                dftR<T, R0, DIR>(v);
-                c2<T>* dst = lds + l * LS;
-#pragma unroll
-                for (int r = 0; r < R0; ++r) dst[sk_add<16 % R0 == 0>(j * R0, sk(j * R0), r)] = v[r];
-            }
-        }
+        first_stage_inputs<T, N, L, LS, R0, ITI, LF, S, DIR>(lds, op, in);
         __syncthreads();
         middle_and_last_stash<T, N, L, LS, R0, DIR, LF, NT, ITL, RL, S, Op>(lds, tw, op, stash);
     }

@@ -35,7 +35,8 @@ template <typename T, int M> struct RowPairLoad {
     const c2<T>* src;   // first row of the tile
     int nl;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
-        v[0] = l < nl ? src[(long)l * M + e] : mk<T>(0, 0);
+        const c2<T> x = src[(long)(l < nl ? l : 0) * M + e];   // unconditional: row 0 read for rows past the end
+        v[0] = l < nl ? x : mk<T>(0, 0);
     }
     __device__ __forceinline__ void store(int, int, int, c2<T>) const {}
 };
@@ -224,12 +225,27 @@ __device__ __forceinline__ void zrow_inverse_lds(c2<T>* lds, const c2<T>* stw, c
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int idx = threadIdx.x + p * kThreads;
-                if (idx < L * M) op.store_at(p, idx / M, idx % M, lds[(idx / M) * LS + sk(idx % M)]);
+                if (idx < L * M) {
+                    const c2<T> v = lds[(idx / M) * LS + sk(idx % M)];
+                    if constexpr (PrefetchOf<Op>::v) {
+                        typename Op::Pre pre;
+                        op.prefetch(idx / M, idx % M, pre);
+                        op.store_at(p, idx / M, idx % M, v, pre);
+                    } else {
+                        op.store_at(p, idx / M, idx % M, v);
+                    }
+                }
             }
         } else {
             for (int idx = threadIdx.x; idx < L * M; idx += kThreads) {
                 const int r = idx / M, n = idx % M;
-                op.store(r, 0, n, lds[r * LS + sk(n)]);
+                if constexpr (PrefetchOf<Op>::v) {
+                    typename Op::Pre pre;
+                    op.prefetch(r, 0, n, pre);
+                    op.store(r, 0, n, lds[r * LS + sk(n)], pre);
+                } else {
+                    op.store(r, 0, n, lds[r * LS + sk(n)]);
+                }
             }
         }
     } else {

@@ -191,19 +191,22 @@ def test_autotune_between_band_rebuilds_restores_the_band_list():
     assert np.array_equal(runs[0][1], runs[1][1], equal_nan=True)
 
 
+@pytest.mark.parametrize("counts", [((32, 2), (48, 1), ((16, 96, 16), 1)), ((64, 2), (96, 1), (128, 1))],
+                         ids=["small", "sweep_shapes"])
 @pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
-def test_uneven_batch_matches_oracle(precision):
+def test_uneven_batch_matches_oracle(precision, counts):
     """An uneven batch shaped like the sweep's instance mix -- grid lengths 32,
-    48 (radix 3) and a 96-length axis, per-instance seeds, coefficients and
-    tau in {5e-5, 1e-4} (inputs.batch_sweep's draws) -- stepped under the
-    graph schedule with concurrent branches, each instance against the FP64
+    48 (radix 3) and a 96-length axis; then the sweep's own shapes, 64^3,
+    96^3 and 128^3 -- with per-instance seeds, coefficients and tau in
+    {5e-5, 1e-4} (inputs.batch_sweep's draws), stepped under the graph
+    schedule with concurrent branches, each instance against the FP64
     oracle: within 1e-12 (FP64) or under the FP32 comparison of
     test_gpu_coupled (flip set counted, u and g u within 1e-4)."""
     from gpu_util import recovery_flips, rel_linf, u_gap_outside_flips
     from oracle.core import Grid
     from oracle.coupled import CoupledOracle
-    cis = inputs.batch_sweep(counts=((32, 2), (48, 1), ((16, 96, 16), 1)))
-    assert {ci.tau for ci in cis} <= {5e-5, 1e-4}
+    cis = inputs.batch_sweep(counts=counts)
+    assert {ci.tau for ci in cis} == {5e-5, 1e-4}
     plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=precision) for ci in cis])
     dt = torch.float64 if precision == etd.FP64 else torch.float32
     for i, ci in enumerate(cis):
