@@ -12,6 +12,9 @@ Besides the headline it reports
                  event-timed total) against the 8 TB/s HBM peak
   cpu_baseline   the FP64 oracle timed on this host on one step of the same
                  workload
+  batched        the uneven 48-instance sweep (32 x 64^3, 12 x 96^3, 4 x
+                 128^3) under the grouped schedule against sequential
+                 per-instance launches, measured in a child process first
 """
 from __future__ import annotations
 
@@ -49,11 +52,11 @@ def parse():
                     help="skip the band-solve leg ((-Delta_S,h)^{-1} on the band, 256^3)")
     ap.add_argument("--surface-n", type=int, default=256)
     ap.add_argument("--surface-steps", type=int, default=4)
-    ap.add_argument("--batch", action="store_true",
-                    help="also run the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances); off by "
-                         "default while a host-side abort seen once in this leg is unexplained")
-    ap.add_argument("--no-batch", action="store_true", help="leave the uneven-batch measurement out (the default)")
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave out the uneven-batch measurement (32x64^3 + 12x96^3 + 4x128^3 instances, run in a "
+                         "child process)")
+    ap.add_argument("--batch-only", action="store_true", help="only the uneven-batch measurement (one JSON line)")
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--coarsening", type=float, default=0.0,
                     help="run the four 2D coarsening experiments to this final time (the paper's: 1000); 0 = off")
     ap.add_argument("--coarsening-every", type=float, default=1.0, help="checkpoint interval (time units)")
@@ -395,9 +398,11 @@ def precision_gap(ci, nsteps):
 
 def batch_measure(steps, warmup):
     """Uneven batch of 48 coupled FP32 ETDRK2 instances (32 x 64^3, 12 x 96^3,
-    4 x 128^3 = 27,394,048 points) in one plan: the autotuned schedule against
-    sequential eager launches of the same plan and against one plan per
-    instance replaying its own graph."""
+    4 x 128^3 = 27,394,048 points) in one plan, each with its own seed,
+    coefficients and tau: sequential per-instance launches (eager, one
+    instance after another) against the grouped schedule (one launch per pass
+    per shape class, captured two steps at a time) over its branch and tile
+    candidates, with the graph schedule on four branches beside them."""
     import torch
 
     from paper_2606_04347_amd import etd, inputs
@@ -405,46 +410,49 @@ def batch_measure(steps, warmup):
     cis = inputs.batch_sweep()
     log(f"batch inputs {time.time() - t0:.1f}s")
     npts = sum(int(ci.phi0.size) for ci in cis)
-
-    def build(sel):
-        plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32) for ci in sel])
-        for i, ci in enumerate(sel):
-            plan.set_state(i, torch.as_tensor(ci.phi0, dtype=torch.float32, device="cuda"),
-                           torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
-        return plan
-
-    base_steps = max(2, (steps // 4) & ~1)
-    plan = build(cis)
+    plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=etd.FP32) for ci in cis])
+    for i, ci in enumerate(cis):
+        plan.set_state(i, torch.as_tensor(ci.phi0, dtype=torch.float32, device="cuda"),
+                       torch.as_tensor(ci.u0, dtype=torch.float32, device="cuda"))
+    base_steps = max(2, (steps // 5) & ~1)
     ms_eager = timed_steps(plan, base_steps, warmup) / base_steps
-    mode, branches, tune = plan.autotune(trial_steps=10)
-    ms_tuned = timed_steps(plan, steps, warmup) / steps
+    log(f"batch eager: {ms_eager:.3f} ms/step")
+    cands = {}
+    for name, mode, branches, xlines in (("grouped1", etd.EXEC_GROUPED, 1, 0), ("grouped3", etd.EXEC_GROUPED, 3, 0),
+                                         ("grouped1_x8", etd.EXEC_GROUPED, 1, 8),
+                                         ("grouped3_x8", etd.EXEC_GROUPED, 3, 8), ("graph4", etd.EXEC_GRAPH, 4, 0)):
+        plan.set_schedule(mode, branches, xlines)
+        n = steps if mode == etd.EXEC_GROUPED else base_steps
+        cands[name] = timed_steps(plan, n, warmup) / n
+        log(f"batch {name}: {cands[name]:.3f} ms/step")
     plan.close()
-    # one plan per instance, each replaying its own two-step graph, launched in turn
-    plans = [build([ci]) for ci in cis]
-    for p in plans:
-        p.set_schedule(etd.EXEC_GRAPH, 1)
-        p.step(2)
-    torch.cuda.synchronize()
-    s = plans[0].stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(base_steps // 2):
-        for p in plans:
-            p.step(2)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms_graphs = e0.elapsed_time(e1) / base_steps
-    for p in plans:
-        p.close()
+    best = min((k for k in cands if k.startswith("grouped")), key=lambda k: cands[k])
     rate = lambda ms: npts / (ms * 1e-3)
     return {"workload": "32 x 64^3 + 12 x 96^3 + 4 x 128^3 coupled ETDRK2 FP32 instances in one plan "
                         f"({npts} points), per-instance seeds, coefficients and tau in {{5e-5, 1e-4}}",
-            "value": rate(ms_tuned), "unit": "grid-pt steps/s", "ms_per_step": ms_tuned, "steps": steps,
-            "schedule": {"mode": "graph" if mode == etd.EXEC_GRAPH else "eager", "branches": branches},
-            "autotune_ms_per_step": tune,
+            "value": rate(cands[best]), "unit": "grid-pt steps/s", "ms_per_step": cands[best], "steps": steps,
+            "schedule": best, "candidates_ms_per_step": cands,
             "eager_sequential": {"value": rate(ms_eager), "ms_per_step": ms_eager, "steps": base_steps},
-            "per_instance_graphs": {"value": rate(ms_graphs), "ms_per_step": ms_graphs, "steps": base_steps},
-            "speedup_vs_eager": ms_eager / ms_tuned, "speedup_vs_per_instance_graphs": ms_graphs / ms_tuned}
+            "speedup_vs_eager": ms_eager / cands[best],
+            "speedup_graph4_vs_eager": ms_eager / cands["graph4"]}
+
+
+def batch_in_child(steps, warmup, timeout=300):
+    """The batch leg in a child process (started before this process touches
+    the GPU): its result, or its exit status and last lines of output."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--batch-only", "--batch-steps", str(steps),
+           "--warmup", str(warmup)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return {"error": f"timed out after {timeout} s"}
+    sys.stderr.write(r.stderr)
+    sys.stderr.flush()
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"exit status {r.returncode}", "stderr_tail": r.stderr.splitlines()[-5:]}
+    return json.loads(lines[-1])
 
 
 def coarsening_measure(T, every, which=(0, 1, 2, 3)):
@@ -549,6 +557,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU slab "
               "decomposition is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
+    if a.batch_only:
+        print(json.dumps(batch_measure(a.batch_steps, a.warmup)))
+        return
+    batched = None if a.no_batch else batch_in_child(a.batch_steps, a.warmup)
     import torch
 
     from paper_2606_04347_amd import etd, inputs
@@ -620,11 +632,13 @@ def main():
             f"{sf['band_solve']['relres_last_solve']:.1e}, {sf['band_solve']['band_points']} band points) vs "
             f"{sf['fft_inverse']['ms_per_step']:.3f} ms/step with (-Delta_h)^-1; U in [{sf['band_solve']['umin']:.4g}, "
             f"{sf['band_solve']['umax']:.4g}] vs [{sf['fft_inverse']['umin']:.4g}, {sf['fft_inverse']['umax']:.4g}]")
-    if a.batch and not a.no_batch:
-        out["batched"] = batch_measure(a.batch_steps, a.warmup)
-        log(f"batched: {out['batched']['ms_per_step']:.3f} ms/step ({out['batched']['schedule']}), "
-            f"x{out['batched']['speedup_vs_eager']:.2f} vs eager, "
-            f"x{out['batched']['speedup_vs_per_instance_graphs']:.2f} vs per-instance graphs")
+    if batched is not None:
+        out["batched"] = batched
+        if "error" in batched:
+            log(f"batched: failed, {batched}")
+        else:
+            log(f"batched: {batched['ms_per_step']:.3f} ms/step ({batched['schedule']}), "
+                f"x{batched['speedup_vs_eager']:.2f} vs sequential per-instance launches")
     if a.coarsening > 0:
         out["coarsening"] = coarsening_measure(a.coarsening, a.coarsening_every,
                                                tuple(int(k) for k in a.coarsening_runs.split(",")))

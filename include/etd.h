@@ -426,12 +426,27 @@ etd_status etd_surface_lapinv(etd_plan_t plan, int instance, const void* g, cons
  *                   dropped by etd_set_state and etd_set_schedule and are
  *                   recaptured when the band-rebuild pattern of the two
  *                   captured steps changes.  Pass timing forces eager steps.
+ *   ETD_EXEC_GROUPED  like ETD_EXEC_GRAPH, but the instances of one shape and
+ *                   configuration (grid, model, scheme, precision, flags)
+ *                   form a group, and each pass of a step runs as ONE launch
+ *                   over the tiles of all instances of the group (the
+ *                   instance is the second grid coordinate; each reads its
+ *                   own arguments -- fields, tau, coefficients -- from a
+ *                   device table the graph owns), so a batch of 48 uneven
+ *                   instances in three shape classes takes three launches per
+ *                   pass instead of 48.  The groups are spread over
+ *                   min(branches, groups) concurrent branches.  Coupled
+ *                   instances on 3D grids without a band, diagnostics ring,
+ *                   mass projection or band solve only (ETD_E_ARG otherwise,
+ *                   at etd_set_schedule, or at the next etd_step if such a
+ *                   feature is turned on later; the states are then left
+ *                   as they were).
  * Results are identical under every schedule (the instances are
  * independent and every kernel runs the same arithmetic). */
-typedef enum { ETD_EXEC_EAGER = 0, ETD_EXEC_GRAPH = 1 } etd_exec_mode;
+typedef enum { ETD_EXEC_EAGER = 0, ETD_EXEC_GRAPH = 1, ETD_EXEC_GROUPED = 2 } etd_exec_mode;
 typedef struct {
     int mode;       /* etd_exec_mode */
-    int branches;   /* concurrent capture branches (graph mode) */
+    int branches;   /* concurrent capture branches (graph and grouped modes) */
     int xlines;     /* lines per workgroup of the ETD x pass of FP32 coupled
                        instances on 3D grids: 0 or 16 (the default tile), 8
                        (twice the workgroups; the same arithmetic, so the same
@@ -442,20 +457,21 @@ etd_status etd_get_schedule(etd_plan_t plan, etd_schedule* out);
 
 /* Schedule autotuner.  Times trial_steps (rounded up to even, >= 2) steps
  * of each candidate -- eager, then graph with 1, 2, 4, 8, 16 and 32 branches
- * (those not above the instance count), then the fastest of these with the
+ * (those not above the instance count), grouped on 1 and 8 branches (where
+ * every instance can be grouped), then the fastest of these with the
  * 8-line ETD x tile (when an FP32 coupled 3D instance takes that pass) --
  * after two untimed warm-up steps each, on the current states; then restores
  * every instance exactly from a device snapshot taken first (state fields,
  * spectrum, derivatives, band mask and list, device scalars, step counter),
  * sets the fastest schedule and returns it in *chosen (may be NULL).  ms_out
- * (may be NULL) receives the per-step milliseconds of the 8 candidates in
+ * (may be NULL) receives the per-step milliseconds of the 10 candidates in
  * that order (negative for a candidate not tried).  cache_path (NULL or empty: the environment's
  * ETD_AUTOTUNE_CACHE, else no cache) names a JSON file of earlier choices keyed by the device architecture and the sorted multiset of (model,
  * scheme, precision, grid) of the instances: a hit selects the cached
  * schedule without trials (ms_out entries then negative); a miss appends the
  * new choice.  Every instance must have a state.  Allocates the snapshot
  * (about the size of the state) for the duration of the call.  Synchronizes. */
-#define ETD_AUTOTUNE_CANDIDATES 8
+#define ETD_AUTOTUNE_CANDIDATES 10
 etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path, etd_schedule* chosen,
                         double* ms_out);
 

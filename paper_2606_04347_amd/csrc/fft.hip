@@ -11,6 +11,7 @@
 
 #include <cmath>
 
+#include "launch.h"
 #include "zrows.h"
 
 namespace etd {
@@ -68,44 +69,75 @@ __device__ __forceinline__ void fft_lines(const c2<T>* in, c2<T>* out, const c2<
 
 // The y- and x-line passes share the body; separate symbols keep them apart in traces.
 template <typename T, int N, int DIR>
+struct k_fft_ylines_body {
+    static __device__ __forceinline__ void run(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
+                                                         int C, int nlines, long ostride, long estride) {
+        fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
+    }
+};
+template <typename T, int N, int DIR>
 __global__ __launch_bounds__(kThreads) void k_fft_ylines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
                                                          int C, int nlines, long ostride, long estride) {
-    fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
+    k_fft_ylines_body<T, N, DIR>::run(in, out, tw, C, nlines, ostride, estride);
 }
+template <typename T, int N, int DIR>
+struct k_fft_xlines_body {
+    static __device__ __forceinline__ void run(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
+                                                         int C, int nlines, long ostride, long estride) {
+        fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
+    }
+};
 template <typename T, int N, int DIR>
 __global__ __launch_bounds__(kThreads) void k_fft_xlines(const c2<T>* in, c2<T>* out, const c2<T>* __restrict__ tw,
                                                          int C, int nlines, long ostride, long estride) {
-    fft_lines<T, N, DIR>(in, out, tw, C, nlines, ostride, estride);
+    k_fft_xlines_body<T, N, DIR>::run(in, out, tw, C, nlines, ostride, estride);
 }
 
 // ---------------------------------------------------------------- z rows (r2c / c2r)
 template <typename T, int NR>
+struct k_fft_z_r2c_body {
+    static __device__ __forceinline__ void run(const T* __restrict__ in, c2<T>* __restrict__ out,
+                                                        const c2<T>* __restrict__ twh,
+                                                        const c2<T>* __restrict__ twf, long nrows) {
+        constexpr int L = z_rows<T, NR>();
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, NR / 2);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        zrow_forward<T, NR>(lds, stw, twf, in + row0 * NR, out + row0 * (NR / 2 + 1), nl);
+    }
+};
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fft_z_r2c(const T* __restrict__ in, c2<T>* __restrict__ out,
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<T, NR>();
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    zrow_forward<T, NR>(lds, stw, twf, in + row0 * NR, out + row0 * (NR / 2 + 1), nl);
+    k_fft_z_r2c_body<T, NR>::run(in, out, twh, twf, nrows);
 }
 
+template <typename T, int NR>
+struct k_fft_z_c2r_body {
+    static __device__ __forceinline__ void run(const c2<T>* __restrict__ in, T* __restrict__ out,
+                                                        const c2<T>* __restrict__ twh,
+                                                        const c2<T>* __restrict__ twf, long nrows,
+                                                        T scale) {
+        constexpr int L = z_rows<T, NR>();
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, NR / 2);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        zrow_inverse<T, NR, false>(lds, stw, twf, in + row0 * (NR / 2 + 1), out + row0 * NR, nl, scale, 0.0);
+    }
+};
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_fft_z_c2r(const c2<T>* __restrict__ in, T* __restrict__ out,
                                                         const c2<T>* __restrict__ twh,
                                                         const c2<T>* __restrict__ twf, long nrows,
                                                         T scale) {
-    constexpr int L = z_rows<T, NR>();
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    zrow_inverse<T, NR, false>(lds, stw, twf, in + row0 * (NR / 2 + 1), out + row0 * NR, nl, scale, 0.0);
+    k_fft_z_c2r_body<T, NR>::run(in, out, twh, twf, nrows, scale);
 }
 
 // ---------------------------------------------------------------- launch helpers
@@ -115,13 +147,19 @@ hipError_t launch_strided(const c2<T>* in, c2<T>* out, const c2<T>* tw, int C, i
     constexpr int L = strided_lines<T, N>();
     const size_t smem = lines_smem<T, N, L, 1>();
     static_assert(lines_smem<T, N, L, 1>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
-    auto kern = XLINES ? k_fft_xlines<T, N, DIR> : k_fft_ylines<T, N, DIR>;
-    static std::once_flag flag;
-    set_smem_limit(kern, smem, flag);
     const long nlines = (long)C * nouter;
     const int ntiles = (int)((nlines + L - 1) / L);
-    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), smem, s, in, out, tw, C, (int)nlines, ostride,
-                       estride);
+    if constexpr (XLINES) {
+        static std::once_flag flag;
+        set_smem_limit(k_fft_xlines<T, N, DIR>, smem, flag);
+        launch_k<k_fft_xlines_body<T, N, DIR>>(k_fft_xlines<T, N, DIR>, dim3(ntiles), dim3(kThreads), smem, s, in,
+                                               out, tw, C, (int)nlines, ostride, estride);
+    } else {
+        static std::once_flag flag;
+        set_smem_limit(k_fft_ylines<T, N, DIR>, smem, flag);
+        launch_k<k_fft_ylines_body<T, N, DIR>>(k_fft_ylines<T, N, DIR>, dim3(ntiles), dim3(kThreads), smem, s, in,
+                                               out, tw, C, (int)nlines, ostride, estride);
+    }
     return hipGetLastError();
 }
 
@@ -136,14 +174,14 @@ hipError_t launch_z(bool forward, const void* in, void* out, const c2<T>* twh, c
         auto kern = k_fft_z_r2c<T, NR>;
         static std::once_flag flag_f;
         set_smem_limit(kern, smem, flag_f);
-        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), smem, s, (const T*)in, (c2<T>*)out, twh, twf,
-                           nrows);
+        launch_k<k_fft_z_r2c_body<T, NR>>(kern, dim3(nblk), dim3(kThreads), smem, s, (const T*)in, (c2<T>*)out,
+                                          twh, twf, nrows);
     } else {
         auto kern = k_fft_z_c2r<T, NR>;
         static std::once_flag flag_i;
         set_smem_limit(kern, smem, flag_i);
-        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), smem, s, (const c2<T>*)in, (T*)out, twh, twf,
-                           nrows, scale);
+        launch_k<k_fft_z_c2r_body<T, NR>>(kern, dim3(nblk), dim3(kThreads), smem, s, (const c2<T>*)in, (T*)out,
+                                          twh, twf, nrows, scale);
     }
     return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 #include "fused.h"
 
 #include "blocksum.h"
+#include "launch.h"
 #include "remainders.h"
 #include "zrows.h"
 
@@ -146,35 +147,49 @@ template <typename T, int L> struct DerivYOp {
 };
 
 template <typename T, int N>
+struct k_deriv_x_body {
+    static __device__ __forceinline__ void run(GridK g, const c2<T>* S, c2<T>* A, c2<T>* B, c2<T>* C,
+                                                      const c2<T>* __restrict__ tw) {
+        constexpr int L = lines_per_block<T, N, 1>();
+        constexpr int LS = line_stride<N>();
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ LineTile<L> tile;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * LS;
+        load_table<T>(stw, tw, N);
+        tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
+        __syncthreads();
+        lines_fft_seq<T, N, L, +1, true>(
+            lds, stw, DerivXOp<T, L>{&tile, S, A, B, C, (long)g.ny * g.nzh, g.nx, kPi / g.X[0]});
+    }
+};
+template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_deriv_x(GridK g, const c2<T>* S, c2<T>* A, c2<T>* B, c2<T>* C,
                                                       const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block<T, N, 1>();
-    constexpr int LS = line_stride<N>();
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ LineTile<L> tile;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, tw, N);
-    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
-    __syncthreads();
-    lines_fft_seq<T, N, L, +1, true>(
-        lds, stw, DerivXOp<T, L>{&tile, S, A, B, C, (long)g.ny * g.nzh, g.nx, kPi / g.X[0]});
+    k_deriv_x_body<T, N>::run(g, S, A, B, C, tw);
 }
 
 template <typename T, int N>
+struct k_deriv_y_body {
+    static __device__ __forceinline__ void run(GridK g, c2<T>* A, c2<T>* B, c2<T>* C, c2<T>* D,
+                                                      const c2<T>* __restrict__ tw) {
+        constexpr int L = lines_per_block<T, N, 1>();
+        constexpr int LS = line_stride<N>();
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ LineTile<L> tile;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * LS;
+        load_table<T>(stw, tw, N);
+        tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
+        __syncthreads();
+        lines_fft_seq<T, N, L, +1, true>(
+            lds, stw, DerivYOp<T, L>{&tile, A, B, C, D, (long)g.nzh, g.ny, kPi / g.X[1], kPi / g.X[2]});
+    }
+};
+template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_deriv_y(GridK g, c2<T>* A, c2<T>* B, c2<T>* C, c2<T>* D,
                                                       const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block<T, N, 1>();
-    constexpr int LS = line_stride<N>();
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ LineTile<L> tile;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, tw, N);
-    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
-    __syncthreads();
-    lines_fft_seq<T, N, L, +1, true>(
-        lds, stw, DerivYOp<T, L>{&tile, A, B, C, D, (long)g.nzh, g.ny, kPi / g.X[1], kPi / g.X[2]});
+    k_deriv_y_body<T, N>::run(g, A, B, C, D, tw);
 }
 
 // RowPairStore that also accumulates the stored values (FP64, compensated).
@@ -300,64 +315,72 @@ template <typename T, int M, int K, bool VEL> struct GradNormStore {
 };
 
 template <typename T, int NR, bool VEL>
+struct k_deriv_z_body {
+    static __device__ __forceinline__ void run(DerivZArgs<T> z, VelocityArgs<T> va,
+                                                      const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
+                                                      long nrows, T scale, double az, double* part) {
+        constexpr int L = z_rows<T, NR>();
+        constexpr int MS = NR / 2 + 1;
+        constexpr int M = NR / 2;
+        constexpr int K = z_out_slots<T, NR>();
+        if (halted(z.halt)) {
+            if constexpr (VEL) {
+                const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
+                for (long i = r0 + threadIdx.x; i < r1; i += kThreads) z.phi[i] = va.po[i];
+            }
+            return;
+        }
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, M);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        const long si = row0 * MS, ro = row0 * NR;
+        auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
+        auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
+        // each input is fetched into registers while the previous output is transformed
+        c2<T> pre[z_fetch_count<T, NR>()];
+        zrow_fetch<T, NR>(pre, z.A + si, nl);
+        zrow_put<T, NR, false>(lds, pre, az);
+        Neu acc;   // this thread's share of sum phi over the tile
+        zrow_inverse_lds<T, NR>(lds, stw, twf, SumRowPairStore<T, M>{pw(z.phi), nl, scale, acc});
+        // gradient components in registers: gz and gx with VEL, else their sum of squares
+        c2<T> kz[K], kx[K];
+        __syncthreads();
+        zrow_put<T, NR, true>(lds, pre, az);
+        zrow_fetch<T, NR>(pre, z.B + si, nl);
+        zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{kz, true, scale});
+        __syncthreads();
+        zrow_put<T, NR, false>(lds, pre, az);
+        zrow_fetch<T, NR>(pre, z.D + si, nl);
+        zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{VEL ? kx : kz, false, scale});
+        __syncthreads();
+        zrow_put<T, NR, false>(lds, pre, az);
+        zrow_fetch<T, NR>(pre, z.C + si, nl);
+        zrow_inverse_lds<T, NR>(
+            lds, stw, twf,
+            GradNormStore<T, M, K, VEL>{kz, kz, kx, pw(z.gn), pr(z.phi), VEL ? pr(va.po) : nullptr,
+                                        VEL ? pw(va.G) : nullptr, VEL ? pw(va.vx) : nullptr, VEL ? pw(va.vy) : nullptr,
+                                        VEL ? pw(va.vz) : nullptr, nl, scale, (T)(VEL ? 1.0 / va.tau : 0.0),
+                                        va.thr});
+        __syncthreads();
+        zrow_put<T, NR, false>(lds, pre, az);
+        zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, M>{pw(z.lap), nl, scale});
+        if (part) {
+            // block partial of sum phi over this tile, for the integral of phi the
+            // next R1 evaluation needs
+            __syncthreads();
+            const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
+            if (threadIdx.x == 0) part[blockIdx.x] = tot;
+        }
+    }
+};
+template <typename T, int NR, bool VEL>
 __global__ __launch_bounds__(kThreads) void k_deriv_z(DerivZArgs<T> z, VelocityArgs<T> va,
                                                       const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
                                                       long nrows, T scale, double az, double* part) {
-    constexpr int L = z_rows<T, NR>();
-    constexpr int MS = NR / 2 + 1;
-    constexpr int M = NR / 2;
-    constexpr int K = z_out_slots<T, NR>();
-    if (halted(z.halt)) {
-        if constexpr (VEL) {
-            const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
-            for (long i = r0 + threadIdx.x; i < r1; i += kThreads) z.phi[i] = va.po[i];
-        }
-        return;
-    }
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, M);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    const long si = row0 * MS, ro = row0 * NR;
-    auto pr = [&](const T* f) { return reinterpret_cast<const c2<T>*>(f + ro); };
-    auto pw = [&](T* f) { return reinterpret_cast<c2<T>*>(f + ro); };
-    // each input is fetched into registers while the previous output is transformed
-    c2<T> pre[z_fetch_count<T, NR>()];
-    zrow_fetch<T, NR>(pre, z.A + si, nl);
-    zrow_put<T, NR, false>(lds, pre, az);
-    Neu acc;   // this thread's share of sum phi over the tile
-    zrow_inverse_lds<T, NR>(lds, stw, twf, SumRowPairStore<T, M>{pw(z.phi), nl, scale, acc});
-    // gradient components in registers: gz and gx with VEL, else their sum of squares
-    c2<T> kz[K], kx[K];
-    __syncthreads();
-    zrow_put<T, NR, true>(lds, pre, az);
-    zrow_fetch<T, NR>(pre, z.B + si, nl);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{kz, true, scale});
-    __syncthreads();
-    zrow_put<T, NR, false>(lds, pre, az);
-    zrow_fetch<T, NR>(pre, z.D + si, nl);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, GradStash<T, K, VEL>{VEL ? kx : kz, false, scale});
-    __syncthreads();
-    zrow_put<T, NR, false>(lds, pre, az);
-    zrow_fetch<T, NR>(pre, z.C + si, nl);
-    zrow_inverse_lds<T, NR>(
-        lds, stw, twf,
-        GradNormStore<T, M, K, VEL>{kz, kz, kx, pw(z.gn), pr(z.phi), VEL ? pr(va.po) : nullptr,
-                                    VEL ? pw(va.G) : nullptr, VEL ? pw(va.vx) : nullptr, VEL ? pw(va.vy) : nullptr,
-                                    VEL ? pw(va.vz) : nullptr, nl, scale, (T)(VEL ? 1.0 / va.tau : 0.0),
-                                    va.thr});
-    __syncthreads();
-    zrow_put<T, NR, false>(lds, pre, az);
-    zrow_inverse_lds<T, NR>(lds, stw, twf, RowPairStore<T, M>{pw(z.lap), nl, scale});
-    if (part) {
-        // block partial of sum phi over this tile, for the integral of phi the
-        // next R1 evaluation needs
-        __syncthreads();
-        const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
-        if (threadIdx.x == 0) part[blockIdx.x] = tot;
-    }
+    k_deriv_z_body<T, NR, VEL>::run(z, va, twh, twf, nrows, scale, az, part);
 }
 
 // z rows c2r of an increment spectrum D with the recovery of U in the store
@@ -396,52 +419,69 @@ template <typename T, int M> struct RecoverStore {
 };
 
 template <typename T, int NR>
+struct k_z_c2r_recover_body {
+    static __device__ __forceinline__ void run(const c2<T>* D, const T* uo, const T* G, T* out,
+                                                            const c2<T>* __restrict__ twh,
+                                                            const c2<T>* __restrict__ twf, long nrows, T scale,
+                                                            double thr, const double* halt) {
+        constexpr int L = z_rows<T, NR>();
+        constexpr int M = NR / 2;
+        if (halted(halt)) {   // U keeps its value: out = u_old
+            if (out != uo) {
+                const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
+                for (long i = r0 + threadIdx.x; i < r1; i += kThreads) out[i] = uo[i];
+            }
+            return;
+        }
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, M);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        const long ro = row0 * NR;
+        c2<T> pre[z_fetch_count<T, NR>()];
+        zrow_fetch<T, NR>(pre, D + row0 * (M + 1), nl);
+        zrow_put<T, NR, false>(lds, pre, 0.0);
+        zrow_inverse_lds<T, NR>(lds, stw, twf,
+                                RecoverStore<T, M>{reinterpret_cast<const c2<T>*>(uo + ro),
+                                                   reinterpret_cast<const c2<T>*>(G + ro),
+                                                   reinterpret_cast<c2<T>*>(out + ro), nl, scale, thr});
+    }
+};
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_c2r_recover(const c2<T>* D, const T* uo, const T* G, T* out,
                                                             const c2<T>* __restrict__ twh,
                                                             const c2<T>* __restrict__ twf, long nrows, T scale,
                                                             double thr, const double* halt) {
-    constexpr int L = z_rows<T, NR>();
-    constexpr int M = NR / 2;
-    if (halted(halt)) {   // U keeps its value: out = u_old
-        if (out != uo) {
-            const long r0 = (long)blockIdx.x * L * NR, r1 = min(r0 + (long)L * NR, nrows * NR);
-            for (long i = r0 + threadIdx.x; i < r1; i += kThreads) out[i] = uo[i];
-        }
-        return;
-    }
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, M);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    const long ro = row0 * NR;
-    c2<T> pre[z_fetch_count<T, NR>()];
-    zrow_fetch<T, NR>(pre, D + row0 * (M + 1), nl);
-    zrow_put<T, NR, false>(lds, pre, 0.0);
-    zrow_inverse_lds<T, NR>(lds, stw, twf,
-                            RecoverStore<T, M>{reinterpret_cast<const c2<T>*>(uo + ro),
-                                               reinterpret_cast<const c2<T>*>(G + ro),
-                                               reinterpret_cast<c2<T>*>(out + ro), nl, scale, thr});
+    k_z_c2r_recover_body<T, NR>::run(D, uo, G, out, twh, twf, nrows, scale, thr, halt);
 }
 
 // ------------------------------------------------------------------ forward pair + ETD
 template <typename T, int NR>
+struct k_z_r2c_pair_body {
+    static __device__ __forceinline__ void run(const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
+                                                         const c2<T>* __restrict__ twh,
+                                                         const c2<T>* __restrict__ twf, long nrows) {
+        constexpr int L = z_rows<T, NR>();
+        constexpr int MS = NR / 2 + 1;
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, NR / 2);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        __syncthreads();
+        zrow_forward<T, NR>(lds, stw, twf, P + row0 * NR, WP + row0 * MS, nl);
+        __syncthreads();
+        zrow_forward<T, NR>(lds, stw, twf, Q + row0 * NR, WQ + row0 * MS, nl);
+    }
+};
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_pair(const T* P, const T* Q, c2<T>* WP, c2<T>* WQ,
                                                          const c2<T>* __restrict__ twh,
                                                          const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows<T, NR>();
-    constexpr int MS = NR / 2 + 1;
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    __syncthreads();
-    zrow_forward<T, NR>(lds, stw, twf, P + row0 * NR, WP + row0 * MS, nl);
-    __syncthreads();
-    zrow_forward<T, NR>(lds, stw, twf, Q + row0 * NR, WQ + row0 * MS, nl);
+    k_z_r2c_pair_body<T, NR>::run(P, Q, WP, WQ, twh, twf, nrows);
 }
 
 // ------------------------------------------------------------------ z r2c with R1 / P2 producers
@@ -609,48 +649,66 @@ template <typename T, int M, bool BAND> struct QPairLoad {
 };
 
 template <typename T, int NR>
+struct k_z_r2c_q_body {
+    static __device__ __forceinline__ void run(const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W,
+                                                      const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
+                                                      long nrows, double* part) {
+        constexpr int L = z_rows<T, NR>();
+        extern __shared__ unsigned char smem_raw[];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * z_row_stride<NR>();
+        load_table<T>(stw, twh, NR / 2);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        const long ro = row0 * NR;
+        Neu acc;
+        if (mask)
+            zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, true>{u + ro, G + ro, mask + ro, nl, ubar, acc},
+                                   W + row0 * (NR / 2 + 1), nl);
+        else
+            zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, false>{u + ro, G + ro, nullptr, nl, ubar, acc},
+                                   W + row0 * (NR / 2 + 1), nl);
+        __syncthreads();
+        const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
+        if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    }
+};
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, const uint8_t* mask, T ubar, c2<T>* W,
                                                       const c2<T>* __restrict__ twh, const c2<T>* __restrict__ twf,
                                                       long nrows, double* part) {
-    constexpr int L = z_rows<T, NR>();
-    extern __shared__ unsigned char smem_raw[];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    const long ro = row0 * NR;
-    Neu acc;
-    if (mask)
-        zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, true>{u + ro, G + ro, mask + ro, nl, ubar, acc},
-                               W + row0 * (NR / 2 + 1), nl);
-    else
-        zrow_forward_op<T, NR>(lds, stw, twf, QPairLoad<T, NR / 2, false>{u + ro, G + ro, nullptr, nl, ubar, acc},
-                               W + row0 * (NR / 2 + 1), nl);
-    __syncthreads();
-    const double tot = block_sum_256(acc.val(), reinterpret_cast<double*>(lds));
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    k_z_r2c_q_body<T, NR>::run(u, G, mask, ubar, W, twh, twf, nrows, part);
 }
 
+template <typename T, int NR>
+struct k_z_r2c_r1_body {
+    static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
+                                                       const T* u, const uint8_t* mask,
+                                                       const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
+                                                       const c2<T>* __restrict__ twh,
+                                                       const c2<T>* __restrict__ twf, long nrows) {
+        constexpr int L = z_rows_pair<T, NR>();
+        constexpr int MS = NR / 2 + 1;
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ RowTile<L> rt;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
+        load_table<T>(stw, twh, NR / 2);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        row_tile_setup<L>(rt, g, row0);
+        __syncthreads();
+        const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
+        zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+    }
+};
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
                                                        const T* u, const uint8_t* mask,
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows_pair<T, NR>();
-    constexpr int MS = NR / 2 + 1;
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ RowTile<L> rt;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
-    load_table<T>(stw, twh, NR / 2);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    row_tile_setup<L>(rt, g, row0);
-    __syncthreads();
-    const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
-    zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+    k_z_r2c_r1_body<T, NR>::run(g, K, phi, lap, gn, u, mask, int_phi, A0, WP, WQ, twh, twf, nrows);
 }
 
 // The pairs of an inverse z transform kept in the LDS (row l at l * M).
@@ -669,34 +727,45 @@ template <typename T, int NR, bool PSI_HAT> constexpr size_t z_smem_p2() {
 }
 
 template <typename T, int NR, bool PSI_HAT>
+struct k_z_r2c_p2_body {
+    static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
+                                                       const T* vy, const T* vz, const T* psi,
+                                                       const c2<T>* psi_hat, T psi_scale, const double* m,
+                                                       const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
+                                                       const c2<T>* __restrict__ twh,
+                                                       const c2<T>* __restrict__ twf, long nrows) {
+        constexpr int L = z_rows_pair<T, NR>();
+        constexpr int MS = NR / 2 + 1;
+        constexpr int M = NR / 2;
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ RowTile<L> rt;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
+        c2<T>* psl = PSI_HAT ? stw + M : nullptr;   // the tile's psi pairs
+        load_table<T>(stw, twh, M);
+        const long row0 = (long)blockIdx.x * L;
+        const int nl = (int)min((long)L, nrows - row0);
+        row_tile_setup<L>(rt, g, row0);
+        if constexpr (PSI_HAT) {
+            // psi of the tile's rows: inverse z transform of its spectrum into the LDS
+            c2<T> pre[z_fetch_count<T, NR, L>()];
+            zrow_fetch<T, NR, L>(pre, psi_hat + row0 * MS, nl);
+            zrow_put<T, NR, false, L>(lds, pre, 0.0);
+            zrow_inverse_lds<T, NR, LdsPairStore<T, M>, L>(lds, stw, twf, LdsPairStore<T, M>{psl, psi_scale});
+        }
+        __syncthreads();
+        const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0]), psl};
+        zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+    }
+};
+template <typename T, int NR, bool PSI_HAT>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
                                                        const T* vy, const T* vz, const T* psi,
                                                        const c2<T>* psi_hat, T psi_scale, const double* m,
                                                        const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    constexpr int L = z_rows_pair<T, NR>();
-    constexpr int MS = NR / 2 + 1;
-    constexpr int M = NR / 2;
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ RowTile<L> rt;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + 2 * L * z_row_stride<NR>();
-    c2<T>* psl = PSI_HAT ? stw + M : nullptr;   // the tile's psi pairs
-    load_table<T>(stw, twh, M);
-    const long row0 = (long)blockIdx.x * L;
-    const int nl = (int)min((long)L, nrows - row0);
-    row_tile_setup<L>(rt, g, row0);
-    if constexpr (PSI_HAT) {
-        // psi of the tile's rows: inverse z transform of its spectrum into the LDS
-        c2<T> pre[z_fetch_count<T, NR, L>()];
-        zrow_fetch<T, NR, L>(pre, psi_hat + row0 * MS, nl);
-        zrow_put<T, NR, false, L>(lds, pre, 0.0);
-        zrow_inverse_lds<T, NR, LdsPairStore<T, M>, L>(lds, stw, twf, LdsPairStore<T, M>{psl, psi_scale});
-    }
-    __syncthreads();
-    const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0]), psl};
-    zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
+    k_z_r2c_p2_body<T, NR, PSI_HAT>::run(g, K, u, G, vx, vy, vz, psi, psi_hat, psi_scale, m, mask, WP, WQ, twh, twf, nrows);
 }
 
 // two spectra through the same plain line transform, one after the other
@@ -720,17 +789,23 @@ template <typename T, int L> struct PairOp {
 };
 
 template <typename T, int N>
+struct k_y_pair_body {
+    static __device__ __forceinline__ void run(GridK g, c2<T>* X0, c2<T>* X1, const c2<T>* __restrict__ tw) {
+        constexpr int L = lines_per_block<T, N, 1>();
+        constexpr int LS = line_stride<N>();
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ LineTile<L> tile;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * LS;
+        load_table<T>(stw, tw, N);
+        tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
+        __syncthreads();
+        lines_fft_seq<T, N, L, -1, true>(lds, stw, PairOp<T, L>{&tile, X0, X1, (long)g.nzh});
+    }
+};
+template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_y_pair(GridK g, c2<T>* X0, c2<T>* X1, const c2<T>* __restrict__ tw) {
-    constexpr int L = lines_per_block<T, N, 1>();
-    constexpr int LS = line_stride<N>();
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ LineTile<L> tile;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, tw, N);
-    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.nx * g.nzh, (long)g.ny * g.nzh);
-    __syncthreads();
-    lines_fft_seq<T, N, L, -1, true>(lds, stw, PairOp<T, L>{&tile, X0, X1, (long)g.nzh});
+    k_y_pair_body<T, N>::run(g, X0, X1, tw);
 }
 
 // forward x lines of P and Q (both fetched up front, transformed one after
@@ -812,37 +887,45 @@ template <typename T, int N> constexpr int xline_tile() {
 // passes need: the derivative triple (S, i kx S, -kx^2 S) -> (X0, X1, X2)
 // after a phi stage, the plain inverse -> X0 after a u stage.
 template <int ST, typename T, int N, int L>
+struct k_x_etd_body {
+    static __device__ __forceinline__ void run(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
+                                                    EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
+                                                    const c2<T>* __restrict__ tw) {
+        if (halted(a.halt)) return;   // the state spectrum keeps its value
+        constexpr int LS = line_stride<N>();
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ LineTile<L> tile;
+        __shared__ double kyz[L];
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * LS;
+        load_table<T>(stw, tw, N);
+        tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
+        if (threadIdx.x < L) {   // the entries tile_setup wrote in this thread
+            const double ly = (kPi / g.X[1]) * lam_index(tile.o[threadIdx.x], g.ny);
+            const double lz = (kPi / g.X[2]) * tile.c[threadIdx.x];
+            kyz[threadIdx.x] = ly * ly + lz * lz;
+        }
+        __syncthreads();
+        const long es = (long)g.ny * g.nzh;
+        lines_fft_seq_joint<T, N, L, -1, true>(
+            lds, stw,
+            EtdXOp<ST, T, L, LS, (N <= 256)>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K,
+                                             a, lds, kyz, store_out});
+        __syncthreads();
+        if constexpr (ST == ETD_STAGE_PHI1 || ST == ETD_STAGE_PHI2) {
+            lines_fft_seq<T, N, L, +1, true, DerivXOp<T, L, LS>, true>(
+                lds, stw, DerivXOp<T, L, LS>{&tile, lds, X0, X1, X2, es, g.nx, kPi / g.X[0]});
+        } else {
+            lines_fft_seq<T, N, L, +1, true, InvXFromLds<T, L, LS>, true>(lds, stw,
+                                                                           InvXFromLds<T, L, LS>{&tile, lds, X0, es});
+        }
+    }
+};
+template <int ST, typename T, int N, int L>
 __global__ __launch_bounds__(kThreads) void k_x_etd(GridK g, CoupledK K, const c2<T>* P, const c2<T>* Q,
                                                     EtdArgs<T> a, int store_out, c2<T>* X0, c2<T>* X1, c2<T>* X2,
                                                     const c2<T>* __restrict__ tw) {
-    if (halted(a.halt)) return;   // the state spectrum keeps its value
-    constexpr int LS = line_stride<N>();
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ LineTile<L> tile;
-    __shared__ double kyz[L];
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, tw, N);
-    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), g.nzh, g.ny * g.nzh, (long)g.nzh);
-    if (threadIdx.x < L) {   // the entries tile_setup wrote in this thread
-        const double ly = (kPi / g.X[1]) * lam_index(tile.o[threadIdx.x], g.ny);
-        const double lz = (kPi / g.X[2]) * tile.c[threadIdx.x];
-        kyz[threadIdx.x] = ly * ly + lz * lz;
-    }
-    __syncthreads();
-    const long es = (long)g.ny * g.nzh;
-    lines_fft_seq_joint<T, N, L, -1, true>(
-        lds, stw,
-        EtdXOp<ST, T, L, LS, (N <= 256)>{&tile, P, Q, es, g.nx, g.ny, kPi / g.X[0], kPi / g.X[1], kPi / g.X[2], &K,
-                                         a, lds, kyz, store_out});
-    __syncthreads();
-    if constexpr (ST == ETD_STAGE_PHI1 || ST == ETD_STAGE_PHI2) {
-        lines_fft_seq<T, N, L, +1, true, DerivXOp<T, L, LS>, true>(
-            lds, stw, DerivXOp<T, L, LS>{&tile, lds, X0, X1, X2, es, g.nx, kPi / g.X[0]});
-    } else {
-        lines_fft_seq<T, N, L, +1, true, InvXFromLds<T, L, LS>, true>(lds, stw,
-                                                                       InvXFromLds<T, L, LS>{&tile, lds, X0, es});
-    }
+    k_x_etd_body<ST, T, N, L>::run(g, K, P, Q, a, store_out, X0, X1, X2, tw);
 }
 
 // ------------------------------------------------------------------ (-Delta_h)^{-1}
@@ -872,30 +955,40 @@ template <typename T, int L> struct TileStore {
 // Lines along the last forward axis: forward transform, times 1/mu with
 // mu = fde[e] + fdo[o] + fdc[c] (0 where mu = 0), inverse transform, in place.
 template <typename T, int N>
+struct k_lapinv_lines_body {
+    static __device__ __forceinline__ void run(c2<T>* X, const c2<T>* __restrict__ tw, int C,
+                                                           int nlines, long ostride, long es,
+                                                           const double* __restrict__ fde,
+                                                           const double* __restrict__ fdo,
+                                                           const double* __restrict__ fdc) {
+        constexpr int L = lines_per_block_8<T, N, 1>();
+        constexpr int LS = line_stride<N>();
+        extern __shared__ unsigned char smem_raw[];
+        __shared__ LineTile<L> tile;
+        c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+        c2<T>* stw = lds + L * LS;
+        load_table<T>(stw, tw, N);
+        tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), C, nlines, ostride);
+        __syncthreads();
+        lines_fft_to_lds<T, N, L, LS, 1, -1, true>(lds, stw, TileLoad<T, L>{&tile, X, es});
+        for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
+            const int l = idx % L, e = idx / L;
+            const double mu = fde[e] + fdo[tile.o[l]] + fdc[tile.c[l]];
+            const T m = (T)(mu > 0.0 ? 1.0 / mu : 0.0);
+            c2<T>& v = lds[l * LS + sk(e)];
+            v = cscale(v, m);
+        }
+        __syncthreads();
+        lines_fft_from_lds<T, N, L, LS, +1, true>(lds, stw, TileStore<T, L>{&tile, X, es});
+    }
+};
+template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_lapinv_lines(c2<T>* X, const c2<T>* __restrict__ tw, int C,
                                                            int nlines, long ostride, long es,
                                                            const double* __restrict__ fde,
                                                            const double* __restrict__ fdo,
                                                            const double* __restrict__ fdc) {
-    constexpr int L = lines_per_block_8<T, N, 1>();
-    constexpr int LS = line_stride<N>();
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ LineTile<L> tile;
-    c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-    c2<T>* stw = lds + L * LS;
-    load_table<T>(stw, tw, N);
-    tile_setup<L>(tile, xcd_remap(blockIdx.x, gridDim.x), C, nlines, ostride);
-    __syncthreads();
-    lines_fft_to_lds<T, N, L, LS, 1, -1, true>(lds, stw, TileLoad<T, L>{&tile, X, es});
-    for (int idx = threadIdx.x; idx < L * N; idx += kThreads) {
-        const int l = idx % L, e = idx / L;
-        const double mu = fde[e] + fdo[tile.o[l]] + fdc[tile.c[l]];
-        const T m = (T)(mu > 0.0 ? 1.0 / mu : 0.0);
-        c2<T>& v = lds[l * LS + sk(e)];
-        v = cscale(v, m);
-    }
-    __syncthreads();
-    lines_fft_from_lds<T, N, L, LS, +1, true>(lds, stw, TileStore<T, L>{&tile, X, es});
+    k_lapinv_lines_body<T, N>::run(X, tw, C, nlines, ostride, es, fde, fdo, fdc);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -907,7 +1000,7 @@ template <typename T, int N> hipError_t launch_deriv_x(const GridK& g, const c2<
     static std::once_flag flag;
     set_smem_limit(k_deriv_x<T, N>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_deriv_x<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, S, A, B, C, tw);
+    launch_k<k_deriv_x_body<T, N>>(k_deriv_x<T, N>, dim3(ntiles), dim3(kThreads), smem, s, g, S, A, B, C, tw);
     return hipGetLastError();
 }
 template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A, c2<T>* B, c2<T>* C, c2<T>* D,
@@ -918,7 +1011,7 @@ template <typename T, int N> hipError_t launch_deriv_y(const GridK& g, c2<T>* A,
     static std::once_flag flag;
     set_smem_limit(k_deriv_y<T, N>, smem, flag);
     const int ntiles = (g.nx * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_deriv_y<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, A, B, C, D, tw);
+    launch_k<k_deriv_y_body<T, N>>(k_deriv_y<T, N>, dim3(ntiles), dim3(kThreads), smem, s, g, A, B, C, D, tw);
     return hipGetLastError();
 }
 template <typename T, int NR, bool VEL>
@@ -926,7 +1019,7 @@ void launch_deriv_z_k(int nb, size_t smem, const DerivZArgs<T>& z, const Velocit
                       const c2<T>* twf, long nrows, T scale, double az, double* part, hipStream_t s) {
     static std::once_flag flag;
     set_smem_limit(k_deriv_z<T, NR, VEL>, smem, flag);
-    hipLaunchKernelGGL((k_deriv_z<T, NR, VEL>), dim3(nb), dim3(kThreads), smem, s, z, va, twh, twf, nrows, scale,
+    launch_k<k_deriv_z_body<T, NR, VEL>>(k_deriv_z<T, NR, VEL>, dim3(nb), dim3(kThreads), smem, s, z, va, twh, twf, nrows, scale,
                        az, part);
 }
 template <typename T, int NR> hipError_t launch_deriv_z(const GridK& g, const DerivZArgs<T>& z,
@@ -957,7 +1050,7 @@ hipError_t launch_z_recover(const GridK& g, const c2<T>* D, const T* uo, const T
     set_smem_limit(k_z_c2r_recover<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
-    hipLaunchKernelGGL((k_z_c2r_recover<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, D, uo, G,
+    launch_k<k_z_c2r_recover_body<T, NR>>(k_z_c2r_recover<T, NR>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, D, uo, G,
                        out, twh, twf, nrows, scale, thr, halt);
     return hipGetLastError();
 }
@@ -971,7 +1064,7 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
     set_smem_limit(k_z_r2c_q<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     const int nb = (int)((nrows + L - 1) / L);
-    hipLaunchKernelGGL((k_z_r2c_q<T, NR>), dim3(nb), dim3(kThreads), smem, s, u, G, mask, ubar, W, twh, twf, nrows,
+    launch_k<k_z_r2c_q_body<T, NR>>(k_z_r2c_q<T, NR>, dim3(nb), dim3(kThreads), smem, s, u, G, mask, ubar, W, twh, twf, nrows,
                        msum.part);
     reduce_final_sum(msum.part, nb, msum.scale, msum.out, s, msum.halt);
     return hipGetLastError();
@@ -986,7 +1079,7 @@ hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, 
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
-    hipLaunchKernelGGL((k_z_r2c_r1<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
+    launch_k<k_z_r2c_r1_body<T, NR>>(k_z_r2c_r1<T, NR>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
                        f.lap, f.gn, f.u, f.mask, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
     return hipGetLastError();
 }
@@ -1002,14 +1095,14 @@ hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, 
         static_assert(z_smem_p2<T, NR, true>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, true>, smem, flag);
-        hipLaunchKernelGGL((k_z_r2c_p2<T, NR, true>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
+        launch_k<k_z_r2c_p2_body<T, NR, true>>(k_z_r2c_p2<T, NR, true>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
                            f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
     } else {
         const size_t smem = z_smem_p2<T, NR, false>();
         static_assert(z_smem_p2<T, NR, false>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, false>, smem, flag);
-        hipLaunchKernelGGL((k_z_r2c_p2<T, NR, false>), grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
+        launch_k<k_z_r2c_p2_body<T, NR, false>>(k_z_r2c_p2<T, NR, false>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
                            f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
     }
     return hipGetLastError();
@@ -1022,7 +1115,7 @@ template <typename T, int NR> hipError_t launch_z_pair(const GridK& g, const T* 
     static std::once_flag flag;
     set_smem_limit(k_z_r2c_pair<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
-    hipLaunchKernelGGL((k_z_r2c_pair<T, NR>), dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, P, Q, WP, WQ,
+    launch_k<k_z_r2c_pair_body<T, NR>>(k_z_r2c_pair<T, NR>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, P, Q, WP, WQ,
                        twh, twf, nrows);
     return hipGetLastError();
 }
@@ -1034,7 +1127,7 @@ template <typename T, int N> hipError_t launch_y_pair(const GridK& g, c2<T>* X0,
     static std::once_flag flag;
     set_smem_limit(k_y_pair<T, N>, smem, flag);
     const int ntiles = (g.nx * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_y_pair<T, N>), dim3(ntiles), dim3(kThreads), smem, s, g, X0, X1, tw);
+    launch_k<k_y_pair_body<T, N>>(k_y_pair<T, N>, dim3(ntiles), dim3(kThreads), smem, s, g, X0, X1, tw);
     return hipGetLastError();
 }
 template <int ST, typename T, int N, int L>
@@ -1045,7 +1138,7 @@ hipError_t launch_x_etd(const GridK& g, const CoupledK& K, const c2<T>* P, const
     static std::once_flag flag;
     set_smem_limit(k_x_etd<ST, T, N, L>, smem, flag);
     const int ntiles = (g.ny * g.nzh + L - 1) / L;
-    hipLaunchKernelGGL((k_x_etd<ST, T, N, L>), dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, store_out, X0,
+    launch_k<k_x_etd_body<ST, T, N, L>>(k_x_etd<ST, T, N, L>, dim3(ntiles), dim3(kThreads), smem, s, g, K, P, Q, a, store_out, X0,
                        X1, X2, tw);
     return hipGetLastError();
 }
@@ -1070,7 +1163,7 @@ hipError_t launch_lapinv(c2<T>* X, const c2<T>* tw, int C, int nouter, long ostr
     set_smem_limit(k_lapinv_lines<T, N>, smem, flag);
     const int nlines = C * nouter;
     const int ntiles = (nlines + L - 1) / L;
-    hipLaunchKernelGGL((k_lapinv_lines<T, N>), dim3(ntiles), dim3(kThreads), smem, s, X, tw, C, nlines, ostride, es,
+    launch_k<k_lapinv_lines_body<T, N>>(k_lapinv_lines<T, N>, dim3(ntiles), dim3(kThreads), smem, s, X, tw, C, nlines, ostride, es,
                        fde, fdo, fdc);
     return hipGetLastError();
 }
@@ -1358,30 +1451,67 @@ hipError_t c2r_recover(const GridK& g, const FFTTables<T>& t, const c2<T>* D, c2
     return c2r_recover_yz<T>(g, t, W, u_old, G, out, thr, halt, s);
 }
 
-#define INST(T)                                                                                                   \
+// The instantiations are spread over several compilations of this file, so
+// that they build in parallel: ETD_FUSED_PART = 2 * pipeline + precision,
+// pipelines 0 (R1 and the plain pair), 1 (P2), 2 (derivatives), 3
+// (recovery and the nonlocal inverse); undefined: all of them.
+#ifndef ETD_FUSED_PART
+#define ETD_FUSED_PART -1
+#endif
+#define ETD_PART(k) (ETD_FUSED_PART < 0 || ETD_FUSED_PART == (k))
+#define INST_R1(T)                                                                                                \
     template hipError_t r1_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const R1Fields<T>&,         \
                                   EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*, c2<T>*,      \
                                   hipStream_t);                                                                   \
-    template hipError_t p2_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const P2Fields<T>&,         \
-                                  EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, hipStream_t);        \
-    template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
-                                       const T*, T*, double, const double*, hipStream_t);                         \
-    template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
-                                        c2<T>*, T*, T*, T*, const GridSum*, hipStream_t);                         \
     template hipError_t fwd_pair_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, EtdStage, const T*,   \
                                         const T*, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, c2<T>*,        \
-                                        c2<T>*, hipStream_t);                                                     \
+                                        c2<T>*, hipStream_t);
+#define INST_P2(T)                                                                                                \
+    template hipError_t p2_etd<T>(const GridK&, const FFTTables<T>&, const CoupledK&, const P2Fields<T>&,         \
+                                  EtdStage, c2<T>*, c2<T>*, const EtdArgs<T>&, bool, c2<T>*, hipStream_t);
+#define INST_DERIVS(T)                                                                                            \
+    template hipError_t derivs_fused<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, c2<T>*, c2<T>*,  \
+                                        c2<T>*, T*, T*, T*, const GridSum*, hipStream_t);                         \
     template hipError_t derivs_fused_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, c2<T>*, c2<T>*, c2<T>*, T*, \
                                            T*, T*, const GridSum*, hipStream_t,                                   \
-                                           const VelocityArgs<T>*);                                               \
+                                           const VelocityArgs<T>*);
+#define INST_REST(T)                                                                                              \
+    template hipError_t c2r_recover<T>(const GridK&, const FFTTables<T>&, const c2<T>*, c2<T>*, const T*,         \
+                                       const T*, T*, double, const double*, hipStream_t);                         \
     template hipError_t c2r_recover_yz<T>(const GridK&, const FFTTables<T>&, c2<T>*, const T*, const T*, T*,      \
                                           double, const double*, hipStream_t);                                    \
     template hipError_t lapinv_fused<T>(const GridK&, const FFTTables<T>&, const double*, const T*, c2<T>*, T*,   \
                                         hipStream_t);                                                             \
     template hipError_t lapinv_q_fused<T>(const GridK&, const FFTTables<T>&, const double*, double, const T*,     \
                                           const T*, const uint8_t*, c2<T>*, T*, const GridSum&, hipStream_t);
-INST(float)
-INST(double)
-#undef INST
+#if ETD_PART(0)
+INST_R1(float)
+#endif
+#if ETD_PART(1)
+INST_R1(double)
+#endif
+#if ETD_PART(2)
+INST_P2(float)
+#endif
+#if ETD_PART(3)
+INST_P2(double)
+#endif
+#if ETD_PART(4)
+INST_DERIVS(float)
+#endif
+#if ETD_PART(5)
+INST_DERIVS(double)
+#endif
+#if ETD_PART(6)
+INST_REST(float)
+#endif
+#if ETD_PART(7)
+INST_REST(double)
+#endif
+#undef INST_R1
+#undef INST_P2
+#undef INST_DERIVS
+#undef INST_REST
+#undef ETD_PART
 
 }  // namespace etd

@@ -150,7 +150,14 @@ struct ScheduleState {
     std::vector<hipStream_t> side;     // capture branches (default priority)
     std::vector<hipEvent_t> join;      // one per branch
     hipEvent_t fork = nullptr;
-    std::map<std::string, hipGraphExec_t> graphs;   // keyed by pointer state and band-rebuild pattern
+    hipStream_t rec = nullptr;         // the grouped schedule's recording stream (default priority)
+    // captured graphs keyed by pointer state and band-rebuild pattern; a
+    // grouped graph also owns the device table of its launches' arguments
+    struct Captured {
+        hipGraphExec_t exec = nullptr;
+        void* table = nullptr;
+    };
+    std::map<std::string, Captured> graphs;
 };
 
 // One step of one instance, enqueued on stream s (api.hip).

@@ -6,6 +6,7 @@
 // results run to run; the totals stay on the device for later kernels.
 #include "blocksum.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace etd {
 
@@ -56,23 +57,30 @@ __global__ __launch_bounds__(kB) void k_reduce(F f, long n, double* part) {
 }
 
 template <int NS, int NM>
-__global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb, double* out, double scale,
+struct k_reduce_final_body {
+    static __device__ __forceinline__ void run(const double* part, int nb, double* out, double scale,
                                                    double* halt) {
-    __shared__ double sh[4];
-    for (int j = 0; j < NS + NM; ++j) {
-        Neu acc;
-        double mx = -INFINITY;
-        for (int b = threadIdx.x; b < nb; b += kB) {
-            const double v = part[(long)b * (NS + NM) + j];
-            if (j < NS) acc.add(v);
-            else mx = fmax(mx, v);
-        }
-        const double r = (j < NS) ? block_sum_256(acc.val(), sh) : block_max_256(mx, sh);
-        if (threadIdx.x == 0) {
-            out[j] = (j < NS) ? scale * r : r;
-            if (halt && j < NS && !isfinite(r)) *halt = 1.0;
+        __shared__ double sh[4];
+        for (int j = 0; j < NS + NM; ++j) {
+            Neu acc;
+            double mx = -INFINITY;
+            for (int b = threadIdx.x; b < nb; b += kB) {
+                const double v = part[(long)b * (NS + NM) + j];
+                if (j < NS) acc.add(v);
+                else mx = fmax(mx, v);
+            }
+            const double r = (j < NS) ? block_sum_256(acc.val(), sh) : block_max_256(mx, sh);
+            if (threadIdx.x == 0) {
+                out[j] = (j < NS) ? scale * r : r;
+                if (halt && j < NS && !isfinite(r)) *halt = 1.0;
+            }
         }
     }
+};
+template <int NS, int NM>
+__global__ __launch_bounds__(kB) void k_reduce_final(const double* part, int nb, double* out, double scale,
+                                                   double* halt) {
+    k_reduce_final_body<NS, NM>::run(part, nb, out, scale, halt);
 }
 
 template <int NS, int NM, class F>
@@ -281,7 +289,7 @@ void diag_ring_push(const double* diag, const double* halt, const int64_t* band_
 }
 
 void reduce_final_sum(const double* part, int nb, double scale, double* out, hipStream_t s, double* halt) {
-    hipLaunchKernelGGL((k_reduce_final<1, 0>), dim3(1), dim3(kB), 0, s, part, nb, out, scale, halt);
+    launch_k<k_reduce_final_body<1, 0>>(k_reduce_final<1, 0>, dim3(1), dim3(kB), 0, s, part, nb, out, scale, halt);
 }
 
 template <typename T>

@@ -12,9 +12,12 @@
 #include <string>
 #include <vector>
 
+#include "launch.h"
 #include "plan.h"
 
 using namespace etd;
+
+thread_local LaunchRecorder* etd::g_launch_recorder = nullptr;
 
 namespace {
 
@@ -113,6 +116,173 @@ etd_status capture_two_steps(etd_plan* plan, hipGraphExec_t* out) {
     return bad;
 }
 
+// Grouped schedule.  Two steps of every instance are recorded (launch_k
+// records instead of launching; the recording stream is under capture, so
+// any other device work a step would enqueue shows up as a graph node and is
+// refused), the instances whose launch sequences agree (kernel, grid, block,
+// LDS, argument size: one shape and configuration) form a group, and each
+// recorded pass of a group becomes ONE launch of the grouped twin over
+// gridDim.x tiles by as many rows as the group has instances, reading its
+// arguments from a device table.  The groups are spread round-robin over
+// min(branches, groups) concurrent branches of one captured graph.
+// Instances the grouped passes cover: coupled, three-dimensional, without a
+// band, diagnostics ring, mass projection or band solve.
+bool groupable(const Instance& I) {
+    return I.d.model == ETD_COUPLED && I.g.nx > 1 && !(I.d.band_threshold > 0.0) && !I.ring &&
+           !(I.d.flags & (ETD_F_MASS_PROJECT | ETD_F_SURFACE_NONLOCAL));
+}
+
+// The host-side state a step advances (restored when a capture fails).
+struct HostStepState {
+    void *phiA, *phiB, *u, *ut;
+    long step;
+};
+
+etd_status record_two_steps(etd_plan* plan, std::vector<LaunchRecorder>& rec) {
+    ScheduleState& S = plan->sched;
+    if (!S.rec) HIPCHK(plan, hipStreamCreateWithFlags(&S.rec, hipStreamNonBlocking));   // default priority
+    rec.assign(plan->inst.size(), LaunchRecorder{});
+    for (int k = 0; k < 2; ++k)
+        for (size_t i = 0; i < plan->inst.size(); ++i) {
+            Instance& I = plan->inst[i];
+            HIPCHK(plan, hipStreamBeginCapture(S.rec, hipStreamCaptureModeRelaxed));
+            g_launch_recorder = &rec[i];
+            const etd_status st = step_instance(plan, I, S.rec);
+            g_launch_recorder = nullptr;
+            ++I.step;
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(S.rec, &gr);
+            size_t nodes = 0;
+            if (e == hipSuccess && gr) e = hipGraphGetNodes(gr, nullptr, &nodes);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (st != ETD_OK) return st;
+            if (e != hipSuccess)
+                return fail(&plan->err, ETD_E_HIP, std::string("grouped schedule: recording: ") + hipGetErrorString(e));
+            if (nodes)
+                return fail(&plan->err, ETD_E_ARG,
+                            "grouped schedule: instance " + std::to_string(i) +
+                                " enqueues work the grouped passes do not cover (band list, diagnostics ring, mass "
+                                "projection, band solve, two-dimensional grid or fixed model); use ETD_EXEC_GRAPH");
+        }
+    return ETD_OK;
+}
+
+std::string launch_signature(const LaunchRecorder& r) {
+    std::string k;
+    char buf[128];
+    for (const LaunchRecord& op : r.ops) {
+        snprintf(buf, sizeof buf, "%p:%u.%u.%u:%u:%zu:%zu;", op.fn, op.grid.x, op.grid.y, op.grid.z, op.block.x, op.smem,
+                 op.args.size());
+        k += buf;
+    }
+    return k;
+}
+
+etd_status capture_grouped_steps(etd_plan* plan, ScheduleState::Captured* out);
+
+// On failure nothing ran and the host-side state is as before.
+etd_status capture_grouped(etd_plan* plan, ScheduleState::Captured* out) {
+    std::vector<HostStepState> before;
+    for (const Instance& I : plan->inst) before.push_back({I.phiA, I.phiB, I.u, I.ut, I.step});
+    const etd_status st = capture_grouped_steps(plan, out);
+    if (st != ETD_OK)
+        for (size_t i = 0; i < plan->inst.size(); ++i) {
+            Instance& I = plan->inst[i];
+            I.phiA = before[i].phiA;
+            I.phiB = before[i].phiB;
+            I.u = before[i].u;
+            I.ut = before[i].ut;
+            I.step = before[i].step;
+        }
+    return st;
+}
+
+etd_status capture_grouped_steps(etd_plan* plan, ScheduleState::Captured* out) {
+    ScheduleState& S = plan->sched;
+    std::vector<LaunchRecorder> rec;
+    etd_status st = record_two_steps(plan, rec);
+    if (st != ETD_OK) return st;
+    // groups of instances with equal launch sequences, in order of first appearance
+    std::vector<std::vector<int>> groups;
+    {
+        std::map<std::string, int> index;
+        for (size_t i = 0; i < rec.size(); ++i) {
+            for (const LaunchRecord& op : rec[i].ops)
+                if (op.grid.y != 1 || op.grid.z != 1 || op.block.y != 1 || op.block.z != 1)
+                    return fail(&plan->err, ETD_E_STATE, "grouped schedule: a recorded launch is not one-dimensional");
+            const auto it = index.emplace(launch_signature(rec[i]), (int)groups.size()).first;
+            if (it->second == (int)groups.size()) groups.emplace_back();
+            groups[it->second].push_back((int)i);
+        }
+    }
+    // the argument table: per group and pass, the instances' records side by side
+    constexpr size_t kAlign = 256;
+    std::vector<std::vector<size_t>> offset(groups.size());
+    size_t total = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const LaunchRecorder& r0 = rec[groups[gi][0]];
+        for (const LaunchRecord& op : r0.ops) {
+            offset[gi].push_back(total);
+            total += (op.args.size() * groups[gi].size() + kAlign - 1) & ~(kAlign - 1);
+        }
+    }
+    std::vector<unsigned char> host(std::max<size_t>(total, 1), 0);
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (size_t p = 0; p < offset[gi].size(); ++p)
+            for (size_t m = 0; m < groups[gi].size(); ++m) {
+                // records at the array stride of the twin's tab[blockIdx.y]: sizeof the
+                // argument record (a multiple of its alignment; the base is 256-aligned)
+                const LaunchRecord& op = rec[groups[gi][m]].ops[p];
+                std::memcpy(host.data() + offset[gi][p] + m * op.args.size(), op.args.data(), op.args.size());
+            }
+    void* table = nullptr;
+    if (hipMalloc(&table, host.size()) != hipSuccess)
+        return fail(&plan->err, ETD_E_NOMEM, "grouped schedule: no memory for the argument table");
+    auto bail = [&](etd_status e) {
+        (void)hipFree(table);
+        return e;
+    };
+    if (hipError_t e = hipMemcpy(table, host.data(), host.size(), hipMemcpyHostToDevice); e != hipSuccess)
+        return bail(fail(&plan->err, ETD_E_HIP, std::string("grouped schedule: table upload: ") + hipGetErrorString(e)));
+    for (const LaunchRecorder& r : rec)
+        for (const LaunchRecord& op : r.ops)
+            (void)hipFuncSetAttribute(op.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)op.smem);
+    const int nb = std::max(1, std::min(S.branches, (int)groups.size()));
+    if ((st = ensure_branches(plan, nb)) != ETD_OK) return bail(st);
+    hipStream_t s = S.cap;
+    if (hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed); e != hipSuccess)
+        return bail(fail(&plan->err, ETD_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e)));
+    hipError_t e = hipEventRecord(S.fork, s);
+    for (int b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(S.side[b], S.fork, 0);
+    for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
+        const LaunchRecorder& r0 = rec[groups[gi][0]];
+        const unsigned m = (unsigned)groups[gi].size();
+        for (size_t p = 0; p < r0.ops.size() && e == hipSuccess; ++p) {
+            const LaunchRecord& op = r0.ops[p];
+            void* tab = static_cast<char*>(table) + offset[gi][p];
+            void* args[] = {&tab};
+            e = hipLaunchKernel(op.fn, dim3(op.grid.x, m, 1), op.block, args, op.smem, S.side[gi % nb]);
+        }
+    }
+    for (int b = 0; b < nb && e == hipSuccess; ++b) {
+        e = hipEventRecord(S.join[b], S.side[b]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, S.join[b], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = ee;
+    if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&out->exec, graph, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return bail(fail(&plan->err, ETD_E_HIP, std::string("grouped schedule: capture: ") + hipGetErrorString(e)));
+    out->table = table;
+    size_t launches = 0;
+    for (const auto& gr : groups) launches += rec[gr[0]].ops.size();
+    log_msg(2, "plan %p: grouped %zu instance(s) into %zu group(s), %zu launches per two steps on %d branch(es)",
+            (void*)plan, plan->inst.size(), groups.size(), launches, nb);
+    return ETD_OK;
+}
+
 // ------------------------------------------------------------------ autotuner cache
 std::string instance_signature(const etd_plan* plan) {
     std::map<std::string, int> count;
@@ -143,7 +313,9 @@ bool cache_lookup(const std::string& path, const std::string& key, etd_schedule*
     const int got = sscanf(txt.c_str() + p + tag.size(), " \"mode\": %d, \"branches\": %d, \"xlines\": %d", &mode,
                            &branches, &xlines);
     if (got < 2) return false;   // entries without the tile field keep the default tile
-    if ((mode != ETD_EXEC_EAGER && mode != ETD_EXEC_GRAPH) || branches < 1 || branches > 64) return false;
+    if ((mode != ETD_EXEC_EAGER && mode != ETD_EXEC_GRAPH && mode != ETD_EXEC_GROUPED) || branches < 1 ||
+        branches > 64)
+        return false;
     if (xlines != 0 && xlines != 8 && xlines != 16) return false;
     out->mode = mode;
     out->branches = branches;
@@ -256,7 +428,13 @@ etd_status restore_snapshot(etd_plan* plan, Instance& I, const Snapshot& v) {
 }  // namespace
 
 void etd::drop_graphs(etd_plan* plan) {
-    for (auto& kv : plan->sched.graphs) (void)hipGraphExecDestroy(kv.second);
+    bool tables = false;
+    for (const auto& kv : plan->sched.graphs) tables |= kv.second.table != nullptr;
+    if (tables) (void)hipStreamSynchronize(plan->stream);   // a replay in flight reads its table
+    for (auto& kv : plan->sched.graphs) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.table) (void)hipFree(kv.second.table);
+    }
     plan->sched.graphs.clear();
 }
 
@@ -267,6 +445,8 @@ void etd::release_schedule(etd_plan* plan) {
     for (hipEvent_t e : S.join) (void)hipEventDestroy(e);
     if (S.fork) (void)hipEventDestroy(S.fork);
     if (S.cap) (void)hipStreamDestroy(S.cap);
+    if (S.rec) (void)hipStreamDestroy(S.rec);
+    S.rec = nullptr;
     S.side.clear();
     S.join.clear();
     S.fork = nullptr;
@@ -277,25 +457,26 @@ etd_status etd::run_steps(etd_plan* plan, int nsteps) {
     ScheduleState& S = plan->sched;
     bool host_checks = false;   // the band solve reads its convergence flag on the host
     for (const Instance& I : plan->inst) host_checks |= (I.d.flags & ETD_F_SURFACE_NONLOCAL) != 0;
-    if (S.mode != ETD_EXEC_GRAPH || plan->timing || host_checks) return eager_steps(plan, nsteps);
+    if (S.mode == ETD_EXEC_EAGER || plan->timing || host_checks) return eager_steps(plan, nsteps);
     int k = 0;
     for (; k + 2 <= nsteps; k += 2) {
         const std::string key = graph_key(plan);
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
             const std::string before = pointer_state(plan);
-            hipGraphExec_t ex = nullptr;
-            etd_status st = capture_two_steps(plan, &ex);
+            ScheduleState::Captured cap;
+            etd_status st = S.mode == ETD_EXEC_GROUPED ? capture_grouped(plan, &cap) : capture_two_steps(plan, &cap.exec);
             if (st != ETD_OK) return st;
             if (pointer_state(plan) != before) {   // the replay would not match the host state
-                (void)hipGraphExecDestroy(ex);
+                (void)hipGraphExecDestroy(cap.exec);
+                if (cap.table) (void)hipFree(cap.table);
                 return fail(&plan->err, ETD_E_STATE, "graph schedule: the step state does not repeat after two steps");
             }
-            it = S.graphs.emplace(key, ex).first;
+            it = S.graphs.emplace(key, cap).first;
         } else {
             for (Instance& I : plan->inst) I.step += 2;
         }
-        HIPCHK(plan, hipGraphLaunch(it->second, plan->stream));
+        HIPCHK(plan, hipGraphLaunch(it->second.exec, plan->stream));
     }
     return eager_steps(plan, nsteps - k);
 }
@@ -304,12 +485,19 @@ extern "C" {
 
 etd_status etd_set_schedule(etd_plan_t plan, const etd_schedule* sched) {
     if (!plan || !sched) return fail(plan ? &plan->err : nullptr, ETD_E_ARG, "null argument");
-    if (sched->mode != ETD_EXEC_EAGER && sched->mode != ETD_EXEC_GRAPH)
-        return fail(&plan->err, ETD_E_ARG, "schedule mode must be ETD_EXEC_EAGER or ETD_EXEC_GRAPH");
+    if (sched->mode != ETD_EXEC_EAGER && sched->mode != ETD_EXEC_GRAPH && sched->mode != ETD_EXEC_GROUPED)
+        return fail(&plan->err, ETD_E_ARG, "schedule mode must be ETD_EXEC_EAGER, ETD_EXEC_GRAPH or ETD_EXEC_GROUPED");
     if (sched->branches < 1 || sched->branches > 64)
         return fail(&plan->err, ETD_E_ARG, "schedule branches must be in 1..64");
     if (sched->xlines != 0 && sched->xlines != 8 && sched->xlines != 16)
         return fail(&plan->err, ETD_E_ARG, "schedule xlines must be 0, 8 or 16");
+    if (sched->mode == ETD_EXEC_GROUPED)
+        for (size_t i = 0; i < plan->inst.size(); ++i)
+            if (!groupable(plan->inst[i]))
+                return fail(&plan->err, ETD_E_ARG,
+                            "grouped schedule: instance " + std::to_string(i) +
+                                " is not a coupled 3D instance without band, diagnostics ring, mass projection and "
+                                "band solve");
     HIPCHK(plan, hipStreamSynchronize(plan->stream));
     drop_graphs(plan);
     plan->sched.mode = sched->mode;
@@ -338,10 +526,13 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
     etd_schedule cand[ETD_AUTOTUNE_CANDIDATES] = {{ETD_EXEC_EAGER, 1, 0}, {ETD_EXEC_GRAPH, 1, 0},
                                                    {ETD_EXEC_GRAPH, 2, 0},  {ETD_EXEC_GRAPH, 4, 0},
                                                    {ETD_EXEC_GRAPH, 8, 0},  {ETD_EXEC_GRAPH, 16, 0},
-                                                   {ETD_EXEC_GRAPH, 32, 0}, {ETD_EXEC_EAGER, 1, 8}};
-    bool tile_knob = false;
-    for (const Instance& I : plan->inst)
+                                                   {ETD_EXEC_GRAPH, 32, 0}, {ETD_EXEC_GROUPED, 1, 0},
+                                                   {ETD_EXEC_GROUPED, 8, 0}, {ETD_EXEC_EAGER, 1, 8}};
+    bool tile_knob = false, all_groupable = true;
+    for (const Instance& I : plan->inst) {
         tile_knob = tile_knob || (I.d.model == ETD_COUPLED && I.f32 && I.g.nx > 1);
+        all_groupable = all_groupable && groupable(I);
+    }
     if (ms_out)
         for (int c = 0; c < ETD_AUTOTUNE_CANDIDATES; ++c) ms_out[c] = -1.0;
     hipDeviceProp_t prop;
@@ -384,6 +575,7 @@ etd_status etd_autotune(etd_plan_t plan, int trial_steps, const char* cache_path
         st = fail(&plan->err, ETD_E_HIP, "autotune: hipEventCreate failed");
     for (int c = 0; c < ETD_AUTOTUNE_CANDIDATES && st == ETD_OK; ++c) {
         if (cand[c].mode == ETD_EXEC_GRAPH && cand[c].branches > 1 && cand[c].branches > ninst) continue;
+        if (cand[c].mode == ETD_EXEC_GROUPED && (!all_groupable || (cand[c].branches > 1 && ninst < 2))) continue;
         if (cand[c].xlines == 8) {   // the last candidate: the best schedule so far, 8-line tiles
             if (!tile_knob) continue;
             cand[c].mode = best.mode;

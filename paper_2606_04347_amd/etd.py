@@ -35,9 +35,9 @@ EXPORTS = ("etd_plan_create", "etd_plan_destroy", "etd_set_state", "etd_set_tau"
            "etd_checkpoint_size", "etd_checkpoint_save", "etd_checkpoint_load",
            "etd_diag_ring_enable", "etd_diag_ring_read",
            "etd_status_string", "etd_last_error")
-EXEC_EAGER, EXEC_GRAPH = 0, 1
+EXEC_EAGER, EXEC_GRAPH, EXEC_GROUPED = 0, 1, 2
 AUTOTUNE_CANDIDATES = (("eager", 1), ("graph", 1), ("graph", 2), ("graph", 4), ("graph", 8), ("graph", 16),
-                       ("graph", 32), ("best_xlines", 8))
+                       ("graph", 32), ("grouped", 1), ("grouped", 8), ("best_xlines", 8))
 PASS_KINDS = ("fft_z_r2c", "fft_z_c2r", "fft_y_lines", "fft_x_lines", "deriv_x", "deriv_y", "deriv_z_c2r",
               "pair_z_r2c", "pair_y_lines", "pair_x_etd", "lapinv_lines", "z_c2r_recover",
               "band", "r1_stencil", "p2_stencil", "pointwise", "reduce", "fixed_stencil", "fixed_pointwise",
@@ -359,8 +359,9 @@ class Plan:
         return v.value
 
     def set_schedule(self, mode, branches=1, xlines=0):
-        """Step schedule: EXEC_EAGER, or EXEC_GRAPH with `branches` concurrent capture branches;
-        xlines: the FP32 ETD x-pass tile (0 or 16: default, 8)."""
+        """Step schedule: EXEC_EAGER; EXEC_GRAPH with `branches` concurrent capture branches;
+        EXEC_GROUPED (one launch per pass per group of like instances, groups on `branches`
+        branches); xlines: the FP32 ETD x-pass tile (0 or 16: default, 8)."""
         self._c(lib().etd_set_schedule(self._ptr, C.byref(Schedule(int(mode), int(branches), int(xlines)))))
 
     def get_schedule(self):
@@ -381,7 +382,7 @@ class Plan:
         ms = (C.c_double * len(AUTOTUNE_CANDIDATES))()
         path = None if cache_path is None else os.fsencode(cache_path)
         self._c(lib().etd_autotune(self._ptr, int(trial_steps), path, C.byref(s), ms))
-        times = {f"{m}{b if m == 'graph' else ''}": ms[k] for k, (m, b) in enumerate(AUTOTUNE_CANDIDATES)
+        times = {f"{m}{b if m in ('graph', 'grouped') else ''}": ms[k] for k, (m, b) in enumerate(AUTOTUNE_CANDIDATES)
                  if ms[k] >= 0}
         return s.mode, s.branches, times
 

@@ -1,5 +1,5 @@
-"""GPU: batched plans of uneven instances under the eager and HIP-graph step
-schedules, and the schedule autotuner.  The instances are independent and
+"""GPU: batched plans of uneven instances under the eager, HIP-graph and
+grouped step schedules, and the schedule autotuner.  The instances are independent and
 every kernel runs the same arithmetic under every schedule, so the states
 must agree bit for bit."""
 import json
@@ -105,7 +105,7 @@ def test_schedule_rejects_bad_arguments():
     b = batch()[:1]
     plan = make_plan(b)
     with pytest.raises(etd.EtdError):
-        plan.set_schedule(2, 1)
+        plan.set_schedule(3, 1)
     with pytest.raises(etd.EtdError):
         plan.set_schedule(etd.EXEC_GRAPH, 0)
     with pytest.raises(etd.EtdError):
@@ -191,6 +191,104 @@ def test_autotune_between_band_rebuilds_restores_the_band_list():
     assert np.array_equal(runs[0][1], runs[1][1], equal_nan=True)
 
 
+def groupable_batch():
+    """Coupled 3D instances the grouped schedule takes: three shape classes
+    (16^3 FP64 ETDRK2 twice with their own seeds and tau, 16 x 24 x 32 FP32
+    ETDRK2 twice, 16 x 96 x 16 FP32 with its radix-3 axis), and a 24^3 FP64
+    ETD1 and a frozen-membrane 16^3 FP64 instance of a group of their own."""
+    out = []
+    for k, (n, scheme, prec, tau, kw) in enumerate((
+            ((16, 16, 16), etd.ETDRK2, etd.FP64, 1e-4, {}),
+            ((16, 24, 32), etd.ETDRK2, etd.FP32, 1e-4, {}),
+            ((16, 16, 16), etd.ETDRK2, etd.FP64, 5e-5, {}),
+            ((16, 96, 16), etd.ETDRK2, etd.FP32, 1e-4, {}),
+            ((24, 24, 24), etd.ETD1, etd.FP64, 1e-4, {}),
+            ((16, 24, 32), etd.ETDRK2, etd.FP32, 5e-5, {}),
+            ((16, 16, 16), etd.ETDRK2, etd.FP64, 1e-4, dict(flags=etd.F_FROZEN_MEMBRANE)))):
+        ci = inputs.coupled_membrane(n=n, seed=41 + k, tau=tau)
+        out.append(("c", ci, etd.coupled_instance(ci, scheme=scheme, precision=prec, **kw), prec))
+    return out
+
+
+@pytest.mark.parametrize("branches", [1, 3])
+def test_grouped_schedule_matches_eager(branches):
+    """One launch per pass per group of like instances (the instance is the
+    second grid coordinate, its arguments read from a device table): the
+    states agree bit for bit with one-instance-at-a-time eager launches,
+    after an odd step count (one eager step), both buffer parities and a
+    recapture after set_state."""
+    b = groupable_batch()
+    ref = make_plan(b)
+    ref.step(5)
+    want = states(ref, len(b))
+    ref.close()
+    plan = make_plan(b)
+    plan.set_schedule(etd.EXEC_GROUPED, branches)
+    assert plan.get_schedule() == (etd.EXEC_GROUPED, branches)
+    plan.step(3)
+    plan.step(2)
+    assert_same(states(plan, len(b)), want)
+    for i in range(len(b)):
+        assert plan.diagnostics(i)["step"] == 5
+    for i, (kind, src, _, prec) in enumerate(b):
+        dt = torch.float64 if prec == etd.FP64 else torch.float32
+        plan.set_state(i, dev(src.phi0, dt), dev(src.u0, dt))
+    plan.step(4)
+    plan.step(1)
+    assert_same(states(plan, len(b)), want)
+    plan.close()
+
+
+def test_grouped_schedule_refuses_what_it_does_not_cover():
+    """A band instance or a fixed-membrane instance cannot be grouped
+    (ETD_E_ARG at etd_set_schedule, the schedule unchanged); a diagnostics
+    ring turned on after the grouped schedule is refused at the next step,
+    with the states and step counters left as they were."""
+    plan = make_plan(batch())
+    with pytest.raises(etd.EtdError):
+        plan.set_schedule(etd.EXEC_GROUPED, 1)
+    assert plan.get_schedule() == (etd.EXEC_EAGER, 1)
+    plan.close()
+    b = groupable_batch()[:3]
+    plan = make_plan(b)
+    plan.set_schedule(etd.EXEC_GROUPED, 2)
+    plan.step(2)
+    before = states(plan, len(b))
+    plan.diag_ring(1, 8)
+    with pytest.raises(etd.EtdError):
+        plan.step(2)
+    assert_same(states(plan, len(b)), before)
+    assert [plan.diagnostics(i)["step"] for i in range(len(b))] == [2] * len(b)
+    plan.diag_ring(1, 0)
+    plan.step(2)
+    ref = make_plan(b)
+    ref.step(4)
+    assert_same(states(plan, len(b)), states(ref, len(b)))
+    plan.close()
+    ref.close()
+
+
+def test_autotune_times_the_grouped_candidates(tmp_path):
+    """On a batch every instance of which can be grouped, the autotuner also
+    times the grouped schedule on 1 and 8 branches, restores every state,
+    and the tuned plan steps like an untuned one."""
+    b = groupable_batch()
+    plan = make_plan(b)
+    plan.step(2)
+    before = states(plan, len(b))
+    mode, branches, times = plan.autotune(trial_steps=4, cache_path=str(tmp_path / "g.json"))
+    report("autotune_grouped", mode=mode, branches=branches, **{k: round(v, 4) for k, v in times.items()})
+    assert "grouped1" in times and "grouped8" in times
+    assert_same(states(plan, len(b)), before)
+    ref = make_plan(b)
+    ref.step(2)
+    plan.step(2)
+    ref.step(2)
+    assert_same(states(plan, len(b)), states(ref, len(b)))
+    plan.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("counts", [((32, 2), (48, 1), ((16, 96, 16), 1)), ((64, 2), (96, 1), (128, 1))],
                          ids=["small", "sweep_shapes"])
 @pytest.mark.parametrize("precision", [etd.FP64, etd.FP32])
@@ -199,7 +297,8 @@ def test_uneven_batch_matches_oracle(precision, counts):
     48 (radix 3) and a 96-length axis; then the sweep's own shapes, 64^3,
     96^3 and 128^3 -- with per-instance seeds, coefficients and tau in
     {5e-5, 1e-4} (inputs.batch_sweep's draws), stepped under the graph
-    schedule with concurrent branches, each instance against the FP64
+    schedule with concurrent branches and under the grouped schedule (one
+    launch per pass per shape class), each instance against the FP64
     oracle: within 1e-12 (FP64) or under the FP32 comparison of
     test_gpu_coupled (flip set counted, u and g u within 1e-4)."""
     from gpu_util import recovery_flips, rel_linf, u_gap_outside_flips
@@ -207,37 +306,48 @@ def test_uneven_batch_matches_oracle(precision, counts):
     from oracle.coupled import CoupledOracle
     cis = inputs.batch_sweep(counts=counts)
     assert {ci.tau for ci in cis} == {5e-5, 1e-4}
-    plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=precision) for ci in cis])
     dt = torch.float64 if precision == etd.FP64 else torch.float32
-    for i, ci in enumerate(cis):
-        plan.set_state(i, dev(ci.phi0, dt), dev(ci.u0, dt))
-    plan.set_schedule(etd.EXEC_GRAPH, 2)
+    plans = {}
+    for mode in (etd.EXEC_GRAPH, etd.EXEC_GROUPED):
+        plan = etd.Plan([etd.coupled_instance(ci, scheme=etd.ETDRK2, precision=precision) for ci in cis])
+        for i, ci in enumerate(cis):
+            plan.set_state(i, dev(ci.phi0, dt), dev(ci.u0, dt))
+        plan.set_schedule(mode, 2)
+        plans[mode] = plan
     oracles = []
     for ci in cis:
         o = CoupledOracle(Grid(ci.shape, ci.half_len), ci.params, ci.tau, etd.ETDRK2)
         o.set_state(ci.phi0, ci.u0)
         oracles.append(o)
-    flips = [np.zeros(ci.shape, dtype=bool) for ci in cis]
+    flips = {m: [np.zeros(ci.shape, dtype=bool) for ci in cis] for m in plans}
     nsteps = 4
     for k in range(nsteps // 2):       # two steps per replay: compare every second step
-        plan.step(2)
+        for plan in plans.values():
+            plan.step(2)
         for i, o in enumerate(oracles):
             o.run(2)
             if precision == etd.FP32:
-                flips[i] |= recovery_flips(host(plan.get_state(i, torch.float32)[0]), o.phi())
-    for i, (ci, o) in enumerate(zip(cis, oracles)):
-        phi, u = (host(t) for t in plan.get_state(i))
-        ephi = rel_linf(phi, o.phi())
-        if precision == etd.FP64:
-            eu = rel_linf(u, o.u)
-            report("batch_oracle", precision=precision, shape=str(ci.shape), tau=ci.tau, err_phi=ephi, err_u=eu)
-            assert ephi <= 1e-12 and eu <= 1e-12
-        else:
-            eu, near, egu, _ = u_gap_outside_flips(u, o.u, o.phi(), flips[i])
-            report("batch_oracle", precision=precision, shape=str(ci.shape), tau=ci.tau, err_phi=ephi, err_u=eu,
-                   err_gu=egu, flips=int(flips[i].sum()))
-            assert ephi <= 1e-4 and eu <= 1e-4 and egu <= 1e-4
-    plan.close()
+                for m, plan in plans.items():
+                    flips[m][i] |= recovery_flips(host(plan.get_state(i, torch.float32)[0]), o.phi())
+    for m, plan in plans.items():
+        sched = "graph" if m == etd.EXEC_GRAPH else "grouped"
+        for i, (ci, o) in enumerate(zip(cis, oracles)):
+            phi, u = (host(t) for t in plan.get_state(i))
+            ephi = rel_linf(phi, o.phi())
+            if precision == etd.FP64:
+                eu = rel_linf(u, o.u)
+                report("batch_oracle", schedule=sched, precision=precision, shape=str(ci.shape), tau=ci.tau,
+                       err_phi=ephi, err_u=eu)
+                assert ephi <= 1e-12 and eu <= 1e-12
+            else:
+                eu, near, egu, _ = u_gap_outside_flips(u, o.u, o.phi(), flips[m][i])
+                report("batch_oracle", schedule=sched, precision=precision, shape=str(ci.shape), tau=ci.tau,
+                       err_phi=ephi, err_u=eu, err_gu=egu, flips=int(flips[m][i].sum()))
+                assert ephi <= 1e-4 and eu <= 1e-4 and egu <= 1e-4
+    # the two schedules run the same arithmetic
+    assert_same(states(plans[etd.EXEC_GROUPED], len(cis)), states(plans[etd.EXEC_GRAPH], len(cis)))
+    for plan in plans.values():
+        plan.close()
 
 
 @pytest.mark.parametrize("mode", [etd.EXEC_EAGER, etd.EXEC_GRAPH])
