@@ -624,6 +624,9 @@ template <typename T, int L> struct P2PairLoad {
 // the mass sum.
 template <typename T, int M, bool BAND> struct QPairLoad {
     static constexpr int NS = 1;
+    // the loop of the first stage: fetching every butterfly first kept the
+    // FP64 mass partials of all of them live (158 VGPRs, 3 waves per SIMD)
+    static constexpr bool kFetchAll = false;
     const T* u;      // first row of the tile
     const T* G;
     const uint8_t* mask;

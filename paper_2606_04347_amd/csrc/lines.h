@@ -33,13 +33,22 @@ namespace stk {
 // them all (a loop over butterflies waits for each one's loads in turn).
 // Larger sets (FP64, length 512, two fields) keep the loop: there the extra
 // registers cost more occupancy than the overlap gains (measured).
+// An Op may declare kFetchAll = false to keep the first stage's loop
+// (a register-heavy Op whose occupancy the early loads would lower).
+template <class Op, class = void> struct FetchAllOf {
+    static constexpr bool v = true;
+};
+template <class Op> struct FetchAllOf<Op, std::enable_if_t<!Op::kFetchAll>> {
+    static constexpr bool v = false;
+};
+
 template <typename T, int N, int L, int LS, int R, int DIR, bool LF, class Op>
 __device__ __forceinline__ void first_stage(c2<T>* lds, const Op& op) {
     constexpr int NS = Op::NS;
     constexpr int NR = N / R;
     constexpr int NB = L * NR;
     constexpr int IT = (NB + kThreads - 1) / kThreads;
-    if constexpr (IT * NS * R * sizeof(c2<T>) <= 32 * 4) {
+    if constexpr (FetchAllOf<Op>::v && IT * NS * R * sizeof(c2<T>) <= 32 * 4) {
         c2<T> v[IT][NS][R];
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -302,15 +311,6 @@ template <typename T, class Op, int S> struct SlotStore {
     static constexpr int NS = 1;
     const Op& op;
     __device__ __forceinline__ void store(int l, int, int e, c2<T> v) const { op.template store<S>(l, e, v); }
-};
-
-// An Op may declare kFetchAll = false to keep the first stage's loop
-// (a register-heavy Op whose occupancy the early loads would lower).
-template <class Op, class = void> struct FetchAllOf {
-    static constexpr bool v = true;
-};
-template <class Op> struct FetchAllOf<Op, std::enable_if_t<!Op::kFetchAll>> {
-    static constexpr bool v = false;
 };
 
 // First stage of transform S of a sequential Op: the inputs of the thread's

@@ -119,10 +119,11 @@ __device__ __forceinline__ void velocity_point(T itau, double thr, T p, T po, T 
     const T gn2 = a * a + b * b + c * c;
     const bool sel = ((double)g > thr) && (gn2 > (T)0);   // threshold decided in FP64
     const T dt = (p - po) * itau;
+    const T w = sel ? -dt / gn2 : (T)0;   // one division for the three components
     *G = g;
-    *vx = sel ? (-dt * a) / gn2 : (T)0;
-    *vy = sel ? (-dt * b) / gn2 : (T)0;
-    *vz = sel ? (-dt * c) / gn2 : (T)0;
+    *vx = sel ? w * a : (T)0;
+    *vy = sel ? w * b : (T)0;
+    *vz = sel ? w * c : (T)0;
 }
 
 }  // namespace etd
