@@ -465,7 +465,14 @@ hipError_t phi_stage(const Instance& I, CoupledView<T>& v, const T* phi_in, cons
     const GridK& g = I.g;
     const FFTTables<T>& t = tables<T>(I);
     if (g.nx > 1) {
-        const R1Fields<T> f{phi_in, v.lap, v.gn, v.u, mask, I.scal + S_INTPHI, I.A0};
+        R1Fields<T> f{phi_in, v.lap, v.gn, v.u, mask, I.scal + S_INTPHI, I.A0};
+        if (mask) {   // the surface part of P1 on the band list (into the P buffer, free in 3D)
+            timed_kernel(PASS_R1, 0.0, s, [&] {
+                r1_surface_band<T>(g, I.K, phi_in, v.lap, v.gn, v.u, I.band_idx, I.band_total, g.nreal(),
+                                   I.scal + S_INTPHI, I.A0, v.P, s);
+            });
+            f.surf = v.P;
+        }
         hipError_t e = r1_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, true, v.Sa, v.Sb, v.Sgu, s);
         if (e != hipSuccess) return e;
         const GridSum isum = grid_sum(I, S_INTPHI);
@@ -516,7 +523,14 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
         e = surface ? surface_psi()
                     : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Stmp, nullptr, grid_sum(I, S_MASS), s);
         if (e != hipSuccess) return e;
-        const P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS, surface ? nullptr : v.Stmp};
+        P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS, surface ? nullptr : v.Stmp};
+        if (mask) {   // P2 without its nonlocal term on the band list (into the Q buffer, free in 3D)
+            timed_kernel(PASS_P2, 0.0, s, [&] {
+                p2_local_band<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, I.band_idx, I.band_total, g.nreal(),
+                                 I.scal + S_MASS, v.Q, s);
+            });
+            f.surf = v.Q;
+        }
         e = p2_etd<T>(g, t, I.K, f, st, v.Sa, v.Sb, a, store_D, v.Sa, s);
         if (e != hipSuccess) return e;
         return c2r_recover_yz<T>(g, t, v.Sa, v.u, v.gp, out, I.K.thr, halt_flag(I), s);

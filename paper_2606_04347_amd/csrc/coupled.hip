@@ -174,6 +174,64 @@ __global__ __launch_bounds__(kBlock) void k_R1_point(GridK g, CoupledK K, const 
     }
 }
 
+// Neighbour indices of grid point i on a periodic 3D grid (x-, x+, y-, y+, z-, z+).
+struct PointNbr {
+    long xm, xp, ym, yp, zm, zp;
+};
+__device__ __forceinline__ PointNbr point_neighbours(const GridK& g, long i) {
+    const long nyz = (long)g.ny * g.nz;
+    const int ix = (int)(i / nyz);
+    const long r = i - (long)ix * nyz;
+    const int iy = (int)(r / g.nz), iz = (int)(r - (long)iy * g.nz);
+    PointNbr n;
+    n.xm = i + (ix > 0 ? -nyz : (long)(g.nx - 1) * nyz);
+    n.xp = i + (ix + 1 < g.nx ? nyz : -(long)(g.nx - 1) * nyz);
+    n.ym = i + (iy > 0 ? -(long)g.nz : (long)(g.ny - 1) * g.nz);
+    n.yp = i + (iy + 1 < g.ny ? (long)g.nz : -(long)(g.ny - 1) * g.nz);
+    n.zm = i + (iz > 0 ? -1 : g.nz - 1);
+    n.zp = i + (iz + 1 < g.nz ? 1 : -(g.nz - 1));
+    return n;
+}
+
+// The surface part of P1 (r1_surf) at every point of the band list.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_r1_surf_band(GridK g, CoupledK K, const T* __restrict__ phi,
+                                                         const T* __restrict__ lap, const T* __restrict__ gn,
+                                                         const T* __restrict__ u, const int32_t* __restrict__ idx,
+                                                         const int64_t* __restrict__ total,
+                                                         const double* __restrict__ int_phi, double A0,
+                                                         T* __restrict__ surf) {
+    const long nb = total[0];
+    const R1Const<T> kc(g, K, int_phi[0], A0);
+    for (long b = (long)blockIdx.x * kBlock + threadIdx.x; b < nb; b += (long)gridDim.x * kBlock) {
+        const long i = idx[b];
+        const PointNbr n = point_neighbours(g, i);
+        const T un[6] = {u[n.xm], u[n.xp], u[n.ym], u[n.yp], u[n.zm], u[n.zp]};
+        const T pn[6] = {phi[n.xm], phi[n.xp], phi[n.ym], phi[n.yp], phi[n.zm], phi[n.zp]};
+        surf[i] = r1_surf(kc, phi[i], lap[i], gn[i], u[i], un, pn);
+    }
+}
+
+// P2 without its nonlocal term (p2_local) at every point of the band list.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_p2_local_band(GridK g, CoupledK K, const T* __restrict__ u,
+                                                          const T* __restrict__ G, const T* __restrict__ vx,
+                                                          const T* __restrict__ vy, const T* __restrict__ vz,
+                                                          const int32_t* __restrict__ idx,
+                                                          const int64_t* __restrict__ total,
+                                                          const double* __restrict__ m, T* __restrict__ surf) {
+    const long nb = total[0];
+    const P2Const<T> kc(g, K, m[0]);
+    for (long b = (long)blockIdx.x * kBlock + threadIdx.x; b < nb; b += (long)gridDim.x * kBlock) {
+        const long i = idx[b];
+        const PointNbr n = point_neighbours(g, i);
+        const T un[6] = {u[n.xm], u[n.xp], u[n.ym], u[n.yp], u[n.zm], u[n.zp]};
+        const T Gn[6] = {G[n.xm], G[n.xp], G[n.ym], G[n.yp], G[n.zm], G[n.zp]};
+        const T vn[6] = {vx[n.xm], vx[n.xp], vy[n.ym], vy[n.yp], vz[n.zm], vz[n.zp]};
+        surf[i] = p2_local(kc, u[i], G[i], un, Gn, vn);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_velocity(GridK g, CoupledK K, const T* __restrict__ po, const T* __restrict__ pn,
                            const T* __restrict__ gx, const T* __restrict__ gy, const T* __restrict__ gz,
@@ -308,6 +366,20 @@ void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* 
                        A0, P, Q, tg.tpb);
 }
 template <typename T>
+void r1_surface_band(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gn, const T* u,
+                     const int32_t* idx, const int64_t* total, long capacity, const double* int_phi, double A0,
+                     T* surf, hipStream_t s) {
+    hipLaunchKernelGGL(k_r1_surf_band<T>, dim3(grid_for(capacity)), dim3(kBlock), 0, s, g, K, phi, lap, gn, u, idx,
+                       total, int_phi, A0, surf);
+}
+template <typename T>
+void p2_local_band(const GridK& g, const CoupledK& K, const T* u, const T* G, const T* vx, const T* vy,
+                   const T* vz, const int32_t* idx, const int64_t* total, long capacity, const double* m, T* surf,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_p2_local_band<T>, dim3(grid_for(capacity)), dim3(kBlock), 0, s, g, K, u, G, vx, vy, vz, idx,
+                       total, m, surf);
+}
+template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* po, const T* pn, const T* gx, const T* gy,
                       const T* gz, T* gp, T* vx, T* vy, T* vz, const double* halt, hipStream_t s) {
     hipLaunchKernelGGL(k_velocity<T>, dim3(grid_for(g.nreal())), dim3(kBlock), 0, s, g, K, po, pn, gx, gy, gz, gp, vx,
@@ -352,6 +424,12 @@ void set_delta(long n, double* x, hipStream_t s) {
     template void coupled_R1_point<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
                                       const T*, const T*, const uint8_t*, const double*, double, T*, T*,          \
                                       hipStream_t);                                                               \
+    template void r1_surface_band<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,       \
+                                     const int32_t*, const int64_t*, long, const double*, double, T*,             \
+                                     hipStream_t);                                                                \
+    template void p2_local_band<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,         \
+                                   const T*, const int32_t*, const int64_t*, long, const double*, T*,             \
+                                   hipStream_t);                                                                  \
     template void coupled_velocity<T>(const GridK&, const CoupledK&, const T*, const T*, const T*, const T*,      \
                                       const T*, T*, T*, T*, T*, const double*, hipStream_t);                      \
     template void coupled_q_gu<T>(const GridK&, const CoupledK&, const T*, const T*, const uint8_t*, T*, T*,      \

@@ -57,6 +57,9 @@ template <typename T> struct R1Fields {
     const uint8_t* mask;
     const double* int_phi;
     double A0;
+    // with mask: the surface part of P1 on the band (r1_surface_band), read
+    // where the mask is set; the z pass then forms no stencils
+    const T* surf = nullptr;
 };
 // Sources of P2 (Section 3.1): u, G = g+, the velocity, psi = the nonlocal
 // inverse of q ((-Delta_h)^{-1} by FFT, or the band solve), the band mask
@@ -69,6 +72,9 @@ template <typename T> struct P2Fields {
     const uint8_t* mask;
     const double* m;
     const c2<T>* psi_hat = nullptr;
+    // with mask: P2 without its nonlocal term on the band (p2_local_band),
+    // read where the mask is set
+    const T* surf = nullptr;
 };
 
 // fwd_pair_etd with the pair (P1, W'(phi) - A1 phi) formed from its sources

@@ -514,6 +514,7 @@ template <typename T, int L> struct R1PairLoad {
     int nl, nz;
     const T *phi, *lap, *gn, *u;
     const uint8_t* mask;
+    const T* surf;   // with the band: the surface part of P1, formed on the band list
     R1Const<T> k;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
         if (l >= nl) {
@@ -521,13 +522,20 @@ template <typename T, int L> struct R1PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        if (mask && mask[c + o] == 0 && mask[c + o + 1] == 0) {
-            // both points off the band: the |grad phi|-weighted terms are 0, so
-            // P1 needs phi and its Laplacian alone (no u, no stencil)
+        if (mask) {
+            // P1 = the local part from phi and its Laplacian, plus on the band
+            // the surface part (every lane runs the same loads: no stencil
+            // here, so the band costs a wave no divergent gathers)
             const c2<T> p = ld2(phi + c + o), L2 = ld2(lap + c + o);
+            const unsigned short mb = *reinterpret_cast<const unsigned short*>(mask + c + o);
             T P0, Q0, P1, Q1;
             r1_core(k, p.x, L2.x, &P0, &Q0);
             r1_core(k, p.y, L2.y, &P1, &Q1);
+            if (mb != 0) {
+                const c2<T> sf = ld2(surf + c + o);
+                P0 = P0 + ((mb & 0xff) ? sf.x : (T)0);
+                P1 = P1 + ((mb >> 8) ? sf.y : (T)0);
+            }
             v[0] = mk<T>(P0, P1);
             v[1] = mk<T>(Q0, Q1);
             return;
@@ -539,21 +547,16 @@ template <typename T, int L> struct R1PairLoad {
                     uyp = ld2(u + rt->yp[l] + o);
         const long zm = c + (o > 0 ? o - 1 : nz - 1), zp = c + (o + 2 < nz ? o + 2 : 0);
         const T pzm = phi[zm], pzp = phi[zp], uzm = u[zm], uzp = u[zp];
-        bool b0 = true, b1 = true;
-        if (mask) {
-            b0 = mask[c + o] != 0;
-            b1 = mask[c + o + 1] != 0;
-        }
         T P0, Q0, P1, Q1;
         {
             const T un[6] = {uxm.x, uxp.x, uym.x, uyp.x, uzm, uu.y};
             const T pn[6] = {pxm.x, pxp.x, pym.x, pyp.x, pzm, p.y};
-            r1_point(k, p.x, L2.x, gg.x, uu.x, un, pn, b0, &P0, &Q0);
+            r1_point(k, p.x, L2.x, gg.x, uu.x, un, pn, true, &P0, &Q0);
         }
         {
             const T un[6] = {uxm.y, uxp.y, uym.y, uyp.y, uu.x, uzp};
             const T pn[6] = {pxm.y, pxp.y, pym.y, pyp.y, p.x, pzp};
-            r1_point(k, p.y, L2.y, gg.y, uu.y, un, pn, b1, &P1, &Q1);
+            r1_point(k, p.y, L2.y, gg.y, uu.y, un, pn, true, &P1, &Q1);
         }
         v[0] = mk<T>(P0, P1);
         v[1] = mk<T>(Q0, Q1);
@@ -570,6 +573,7 @@ template <typename T, int L> struct P2PairLoad {
     int nl, nz;
     const T *u, *G, *vx, *vy, *vz, *psi;
     const uint8_t* mask;
+    const T* surf;   // with the band: P2 without its nonlocal term, formed on the band list
     P2Const<T> k;
     const c2<T>* psl;
     __device__ __forceinline__ void load(int l, int e, c2<T>* v) const {
@@ -578,10 +582,19 @@ template <typename T, int L> struct P2PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        if (mask && mask[c + o] == 0 && mask[c + o + 1] == 0) {
-            // both points off the band: P2 is 0 there; g+ u alone is formed
+        if (mask) {
+            // g+ u everywhere; P2 (0 off the band) from its stencil part formed on
+            // the band list and the nonlocal term - gamma g+ psi
             const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o);
-            v[0] = mk<T>(0, 0);
+            const unsigned short mb = *reinterpret_cast<const unsigned short*>(mask + c + o);
+            T P0 = (T)0, P1 = (T)0;
+            if (mb != 0) {
+                const c2<T> sf = ld2(surf + c + o);
+                const c2<T> ps = psl ? psl[l * (nz / 2) + e] : ld2(psi + c + o);
+                if (mb & 0xff) P0 = p2_from_local(k, sf.x, GG.x, ps.x);
+                if (mb >> 8) P1 = p2_from_local(k, sf.y, GG.y, ps.y);
+            }
+            v[0] = mk<T>(P0, P1);
             v[1] = mk<T>(GG.x * uu.x, GG.y * uu.y);
             return;
         }
@@ -595,23 +608,18 @@ template <typename T, int L> struct P2PairLoad {
                     vyp = ld2(vy + rt->yp[l] + o);
         const long zm = c + (o > 0 ? o - 1 : nz - 1), zp = c + (o + 2 < nz ? o + 2 : 0);
         const T uzm = u[zm], uzp = u[zp], Gzm = G[zm], Gzp = G[zp], vzm = vz[zm], vzp = vz[zp];
-        bool b0 = true, b1 = true;
-        if (mask) {
-            b0 = mask[c + o] != 0;
-            b1 = mask[c + o + 1] != 0;
-        }
         T P0, P1;
         {
             const T un[6] = {uxm.x, uxp.x, uym.x, uyp.x, uzm, uu.y};
             const T Gn[6] = {Gxm.x, Gxp.x, Gym.x, Gyp.x, Gzm, GG.y};
             const T vn[6] = {vxm.x, vxp.x, vym.x, vyp.x, vzm, wz.y};
-            P0 = p2_point(k, uu.x, GG.x, ps.x, un, Gn, vn, b0);
+            P0 = p2_point(k, uu.x, GG.x, ps.x, un, Gn, vn, true);
         }
         {
             const T un[6] = {uxm.y, uxp.y, uym.y, uyp.y, uu.x, uzp};
             const T Gn[6] = {Gxm.y, Gxp.y, Gym.y, Gyp.y, GG.x, Gzp};
             const T vn[6] = {vxm.y, vxp.y, vym.y, vyp.y, wz.x, vzp};
-            P1 = p2_point(k, uu.y, GG.y, ps.y, un, Gn, vn, b1);
+            P1 = p2_point(k, uu.y, GG.y, ps.y, un, Gn, vn, true);
         }
         v[0] = mk<T>(P0, P1);
         v[1] = mk<T>(GG.x * uu.x, GG.y * uu.y);
@@ -686,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, co
 template <typename T, int NR>
 struct k_z_r2c_r1_body {
     static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
-                                                       const T* u, const uint8_t* mask,
+                                                       const T* u, const uint8_t* mask, const T* surf,
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
@@ -701,17 +709,17 @@ struct k_z_r2c_r1_body {
         const int nl = (int)min((long)L, nrows - row0);
         row_tile_setup<L>(rt, g, row0);
         __syncthreads();
-        const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, R1Const<T>(g, K, int_phi[0], A0)};
+        const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, surf, R1Const<T>(g, K, int_phi[0], A0)};
         zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
     }
 };
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
-                                                       const T* u, const uint8_t* mask,
+                                                       const T* u, const uint8_t* mask, const T* surf,
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    k_z_r2c_r1_body<T, NR>::run(g, K, phi, lap, gn, u, mask, int_phi, A0, WP, WQ, twh, twf, nrows);
+    k_z_r2c_r1_body<T, NR>::run(g, K, phi, lap, gn, u, mask, surf, int_phi, A0, WP, WQ, twh, twf, nrows);
 }
 
 // The pairs of an inverse z transform kept in the LDS (row l at l * M).
@@ -734,7 +742,7 @@ struct k_z_r2c_p2_body {
     static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
                                                        const T* vy, const T* vz, const T* psi,
                                                        const c2<T>* psi_hat, T psi_scale, const double* m,
-                                                       const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
+                                                       const uint8_t* mask, const T* surf, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
         constexpr int L = z_rows_pair<T, NR>();
@@ -757,7 +765,7 @@ struct k_z_r2c_p2_body {
             zrow_inverse_lds<T, NR, LdsPairStore<T, M>, L>(lds, stw, twf, LdsPairStore<T, M>{psl, psi_scale});
         }
         __syncthreads();
-        const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, P2Const<T>(g, K, m[0]), psl};
+        const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, surf, P2Const<T>(g, K, m[0]), psl};
         zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
     }
 };
@@ -765,10 +773,11 @@ template <typename T, int NR, bool PSI_HAT>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
                                                        const T* vy, const T* vz, const T* psi,
                                                        const c2<T>* psi_hat, T psi_scale, const double* m,
-                                                       const uint8_t* mask, c2<T>* WP, c2<T>* WQ,
+                                                       const uint8_t* mask, const T* surf, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    k_z_r2c_p2_body<T, NR, PSI_HAT>::run(g, K, u, G, vx, vy, vz, psi, psi_hat, psi_scale, m, mask, WP, WQ, twh, twf, nrows);
+    k_z_r2c_p2_body<T, NR, PSI_HAT>::run(g, K, u, G, vx, vy, vz, psi, psi_hat, psi_scale, m, mask, surf, WP, WQ, twh,
+                                             twf, nrows);
 }
 
 // two spectra through the same plain line transform, one after the other
@@ -1083,7 +1092,7 @@ hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, 
     set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
     const long nrows = (long)g.nx * g.ny;
     launch_k<k_z_r2c_r1_body<T, NR>>(k_z_r2c_r1<T, NR>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
-                       f.lap, f.gn, f.u, f.mask, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
+                       f.lap, f.gn, f.u, f.mask, f.surf, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
     return hipGetLastError();
 }
 template <typename T, int NR>
@@ -1099,14 +1108,14 @@ hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, 
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, true>, smem, flag);
         launch_k<k_z_r2c_p2_body<T, NR, true>>(k_z_r2c_p2<T, NR, true>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
-                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
+                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, f.surf, WP, WQ, twh, twf, nrows);
     } else {
         const size_t smem = z_smem_p2<T, NR, false>();
         static_assert(z_smem_p2<T, NR, false>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
         static std::once_flag flag;
         set_smem_limit(k_z_r2c_p2<T, NR, false>, smem, flag);
         launch_k<k_z_r2c_p2_body<T, NR, false>>(k_z_r2c_p2<T, NR, false>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
-                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, WP, WQ, twh, twf, nrows);
+                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, f.surf, WP, WQ, twh, twf, nrows);
     }
     return hipGetLastError();
 }
@@ -1301,8 +1310,10 @@ hipError_t r1_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
-    const double mb = f.mask ? (double)g.nreal() : 0.0;
-    hipError_t e = timed_pass(PASS_Z_R2C_R1, 4.0 * rb + mb + 2.0 * cb, s, [&]() -> hipError_t {
+    // with the band: phi, its Laplacian and the mask (the surface part is
+    // read on the band alone); else phi, lap, |grad phi| and u
+    const double in = f.mask ? 2.0 * rb + (double)g.nreal() : 4.0 * rb;
+    hipError_t e = timed_pass(PASS_Z_R2C_R1, in + 2.0 * cb, s, [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \
     case n: return launch_z_r1<T, n>(g, K, f, WP, WQ, t.tzh, t.tzf, s);
@@ -1321,9 +1332,12 @@ hipError_t p2_etd(const GridK& g, const FFTTables<T>& t, const CoupledK& K, cons
     if (g.nx < 2) return hipErrorInvalidValue;
     const double cb = 2.0 * sizeof(T) * (double)g.nspec();
     const double rb = sizeof(T) * (double)g.nreal();
-    const double mb = f.mask ? (double)g.nreal() : 0.0;
-    // with psi from its spectrum the pass reads that spectrum in place of psi
-    hipError_t e = timed_pass(PASS_Z_R2C_P2, (f.psi_hat ? 5.0 * rb + cb : 6.0 * rb) + mb + 2.0 * cb, s,
+    // with psi from its spectrum the pass reads that spectrum in place of psi;
+    // with the band: u, g+ and the mask (the stencil part, and psi from
+    // memory, are read on the band alone); else u, g+, v and psi
+    const double in = f.mask ? 2.0 * rb + (double)g.nreal() + (f.psi_hat ? cb : 0.0)
+                             : (f.psi_hat ? 5.0 * rb + cb : 6.0 * rb);
+    hipError_t e = timed_pass(PASS_Z_R2C_P2, in + 2.0 * cb, s,
                               [&]() -> hipError_t {
         switch (g.nz) {
 #define CASE(n) \

@@ -61,6 +61,19 @@ template <typename T>
 void coupled_R1_point(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gx, const T* gy,
                       const T* gz, const T* u, const uint8_t* mask, const double* int_phi, double A0, T* P,
                       T* Q, hipStream_t s);
+// On a 3D grid with the band: the surface part of P1 (the |grad phi|-weighted
+// terms, stencils of u and g(phi)) and P2 without its nonlocal term (the
+// stencils of u, g+ and v) at the points of the band list idx (total[0]
+// entries on the device, at most capacity), written to surf at those points
+// only; the z passes add them where the band mask is set.
+template <typename T>
+void r1_surface_band(const GridK& g, const CoupledK& K, const T* phi, const T* lap, const T* gn, const T* u,
+                     const int32_t* idx, const int64_t* total, long capacity, const double* int_phi, double A0,
+                     T* surf, hipStream_t s);
+template <typename T>
+void p2_local_band(const GridK& g, const CoupledK& K, const T* u, const T* gplus, const T* vx, const T* vy,
+                   const T* vz, const int32_t* idx, const int64_t* total, long capacity, const double* m, T* surf,
+                   hipStream_t s);
 template <typename T>
 void coupled_velocity(const GridK& g, const CoupledK& K, const T* phi_old, const T* phi_new, const T* gx,
                       const T* gy, const T* gz, T* gplus, T* vx, T* vy, T* vz, const double* halt, hipStream_t s);

@@ -59,19 +59,24 @@ template <typename T> __device__ __forceinline__ void r1_core(const R1Const<T>& 
     *Q = q1;
 }
 
+// The |grad phi|-weighted (surface) part of P1 at one point: zero off the band.
 template <typename T>
-__device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
-                                         const T (&pn)[6], bool band, T* P, T* Q) {
+__device__ __forceinline__ T r1_surf(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
+                                     const T (&pn)[6]) {
     const T gc = gloc(pc);
     T S = lapS_axis(un[0], uc, un[1], gloc(pn[0]), gc, gloc(pn[1]), k.ihx);
     S += lapS_axis(un[2], uc, un[3], gloc(pn[2]), gc, gloc(pn[3]), k.ihy);
     S += lapS_axis(un[4], uc, un[5], gloc(pn[4]), gc, gloc(pn[5]), k.ihz);
-    const T wp = Wp(pc), wpp = Wpp(pc);
-    const T q1 = wp - k.A1 * pc;
-    const T p1 = k.c1 * (wpp - k.A2) * (L - k.A1 * pc / k.e2) - (k.cW * wpp + k.cs) * q1;
-    T surf = k.cl * (k.eu * S - gc * Wp(uc) * k.ieu) * gn - k.area * gn +
-             k.ca * (uc + k.u0) * gn * (k.ep * L - wp * k.iep);
-    if (!band) surf = (T)0;
+    const T wp = Wp(pc);
+    return k.cl * (k.eu * S - gc * Wp(uc) * k.ieu) * gn - k.area * gn + k.ca * (uc + k.u0) * gn * (k.ep * L - wp * k.iep);
+}
+
+template <typename T>
+__device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
+                                         const T (&pn)[6], bool band, T* P, T* Q) {
+    T p1, q1;
+    r1_core(k, pc, L, &p1, &q1);
+    const T surf = band ? r1_surf(k, pc, L, gn, uc, un, pn) : (T)0;
     *P = p1 + surf;
     *Q = q1;
 }
@@ -97,17 +102,27 @@ template <typename T> struct P2Const {
 // P2 at one point: centre u, G, psi; the six neighbours of u and G; the
 // velocity component along each neighbour's axis (vx at x-+, vy at y-+,
 // vz at z-+); the band flag.
+// P2 at one point without its nonlocal term - gamma G psi (the stencil part,
+// formed on the band list when the band is in use).
 template <typename T>
-__device__ __forceinline__ T p2_point(const P2Const<T>& k, T uc, T Gc, T ps, const T (&un)[6], const T (&Gn)[6],
-                                      const T (&vn)[6], bool band) {
+__device__ __forceinline__ T p2_local(const P2Const<T>& k, T uc, T Gc, const T (&un)[6], const T (&Gn)[6],
+                                      const T (&vn)[6]) {
     T S = lapS_axis(un[0], uc, un[1], Gn[0], Gc, Gn[1], k.ihx);
     S += lapS_axis(un[2], uc, un[3], Gn[2], Gc, Gn[3], k.ihy);
     S += lapS_axis(un[4], uc, un[5], Gn[4], Gc, Gn[5], k.ihz);
     const T div = (Gn[1] * un[1] * vn[1] - Gn[0] * un[0] * vn[0]) * k.i2hx +
                   (Gn[3] * un[3] * vn[3] - Gn[2] * un[2] * vn[2]) * k.i2hy +
                   (Gn[5] * un[5] * vn[5] - Gn[4] * un[4] * vn[4]) * k.i2hz;
-    const T p2 = k.eu * S + k.B2 * Gc * uc - Gc * Wp(uc) * k.ieu - k.gam * Gc * ps - k.Mm * Gc - div;
-    return band ? p2 : (T)0;
+    return k.eu * S + k.B2 * Gc * uc - Gc * Wp(uc) * k.ieu - k.Mm * Gc - div;
+}
+template <typename T> __device__ __forceinline__ T p2_from_local(const P2Const<T>& k, T local, T Gc, T ps) {
+    return local - k.gam * Gc * ps;
+}
+
+template <typename T>
+__device__ __forceinline__ T p2_point(const P2Const<T>& k, T uc, T Gc, T ps, const T (&un)[6], const T (&Gn)[6],
+                                      const T (&vn)[6], bool band) {
+    return band ? p2_from_local(k, p2_local(k, uc, Gc, un, Gn, vn), Gc, ps) : (T)0;
 }
 
 // g+ = g(phi^{n+1}) and the velocity v = -phi_t grad phi / |grad phi|^2
