@@ -520,10 +520,13 @@ hipError_t u_stage(Instance& I, CoupledView<T>& v, const T* uu, const uint8_t* m
     if (g.nx > 1) {
         // q formed in the load of the nonlocal transform (with m), whose last (z)
         // pass runs inside the P2 pass; P2 and g+ u in the load of the pair
+        // with the band, P2 reads psi at band points only: psi's inverse z
+        // transform runs as its own plain pass instead of inside every P2 tile
         e = surface ? surface_psi()
-                    : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Stmp, nullptr, grid_sum(I, S_MASS), s);
+                    : lapinv_q_fused<T>(g, t, I.fd, I.K.ubar, uu, v.gp, mask, v.Stmp, mask ? v.psi : nullptr,
+                                        grid_sum(I, S_MASS), s);
         if (e != hipSuccess) return e;
-        P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS, surface ? nullptr : v.Stmp};
+        P2Fields<T> f{uu, v.gp, v.vx, v.vy, v.vz, v.psi, mask, I.scal + S_MASS, (surface || mask) ? nullptr : v.Stmp};
         if (mask) {   // P2 without its nonlocal term on the band list (into the Q buffer, free in 3D)
             timed_kernel(PASS_P2, 0.0, s, [&] {
                 p2_local_band<T>(g, I.K, uu, v.gp, v.vx, v.vy, v.vz, I.band_idx, I.band_total, g.nreal(),
