@@ -302,7 +302,7 @@ etd_status setup_coupled(etd_plan* P, Instance& I) {
 etd_status setup_fixed(etd_plan* P, Instance& I) {
     const GridK& g = I.g;
     const size_t nr = (size_t)g.nreal(), ns = (size_t)g.nspec();
-    double** reals[] = {&I.G, &I.sg, &I.isg, &I.U, &I.w, &I.R0, &I.R1, &I.vv, &I.t1, &I.t2, &I.acc, &I.q, &I.mq,
+    double** reals[] = {&I.G, &I.sg, &I.isg, &I.U, &I.w, &I.R0, &I.vv, &I.t1, &I.t2, &I.acc, &I.q, &I.mq,
                         &I.psid};
     for (double** r : reals) ALLOC(*r, nr * sizeof(double));
     if (fixed_cheb_pair_supported(g)) {
@@ -643,7 +643,9 @@ etd_status fixed_nonlocal(etd_plan* plan, Instance& I, const double* q, hipStrea
     return ETD_OK;
 }
 
-etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipStream_t s) {
+// R = R(U); with Rprev (nullable) R receives R(U) - Rprev instead.
+etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipStream_t s,
+                   const double* Rprev = nullptr) {
     const GridK& g = I.g;
     const long n = g.nreal();
     const double fb = 8.0 * n;
@@ -654,11 +656,11 @@ etd_status fixed_R(etd_plan* plan, Instance& I, const double* U, double* R, hipS
     });
     etd_status st = fixed_nonlocal(plan, I, I.q, s);
     if (st != ETD_OK) return st;
-    timed_kernel(PASS_FIXED_POINT, 3.0 * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
+    timed_kernel(PASS_FIXED_POINT, (Rprev ? 4.0 : 3.0) * fb + (I.f32 ? 4.0 : 8.0) * n, s, [&] {
         if (!I.f32 || (I.d.flags & ETD_F_SURFACE_NONLOCAL))
-            fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, band, s);
+            fixed_remainder<double>(n, I.FK, I.sg, U, I.psid, I.scal + S_MASS, R, band, s, Rprev);
         else
-            fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, band, s);
+            fixed_remainder<float>(n, I.FK, I.sg, U, I.psif, I.scal + S_MASS, R, band, s, Rprev);
     });
     return ETD_OK;
 }
@@ -711,23 +713,18 @@ etd_status step_fixed(etd_plan* plan, Instance& I, hipStream_t s) {
     StageRange r1("etd.fixed.stage1");
     timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { mul(n, I.sg, I.U, I.w, s); });
     if ((st = fixed_R(plan, I, I.U, I.R0, s)) != ETD_OK) return st;
-    timed_kernel(PASS_FIXED_STENCIL, 4.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.gf, I.isg, I.w, I.vv, s); });
+    // v = R0 - L w in the operator pass
+    timed_kernel(PASS_FIXED_STENCIL, 5.0 * fb, s, [&] { fixed_L_apply(g, I.FK, I.gf, I.isg, I.w, I.vv, s, I.R0); });
     const double* band = (I.d.flags & ETD_F_BAND_STEP) ? I.gf : nullptr;   // U changes on the band only
-    timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R0, -1.0, I.vv, I.vv, s); });
     cheb_apply(I, I.ch1, I.vv, I.acc, s);
-    timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
-        axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);   // w = w~
-        mul(n, I.isg, I.w, I.U, s, halt_flag(I), band);   // U = w~ / sg  (ETD1 result / predictor)
-    });
+    // w = w~ = w + tau acc, U = w~ / sg (the ETD1 result / the predictor)
+    timed_kernel(PASS_FIXED_POINT, 5.0 * fb, s, [&] { fixed_advance(n, I.d.tau, I.acc, I.w, I.isg, I.U, halt_flag(I), band, s); });
     if (I.d.scheme == ETD_ETDRK2) {
         StageRange r2("etd.fixed.stage2");
-        if ((st = fixed_R(plan, I, I.U, I.R1, s)) != ETD_OK) return st;
-        timed_kernel(PASS_FIXED_POINT, 3.0 * fb, s, [&] { axpby(n, 1.0, I.R1, -1.0, I.R0, I.vv, s); });
+        // v = R(U~) - R0, formed where R(U~) is
+        if ((st = fixed_R(plan, I, I.U, I.vv, s, I.R0)) != ETD_OK) return st;
         cheb_apply(I, I.ch2, I.vv, I.acc, s);
-        timed_kernel(PASS_FIXED_POINT, 6.0 * fb, s, [&] {
-            axpby(n, 1.0, I.w, I.d.tau, I.acc, I.w, s);
-            mul(n, I.isg, I.w, I.U, s, halt_flag(I), band);
-        });
+        timed_kernel(PASS_FIXED_POINT, 5.0 * fb, s, [&] { fixed_advance(n, I.d.tau, I.acc, I.w, I.isg, I.U, halt_flag(I), band, s); });
     }
     if (I.d.flags & ETD_F_MASS_PROJECT) {
         timed_kernel(PASS_FIXED_POINT, 5.0 * fb, s, [&] {

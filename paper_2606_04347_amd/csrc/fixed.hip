@@ -50,17 +50,19 @@ __global__ __launch_bounds__(kB) void k_nonlocal_arg(long n, FixedK K, const dou
 template <typename TP>
 __global__ __launch_bounds__(kB) void k_remainder(long n, FixedK K, const double* __restrict__ sg, const double* __restrict__ U,
                             const TP* __restrict__ psi, const double* __restrict__ m, double* __restrict__ R,
-                            const double* __restrict__ gf) {
+                            const double* __restrict__ gf, const double* __restrict__ Rprev) {
     const double Mm = K.M * m[0];
     const double ieu = 1.0 / K.eps_u;
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
         const double u = U[i], s = sg[i];
+        double r;
         if (gf && gf[i] < 0.0) {
-            R[i] = K.B * (s * u);
-            continue;
+            r = K.B * (s * u);
+        } else {
+            const double fp = fp_ind(u);
+            r = K.B * s * u - s * Wp(u) * ieu - K.gamma * s * (double)psi[i] * fp - Mm * s * fp;
         }
-        const double fp = fp_ind(u);
-        R[i] = K.B * s * u - s * Wp(u) * ieu - K.gamma * s * (double)psi[i] * fp - Mm * s * fp;
+        R[i] = Rprev ? r - Rprev[i] : r;
     }
 }
 
@@ -322,14 +324,26 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
 }
 
 __global__ __launch_bounds__(kB) void k_L(GridK g, FixedK K, const double* __restrict__ G, const double* __restrict__ isg,
-                    const double* __restrict__ x, double* __restrict__ out) {
+                    const double* __restrict__ x, const double* __restrict__ r, double* __restrict__ out) {
     const long n = g.nreal();
-    for (long i = (long)xcd_remap(blockIdx.x, gridDim.x) * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB)
-        out[i] = K.B * x[i] + K.eps_u * (-isg[i] * H_flux(g, i, G, isg, x));
+    for (long i = (long)xcd_remap(blockIdx.x, gridDim.x) * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+        const double Lx = K.B * x[i] + K.eps_u * (-isg[i] * H_flux(g, i, G, isg, x));
+        out[i] = r ? r[i] - Lx : Lx;
+    }
 }
 
-__global__ __launch_bounds__(kB) void k_axpby(long n, double a, const double* x, double b, const double* y, double* out) {
-    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) out[i] = a * x[i] + b * y[i];
+// w = w + tau acc, then U = isg w (where gf >= 0, when gf is given); once the
+// instance is halted neither is written
+__global__ __launch_bounds__(kB) void k_advance(long n, double tau, const double* __restrict__ acc,
+                                                double* __restrict__ w, const double* __restrict__ isg,
+                                                double* __restrict__ U, const double* halt,
+                                                const double* __restrict__ gf) {
+    if (halted(halt)) return;
+    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+        const double wn = w[i] + tau * acc[i];
+        w[i] = wn;
+        if (!gf || gf[i] >= 0.0) U[i] = isg[i] * wn;
+    }
 }
 
 __global__ __launch_bounds__(kB) void k_mul(long n, const double* x, const double* y, double* out,
@@ -350,13 +364,13 @@ void fixed_nonlocal_arg(long n, const FixedK& K, const double* G, const double* 
 }
 template <typename TP>
 void fixed_remainder(long n, const FixedK& K, const double* sg, const double* U, const TP* psi, const double* m,
-                     double* R, const double* gf, hipStream_t s) {
-    hipLaunchKernelGGL(k_remainder<TP>, dim3(grid_for(n)), dim3(kB), 0, s, n, K, sg, U, psi, m, R, gf);
+                     double* R, const double* gf, hipStream_t s, const double* Rprev) {
+    hipLaunchKernelGGL(k_remainder<TP>, dim3(grid_for(n)), dim3(kB), 0, s, n, K, sg, U, psi, m, R, gf, Rprev);
 }
 template void fixed_remainder<double>(long, const FixedK&, const double*, const double*, const double*,
-                                      const double*, double*, const double*, hipStream_t);
+                                      const double*, double*, const double*, hipStream_t, const double*);
 template void fixed_remainder<float>(long, const FixedK&, const double*, const double*, const float*,
-                                     const double*, double*, const double*, hipStream_t);
+                                     const double*, double*, const double*, hipStream_t, const double*);
 void fixed_band_field(long n, const double* G, double delta, double* gf, hipStream_t s) {
     hipLaunchKernelGGL(k_band_field, dim3(grid_for(n)), dim3(kB), 0, s, n, G, delta, gf);
 }
@@ -375,11 +389,12 @@ void fixed_cheb_pair(const GridK& g, const FixedK& K, const double* G, const dou
                        c1, c2);
 }
 void fixed_L_apply(const GridK& g, const FixedK& K, const double* G, const double* isg, const double* x,
-                   double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_L, dim3(grid_for(g.nreal())), dim3(kB), 0, s, g, K, G, isg, x, out);
+                   double* out, hipStream_t s, const double* r) {
+    hipLaunchKernelGGL(k_L, dim3(grid_for(g.nreal())), dim3(kB), 0, s, g, K, G, isg, x, r, out);
 }
-void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kB), 0, s, n, a, x, b, y, out);
+void fixed_advance(long n, double tau, const double* acc, double* w, const double* isg, double* U,
+                   const double* halt, const double* gf, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(grid_for(n)), dim3(kB), 0, s, n, tau, acc, w, isg, U, halt, gf);
 }
 void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt,
          const double* gf) {

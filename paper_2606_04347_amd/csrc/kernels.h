@@ -140,10 +140,11 @@ void fixed_band_field(long n, const double* G, double delta, double* gf, hipStre
 void fixed_nonlocal_arg(long n, const FixedK& K, const double* gg, const double* U, double* q, double* mq,
                         const double* gf, hipStream_t s);
 // R = B sg U - sg W'(U)/eps_u - gamma sg psi f'(U) - M m sg f'(U); gf (nullable):
-// off the band of a restricted step R = B (sg U)
+// off the band of a restricted step R = B (sg U).  With Rprev (nullable) R
+// receives that value minus Rprev (the difference the second ETDRK2 stage uses).
 template <typename TP>
 void fixed_remainder(long n, const FixedK& K, const double* sg, const double* U, const TP* psi,
-                     const double* m, double* R, const double* gf, hipStream_t s);
+                     const double* m, double* R, const double* gf, hipStream_t s, const double* Rprev = nullptr);
 // y = alpha * Atil x - beta * xprev  (Atil = (2 L - (a + b)) / (b - a), L = B + eps_u H),
 // acc (+)= c * y.  xprev may be null when beta == 0.  first != 0: acc = c0 * x + c * y.
 void fixed_cheb_step(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
@@ -156,11 +157,14 @@ bool fixed_cheb_pair_supported(const GridK& g);
 void fixed_cheb_pair(const GridK& g, const FixedK& K, const double* gg, const double* isg, double a, double b,
                      double alpha, double beta, const double* x, const double* xprev, double* y1, double* y2,
                      double* acc, double c1, double c2, hipStream_t s);
-// out = L x
+// out = L x, or with r (nullable) out = r - L x
 void fixed_L_apply(const GridK& g, const FixedK& K, const double* gg, const double* isg, const double* x,
-                   double* out, hipStream_t s);
+                   double* out, hipStream_t s, const double* r = nullptr);
+// w = w + tau acc, then U = isg w (on the band only when gf is given); a no-op
+// once *halt != 0
+void fixed_advance(long n, double tau, const double* acc, double* w, const double* isg, double* U,
+                   const double* halt, const double* gf, hipStream_t s);
 // elementwise helpers
-void axpby(long n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
 // out = x * y; a no-op once *halt != 0 (halt nullable); with gf (nullable) only
 // on the band of a restricted step (gf >= 0)
 void mul(long n, const double* x, const double* y, double* out, hipStream_t s, const double* halt = nullptr,

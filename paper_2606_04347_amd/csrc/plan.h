@@ -65,7 +65,7 @@ struct Instance {
     void *Sphi = nullptr, *St = nullptr, *Sra = nullptr, *Sa = nullptr, *Sb = nullptr, *Sgu = nullptr,
          *Stmp = nullptr;
     // fixed buffers (double unless noted)
-    double *G = nullptr, *sg = nullptr, *isg = nullptr, *U = nullptr, *w = nullptr, *R0 = nullptr, *R1 = nullptr,
+    double *G = nullptr, *sg = nullptr, *isg = nullptr, *U = nullptr, *w = nullptr, *R0 = nullptr,
            *vv = nullptr, *t1 = nullptr, *t2 = nullptr, *acc = nullptr, *q = nullptr, *mq = nullptr,
            *t3 = nullptr, *t4 = nullptr,   // two-term recurrence passes (3D grids)
            *psid = nullptr;
