@@ -508,7 +508,7 @@ template <typename T> __device__ __forceinline__ c2<T> ld2(const T* p) { return 
 
 // (P1, W'(phi) - A1 phi) at the point pair (2e, 2e + 1) of row l: the R1
 // remainder formed where the z transform loads it.
-template <typename T, int L> struct R1PairLoad {
+template <typename T, int L, bool BAND> struct R1PairLoad {
     static constexpr int NS = 2;
     const RowTile<L>* rt;
     int nl, nz;
@@ -522,7 +522,7 @@ template <typename T, int L> struct R1PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        if (mask) {
+        if constexpr (BAND) {
             // P1 = the local part from phi and its Laplacian, plus on the band
             // the surface part (every lane runs the same loads: no stencil
             // here, so the band costs a wave no divergent gathers)
@@ -567,7 +567,7 @@ template <typename T, int L> struct R1PairLoad {
 // (P2, g+ u) at the point pair (2e, 2e + 1) of row l; psi from memory, or
 // with psl != null from the pairs of the tile's rows in the LDS (row l at
 // l * NR / 2).
-template <typename T, int L> struct P2PairLoad {
+template <typename T, int L, bool BAND> struct P2PairLoad {
     static constexpr int NS = 2;
     const RowTile<L>* rt;
     int nl, nz;
@@ -582,7 +582,7 @@ template <typename T, int L> struct P2PairLoad {
             return;
         }
         const long c = rt->c[l], o = 2 * (long)e;
-        if (mask) {
+        if constexpr (BAND) {
             // g+ u everywhere; P2 (0 off the band) from its stencil part formed on
             // the band list and the nonlocal term - gamma g+ psi
             const c2<T> uu = ld2(u + c + o), GG = ld2(G + c + o);
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(kThreads) void k_z_r2c_q(const T* u, const T* G, co
     k_z_r2c_q_body<T, NR>::run(u, G, mask, ubar, W, twh, twf, nrows, part);
 }
 
-template <typename T, int NR>
+template <typename T, int NR, bool BAND>
 struct k_z_r2c_r1_body {
     static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
                                                        const T* u, const uint8_t* mask, const T* surf,
@@ -709,17 +709,17 @@ struct k_z_r2c_r1_body {
         const int nl = (int)min((long)L, nrows - row0);
         row_tile_setup<L>(rt, g, row0);
         __syncthreads();
-        const R1PairLoad<T, L> op{&rt, nl, g.nz, phi, lap, gn, u, mask, surf, R1Const<T>(g, K, int_phi[0], A0)};
+        const R1PairLoad<T, L, BAND> op{&rt, nl, g.nz, phi, lap, gn, u, mask, surf, R1Const<T>(g, K, int_phi[0], A0)};
         zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
     }
 };
-template <typename T, int NR>
+template <typename T, int NR, bool BAND>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_r1(GridK g, CoupledK K, const T* phi, const T* lap, const T* gn,
                                                        const T* u, const uint8_t* mask, const T* surf,
                                                        const double* int_phi, double A0, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    k_z_r2c_r1_body<T, NR>::run(g, K, phi, lap, gn, u, mask, surf, int_phi, A0, WP, WQ, twh, twf, nrows);
+    k_z_r2c_r1_body<T, NR, BAND>::run(g, K, phi, lap, gn, u, mask, surf, int_phi, A0, WP, WQ, twh, twf, nrows);
 }
 
 // The pairs of an inverse z transform kept in the LDS (row l at l * M).
@@ -737,7 +737,7 @@ template <typename T, int NR, bool PSI_HAT> constexpr size_t z_smem_p2() {
     return z_smem2<T, NR>() + (PSI_HAT ? sizeof(c2<T>) * (size_t)z_rows_pair<T, NR>() * (NR / 2) : 0);
 }
 
-template <typename T, int NR, bool PSI_HAT>
+template <typename T, int NR, bool PSI_HAT, bool BAND>
 struct k_z_r2c_p2_body {
     static __device__ __forceinline__ void run(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
                                                        const T* vy, const T* vz, const T* psi,
@@ -765,18 +765,18 @@ struct k_z_r2c_p2_body {
             zrow_inverse_lds<T, NR, LdsPairStore<T, M>, L>(lds, stw, twf, LdsPairStore<T, M>{psl, psi_scale});
         }
         __syncthreads();
-        const P2PairLoad<T, L> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, surf, P2Const<T>(g, K, m[0]), psl};
+        const P2PairLoad<T, L, BAND> op{&rt, nl, g.nz, u, G, vx, vy, vz, psi, mask, surf, P2Const<T>(g, K, m[0]), psl};
         zrow_forward2<T, NR>(lds, stw, twf, op, WP + row0 * MS, WQ + row0 * MS, nl);
     }
 };
-template <typename T, int NR, bool PSI_HAT>
+template <typename T, int NR, bool PSI_HAT, bool BAND>
 __global__ __launch_bounds__(kThreads) void k_z_r2c_p2(GridK g, CoupledK K, const T* u, const T* G, const T* vx,
                                                        const T* vy, const T* vz, const T* psi,
                                                        const c2<T>* psi_hat, T psi_scale, const double* m,
                                                        const uint8_t* mask, const T* surf, c2<T>* WP, c2<T>* WQ,
                                                        const c2<T>* __restrict__ twh,
                                                        const c2<T>* __restrict__ twf, long nrows) {
-    k_z_r2c_p2_body<T, NR, PSI_HAT>::run(g, K, u, G, vx, vy, vz, psi, psi_hat, psi_scale, m, mask, surf, WP, WQ, twh,
+    k_z_r2c_p2_body<T, NR, PSI_HAT, BAND>::run(g, K, u, G, vx, vy, vz, psi, psi_hat, psi_scale, m, mask, surf, WP, WQ, twh,
                                              twf, nrows);
 }
 
@@ -1082,40 +1082,56 @@ hipError_t launch_z_q(const GridK& g, const T* u, const T* G, const uint8_t* mas
     return hipGetLastError();
 }
 
+template <typename T, int NR, bool BAND>
+void launch_z_r1_k(const GridK& g, const CoupledK& K, const R1Fields<T>& f, c2<T>* WP, c2<T>* WQ, const c2<T>* twh,
+                   const c2<T>* twf, hipStream_t s) {
+    constexpr int L = z_rows_pair<T, NR>();
+    const size_t smem = z_smem2<T, NR>();
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_r1<T, NR, BAND>, smem, flag);
+    const long nrows = (long)g.nx * g.ny;
+    launch_k<k_z_r2c_r1_body<T, NR, BAND>>(k_z_r2c_r1<T, NR, BAND>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads),
+                                           smem, s, g, K, f.phi, f.lap, f.gn, f.u, f.mask, f.surf, f.int_phi, f.A0, WP,
+                                           WQ, twh, twf, nrows);
+}
+// The band form (mask set) is its own instantiation, so the full-grid pass
+// carries none of its code.
 template <typename T, int NR>
 hipError_t launch_z_r1(const GridK& g, const CoupledK& K, const R1Fields<T>& f, c2<T>* WP, c2<T>* WQ,
                        const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
-    constexpr int L = z_rows_pair<T, NR>();
-    const size_t smem = z_smem2<T, NR>();
     static_assert(z_smem2<T, NR>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
-    static std::once_flag flag;
-    set_smem_limit(k_z_r2c_r1<T, NR>, smem, flag);
-    const long nrows = (long)g.nx * g.ny;
-    launch_k<k_z_r2c_r1_body<T, NR>>(k_z_r2c_r1<T, NR>, dim3((int)((nrows + L - 1) / L)), dim3(kThreads), smem, s, g, K, f.phi,
-                       f.lap, f.gn, f.u, f.mask, f.surf, f.int_phi, f.A0, WP, WQ, twh, twf, nrows);
+    if (f.mask) launch_z_r1_k<T, NR, true>(g, K, f, WP, WQ, twh, twf, s);
+    else launch_z_r1_k<T, NR, false>(g, K, f, WP, WQ, twh, twf, s);
     return hipGetLastError();
 }
-template <typename T, int NR>
-hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ,
-                       const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+template <typename T, int NR, bool PSI_HAT, bool BAND>
+void launch_z_p2_k(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ, const c2<T>* twh,
+                   const c2<T>* twf, hipStream_t s) {
     constexpr int L = z_rows_pair<T, NR>();
     const long nrows = (long)g.nx * g.ny;
     const dim3 grid((int)((nrows + L - 1) / L));
     const T scale = (T)(1.0 / ((double)g.nx * g.ny * g.nz));
-    if (f.psi_hat) {
-        const size_t smem = z_smem_p2<T, NR, true>();
-        static_assert(z_smem_p2<T, NR, true>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
-        static std::once_flag flag;
-        set_smem_limit(k_z_r2c_p2<T, NR, true>, smem, flag);
-        launch_k<k_z_r2c_p2_body<T, NR, true>>(k_z_r2c_p2<T, NR, true>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
-                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, f.surf, WP, WQ, twh, twf, nrows);
+    const size_t smem = z_smem_p2<T, NR, PSI_HAT>();
+    static_assert(z_smem_p2<T, NR, PSI_HAT>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
+    static std::once_flag flag;
+    set_smem_limit(k_z_r2c_p2<T, NR, PSI_HAT, BAND>, smem, flag);
+    launch_k<k_z_r2c_p2_body<T, NR, PSI_HAT, BAND>>(k_z_r2c_p2<T, NR, PSI_HAT, BAND>, grid, dim3(kThreads), smem, s, g,
+                                                    K, f.u, f.G, f.vx, f.vy, f.vz, f.psi, f.psi_hat, scale, f.m,
+                                                    f.mask, f.surf, WP, WQ, twh, twf, nrows);
+}
+// Forms: psi from its spectrum (the full-grid FFT path), psi from memory (the
+// band solve without a band list in the pass), and the band form (psi from
+// memory at band points).
+template <typename T, int NR>
+hipError_t launch_z_p2(const GridK& g, const CoupledK& K, const P2Fields<T>& f, c2<T>* WP, c2<T>* WQ,
+                       const c2<T>* twh, const c2<T>* twf, hipStream_t s) {
+    if (f.mask) {
+        if (f.psi_hat) return hipErrorInvalidValue;   // the band form reads psi from memory
+        launch_z_p2_k<T, NR, false, true>(g, K, f, WP, WQ, twh, twf, s);
+    } else if (f.psi_hat) {
+        launch_z_p2_k<T, NR, true, false>(g, K, f, WP, WQ, twh, twf, s);
     } else {
-        const size_t smem = z_smem_p2<T, NR, false>();
-        static_assert(z_smem_p2<T, NR, false>() <= kLdsBytes, "LDS tile larger than a workgroup can hold");
-        static std::once_flag flag;
-        set_smem_limit(k_z_r2c_p2<T, NR, false>, smem, flag);
-        launch_k<k_z_r2c_p2_body<T, NR, false>>(k_z_r2c_p2<T, NR, false>, grid, dim3(kThreads), smem, s, g, K, f.u, f.G, f.vx, f.vy,
-                           f.vz, f.psi, f.psi_hat, scale, f.m, f.mask, f.surf, WP, WQ, twh, twf, nrows);
+        launch_z_p2_k<T, NR, false, false>(g, K, f, WP, WQ, twh, twf, s);
     }
     return hipGetLastError();
 }

@@ -59,24 +59,37 @@ template <typename T> __device__ __forceinline__ void r1_core(const R1Const<T>& 
     *Q = q1;
 }
 
-// The |grad phi|-weighted (surface) part of P1 at one point: zero off the band.
+// The |grad phi|-weighted (surface) part of P1 at one point from its
+// ingredients: gc = g(phi), the weighted Laplacian S of u, wp = W'(phi).
+template <typename T>
+__device__ __forceinline__ T r1_surf_terms(const R1Const<T>& k, T L, T gn, T uc, T gc, T S, T wp) {
+    return k.cl * (k.eu * S - gc * Wp(uc) * k.ieu) * gn - k.area * gn + k.ca * (uc + k.u0) * gn * (k.ep * L - wp * k.iep);
+}
+// S = the g(phi)-weighted Laplacian of u at one point (six neighbours of u and phi).
+template <typename T>
+__device__ __forceinline__ T r1_stencil(const R1Const<T>& k, T uc, T gc, const T (&un)[6], const T (&pn)[6]) {
+    T S = lapS_axis(un[0], uc, un[1], gloc(pn[0]), gc, gloc(pn[1]), k.ihx);
+    S += lapS_axis(un[2], uc, un[3], gloc(pn[2]), gc, gloc(pn[3]), k.ihy);
+    S += lapS_axis(un[4], uc, un[5], gloc(pn[4]), gc, gloc(pn[5]), k.ihz);
+    return S;
+}
+// The surface part of P1 at one point (zero off the band).
 template <typename T>
 __device__ __forceinline__ T r1_surf(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
                                      const T (&pn)[6]) {
     const T gc = gloc(pc);
-    T S = lapS_axis(un[0], uc, un[1], gloc(pn[0]), gc, gloc(pn[1]), k.ihx);
-    S += lapS_axis(un[2], uc, un[3], gloc(pn[2]), gc, gloc(pn[3]), k.ihy);
-    S += lapS_axis(un[4], uc, un[5], gloc(pn[4]), gc, gloc(pn[5]), k.ihz);
-    const T wp = Wp(pc);
-    return k.cl * (k.eu * S - gc * Wp(uc) * k.ieu) * gn - k.area * gn + k.ca * (uc + k.u0) * gn * (k.ep * L - wp * k.iep);
+    return r1_surf_terms(k, L, gn, uc, gc, r1_stencil(k, uc, gc, un, pn), Wp(pc));
 }
 
 template <typename T>
 __device__ __forceinline__ void r1_point(const R1Const<T>& k, T pc, T L, T gn, T uc, const T (&un)[6],
                                          const T (&pn)[6], bool band, T* P, T* Q) {
-    T p1, q1;
-    r1_core(k, pc, L, &p1, &q1);
-    const T surf = band ? r1_surf(k, pc, L, gn, uc, un, pn) : (T)0;
+    const T gc = gloc(pc);
+    const T S = r1_stencil(k, uc, gc, un, pn);
+    const T wp = Wp(pc), wpp = Wpp(pc);
+    const T q1 = wp - k.A1 * pc;
+    const T p1 = k.c1 * (wpp - k.A2) * (L - k.A1 * pc / k.e2) - (k.cW * wpp + k.cs) * q1;
+    const T surf = band ? r1_surf_terms(k, L, gn, uc, gc, S, wp) : (T)0;
     *P = p1 + surf;
     *Q = q1;
 }
