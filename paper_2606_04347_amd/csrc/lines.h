@@ -284,9 +284,11 @@ __device__ __forceinline__ void lines_fft_from_lds(c2<T>* lds, const c2<T>* tw, 
 
 // Global -> LDS: first stage from Op::load, every later stage in LDS; the
 // result is left in LDS in natural order, after a barrier.
-template <typename T, int N, int L, int LS, int NSLOT, int DIR, bool LF, class Op>
+// FIRST: the radix of the first stage (0: the plan's own, NextRadix<N>).
+template <typename T, int N, int L, int LS, int NSLOT, int DIR, bool LF, int FIRST = 0, class Op>
 __device__ __forceinline__ void lines_fft_to_lds(c2<T>* lds, const c2<T>* tw, const Op& op) {
-    constexpr int R0 = NextRadix<N>::v;
+    constexpr int R0 = FIRST > 0 ? FIRST : NextRadix<N>::v;
+    static_assert(N % R0 == 0, "the first radix must divide the length");
     first_stage<T, N, L, LS, R0, DIR, LF, Op>(lds, op);
     stockham<T, N, L * NSLOT, LS, R0, DIR>(lds, tw);
 }
