@@ -27,6 +27,16 @@
 namespace etd {
 namespace stk {
 
+// Radix of the first stage for L lines of length N: the plan's own, unless a
+// radix-8 first stage leaves threads of the workgroup without a butterfly
+// (lengths 32 and 64 at 16 lines); then 4 or 2, so every thread holds one
+// (one LDS stage more).  The first stage issues the pass's global loads.
+template <int N, int L> constexpr int first_radix() {
+    constexpr int R = NextRadix<N>::v;
+    if constexpr (R != 8 || L * (N / 8) >= kThreads) return R;
+    else return L * (N / 4) >= kThreads ? 4 : 2;
+}
+
 // First stage (span 1, radix R): global -> registers -> DFT -> LDS.
 // When the values of all of a thread's butterflies fit in 32 registers, every
 // load is issued before the first transform, so one memory latency covers
@@ -265,7 +275,7 @@ __device__ __forceinline__ void single_stage(const Op& op) {
 template <typename T, int N, int L, int DIR, bool LF, class Op>
 __device__ __forceinline__ void lines_fft(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int LS = line_stride<N>();
-    constexpr int R0 = NextRadix<N>::v;
+    constexpr int R0 = first_radix<N, L>();
     if constexpr (R0 == N) {
         single_stage<T, N, L, DIR, Op>(op);
     } else {
@@ -284,10 +294,10 @@ __device__ __forceinline__ void lines_fft_from_lds(c2<T>* lds, const c2<T>* tw, 
 
 // Global -> LDS: first stage from Op::load, every later stage in LDS; the
 // result is left in LDS in natural order, after a barrier.
-// FIRST: the radix of the first stage (0: the plan's own, NextRadix<N>).
+// FIRST: the radix of the first stage (0: first_radix).
 template <typename T, int N, int L, int LS, int NSLOT, int DIR, bool LF, int FIRST = 0, class Op>
 __device__ __forceinline__ void lines_fft_to_lds(c2<T>* lds, const c2<T>* tw, const Op& op) {
-    constexpr int R0 = FIRST > 0 ? FIRST : NextRadix<N>::v;
+    constexpr int R0 = FIRST > 0 ? FIRST : first_radix<N, L>();
     static_assert(N % R0 == 0, "the first radix must divide the length");
     first_stage<T, N, L, LS, R0, DIR, LF, Op>(lds, op);
     stockham<T, N, L * NSLOT, LS, R0, DIR>(lds, tw);
@@ -385,7 +395,7 @@ __device__ __forceinline__ void seq_transforms(c2<T>* lds, const c2<T>* tw, cons
 template <typename T, int N, int L, int DIR, bool LF, class Op, bool SYNC = false>
 __device__ __forceinline__ void lines_fft_seq(c2<T>* lds, const c2<T>* tw, const Op& op) {
     constexpr int LS = line_stride<N>();
-    constexpr int R0 = NextRadix<N>::v;
+    constexpr int R0 = first_radix<N, L>();
     constexpr int NR = N / R0;
     constexpr int NB = L * NR;
     constexpr int IT = (NB + kThreads - 1) / kThreads;

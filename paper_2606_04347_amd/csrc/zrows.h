@@ -124,14 +124,8 @@ __device__ __forceinline__ void zrow_forward2(c2<T>* lds, const c2<T>* stw, cons
         stockham<T, M, 2 * L, LS, 1, -1>(lds, stw);
     } else {
         // The first stage issues the producer's loads (the stencils of R1 and
-        // P2).  Where the plan's first radix leaves threads without a
-        // butterfly (M = 32, 64 at 16 rows: 64 or 128 of 256), a smaller
-        // first radix gives every thread one.
-        constexpr int R8 = NextRadix<M>::v;
-        constexpr int FIRST = (R8 == 8 && L * (M / 8) < kThreads)
-                                  ? (L * (M / 4) >= kThreads ? 4 : 2)
-                                  : 0;
-        lines_fft_to_lds<T, M, L, LS, 2, -1, false, FIRST>(lds, stw, op);
+        // P2), at the radix first_radix picks: one butterfly per thread.
+        lines_fft_to_lds<T, M, L, LS, 2, -1, false>(lds, stw, op);
     }
     const T half = (T)0.5;
     for (int idx = threadIdx.x; idx < 2 * L * (M + 1); idx += kThreads) {
