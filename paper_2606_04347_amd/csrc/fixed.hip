@@ -153,8 +153,9 @@ __global__ __launch_bounds__(kB) void k_cheb(GridK g, FixedK K, const double* __
 constexpr int kPY = 16, kPZ = 32, kPX = 8;
 constexpr int kH2Y = kPY + 4, kH2Z = kPZ + 4, kH2 = kH2Y * kH2Z;   // tile + 2-node halo
 constexpr int kH1Y = kPY + 2, kH1Z = kPZ + 2, kH1 = kH1Y * kH1Z;   // tile + 1-node halo
-constexpr int kSlots2 = (kH2 + kB - 1) / kB;
-constexpr int kSlots1 = (kH1 + kB - 1) / kB;
+constexpr int kBP = 512;   // threads of a workgroup: one per node of the tile
+constexpr int kSlots2 = (kH2 + kBP - 1) / kBP;
+constexpr int kSlots1 = (kH1 + kBP - 1) / kBP;
 
 // v mod n in [0, n) (tiles wider than the grid wrap more than once)
 __device__ __forceinline__ int wrap(int v, int n) {
@@ -170,7 +171,7 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const double* __restrict__ G,
+__global__ __launch_bounds__(kBP) void k_cheb_pair(GridK g, FixedK K, const double* __restrict__ G,
                                                   const double* __restrict__ isg, double a, double b, double alpha,
                                                   double beta, const double* __restrict__ x,
                                                   const double* __restrict__ xprev, double* __restrict__ y1out,
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
     long off2[kSlots2];
 #pragma unroll
     for (int k = 0; k < kSlots2; ++k) {
-        const int j = threadIdx.x + k * kB;
+        const int j = threadIdx.x + k * kBP;
         const int jy = j / kH2Z, jz = j - jy * kH2Z;
         off2[k] = (long)wrap(y0 - 2 + jy, g.ny) * g.nz + wrap(z0 - 2 + jz, g.nz);
     }
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
     double y1keep[kSlots1], y1now[kSlots1];
 #pragma unroll
     for (int k = 0; k < kSlots1; ++k) {
-        const int j = threadIdx.x + k * kB;
+        const int j = threadIdx.x + k * kBP;
         const int jy = j / kH1Z, jz = j - jy * kH1Z;
         const int yy = y0 - 1 + jy, zz = z0 - 1 + jz;
         off1[k] = (long)wrap(yy, g.ny) * g.nz + wrap(zz, g.nz);
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
         const long base = plane(p);
 #pragma unroll
         for (int k = 0; k < kSlots2; ++k) {
-            if (threadIdx.x + k * kB >= kH2) continue;
+            if (threadIdx.x + k * kBP >= kH2) continue;
             const long i = base + off2[k];
             lx[k] = x[i];
             li[k] = isg[i];
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
     fetch_plane(xs - 2);
 #pragma unroll
     for (int k = 0; k < kSlots1; ++k) {
-        if (threadIdx.x + k * kB < kH1) fetch_y1(xs - 1, k);
+        if (threadIdx.x + k * kBP < kH1) fetch_y1(xs - 1, k);
         if (own[k]) fetch_y2(xs, k);
     }
     for (int p = xs - 2; p <= xe + 1; ++p) {
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
             double* gp = gb[(p + 4) % 4];
 #pragma unroll
             for (int k = 0; k < kSlots2; ++k) {
-                const int j = threadIdx.x + k * kB;
+                const int j = threadIdx.x + k * kBP;
                 if (j >= kH2) continue;
                 zp[j] = li[k] * lx[k];
                 gp[j] = lg[k];
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
             const long base = plane(q);
 #pragma unroll
             for (int k = 0; k < kSlots1; ++k) {
-                const int j = threadIdx.x + k * kB;
+                const int j = threadIdx.x + k * kBP;
                 if (j >= kH1) continue;
                 const int c = c2i[k];
                 const double gci = gc[c], zci = zc[c];
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kB) void k_cheb_pair(GridK g, FixedK K, const doubl
 #pragma unroll
             for (int k = 0; k < kSlots1; ++k) {
                 if (!own[k]) continue;
-                const int j = threadIdx.x + k * kB;
+                const int j = threadIdx.x + k * kBP;
                 const int c = c2i[k];
                 const long i = base + off1[k];
                 const double gci = gc[c], zci = zc[j];
@@ -385,7 +386,7 @@ void fixed_cheb_pair(const GridK& g, const FixedK& K, const double* G, const dou
                      double alpha, double beta, const double* x, const double* xprev, double* y1, double* y2,
                      double* acc, double c1, double c2, hipStream_t s) {
     const int nb = ((g.nx + kPX - 1) / kPX) * ((g.ny + kPY - 1) / kPY) * ((g.nz + kPZ - 1) / kPZ);
-    hipLaunchKernelGGL(k_cheb_pair, dim3(nb), dim3(kB), 0, s, g, K, G, isg, a, b, alpha, beta, x, xprev, y1, y2, acc,
+    hipLaunchKernelGGL(k_cheb_pair, dim3(nb), dim3(kBP), 0, s, g, K, G, isg, a, b, alpha, beta, x, xprev, y1, y2, acc,
                        c1, c2);
 }
 void fixed_L_apply(const GridK& g, const FixedK& K, const double* G, const double* isg, const double* x,
