@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kB) void k_cheb(GridK g, FixedK K, const double* __
 //   y1 = alpha (s2 L x - sh x) - beta xprev,   y2 = alpha (s2 L y1 - sh y1) - beta x,
 //   acc += c1 y1, then acc += c2 y2,
 // each node's arithmetic exactly as one term of k_cheb takes it.  A workgroup
-// owns a tile of kPY x kPZ nodes in (y, z) and kPX consecutive x planes, and
+// owns a tile of kPY x kPZ nodes in (y, z) (one thread per node) and kPX
+// consecutive x planes, and
 // walks along x with rolling LDS planes: z = isg x and G over the tile with a
 // two-node halo, z1 = isg y1 over the tile with a one-node halo (y1 is formed
 // there too, so a tile needs no y1 of its neighbours).  Per node one pass
